@@ -1,0 +1,138 @@
+"""Pins of the oracle's discretisation and kernel against closed forms and
+textbook limits (no GPU)."""
+import math
+
+import numpy as np
+import pytest
+import scipy.integrate
+
+import workloads as W
+from oracle import discretise, greens
+
+
+def test_square_rule_has_24_cells_and_is_symmetric():
+    sq = discretise.square_offsets()
+    assert sq.shape == (24, 2)
+    # closed under x -> -x, y -> -y and x <-> y
+    s = {tuple(r) for r in sq}
+    for x, y in s:
+        assert (-x, y) in s and (x, -y) in s and (y, x) in s
+    # the radius^2 classes 0.5, 2.5, 4.5, 6.5 with multiplicities 4, 8, 4, 8
+    r2, counts = np.unique(np.sum(sq ** 2, axis=1), return_counts=True)
+    assert np.allclose(r2, [0.5, 2.5, 4.5, 6.5])
+    assert list(counts) == [4, 8, 4, 8]
+    # the next class (1.5, 2.5) -> 8.5 lies outside 24/pi
+    assert 6.5 < 24 / math.pi < 8.5
+
+
+@pytest.mark.parametrize("r,t", [(0.2, 0.1), (0.15, 0.1), (0.25, 0.07)])
+def test_cells_are_volume_exact(r, t):
+    cells, vol = discretise.particle_cells(r, t)
+    assert cells.shape == (48, 3)
+    assert math.isclose(48 * vol, math.pi * r * r * t, rel_tol=1e-14)
+    # canonical order: lower layer first, b then a ascending within a layer
+    assert np.all(cells[:24, 2] < 0) and np.all(cells[24:, 2] > 0)
+    lay = cells[:24, :2]
+    keys = [(y, x) for x, y in lay]
+    assert keys == sorted(keys)
+    assert np.allclose(cells.mean(axis=0), 0.0, atol=1e-16)
+
+
+def test_dyadic_matches_finite_difference_of_scalar_green():
+    """G = (I + grad grad / k^2) g, checked with central differences."""
+    k = 2 * math.pi
+    d0 = np.array([0.31, -0.17, 0.05])
+    h = 1e-4
+    g = lambda x: greens.scalar_g(np.linalg.norm(x), k)
+    hess = np.zeros((3, 3), dtype=complex)
+    e = np.eye(3) * h
+    for i in range(3):
+        for j in range(3):
+            hess[i, j] = (g(d0 + e[i] + e[j]) - g(d0 + e[i] - e[j])
+                          - g(d0 - e[i] + e[j]) + g(d0 - e[i] - e[j])) / (4 * h * h)
+    fd = g(d0) * np.eye(3) + hess / k ** 2
+    G = greens.dyadic(d0, k)
+    assert np.max(np.abs(G - fd)) / np.max(np.abs(G)) < 1e-6
+
+
+def test_dyadic_far_field_limit():
+    k = 2 * math.pi
+    dh = np.array([1.0, 2.0, -0.5]) / np.linalg.norm([1.0, 2.0, -0.5])
+    for R in (50.0, 500.0):
+        G = greens.dyadic(dh * R, k)
+        far = greens.scalar_g(R, k) * (np.eye(3) - np.outer(dh, dh))
+        rel = np.max(np.abs(G - far)) / np.max(np.abs(far))
+        assert rel < 3.0 / (k * R)
+
+
+def test_self_term_is_the_pv_integral_plus_depolarisation():
+    """k^2 PV-integral of the trace/3 of G over the sphere, by quadrature, minus 1/3."""
+    k = 2 * math.pi
+    for a in (0.01, 0.04, 0.1):
+        # tr G = 2 g; the 1/R^3 parts integrate to zero over directions
+        f = lambda R, part: (2.0 / 3.0) * k * k * (R * np.exp(-1j * k * R)).__getattribute__(part)
+        re = scipy.integrate.quad(f, 0, a, args=("real",), epsabs=1e-15, epsrel=1e-13)[0]
+        im = scipy.integrate.quad(f, 0, a, args=("imag",), epsabs=1e-15, epsrel=1e-13)[0]
+        ref = re + 1j * im - 1.0 / 3.0
+        assert abs(greens.self_term(a, k) - ref) < 1e-12
+
+
+def test_self_term_small_ka_series():
+    k = 2 * math.pi
+    for a in (1e-3, 5e-3, 2e-2):
+        ka = k * a
+        series = -1 / 3 + ka ** 2 / 3 - 1j * (2 / 9) * ka ** 3
+        assert abs(greens.self_term(a, k) - series) < 2 * ka ** 4
+
+
+def test_single_cell_polarisability_clausius_mossotti_and_radiation_reaction():
+    """alpha = V / (1/chi - s(a)) -> 4 pi a^3 (eps-1)/(eps+2), plus j k^3/(6 pi) in 1/alpha."""
+    eps = 12 + 0.1j
+    chi = eps - 1
+    k = 2 * math.pi
+    a = 1e-3
+    V = 4 * math.pi * a ** 3 / 3
+    alpha = V / (1 / chi - greens.self_term(a, k))
+    alpha0 = 4 * math.pi * a ** 3 * (eps - 1) / (eps + 2)
+    assert abs(alpha / alpha0 - 1) < 1e-4
+    corr = 1 / alpha - 1 / alpha0
+    # leading terms: -(ka)^2/3 / V (real, dynamic depolarisation) + j k^3 / (6 pi)
+    assert abs(corr.imag - k ** 3 / (6 * math.pi)) / (k ** 3 / (6 * math.pi)) < 1e-3
+
+
+def test_matrix_is_complex_symmetric(tiny_oracle):
+    Z = tiny_oracle["Z"]
+    assert np.max(np.abs(Z - Z.T)) <= 1e-15 * np.max(np.abs(Z))
+
+
+def test_blocks_are_reciprocal_on_a_random_array():
+    arr = W.random_lattice(3, 2, seed=3)
+    d = discretise.Discretisation(arr)
+    A = greens.assemble_block(d, [0, 4], [1, 5, 2])
+    B = greens.assemble_block(d, [1, 5, 2], [0, 4])
+    assert np.max(np.abs(A - B.T)) <= 1e-15 * np.max(np.abs(A))
+
+
+def test_identical_particles_have_identical_self_blocks(tiny_oracle):
+    sb = tiny_oracle["self_blocks"]
+    for p in range(1, sb.shape[0]):
+        assert np.array_equal(sb[0], sb[p])
+
+
+def test_plane_wave_normal_x_polarised(tiny_oracle):
+    d = tiny_oracle["disc"]
+    v = tiny_oracle["v"].reshape(-1, 3)
+    pos, vol, _, _ = d.cell_arrays()
+    # theta = 0: e = x^, phase exp(-j k z)
+    assert np.allclose(v[:, 1], 0) and np.allclose(v[:, 2], 0)
+    assert np.allclose(v[:, 0], vol * np.exp(-1j * d.k * pos[:, 2]), rtol=1e-15, atol=0)
+
+
+def test_matrix_free_product_equals_dense(tiny_oracle):
+    d, Z = tiny_oracle["disc"], tiny_oracle["Z"]
+    x = np.random.default_rng(1).standard_normal(Z.shape[0]) + 0j
+    assert np.allclose(greens.matvec_free(d, x, chunk=5), Z @ x, rtol=1e-13, atol=0)
+    rows = np.array([3, 7])
+    y = greens.matvec_free(d, x, rows=rows)
+    ref = (Z @ x).reshape(16, 144)[rows].reshape(-1)
+    assert np.allclose(y, ref, rtol=1e-13, atol=0)
