@@ -1,0 +1,244 @@
+/*
+ * qrvie — compressed volume-integral-equation solver for large arrays of
+ * sub-wavelength particles, on one AMD Instinct MI355X (gfx950).
+ *
+ * C ABI.  Every call returns a qrvie_status; no exception or abort crosses
+ * the boundary.  qrvie_last_error(ctx) gives a human-readable detail for the
+ * last failing call on that context.
+ *
+ * Conventions
+ *  - Complex numbers are complex128, interleaved {re, im} (torch.complex128).
+ *  - Vectors and multi-vectors are DEVICE pointers owned by the caller, laid
+ *    out column-major (n x nrhs) with a leading dimension >= n.  The library
+ *    never frees caller memory.
+ *  - Degree-of-freedom order at the ABI ("caller order"): particle in the order
+ *    of qrvie_array_desc, then the particle's 48 cells in canonical order
+ *    (lower layer, then upper; within a layer row b ascending, then column a
+ *    ascending), then the Cartesian component x, y, z fastest: 144 DoFs per
+ *    particle.  Unknowns are grouped particle by particle as in the paper's
+ *    block partition of Z (§4, eq. 4.1).  Internally the library reorders
+ *    particles along a Morton curve; that order never appears at the ABI
+ *    except through qrvie_geom_order and block exports.
+ *  - Units: lengths in the same unit as `wavelength`; k = 2 pi / wavelength.
+ *  - Handles (ctx, geom, op) are library-owned.  geom and op are immutable
+ *    after creation.  All device work is ordered on the context's stream;
+ *    calls that return host information synchronise that stream.
+ *  - A context is not thread-safe: serialise calls on one context.
+ */
+#ifndef QRVIE_H
+#define QRVIE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QRVIE_OK = 0,
+    QRVIE_ERR_INVALID_ARG = 1,   /* null pointer, bad size, NaN/Inf input, eps <= 0 */
+    QRVIE_ERR_GEOMETRY = 2,      /* two particles on one lattice site, bad lattice indices */
+    QRVIE_ERR_OUT_OF_MEMORY = 3, /* HBM budget of the context or device memory exhausted */
+    QRVIE_ERR_DEVICE = 4,        /* a HIP runtime error; see qrvie_last_error */
+    QRVIE_NOT_CONVERGED = 5,     /* soft: x holds the best iterate and info is filled */
+    QRVIE_ERR_QUEUE_FULL = 6     /* server: no admission slot */
+} qrvie_status;
+
+typedef struct { double re, im; } qrvie_c128;
+
+typedef struct qrvie_ctx qrvie_ctx;
+typedef struct qrvie_geom qrvie_geom;
+typedef struct qrvie_op qrvie_op;
+
+/* Static string for a status code. */
+const char* qrvie_status_string(qrvie_status s);
+
+/* ------------------------------------------------------------------ context */
+/*
+ * Create a context on HIP device `hip_device`.  `hip_stream` is a hipStream_t
+ * to order all work on (for instance torch.cuda.current_stream().cuda_stream);
+ * NULL makes the library create and own a default-priority stream.
+ * `hbm_budget` caps the bytes of device memory the library itself allocates
+ * for geometries, operators and solver workspaces (0 = no cap besides the
+ * device).  Caller-owned buffers do not count.
+ */
+qrvie_status qrvie_ctx_create(int hip_device, void* hip_stream, size_t hbm_budget, qrvie_ctx** out);
+void         qrvie_ctx_destroy(qrvie_ctx* ctx);
+const char*  qrvie_last_error(const qrvie_ctx* ctx);
+/* Bytes currently allocated by the library on this context. */
+size_t       qrvie_ctx_bytes_in_use(const qrvie_ctx* ctx);
+
+/* ----------------------------------------------------------------- geometry */
+/*
+ * An array of disk meta-atoms (the paper's scatterers, §6.1; disks with the
+ * voxel discretisation of the configured workloads).  All pointers are HOST
+ * pointers, read during the call only.
+ *   n                  number of particles (>= 1)
+ *   centers[n][3]      particle centres; the disks' axes are along z
+ *   radius[n]          disk radius (> 0)
+ *   height[n]          disk height (> 0)
+ *   eps_r[n_eps]       relative permittivity; n_eps is 1 (shared) or n
+ *   lattice_ij[n][2]   integer lattice site of each particle; sites must be
+ *                      distinct.  Grouping follows the lattice (§5.4: a particle
+ *                      belongs whole to the grid block containing its centre).
+ *   pitch              lattice pitch (informational; centres are authoritative)
+ *   wavelength         free-space wavelength (> 0)
+ *   cells_per_particle must be 48 (24 in-plane squares x 2 layers)
+ */
+typedef struct {
+    int32_t n;
+    const double* centers;
+    const double* radius;
+    const double* height;
+    const qrvie_c128* eps_r;
+    int32_t n_eps;
+    const int32_t* lattice_ij;
+    double pitch;
+    double wavelength;
+    int32_t cells_per_particle;
+} qrvie_array_desc;
+
+/* Discretise the array (paper §3 / the voxel reading) and build the recursive
+ * near/far grouping (§5.1, §5.3, §5.4).  Uploads cell data to the device. */
+qrvie_status qrvie_geom_create(qrvie_ctx* ctx, const qrvie_array_desc* desc, qrvie_geom** out);
+int64_t      qrvie_geom_ndof(const qrvie_geom* g);
+int32_t      qrvie_geom_nlevels(const qrvie_geom* g);
+/* internal_to_caller[N] (host): caller particle index of each internal particle. */
+qrvie_status qrvie_geom_order(const qrvie_geom* g, int32_t* internal_to_caller);
+/* Cell centres [N*48][3] and cell volumes [N*48] in caller order (host buffers). */
+qrvie_status qrvie_geom_cells(const qrvie_geom* g, double* centers, double* volumes);
+void         qrvie_geom_destroy(qrvie_geom* g);
+
+/*
+ * Assemble the dense block of Z for caller particles rows[0..nr) x cols[0..nc)
+ * (host index lists) into the DEVICE buffer B (column-major, ldb >= 144*nr),
+ * DoFs in the order of the lists.  Entries follow the discretised kernel:
+ * Z[(m,a),(n,b)] = -k^2 V_m V_n G_ab(r_m - r_n) for distinct cells, with the
+ * dyadic Green's function G = (I + grad grad / k^2) g, g = exp(-jkR)/(4 pi R)
+ * (§2, eq. 2.4), and V_m [1/chi_m - s(a_m)] on the cell diagonal.
+ * Stream-ordered; B is valid after the stream reaches this point.
+ */
+qrvie_status qrvie_assemble(qrvie_ctx* ctx, const qrvie_geom* g, int32_t nr, const int32_t* rows,
+                            int32_t nc, const int32_t* cols, qrvie_c128* B, int64_t ldb);
+
+/* ----------------------------------------------------------------- operator */
+enum { QRVIE_PREC_C128 = 0, QRVIE_PREC_C64 = 1, QRVIE_PREC_BF16X2 = 2 };
+
+/*
+ *   eps              per-block relative Frobenius tolerance of the low-rank
+ *                    factors, ||B - Q R||_F <= eps ||B||_F (§5.2, eq. 5.3); > 0
+ *   far_prec         storage of the far factors: QRVIE_PREC_C128 only for now
+ *   near_prec        storage of the self blocks: QRVIE_PREC_C128 only for now
+ *   max_block_rows   far blocks with more rows are split into their child
+ *                    pairs (always far); 0 = no cap (the paper's scheme)
+ *   share_transpose  reserved, must be 0
+ *   seed             seed of the random sketches used by compression
+ */
+typedef struct {
+    double eps;
+    int32_t far_prec;
+    int32_t near_prec;
+    int64_t max_block_rows;
+    int32_t share_transpose;
+    uint64_t seed;
+} qrvie_compress_opts;
+
+#define QRVIE_MAX_LEVELS 24
+
+typedef struct {
+    int32_t n_levels;
+    int64_t n_blocks;                         /* ordered far/finest pairs */
+    int64_t n_blocks_level[QRVIE_MAX_LEVELS];
+    int32_t min_rank_level[QRVIE_MAX_LEVELS];
+    int32_t max_rank_level[QRVIE_MAX_LEVELS];
+    double  mean_rank_level[QRVIE_MAX_LEVELS];
+    int32_t n_self_types;                     /* distinct self blocks (identical atoms share one) */
+    int64_t n_qr_entries;                     /* N_QR of eq. 5.6 (complex entries) */
+    double  gain;                             /* G = N_dof^2 / N_QR, eq. 5.5 */
+    double  max_block_rel_err;                /* certified max_b ||B - QR||_F / ||B||_F */
+    int64_t apply_bytes;                      /* algorithmic HBM bytes of one single-RHS product */
+    int64_t device_bytes;                     /* device memory held by the operator */
+    double  t_assembly_s, t_compression_s, t_precond_setup_s;
+} qrvie_op_stats;
+
+typedef struct {
+    int32_t level;
+    int32_t m, n, rank;
+    int32_t row_first, row_count;   /* internal particle range of the row block */
+    int32_t col_first, col_count;   /* internal particle range of the column block */
+    double rel_err;                 /* certified ||B - QR||_F / ||B||_F */
+} qrvie_block_info;
+
+/* Upper bound of the operator's device bytes before it is built. */
+qrvie_status qrvie_op_footprint_estimate(const qrvie_geom* g, const qrvie_compress_opts* o, size_t* bytes);
+/*
+ * Build the compressed operator Z_QR: self blocks Z_pp and the preconditioner
+ * Z_D^-1 (§4, eq. 4.2), then every far/finest pair block of the recursive
+ * grouping as certified low-rank factors Q R (§5.2-5.4).  Z_QR is exactly
+ * complex-symmetric: the pair (J, I) stores the transpose of the factors of
+ * (I, J).  Fails with QRVIE_ERR_OUT_OF_MEMORY if the estimate exceeds the
+ * context's remaining budget.
+ */
+qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_compress_opts* o, qrvie_op** out);
+qrvie_status qrvie_op_stats_get(const qrvie_op* op, qrvie_op_stats* out);
+int64_t      qrvie_op_num_blocks(const qrvie_op* op);
+/* Export block b's factors to HOST buffers Q[m*rank] and R[rank*n] (column-major;
+ * either may be NULL).  Rows/columns in internal DoF order of the particle ranges. */
+qrvie_status qrvie_op_export_block(const qrvie_op* op, int64_t b, qrvie_block_info* info,
+                                   qrvie_c128* Q, qrvie_c128* R);
+/* Export the self block Z_pp and/or its inverse of caller particle p (HOST, 144x144 column-major). */
+qrvie_status qrvie_op_export_self(const qrvie_op* op, int32_t p, qrvie_c128* Zpp, qrvie_c128* Zpp_inv);
+void         qrvie_op_destroy(qrvie_op* op);
+
+/* ---------------------------------------------------------------- products */
+/* y = Z_QR x for nrhs columns (device pointers, caller order): the compressed
+ * product Z_D x + sum_b Q_b (R_b x_J) of §5.2. */
+qrvie_status qrvie_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs,
+                         const qrvie_c128* x, int64_t ldx, qrvie_c128* y, int64_t ldy);
+/* z = Z_D^-1 y, the block-diagonal left preconditioner (§4, eq. 4.2). */
+qrvie_status qrvie_precondition(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs,
+                                const qrvie_c128* y, int64_t ldy, qrvie_c128* z, int64_t ldz);
+/*
+ * Right-hand sides v0 (eq. 3.4) for plane waves: v[(m,a)] = V_m E0_a(r_m),
+ * E0(r) = e exp(-j k k^.r), k^ = (sin t cos f, sin t sin f, cos t),
+ * pol 0 = TE: e = (-sin f, cos f, 0); pol 1 = TM: e = (cos t cos f, cos t sin f, -sin t).
+ * Angles in degrees (host arrays of length nrhs); v is a device n x nrhs buffer.
+ */
+qrvie_status qrvie_rhs_plane_waves(qrvie_ctx* ctx, const qrvie_geom* g, int32_t nrhs,
+                                   const double* theta_deg, const double* phi_deg,
+                                   const int32_t* pol, qrvie_c128* v, int64_t ldv);
+
+/* ------------------------------------------------------------------- solve */
+enum { QRVIE_SOLVE_FP64 = 0 };
+
+typedef struct {
+    int32_t restart;      /* GMRES(m) restart length, 1..256 */
+    int32_t max_iter;     /* total Arnoldi steps per right-hand side */
+    int32_t mode;         /* QRVIE_SOLVE_FP64 */
+    double  tol;          /* relative residual; converged when both the preconditioned
+                             estimate and the true residual ||v - Z_QR x||/||v|| meet it */
+    int32_t use_x0;       /* 1: x holds the initial guess on entry; 0: x0 = 0 */
+} qrvie_solve_opts;
+
+typedef struct {
+    int32_t iterations, restarts, converged;
+    double  rel_res_prec, rel_res_true;
+    int32_t n_apply, n_prec;
+    double  t_apply_s, t_prec_s, t_krylov_s, t_total_s;
+} qrvie_solve_info;
+
+/*
+ * Solve Z_QR x = v with left-preconditioned restarted GMRES (the paper's
+ * solver with the preconditioner of §4), one right-hand side after another.
+ * v, x: device n x nrhs (caller order).  info: host array of nrhs entries
+ * (may be NULL).  Returns QRVIE_NOT_CONVERGED (soft) if any column missed tol.
+ */
+qrvie_status qrvie_solve(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs,
+                         const qrvie_c128* v, int64_t ldv, qrvie_c128* x, int64_t ldx,
+                         const qrvie_solve_opts* opts, qrvie_solve_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QRVIE_H */

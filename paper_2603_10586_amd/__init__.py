@@ -1,0 +1,10 @@
+"""qrvie: compressed volume-integral-equation solves on one MI355X.
+
+Thin Python layer over the C ABI of libqrvie (include/qrvie.h).  PyTorch provides
+device memory and the stream; every step of the solve runs in the library's HIP
+kernels.  Importing this package does not touch the GPU; the library is loaded on
+first use and a missing library raises (there is no CPU fallback).
+"""
+from .api import (Context, Geometry, Operator, QrvieError, assemble, rhs_plane_waves)  # noqa: F401
+
+__all__ = ["Context", "Geometry", "Operator", "QrvieError", "assemble", "rhs_plane_waves"]

@@ -1,0 +1,253 @@
+"""Python handles over the C ABI.  Argument marshalling only: no numerics here."""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+
+
+class QrvieError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"qrvie status {status}: {msg}")
+        self.status = status
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Context:
+    """A device, a stream (torch's current stream by default) and an HBM budget."""
+
+    def __init__(self, device: int = 0, stream=None, hbm_budget: int = 0):
+        torch = _torch()
+        self.lib = L.load()
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.Stream(device)      # default priority
+        self.stream = stream
+        h = C.c_void_p()
+        st = self.lib.qrvie_ctx_create(device, C.c_void_p(stream.cuda_stream), hbm_budget, C.byref(h))
+        if st != L.OK:
+            raise QrvieError(st, "ctx_create failed")
+        self.h = h
+
+    def order(self):
+        """Make the library stream wait for work queued on torch's current stream."""
+        torch = _torch()
+        cur = torch.cuda.current_stream(self.device)
+        if cur.cuda_stream != self.stream.cuda_stream:
+            self.stream.wait_stream(cur)
+
+    def check(self, st: int, what: str = "") -> int:
+        if st not in (L.OK, L.NOT_CONVERGED):
+            msg = self.lib.qrvie_last_error(self.h).decode()
+            raise QrvieError(st, f"{what}: {msg}")
+        return st
+
+    def bytes_in_use(self) -> int:
+        return int(self.lib.qrvie_ctx_bytes_in_use(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.qrvie_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _dptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+class Geometry:
+    """An array of disks: any object with centers, radius, height, eps_r, lattice_ij,
+    pitch, wavelength and cells_per_particle attributes (numpy arrays)."""
+
+    def __init__(self, ctx: Context, array):
+        self.ctx = ctx
+        lib = ctx.lib
+        self._keep = dict(
+            centers=np.ascontiguousarray(array.centers, dtype=np.float64),
+            radius=np.ascontiguousarray(array.radius, dtype=np.float64),
+            height=np.ascontiguousarray(array.height, dtype=np.float64),
+            eps=np.ascontiguousarray(np.asarray(array.eps_r, dtype=np.complex128).reshape(-1)),
+            ij=np.ascontiguousarray(array.lattice_ij, dtype=np.int32),
+        )
+        k = self._keep
+        d = L.ArrayDescC()
+        d.n = int(k["centers"].shape[0])
+        d.centers = _dptr(k["centers"], C.c_double)
+        d.radius = _dptr(k["radius"], C.c_double)
+        d.height = _dptr(k["height"], C.c_double)
+        d.eps_r = k["eps"].ctypes.data_as(C.POINTER(L.C128))
+        d.n_eps = int(k["eps"].shape[0])
+        d.lattice_ij = _dptr(k["ij"], C.c_int32)
+        d.pitch = float(getattr(array, "pitch", 0.0))
+        d.wavelength = float(getattr(array, "wavelength", 1.0))
+        d.cells_per_particle = int(getattr(array, "cells_per_particle", 48))
+        h = C.c_void_p()
+        ctx.check(lib.qrvie_geom_create(ctx.h, C.byref(d), C.byref(h)), "geom_create")
+        self.h = h
+        self.n_particles = d.n
+        self.ndof = int(lib.qrvie_geom_ndof(h))
+        self.n_levels = int(lib.qrvie_geom_nlevels(h))
+
+    def order(self) -> np.ndarray:
+        out = np.zeros(self.n_particles, dtype=np.int32)
+        self.ctx.check(self.ctx.lib.qrvie_geom_order(self.h, _dptr(out, C.c_int32)), "geom_order")
+        return out
+
+    def cells(self):
+        c = np.zeros((self.n_particles * 48, 3))
+        v = np.zeros(self.n_particles * 48)
+        self.ctx.check(self.ctx.lib.qrvie_geom_cells(self.h, _dptr(c, C.c_double), _dptr(v, C.c_double)), "cells")
+        return c, v
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.qrvie_geom_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _cols(t, n: int):
+    """(nrhs, n) contiguous complex128 device tensor -> (ptr, ld, nrhs)."""
+    torch = _torch()
+    assert t.dtype == torch.complex128 and t.is_cuda and t.is_contiguous() and t.shape[-1] == n
+    nrhs = 1 if t.dim() == 1 else t.shape[0]
+    return C.c_void_p(t.data_ptr()), n, nrhs
+
+
+def assemble(ctx: Context, geom: Geometry, rows, cols):
+    """Dense block of Z for caller particle lists rows x cols -> (144*len(rows)) x (144*len(cols))
+    device tensor (returned transposed view of the column-major buffer)."""
+    torch = _torch()
+    r = np.ascontiguousarray(rows, dtype=np.int32)
+    c = np.ascontiguousarray(cols, dtype=np.int32)
+    m, n = 144 * r.size, 144 * c.size
+    buf = torch.empty((n, m), dtype=torch.complex128, device=f"cuda:{ctx.device}")
+    ctx.order()
+    ctx.check(ctx.lib.qrvie_assemble(ctx.h, geom.h, r.size, _dptr(r, C.c_int32), c.size, _dptr(c, C.c_int32),
+                                     C.c_void_p(buf.data_ptr()), m), "assemble")
+    return buf.t()
+
+
+def rhs_plane_waves(ctx: Context, geom: Geometry, theta_deg, phi_deg, pol):
+    torch = _torch()
+    th = np.ascontiguousarray(np.atleast_1d(theta_deg), dtype=np.float64)
+    ph = np.ascontiguousarray(np.atleast_1d(phi_deg), dtype=np.float64)
+    po = np.ascontiguousarray(np.atleast_1d(pol), dtype=np.int32)
+    v = torch.empty((th.size, geom.ndof), dtype=torch.complex128, device=f"cuda:{ctx.device}")
+    ctx.order()
+    ctx.check(ctx.lib.qrvie_rhs_plane_waves(ctx.h, geom.h, th.size, _dptr(th, C.c_double), _dptr(ph, C.c_double),
+                                            _dptr(po, C.c_int32), C.c_void_p(v.data_ptr()), geom.ndof), "rhs")
+    return v
+
+
+class Operator:
+    """The compressed interaction operator Z_QR with its block-diagonal preconditioner."""
+
+    def __init__(self, ctx: Context, geom: Geometry, eps: float = 1e-6, max_block_rows: int = 0, seed: int = 0):
+        self.ctx, self.geom = ctx, geom
+        o = L.CompressOpts(eps=eps, far_prec=L.PREC_C128, near_prec=L.PREC_C128, max_block_rows=max_block_rows,
+                           share_transpose=0, seed=seed)
+        self.opts = o
+        h = C.c_void_p()
+        ctx.check(ctx.lib.qrvie_op_create(ctx.h, geom.h, C.byref(o), C.byref(h)), "op_create")
+        self.h = h
+
+    @staticmethod
+    def footprint_estimate(geom: Geometry, eps: float = 1e-6, max_block_rows: int = 0) -> int:
+        o = L.CompressOpts(eps=eps, max_block_rows=max_block_rows)
+        out = C.c_size_t()
+        st = geom.ctx.lib.qrvie_op_footprint_estimate(geom.h, C.byref(o), C.byref(out))
+        geom.ctx.check(st, "footprint")
+        return int(out.value)
+
+    def stats(self) -> dict:
+        s = L.OpStats()
+        self.ctx.check(self.ctx.lib.qrvie_op_stats_get(self.h, C.byref(s)), "stats")
+        nl = s.n_levels + 1
+        return dict(n_levels=s.n_levels, n_blocks=s.n_blocks, n_blocks_level=list(s.n_blocks_level[:nl]),
+                    min_rank_level=list(s.min_rank_level[:nl]), max_rank_level=list(s.max_rank_level[:nl]),
+                    mean_rank_level=list(s.mean_rank_level[:nl]), n_self_types=s.n_self_types,
+                    n_qr_entries=s.n_qr_entries, gain=s.gain, max_block_rel_err=s.max_block_rel_err,
+                    apply_bytes=s.apply_bytes, device_bytes=s.device_bytes,
+                    t_compression_s=s.t_compression_s, t_precond_setup_s=s.t_precond_setup_s)
+
+    def num_blocks(self) -> int:
+        return int(self.ctx.lib.qrvie_op_num_blocks(self.h))
+
+    def export_block(self, b: int, factors: bool = True):
+        info = L.BlockInfo()
+        self.ctx.check(self.ctx.lib.qrvie_op_export_block(self.h, b, C.byref(info), None, None), "export")
+        Q = R = None
+        if factors and info.rank > 0:
+            Qb = np.zeros(info.m * info.rank, dtype=np.complex128)
+            Rb = np.zeros(info.rank * info.n, dtype=np.complex128)
+            self.ctx.check(self.ctx.lib.qrvie_op_export_block(self.h, b, C.byref(info), C.c_void_p(Qb.ctypes.data),
+                                                              C.c_void_p(Rb.ctypes.data)), "export")
+            Q = Qb.reshape(info.rank, info.m).T
+            R = Rb.reshape(info.n, info.rank).T
+        d = {f: getattr(info, f) for f, _ in L.BlockInfo._fields_}
+        return d, Q, R
+
+    def export_self(self, p: int):
+        Z = np.zeros(144 * 144, dtype=np.complex128)
+        Zi = np.zeros(144 * 144, dtype=np.complex128)
+        self.ctx.check(self.ctx.lib.qrvie_op_export_self(self.h, p, C.c_void_p(Z.ctypes.data),
+                                                         C.c_void_p(Zi.ctypes.data)), "export_self")
+        return Z.reshape(144, 144).T, Zi.reshape(144, 144).T
+
+    def apply(self, x):
+        torch = _torch()
+        px, ld, nrhs = _cols(x, self.geom.ndof)
+        y = torch.empty_like(x)
+        self.ctx.order()
+        self.ctx.check(self.ctx.lib.qrvie_apply(self.ctx.h, self.h, nrhs, px, ld, C.c_void_p(y.data_ptr()), ld), "apply")
+        return y
+
+    def precondition(self, y):
+        torch = _torch()
+        py, ld, nrhs = _cols(y, self.geom.ndof)
+        z = torch.empty_like(y)
+        self.ctx.order()
+        self.ctx.check(self.ctx.lib.qrvie_precondition(self.ctx.h, self.h, nrhs, py, ld, C.c_void_p(z.data_ptr()), ld),
+                       "precondition")
+        return z
+
+    def solve(self, v, restart: int = 30, tol: float = 1e-8, max_iter: int = 10000, x0=None):
+        torch = _torch()
+        pv, ld, nrhs = _cols(v, self.geom.ndof)
+        x = torch.zeros_like(v) if x0 is None else x0.clone()
+        o = L.SolveOpts(restart=restart, max_iter=max_iter, mode=L.SOLVE_FP64, tol=tol, use_x0=0 if x0 is None else 1)
+        infos = (L.SolveInfo * nrhs)()
+        self.ctx.order()
+        st = self.ctx.check(self.ctx.lib.qrvie_solve(self.ctx.h, self.h, nrhs, pv, ld, C.c_void_p(x.data_ptr()), ld,
+                                                     C.byref(o), infos), "solve")
+        out = [{f: getattr(i, f) for f, _ in L.SolveInfo._fields_} for i in infos]
+        return x, out, st
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.qrvie_op_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,224 @@
+// Internal structures of libqrvie: context, geometry, operator, kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/qrvie.h"
+
+namespace qrvie {
+
+constexpr int kCells = 48;          // cells per particle (24 squares x 2 layers)
+constexpr int kNp = 144;            // DoFs per particle (48 cells x 3 components)
+constexpr int kStrip = 64;          // rows per wavefront strip in the products
+
+typedef double2 c128;
+
+// ---------------------------------------------------------------- host records
+struct PType {                      // one distinct particle shape/material
+    double radius, height;
+    double eps_re, eps_im;
+    double vol, aeq;                // cell volume, equal-volume sphere radius
+    double off[kCells * 3];         // cell-centre offsets, canonical order
+};
+
+struct BlockRec {                   // one ordered pair block (I, J) of the grouping
+    int32_t level;
+    int32_t r0, rn;                 // internal particle range of the row node
+    int32_t c0, cn;                 // internal particle range of the column node
+    int32_t mirror;                 // index of the (J, I) block
+    int32_t primary;                // 1: compressed here (r0 < c0); 0: transpose of its mirror
+    int32_t rnode, cnode;           // node ids within the level
+};
+
+struct NodeRec { int32_t level, first, count; };
+
+// Flattened work descriptors of the products ------------------------------
+struct RStrip {                     // t[tmap[tmap_off + i]] = sum_j A[i + j*ld] x[x_off + j]
+    int64_t a_off;                  // element offset of row `row0` col 0 of the panel
+    int32_t ld, ncols, nrows;
+    int32_t x_off;                  // DoF start of the column node
+    int64_t tmap_off;
+};
+struct QStrip {                     // y[y_off + i] = sum_j A[i + j*ld] t[t_off + j]
+    int64_t a_off;
+    int32_t ld, ncols, nrows;
+    int64_t y_off;                  // level partial index of the strip's first row
+    int64_t t_off;
+};
+
+// Batched dense-kernel descriptors -----------------------------------------
+struct GemmDesc {                   // C (m x n) = op(A) (m x k) * op(B) (k x n)
+    const c128* A; int64_t lda;
+    const c128* B; int64_t ldb;
+    c128* C; int64_t ldc;
+    int32_t m, n, k;
+    uint64_t seed;                  // for a generated B
+    double* out_norm2;              // residual mode: ||C_ref - A B||^2 partial sink
+};
+struct QrcpDesc {                   // truncated column-pivoted QR of A (m x n), in place
+    c128* A; int32_t m, n, lda, kmax;
+    double* colnorm2;               // workspace n
+    int32_t* perm;                  // n
+    double* tau;                    // kmax
+    c128* wtop;                     // kmax
+    double rel2;                    // tolerance: trailing^2 <= rel2 * base2 - sub2
+    double base2;                   // <= 0: use the initial ||A||_F^2
+    double sub2;                    // < 0: use max(0, base2 - initial ||A||_F^2) (sketch residual)
+    int32_t* rank_out;
+    double* trail2_out;
+    double* norm2_out;
+};
+struct FormQDesc {                  // Q (m x r) = P_0 ... P_{r-1} [I_r; 0] from QRCP reflectors
+    const c128* A; int32_t m, lda, r;
+    const double* tau; const c128* wtop;
+    c128* Q; int32_t ldq;
+};
+struct ExtractRDesc {               // R[:, perm[j]] = triu(A[0:r, j])
+    const c128* A; int32_t lda, r, n;
+    const int32_t* perm;
+    c128* R; int32_t ldr;
+};
+struct Cgs2Desc {                   // orthonormalise the columns of Y (m x k) in place
+    c128* Y; int32_t m, k, ldy;
+    double drop_rel;
+    int32_t* kept_out;
+};
+struct PackDesc {                   // copy compact factors into panel layouts
+    const c128* src; int32_t rows, cols, lds; // src (rows x cols), column-major
+    c128* dst; int64_t ldd; int32_t transpose; // dst(i,j) = src(i,j) or src(j,i)
+};
+struct AsmDesc {                    // far block assembly: rows of particles r0.., cols c0..
+    c128* B; int64_t ldb;
+    int32_t r0, rn, c0, cn;
+};
+
+// ---------------------------------------------------------------- handles
+}  // namespace qrvie
+
+struct qrvie_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    size_t budget = 0;
+    size_t in_use = 0;
+    std::string err;
+};
+
+struct qrvie_geom {
+    qrvie_ctx* ctx = nullptr;
+    int32_t N = 0;
+    int32_t L = 0;
+    double wavelength = 1.0, k = 0.0;
+    std::vector<int32_t> i2c, c2i;            // internal <-> caller particle index
+    std::vector<int32_t> ptype;               // internal particle -> type
+    std::vector<qrvie::PType> types;
+    std::vector<double> center;               // internal order, N x 3
+    std::vector<qrvie::NodeRec> nodes;        // all occupied nodes, all levels
+    std::vector<std::vector<int32_t>> level_nodes;  // level -> node ids (Morton order)
+    std::vector<qrvie::BlockRec> blocks;      // sorted by (level, r0, c0)
+    // device
+    double* d_center = nullptr;               // N x 3
+    int32_t* d_ptype = nullptr;               // N
+    int32_t* d_i2c = nullptr;                 // N
+    double* d_tvol = nullptr;                 // ntypes
+    double* d_taeq = nullptr;
+    qrvie::c128* d_tchi = nullptr;
+    double* d_toff = nullptr;                 // ntypes x 48 x 3
+    int32_t* d_trep = nullptr;                // ntypes: a representative internal particle
+    size_t dev_bytes = 0;
+    int64_t ndof() const { return (int64_t)N * qrvie::kNp; }
+};
+
+struct qrvie_op {
+    qrvie_ctx* ctx = nullptr;
+    const qrvie_geom* g = nullptr;
+    qrvie_compress_opts opts{};
+    int32_t ntypes = 0;
+    qrvie::c128* d_self = nullptr;            // ntypes x 144 x 144 (column-major)
+    qrvie::c128* d_pinv = nullptr;            // inverses
+    qrvie::c128* d_fac = nullptr;             // all panels
+    int64_t fac_elems = 0;
+    qrvie::c128* d_t = nullptr;               // rank-space vector of the product
+    int64_t t_len = 0;
+    int64_t* d_tmap = nullptr;                // stacked R row -> t index
+    int64_t tmap_len = 0;
+    qrvie::RStrip* d_rstrips = nullptr;
+    qrvie::QStrip* d_qstrips = nullptr;
+    qrvie::c128* d_ylev = nullptr;            // n_active x n
+    struct Launch { int level; int64_t begin, count; int waves; };
+    std::vector<Launch> rlaunch, qlaunch;
+    int32_t n_active = 0;
+    std::vector<qrvie::BlockRec> blocks;      // the compressed pair blocks (after any row cap)
+    std::vector<int32_t> rank;                // per block
+    std::vector<double> relerr;               // per block
+    std::vector<int64_t> q_off;               // Q_b first element in d_fac (ld = m_b)
+    std::vector<int64_t> r_off;               // R_b (row 0, col 0) in d_fac
+    std::vector<int32_t> r_ld;
+    qrvie_op_stats stats{};
+    std::vector<std::pair<void*, size_t>> allocs;  // owned device memory
+    size_t dev_bytes = 0;
+};
+
+namespace qrvie {
+
+// ---------------------------------------------------------------- helpers
+bool set_err(qrvie_ctx* ctx, const std::string& msg);
+qrvie_status hip_check(qrvie_ctx* ctx, hipError_t e, const char* what);
+qrvie_status dalloc(qrvie_ctx* ctx, void** p, size_t bytes, const char* what);
+void dfree(qrvie_ctx* ctx, void* p, size_t bytes);
+
+// ---------------------------------------------------------------- launchers
+// assembly (k_assemble.hip)
+void launch_assemble_self(hipStream_t s, const qrvie_geom* g, c128* out, int ntypes);
+void launch_assemble_far(hipStream_t s, const qrvie_geom* g, const AsmDesc* d_descs,
+                         const int32_t* d_work_block, const int32_t* d_work_col, int64_t nwork);
+void launch_assemble_lists(hipStream_t s, const qrvie_geom* g, const int32_t* d_rows, int32_t nr,
+                           const int32_t* d_cols, int32_t nc, c128* B, int64_t ldb);
+void launch_rhs(hipStream_t s, const qrvie_geom* g, int nrhs, const double* d_par, c128* v, int64_t ldv);
+void launch_permute(hipStream_t s, int32_t N, const int32_t* d_i2c, const c128* in, c128* out, int to_internal);
+
+// dense linear algebra (k_linalg.hip)
+void launch_gemm(hipStream_t s, int mode, const GemmDesc* d_descs, const int32_t* d_tile_desc,
+                 const int32_t* d_tile_mn, int64_t ntiles);
+void launch_qrcp(hipStream_t s, const QrcpDesc* d, int n, int maxrows);
+void launch_form_q(hipStream_t s, const FormQDesc* d, int n, int maxrows);
+void launch_gemm_residual(hipStream_t s, const GemmDesc* d, const int32_t* td, const int32_t* tmn, int64_t nt,
+                          double* partial);
+void launch_extract_r(hipStream_t s, const ExtractRDesc* d, int n);
+void launch_cgs2(hipStream_t s, const Cgs2Desc* d, int n);
+void launch_pack(hipStream_t s, const PackDesc* d, int n);
+void launch_frob2(hipStream_t s, const c128* const* d_ptr, const int64_t* d_len, double* out, int n);
+void launch_invert(hipStream_t s, c128* A, int nmat, int* d_info);
+void launch_sum_partials(hipStream_t s, const double* part, const int32_t* d_first, const int32_t* d_count,
+                         double* out, int n);
+
+// products (k_apply.hip)
+void launch_rphase(hipStream_t s, const RStrip* st, int64_t n, int waves, const c128* fac,
+                   const c128* x, c128* t, const int64_t* tmap);
+void launch_qphase(hipStream_t s, const QStrip* st, int64_t n, int waves, const c128* fac,
+                   const c128* t, c128* y);
+void launch_final(hipStream_t s, int32_t N, const int32_t* ptype, const c128* self, const c128* pinv,
+                  const c128* x, const c128* ylev, int nlev, int64_t n, const c128* v,
+                  c128* out_r, c128* out_z);
+void launch_block_apply(hipStream_t s, int32_t N, const int32_t* ptype, const c128* blocks,
+                        const c128* x, c128* y);
+
+// Krylov helpers (k_krylov.hip)
+int krylov_nchunks(int64_t n);
+void launch_multidot(hipStream_t s, const c128* V, int64_t ldv, int ncols, const c128* w, int64_t n,
+                     c128* partial);
+void launch_reduce_dots(hipStream_t s, const c128* partial, int nchunks, int ncols, c128* h, int accumulate);
+void launch_gemv_sub(hipStream_t s, const c128* V, int64_t ldv, int ncols, const c128* h, c128* w, int64_t n);
+void launch_norm2(hipStream_t s, const c128* w, int64_t n, double* partial);
+void launch_reduce_norm(hipStream_t s, const double* partial, int nchunks, double* out);
+void launch_scale_into(hipStream_t s, const c128* w, int64_t n, const double* norm2, c128* out, c128* gslot);
+void launch_givens(hipStream_t s, int j, c128* hcol, c128* H, int ldh, double* cs, c128* sn, c128* gvec,
+                   const double* hnorm2, double* status);
+void launch_trisolve(hipStream_t s, int k, const c128* H, int ldh, const c128* gvec, c128* y);
+void launch_gemv_add(hipStream_t s, const c128* V, int64_t ldv, int ncols, const c128* y, c128* x, int64_t n);
+
+}  // namespace qrvie

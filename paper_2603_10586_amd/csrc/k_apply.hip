@@ -1,0 +1,217 @@
+// The compressed product y = Z_QR x (§5.2: each far block applied as Q (R x)) and the
+// block-diagonal preconditioner z = Z_D^-1 y (§4, eq. 4.2).
+//
+// Layout (internal Morton order, complex128):
+//  * R panels: for each (level, column node J) the R factors of every block with
+//    column J stacked vertically, column-major with ld = total rank.  R-phase:
+//    t = R_panel x_J, one 64-row strip per workgroup, the workgroup's waves
+//    splitting the columns, x_J read as a wave-uniform broadcast.
+//  * Q panels: for each (level, row node I) the Q factors of every block with row I
+//    side by side, column-major with ld = rows of I.  Q-phase: y_l = Q_panel t_I,
+//    the same strip/split scheme; one partial vector per active level.
+//  * Final: per particle, y_p = Z_pp x_p + sum over levels of y_l (fixed order),
+//    optionally r = v - y and z = Z_pp^-1 r, so a preconditioned residual or a
+//    preconditioned product costs one pass.
+// Every lane streams 16-byte complex loads down a column (coalesced 1 KiB per wave
+// per column); no atomics, so results are bitwise reproducible.
+#include "internal.h"
+
+namespace qrvie {
+
+namespace {
+
+__device__ __forceinline__ void cfma(c128& acc, c128 a, c128 b) {
+    acc.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
+    acc.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
+}
+
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+// Streaming 16-byte load: the factors are read once per product, so keep them out of the caches.
+__device__ __forceinline__ c128 load_stream(const c128* p) {
+    const v2d v = __builtin_nontemporal_load(reinterpret_cast<const v2d*>(p));
+    return make_double2(v.x, v.y);
+}
+
+// acc += sum_{j in [j0, j1)} A[j*ld] * v[j]   (A already offset to this lane's row)
+__device__ __forceinline__ c128 column_stream(const c128* __restrict__ A, int64_t ld, const c128* __restrict__ v,
+                                              int j0, int j1) {
+    c128 acc0 = make_double2(0.0, 0.0), acc1 = acc0;
+    int j = j0;
+    for (; j + 8 <= j1; j += 8) {
+        c128 a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = load_stream(A + (int64_t)(j + u) * ld);
+#pragma unroll
+        for (int u = 0; u < 8; u += 2) {
+            cfma(acc0, a[u], v[j + u]);
+            cfma(acc1, a[u + 1], v[j + u + 1]);
+        }
+    }
+    for (; j < j1; ++j) cfma(acc0, A[(int64_t)j * ld], v[j]);
+    return make_double2(acc0.x + acc1.x, acc0.y + acc1.y);
+}
+
+template <int WAVES>
+__global__ void __launch_bounds__(64 * WAVES) k_rphase(const RStrip* __restrict__ strips, const c128* __restrict__ fac,
+                                                       const c128* __restrict__ x, c128* __restrict__ t,
+                                                       const int64_t* __restrict__ tmap) {
+    const RStrip s = strips[blockIdx.x];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int row = min(lane, s.nrows - 1);
+    const int per = (s.ncols + WAVES - 1) / WAVES;
+    const int j0 = min(s.ncols, wv * per), j1 = min(s.ncols, j0 + per);
+    const c128 acc = column_stream(fac + s.a_off + row, s.ld, x + s.x_off, j0, j1);
+    if (WAVES == 1) {
+        if (lane < s.nrows) t[tmap[s.tmap_off + lane]] = acc;
+        return;
+    }
+    __shared__ c128 red[WAVES][64];
+    red[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0 && lane < s.nrows) {
+        c128 sum = red[0][lane];
+#pragma unroll
+        for (int w = 1; w < WAVES; ++w) sum = make_double2(sum.x + red[w][lane].x, sum.y + red[w][lane].y);
+        t[tmap[s.tmap_off + lane]] = sum;
+    }
+}
+
+template <int WAVES>
+__global__ void __launch_bounds__(64 * WAVES) k_qphase(const QStrip* __restrict__ strips, const c128* __restrict__ fac,
+                                                       const c128* __restrict__ t, c128* __restrict__ y) {
+    const QStrip s = strips[blockIdx.x];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int row = min(lane, max(s.nrows - 1, 0));
+    const int per = (s.ncols + WAVES - 1) / WAVES;
+    const int j0 = min(s.ncols, wv * per), j1 = min(s.ncols, j0 + per);
+    const c128 acc = column_stream(fac + s.a_off + row, s.ld, t + s.t_off, j0, j1);
+    if (WAVES == 1) {
+        if (lane < s.nrows) y[s.y_off + lane] = acc;
+        return;
+    }
+    __shared__ c128 red[WAVES][64];
+    red[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0 && lane < s.nrows) {
+        c128 sum = red[0][lane];
+#pragma unroll
+        for (int w = 1; w < WAVES; ++w) sum = make_double2(sum.x + red[w][lane].x, sum.y + red[w][lane].y);
+        y[s.y_off + lane] = sum;
+    }
+}
+
+// 576 threads per particle: thread -> (row = tid % 144, column group = tid / 144).
+constexpr int kGroups = 4;
+constexpr int kColsPerGroup = kNp / kGroups;
+
+__device__ __forceinline__ c128 block_row_product(const c128* __restrict__ M, const c128* vin, int row, int grp) {
+    c128 acc = make_double2(0.0, 0.0);
+    const c128* a = M + row + (int64_t)grp * kColsPerGroup * kNp;
+#pragma unroll 6
+    for (int j = 0; j < kColsPerGroup; ++j) cfma(acc, a[(int64_t)j * kNp], vin[grp * kColsPerGroup + j]);
+    return acc;
+}
+
+__global__ void __launch_bounds__(kNp * kGroups) k_final(const int32_t* __restrict__ ptype, const c128* __restrict__ self,
+                                                         const c128* __restrict__ pinv, const c128* __restrict__ x,
+                                                         const c128* __restrict__ ylev, int nlev, int64_t n,
+                                                         const c128* __restrict__ v, c128* __restrict__ out_r,
+                                                         c128* __restrict__ out_z) {
+    const int p = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int row = tid % kNp, grp = tid / kNp;
+    const int64_t base = (int64_t)p * kNp;
+    const int ty = ptype[p];
+    __shared__ c128 vin[kNp];
+    __shared__ c128 part[kGroups][kNp];
+    if (tid < kNp) vin[tid] = x[base + tid];
+    __syncthreads();
+    part[grp][row] = block_row_product(self + (size_t)ty * kNp * kNp, vin, row, grp);
+    __syncthreads();
+    if (tid < kNp) {
+        c128 y = part[0][row];
+#pragma unroll
+        for (int g = 1; g < kGroups; ++g) y = make_double2(y.x + part[g][row].x, y.y + part[g][row].y);
+        for (int l = 0; l < nlev; ++l) {
+            const c128 a = ylev[(int64_t)l * n + base + row];
+            y = make_double2(y.x + a.x, y.y + a.y);
+        }
+        if (v) {
+            const c128 b = v[base + row];
+            y = make_double2(b.x - y.x, b.y - y.y);
+        }
+        if (out_r) out_r[base + row] = y;
+        vin[row] = y;
+    }
+    if (!out_z) return;
+    __syncthreads();
+    part[grp][row] = block_row_product(pinv + (size_t)ty * kNp * kNp, vin, row, grp);
+    __syncthreads();
+    if (tid < kNp) {
+        c128 z = part[0][row];
+#pragma unroll
+        for (int g = 1; g < kGroups; ++g) z = make_double2(z.x + part[g][row].x, z.y + part[g][row].y);
+        out_z[base + row] = z;
+    }
+}
+
+// y_p = M_type(p) x_p for every particle (the standalone preconditioner).
+__global__ void __launch_bounds__(kNp * kGroups) k_block_apply(const int32_t* __restrict__ ptype,
+                                                               const c128* __restrict__ mats, const c128* __restrict__ x,
+                                                               c128* __restrict__ y) {
+    const int p = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int row = tid % kNp, grp = tid / kNp;
+    const int64_t base = (int64_t)p * kNp;
+    __shared__ c128 vin[kNp];
+    __shared__ c128 part[kGroups][kNp];
+    if (tid < kNp) vin[tid] = x[base + tid];
+    __syncthreads();
+    part[grp][row] = block_row_product(mats + (size_t)ptype[p] * kNp * kNp, vin, row, grp);
+    __syncthreads();
+    if (tid < kNp) {
+        c128 z = part[0][row];
+#pragma unroll
+        for (int g = 1; g < kGroups; ++g) z = make_double2(z.x + part[g][row].x, z.y + part[g][row].y);
+        y[base + row] = z;
+    }
+}
+
+}  // namespace
+
+void launch_rphase(hipStream_t s, const RStrip* st, int64_t n, int waves, const c128* fac, const c128* x, c128* t,
+                   const int64_t* tmap) {
+    if (n <= 0) return;
+    dim3 g((unsigned)n);
+    switch (waves) {
+        case 1: hipLaunchKernelGGL(k_rphase<1>, g, dim3(64), 0, s, st, fac, x, t, tmap); break;
+        case 2: hipLaunchKernelGGL(k_rphase<2>, g, dim3(128), 0, s, st, fac, x, t, tmap); break;
+        case 4: hipLaunchKernelGGL(k_rphase<4>, g, dim3(256), 0, s, st, fac, x, t, tmap); break;
+        case 8: hipLaunchKernelGGL(k_rphase<8>, g, dim3(512), 0, s, st, fac, x, t, tmap); break;
+        default: hipLaunchKernelGGL(k_rphase<16>, g, dim3(1024), 0, s, st, fac, x, t, tmap); break;
+    }
+}
+
+void launch_qphase(hipStream_t s, const QStrip* st, int64_t n, int waves, const c128* fac, const c128* t, c128* y) {
+    if (n <= 0) return;
+    dim3 g((unsigned)n);
+    switch (waves) {
+        case 1: hipLaunchKernelGGL(k_qphase<1>, g, dim3(64), 0, s, st, fac, t, y); break;
+        case 2: hipLaunchKernelGGL(k_qphase<2>, g, dim3(128), 0, s, st, fac, t, y); break;
+        case 4: hipLaunchKernelGGL(k_qphase<4>, g, dim3(256), 0, s, st, fac, t, y); break;
+        case 8: hipLaunchKernelGGL(k_qphase<8>, g, dim3(512), 0, s, st, fac, t, y); break;
+        default: hipLaunchKernelGGL(k_qphase<16>, g, dim3(1024), 0, s, st, fac, t, y); break;
+    }
+}
+
+void launch_final(hipStream_t s, int32_t N, const int32_t* ptype, const c128* self, const c128* pinv, const c128* x,
+                  const c128* ylev, int nlev, int64_t n, const c128* v, c128* out_r, c128* out_z) {
+    hipLaunchKernelGGL(k_final, dim3(N), dim3(kNp * kGroups), 0, s, ptype, self, pinv, x, ylev, nlev, n, v, out_r, out_z);
+}
+
+void launch_block_apply(hipStream_t s, int32_t N, const int32_t* ptype, const c128* mats, const c128* x, c128* y) {
+    hipLaunchKernelGGL(k_block_apply, dim3(N), dim3(kNp * kGroups), 0, s, ptype, mats, x, y);
+}
+
+}  // namespace qrvie

@@ -1,0 +1,772 @@
+// Compressed operator: build (assembly + certified low-rank compression of every
+// far/finest pair block, §5.2-5.4), panel layout for the product, and the product
+// and preconditioner entry points.
+//
+// Compression of a block B (m x n), relative Frobenius tolerance eps (§5.2, eq. 5.3):
+//  * small blocks (both sides <= 2 particles): truncated column-pivoted Householder QR
+//    of B itself;
+//  * larger blocks: a randomised range sketch Y = B Omega (k columns), an orthonormal
+//    basis Q_k of Y (CGS2), W = Q_k^H B, and the truncated pivoted QR of W, whose
+//    tolerance is reduced by the sketch residual ||B||^2 - ||W||^2; Q = Q_k Q_W.
+// Every block is then certified by recomputing ||B - Q R||_F from B; a block that
+// misses eps is redone with a wider sketch.  Only the pairs (I, J) with I before J are
+// compressed; (J, I) stores the transposed factors, so Z_QR is exactly symmetric like Z.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+
+#include "internal.h"
+
+using namespace qrvie;
+
+namespace qrvie {
+std::vector<int32_t> node_children(const qrvie_geom* g, int32_t id);
+void launch_gemm_residual(hipStream_t s, const GemmDesc* d, const int32_t* td, const int32_t* tmn, int64_t nt,
+                          double* partial);
+void launch_form_q(hipStream_t s, const FormQDesc* d, int n, int maxrows);
+}  // namespace qrvie
+
+namespace {
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Device allocations released together.  Host staging copies of uploaded data are kept
+// alive until the stream has been synchronised (asynchronous copies may read them late).
+struct Arena {
+    qrvie_ctx* ctx;
+    std::vector<std::pair<void*, size_t>> bufs;
+    std::vector<std::vector<char>> staged;
+    explicit Arena(qrvie_ctx* c) : ctx(c) {}
+    ~Arena() { release(); }
+    void release() {
+        if (!bufs.empty() || !staged.empty()) (void)hipStreamSynchronize(ctx->stream);
+        for (auto& b : bufs) dfree(ctx, b.first, b.second);
+        bufs.clear();
+        staged.clear();
+    }
+    template <class T>
+    qrvie_status alloc(T** p, size_t count, const char* what) {
+        *p = nullptr;
+        if (count == 0) return QRVIE_OK;
+        qrvie_status st = dalloc(ctx, (void**)p, sizeof(T) * count, what);
+        if (st == QRVIE_OK) bufs.push_back({(void*)*p, sizeof(T) * count});
+        return st;
+    }
+    template <class T>
+    qrvie_status upload(T** p, const std::vector<T>& v, const char* what) {
+        qrvie_status st = alloc(p, v.size(), what);
+        if (st != QRVIE_OK || v.empty()) return st;
+        staged.emplace_back(reinterpret_cast<const char*>(v.data()),
+                            reinterpret_cast<const char*>(v.data()) + sizeof(T) * v.size());
+        return hip_check(ctx, hipMemcpyAsync(*p, staged.back().data(), sizeof(T) * v.size(), hipMemcpyHostToDevice,
+                                             ctx->stream), what);
+    }
+};
+
+template <class T>
+qrvie_status download(qrvie_ctx* ctx, std::vector<T>& v, const T* d, size_t n, const char* what) {
+    v.resize(n);
+    if (n == 0) return QRVIE_OK;
+    qrvie_status st = hip_check(ctx, hipMemcpyAsync(v.data(), d, sizeof(T) * n, hipMemcpyDeviceToHost, ctx->stream), what);
+    if (st == QRVIE_OK) st = hip_check(ctx, hipStreamSynchronize(ctx->stream), what);
+    return st;
+}
+
+#define CHECK(x)                              \
+    do {                                      \
+        qrvie_status _s = (x);                \
+        if (_s != QRVIE_OK) return _s;        \
+    } while (0)
+
+struct Factor {            // compact factors of one primary block
+    c128* Q = nullptr;     // m x r, ld m
+    c128* R = nullptr;     // r x n, ld r
+    int32_t rank = 0;
+    double rel_err = 0.0;
+};
+
+// Tile list of a batch of GEMM descriptors.
+void gemm_tiles(const std::vector<GemmDesc>& d, std::vector<int32_t>& td, std::vector<int32_t>& tmn,
+                std::vector<int32_t>* first = nullptr, std::vector<int32_t>* count = nullptr) {
+    td.clear();
+    tmn.clear();
+    if (first) first->clear();
+    if (count) count->clear();
+    for (size_t i = 0; i < d.size(); ++i) {
+        const int nm = (d[i].m + 63) / 64, nn = (d[i].n + 63) / 64;
+        if (first) first->push_back((int32_t)td.size());
+        if (count) count->push_back(nm * nn);
+        for (int a = 0; a < nm; ++a)
+            for (int b = 0; b < nn; ++b) {
+                td.push_back((int32_t)i);
+                tmn.push_back((a << 16) | b);
+            }
+    }
+}
+
+constexpr int kDirectMaxParticles = 2;   // both sides at most this many particles: direct QRCP
+constexpr int kSketchStart = 128;
+constexpr int kMaxSketch = 512;          // widest sketch the CGS2 kernel orthonormalises
+
+struct Builder {
+    qrvie_op* op;
+    qrvie_ctx* ctx;
+    const qrvie_geom* g;
+    std::vector<BlockRec> blocks;
+    std::vector<Factor> fac;                        // per block (primary only filled)
+    std::vector<std::pair<void*, size_t>> segments; // compact factor storage
+    double eps;
+
+    qrvie_status new_segment(size_t elems, c128** p) {
+        *p = nullptr;
+        if (elems == 0) return QRVIE_OK;
+        CHECK(dalloc(ctx, (void**)p, elems * sizeof(c128), "compact factors"));
+        segments.push_back({(void*)*p, elems * sizeof(c128)});
+        return QRVIE_OK;
+    }
+
+    // Compress the primary blocks `ids`; sketch width k[i] (0 = direct QRCP).
+    qrvie_status compress(const std::vector<int32_t>& ids, const std::vector<int32_t>& kw) {
+        hipStream_t s = ctx->stream;
+        Arena ar(ctx);
+        const size_t nb = ids.size();
+        std::vector<int64_t> m(nb), n(nb), boff(nb);
+        int64_t btot = 0;
+        for (size_t i = 0; i < nb; ++i) {
+            const BlockRec& b = blocks[ids[i]];
+            m[i] = (int64_t)b.rn * kNp;
+            n[i] = (int64_t)b.cn * kNp;
+            boff[i] = btot;
+            btot += m[i] * n[i];
+        }
+        c128* dB;
+        CHECK(ar.alloc(&dB, btot, "block buffer"));
+        {   // assembly
+            std::vector<AsmDesc> ad(nb);
+            std::vector<int32_t> wb, wc;
+            for (size_t i = 0; i < nb; ++i) {
+                const BlockRec& b = blocks[ids[i]];
+                ad[i] = AsmDesc{dB + boff[i], m[i], b.r0, b.rn, b.c0, b.cn};
+                for (int q = 0; q < b.cn; ++q) { wb.push_back((int32_t)i); wc.push_back(q); }
+            }
+            AsmDesc* dad; int32_t *dwb, *dwc;
+            CHECK(ar.upload(&dad, ad, "asm descs"));
+            CHECK(ar.upload(&dwb, wb, "asm work"));
+            CHECK(ar.upload(&dwc, wc, "asm work"));
+            launch_assemble_far(s, g, dad, dwb, dwc, (int64_t)wb.size());
+            CHECK(hip_check(ctx, hipGetLastError(), "assemble far"));
+        }
+        std::vector<size_t> dir, sk;
+        for (size_t i = 0; i < nb; ++i) (kw[i] == 0 ? dir : sk).push_back(i);
+        // Direct blocks are factorised in place, so they get a second copy (assembled
+        // again, which is cheaper than storing it) while B stays the certification reference.
+        std::vector<int64_t> aoff(nb, 0);
+        c128* dA = nullptr;
+        if (!dir.empty()) {
+            int64_t atot = 0;
+            std::vector<AsmDesc> ad;
+            std::vector<int32_t> wb, wc;
+            for (size_t i : dir) {
+                const BlockRec& b = blocks[ids[i]];
+                aoff[i] = atot;
+                atot += m[i] * n[i];
+            }
+            CHECK(ar.alloc(&dA, atot, "factorisation buffer"));
+            for (size_t i : dir) {
+                const BlockRec& b = blocks[ids[i]];
+                ad.push_back(AsmDesc{dA + aoff[i], m[i], b.r0, b.rn, b.c0, b.cn});
+                for (int q = 0; q < b.cn; ++q) { wb.push_back((int32_t)ad.size() - 1); wc.push_back(q); }
+            }
+            AsmDesc* dad; int32_t *dwb, *dwc;
+            CHECK(ar.upload(&dad, ad, "asm descs"));
+            CHECK(ar.upload(&dwb, wb, "asm work"));
+            CHECK(ar.upload(&dwc, wc, "asm work"));
+            launch_assemble_far(s, g, dad, dwb, dwc, (int64_t)wb.size());
+            CHECK(hip_check(ctx, hipGetLastError(), "assemble far (work copy)"));
+        }
+
+        // per-block results
+        int32_t* d_rank; double *d_trail, *d_norm2;
+        CHECK(ar.alloc(&d_rank, nb, "ranks"));
+        CHECK(ar.alloc(&d_trail, nb, "trail"));
+        CHECK(ar.alloc(&d_norm2, nb, "norm2"));
+
+        // QRCP workspaces sized per block
+        std::vector<int64_t> wsn(nb), wsk(nb);
+        int64_t tot_n = 0, tot_k = 0;
+        // sketch buffers
+        std::vector<int64_t> yoff(nb, 0), woff(nb, 0), kk(nb, 0);
+        int64_t ytot = 0;
+        for (size_t i : sk) {
+            kk[i] = std::min<int64_t>(kw[i], std::min(m[i], n[i]));
+            yoff[i] = ytot;
+            ytot += m[i] * kk[i];
+        }
+        c128* dY = nullptr;
+        CHECK(ar.alloc(&dY, ytot, "sketch"));
+        std::vector<int32_t> kept(nb, 0);
+        std::vector<double> normB2(nb, 0.0);
+        if (!sk.empty()) {
+            // Y = B Omega
+            std::vector<GemmDesc> gd;
+            for (size_t i : sk)
+                gd.push_back(GemmDesc{dB + boff[i], m[i], nullptr, 0, dY + yoff[i], m[i], (int32_t)m[i], (int32_t)kk[i],
+                                      (int32_t)n[i], op->opts.seed * 0x9E3779B97F4A7C15ull + (uint64_t)ids[i], nullptr});
+            std::vector<int32_t> td, tmn;
+            gemm_tiles(gd, td, tmn);
+            GemmDesc* dgd; int32_t *dtd, *dtmn;
+            CHECK(ar.upload(&dgd, gd, "gemm descs"));
+            CHECK(ar.upload(&dtd, td, "gemm tiles"));
+            CHECK(ar.upload(&dtmn, tmn, "gemm tiles"));
+            launch_gemm(s, 2, dgd, dtd, dtmn, (int64_t)td.size());
+            // ||B||^2
+            std::vector<const c128*> ptr;
+            std::vector<int64_t> len;
+            for (size_t i : sk) { ptr.push_back(dB + boff[i]); len.push_back(m[i] * n[i]); }
+            const c128** dptr; int64_t* dlen; double* dn2;
+            CHECK(ar.upload(&dptr, ptr, "frob ptrs"));
+            CHECK(ar.upload(&dlen, len, "frob lens"));
+            CHECK(ar.alloc(&dn2, sk.size(), "frob out"));
+            launch_frob2(s, dptr, dlen, dn2, (int)sk.size());
+            // orthonormal basis of Y
+            std::vector<Cgs2Desc> cd;
+            int32_t* dkept;
+            CHECK(ar.alloc(&dkept, sk.size(), "kept"));
+            for (size_t a = 0; a < sk.size(); ++a) {
+                const size_t i = sk[a];
+                cd.push_back(Cgs2Desc{dY + yoff[i], (int32_t)m[i], (int32_t)kk[i], (int32_t)m[i], 1e-12, dkept + a});
+            }
+            Cgs2Desc* dcd;
+            CHECK(ar.upload(&dcd, cd, "cgs2 descs"));
+            launch_cgs2(s, dcd, (int)cd.size());
+            CHECK(hip_check(ctx, hipGetLastError(), "sketch"));
+            std::vector<int32_t> hk;
+            std::vector<double> hn2;
+            CHECK(download(ctx, hk, dkept, sk.size(), "kept"));
+            CHECK(download(ctx, hn2, dn2, sk.size(), "norms"));
+            for (size_t a = 0; a < sk.size(); ++a) { kept[sk[a]] = hk[a]; normB2[sk[a]] = hn2[a]; }
+        }
+        int64_t wtot = 0;
+        for (size_t i : sk) { woff[i] = wtot; wtot += (int64_t)kept[i] * n[i]; }
+        c128* dW = nullptr;
+        CHECK(ar.alloc(&dW, wtot, "projected block"));
+        if (!sk.empty()) {
+            std::vector<GemmDesc> gd;
+            for (size_t i : sk)
+                gd.push_back(GemmDesc{dY + yoff[i], m[i], dB + boff[i], m[i], dW + woff[i], kept[i], kept[i],
+                                      (int32_t)n[i], (int32_t)m[i], 0, nullptr});
+            std::vector<int32_t> td, tmn;
+            gemm_tiles(gd, td, tmn);
+            GemmDesc* dgd; int32_t *dtd, *dtmn;
+            CHECK(ar.upload(&dgd, gd, "gemm descs"));
+            CHECK(ar.upload(&dtd, td, "gemm tiles"));
+            CHECK(ar.upload(&dtmn, tmn, "gemm tiles"));
+            launch_gemm(s, 1, dgd, dtd, dtmn, (int64_t)td.size());
+        }
+        // QRCP: direct on B, sketch on W
+        std::vector<QrcpDesc> qd(nb);
+        std::vector<int64_t> am(nb), an(nb);
+        for (size_t i = 0; i < nb; ++i) {
+            am[i] = kw[i] == 0 ? m[i] : kept[i];
+            an[i] = n[i];
+            wsn[i] = tot_n; tot_n += an[i];
+            wsk[i] = tot_k; tot_k += std::min(am[i], an[i]);
+        }
+        double* dcn; int32_t* dperm; double* dtau; c128* dwtop;
+        CHECK(ar.alloc(&dcn, std::max<int64_t>(tot_n, 1), "qrcp norms"));
+        CHECK(ar.alloc(&dperm, std::max<int64_t>(tot_n, 1), "qrcp perm"));
+        CHECK(ar.alloc(&dtau, std::max<int64_t>(tot_k, 1), "qrcp tau"));
+        CHECK(ar.alloc(&dwtop, std::max<int64_t>(tot_k, 1), "qrcp w"));
+        const double rel2 = (0.95 * eps) * (0.95 * eps);
+        int maxrows_dir = 0, maxrows_sk = 0;
+        std::vector<QrcpDesc> qdir, qsk;
+        for (size_t i = 0; i < nb; ++i) {
+            QrcpDesc q{};
+            q.A = kw[i] == 0 ? dA + aoff[i] : dW + woff[i];
+            q.m = (int32_t)am[i];
+            q.n = (int32_t)an[i];
+            q.lda = (int32_t)std::max<int64_t>(am[i], 1);
+            q.kmax = (int32_t)std::min(am[i], an[i]);
+            q.colnorm2 = dcn + wsn[i];
+            q.perm = dperm + wsn[i];
+            q.tau = dtau + wsk[i];
+            q.wtop = dwtop + wsk[i];
+            q.rel2 = rel2;
+            if (kw[i] == 0) { q.base2 = 0.0; q.sub2 = 0.0; }
+            else { q.base2 = normB2[i]; q.sub2 = -1.0; }     // sub2 < 0: subtract base2 - ||W||^2
+            q.rank_out = d_rank + i;
+            q.trail2_out = d_trail + i;
+            q.norm2_out = d_norm2 + i;
+            qd[i] = q;
+            if (kw[i] == 0) { qdir.push_back(q); maxrows_dir = std::max<int>(maxrows_dir, q.m); }
+            else { qsk.push_back(q); maxrows_sk = std::max<int>(maxrows_sk, q.m); }
+        }
+        QrcpDesc *dqdir, *dqsk;
+        CHECK(ar.upload(&dqdir, qdir, "qrcp descs"));
+        CHECK(ar.upload(&dqsk, qsk, "qrcp descs"));
+        launch_qrcp(s, dqdir, (int)qdir.size(), maxrows_dir);
+        launch_qrcp(s, dqsk, (int)qsk.size(), maxrows_sk);
+        CHECK(hip_check(ctx, hipGetLastError(), "qrcp"));
+        std::vector<int32_t> rank;
+        std::vector<double> n2;
+        CHECK(download(ctx, rank, d_rank, nb, "ranks"));
+        CHECK(download(ctx, n2, d_norm2, nb, "norms"));
+        for (size_t i = 0; i < nb; ++i)
+            if (kw[i] == 0) normB2[i] = n2[i];
+
+        // compact storage
+        int64_t ctot = 0;
+        std::vector<int64_t> qo(nb), ro(nb);
+        for (size_t i = 0; i < nb; ++i) {
+            qo[i] = ctot; ctot += m[i] * rank[i];
+            ro[i] = ctot; ctot += (int64_t)rank[i] * n[i];
+        }
+        c128* seg;
+        CHECK(new_segment(ctot, &seg));
+        // Q
+        {
+            std::vector<FormQDesc> fdir, fsk;
+            int64_t qwtot = 0;
+            std::vector<int64_t> qwo(nb, 0);
+            for (size_t i : sk) { qwo[i] = qwtot; qwtot += (int64_t)kept[i] * rank[i]; }
+            c128* dQW;
+            CHECK(ar.alloc(&dQW, qwtot, "sketch Q"));
+            for (size_t i = 0; i < nb; ++i) {
+                if (rank[i] == 0) continue;
+                if (kw[i] == 0)
+                    fdir.push_back(FormQDesc{dA + aoff[i], (int32_t)m[i], (int32_t)m[i], rank[i], dtau + wsk[i],
+                                             dwtop + wsk[i], seg + qo[i], (int32_t)m[i]});
+                else
+                    fsk.push_back(FormQDesc{dW + woff[i], kept[i], std::max(kept[i], 1), rank[i], dtau + wsk[i],
+                                            dwtop + wsk[i], dQW + qwo[i], std::max(kept[i], 1)});
+            }
+            FormQDesc *dfd, *dfs;
+            CHECK(ar.upload(&dfd, fdir, "formq descs"));
+            CHECK(ar.upload(&dfs, fsk, "formq descs"));
+            launch_form_q(s, dfd, (int)fdir.size(), maxrows_dir);
+            launch_form_q(s, dfs, (int)fsk.size(), maxrows_sk);
+            if (!sk.empty()) {
+                std::vector<GemmDesc> gd;
+                for (size_t i : sk)
+                    if (rank[i] > 0)
+                        gd.push_back(GemmDesc{dY + yoff[i], m[i], dQW + qwo[i], std::max(kept[i], 1), seg + qo[i], m[i],
+                                              (int32_t)m[i], rank[i], kept[i], 0, nullptr});
+                std::vector<int32_t> td, tmn;
+                gemm_tiles(gd, td, tmn);
+                GemmDesc* dgd; int32_t *dtd, *dtmn;
+                CHECK(ar.upload(&dgd, gd, "gemm descs"));
+                CHECK(ar.upload(&dtd, td, "gemm tiles"));
+                CHECK(ar.upload(&dtmn, tmn, "gemm tiles"));
+                launch_gemm(s, 0, dgd, dtd, dtmn, (int64_t)td.size());
+            }
+            CHECK(hip_check(ctx, hipGetLastError(), "form Q"));
+            // R
+            std::vector<ExtractRDesc> ed;
+            for (size_t i = 0; i < nb; ++i)
+                if (rank[i] > 0)
+                    ed.push_back(ExtractRDesc{qd[i].A, qd[i].lda, rank[i], (int32_t)n[i], qd[i].perm, seg + ro[i], rank[i]});
+            ExtractRDesc* ded;
+            CHECK(ar.upload(&ded, ed, "extract descs"));
+            launch_extract_r(s, ded, (int)ed.size());
+            CHECK(hip_check(ctx, hipGetLastError(), "extract R"));
+        }
+        // certification: ||B - Q R||_F^2 from B itself
+        {
+            std::vector<GemmDesc> gd;
+            for (size_t i = 0; i < nb; ++i)
+                gd.push_back(GemmDesc{seg + qo[i], m[i], seg + ro[i], std::max(rank[i], 1), dB + boff[i], m[i],
+                                      (int32_t)m[i], (int32_t)n[i], rank[i], 0, nullptr});
+            std::vector<int32_t> td, tmn, first, count;
+            gemm_tiles(gd, td, tmn, &first, &count);
+            GemmDesc* dgd; int32_t *dtd, *dtmn, *dfirst, *dcount; double *dpart, *derr;
+            CHECK(ar.upload(&dgd, gd, "cert descs"));
+            CHECK(ar.upload(&dtd, td, "cert tiles"));
+            CHECK(ar.upload(&dtmn, tmn, "cert tiles"));
+            CHECK(ar.upload(&dfirst, first, "cert tiles"));
+            CHECK(ar.upload(&dcount, count, "cert tiles"));
+            CHECK(ar.alloc(&dpart, std::max<size_t>(td.size(), 1), "cert partials"));
+            CHECK(ar.alloc(&derr, nb, "cert err"));
+            launch_gemm_residual(s, dgd, dtd, dtmn, (int64_t)td.size(), dpart);
+            launch_sum_partials(s, dpart, dfirst, dcount, derr, (int)nb);
+            CHECK(hip_check(ctx, hipGetLastError(), "certify"));
+            std::vector<double> err2;
+            CHECK(download(ctx, err2, derr, nb, "cert err"));
+            for (size_t i = 0; i < nb; ++i) {
+                Factor& f = fac[ids[i]];
+                f.Q = seg + qo[i];
+                f.R = seg + ro[i];
+                f.rank = rank[i];
+                f.rel_err = normB2[i] > 0.0 ? std::sqrt(err2[i] / normB2[i]) : 0.0;
+            }
+        }
+        // retry blocks that missed eps with a wider sketch
+        std::vector<int32_t> rids, rk;
+        for (size_t i = 0; i < nb; ++i) {
+            if (fac[ids[i]].rel_err <= eps) continue;
+            const int64_t full = std::min<int64_t>(std::min(m[i], n[i]), kMaxSketch);
+            if (kw[i] == 0 || kk[i] >= full) {
+                set_err(ctx, "compression: block " + std::to_string(ids[i]) + " misses eps: rel err " +
+                                 std::to_string(fac[ids[i]].rel_err) + ", ||B||^2 " + std::to_string(normB2[i]) +
+                                 ", rank " + std::to_string(rank[i]) + ", m " + std::to_string(m[i]) + ", n " +
+                                 std::to_string(n[i]) + ", sketch " + std::to_string(kk[i]));
+                return QRVIE_ERR_DEVICE;
+            }
+            rids.push_back(ids[i]);
+            rk.push_back((int32_t)std::min<int64_t>(2 * kk[i], full));
+        }
+        ar.release();
+        if (!rids.empty()) return compress(rids, rk);
+        return QRVIE_OK;
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+qrvie_status qrvie_op_footprint_estimate(const qrvie_geom* g, const qrvie_compress_opts* o, size_t* bytes) {
+    if (!g || !o || !bytes) return QRVIE_ERR_INVALID_ARG;
+    // rank model: r ~ 64 per block side (mid-size arrays at eps = 1e-6 measure 27-89)
+    double elems = 0.0;
+    const double rmodel = 64.0 + 8.0 * std::max(0.0, -std::log10(o->eps) - 6.0);
+    for (const BlockRec& b : g->blocks) {
+        const double mm = (double)b.rn * kNp, nn = (double)b.cn * kNp;
+        elems += std::min(mm * nn, (mm + nn) * std::min(rmodel, std::min(mm, nn)));
+    }
+    const double self = 2.0 * g->types.size() * kNp * kNp;
+    const double vec = 8.0 * (double)g->ndof();
+    *bytes = (size_t)((elems * 1.5 + self + vec) * sizeof(c128));
+    return QRVIE_OK;
+}
+
+qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_compress_opts* o, qrvie_op** out) {
+    if (!ctx || !g || !o || !out) return QRVIE_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!(o->eps > 0.0) || !(o->eps < 1.0)) { set_err(ctx, "op_create: eps must be in (0, 1)"); return QRVIE_ERR_INVALID_ARG; }
+    if (o->far_prec != QRVIE_PREC_C128 || o->near_prec != QRVIE_PREC_C128 || o->share_transpose != 0 ||
+        o->max_block_rows < 0) {
+        set_err(ctx, "op_create: unsupported precision or option");
+        return QRVIE_ERR_INVALID_ARG;
+    }
+    size_t est = 0;
+    qrvie_op_footprint_estimate(g, o, &est);
+    if (ctx->budget && ctx->in_use + est > ctx->budget) {
+        set_err(ctx, "op_create: footprint estimate " + std::to_string(est) + " exceeds the remaining HBM budget");
+        return QRVIE_ERR_OUT_OF_MEMORY;
+    }
+    hipStream_t s = ctx->stream;
+    auto* op = new qrvie_op;
+    op->ctx = ctx;
+    op->g = g;
+    op->opts = *o;
+    op->ntypes = (int32_t)g->types.size();
+    auto fail = [&](qrvie_status st) {
+        qrvie_op_destroy(op);
+        return st;
+    };
+    const double t0 = now_s();
+    const size_t selfb = sizeof(c128) * (size_t)op->ntypes * kNp * kNp;
+    qrvie_status st = QRVIE_OK;
+    auto keep = [&](void** p, size_t bytes, const char* what) {
+        if (st != QRVIE_OK) return;
+        st = dalloc(ctx, p, bytes, what);
+        if (st == QRVIE_OK) op->allocs.push_back({*p, bytes});
+    };
+    keep((void**)&op->d_self, selfb, "self blocks");
+    keep((void**)&op->d_pinv, selfb, "preconditioner");
+    if (st != QRVIE_OK) return fail(st);
+    launch_assemble_self(s, g, op->d_self, op->ntypes);
+    st = hip_check(ctx, hipMemcpyAsync(op->d_pinv, op->d_self, selfb, hipMemcpyDeviceToDevice, s), "copy self");
+    if (st != QRVIE_OK) return fail(st);
+    int* dinfo = nullptr;
+    st = dalloc(ctx, (void**)&dinfo, sizeof(int) * op->ntypes, "invert info");
+    if (st != QRVIE_OK) return fail(st);
+    (void)hipMemsetAsync(dinfo, 0, sizeof(int) * op->ntypes, s);
+    launch_invert(s, op->d_pinv, op->ntypes, dinfo);
+    std::vector<int> hinfo;
+    st = download(ctx, hinfo, dinfo, op->ntypes, "invert info");
+    dfree(ctx, dinfo, sizeof(int) * op->ntypes);
+    if (st != QRVIE_OK) return fail(st);
+    for (int t = 0; t < op->ntypes; ++t)
+        if (hinfo[t] != 0) {
+            set_err(ctx, "op_create: singular self block");
+            return fail(QRVIE_ERR_DEVICE);
+        }
+    const double t1 = now_s();
+    op->stats.t_precond_setup_s = t1 - t0;
+
+    // block list, with the optional row cap splitting far pairs into child pairs
+    Builder bld{op, ctx, g, {}, {}, {}, o->eps};
+    {
+        std::vector<BlockRec> work(g->blocks.begin(), g->blocks.end());
+        const int64_t cap = o->max_block_rows;
+        while (!work.empty()) {
+            BlockRec b = work.back();
+            work.pop_back();
+            if (cap > 0 && b.level < g->L && ((int64_t)b.rn * kNp > cap || (int64_t)b.cn * kNp > cap)) {
+                for (int32_t ci : node_children(g, b.rnode))
+                    for (int32_t cj : node_children(g, b.cnode)) {
+                        const auto& a = g->nodes[ci];
+                        const auto& c = g->nodes[cj];
+                        work.push_back(BlockRec{b.level + 1, a.first, a.count, c.first, c.count, -1,
+                                                a.first < c.first ? 1 : 0, ci, cj});
+                    }
+            } else {
+                bld.blocks.push_back(b);
+            }
+        }
+        std::sort(bld.blocks.begin(), bld.blocks.end(), [](const BlockRec& a, const BlockRec& b) {
+            if (a.level != b.level) return a.level < b.level;
+            if (a.r0 != b.r0) return a.r0 < b.r0;
+            return a.c0 < b.c0;
+        });
+        std::map<std::tuple<int, int, int>, int32_t> idx;
+        for (size_t i = 0; i < bld.blocks.size(); ++i)
+            idx[{bld.blocks[i].level, bld.blocks[i].r0, bld.blocks[i].c0}] = (int32_t)i;
+        for (auto& b : bld.blocks) b.mirror = idx.at({b.level, b.c0, b.r0});
+    }
+    const size_t NB = bld.blocks.size();
+    bld.fac.resize(NB);
+
+    // compress primary blocks in chunks bounded by the materialised block bytes
+    const int64_t chunk_elems = (int64_t)(std::min<double>(8.0 * (1ull << 30),
+                                          ctx->budget ? std::max<double>(2.56e8, (double)(ctx->budget - ctx->in_use) / 4.0)
+                                                      : 8.0 * (1ull << 30)) / sizeof(c128));
+    {
+        std::vector<int32_t> ids, kw;
+        int64_t acc = 0;
+        for (size_t i = 0; i <= NB; ++i) {
+            bool flush = (i == NB);
+            if (!flush) {
+                const BlockRec& b = bld.blocks[i];
+                if (!b.primary) continue;
+                const int64_t e = (int64_t)b.rn * kNp * b.cn * kNp;
+                if (acc > 0 && acc + e > chunk_elems) flush = true;
+                if (!flush) {
+                    ids.push_back((int32_t)i);
+                    const bool direct = b.rn <= kDirectMaxParticles && b.cn <= kDirectMaxParticles;
+                    kw.push_back(direct ? 0 : kSketchStart);
+                    acc += e;
+                    continue;
+                }
+            }
+            if (!ids.empty()) {
+                st = bld.compress(ids, kw);
+                if (st != QRVIE_OK) {
+                    for (auto& sg : bld.segments) dfree(ctx, sg.first, sg.second);
+                    return fail(st);
+                }
+            }
+            ids.clear();
+            kw.clear();
+            acc = 0;
+            if (i < NB) --i;   // re-visit the block that did not fit
+        }
+    }
+    (void)hipStreamSynchronize(s);
+    const double t2 = now_s();
+    op->stats.t_compression_s = t2 - t1;
+
+    // ranks of mirrors; per-block bookkeeping
+    op->blocks = bld.blocks;
+    op->rank.assign(NB, 0);
+    op->relerr.assign(NB, 0.0);
+    for (size_t i = 0; i < NB; ++i) {
+        const BlockRec& b = bld.blocks[i];
+        const Factor& f = bld.fac[b.primary ? i : b.mirror];
+        op->rank[i] = f.rank;
+        op->relerr[i] = f.rel_err;
+    }
+
+    // panel layout
+    const int64_t n = g->ndof();
+    std::vector<int> active(g->L + 2, -1);
+    for (const auto& b : bld.blocks) active[b.level] = 1;
+    int nact = 0;
+    for (int l = 0; l <= g->L + 1; ++l)
+        if (active[l] > 0) active[l] = nact++;
+    op->n_active = nact;
+    op->q_off.assign(NB, 0);
+    op->r_off.assign(NB, 0);
+    op->r_ld.assign(NB, 0);
+    std::vector<int64_t> toff(NB, 0);
+    std::vector<RStrip> rstr;
+    std::vector<QStrip> qstr;
+    std::vector<int64_t> tmap;
+    int64_t fcur = 0, tcur = 0;
+    for (int l = 0; l <= g->L; ++l) {
+        if (active[l] < 0) continue;
+        // Q panels over every occupied node of the level
+        int64_t qbegin = (int64_t)qstr.size();
+        int maxK = 0;
+        size_t bi = 0;
+        while (bi < NB && bld.blocks[bi].level != l) ++bi;
+        for (int32_t I : g->level_nodes[l]) {
+            const auto& nd = g->nodes[I];
+            const int64_t mI = (int64_t)nd.count * kNp;
+            size_t b0 = bi;
+            while (b0 < NB && bld.blocks[b0].level == l && bld.blocks[b0].r0 < nd.first) ++b0;
+            size_t b1 = b0;
+            int64_t K = 0;
+            while (b1 < NB && bld.blocks[b1].level == l && bld.blocks[b1].r0 == nd.first) { K += op->rank[b1]; ++b1; }
+            const int64_t base = fcur;
+            fcur += mI * K;
+            int64_t col = 0;
+            for (size_t b = b0; b < b1; ++b) {
+                op->q_off[b] = base + mI * col;
+                toff[b] = tcur + col;
+                col += op->rank[b];
+            }
+            for (int64_t r0 = 0; r0 < mI; r0 += kStrip)
+                qstr.push_back(QStrip{base + r0, (int32_t)mI, (int32_t)K, (int32_t)std::min<int64_t>(kStrip, mI - r0),
+                                      (int64_t)active[l] * n + (int64_t)nd.first * kNp + r0, tcur});
+            tcur += K;
+            maxK = std::max<int>(maxK, (int)K);
+            bi = b1;
+        }
+        // R panels per column node
+        std::map<int32_t, std::vector<size_t>> bycol;
+        int maxN = 0;
+        for (size_t b = 0; b < NB; ++b)
+            if (bld.blocks[b].level == l) bycol[bld.blocks[b].c0].push_back(b);
+        int64_t rbegin = (int64_t)rstr.size();
+        for (auto& kv : bycol) {
+            const BlockRec& b0 = bld.blocks[kv.second.front()];
+            const int64_t nJ = (int64_t)b0.cn * kNp;
+            int64_t Kp = 0;
+            for (size_t b : kv.second) Kp += op->rank[b];
+            const int64_t base = fcur;
+            fcur += Kp * nJ;
+            const int64_t tbase = (int64_t)tmap.size();
+            int64_t row = 0;
+            for (size_t b : kv.second) {
+                op->r_off[b] = base + row;
+                op->r_ld[b] = (int32_t)Kp;
+                for (int k = 0; k < op->rank[b]; ++k) tmap.push_back(toff[b] + k);
+                row += op->rank[b];
+            }
+            for (int64_t r0 = 0; r0 < Kp; r0 += kStrip)
+                rstr.push_back(RStrip{base + r0, (int32_t)Kp, (int32_t)nJ, (int32_t)std::min<int64_t>(kStrip, Kp - r0),
+                                      b0.c0 * kNp, tbase + r0});
+            maxN = std::max<int>(maxN, (int)nJ);
+        }
+        auto waves_for = [](int cols, int per) {
+            int w = 1;
+            while (w < 16 && w * per < cols) w *= 2;
+            return w;
+        };
+        op->qlaunch.push_back({l, qbegin, (int64_t)qstr.size() - qbegin, waves_for(maxK, 384)});
+        op->rlaunch.push_back({l, rbegin, (int64_t)rstr.size() - rbegin, waves_for(maxN, 512)});
+    }
+    op->fac_elems = fcur;
+    op->t_len = tcur;
+    op->tmap_len = (int64_t)tmap.size();
+
+    keep((void**)&op->d_fac, sizeof(c128) * (size_t)std::max<int64_t>(fcur, 1), "factor panels");
+    keep((void**)&op->d_t, sizeof(c128) * (size_t)std::max<int64_t>(tcur, 1), "rank vector");
+    keep((void**)&op->d_tmap, sizeof(int64_t) * std::max<size_t>(tmap.size(), 1), "rank map");
+    keep((void**)&op->d_rstrips, sizeof(RStrip) * std::max<size_t>(rstr.size(), 1), "R strips");
+    keep((void**)&op->d_qstrips, sizeof(QStrip) * std::max<size_t>(qstr.size(), 1), "Q strips");
+    keep((void**)&op->d_ylev, sizeof(c128) * (size_t)std::max<int64_t>(nact * n, 1), "level partials");
+    if (st != QRVIE_OK) {
+        for (auto& sg : bld.segments) dfree(ctx, sg.first, sg.second);
+        return fail(st);
+    }
+    if (!tmap.empty()) (void)hipMemcpyAsync(op->d_tmap, tmap.data(), sizeof(int64_t) * tmap.size(), hipMemcpyHostToDevice, s);
+    if (!rstr.empty()) (void)hipMemcpyAsync(op->d_rstrips, rstr.data(), sizeof(RStrip) * rstr.size(), hipMemcpyHostToDevice, s);
+    if (!qstr.empty()) (void)hipMemcpyAsync(op->d_qstrips, qstr.data(), sizeof(QStrip) * qstr.size(), hipMemcpyHostToDevice, s);
+    st = hip_check(ctx, hipStreamSynchronize(s), "upload layout");   // the host vectors die at return
+    if (st != QRVIE_OK) {
+        for (auto& sg : bld.segments) dfree(ctx, sg.first, sg.second);
+        return fail(st);
+    }
+
+    // pack compact factors into the panels
+    {
+        std::vector<PackDesc> pd;
+        for (size_t i = 0; i < NB; ++i) {
+            const BlockRec& b = bld.blocks[i];
+            if (!b.primary || op->rank[i] == 0) continue;
+            const Factor& f = bld.fac[i];
+            const int32_t mm = b.rn * kNp, nn = b.cn * kNp, r = f.rank;
+            const size_t j = (size_t)b.mirror;
+            pd.push_back(PackDesc{f.Q, mm, r, mm, op->d_fac + op->q_off[i], mm, 0});           // Q_IJ
+            pd.push_back(PackDesc{f.R, r, nn, r, op->d_fac + op->r_off[i], op->r_ld[i], 0});   // R_IJ
+            pd.push_back(PackDesc{f.R, r, nn, r, op->d_fac + op->q_off[j], nn, 1});            // Q_JI = R_IJ^T
+            pd.push_back(PackDesc{f.Q, mm, r, mm, op->d_fac + op->r_off[j], op->r_ld[j], 1});  // R_JI = Q_IJ^T
+        }
+        PackDesc* dpd = nullptr;
+        if (!pd.empty()) {
+            st = dalloc(ctx, (void**)&dpd, sizeof(PackDesc) * pd.size(), "pack descs");
+            if (st == QRVIE_OK)
+                st = hip_check(ctx, hipMemcpyAsync(dpd, pd.data(), sizeof(PackDesc) * pd.size(), hipMemcpyHostToDevice, s), "pack");
+            if (st == QRVIE_OK) {
+                launch_pack(s, dpd, (int)pd.size());
+                st = hip_check(ctx, hipGetLastError(), "pack");
+            }
+            if (st == QRVIE_OK) st = hip_check(ctx, hipStreamSynchronize(s), "pack");
+            dfree(ctx, dpd, sizeof(PackDesc) * pd.size());
+        }
+        for (auto& sg : bld.segments) dfree(ctx, sg.first, sg.second);
+        bld.segments.clear();
+        if (st != QRVIE_OK) return fail(st);
+    }
+    const double t3 = now_s();
+    op->stats.t_compression_s += t3 - t2;
+
+    // statistics (eqs. 5.5-5.6 and the product's algorithmic bytes)
+    qrvie_op_stats& S = op->stats;
+    S.n_levels = g->L;
+    S.n_blocks = (int64_t)NB;
+    S.n_self_types = op->ntypes;
+    for (int l = 0; l < QRVIE_MAX_LEVELS; ++l) { S.min_rank_level[l] = 0; S.max_rank_level[l] = 0; }
+    std::vector<double> rsum(QRVIE_MAX_LEVELS, 0.0);
+    int64_t nqr = (int64_t)g->N * kNp * kNp, sum_r = 0;
+    double maxerr = 0.0;
+    for (size_t i = 0; i < NB; ++i) {
+        const BlockRec& b = bld.blocks[i];
+        const int l = std::min(b.level, QRVIE_MAX_LEVELS - 1);
+        const int r = op->rank[i];
+        if (S.n_blocks_level[l] == 0 || r < S.min_rank_level[l]) S.min_rank_level[l] = r;
+        S.max_rank_level[l] = std::max(S.max_rank_level[l], r);
+        S.n_blocks_level[l]++;
+        rsum[l] += r;
+        nqr += ((int64_t)b.rn * kNp + (int64_t)b.cn * kNp) * r;
+        sum_r += r;
+        maxerr = std::max(maxerr, op->relerr[i]);
+    }
+    for (int l = 0; l < QRVIE_MAX_LEVELS; ++l)
+        S.mean_rank_level[l] = S.n_blocks_level[l] ? rsum[l] / S.n_blocks_level[l] : 0.0;
+    S.n_qr_entries = nqr;
+    S.gain = (double)n * (double)n / (double)nqr;
+    S.max_block_rel_err = maxerr;
+    S.apply_bytes = (int64_t)sizeof(c128) * ((nqr - (int64_t)g->N * kNp * kNp) + (int64_t)op->ntypes * kNp * kNp +
+                                             2 * n + 2 * sum_r);
+    for (auto& a : op->allocs) op->dev_bytes += a.second;
+    S.device_bytes = (int64_t)op->dev_bytes;
+    S.t_assembly_s = 0.0;  // assembly is fused into compression; see t_compression_s
+    *out = op;
+    return QRVIE_OK;
+}
+
+qrvie_status qrvie_op_stats_get(const qrvie_op* op, qrvie_op_stats* out) {
+    if (!op || !out) return QRVIE_ERR_INVALID_ARG;
+    *out = op->stats;
+    return QRVIE_OK;
+}
+
+int64_t qrvie_op_num_blocks(const qrvie_op* op) { return op ? (int64_t)op->rank.size() : 0; }
+
+void qrvie_op_destroy(qrvie_op* op) {
+    if (!op) return;
+    qrvie_ctx* ctx = op->ctx;
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto& a : op->allocs) dfree(ctx, a.first, a.second);
+    delete op;
+}
+
+}  // extern "C"
