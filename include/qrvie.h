@@ -196,6 +196,16 @@ void         qrvie_op_destroy(qrvie_op* op);
  * product Z_D x + sum_b Q_b (R_b x_J) of §5.2. */
 qrvie_status qrvie_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs,
                          const qrvie_c128* x, int64_t ldx, qrvie_c128* y, int64_t ldy);
+/*
+ * Stage timers of the single-RHS product (the product stage of the paper's timing
+ * table, §6.5), measured with HIP events on the context stream over `reps` products
+ * of a fixed internal test vector.  ms[0] R-phase (t = R x for every block), ms[1]
+ * Q-phase (y_l = Q t per level), ms[2] final pass (self blocks Z_pp x + level sum),
+ * ms[3] whole product; averages per product.  bytes[0..3]: algorithmic HBM bytes of
+ * the same stages per product (factor, self-block and vector traffic; the per-level
+ * partial vectors are counted as overhead, not algorithmic bytes).  Host arrays of 4.
+ */
+qrvie_status qrvie_op_profile_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t reps, double* ms, int64_t* bytes);
 /* z = Z_D^-1 y, the block-diagonal left preconditioner (§4, eq. 4.2). */
 qrvie_status qrvie_precondition(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs,
                                 const qrvie_c128* y, int64_t ldy, qrvie_c128* z, int64_t ldz);
@@ -213,7 +223,8 @@ qrvie_status qrvie_rhs_plane_waves(qrvie_ctx* ctx, const qrvie_geom* g, int32_t 
 enum { QRVIE_SOLVE_FP64 = 0 };
 
 typedef struct {
-    int32_t restart;      /* GMRES(m) restart length, 1..256 */
+    int32_t restart;      /* GMRES(m) restart length, 1..16384 (m >= max_iter: unrestarted, as in §6);
+                             the basis takes (m + 1) x n complex128 of device memory */
     int32_t max_iter;     /* total Arnoldi steps per right-hand side */
     int32_t mode;         /* QRVIE_SOLVE_FP64 */
     double  tol;          /* relative residual; converged when both the preconditioned
@@ -226,6 +237,7 @@ typedef struct {
     double  rel_res_prec, rel_res_true;
     int32_t n_apply, n_prec;
     double  t_apply_s, t_prec_s, t_krylov_s, t_total_s;
+    int32_t n_reorth;     /* Arnoldi steps that needed the second Gram-Schmidt pass */
 } qrvie_solve_info;
 
 /*

@@ -62,6 +62,15 @@ def particle_dofs(particles) -> np.ndarray:
     return (p[:, None] * N_DOF_PER_PARTICLE + np.arange(N_DOF_PER_PARTICLE)[None, :]).reshape(-1)
 
 
+def factor_apply(factors, x: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """y += sum over blocks of Q (R x_J): the far part of the product, in the order of §5.2."""
+    for rows, cols, Q, R in factors:
+        ri = particle_dofs(rows)
+        ci = particle_dofs(cols)
+        y[ri] += Q @ (R @ x[ci])
+    return y
+
+
 def compressed_apply(self_blocks: np.ndarray, factors, x: np.ndarray) -> np.ndarray:
     """Z_QR x = Z_D x + sum over blocks of Q (R x_J).
 
@@ -71,10 +80,7 @@ def compressed_apply(self_blocks: np.ndarray, factors, x: np.ndarray) -> np.ndar
     nb = self_blocks.shape[1]
     x2 = x.reshape(n * nb, -1)
     y = np.einsum("pij,pjk->pik", self_blocks, x2.reshape(n, nb, -1)).reshape(n * nb, -1)
-    for rows, cols, Q, R in factors:
-        ri = particle_dofs(rows)
-        ci = particle_dofs(cols)
-        y[ri] += Q @ (R @ x2[ci])
+    factor_apply(factors, x2, y)
     return y.reshape(x.shape)
 
 

@@ -53,7 +53,7 @@ class SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("restarts", C.c_int32), ("converged", C.c_int32),
                 ("rel_res_prec", C.c_double), ("rel_res_true", C.c_double), ("n_apply", C.c_int32),
                 ("n_prec", C.c_int32), ("t_apply_s", C.c_double), ("t_prec_s", C.c_double),
-                ("t_krylov_s", C.c_double), ("t_total_s", C.c_double)]
+                ("t_krylov_s", C.c_double), ("t_total_s", C.c_double), ("n_reorth", C.c_int32)]
 
 
 P = C.c_void_p
@@ -83,6 +83,7 @@ SIGNATURES = {
     "qrvie_op_export_self": (ST, [P, I32, P, P]),
     "qrvie_op_destroy": (None, [P]),
     "qrvie_apply": (ST, [P, P, I32, P, I64, P, I64]),
+    "qrvie_op_profile_apply": (ST, [P, P, I32, C.POINTER(C.c_double), C.POINTER(I64)]),
     "qrvie_precondition": (ST, [P, P, I32, P, I64, P, I64]),
     "qrvie_rhs_plane_waves": (ST, [P, P, I32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(I32), P, I64]),
     "qrvie_solve": (ST, [P, P, I32, P, I64, P, I64, C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),

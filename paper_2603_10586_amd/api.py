@@ -220,6 +220,15 @@ class Operator:
         self.ctx.check(self.ctx.lib.qrvie_apply(self.ctx.h, self.h, nrhs, px, ld, C.c_void_p(y.data_ptr()), ld), "apply")
         return y
 
+    def profile_apply(self, reps: int = 10) -> dict:
+        """Per-stage device time (ms) and algorithmic bytes of one single-RHS product."""
+        ms = (C.c_double * 4)()
+        by = (C.c_int64 * 4)()
+        self.ctx.order()
+        self.ctx.check(self.ctx.lib.qrvie_op_profile_apply(self.ctx.h, self.h, reps, ms, by), "profile")
+        names = ("rphase", "qphase", "final", "product")
+        return {k: dict(ms=ms[i], bytes=by[i]) for i, k in enumerate(names)}
+
     def precondition(self, y):
         torch = _torch()
         py, ld, nrhs = _cols(y, self.geom.ndof)

@@ -1,8 +1,14 @@
-// Krylov building blocks of left-preconditioned restarted GMRES (the paper's solver
-// of §6 with the preconditioner of §4): classical Gram-Schmidt passes as multi-dot /
-// multi-axpy kernels over the column-major basis V (n x (m+1)), norms, and the
-// Hessenberg least-squares update by complex Givens rotations, all in FP64 and on
-// the device.  Reductions are two-stage with a fixed order (bitwise reproducible).
+// Krylov building blocks of left-preconditioned GMRES (the paper's solver of §6 with
+// the preconditioner of §4): Gram-Schmidt projections as multi-dot / multi-axpy kernels
+// over the column-major basis V (n x (m+1)) with the vector norms fused in, a device-side
+// reorthogonalisation gate, and the Hessenberg least-squares update by complex Givens
+// rotations, all in FP64 on the device.  Reductions are two-stage with a fixed order, so
+// results are bitwise reproducible.
+//
+// Orthogonalisation: one classical Gram-Schmidt pass, then a second pass only when the
+// projection removed most of the vector (||w'|| < ||w|| / sqrt 2, the Daniel-Gragg-
+// Kaufman-Stewart criterion).  The gate is evaluated on the device and the second pass's
+// kernels return immediately when it is closed, so the host never waits for it.
 #include "internal.h"
 
 namespace qrvie {
@@ -17,30 +23,69 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// partial[c * ncols + i] = sum_{e in chunk c} conj(V_i[e]) w[e]
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__device__ __forceinline__ bool closed(const int* gate) { return gate && *gate == 0; }
+
+// partial[c * ncols + i] = sum_{e in chunk c} conj(V_i[e]) w[e];  wpart[c] = ||w_chunk||^2.
+// Grid: (row chunks of 1024, groups of 64 basis vectors).  Each lane keeps its 16 elements
+// of the w chunk in registers; a wave streams one basis vector's chunk per step.
+constexpr int kPerLane = kChunk / 64;
+constexpr int kVecGroup = 64;
+
 __global__ void __launch_bounds__(256) k_multidot(const c128* __restrict__ V, int64_t ldv, int ncols,
-                                                  const c128* __restrict__ w, int64_t n, c128* __restrict__ partial) {
+                                                  const c128* __restrict__ w, int64_t n, c128* __restrict__ partial,
+                                                  double* __restrict__ wpart, const int* gate) {
+    if (closed(gate)) return;
     const int c = blockIdx.x;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t e0 = (int64_t)c * kChunk, e1 = min(n, e0 + kChunk);
-    for (int i = wv; i < ncols; i += 4) {
-        const c128* vi = V + (int64_t)i * ldv;
-        double re = 0.0, im = 0.0;
-        for (int64_t e = e0 + lane; e < e1; e += 64) {
-            const c128 a = vi[e], b = w[e];
-            re = fma(a.x, b.x, fma(a.y, b.y, re));
-            im = fma(a.x, b.y, fma(-a.y, b.x, im));
+    const int64_t e0 = (int64_t)c * kChunk;
+    const int cnt = (n - e0) < kChunk ? (int)(n - e0) : kChunk;
+    c128 wr[kPerLane];
+#pragma unroll
+    for (int t = 0; t < kPerLane; ++t) {
+        const int o = lane + 64 * t;
+        wr[t] = o < cnt ? w[e0 + o] : make_double2(0.0, 0.0);
+    }
+    const int i1 = min(ncols, (int)(blockIdx.y + 1) * kVecGroup);
+    for (int i = blockIdx.y * kVecGroup + wv; i < i1; i += 4) {
+        const c128* vi = V + (int64_t)i * ldv + e0;
+        double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
+#pragma unroll
+        for (int t = 0; t < kPerLane; t += 2) {
+            const int o0 = lane + 64 * t, o1 = o0 + 64;
+            const c128 a0 = o0 < cnt ? vi[o0] : make_double2(0.0, 0.0);
+            const c128 a1 = o1 < cnt ? vi[o1] : make_double2(0.0, 0.0);
+            re0 = fma(a0.x, wr[t].x, fma(a0.y, wr[t].y, re0));
+            im0 = fma(a0.x, wr[t].y, fma(-a0.y, wr[t].x, im0));
+            re1 = fma(a1.x, wr[t + 1].x, fma(a1.y, wr[t + 1].y, re1));
+            im1 = fma(a1.x, wr[t + 1].y, fma(-a1.y, wr[t + 1].x, im1));
         }
-        re = wave_sum(re);
-        im = wave_sum(im);
+        const double re = wave_sum(re0 + re1), im = wave_sum(im0 + im1);
         if (lane == 0) partial[(int64_t)c * ncols + i] = make_double2(re, im);
+    }
+    if (wpart && blockIdx.y == 0) {
+        __shared__ double red[4];
+        double s = 0.0;
+#pragma unroll
+        for (int t = 0; t < kPerLane; ++t) s = fma(wr[t].x, wr[t].x, fma(wr[t].y, wr[t].y, s));
+        s = block_sum(s, red);
+        if (threadIdx.x == 0) wpart[c] = s;
     }
 }
 
-__global__ void k_reduce_dots(const c128* __restrict__ partial, int nchunks, int ncols, c128* h, int accumulate) {
+__global__ void k_reduce_dots(const c128* __restrict__ partial, int nchunks, int ncols, c128* h, int accumulate,
+                              const int* gate) {
+    if (closed(gate)) return;
     const int i = threadIdx.x + blockIdx.x * blockDim.x;
     if (i >= ncols) return;
     double re = 0.0, im = 0.0;
+#pragma unroll 8
     for (int c = 0; c < nchunks; ++c) {
         const c128 p = partial[(int64_t)c * ncols + i];
         re += p.x;
@@ -50,38 +95,47 @@ __global__ void k_reduce_dots(const c128* __restrict__ partial, int nchunks, int
     h[i] = make_double2(re, im);
 }
 
-// w -= V h  (h length ncols)
-__global__ void __launch_bounds__(256) k_gemv_sub(const c128* __restrict__ V, int64_t ldv, int ncols,
-                                                  const c128* __restrict__ h, c128* __restrict__ w, int64_t n) {
+// w += SIGN * V h (coefficients staged through LDS 512 at a time); npart[block] = ||w_block||^2 after.
+template <int SIGN>
+__global__ void __launch_bounds__(256) k_gemv_acc(const c128* __restrict__ V, int64_t ldv, int ncols,
+                                                  const c128* __restrict__ h, c128* __restrict__ w, int64_t n,
+                                                  double* __restrict__ npart, const int* gate) {
+    if (closed(gate)) return;
     __shared__ c128 hs[512];
-    for (int i = threadIdx.x; i < ncols; i += blockDim.x) hs[i] = h[i];
-    __syncthreads();
+    __shared__ double red[4];
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
-    double re = w[e].x, im = w[e].y;
-    for (int i = 0; i < ncols; ++i) {
-        const c128 a = V[e + (int64_t)i * ldv];
-        re = fma(-a.x, hs[i].x, fma(a.y, hs[i].y, re));
-        im = fma(-a.x, hs[i].y, fma(-a.y, hs[i].x, im));
+    const bool live = e < n;
+    double re = live ? w[e].x : 0.0, im = live ? w[e].y : 0.0;
+    for (int c0 = 0; c0 < ncols; c0 += 512) {
+        const int cn = min(512, ncols - c0);
+        __syncthreads();
+        for (int i = threadIdx.x; i < cn; i += blockDim.x) hs[i] = make_double2(SIGN * h[c0 + i].x, SIGN * h[c0 + i].y);
+        __syncthreads();
+        if (live) {
+            const c128* vp = V + e + (int64_t)c0 * ldv;
+            int i = 0;
+            for (; i + 8 <= cn; i += 8) {
+                c128 a[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) a[u] = vp[(int64_t)(i + u) * ldv];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    re = fma(a[u].x, hs[i + u].x, fma(-a[u].y, hs[i + u].y, re));
+                    im = fma(a[u].x, hs[i + u].y, fma(a[u].y, hs[i + u].x, im));
+                }
+            }
+            for (; i < cn; ++i) {
+                const c128 a = vp[(int64_t)i * ldv];
+                re = fma(a.x, hs[i].x, fma(-a.y, hs[i].y, re));
+                im = fma(a.x, hs[i].y, fma(a.y, hs[i].x, im));
+            }
+        }
     }
-    w[e] = make_double2(re, im);
-}
-
-// x += V y
-__global__ void __launch_bounds__(256) k_gemv_add(const c128* __restrict__ V, int64_t ldv, int ncols,
-                                                  const c128* __restrict__ y, c128* __restrict__ x, int64_t n) {
-    __shared__ c128 ys[512];
-    for (int i = threadIdx.x; i < ncols; i += blockDim.x) ys[i] = y[i];
-    __syncthreads();
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
-    double re = x[e].x, im = x[e].y;
-    for (int i = 0; i < ncols; ++i) {
-        const c128 a = V[e + (int64_t)i * ldv];
-        re = fma(a.x, ys[i].x, fma(-a.y, ys[i].y, re));
-        im = fma(a.x, ys[i].y, fma(a.y, ys[i].x, im));
+    if (live) w[e] = make_double2(re, im);
+    if (npart) {
+        const double s = block_sum(live ? re * re + im * im : 0.0, red);
+        if (threadIdx.x == 0) npart[blockIdx.x] = s;
     }
-    x[e] = make_double2(re, im);
 }
 
 __global__ void __launch_bounds__(256) k_norm2(const c128* __restrict__ w, int64_t n, double* __restrict__ partial) {
@@ -90,17 +144,33 @@ __global__ void __launch_bounds__(256) k_norm2(const c128* __restrict__ w, int64
     double s = 0.0;
     for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) s = fma(w[e].x, w[e].x, fma(w[e].y, w[e].y, s));
     __shared__ double red[4];
-    s = wave_sum(s);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) partial[c] = (red[0] + red[1]) + (red[2] + red[3]);
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) partial[c] = s;
 }
 
-__global__ void k_reduce_norm(const double* __restrict__ partial, int nchunks, double* out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ void __launch_bounds__(256) k_reduce_norm(const double* __restrict__ partial, int count, double* out,
+                                                     const int* gate) {
+    if (closed(gate)) return;
+    __shared__ double red[256];
+    const int tid = threadIdx.x;
     double s = 0.0;
-    for (int c = 0; c < nchunks; ++c) s += partial[c];
-    out[0] = s;
+    for (int c = tid; c < count; c += 256) s += partial[c];
+    red[tid] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) red[tid] += red[tid + o];
+        __syncthreads();
+    }
+    if (tid == 0) out[0] = red[0];
+}
+
+// gate[0] = 1 when the projected norm fell below 1/sqrt(2) of the original; gate[1] counts openings
+__global__ void k_reorth_gate(const double* an2, const double* wn2, int* gate) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const int open = (an2[0] < 0.5 * wn2[0]) ? 1 : 0;
+        gate[0] = open;
+        gate[1] += open;
+    }
 }
 
 // out = w / sqrt(norm2); gslot (optional) = sqrt(norm2)
@@ -117,93 +187,137 @@ __global__ void k_scale_into(const c128* __restrict__ w, int64_t n, const double
 // Column j of the Hessenberg matrix: hcol[0..j] from Gram-Schmidt, h_{j+1,j} = sqrt(hnorm2).
 // Apply the previous rotations, build rotation j so that [[c, s], [-conj(s), c]] zeroes
 // h_{j+1,j} (c real), and rotate the right-hand side g.  status = {|g_{j+1}|, h_{j+1,j}}.
-__global__ void k_givens(int j, c128* hcol, c128* H, int ldh, double* cs, c128* sn, c128* g, const double* hnorm2,
-                         double* status) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// The previous rotations are a sequential sweep; their operands are staged through LDS
+// in segments by the whole workgroup so that the sweep itself only touches LDS.
+constexpr int kSeg = 2048;
+
+__global__ void __launch_bounds__(256) k_givens(int j, c128* hcol, c128* H, int ldh, double* cs, c128* sn, c128* g,
+                                                const double* hnorm2, double* status) {
+    __shared__ c128 hs[kSeg + 1];
+    __shared__ double cl[kSeg];
+    __shared__ c128 sl[kSeg];
+    __shared__ c128 carry;
+    const int tid = threadIdx.x;
     const double hn = sqrt(hnorm2[0]);
-    hcol[j + 1] = make_double2(hn, 0.0);
-    for (int i = 0; i < j; ++i) {
-        const c128 a = hcol[i], b = hcol[i + 1];
-        const double c = cs[i];
-        const c128 s = sn[i];
-        // [c a + s b, -conj(s) a + c b]
-        const c128 na = make_double2(c * a.x + (s.x * b.x - s.y * b.y), c * a.y + (s.x * b.y + s.y * b.x));
-        const c128 nb = make_double2(-(s.x * a.x + s.y * a.y) + c * b.x, -(s.x * a.y - s.y * a.x) + c * b.y);
-        hcol[i] = na;
-        hcol[i + 1] = nb;
+    if (tid == 0) carry = hcol[0];
+    __syncthreads();
+    for (int i0 = 0; i0 < j; i0 += kSeg) {
+        const int cnt = min(kSeg, j - i0);
+        for (int t = tid; t < cnt; t += 256) {
+            hs[t + 1] = (i0 + t + 1 == j + 1) ? make_double2(hn, 0.0) : hcol[i0 + t + 1];
+            cl[t] = cs[i0 + t];
+            sl[t] = sn[i0 + t];
+        }
+        __syncthreads();
+        if (tid == 0) {
+            c128 a = carry;
+            for (int t = 0; t < cnt; ++t) {
+                const c128 b = hs[t + 1];
+                const double c = cl[t];
+                const c128 s = sl[t];
+                // [c a + s b, -conj(s) a + c b]
+                hs[t] = make_double2(c * a.x + (s.x * b.x - s.y * b.y), c * a.y + (s.x * b.y + s.y * b.x));
+                a = make_double2(-(s.x * a.x + s.y * a.y) + c * b.x, -(s.x * a.y - s.y * a.x) + c * b.y);
+            }
+            carry = a;
+        }
+        __syncthreads();
+        for (int t = tid; t < cnt; t += 256) hcol[i0 + t] = hs[t];
+        __syncthreads();
     }
-    const c128 a = hcol[j], b = hcol[j + 1];
-    const double aa = sqrt(a.x * a.x + a.y * a.y), ab = sqrt(b.x * b.x + b.y * b.y);
-    double c;
-    c128 s;
-    if (ab == 0.0) { c = 1.0; s = make_double2(0.0, 0.0); }
-    else if (aa == 0.0) { c = 0.0; s = make_double2(b.x / ab, -b.y / ab); }
-    else {
-        const double rho = hypot(aa, ab);
-        c = aa / rho;
-        const c128 ph = make_double2(a.x / aa, a.y / aa);
-        // s = ph * conj(b) / rho
-        s = make_double2((ph.x * b.x + ph.y * b.y) / rho, (ph.y * b.x - ph.x * b.y) / rho);
+    if (tid == 0) {
+        const c128 a = carry, b = make_double2(hn, 0.0);
+        const double aa = sqrt(a.x * a.x + a.y * a.y), ab = sqrt(b.x * b.x + b.y * b.y);
+        double c;
+        c128 s;
+        if (ab == 0.0) { c = 1.0; s = make_double2(0.0, 0.0); }
+        else if (aa == 0.0) { c = 0.0; s = make_double2(b.x / ab, -b.y / ab); }
+        else {
+            const double rho = hypot(aa, ab);
+            c = aa / rho;
+            const c128 ph = make_double2(a.x / aa, a.y / aa);
+            // s = ph * conj(b) / rho
+            s = make_double2((ph.x * b.x + ph.y * b.y) / rho, (ph.y * b.x - ph.x * b.y) / rho);
+        }
+        cs[j] = c;
+        sn[j] = s;
+        hcol[j] = make_double2(c * a.x + (s.x * b.x - s.y * b.y), c * a.y + (s.x * b.y + s.y * b.x));
+        hcol[j + 1] = make_double2(0.0, 0.0);
+        const c128 gj = g[j];
+        g[j + 1] = make_double2(-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x));
+        g[j] = make_double2(c * gj.x, c * gj.y);
+        status[0] = sqrt(g[j + 1].x * g[j + 1].x + g[j + 1].y * g[j + 1].y);
+        status[1] = hn;
     }
-    cs[j] = c;
-    sn[j] = s;
-    hcol[j] = make_double2(c * a.x + (s.x * b.x - s.y * b.y), c * a.y + (s.x * b.y + s.y * b.x));
-    hcol[j + 1] = make_double2(0.0, 0.0);
-    for (int i = 0; i <= j; ++i) H[i + (int64_t)j * ldh] = hcol[i];
-    const c128 gj = g[j];
-    g[j + 1] = make_double2(-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x));
-    g[j] = make_double2(c * gj.x, c * gj.y);
-    status[0] = sqrt(g[j + 1].x * g[j + 1].x + g[j + 1].y * g[j + 1].y);
-    status[1] = hn;
+    __syncthreads();
+    for (int i = tid; i <= j; i += 256) H[i + (int64_t)j * ldh] = hcol[i];
 }
 
-// Solve the k x k upper-triangular system H y = g.
-__global__ void k_trisolve(int k, const c128* H, int ldh, const c128* g, c128* y) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Solve the k x k upper-triangular system H y = g by column sweeps (one workgroup):
+// y_i = r_i / H_ii, then r_l -= H_li y_i for l < i in parallel.
+__global__ void __launch_bounds__(256) k_trisolve(int k, const c128* H, int ldh, const c128* g, c128* y) {
+    __shared__ c128 yi_s;
+    for (int l = threadIdx.x; l < k; l += blockDim.x) y[l] = g[l];
+    __syncthreads();
     for (int i = k - 1; i >= 0; --i) {
-        double re = g[i].x, im = g[i].y;
-        for (int l = i + 1; l < k; ++l) {
-            const c128 h = H[i + (int64_t)l * ldh], v = y[l];
-            re -= h.x * v.x - h.y * v.y;
-            im -= h.x * v.y + h.y * v.x;
+        if (threadIdx.x == 0) {
+            const c128 r = y[i], d = H[i + (int64_t)i * ldh];
+            const double den = d.x * d.x + d.y * d.y;
+            const c128 v = make_double2((r.x * d.x + r.y * d.y) / den, (r.y * d.x - r.x * d.y) / den);
+            y[i] = v;
+            yi_s = v;
         }
-        const c128 d = H[i + (int64_t)i * ldh];
-        const double den = d.x * d.x + d.y * d.y;
-        y[i] = make_double2((re * d.x + im * d.y) / den, (im * d.x - re * d.y) / den);
+        __syncthreads();
+        const c128 v = yi_s;
+        for (int l = threadIdx.x; l < i; l += blockDim.x) {
+            const c128 h = H[l + (int64_t)i * ldh];
+            y[l] = make_double2(y[l].x - (h.x * v.x - h.y * v.y), y[l].y - (h.x * v.y + h.y * v.x));
+        }
+        __syncthreads();
     }
 }
 
 }  // namespace
 
 int krylov_nchunks(int64_t n) { return (int)((n + kChunk - 1) / kChunk); }
+int krylov_nblocks(int64_t n) { return (int)((n + 255) / 256); }
 
-void launch_multidot(hipStream_t s, const c128* V, int64_t ldv, int ncols, const c128* w, int64_t n, c128* partial) {
-    hipLaunchKernelGGL(k_multidot, dim3(krylov_nchunks(n)), dim3(256), 0, s, V, ldv, ncols, w, n, partial);
+void launch_multidot(hipStream_t s, const c128* V, int64_t ldv, int ncols, const c128* w, int64_t n, c128* partial,
+                     double* wpart, const int* gate) {
+    dim3 grid(krylov_nchunks(n), (ncols + kVecGroup - 1) / kVecGroup);
+    hipLaunchKernelGGL(k_multidot, grid, dim3(256), 0, s, V, ldv, ncols, w, n, partial, wpart, gate);
 }
-void launch_reduce_dots(hipStream_t s, const c128* partial, int nchunks, int ncols, c128* h, int accumulate) {
-    hipLaunchKernelGGL(k_reduce_dots, dim3((ncols + 255) / 256), dim3(256), 0, s, partial, nchunks, ncols, h, accumulate);
+void launch_reduce_dots(hipStream_t s, const c128* partial, int nchunks, int ncols, c128* h, int accumulate,
+                        const int* gate) {
+    hipLaunchKernelGGL(k_reduce_dots, dim3((ncols + 255) / 256), dim3(256), 0, s, partial, nchunks, ncols, h,
+                       accumulate, gate);
 }
-void launch_gemv_sub(hipStream_t s, const c128* V, int64_t ldv, int ncols, const c128* h, c128* w, int64_t n) {
-    hipLaunchKernelGGL(k_gemv_sub, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, V, ldv, ncols, h, w, n);
+void launch_gemv_sub(hipStream_t s, const c128* V, int64_t ldv, int ncols, const c128* h, c128* w, int64_t n,
+                     double* npart, const int* gate) {
+    hipLaunchKernelGGL(k_gemv_acc<-1>, dim3(krylov_nblocks(n)), dim3(256), 0, s, V, ldv, ncols, h, w, n, npart, gate);
 }
 void launch_gemv_add(hipStream_t s, const c128* V, int64_t ldv, int ncols, const c128* y, c128* x, int64_t n) {
-    hipLaunchKernelGGL(k_gemv_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, V, ldv, ncols, y, x, n);
+    hipLaunchKernelGGL(k_gemv_acc<1>, dim3(krylov_nblocks(n)), dim3(256), 0, s, V, ldv, ncols, y, x, n, nullptr,
+                       nullptr);
 }
 void launch_norm2(hipStream_t s, const c128* w, int64_t n, double* partial) {
     hipLaunchKernelGGL(k_norm2, dim3(krylov_nchunks(n)), dim3(256), 0, s, w, n, partial);
 }
-void launch_reduce_norm(hipStream_t s, const double* partial, int nchunks, double* out) {
-    hipLaunchKernelGGL(k_reduce_norm, dim3(1), dim3(64), 0, s, partial, nchunks, out);
+void launch_reduce_norm(hipStream_t s, const double* partial, int count, double* out, const int* gate) {
+    hipLaunchKernelGGL(k_reduce_norm, dim3(1), dim3(256), 0, s, partial, count, out, gate);
+}
+void launch_reorth_gate(hipStream_t s, const double* an2, const double* wn2, int* gate) {
+    hipLaunchKernelGGL(k_reorth_gate, dim3(1), dim3(64), 0, s, an2, wn2, gate);
 }
 void launch_scale_into(hipStream_t s, const c128* w, int64_t n, const double* norm2, c128* out, c128* gslot) {
     hipLaunchKernelGGL(k_scale_into, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w, n, norm2, out, gslot);
 }
 void launch_givens(hipStream_t s, int j, c128* hcol, c128* H, int ldh, double* cs, c128* sn, c128* g,
                    const double* hnorm2, double* status) {
-    hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, s, j, hcol, H, ldh, cs, sn, g, hnorm2, status);
+    hipLaunchKernelGGL(k_givens, dim3(1), dim3(256), 0, s, j, hcol, H, ldh, cs, sn, g, hnorm2, status);
 }
 void launch_trisolve(hipStream_t s, int k, const c128* H, int ldh, const c128* g, c128* y) {
-    hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(64), 0, s, k, H, ldh, g, y);
+    hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(256), 0, s, k, H, ldh, g, y);
 }
 
 }  // namespace qrvie

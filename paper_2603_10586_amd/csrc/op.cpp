@@ -111,6 +111,7 @@ void gemm_tiles(const std::vector<GemmDesc>& d, std::vector<int32_t>& td, std::v
 constexpr int kDirectMaxParticles = 2;   // both sides at most this many particles: direct QRCP
 constexpr int kSketchStart = 128;
 constexpr int kMaxSketch = 512;          // widest sketch the CGS2 kernel orthonormalises
+constexpr int kPhaseWaves = 4;           // waves per strip in the product kernels
 
 struct Builder {
     qrvie_op* op;
@@ -662,6 +663,14 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
         op->qlaunch.push_back({l, qbegin, (int64_t)qstr.size() - qbegin, waves_for(maxK, 384)});
         op->rlaunch.push_back({l, rbegin, (int64_t)rstr.size() - rbegin, waves_for(maxN, 512)});
     }
+    // One launch per phase over all levels: four waves per strip split its columns, and the
+    // strips are issued longest first so the long coarse-level strips overlap the many
+    // short fine-level ones (largest-first greedy, the load-balancing rule of the paper's
+    // appendix C applied to workgroups).
+    std::stable_sort(rstr.begin(), rstr.end(), [](const RStrip& a, const RStrip& b) { return a.ncols > b.ncols; });
+    std::stable_sort(qstr.begin(), qstr.end(), [](const QStrip& a, const QStrip& b) { return a.ncols > b.ncols; });
+    op->rlaunch.assign(1, {-1, 0, (int64_t)rstr.size(), kPhaseWaves});
+    op->qlaunch.assign(1, {-1, 0, (int64_t)qstr.size(), kPhaseWaves});
     op->fac_elems = fcur;
     op->t_len = tcur;
     op->tmap_len = (int64_t)tmap.size();

@@ -87,6 +87,55 @@ qrvie_status qrvie_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const
     return hip_check(ctx, hipStreamSynchronize(ctx->stream), "apply");
 }
 
+qrvie_status qrvie_op_profile_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t reps, double* ms, int64_t* bytes) {
+    if (!ctx || !op || reps < 1 || !ms || !bytes) return QRVIE_ERR_INVALID_ARG;
+    const qrvie_geom* g = op->g;
+    const int64_t n = g->ndof();
+    hipStream_t s = ctx->stream;
+    Work w(ctx);
+    c128 *xi, *yi;
+    CHECK(w.alloc(&xi, n, "profile x"));
+    CHECK(w.alloc(&yi, n, "profile y"));
+    CHECK(hip_check(ctx, hipMemsetAsync(xi, 0, sizeof(c128) * n, s), "profile x"));
+    hipEvent_t ev[4];
+    for (auto& e : ev) (void)hipEventCreate(&e);
+    double acc[4] = {0, 0, 0, 0};
+    for (int r = 0; r < reps; ++r) {
+        (void)hipEventRecord(ev[0], s);
+        for (const auto& L : op->rlaunch)
+            launch_rphase(s, op->d_rstrips + L.begin, L.count, L.waves, op->d_fac, xi, op->d_t, op->d_tmap);
+        (void)hipEventRecord(ev[1], s);
+        for (const auto& L : op->qlaunch)
+            launch_qphase(s, op->d_qstrips + L.begin, L.count, L.waves, op->d_fac, op->d_t, op->d_ylev);
+        (void)hipEventRecord(ev[2], s);
+        launch_final(s, g->N, g->d_ptype, op->d_self, nullptr, xi, op->d_ylev, op->n_active, n, nullptr, yi, nullptr);
+        (void)hipEventRecord(ev[3], s);
+        CHECK(hip_check(ctx, hipEventSynchronize(ev[3]), "profile"));
+        float t = 0.f;
+        for (int k = 0; k < 3; ++k) {
+            (void)hipEventElapsedTime(&t, ev[k], ev[k + 1]);
+            acc[k] += t;
+        }
+        (void)hipEventElapsedTime(&t, ev[0], ev[3]);
+        acc[3] += t;
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    for (int k = 0; k < 4; ++k) ms[k] = acc[k] / reps;
+    int64_t rn = 0, mr = 0, sr = 0;
+    for (size_t b = 0; b < op->blocks.size(); ++b) {
+        const int64_t r = op->rank[b];
+        rn += r * op->blocks[b].cn * (int64_t)kNp;
+        mr += r * op->blocks[b].rn * (int64_t)kNp;
+        sr += r;
+    }
+    const int64_t cb = (int64_t)sizeof(c128);
+    bytes[0] = cb * (rn + sr + n);
+    bytes[1] = cb * (mr + sr);
+    bytes[2] = cb * ((int64_t)op->ntypes * kNp * kNp + n);
+    bytes[3] = bytes[0] + bytes[1] + bytes[2];
+    return hip_check(ctx, hipGetLastError(), "profile");
+}
+
 qrvie_status qrvie_precondition(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const qrvie_c128* y, int64_t ldy,
                                 qrvie_c128* z, int64_t ldz) {
     CHECK(check_vec_args(ctx, op, nrhs, y, ldy, z, ldz, "precondition"));
@@ -144,7 +193,7 @@ qrvie_status qrvie_op_export_self(const qrvie_op* op, int32_t p, qrvie_c128* Zpp
 qrvie_status qrvie_solve(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const qrvie_c128* v, int64_t ldv,
                          qrvie_c128* x, int64_t ldx, const qrvie_solve_opts* o, qrvie_solve_info* info) {
     CHECK(check_vec_args(ctx, op, nrhs, v, ldv, x, ldx, "solve"));
-    if (!o || o->restart < 1 || o->restart > 256 || o->max_iter < 1 || !(o->tol > 0.0) || o->mode != QRVIE_SOLVE_FP64) {
+    if (!o || o->restart < 1 || o->restart > 16384 || o->max_iter < 1 || !(o->tol > 0.0) || o->mode != QRVIE_SOLVE_FP64) {
         set_err(ctx, "solve: invalid options");
         return QRVIE_ERR_INVALID_ARG;
     }
@@ -159,6 +208,8 @@ qrvie_status qrvie_solve(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const
     CHECK(w.alloc(&V, (size_t)n * (m + 1), "krylov basis"));
     CHECK(w.alloc(&wv, n, "krylov w"));
     CHECK(w.alloc(&xi, n, "solve x"));
+    c128* xc;
+    CHECK(w.alloc(&xc, n, "solve candidate x"));
     CHECK(w.alloc(&vi, n, "solve v"));
     CHECK(w.alloc(&r, n, "solve r"));
     CHECK(w.alloc(&pd, (size_t)nch * (m + 1), "dot partials"));
@@ -175,9 +226,14 @@ qrvie_status qrvie_solve(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const
     CHECK(hip_check(ctx, hipHostMalloc((void**)&hstat, 4 * sizeof(double), hipHostMallocDefault), "pinned status"));
     struct PinnedFree { double* p; ~PinnedFree() { if (p) (void)hipHostFree(p); } } pf{hstat};
 
+    const int nblk = krylov_nblocks(n);
+    double* bp;
+    int* gate;
+    CHECK(w.alloc(&bp, nblk, "update norm partials"));
+    CHECK(w.alloc(&gate, 2, "reorthogonalisation gate"));
     auto norm_to = [&](const c128* vec, double* dst) {
         launch_norm2(s, vec, n, np);
-        launch_reduce_norm(s, np, nch, dst);
+        launch_reduce_norm(s, np, nch, dst, nullptr);
     };
     auto read = [&](const double* d, int cnt) -> qrvie_status {
         CHECK(hip_check(ctx, hipMemcpyAsync(hstat, d, sizeof(double) * cnt, hipMemcpyDeviceToHost, s), "read"));
@@ -211,6 +267,7 @@ qrvie_status qrvie_solve(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const
             if (info) info[rhs] = inf;
             continue;
         }
+        CHECK(hip_check(ctx, hipMemsetAsync(gate, 0, 2 * sizeof(int), s), "gate"));
         double prec_tol = o->tol;
         int iters = 0;
         bool converged = false;
@@ -240,26 +297,26 @@ qrvie_status qrvie_solve(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const
             const double tk0 = now_s();
             launch_scale_into(s, wv, n, nrm + 1, V, gv);     // V0 = w / beta, g0 = beta
             int k_used = 0;
-            for (int j = 0; j < m && iters < o->max_iter; ++j) {
+            bool cycle_done = false;
+            for (int j = 0; j < m && iters < o->max_iter && !cycle_done; ++j) {
                 (void)hipEventRecord(ev0, s);
                 apply_internal(op, s, V + (size_t)j * n, nullptr, nullptr, wv);   // w = Z_D^-1 Z v_j
                 (void)hipEventRecord(ev1, s);
                 inf.n_apply++;
                 inf.n_prec++;
-                for (int pass = 0; pass < 2; ++pass) {
-                    launch_multidot(s, V, n, j + 1, wv, n, pd);
-                    launch_reduce_dots(s, pd, nch, j + 1, h, pass);
-                    // subtract only this pass's coefficients: keep them in y as scratch
-                    if (pass == 0) {
-                        CHECK(hip_check(ctx, hipMemcpyAsync(y, h, sizeof(c128) * (j + 1), hipMemcpyDeviceToDevice, s), "h"));
-                        launch_gemv_sub(s, V, n, j + 1, y, wv, n);
-                    } else {
-                        // h now holds h1 + h2; y holds h1: subtract h2 = h - y
-                        launch_reduce_dots(s, pd, nch, j + 1, y, 0);
-                        launch_gemv_sub(s, V, n, j + 1, y, wv, n);
-                    }
-                }
-                norm_to(wv, nrm + 2);
+                // one classical Gram-Schmidt pass with ||w|| and ||w'|| fused in
+                launch_multidot(s, V, n, j + 1, wv, n, pd, np, nullptr);
+                launch_reduce_dots(s, pd, nch, j + 1, h, 0, nullptr);
+                launch_reduce_norm(s, np, nch, nrm + 3, nullptr);
+                launch_gemv_sub(s, V, n, j + 1, h, wv, n, bp, nullptr);
+                launch_reduce_norm(s, bp, nblk, nrm + 2, nullptr);
+                // the second pass runs only if the gate opens (||w'||^2 < ||w||^2 / 2)
+                launch_reorth_gate(s, nrm + 2, nrm + 3, gate);
+                launch_multidot(s, V, n, j + 1, wv, n, pd, nullptr, gate);
+                launch_reduce_dots(s, pd, nch, j + 1, y, 0, gate);
+                launch_reduce_dots(s, pd, nch, j + 1, h, 1, gate);
+                launch_gemv_sub(s, V, n, j + 1, y, wv, n, bp, gate);
+                launch_reduce_norm(s, bp, nblk, nrm + 2, gate);
                 launch_givens(s, j, h, H, m + 1, cs, sn, gv, nrm + 2, status);
                 launch_scale_into(s, wv, n, nrm + 2, V + (size_t)(j + 1) * n, nullptr);
                 CHECK(read(status, 2));
@@ -269,15 +326,51 @@ qrvie_status qrvie_solve(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const
                 ++iters;
                 k_used = j + 1;
                 const double est = hstat[0] / pvnorm;
-                if (est <= prec_tol || hstat[1] == 0.0) break;
+                const bool breakdown = hstat[1] == 0.0;
+                if (est <= prec_tol || breakdown) {
+                    // candidate x_c = x + V y: accept it if the true residual meets tol too;
+                    // otherwise tighten the preconditioned target and keep extending this
+                    // Krylov space instead of restarting
+                    launch_trisolve(s, k_used, H, m + 1, gv, y);
+                    CHECK(hip_check(ctx, hipMemcpyAsync(xc, xi, sizeof(c128) * n, hipMemcpyDeviceToDevice, s), "x_c"));
+                    launch_gemv_add(s, V, n, k_used, y, xc, n);
+                    (void)hipEventRecord(ev0, s);
+                    apply_internal(op, s, xc, vi, r, nullptr);
+                    (void)hipEventRecord(ev1, s);
+                    inf.n_apply++;
+                    norm_to(r, nrm + 0);
+                    CHECK(read(nrm, 1));
+                    float ms3 = 0.f;
+                    (void)hipEventElapsedTime(&ms3, ev0, ev1);
+                    t_apply += ms3 * 1e-3;
+                    const double tr = std::sqrt(hstat[0]) / vnorm;
+                    inf.rel_res_true = tr;
+                    inf.rel_res_prec = est;
+                    if (tr <= o->tol) {
+                        CHECK(hip_check(ctx, hipMemcpyAsync(xi, xc, sizeof(c128) * n, hipMemcpyDeviceToDevice, s), "x"));
+                        converged = true;
+                        cycle_done = true;
+                        k_used = 0;
+                    } else {
+                        prec_tol = std::max(prec_tol * 0.5 * o->tol / tr, 1e-15);
+                        if (breakdown) cycle_done = true;
+                    }
+                }
             }
-            launch_trisolve(s, k_used, H, m + 1, gv, y);
-            launch_gemv_add(s, V, n, k_used, y, xi, n);
+            if (k_used > 0) {
+                launch_trisolve(s, k_used, H, m + 1, gv, y);
+                launch_gemv_add(s, V, n, k_used, y, xi, n);
+            }
             CHECK(hip_check(ctx, hipGetLastError(), "gmres launch"));
             inf.restarts++;
             t_kry += now_s() - tk0;
+            if (converged) break;
         }
         inf.iterations = iters;
+        int hgate[2] = {0, 0};
+        CHECK(hip_check(ctx, hipMemcpyAsync(hgate, gate, sizeof hgate, hipMemcpyDeviceToHost, s), "gate"));
+        CHECK(hip_check(ctx, hipStreamSynchronize(s), "gate"));
+        inf.n_reorth = hgate[1];
         inf.converged = converged ? 1 : 0;
         launch_permute(s, g->N, g->d_i2c, xi, (c128*)x + rhs * ldx, 0);
         CHECK(hip_check(ctx, hipStreamSynchronize(s), "solve"));

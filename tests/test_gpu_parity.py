@@ -161,6 +161,31 @@ def test_solve_matches_lu_of_the_same_operator(name):
         assert info[r]["rel_res_true"] <= 1e-10
 
 
+@pytest.mark.parametrize("restart", [7, 40, 4096])
+def test_solve_is_independent_of_the_restart_length(restart):
+    """Short restarts, mid-cycle acceptance and unrestarted runs reach the same solution."""
+    import paper_2603_10586_amd as q
+    c = case("rand6x7")
+    v = q.rhs_plane_waves(c.ctx, c.geom, [5.0], [0.0], [0])
+    x, info, st = c.op.solve(v, restart=restart, tol=1e-10, max_iter=4000)
+    assert st == 0 and info[0]["converged"] and info[0]["rel_res_true"] <= 1e-10
+    sb = greens.self_blocks(c.disc)
+    ZQR = compressed.dense_from_factors(sb, [(f[0], f[1], f[2], f[3]) for f in c.factors()])
+    ref = np.linalg.solve(ZQR, to_host(v)[0])
+    assert np.linalg.norm(to_host(x)[0] - ref) <= 1e-8 * np.linalg.norm(ref)
+    if restart >= 4096:
+        assert info[0]["restarts"] == 1
+
+
+def test_solve_reports_not_converged_with_the_best_iterate():
+    import paper_2603_10586_amd as q
+    c = case("rand6x7")
+    v = q.rhs_plane_waves(c.ctx, c.geom, [0.0], [0.0], [1])
+    x, info, st = c.op.solve(v, restart=30, tol=1e-12, max_iter=5)
+    assert st == 5 and not info[0]["converged"] and info[0]["iterations"] == 5
+    assert 0 < info[0]["rel_res_true"] < 1.0
+
+
 def test_solve_method_accuracy_against_uncompressed_lu():
     """F3 on the tiny array: eps_sol within 3x the oracle's own QRCP compression."""
     import paper_2603_10586_amd as q
