@@ -112,6 +112,7 @@ constexpr int kDirectMaxParticles = 2;   // both sides at most this many particl
 constexpr int kSketchStart = 128;
 constexpr int kMaxSketch = 512;          // widest sketch the CGS2 kernel orthonormalises
 constexpr int kPhaseWaves = 4;           // waves per strip in the product kernels
+constexpr int64_t kAlign = 8;            // panel alignment in complex128 elements (128 B)
 
 struct Builder {
     qrvie_op* op;
@@ -640,18 +641,21 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
             const int64_t nJ = (int64_t)b0.cn * kNp;
             int64_t Kp = 0;
             for (size_t b : kv.second) Kp += op->rank[b];
+            // leading dimension padded to 8 complex (128 B) so every wave's 64-row column
+            // segment starts on a cache-line boundary
+            const int64_t ldp = (Kp + kAlign - 1) / kAlign * kAlign;
             const int64_t base = fcur;
-            fcur += Kp * nJ;
+            fcur += ldp * nJ;
             const int64_t tbase = (int64_t)tmap.size();
             int64_t row = 0;
             for (size_t b : kv.second) {
                 op->r_off[b] = base + row;
-                op->r_ld[b] = (int32_t)Kp;
+                op->r_ld[b] = (int32_t)ldp;
                 for (int k = 0; k < op->rank[b]; ++k) tmap.push_back(toff[b] + k);
                 row += op->rank[b];
             }
             for (int64_t r0 = 0; r0 < Kp; r0 += kStrip)
-                rstr.push_back(RStrip{base + r0, (int32_t)Kp, (int32_t)nJ, (int32_t)std::min<int64_t>(kStrip, Kp - r0),
+                rstr.push_back(RStrip{base + r0, (int32_t)ldp, (int32_t)nJ, (int32_t)std::min<int64_t>(kStrip, Kp - r0),
                                       b0.c0 * kNp, tbase + r0});
             maxN = std::max<int>(maxN, (int)nJ);
         }
