@@ -142,13 +142,11 @@ struct qrvie_op {
     qrvie::c128* d_pinv = nullptr;            // inverses
     qrvie::c128* d_fac = nullptr;             // all panels
     int64_t fac_elems = 0;
-    qrvie::c128* d_t = nullptr;               // rank-space vector of the product
-    int64_t t_len = 0;
+    int64_t t_len = 0;                        // length of the rank-space vector (per-call workspace)
     int64_t* d_tmap = nullptr;                // stacked R row -> t index
     int64_t tmap_len = 0;
     qrvie::RStrip* d_rstrips = nullptr;
     qrvie::QStrip* d_qstrips = nullptr;
-    qrvie::c128* d_ylev = nullptr;            // n_active x n
     struct Launch { int level; int64_t begin, count; int waves; };
     std::vector<Launch> rlaunch, qlaunch;
     int32_t n_active = 0;
@@ -206,6 +204,14 @@ void launch_final(hipStream_t s, int32_t N, const int32_t* ptype, const c128* se
                   c128* out_r, c128* out_z);
 void launch_block_apply(hipStream_t s, int32_t N, const int32_t* ptype, const c128* blocks,
                         const c128* x, c128* y);
+// many right-hand sides (nr in {2, 4, 8}), RHS-interleaved blocks
+void launch_rphase_m(hipStream_t s, int nr, const RStrip* st, int64_t n, const c128* fac, const c128* X, c128* T,
+                     const int64_t* tmap);
+void launch_qphase_m(hipStream_t s, int nr, const QStrip* st, int64_t n, const c128* fac, const c128* T, c128* Y);
+void launch_final_m(hipStream_t s, int nr, int32_t N, const int32_t* ptype, const c128* self, const c128* pinv,
+                    const c128* X, const c128* ylev, int nlev, int64_t n, const c128* V, c128* out_r, c128* out_z);
+void launch_interleave(hipStream_t s, int nr, int64_t n, const c128* const* cols, c128* blk, int ncols);
+void launch_deinterleave(hipStream_t s, int nr, int64_t n, const c128* blk, c128* const* cols, int ncols);
 
 // Krylov helpers (k_krylov.hip)
 int krylov_nchunks(int64_t n);      // multidot / norm2 partial count

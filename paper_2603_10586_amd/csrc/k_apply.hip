@@ -178,7 +178,210 @@ __global__ void __launch_bounds__(kNp * kGroups) k_block_apply(const int32_t* __
     }
 }
 
+// ------------------------------------------------------------------ many right-hand sides
+// Blocks of NR vectors are stored RHS-interleaved (element (e, r) at e * NR + r), so the
+// NR entries a lane needs for one column are one contiguous wave-uniform row.  Each
+// factor element is loaded once and applied to all NR vectors: the streaming pattern and
+// the HBM bytes of the factors are those of the single-RHS product.
+template <int NR>
+__device__ __forceinline__ void column_stream_m(const c128* __restrict__ A, int64_t ld, const c128* __restrict__ v,
+                                                int j0, int j1, c128 acc[NR]) {
+    int j = j0;
+    for (; j + 4 <= j1; j += 4) {
+        c128 a[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[u] = load_stream(A + (int64_t)(j + u) * ld);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int r = 0; r < NR; ++r) cfma(acc[r], a[u], v[(int64_t)(j + u) * NR + r]);
+    }
+    for (; j < j1; ++j) {
+        const c128 a = A[(int64_t)j * ld];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) cfma(acc[r], a, v[(int64_t)j * NR + r]);
+    }
+}
+
+template <int NR>
+__global__ void __launch_bounds__(256) k_rphase_m(const RStrip* __restrict__ strips, const c128* __restrict__ fac,
+                                                  const c128* __restrict__ X, c128* __restrict__ T,
+                                                  const int64_t* __restrict__ tmap) {
+    const RStrip s = strips[blockIdx.x];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int row = min(lane, s.nrows - 1);
+    const int per = (s.ncols + 3) / 4;
+    const int j0 = min(s.ncols, wv * per), j1 = min(s.ncols, j0 + per);
+    c128 acc[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[r] = make_double2(0.0, 0.0);
+    column_stream_m<NR>(fac + s.a_off + row, s.ld, X + (int64_t)s.x_off * NR, j0, j1, acc);
+    __shared__ c128 red[4][64 * NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) red[wv][lane * NR + r] = acc[r];
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * NR; e += 256) {
+        const int l = e / NR, r = e % NR;
+        if (l < s.nrows) {
+            c128 sum = red[0][e];
+#pragma unroll
+            for (int w = 1; w < 4; ++w) sum = make_double2(sum.x + red[w][e].x, sum.y + red[w][e].y);
+            T[tmap[s.tmap_off + l] * NR + r] = sum;
+        }
+    }
+}
+
+template <int NR>
+__global__ void __launch_bounds__(256) k_qphase_m(const QStrip* __restrict__ strips, const c128* __restrict__ fac,
+                                                  const c128* __restrict__ T, c128* __restrict__ Y) {
+    const QStrip s = strips[blockIdx.x];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int row = min(lane, max(s.nrows - 1, 0));
+    const int per = (s.ncols + 3) / 4;
+    const int j0 = min(s.ncols, wv * per), j1 = min(s.ncols, j0 + per);
+    c128 acc[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[r] = make_double2(0.0, 0.0);
+    column_stream_m<NR>(fac + s.a_off + row, s.ld, T + s.t_off * NR, j0, j1, acc);
+    __shared__ c128 red[4][64 * NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) red[wv][lane * NR + r] = acc[r];
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * NR; e += 256) {
+        const int l = e / NR, r = e % NR;
+        if (l < s.nrows) {
+            c128 sum = red[0][e];
+#pragma unroll
+            for (int w = 1; w < 4; ++w) sum = make_double2(sum.x + red[w][e].x, sum.y + red[w][e].y);
+            Y[(s.y_off + l) * NR + r] = sum;
+        }
+    }
+}
+
+// Per particle: Y = Z_pp X + sum_l Y_l for NR interleaved vectors; optionally R = V - Y and
+// Z = Z_pp^-1 R.  576 threads: row = tid % 144, column group = tid / 144.
+template <int NR>
+__global__ void __launch_bounds__(kNp * kGroups) k_final_m(const int32_t* __restrict__ ptype,
+                                                           const c128* __restrict__ self, const c128* __restrict__ pinv,
+                                                           const c128* __restrict__ X, const c128* __restrict__ ylev,
+                                                           int nlev, int64_t n, const c128* __restrict__ V,
+                                                           c128* __restrict__ out_r, c128* __restrict__ out_z) {
+    const int p = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int row = tid % kNp, grp = tid / kNp;
+    const int64_t base = (int64_t)p * kNp;
+    const int ty = ptype[p];
+    __shared__ c128 vin[kNp * NR];
+    __shared__ c128 part[kGroups][kNp * NR];
+    for (int e = tid; e < kNp * NR; e += kNp * kGroups) vin[e] = X[base * NR + e];
+    __syncthreads();
+    auto product = [&](const c128* M) {
+        c128 acc[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) acc[r] = make_double2(0.0, 0.0);
+        const c128* a = M + row + (int64_t)grp * kColsPerGroup * kNp;
+        for (int j = 0; j < kColsPerGroup; ++j) {
+            const c128 m = a[(int64_t)j * kNp];
+            const c128* vv = vin + (grp * kColsPerGroup + j) * NR;
+#pragma unroll
+            for (int r = 0; r < NR; ++r) cfma(acc[r], m, vv[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) part[grp][row * NR + r] = acc[r];
+    };
+    product(self + (size_t)ty * kNp * kNp);
+    __syncthreads();
+    for (int e = tid; e < kNp * NR; e += kNp * kGroups) {
+        c128 y = part[0][e];
+#pragma unroll
+        for (int g = 1; g < kGroups; ++g) y = make_double2(y.x + part[g][e].x, y.y + part[g][e].y);
+        for (int l = 0; l < nlev; ++l) {
+            const c128 a = ylev[((int64_t)l * n + base) * NR + e];
+            y = make_double2(y.x + a.x, y.y + a.y);
+        }
+        if (V) {
+            const c128 b = V[base * NR + e];
+            y = make_double2(b.x - y.x, b.y - y.y);
+        }
+        if (out_r) out_r[base * NR + e] = y;
+        vin[e] = y;
+    }
+    if (!out_z) return;
+    __syncthreads();
+    product(pinv + (size_t)ty * kNp * kNp);
+    __syncthreads();
+    for (int e = tid; e < kNp * NR; e += kNp * kGroups) {
+        c128 z = part[0][e];
+#pragma unroll
+        for (int g = 1; g < kGroups; ++g) z = make_double2(z.x + part[g][e].x, z.y + part[g][e].y);
+        out_z[base * NR + e] = z;
+    }
+}
+
+// Interleave NR columns (stride ld) into an RHS-interleaved block and back; `map`
+// optionally permutes particles (caller <-> internal order).
+template <int NR>
+__global__ void k_interleave(int64_t n, const c128* const* __restrict__ cols, c128* __restrict__ blk, int ncols) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) blk[e * NR + r] = r < ncols ? cols[r][e] : make_double2(0.0, 0.0);
+}
+template <int NR>
+__global__ void k_deinterleave(int64_t n, const c128* __restrict__ blk, c128* const* __restrict__ cols, int ncols) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+        if (r < ncols) cols[r][e] = blk[e * NR + r];
+}
+
 }  // namespace
+
+void launch_rphase_m(hipStream_t s, int nr, const RStrip* st, int64_t n, const c128* fac, const c128* X, c128* T,
+                     const int64_t* tmap) {
+    if (n <= 0) return;
+    dim3 g((unsigned)n);
+    switch (nr) {
+        case 2: hipLaunchKernelGGL(k_rphase_m<2>, g, dim3(256), 0, s, st, fac, X, T, tmap); break;
+        case 4: hipLaunchKernelGGL(k_rphase_m<4>, g, dim3(256), 0, s, st, fac, X, T, tmap); break;
+        default: hipLaunchKernelGGL(k_rphase_m<8>, g, dim3(256), 0, s, st, fac, X, T, tmap); break;
+    }
+}
+void launch_qphase_m(hipStream_t s, int nr, const QStrip* st, int64_t n, const c128* fac, const c128* T, c128* Y) {
+    if (n <= 0) return;
+    dim3 g((unsigned)n);
+    switch (nr) {
+        case 2: hipLaunchKernelGGL(k_qphase_m<2>, g, dim3(256), 0, s, st, fac, T, Y); break;
+        case 4: hipLaunchKernelGGL(k_qphase_m<4>, g, dim3(256), 0, s, st, fac, T, Y); break;
+        default: hipLaunchKernelGGL(k_qphase_m<8>, g, dim3(256), 0, s, st, fac, T, Y); break;
+    }
+}
+void launch_final_m(hipStream_t s, int nr, int32_t N, const int32_t* ptype, const c128* self, const c128* pinv,
+                    const c128* X, const c128* ylev, int nlev, int64_t n, const c128* V, c128* out_r, c128* out_z) {
+    dim3 g(N), b(kNp * kGroups);
+    switch (nr) {
+        case 2: hipLaunchKernelGGL(k_final_m<2>, g, b, 0, s, ptype, self, pinv, X, ylev, nlev, n, V, out_r, out_z); break;
+        case 4: hipLaunchKernelGGL(k_final_m<4>, g, b, 0, s, ptype, self, pinv, X, ylev, nlev, n, V, out_r, out_z); break;
+        default: hipLaunchKernelGGL(k_final_m<8>, g, b, 0, s, ptype, self, pinv, X, ylev, nlev, n, V, out_r, out_z); break;
+    }
+}
+void launch_interleave(hipStream_t s, int nr, int64_t n, const c128* const* cols, c128* blk, int ncols) {
+    dim3 g((unsigned)((n + 255) / 256));
+    switch (nr) {
+        case 2: hipLaunchKernelGGL(k_interleave<2>, g, dim3(256), 0, s, n, cols, blk, ncols); break;
+        case 4: hipLaunchKernelGGL(k_interleave<4>, g, dim3(256), 0, s, n, cols, blk, ncols); break;
+        default: hipLaunchKernelGGL(k_interleave<8>, g, dim3(256), 0, s, n, cols, blk, ncols); break;
+    }
+}
+void launch_deinterleave(hipStream_t s, int nr, int64_t n, const c128* blk, c128* const* cols, int ncols) {
+    dim3 g((unsigned)((n + 255) / 256));
+    switch (nr) {
+        case 2: hipLaunchKernelGGL(k_deinterleave<2>, g, dim3(256), 0, s, n, blk, cols, ncols); break;
+        case 4: hipLaunchKernelGGL(k_deinterleave<4>, g, dim3(256), 0, s, n, blk, cols, ncols); break;
+        default: hipLaunchKernelGGL(k_deinterleave<8>, g, dim3(256), 0, s, n, blk, cols, ncols); break;
+    }
+}
 
 void launch_rphase(hipStream_t s, const RStrip* st, int64_t n, int waves, const c128* fac, const c128* x, c128* t,
                    const int64_t* tmap) {

@@ -680,11 +680,9 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
     op->tmap_len = (int64_t)tmap.size();
 
     keep((void**)&op->d_fac, sizeof(c128) * (size_t)std::max<int64_t>(fcur, 1), "factor panels");
-    keep((void**)&op->d_t, sizeof(c128) * (size_t)std::max<int64_t>(tcur, 1), "rank vector");
     keep((void**)&op->d_tmap, sizeof(int64_t) * std::max<size_t>(tmap.size(), 1), "rank map");
     keep((void**)&op->d_rstrips, sizeof(RStrip) * std::max<size_t>(rstr.size(), 1), "R strips");
     keep((void**)&op->d_qstrips, sizeof(QStrip) * std::max<size_t>(qstr.size(), 1), "Q strips");
-    keep((void**)&op->d_ylev, sizeof(c128) * (size_t)std::max<int64_t>(nact * n, 1), "level partials");
     if (st != QRVIE_OK) {
         for (auto& sg : bld.segments) dfree(ctx, sg.first, sg.second);
         return fail(st);

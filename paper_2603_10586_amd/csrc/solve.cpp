@@ -1,17 +1,22 @@
 // Product, preconditioner, factor export and the GMRES driver (host side).
 //
-// The solve is the paper's left-preconditioned GMRES (§6, with Z_D^-1 of §4):
-// restarted GMRES(m), x0 = 0 unless given; every Arnoldi step costs one fused
-// "product + preconditioner" pass, two classical Gram-Schmidt passes (multi-dot and
-// multi-axpy kernels), a norm and a device-side Givens update.  The host reads two
-// numbers per step (residual estimate and h_{j+1,j}) to decide convergence.  A column
-// is converged when the preconditioned estimate is <= tol ||Z_D^-1 v|| and the true
-// residual ||v - Z_QR x|| / ||v|| <= tol; if only the first holds the solver restarts
-// with a tightened internal tolerance.
+// The solve is the paper's left-preconditioned GMRES (§6, with Z_D^-1 of §4).  Up to
+// eight right-hand sides advance together: each keeps its own Krylov basis, Hessenberg
+// matrix and Givens rotations, while every Arnoldi step applies the compressed operator
+// and the preconditioner to all of them in one multi-RHS product, so the factor panels
+// are streamed from HBM once per step for the whole group.
+//
+// Per Arnoldi step and RHS: one classical Gram-Schmidt pass with the norms fused in, a
+// second pass when the device-side gate opens, and a device-side Givens update.  The host
+// reads two numbers per RHS and step.  A column is converged when its preconditioned
+// estimate is <= tol ||Z_D^-1 v|| and its true residual ||v - Z_QR x|| / ||v|| <= tol.
+// When only the estimate meets its target, the target is tightened and the same Krylov
+// space keeps growing (no restart); restarts happen only at the configured length m.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "internal.h"
 
@@ -19,19 +24,10 @@ using namespace qrvie;
 
 namespace {
 
+constexpr int kGroup = 8;   // right-hand sides advanced together
+
 double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
-}
-
-// y_int = Z_QR x_int (out_r), optionally r = v - Z x and z = Z_D^-1 r (internal order).
-void apply_internal(const qrvie_op* op, hipStream_t s, const c128* x, const c128* v, c128* out_r, c128* out_z) {
-    const qrvie_geom* g = op->g;
-    for (const auto& L : op->rlaunch)
-        launch_rphase(s, op->d_rstrips + L.begin, L.count, L.waves, op->d_fac, x, op->d_t, op->d_tmap);
-    for (const auto& L : op->qlaunch)
-        launch_qphase(s, op->d_qstrips + L.begin, L.count, L.waves, op->d_fac, op->d_t, op->d_ylev);
-    launch_final(s, g->N, g->d_ptype, op->d_self, out_z ? op->d_pinv : nullptr, x, op->d_ylev, op->n_active,
-                 g->ndof(), v, out_r, out_z);
 }
 
 struct Work {
@@ -57,6 +53,43 @@ struct Work {
         if (_s != QRVIE_OK) return _s; \
     } while (0)
 
+// Rank-space and level-partial buffers of the product, owned by the caller of a product
+// so that one operator can be applied from several streams at once.
+struct ProdWork {
+    c128* T = nullptr;
+    c128* Y = nullptr;
+    qrvie_status init(Work& w, const qrvie_op* op, int nr) {
+        CHECK(w.alloc(&T, (size_t)op->t_len * nr, "rank-space vector"));
+        return w.alloc(&Y, (size_t)std::max(op->n_active, 1) * op->g->ndof() * nr, "level partials");
+    }
+};
+
+int round_nr(int na) { return na <= 2 ? 2 : (na <= 4 ? 4 : 8); }
+
+// out_r = v - Z x (or Z x when v is null), out_z = Z_D^-1 out_r (optional); internal order
+void apply_one(const qrvie_op* op, hipStream_t s, const ProdWork& pw, const c128* x, const c128* v, c128* out_r,
+               c128* out_z) {
+    const qrvie_geom* g = op->g;
+    for (const auto& L : op->rlaunch)
+        launch_rphase(s, op->d_rstrips + L.begin, L.count, L.waves, op->d_fac, x, pw.T, op->d_tmap);
+    for (const auto& L : op->qlaunch)
+        launch_qphase(s, op->d_qstrips + L.begin, L.count, L.waves, op->d_fac, pw.T, pw.Y);
+    launch_final(s, g->N, g->d_ptype, op->d_self, out_z ? op->d_pinv : nullptr, x, pw.Y, op->n_active, g->ndof(), v,
+                 out_r, out_z);
+}
+
+// The same for nr RHS-interleaved vectors.
+void apply_multi(const qrvie_op* op, hipStream_t s, const ProdWork& pw, int nr, const c128* X, const c128* V,
+                 c128* out_r, c128* out_z) {
+    const qrvie_geom* g = op->g;
+    for (const auto& L : op->rlaunch)
+        launch_rphase_m(s, nr, op->d_rstrips + L.begin, L.count, op->d_fac, X, pw.T, op->d_tmap);
+    for (const auto& L : op->qlaunch)
+        launch_qphase_m(s, nr, op->d_qstrips + L.begin, L.count, op->d_fac, pw.T, pw.Y);
+    launch_final_m(s, nr, g->N, g->d_ptype, op->d_self, out_z ? op->d_pinv : nullptr, X, pw.Y, op->n_active,
+                   g->ndof(), V, out_r, out_z);
+}
+
 qrvie_status check_vec_args(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const void* a, int64_t lda, const void* b,
                             int64_t ldb, const char* what) {
     if (!ctx || !op || !a || !b || nrhs < 1 || lda < op->g->ndof() || ldb < op->g->ndof()) {
@@ -64,6 +97,278 @@ qrvie_status check_vec_args(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, co
         return QRVIE_ERR_INVALID_ARG;
     }
     return QRVIE_OK;
+}
+
+// ------------------------------------------------------------------ GMRES group engine
+struct Col {
+    c128 *V, *w, *x, *xc, *v, *r, *h, *H, *sn, *g, *y;
+    double *cs, *nrm, *np, *bp;
+    int* gate;
+    double vnorm = 0, pvnorm = 0, prec_tol = 0;
+    int iters = 0, j = 0;
+    bool active = false, converged = false, start = true;
+    double t_apply = 0, t0 = 0;
+    qrvie_solve_info inf{};
+};
+
+struct Group {
+    qrvie_ctx* ctx;
+    const qrvie_op* op;
+    const qrvie_solve_opts* o;
+    hipStream_t s;
+    int64_t n;
+    int m, nch, nblk, na;
+    Work w;
+    ProdWork pw;
+    std::vector<Col> c;
+    c128 *X = nullptr, *Z = nullptr;
+    const c128** dcolsX = nullptr;
+    c128** dcolsW = nullptr;
+    double* status = nullptr;
+    double* hstat = nullptr;      // pinned
+    const c128** hcols = nullptr; // pinned
+    hipEvent_t ev0{}, ev1{};
+
+    Group(qrvie_ctx* cx, const qrvie_op* p, const qrvie_solve_opts* opt, int count)
+        : ctx(cx), op(p), o(opt), s(cx->stream), n(p->g->ndof()), m(0), nch(0), nblk(0), na(count), w(cx), c(count) {}
+    ~Group() {
+        if (hstat) (void)hipHostFree(hstat);
+        if (hcols) (void)hipHostFree(hcols);
+        (void)hipEventDestroy(ev0);
+        (void)hipEventDestroy(ev1);
+    }
+
+    qrvie_status init() {
+        m = std::min(o->restart, o->max_iter);
+        nch = krylov_nchunks(n);
+        nblk = krylov_nblocks(n);
+        CHECK(pw.init(w, op, na > 1 ? round_nr(na) : 1));
+        for (Col& k : c) {
+            CHECK(w.alloc(&k.V, (size_t)n * (m + 1), "krylov basis"));
+            CHECK(w.alloc(&k.w, n, "krylov w"));
+            CHECK(w.alloc(&k.x, n, "solve x"));
+            CHECK(w.alloc(&k.xc, n, "candidate x"));
+            CHECK(w.alloc(&k.v, n, "solve v"));
+            CHECK(w.alloc(&k.r, n, "solve r"));
+            CHECK(w.alloc(&k.h, m + 2, "hessenberg column"));
+            CHECK(w.alloc(&k.H, (size_t)(m + 1) * m, "hessenberg"));
+            CHECK(w.alloc(&k.sn, m, "givens s"));
+            CHECK(w.alloc(&k.g, m + 1, "givens rhs"));
+            CHECK(w.alloc(&k.y, std::max(m, 1), "lsq solution"));
+            CHECK(w.alloc(&k.cs, m, "givens c"));
+            CHECK(w.alloc(&k.nrm, 4, "norms"));
+            CHECK(w.alloc(&k.np, nch, "norm partials"));
+            CHECK(w.alloc(&k.bp, nblk, "update norm partials"));
+            CHECK(w.alloc(&k.gate, 2, "gate"));
+        }
+        CHECK(w.alloc(&pd_all, (size_t)nch * (m + 1) * na, "dot partials"));
+        CHECK(w.alloc(&status, 2 * (size_t)na, "status"));
+        if (na > 1) {
+            const int nr = round_nr(na);
+            CHECK(w.alloc(&X, (size_t)n * nr, "block x"));
+            CHECK(w.alloc(&Z, (size_t)n * nr, "block z"));
+            CHECK(w.alloc(&dcolsX, nr, "column pointers"));
+            CHECK(w.alloc(&dcolsW, nr, "column pointers"));
+        }
+        CHECK(hip_check(ctx, hipHostMalloc((void**)&hstat, sizeof(double) * 2 * (na + 2), hipHostMallocDefault), "pinned"));
+        CHECK(hip_check(ctx, hipHostMalloc((void**)&hcols, sizeof(void*) * 16, hipHostMallocDefault), "pinned"));
+        (void)hipEventCreate(&ev0);
+        (void)hipEventCreate(&ev1);
+        return QRVIE_OK;
+    }
+    c128* pd_all = nullptr;
+    c128* pd(int k) { return pd_all + (size_t)k * nch * (m + 1); }
+
+    qrvie_status read(const double* d, int cnt) {
+        CHECK(hip_check(ctx, hipMemcpyAsync(hstat, d, sizeof(double) * cnt, hipMemcpyDeviceToHost, s), "read"));
+        return hip_check(ctx, hipStreamSynchronize(s), "sync");
+    }
+    void norm_to(Col& k, const c128* vec, double* dst) {
+        launch_norm2(s, vec, n, k.np);
+        launch_reduce_norm(s, k.np, nch, dst, nullptr);
+    }
+    float elapsed() {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ev0, ev1);
+        return ms * 1e-3f;
+    }
+
+    // r = v - Z x, w = Z_D^-1 r: starts a cycle (or finishes the column)
+    qrvie_status start_cycle(int i) {
+        Col& k = c[i];
+        (void)hipEventRecord(ev0, s);
+        apply_one(op, s, pw, k.x, k.v, k.r, k.w);
+        (void)hipEventRecord(ev1, s);
+        k.inf.n_apply++;
+        k.inf.n_prec++;
+        norm_to(k, k.r, k.nrm + 0);
+        norm_to(k, k.w, k.nrm + 1);
+        CHECK(read(k.nrm, 2));
+        k.t_apply += elapsed();
+        const double tr = std::sqrt(hstat[0]) / k.vnorm;
+        const double beta = std::sqrt(hstat[1]);
+        if (!std::isfinite(beta)) { set_err(ctx, "solve: non-finite residual"); return QRVIE_ERR_DEVICE; }
+        k.inf.rel_res_true = tr;
+        k.inf.rel_res_prec = beta / k.pvnorm;
+        if (k.inf.rel_res_prec <= k.prec_tol) {
+            if (tr <= o->tol) { k.converged = true; k.active = false; return QRVIE_OK; }
+            k.prec_tol = std::max(k.prec_tol * 0.5 * o->tol / tr, 1e-15);
+        }
+        if (k.iters >= o->max_iter) { k.active = false; return QRVIE_OK; }
+        launch_scale_into(s, k.w, n, k.nrm + 1, k.V, k.g);       // V0 = w / beta, g0 = beta
+        k.j = 0;
+        k.start = false;
+        return QRVIE_OK;
+    }
+
+    // Gram-Schmidt + Givens of column i's step j (w already holds Z_D^-1 Z v_j)
+    void arnoldi_tail(int i) {
+        Col& k = c[i];
+        const int j = k.j;
+        c128* P = pd(i);
+        launch_multidot(s, k.V, n, j + 1, k.w, n, P, k.np, nullptr);
+        launch_reduce_dots(s, P, nch, j + 1, k.h, 0, nullptr);
+        launch_reduce_norm(s, k.np, nch, k.nrm + 3, nullptr);
+        launch_gemv_sub(s, k.V, n, j + 1, k.h, k.w, n, k.bp, nullptr);
+        launch_reduce_norm(s, k.bp, nblk, k.nrm + 2, nullptr);
+        launch_reorth_gate(s, k.nrm + 2, k.nrm + 3, k.gate);
+        launch_multidot(s, k.V, n, j + 1, k.w, n, P, nullptr, k.gate);
+        launch_reduce_dots(s, P, nch, j + 1, k.y, 0, k.gate);
+        launch_reduce_dots(s, P, nch, j + 1, k.h, 1, k.gate);
+        launch_gemv_sub(s, k.V, n, j + 1, k.y, k.w, n, k.bp, k.gate);
+        launch_reduce_norm(s, k.bp, nblk, k.nrm + 2, k.gate);
+        launch_givens(s, j, k.h, k.H, m + 1, k.cs, k.sn, k.g, k.nrm + 2, status + 2 * i);
+        launch_scale_into(s, k.w, n, k.nrm + 2, k.V + (size_t)(j + 1) * n, nullptr);
+    }
+
+    // candidate x_c = x + V y; accept if the true residual meets tol
+    qrvie_status candidate(int i, int kused, bool& accepted) {
+        Col& k = c[i];
+        launch_trisolve(s, kused, k.H, m + 1, k.g, k.y);
+        CHECK(hip_check(ctx, hipMemcpyAsync(k.xc, k.x, sizeof(c128) * n, hipMemcpyDeviceToDevice, s), "x_c"));
+        launch_gemv_add(s, k.V, n, kused, k.y, k.xc, n);
+        (void)hipEventRecord(ev0, s);
+        apply_one(op, s, pw, k.xc, k.v, k.r, nullptr);
+        (void)hipEventRecord(ev1, s);
+        k.inf.n_apply++;
+        norm_to(k, k.r, k.nrm + 0);
+        CHECK(read(k.nrm, 1));
+        k.t_apply += elapsed();
+        const double tr = std::sqrt(hstat[0]) / k.vnorm;
+        k.inf.rel_res_true = tr;
+        accepted = tr <= o->tol;
+        if (accepted) CHECK(hip_check(ctx, hipMemcpyAsync(k.x, k.xc, sizeof(c128) * n, hipMemcpyDeviceToDevice, s), "x"));
+        else k.prec_tol = std::max(k.prec_tol * 0.5 * o->tol / tr, 1e-15);
+        return QRVIE_OK;
+    }
+
+    qrvie_status run() {
+        for (;;) {
+            for (int i = 0; i < na; ++i)
+                if (c[i].active && c[i].start) CHECK(start_cycle(i));
+            std::vector<int> act;
+            for (int i = 0; i < na; ++i)
+                if (c[i].active) act.push_back(i);
+            if (act.empty()) return QRVIE_OK;
+            // one product + preconditioner for every active column
+            (void)hipEventRecord(ev0, s);
+            if (act.size() == 1) {
+                Col& k = c[act[0]];
+                apply_one(op, s, pw, k.V + (size_t)k.j * n, nullptr, nullptr, k.w);
+            } else {
+                const int nr = round_nr((int)act.size());
+                for (size_t a = 0; a < act.size(); ++a) hcols[a] = c[act[a]].V + (size_t)c[act[a]].j * n;
+                for (size_t a = 0; a < act.size(); ++a) hcols[8 + a] = c[act[a]].w;
+                CHECK(hip_check(ctx, hipMemcpyAsync(dcolsX, hcols, sizeof(void*) * act.size(), hipMemcpyHostToDevice, s), "cols"));
+                CHECK(hip_check(ctx, hipMemcpyAsync(dcolsW, hcols + 8, sizeof(void*) * act.size(), hipMemcpyHostToDevice, s), "cols"));
+                launch_interleave(s, nr, n, dcolsX, X, (int)act.size());
+                apply_multi(op, s, pw, nr, X, nullptr, nullptr, Z);
+                launch_deinterleave(s, nr, n, Z, dcolsW, (int)act.size());
+            }
+            (void)hipEventRecord(ev1, s);
+            for (int i : act) arnoldi_tail(i);
+            CHECK(hip_check(ctx, hipGetLastError(), "gmres launch"));
+            CHECK(read(status, 2 * na));
+            const double tshare = elapsed() / act.size();
+            std::vector<double> st(hstat, hstat + 2 * na);
+            for (int i : act) {
+                Col& k = c[i];
+                k.t_apply += tshare;
+                k.inf.n_apply++;
+                k.inf.n_prec++;
+                k.iters++;
+                k.j++;
+                const int kused = k.j;
+                const double est = st[2 * i] / k.pvnorm;
+                const bool breakdown = st[2 * i + 1] == 0.0;
+                k.inf.rel_res_prec = est;
+                bool end_cycle = kused >= m || k.iters >= o->max_iter;
+                if (est <= k.prec_tol || breakdown) {
+                    bool ok = false;
+                    CHECK(candidate(i, kused, ok));
+                    if (ok) { k.converged = true; k.active = false; continue; }
+                    if (breakdown) end_cycle = true;
+                }
+                if (end_cycle) {
+                    launch_trisolve(s, kused, k.H, m + 1, k.g, k.y);
+                    launch_gemv_add(s, k.V, n, kused, k.y, k.x, n);
+                    k.inf.restarts++;
+                    k.start = true;   // the next start_cycle computes the true residual
+                }
+            }
+        }
+    }
+};
+
+qrvie_status solve_group(qrvie_ctx* ctx, const qrvie_op* op, int na, const c128* const* v, c128* const* x,
+                         const qrvie_solve_opts* o, qrvie_solve_info* info) {
+    const double t0 = now_s();
+    Group G(ctx, op, o, na);
+    CHECK(G.init());
+    hipStream_t s = ctx->stream;
+    const qrvie_geom* g = op->g;
+    for (int i = 0; i < na; ++i) {
+        Col& k = G.c[i];
+        launch_permute(s, g->N, g->d_i2c, v[i], k.v, 1);
+        if (o->use_x0) launch_permute(s, g->N, g->d_i2c, x[i], k.x, 1);
+        else CHECK(hip_check(ctx, hipMemsetAsync(k.x, 0, sizeof(c128) * G.n, s), "x0"));
+        CHECK(hip_check(ctx, hipMemsetAsync(k.gate, 0, 2 * sizeof(int), s), "gate"));
+        G.norm_to(k, k.v, k.nrm + 0);
+        launch_block_apply(s, g->N, g->d_ptype, op->d_pinv, k.v, k.r);
+        G.norm_to(k, k.r, k.nrm + 1);
+        CHECK(G.read(k.nrm, 2));
+        k.vnorm = std::sqrt(G.hstat[0]);
+        k.pvnorm = std::sqrt(G.hstat[1]);
+        if (!std::isfinite(k.vnorm)) {
+            set_err(ctx, "solve: right-hand side has non-finite entries");
+            return QRVIE_ERR_INVALID_ARG;
+        }
+        k.prec_tol = o->tol;
+        k.active = k.vnorm > 0.0;
+        if (!k.active) {
+            CHECK(hip_check(ctx, hipMemsetAsync(k.x, 0, sizeof(c128) * G.n, s), "zero x"));
+            k.converged = true;
+        }
+    }
+    CHECK(G.run());
+    qrvie_status overall = QRVIE_OK;
+    for (int i = 0; i < na; ++i) {
+        Col& k = G.c[i];
+        int hg[2] = {0, 0};
+        CHECK(hip_check(ctx, hipMemcpyAsync(hg, k.gate, sizeof hg, hipMemcpyDeviceToHost, s), "gate"));
+        launch_permute(s, g->N, g->d_i2c, k.x, x[i], 0);
+        CHECK(hip_check(ctx, hipStreamSynchronize(s), "solve"));
+        k.inf.iterations = k.iters;
+        k.inf.converged = k.converged ? 1 : 0;
+        k.inf.n_reorth = hg[1];
+        k.inf.t_apply_s = k.t_apply;
+        k.inf.t_prec_s = 0.0;   // fused into the product pass
+        k.inf.t_total_s = now_s() - t0;
+        k.inf.t_krylov_s = std::max(0.0, k.inf.t_total_s - k.t_apply);
+        if (info) info[i] = k.inf;
+        if (!k.converged) overall = QRVIE_NOT_CONVERGED;
+    }
+    return overall;
 }
 
 }  // namespace
@@ -74,17 +379,49 @@ qrvie_status qrvie_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const
                          qrvie_c128* y, int64_t ldy) {
     CHECK(check_vec_args(ctx, op, nrhs, x, ldx, y, ldy, "apply"));
     const int64_t n = op->g->ndof();
+    hipStream_t s = ctx->stream;
     Work w(ctx);
-    c128 *xi, *yi;
-    CHECK(w.alloc(&xi, n, "apply work"));
-    CHECK(w.alloc(&yi, n, "apply work"));
-    for (int r = 0; r < nrhs; ++r) {
-        launch_permute(ctx->stream, op->g->N, op->g->d_i2c, (const c128*)x + r * ldx, xi, 1);
-        apply_internal(op, ctx->stream, xi, nullptr, yi, nullptr);
-        launch_permute(ctx->stream, op->g->N, op->g->d_i2c, yi, (c128*)y + r * ldy, 0);
+    ProdWork pw;
+    const int nrmax = nrhs > 1 ? kGroup : 1;
+    CHECK(pw.init(w, op, nrmax));
+    c128 *xi, *yi, *X = nullptr, *Y = nullptr;
+    CHECK(w.alloc(&xi, (size_t)n * nrmax, "apply work"));
+    CHECK(w.alloc(&yi, (size_t)n * nrmax, "apply work"));
+    if (nrhs == 1) {
+        launch_permute(s, op->g->N, op->g->d_i2c, (const c128*)x, xi, 1);
+        apply_one(op, s, pw, xi, nullptr, yi, nullptr);
+        launch_permute(s, op->g->N, op->g->d_i2c, yi, (c128*)y, 0);
+    } else {
+        CHECK(w.alloc(&X, (size_t)n * kGroup, "apply block"));
+        CHECK(w.alloc(&Y, (size_t)n * kGroup, "apply block"));
+        c128** dcols;
+        CHECK(w.alloc(&dcols, 2 * kGroup, "column pointers"));
+        std::vector<c128*> hc(2 * kGroup);
+        for (int r0 = 0; r0 < nrhs; r0 += kGroup) {
+            const int cnt = std::min(kGroup, nrhs - r0);
+            if (cnt == 1) {
+                launch_permute(s, op->g->N, op->g->d_i2c, (const c128*)x + r0 * ldx, xi, 1);
+                apply_one(op, s, pw, xi, nullptr, yi, nullptr);
+                launch_permute(s, op->g->N, op->g->d_i2c, yi, (c128*)y + r0 * ldy, 0);
+                continue;
+            }
+            const int nr = round_nr(cnt);
+            for (int a = 0; a < cnt; ++a) {
+                launch_permute(s, op->g->N, op->g->d_i2c, (const c128*)x + (r0 + a) * ldx, xi + (size_t)a * n, 1);
+                hc[a] = xi + (size_t)a * n;
+                hc[kGroup + a] = yi + (size_t)a * n;
+            }
+            CHECK(hip_check(ctx, hipMemcpyAsync(dcols, hc.data(), sizeof(void*) * 2 * kGroup, hipMemcpyHostToDevice, s), "cols"));
+            CHECK(hip_check(ctx, hipStreamSynchronize(s), "cols"));   // hc is reused next pass
+            launch_interleave(s, nr, n, (const c128* const*)dcols, X, cnt);
+            apply_multi(op, s, pw, nr, X, nullptr, Y, nullptr);
+            launch_deinterleave(s, nr, n, Y, dcols + kGroup, cnt);
+            for (int a = 0; a < cnt; ++a)
+                launch_permute(s, op->g->N, op->g->d_i2c, yi + (size_t)a * n, (c128*)y + (r0 + a) * ldy, 0);
+        }
     }
     CHECK(hip_check(ctx, hipGetLastError(), "apply launch"));
-    return hip_check(ctx, hipStreamSynchronize(ctx->stream), "apply");
+    return hip_check(ctx, hipStreamSynchronize(s), "apply");
 }
 
 qrvie_status qrvie_op_profile_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t reps, double* ms, int64_t* bytes) {
@@ -93,6 +430,8 @@ qrvie_status qrvie_op_profile_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t 
     const int64_t n = g->ndof();
     hipStream_t s = ctx->stream;
     Work w(ctx);
+    ProdWork pw;
+    CHECK(pw.init(w, op, 1));
     c128 *xi, *yi;
     CHECK(w.alloc(&xi, n, "profile x"));
     CHECK(w.alloc(&yi, n, "profile y"));
@@ -103,12 +442,12 @@ qrvie_status qrvie_op_profile_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t 
     for (int r = 0; r < reps; ++r) {
         (void)hipEventRecord(ev[0], s);
         for (const auto& L : op->rlaunch)
-            launch_rphase(s, op->d_rstrips + L.begin, L.count, L.waves, op->d_fac, xi, op->d_t, op->d_tmap);
+            launch_rphase(s, op->d_rstrips + L.begin, L.count, L.waves, op->d_fac, xi, pw.T, op->d_tmap);
         (void)hipEventRecord(ev[1], s);
         for (const auto& L : op->qlaunch)
-            launch_qphase(s, op->d_qstrips + L.begin, L.count, L.waves, op->d_fac, op->d_t, op->d_ylev);
+            launch_qphase(s, op->d_qstrips + L.begin, L.count, L.waves, op->d_fac, pw.T, pw.Y);
         (void)hipEventRecord(ev[2], s);
-        launch_final(s, g->N, g->d_ptype, op->d_self, nullptr, xi, op->d_ylev, op->n_active, n, nullptr, yi, nullptr);
+        launch_final(s, g->N, g->d_ptype, op->d_self, nullptr, xi, pw.Y, op->n_active, n, nullptr, yi, nullptr);
         (void)hipEventRecord(ev[3], s);
         CHECK(hip_check(ctx, hipEventSynchronize(ev[3]), "profile"));
         float t = 0.f;
@@ -156,7 +495,6 @@ qrvie_status qrvie_precondition(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs
 qrvie_status qrvie_op_export_block(const qrvie_op* op, int64_t b, qrvie_block_info* info, qrvie_c128* Q,
                                    qrvie_c128* R) {
     if (!op || b < 0 || b >= (int64_t)op->rank.size()) return QRVIE_ERR_INVALID_ARG;
-    // recover the block geometry from the panel bookkeeping
     qrvie_ctx* ctx = op->ctx;
     const int r = op->rank[b];
     const BlockRec& e = op->blocks[b];
@@ -197,192 +535,19 @@ qrvie_status qrvie_solve(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const
         set_err(ctx, "solve: invalid options");
         return QRVIE_ERR_INVALID_ARG;
     }
-    hipStream_t s = ctx->stream;
-    const qrvie_geom* g = op->g;
-    const int64_t n = g->ndof();
-    const int m = o->restart;
-    const int nch = krylov_nchunks(n);
-    Work w(ctx);
-    c128 *V, *wv, *xi, *vi, *r, *pd, *h, *H, *sn, *gv, *y;
-    double *np, *nrm, *cs, *status;
-    CHECK(w.alloc(&V, (size_t)n * (m + 1), "krylov basis"));
-    CHECK(w.alloc(&wv, n, "krylov w"));
-    CHECK(w.alloc(&xi, n, "solve x"));
-    c128* xc;
-    CHECK(w.alloc(&xc, n, "solve candidate x"));
-    CHECK(w.alloc(&vi, n, "solve v"));
-    CHECK(w.alloc(&r, n, "solve r"));
-    CHECK(w.alloc(&pd, (size_t)nch * (m + 1), "dot partials"));
-    CHECK(w.alloc(&np, nch, "norm partials"));
-    CHECK(w.alloc(&nrm, 4, "norms"));
-    CHECK(w.alloc(&h, m + 2, "hessenberg column"));
-    CHECK(w.alloc(&H, (size_t)(m + 1) * m, "hessenberg"));
-    CHECK(w.alloc(&cs, m, "givens c"));
-    CHECK(w.alloc(&sn, m, "givens s"));
-    CHECK(w.alloc(&gv, m + 1, "givens rhs"));
-    CHECK(w.alloc(&y, m, "lsq solution"));
-    CHECK(w.alloc(&status, 2, "status"));
-    double* hstat = nullptr;
-    CHECK(hip_check(ctx, hipHostMalloc((void**)&hstat, 4 * sizeof(double), hipHostMallocDefault), "pinned status"));
-    struct PinnedFree { double* p; ~PinnedFree() { if (p) (void)hipHostFree(p); } } pf{hstat};
-
-    const int nblk = krylov_nblocks(n);
-    double* bp;
-    int* gate;
-    CHECK(w.alloc(&bp, nblk, "update norm partials"));
-    CHECK(w.alloc(&gate, 2, "reorthogonalisation gate"));
-    auto norm_to = [&](const c128* vec, double* dst) {
-        launch_norm2(s, vec, n, np);
-        launch_reduce_norm(s, np, nch, dst, nullptr);
-    };
-    auto read = [&](const double* d, int cnt) -> qrvie_status {
-        CHECK(hip_check(ctx, hipMemcpyAsync(hstat, d, sizeof(double) * cnt, hipMemcpyDeviceToHost, s), "read"));
-        return hip_check(ctx, hipStreamSynchronize(s), "sync");
-    };
-
     qrvie_status overall = QRVIE_OK;
-    hipEvent_t ev0, ev1;
-    (void)hipEventCreate(&ev0);
-    (void)hipEventCreate(&ev1);
-    for (int rhs = 0; rhs < nrhs; ++rhs) {
-        const double t0 = now_s();
-        qrvie_solve_info inf{};
-        double t_apply = 0.0, t_kry = 0.0;
-        launch_permute(s, g->N, g->d_i2c, (const c128*)v + rhs * ldv, vi, 1);
-        if (o->use_x0) launch_permute(s, g->N, g->d_i2c, (const c128*)x + rhs * ldx, xi, 1);
-        else CHECK(hip_check(ctx, hipMemsetAsync(xi, 0, sizeof(c128) * n, s), "x0"));
-        // ||v|| and ||Z_D^-1 v||
-        norm_to(vi, nrm + 0);
-        launch_block_apply(s, g->N, g->d_ptype, op->d_pinv, vi, r);
-        norm_to(r, nrm + 1);
-        CHECK(read(nrm, 2));
-        const double vnorm = std::sqrt(hstat[0]), pvnorm = std::sqrt(hstat[1]);
-        if (!(std::isfinite(vnorm))) {
-            set_err(ctx, "solve: right-hand side has non-finite entries");
-            return QRVIE_ERR_INVALID_ARG;
+    for (int r0 = 0; r0 < nrhs; r0 += kGroup) {
+        const int cnt = std::min(kGroup, nrhs - r0);
+        std::vector<const c128*> vv(cnt);
+        std::vector<c128*> xx(cnt);
+        for (int a = 0; a < cnt; ++a) {
+            vv[a] = (const c128*)v + (r0 + a) * ldv;
+            xx[a] = (c128*)x + (r0 + a) * ldx;
         }
-        if (vnorm == 0.0) {
-            CHECK(hip_check(ctx, hipMemsetAsync((c128*)x + rhs * ldx, 0, sizeof(c128) * n, s), "zero x"));
-            inf.converged = 1;
-            if (info) info[rhs] = inf;
-            continue;
-        }
-        CHECK(hip_check(ctx, hipMemsetAsync(gate, 0, 2 * sizeof(int), s), "gate"));
-        double prec_tol = o->tol;
-        int iters = 0;
-        bool converged = false;
-        while (true) {
-            // r = v - Z x (true residual), V0 = Z_D^-1 r
-            (void)hipEventRecord(ev0, s);
-            apply_internal(op, s, xi, vi, r, wv);
-            (void)hipEventRecord(ev1, s);
-            inf.n_apply++;
-            inf.n_prec++;
-            norm_to(r, nrm + 0);
-            norm_to(wv, nrm + 1);
-            CHECK(read(nrm, 2));
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, ev0, ev1);
-            t_apply += ms * 1e-3;
-            const double true_rel = std::sqrt(hstat[0]) / vnorm;
-            const double beta = std::sqrt(hstat[1]);
-            inf.rel_res_true = true_rel;
-            inf.rel_res_prec = beta / pvnorm;
-            if (!std::isfinite(beta)) { set_err(ctx, "solve: non-finite residual"); return QRVIE_ERR_DEVICE; }
-            if (inf.rel_res_prec <= prec_tol) {
-                if (true_rel <= o->tol) { converged = true; break; }
-                prec_tol = std::max(prec_tol * 0.5 * o->tol / true_rel, 1e-15);
-            }
-            if (iters >= o->max_iter) break;
-            const double tk0 = now_s();
-            launch_scale_into(s, wv, n, nrm + 1, V, gv);     // V0 = w / beta, g0 = beta
-            int k_used = 0;
-            bool cycle_done = false;
-            for (int j = 0; j < m && iters < o->max_iter && !cycle_done; ++j) {
-                (void)hipEventRecord(ev0, s);
-                apply_internal(op, s, V + (size_t)j * n, nullptr, nullptr, wv);   // w = Z_D^-1 Z v_j
-                (void)hipEventRecord(ev1, s);
-                inf.n_apply++;
-                inf.n_prec++;
-                // one classical Gram-Schmidt pass with ||w|| and ||w'|| fused in
-                launch_multidot(s, V, n, j + 1, wv, n, pd, np, nullptr);
-                launch_reduce_dots(s, pd, nch, j + 1, h, 0, nullptr);
-                launch_reduce_norm(s, np, nch, nrm + 3, nullptr);
-                launch_gemv_sub(s, V, n, j + 1, h, wv, n, bp, nullptr);
-                launch_reduce_norm(s, bp, nblk, nrm + 2, nullptr);
-                // the second pass runs only if the gate opens (||w'||^2 < ||w||^2 / 2)
-                launch_reorth_gate(s, nrm + 2, nrm + 3, gate);
-                launch_multidot(s, V, n, j + 1, wv, n, pd, nullptr, gate);
-                launch_reduce_dots(s, pd, nch, j + 1, y, 0, gate);
-                launch_reduce_dots(s, pd, nch, j + 1, h, 1, gate);
-                launch_gemv_sub(s, V, n, j + 1, y, wv, n, bp, gate);
-                launch_reduce_norm(s, bp, nblk, nrm + 2, gate);
-                launch_givens(s, j, h, H, m + 1, cs, sn, gv, nrm + 2, status);
-                launch_scale_into(s, wv, n, nrm + 2, V + (size_t)(j + 1) * n, nullptr);
-                CHECK(read(status, 2));
-                float ms2 = 0.f;
-                (void)hipEventElapsedTime(&ms2, ev0, ev1);
-                t_apply += ms2 * 1e-3;
-                ++iters;
-                k_used = j + 1;
-                const double est = hstat[0] / pvnorm;
-                const bool breakdown = hstat[1] == 0.0;
-                if (est <= prec_tol || breakdown) {
-                    // candidate x_c = x + V y: accept it if the true residual meets tol too;
-                    // otherwise tighten the preconditioned target and keep extending this
-                    // Krylov space instead of restarting
-                    launch_trisolve(s, k_used, H, m + 1, gv, y);
-                    CHECK(hip_check(ctx, hipMemcpyAsync(xc, xi, sizeof(c128) * n, hipMemcpyDeviceToDevice, s), "x_c"));
-                    launch_gemv_add(s, V, n, k_used, y, xc, n);
-                    (void)hipEventRecord(ev0, s);
-                    apply_internal(op, s, xc, vi, r, nullptr);
-                    (void)hipEventRecord(ev1, s);
-                    inf.n_apply++;
-                    norm_to(r, nrm + 0);
-                    CHECK(read(nrm, 1));
-                    float ms3 = 0.f;
-                    (void)hipEventElapsedTime(&ms3, ev0, ev1);
-                    t_apply += ms3 * 1e-3;
-                    const double tr = std::sqrt(hstat[0]) / vnorm;
-                    inf.rel_res_true = tr;
-                    inf.rel_res_prec = est;
-                    if (tr <= o->tol) {
-                        CHECK(hip_check(ctx, hipMemcpyAsync(xi, xc, sizeof(c128) * n, hipMemcpyDeviceToDevice, s), "x"));
-                        converged = true;
-                        cycle_done = true;
-                        k_used = 0;
-                    } else {
-                        prec_tol = std::max(prec_tol * 0.5 * o->tol / tr, 1e-15);
-                        if (breakdown) cycle_done = true;
-                    }
-                }
-            }
-            if (k_used > 0) {
-                launch_trisolve(s, k_used, H, m + 1, gv, y);
-                launch_gemv_add(s, V, n, k_used, y, xi, n);
-            }
-            CHECK(hip_check(ctx, hipGetLastError(), "gmres launch"));
-            inf.restarts++;
-            t_kry += now_s() - tk0;
-            if (converged) break;
-        }
-        inf.iterations = iters;
-        int hgate[2] = {0, 0};
-        CHECK(hip_check(ctx, hipMemcpyAsync(hgate, gate, sizeof hgate, hipMemcpyDeviceToHost, s), "gate"));
-        CHECK(hip_check(ctx, hipStreamSynchronize(s), "gate"));
-        inf.n_reorth = hgate[1];
-        inf.converged = converged ? 1 : 0;
-        launch_permute(s, g->N, g->d_i2c, xi, (c128*)x + rhs * ldx, 0);
-        CHECK(hip_check(ctx, hipStreamSynchronize(s), "solve"));
-        inf.t_total_s = now_s() - t0;
-        inf.t_apply_s = t_apply;
-        inf.t_krylov_s = std::max(0.0, t_kry - t_apply);
-        inf.t_prec_s = 0.0;  // fused into the product pass
-        if (info) info[rhs] = inf;
-        if (!converged) overall = QRVIE_NOT_CONVERGED;
+        const qrvie_status st = solve_group(ctx, op, cnt, vv.data(), xx.data(), o, info ? info + r0 : nullptr);
+        if (st == QRVIE_NOT_CONVERGED) overall = st;
+        else if (st != QRVIE_OK) return st;
     }
-    (void)hipEventDestroy(ev0);
-    (void)hipEventDestroy(ev1);
     return overall;
 }
 

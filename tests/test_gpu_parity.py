@@ -125,6 +125,40 @@ def test_apply_matches_oracle_on_the_same_factors_and_bounds_dense(name):
         assert np.linalg.norm(y[r] - Zx) <= c.eps * np.linalg.norm(Zoff) * np.linalg.norm(x[r])
 
 
+@pytest.mark.parametrize("nrhs", [2, 3, 8, 11])
+def test_multi_rhs_apply_matches_the_oracle(nrhs):
+    """Blocks of right-hand sides stream each factor once for the whole block."""
+    c = case("rand6x7")
+    n = c.geom.ndof
+    rng = np.random.default_rng(nrhs)
+    x = rng.standard_normal((nrhs, n)) + 1j * rng.standard_normal((nrhs, n))
+    y = to_host(c.op.apply(to_dev(x)))
+    sb = greens.self_blocks(c.disc)
+    fac = [(f[0], f[1], f[2], f[3]) for f in c.factors()]
+    ref = compressed.compressed_apply(sb, fac, x.T).T
+    for r in range(nrhs):
+        assert np.linalg.norm(y[r] - ref[r]) <= 1e-12 * np.linalg.norm(ref[r])
+
+
+def test_grouped_solve_matches_lu_for_every_rhs():
+    """Up to eight right-hand sides advance together and share each product (§8 a8)."""
+    import paper_2603_10586_amd as q
+    c = case("rand6x7")
+    th = np.linspace(-30, 30, 5)
+    v = q.rhs_plane_waves(c.ctx, c.geom, np.concatenate([th, th]), np.zeros(10), [0] * 5 + [1] * 5)
+    x, info, st = c.op.solve(v, restart=60, tol=1e-10, max_iter=3000)
+    assert st == 0 and all(i["converged"] for i in info)
+    sb = greens.self_blocks(c.disc)
+    ZQR = compressed.dense_from_factors(sb, [(f[0], f[1], f[2], f[3]) for f in c.factors()])
+    vh, xh = to_host(v), to_host(x)
+    ref = np.linalg.solve(ZQR, vh.T).T
+    for r in range(10):
+        assert np.linalg.norm(xh[r] - ref[r]) <= 1e-8 * np.linalg.norm(ref[r])
+    # each column alone gives the same solution (to the solver tolerance)
+    x1, info1, _ = c.op.solve(v[3:4].contiguous(), restart=60, tol=1e-10, max_iter=3000)
+    assert np.linalg.norm(to_host(x1)[0] - xh[3]) <= 1e-8 * np.linalg.norm(xh[3])
+
+
 def test_apply_is_bitwise_reproducible():
     c = case("rand6x7")
     x = to_dev(np.random.default_rng(9).standard_normal(c.geom.ndof) + 0.5j)
@@ -174,7 +208,7 @@ def test_solve_is_independent_of_the_restart_length(restart):
     ref = np.linalg.solve(ZQR, to_host(v)[0])
     assert np.linalg.norm(to_host(x)[0] - ref) <= 1e-8 * np.linalg.norm(ref)
     if restart >= 4096:
-        assert info[0]["restarts"] == 1
+        assert info[0]["restarts"] == 0          # accepted inside the first Krylov space
 
 
 def test_solve_reports_not_converged_with_the_best_iterate():
