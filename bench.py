@@ -104,6 +104,37 @@ def cpu_baseline(op, geom, seconds: float = 15.0, seed: int = 0) -> dict:
                       f"({fbytes / 1e9:.2f} GB of factors), {reps} passes in {t:.1f} s; CPU {cpu_model()}"}
 
 
+def serving(args) -> int:
+    """Continuous batching: Poisson arrivals of arrays with side U{lo..hi}, random radii,
+    1-16 plane waves each, tolerance 1e-6; latency is arrival to result on the host."""
+    import workloads as W
+    from paper_2603_10586_amd.server import DeviceExecutor, Server, ServerOpts, replay
+    reqs = W.serving_requests(n=args.serving, seed=0, rate_per_s=args.serving_rate,
+                              side_lo=args.serving_side[0], side_hi=args.serving_side[1])
+    opts = ServerOpts(slots=args.serving_slots, hbm_budget=200 << 30, eps=args.eps, restart=args.restart,
+                      max_iter=args.max_iter)
+    srv = Server(opts, DeviceExecutor)
+    t0 = time.perf_counter()
+    jobs = replay(srv, reqs)
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    ok = all(j.status == 0 for j in jobs)
+    worst = max(i["rel_res_true"] for j in jobs for i in j.info)
+    print(json.dumps({
+        "metric": METRIC, "value": round(st["rhs_solves_per_s"], 4), "unit": "RHS solves/s", "n_gpus": 1,
+        "steps": len(jobs), "warmup": 0, "ms_per_step": round(wall / len(jobs) * 1e3, 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"serving: {len(jobs)} requests, Poisson {args.serving_rate}/s, side "
+                               f"U{{{args.serving_side[0]}..{args.serving_side[1]}}}, radii U[0.15, 0.25], "
+                               f"1-16 RHS, tol 1e-6, {args.serving_slots} slots"},
+        "latency_ms_p50": round(st["latency_p50_s"] * 1e3, 1), "latency_ms_p99": round(st["latency_p99_s"] * 1e3, 1),
+        "requests_per_s": round(st["requests_per_s"], 4), "queue_wait_ms_p50": round(st["queue_wait_p50_s"] * 1e3, 1),
+        "peak_admitted_bytes": st["peak_bytes"], "all_converged": ok, "worst_true_residual": worst,
+        "wall_s": round(wall, 1)}))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +153,11 @@ def main() -> int:
                     help="build the operator and time products only (for hardware-counter runs)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device copy of this many MiB five times (counter calibration)")
+    ap.add_argument("--serving", type=int, default=0,
+                    help="run the serving workload with this many Poisson-arriving requests instead")
+    ap.add_argument("--serving-rate", type=float, default=1.0, help="request arrival rate (1/s)")
+    ap.add_argument("--serving-side", type=int, nargs=2, default=[8, 48], help="array side range")
+    ap.add_argument("--serving-slots", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -141,6 +177,9 @@ def main() -> int:
 
     import paper_2603_10586_amd as q
     import workloads as W
+
+    if args.serving:
+        return serving(args)
 
     arr = W.mid(0) if args.side == 32 else W.random_lattice(args.side, seed=0)
     inc = W.mid_incidence()

@@ -240,6 +240,12 @@ typedef struct {
     int32_t n_reorth;     /* Arnoldi steps that needed the second Gram-Schmidt pass */
 } qrvie_solve_info;
 
+/* Upper bound of the device bytes qrvie_solve allocates for nrhs right-hand sides
+ * (Krylov bases, Hessenberg data and product workspaces), for admission control by
+ * callers that share one device; `op` may be NULL before the operator exists. */
+qrvie_status qrvie_solve_footprint_estimate(const qrvie_geom* g, const qrvie_op* op, int32_t nrhs,
+                                            const qrvie_solve_opts* opts, size_t* bytes);
+
 /*
  * Solve Z_QR x = v with left-preconditioned restarted GMRES (the paper's
  * solver with the preconditioner of §4), one right-hand side after another.

@@ -87,6 +87,7 @@ SIGNATURES = {
     "qrvie_precondition": (ST, [P, P, I32, P, I64, P, I64]),
     "qrvie_rhs_plane_waves": (ST, [P, P, I32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(I32), P, I64]),
     "qrvie_solve": (ST, [P, P, I32, P, I64, P, I64, C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),
+    "qrvie_solve_footprint_estimate": (ST, [P, P, I32, C.POINTER(SolveOpts), C.POINTER(C.c_size_t)]),
 }
 
 _lib = None

@@ -177,6 +177,15 @@ class Operator:
         geom.ctx.check(st, "footprint")
         return int(out.value)
 
+    @staticmethod
+    def solve_footprint_estimate(geom: Geometry, nrhs: int, restart: int, max_iter: int, op=None) -> int:
+        o = L.SolveOpts(restart=restart, max_iter=max_iter, mode=L.SOLVE_FP64, tol=1e-6, use_x0=0)
+        out = C.c_size_t()
+        st = geom.ctx.lib.qrvie_solve_footprint_estimate(geom.h, op.h if op is not None else None, nrhs,
+                                                         C.byref(o), C.byref(out))
+        geom.ctx.check(st, "solve footprint")
+        return int(out.value)
+
     def stats(self) -> dict:
         s = L.OpStats()
         self.ctx.check(self.ctx.lib.qrvie_op_stats_get(self.h, C.byref(s)), "stats")

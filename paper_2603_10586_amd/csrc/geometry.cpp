@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <unordered_map>
 
 #include "internal.h"
@@ -103,10 +104,15 @@ static std::map<const qrvie_geom*, GeomLattice>& lattices() {
     static std::map<const qrvie_geom*, GeomLattice> m;
     return m;
 }
+static std::mutex& lattice_mutex() {   // geometries are created and destroyed from several threads
+    static std::mutex mu;
+    return mu;
+}
 
 namespace qrvie {
 // Children of node `id` (level l) at level l+1.
 std::vector<int32_t> node_children(const qrvie_geom* g, int32_t id) {
+    std::lock_guard<std::mutex> lock(lattice_mutex());
     auto& lat = lattices().at(g);
     const auto& nd = g->nodes[id];
     std::vector<int32_t> out;
@@ -339,7 +345,10 @@ qrvie_status qrvie_geom_create(qrvie_ctx* ctx, const qrvie_array_desc* d, qrvie_
     up((void**)&g->d_toff, toff.data(), sizeof(double) * toff.size(), "geom offsets");
     up((void**)&g->d_trep, trep.data(), sizeof(int32_t) * nt, "geom type representatives");
     if (st == QRVIE_OK) st = hip_check(ctx, hipStreamSynchronize(ctx->stream), "geom upload");
-    lattices()[g] = std::move(lat);
+    {
+        std::lock_guard<std::mutex> lock(lattice_mutex());
+        lattices()[g] = std::move(lat);
+    }
     if (st != QRVIE_OK) {
         qrvie_geom_destroy(g);
         return st;
@@ -385,7 +394,10 @@ void qrvie_geom_destroy(qrvie_geom* g) {
     dfree(ctx, g->d_tchi, sizeof(c128) * nt);
     dfree(ctx, g->d_toff, sizeof(double) * nt * kCells * 3);
     dfree(ctx, g->d_trep, sizeof(int32_t) * nt);
-    lattices().erase(g);
+    {
+        std::lock_guard<std::mutex> lock(lattice_mutex());
+        lattices().erase(g);
+    }
     delete g;
 }
 

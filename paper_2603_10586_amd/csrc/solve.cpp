@@ -528,6 +528,24 @@ qrvie_status qrvie_op_export_self(const qrvie_op* op, int32_t p, qrvie_c128* Zpp
     return hip_check(ctx, hipStreamSynchronize(ctx->stream), "export self");
 }
 
+qrvie_status qrvie_solve_footprint_estimate(const qrvie_geom* g, const qrvie_op* op, int32_t nrhs,
+                                            const qrvie_solve_opts* o, size_t* bytes) {
+    if (!g || !o || !bytes || nrhs < 1 || o->restart < 1 || o->max_iter < 1) return QRVIE_ERR_INVALID_ARG;
+    const int64_t n = g->ndof();
+    const int64_t m = std::min(o->restart, o->max_iter);
+    const int64_t na = std::min(nrhs, kGroup);
+    const int64_t nr = na > 1 ? round_nr((int)na) : 1;
+    const int64_t nch = krylov_nchunks(n), nblk = krylov_nblocks(n);
+    // per column: basis, six vectors, Hessenberg data, partials
+    const int64_t col = n * (m + 1) + 6 * n + (m + 1) * m + 4 * (m + 2) + nch * (m + 1) + nch + nblk;
+    // product workspace: rank-space block (sum of ranks <= 2 x 64 per block side when unknown) and level partials
+    const int64_t tlen = op ? op->t_len : (int64_t)g->blocks.size() * 64;
+    const int64_t nlev = op ? std::max(op->n_active, 1) : std::max(g->L, 1);
+    const int64_t prod = tlen * nr + nlev * n * nr + (na > 1 ? 2 * n * nr : 0);
+    *bytes = (size_t)((na * col + prod) * (int64_t)sizeof(c128)) + (size_t)(1 << 20);
+    return QRVIE_OK;
+}
+
 qrvie_status qrvie_solve(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const qrvie_c128* v, int64_t ldv,
                          qrvie_c128* x, int64_t ldx, const qrvie_solve_opts* o, qrvie_solve_info* info) {
     CHECK(check_vec_args(ctx, op, nrhs, v, ldv, x, ldx, "solve"));
