@@ -48,6 +48,7 @@ def cpu_model() -> str:
 
 
 KERNEL_SYMBOL = {"rphase": "k_rphase<4>", "qphase": "k_qphase<4>", "final": "k_final"}
+KERNEL_SYMBOL_C64 = {"rphase": "k_rphase_c64<4>", "qphase": "k_qphase_c64<4>", "final": "k_final"}
 COUNTERS = os.path.join(ROOT, "profiles", "product_mid32x32_counters.txt")
 PRODUCT_SOURCES = [os.path.join(ROOT, "paper_2603_10586_amd", "csrc", f) for f in ("k_apply.hip", "op.cpp")]
 
@@ -158,6 +159,8 @@ def main() -> int:
     ap.add_argument("--serving-rate", type=float, default=1.0, help="request arrival rate (1/s)")
     ap.add_argument("--serving-side", type=int, nargs=2, default=[8, 48], help="array side range")
     ap.add_argument("--serving-slots", type=int, default=3)
+    ap.add_argument("--mixed-ir", action="store_true",
+                    help="iterative refinement: complex64 far factors inside, complex128 residuals outside")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -187,7 +190,8 @@ def main() -> int:
     ctx = q.Context(0)
     t0 = time.perf_counter()
     geom = q.Geometry(ctx, arr)
-    op = q.Operator(ctx, geom, eps=args.eps)
+    op = q.Operator(ctx, geom, eps=args.eps, far_prec=q.PREC_C64 if args.mixed_ir else q.PREC_C128)
+    mode = q.SOLVE_MIXED_IR if args.mixed_ir else q.SOLVE_FP64
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     st = op.stats()
@@ -206,13 +210,13 @@ def main() -> int:
         return 0
 
     for _ in range(args.warmup):
-        op.solve(v, restart=args.restart, tol=args.tol, max_iter=args.max_iter)
+        op.solve(v, restart=args.restart, tol=args.tol, max_iter=args.max_iter, mode=mode)
     torch.cuda.synchronize()
     lat, infos = [], []
     t_start = time.perf_counter()
     for k in range(args.steps):
         t = time.perf_counter()
-        x, info, status = op.solve(v, restart=args.restart, tol=args.tol, max_iter=args.max_iter)
+        x, info, status = op.solve(v, restart=args.restart, tol=args.tol, max_iter=args.max_iter, mode=mode)
         lat.append(time.perf_counter() - t)
         infos.extend(info)
         print(f"[bench] step {k}: {lat[-1] * 1e3:.1f} ms, iterations {[i['iterations'] for i in info]}, "
@@ -223,24 +227,33 @@ def main() -> int:
 
     n_apply = sum(i["n_apply"] for i in infos)
     t_apply = sum(i["t_apply_s"] for i in infos)
-    value = prec_bytes * n_apply / t_apply / 1e9
+    if args.mixed_ir:
+        # outer residuals (complex128 factors): one per refinement plus the final check
+        n_hi = sum(i["n_refine"] + 1 for i in infos)
+        lo_bytes = st["apply_bytes_c64"] + st["n_self_types"] * 144 * 144 * 16
+        value = (prec_bytes * n_hi + lo_bytes * (n_apply - n_hi)) / t_apply / 1e9
+    else:
+        value = prec_bytes * n_apply / t_apply / 1e9
 
-    prof = op.profile_apply(reps=20)
+    prof = op.profile_apply(reps=20, prec=q.PREC_C64 if args.mixed_ir else q.PREC_C128)
     dom = max(("rphase", "qphase", "final"), key=lambda k: prof[k]["ms"])
     ach = prof[dom]["bytes"] / (prof[dom]["ms"] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
-                "algorithmic_bytes": prof[dom]["bytes"], "kernel": KERNEL_SYMBOL[dom],
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None if args.mixed_ir else measured_traffic(dom),
+                "algorithmic_bytes": prof[dom]["bytes"],
+                "kernel": KERNEL_SYMBOL_C64[dom] if args.mixed_ir else KERNEL_SYMBOL[dom],
                 "stages_ms": {k: round(prof[k]["ms"], 4) for k in prof},
                 "stages_gbs": {k: round(prof[k]["bytes"] / (prof[k]["ms"] * 1e-3) / 1e9, 1) for k in prof}}
     lat_ms = np.array(lat) * 1e3
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(total_s / args.steps * 1e3, 2), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 factors, f64 accumulation" if args.mixed_ir else "f64",
+        "data": "synthetic",
         "config": {"workload": f"{arr.name}: {arr.n_particles} disks, {n} unknowns, eps {args.eps:g}, "
                                + (f"GMRES({args.restart})" if args.restart < args.max_iter else "unrestarted GMRES")
-                               + f" to {args.tol:g}, one TM plane wave at 10 deg",
+                               + f" to {args.tol:g}, one TM plane wave at 10 deg"
+                               + (", mixed-precision refinement (complex64 inner)" if args.mixed_ir else ""),
                    "particles": arr.n_particles, "unknowns": n, "eps": args.eps, "restart": args.restart,
                    "tol": args.tol},
         "solves_per_s": round(args.steps * args.nrhs / total_s, 3),
@@ -248,7 +261,7 @@ def main() -> int:
         "latency_ms_p50": round(float(np.percentile(lat_ms, 50)), 2),
         "latency_ms_p99": round(float(np.percentile(lat_ms, 99)), 2),
         "iterations": infos[-1]["iterations"], "rel_res_true": infos[-1]["rel_res_true"],
-        "reorthogonalised_steps": infos[-1]["n_reorth"],
+        "reorthogonalised_steps": infos[-1]["n_reorth"], "refinements": infos[-1]["n_refine"],
         "solve_split_s": {"products": round(infos[-1]["t_apply_s"], 3),
                           "krylov_and_host": round(lat[-1] - infos[-1]["t_apply_s"], 3)},
         "setup_s": round(setup_s, 2), "gain": round(st["gain"], 3), "product_bytes": st["apply_bytes"],

@@ -128,7 +128,9 @@ enum { QRVIE_PREC_C128 = 0, QRVIE_PREC_C64 = 1, QRVIE_PREC_BF16X2 = 2 };
 /*
  *   eps              per-block relative Frobenius tolerance of the low-rank
  *                    factors, ||B - Q R||_F <= eps ||B||_F (§5.2, eq. 5.3); > 0
- *   far_prec         storage of the far factors: QRVIE_PREC_C128 only for now
+ *   far_prec         QRVIE_PREC_C128: complex128 far factors; QRVIE_PREC_C64: in addition a
+ *                    complex64 copy (rounded to nearest) used by the inner solves of
+ *                    QRVIE_SOLVE_MIXED_IR, which streams half the factor bytes
  *   near_prec        storage of the self blocks: QRVIE_PREC_C128 only for now
  *   max_block_rows   far blocks with more rows are split into their child
  *                    pairs (always far); 0 = no cap (the paper's scheme)
@@ -160,6 +162,7 @@ typedef struct {
     int64_t apply_bytes;                      /* algorithmic HBM bytes of one single-RHS product */
     int64_t device_bytes;                     /* device memory held by the operator */
     double  t_assembly_s, t_compression_s, t_precond_setup_s;
+    int64_t apply_bytes_c64;                  /* the same product with complex64 far factors (0: none) */
 } qrvie_op_stats;
 
 typedef struct {
@@ -196,6 +199,11 @@ void         qrvie_op_destroy(qrvie_op* op);
  * product Z_D x + sum_b Q_b (R_b x_J) of §5.2. */
 qrvie_status qrvie_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs,
                          const qrvie_c128* x, int64_t ldx, qrvie_c128* y, int64_t ldy);
+/* The same product with the far factors of precision prec: QRVIE_PREC_C128 (as qrvie_apply)
+ * or QRVIE_PREC_C64 (the complex64 copy; products accumulate in FP64).  An operator built
+ * without a copy of that precision gives QRVIE_ERR_INVALID_ARG. */
+qrvie_status qrvie_apply_prec(qrvie_ctx* ctx, const qrvie_op* op, int32_t prec, int32_t nrhs,
+                              const qrvie_c128* x, int64_t ldx, qrvie_c128* y, int64_t ldy);
 /*
  * Stage timers of the single-RHS product (the product stage of the paper's timing
  * table, §6.5), measured with HIP events on the context stream over `reps` products
@@ -204,8 +212,11 @@ qrvie_status qrvie_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs,
  * ms[3] whole product; averages per product.  bytes[0..3]: algorithmic HBM bytes of
  * the same stages per product (factor, self-block and vector traffic; the per-level
  * partial vectors are counted as overhead, not algorithmic bytes).  Host arrays of 4.
+ * prec selects the far factors as in qrvie_apply_prec (complex64 factors count 8 bytes
+ * per entry).
  */
-qrvie_status qrvie_op_profile_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t reps, double* ms, int64_t* bytes);
+qrvie_status qrvie_op_profile_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t prec, int32_t reps, double* ms,
+                                    int64_t* bytes);
 /* z = Z_D^-1 y, the block-diagonal left preconditioner (§4, eq. 4.2). */
 qrvie_status qrvie_precondition(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs,
                                 const qrvie_c128* y, int64_t ldy, qrvie_c128* z, int64_t ldz);
@@ -220,13 +231,21 @@ qrvie_status qrvie_rhs_plane_waves(qrvie_ctx* ctx, const qrvie_geom* g, int32_t 
                                    const int32_t* pol, qrvie_c128* v, int64_t ldv);
 
 /* ------------------------------------------------------------------- solve */
-enum { QRVIE_SOLVE_FP64 = 0 };
+/*
+ * QRVIE_SOLVE_FP64      GMRES on the complex128 factors.
+ * QRVIE_SOLVE_MIXED_IR  iterative refinement: residuals r = v - Z_QR x with the complex128
+ *                       factors, corrections from GMRES on the complex64 copy of the far
+ *                       factors (FP64 accumulation and Krylov algebra), x += d, until
+ *                       ||r|| <= tol ||v||.  Needs an operator built with
+ *                       far_prec = QRVIE_PREC_C64; otherwise QRVIE_ERR_INVALID_ARG.
+ */
+enum { QRVIE_SOLVE_FP64 = 0, QRVIE_SOLVE_MIXED_IR = 1 };
 
 typedef struct {
     int32_t restart;      /* GMRES(m) restart length, 1..16384 (m >= max_iter: unrestarted, as in §6);
                              the basis takes (m + 1) x n complex128 of device memory */
     int32_t max_iter;     /* total Arnoldi steps per right-hand side */
-    int32_t mode;         /* QRVIE_SOLVE_FP64 */
+    int32_t mode;         /* QRVIE_SOLVE_FP64 or QRVIE_SOLVE_MIXED_IR */
     double  tol;          /* relative residual; converged when both the preconditioned
                              estimate and the true residual ||v - Z_QR x||/||v|| meet it */
     int32_t use_x0;       /* 1: x holds the initial guess on entry; 0: x0 = 0 */
@@ -238,6 +257,8 @@ typedef struct {
     int32_t n_apply, n_prec;
     double  t_apply_s, t_prec_s, t_krylov_s, t_total_s;
     int32_t n_reorth;     /* Arnoldi steps that needed the second Gram-Schmidt pass */
+    int32_t n_refine;     /* MIXED_IR: correction solves (iterations and n_apply count all of
+                             them; rel_res_prec is the last correction's own estimate) */
 } qrvie_solve_info;
 
 /* Upper bound of the device bytes qrvie_solve allocates for nrhs right-hand sides

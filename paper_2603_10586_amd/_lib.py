@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(HERE, "libqrvie.so")
 MAX_LEVELS = 24
 OK, ERR_INVALID_ARG, ERR_GEOMETRY, ERR_OUT_OF_MEMORY, ERR_DEVICE, NOT_CONVERGED, ERR_QUEUE_FULL = range(7)
 PREC_C128, PREC_C64, PREC_BF16X2 = 0, 1, 2
-SOLVE_FP64 = 0
+SOLVE_FP64, SOLVE_MIXED_IR = 0, 1
 
 
 class C128(C.Structure):
@@ -35,7 +35,8 @@ class OpStats(C.Structure):
                 ("mean_rank_level", C.c_double * MAX_LEVELS), ("n_self_types", C.c_int32),
                 ("n_qr_entries", C.c_int64), ("gain", C.c_double), ("max_block_rel_err", C.c_double),
                 ("apply_bytes", C.c_int64), ("device_bytes", C.c_int64), ("t_assembly_s", C.c_double),
-                ("t_compression_s", C.c_double), ("t_precond_setup_s", C.c_double)]
+                ("t_compression_s", C.c_double), ("t_precond_setup_s", C.c_double),
+                ("apply_bytes_c64", C.c_int64)]
 
 
 class BlockInfo(C.Structure):
@@ -53,7 +54,8 @@ class SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("restarts", C.c_int32), ("converged", C.c_int32),
                 ("rel_res_prec", C.c_double), ("rel_res_true", C.c_double), ("n_apply", C.c_int32),
                 ("n_prec", C.c_int32), ("t_apply_s", C.c_double), ("t_prec_s", C.c_double),
-                ("t_krylov_s", C.c_double), ("t_total_s", C.c_double), ("n_reorth", C.c_int32)]
+                ("t_krylov_s", C.c_double), ("t_total_s", C.c_double), ("n_reorth", C.c_int32),
+                ("n_refine", C.c_int32)]
 
 
 P = C.c_void_p
@@ -83,7 +85,8 @@ SIGNATURES = {
     "qrvie_op_export_self": (ST, [P, I32, P, P]),
     "qrvie_op_destroy": (None, [P]),
     "qrvie_apply": (ST, [P, P, I32, P, I64, P, I64]),
-    "qrvie_op_profile_apply": (ST, [P, P, I32, C.POINTER(C.c_double), C.POINTER(I64)]),
+    "qrvie_apply_prec": (ST, [P, P, I32, I32, P, I64, P, I64]),
+    "qrvie_op_profile_apply": (ST, [P, P, I32, I32, C.POINTER(C.c_double), C.POINTER(I64)]),
     "qrvie_precondition": (ST, [P, P, I32, P, I64, P, I64]),
     "qrvie_rhs_plane_waves": (ST, [P, P, I32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(I32), P, I64]),
     "qrvie_solve": (ST, [P, P, I32, P, I64, P, I64, C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),

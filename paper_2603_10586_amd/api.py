@@ -160,9 +160,10 @@ def rhs_plane_waves(ctx: Context, geom: Geometry, theta_deg, phi_deg, pol):
 class Operator:
     """The compressed interaction operator Z_QR with its block-diagonal preconditioner."""
 
-    def __init__(self, ctx: Context, geom: Geometry, eps: float = 1e-6, max_block_rows: int = 0, seed: int = 0):
+    def __init__(self, ctx: Context, geom: Geometry, eps: float = 1e-6, max_block_rows: int = 0, seed: int = 0,
+                 far_prec: int = L.PREC_C128):
         self.ctx, self.geom = ctx, geom
-        o = L.CompressOpts(eps=eps, far_prec=L.PREC_C128, near_prec=L.PREC_C128, max_block_rows=max_block_rows,
+        o = L.CompressOpts(eps=eps, far_prec=far_prec, near_prec=L.PREC_C128, max_block_rows=max_block_rows,
                            share_transpose=0, seed=seed)
         self.opts = o
         h = C.c_void_p()
@@ -178,8 +179,9 @@ class Operator:
         return int(out.value)
 
     @staticmethod
-    def solve_footprint_estimate(geom: Geometry, nrhs: int, restart: int, max_iter: int, op=None) -> int:
-        o = L.SolveOpts(restart=restart, max_iter=max_iter, mode=L.SOLVE_FP64, tol=1e-6, use_x0=0)
+    def solve_footprint_estimate(geom: Geometry, nrhs: int, restart: int, max_iter: int, op=None,
+                                 mode: int = L.SOLVE_FP64) -> int:
+        o = L.SolveOpts(restart=restart, max_iter=max_iter, mode=mode, tol=1e-6, use_x0=0)
         out = C.c_size_t()
         st = geom.ctx.lib.qrvie_solve_footprint_estimate(geom.h, op.h if op is not None else None, nrhs,
                                                          C.byref(o), C.byref(out))
@@ -194,7 +196,7 @@ class Operator:
                     min_rank_level=list(s.min_rank_level[:nl]), max_rank_level=list(s.max_rank_level[:nl]),
                     mean_rank_level=list(s.mean_rank_level[:nl]), n_self_types=s.n_self_types,
                     n_qr_entries=s.n_qr_entries, gain=s.gain, max_block_rel_err=s.max_block_rel_err,
-                    apply_bytes=s.apply_bytes, device_bytes=s.device_bytes,
+                    apply_bytes=s.apply_bytes, apply_bytes_c64=s.apply_bytes_c64, device_bytes=s.device_bytes,
                     t_compression_s=s.t_compression_s, t_precond_setup_s=s.t_precond_setup_s)
 
     def num_blocks(self) -> int:
@@ -221,20 +223,24 @@ class Operator:
                                                          C.c_void_p(Zi.ctypes.data)), "export_self")
         return Z.reshape(144, 144).T, Zi.reshape(144, 144).T
 
-    def apply(self, x):
+    def apply(self, x, prec: int = L.PREC_C128):
         torch = _torch()
         px, ld, nrhs = _cols(x, self.geom.ndof)
         y = torch.empty_like(x)
         self.ctx.order()
-        self.ctx.check(self.ctx.lib.qrvie_apply(self.ctx.h, self.h, nrhs, px, ld, C.c_void_p(y.data_ptr()), ld), "apply")
+        if prec == L.PREC_C128:
+            st = self.ctx.lib.qrvie_apply(self.ctx.h, self.h, nrhs, px, ld, C.c_void_p(y.data_ptr()), ld)
+        else:
+            st = self.ctx.lib.qrvie_apply_prec(self.ctx.h, self.h, prec, nrhs, px, ld, C.c_void_p(y.data_ptr()), ld)
+        self.ctx.check(st, "apply")
         return y
 
-    def profile_apply(self, reps: int = 10) -> dict:
+    def profile_apply(self, reps: int = 10, prec: int = L.PREC_C128) -> dict:
         """Per-stage device time (ms) and algorithmic bytes of one single-RHS product."""
         ms = (C.c_double * 4)()
         by = (C.c_int64 * 4)()
         self.ctx.order()
-        self.ctx.check(self.ctx.lib.qrvie_op_profile_apply(self.ctx.h, self.h, reps, ms, by), "profile")
+        self.ctx.check(self.ctx.lib.qrvie_op_profile_apply(self.ctx.h, self.h, prec, reps, ms, by), "profile")
         names = ("rphase", "qphase", "final", "product")
         return {k: dict(ms=ms[i], bytes=by[i]) for i, k in enumerate(names)}
 
@@ -247,11 +253,12 @@ class Operator:
                        "precondition")
         return z
 
-    def solve(self, v, restart: int = 30, tol: float = 1e-8, max_iter: int = 10000, x0=None):
+    def solve(self, v, restart: int = 30, tol: float = 1e-8, max_iter: int = 10000, x0=None,
+              mode: int = L.SOLVE_FP64):
         torch = _torch()
         pv, ld, nrhs = _cols(v, self.geom.ndof)
         x = torch.zeros_like(v) if x0 is None else x0.clone()
-        o = L.SolveOpts(restart=restart, max_iter=max_iter, mode=L.SOLVE_FP64, tol=tol, use_x0=0 if x0 is None else 1)
+        o = L.SolveOpts(restart=restart, max_iter=max_iter, mode=mode, tol=tol, use_x0=0 if x0 is None else 1)
         infos = (L.SolveInfo * nrhs)()
         self.ctx.order()
         st = self.ctx.check(self.ctx.lib.qrvie_solve(self.ctx.h, self.h, nrhs, pv, ld, C.c_void_p(x.data_ptr()), ld,

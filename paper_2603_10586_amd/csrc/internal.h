@@ -141,6 +141,7 @@ struct qrvie_op {
     qrvie::c128* d_self = nullptr;            // ntypes x 144 x 144 (column-major)
     qrvie::c128* d_pinv = nullptr;            // inverses
     qrvie::c128* d_fac = nullptr;             // all panels
+    float2* d_fac32 = nullptr;                // complex64 copy of the panels (far_prec = C64), same offsets
     int64_t fac_elems = 0;
     int64_t t_len = 0;                        // length of the rank-space vector (per-call workspace)
     int64_t* d_tmap = nullptr;                // stacked R row -> t index
@@ -210,6 +211,15 @@ void launch_rphase_m(hipStream_t s, int nr, const RStrip* st, int64_t n, const c
 void launch_qphase_m(hipStream_t s, int nr, const QStrip* st, int64_t n, const c128* fac, const c128* T, c128* Y);
 void launch_final_m(hipStream_t s, int nr, int32_t N, const int32_t* ptype, const c128* self, const c128* pinv,
                     const c128* X, const c128* ylev, int nlev, int64_t n, const c128* V, c128* out_r, c128* out_z);
+// complex64 factor panels (the reduced-precision operator), FP64 accumulation
+void launch_to_c64(hipStream_t s, const c128* in, float2* out, int64_t n);
+void launch_rphase_c64(hipStream_t s, const RStrip* st, int64_t n, const float2* fac, const c128* x, c128* t,
+                       const int64_t* tmap);
+void launch_qphase_c64(hipStream_t s, const QStrip* st, int64_t n, const float2* fac, const c128* t, c128* y);
+void launch_rphase_m_c64(hipStream_t s, int nr, const RStrip* st, int64_t n, const float2* fac, const c128* X,
+                         c128* T, const int64_t* tmap);
+void launch_qphase_m_c64(hipStream_t s, int nr, const QStrip* st, int64_t n, const float2* fac, const c128* T,
+                         c128* Y);
 void launch_interleave(hipStream_t s, int nr, int64_t n, const c128* const* cols, c128* blk, int ncols);
 void launch_deinterleave(hipStream_t s, int nr, int64_t n, const c128* blk, c128* const* cols, int ncols);
 
@@ -230,5 +240,6 @@ void launch_givens(hipStream_t s, int j, c128* hcol, c128* H, int ldh, double* c
                    const double* hnorm2, double* status);
 void launch_trisolve(hipStream_t s, int k, const c128* H, int ldh, const c128* gvec, c128* y);
 void launch_gemv_add(hipStream_t s, const c128* V, int64_t ldv, int ncols, const c128* y, c128* x, int64_t n);
+void launch_add(hipStream_t s, const c128* d, int64_t n, c128* x);
 
 }  // namespace qrvie

@@ -26,42 +26,54 @@ __device__ __forceinline__ void cfma(c128& acc, c128 a, c128 b) {
 }
 
 typedef double v2d __attribute__((ext_vector_type(2)));
+typedef float v2f __attribute__((ext_vector_type(2)));
 
-// Streaming 16-byte load: the factors are read once per product, so keep them out of the caches.
+// Streaming loads: the factors are read once per product, so keep them out of the caches.
+// Complex64 factors (the reduced-precision panels) are widened to FP64 on load; the
+// accumulation is FP64 either way.
 __device__ __forceinline__ c128 load_stream(const c128* p) {
     const v2d v = __builtin_nontemporal_load(reinterpret_cast<const v2d*>(p));
     return make_double2(v.x, v.y);
 }
+__device__ __forceinline__ c128 load_stream(const float2* p) {
+    const v2f v = __builtin_nontemporal_load(reinterpret_cast<const v2f*>(p));
+    return make_double2((double)v.x, (double)v.y);
+}
+__device__ __forceinline__ c128 load_plain(const c128* p) { return *p; }
+__device__ __forceinline__ c128 load_plain(const float2* p) { return make_double2((double)p->x, (double)p->y); }
+
+// Columns loaded per batch: the same bytes in flight for 16- and 8-byte entries.
+template <typename F> struct Unroll { static constexpr int U = sizeof(F) == 16 ? 8 : 16; };
 
 // acc += sum_{j in [j0, j1)} A[j*ld] * v[j]   (A already offset to this lane's row)
-__device__ __forceinline__ c128 column_stream(const c128* __restrict__ A, int64_t ld, const c128* __restrict__ v,
+template <typename F>
+__device__ __forceinline__ c128 column_stream(const F* __restrict__ A, int64_t ld, const c128* __restrict__ v,
                                               int j0, int j1) {
+    constexpr int U = Unroll<F>::U;
     c128 acc0 = make_double2(0.0, 0.0), acc1 = acc0;
     int j = j0;
-    for (; j + 8 <= j1; j += 8) {
-        c128 a[8];
+    for (; j + U <= j1; j += U) {
+        c128 a[U];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) a[u] = load_stream(A + (int64_t)(j + u) * ld);
+        for (int u = 0; u < U; ++u) a[u] = load_stream(A + (int64_t)(j + u) * ld);
 #pragma unroll
-        for (int u = 0; u < 8; u += 2) {
+        for (int u = 0; u < U; u += 2) {
             cfma(acc0, a[u], v[j + u]);
             cfma(acc1, a[u + 1], v[j + u + 1]);
         }
     }
-    for (; j < j1; ++j) cfma(acc0, A[(int64_t)j * ld], v[j]);
+    for (; j < j1; ++j) cfma(acc0, load_plain(A + (int64_t)j * ld), v[j]);
     return make_double2(acc0.x + acc1.x, acc0.y + acc1.y);
 }
 
-template <int WAVES>
-__global__ void __launch_bounds__(64 * WAVES) k_rphase(const RStrip* __restrict__ strips, const c128* __restrict__ fac,
-                                                       const c128* __restrict__ x, c128* __restrict__ t,
-                                                       const int64_t* __restrict__ tmap) {
-    const RStrip s = strips[blockIdx.x];
+template <typename F, int WAVES>
+__device__ __forceinline__ void rphase_body(const RStrip& s, const F* __restrict__ fac, const c128* __restrict__ x,
+                                            c128* __restrict__ t, const int64_t* __restrict__ tmap) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int row = min(lane, s.nrows - 1);
     const int per = (s.ncols + WAVES - 1) / WAVES;
     const int j0 = min(s.ncols, wv * per), j1 = min(s.ncols, j0 + per);
-    const c128 acc = column_stream(fac + s.a_off + row, s.ld, x + s.x_off, j0, j1);
+    const c128 acc = column_stream<F>(fac + s.a_off + row, s.ld, x + s.x_off, j0, j1);
     if (WAVES == 1) {
         if (lane < s.nrows) t[tmap[s.tmap_off + lane]] = acc;
         return;
@@ -77,15 +89,14 @@ __global__ void __launch_bounds__(64 * WAVES) k_rphase(const RStrip* __restrict_
     }
 }
 
-template <int WAVES>
-__global__ void __launch_bounds__(64 * WAVES) k_qphase(const QStrip* __restrict__ strips, const c128* __restrict__ fac,
-                                                       const c128* __restrict__ t, c128* __restrict__ y) {
-    const QStrip s = strips[blockIdx.x];
+template <typename F, int WAVES>
+__device__ __forceinline__ void qphase_body(const QStrip& s, const F* __restrict__ fac, const c128* __restrict__ t,
+                                            c128* __restrict__ y) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int row = min(lane, max(s.nrows - 1, 0));
     const int per = (s.ncols + WAVES - 1) / WAVES;
     const int j0 = min(s.ncols, wv * per), j1 = min(s.ncols, j0 + per);
-    const c128 acc = column_stream(fac + s.a_off + row, s.ld, t + s.t_off, j0, j1);
+    const c128 acc = column_stream<F>(fac + s.a_off + row, s.ld, t + s.t_off, j0, j1);
     if (WAVES == 1) {
         if (lane < s.nrows) y[s.y_off + lane] = acc;
         return;
@@ -99,6 +110,30 @@ __global__ void __launch_bounds__(64 * WAVES) k_qphase(const QStrip* __restrict_
         for (int w = 1; w < WAVES; ++w) sum = make_double2(sum.x + red[w][lane].x, sum.y + red[w][lane].y);
         y[s.y_off + lane] = sum;
     }
+}
+
+template <int WAVES>
+__global__ void __launch_bounds__(64 * WAVES) k_rphase(const RStrip* __restrict__ strips, const c128* __restrict__ fac,
+                                                       const c128* __restrict__ x, c128* __restrict__ t,
+                                                       const int64_t* __restrict__ tmap) {
+    rphase_body<c128, WAVES>(strips[blockIdx.x], fac, x, t, tmap);
+}
+template <int WAVES>
+__global__ void __launch_bounds__(64 * WAVES) k_rphase_c64(const RStrip* __restrict__ strips,
+                                                           const float2* __restrict__ fac, const c128* __restrict__ x,
+                                                           c128* __restrict__ t, const int64_t* __restrict__ tmap) {
+    rphase_body<float2, WAVES>(strips[blockIdx.x], fac, x, t, tmap);
+}
+template <int WAVES>
+__global__ void __launch_bounds__(64 * WAVES) k_qphase(const QStrip* __restrict__ strips, const c128* __restrict__ fac,
+                                                       const c128* __restrict__ t, c128* __restrict__ y) {
+    qphase_body<c128, WAVES>(strips[blockIdx.x], fac, t, y);
+}
+template <int WAVES>
+__global__ void __launch_bounds__(64 * WAVES) k_qphase_c64(const QStrip* __restrict__ strips,
+                                                           const float2* __restrict__ fac, const c128* __restrict__ t,
+                                                           c128* __restrict__ y) {
+    qphase_body<float2, WAVES>(strips[blockIdx.x], fac, t, y);
 }
 
 // 576 threads per particle: thread -> (row = tid % 144, column group = tid / 144).
@@ -183,8 +218,8 @@ __global__ void __launch_bounds__(kNp * kGroups) k_block_apply(const int32_t* __
 // NR entries a lane needs for one column are one contiguous wave-uniform row.  Each
 // factor element is loaded once and applied to all NR vectors: the streaming pattern and
 // the HBM bytes of the factors are those of the single-RHS product.
-template <int NR>
-__device__ __forceinline__ void column_stream_m(const c128* __restrict__ A, int64_t ld, const c128* __restrict__ v,
+template <typename F, int NR>
+__device__ __forceinline__ void column_stream_m(const F* __restrict__ A, int64_t ld, const c128* __restrict__ v,
                                                 int j0, int j1, c128 acc[NR]) {
     int j = j0;
     for (; j + 4 <= j1; j += 4) {
@@ -197,17 +232,15 @@ __device__ __forceinline__ void column_stream_m(const c128* __restrict__ A, int6
             for (int r = 0; r < NR; ++r) cfma(acc[r], a[u], v[(int64_t)(j + u) * NR + r]);
     }
     for (; j < j1; ++j) {
-        const c128 a = A[(int64_t)j * ld];
+        const c128 a = load_plain(A + (int64_t)j * ld);
 #pragma unroll
         for (int r = 0; r < NR; ++r) cfma(acc[r], a, v[(int64_t)j * NR + r]);
     }
 }
 
-template <int NR>
-__global__ void __launch_bounds__(256) k_rphase_m(const RStrip* __restrict__ strips, const c128* __restrict__ fac,
-                                                  const c128* __restrict__ X, c128* __restrict__ T,
-                                                  const int64_t* __restrict__ tmap) {
-    const RStrip s = strips[blockIdx.x];
+template <typename F, int NR>
+__device__ __forceinline__ void rphase_m_body(const RStrip& s, const F* __restrict__ fac, const c128* __restrict__ X,
+                                              c128* __restrict__ T, const int64_t* __restrict__ tmap) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int row = min(lane, s.nrows - 1);
     const int per = (s.ncols + 3) / 4;
@@ -215,7 +248,7 @@ __global__ void __launch_bounds__(256) k_rphase_m(const RStrip* __restrict__ str
     c128 acc[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[r] = make_double2(0.0, 0.0);
-    column_stream_m<NR>(fac + s.a_off + row, s.ld, X + (int64_t)s.x_off * NR, j0, j1, acc);
+    column_stream_m<F, NR>(fac + s.a_off + row, s.ld, X + (int64_t)s.x_off * NR, j0, j1, acc);
     __shared__ c128 red[4][64 * NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) red[wv][lane * NR + r] = acc[r];
@@ -232,9 +265,21 @@ __global__ void __launch_bounds__(256) k_rphase_m(const RStrip* __restrict__ str
 }
 
 template <int NR>
-__global__ void __launch_bounds__(256) k_qphase_m(const QStrip* __restrict__ strips, const c128* __restrict__ fac,
-                                                  const c128* __restrict__ T, c128* __restrict__ Y) {
-    const QStrip s = strips[blockIdx.x];
+__global__ void __launch_bounds__(256) k_rphase_m(const RStrip* __restrict__ strips, const c128* __restrict__ fac,
+                                                  const c128* __restrict__ X, c128* __restrict__ T,
+                                                  const int64_t* __restrict__ tmap) {
+    rphase_m_body<c128, NR>(strips[blockIdx.x], fac, X, T, tmap);
+}
+template <int NR>
+__global__ void __launch_bounds__(256) k_rphase_m_c64(const RStrip* __restrict__ strips, const float2* __restrict__ fac,
+                                                      const c128* __restrict__ X, c128* __restrict__ T,
+                                                      const int64_t* __restrict__ tmap) {
+    rphase_m_body<float2, NR>(strips[blockIdx.x], fac, X, T, tmap);
+}
+
+template <typename F, int NR>
+__device__ __forceinline__ void qphase_m_body(const QStrip& s, const F* __restrict__ fac, const c128* __restrict__ T,
+                                              c128* __restrict__ Y) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int row = min(lane, max(s.nrows - 1, 0));
     const int per = (s.ncols + 3) / 4;
@@ -242,7 +287,7 @@ __global__ void __launch_bounds__(256) k_qphase_m(const QStrip* __restrict__ str
     c128 acc[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[r] = make_double2(0.0, 0.0);
-    column_stream_m<NR>(fac + s.a_off + row, s.ld, T + s.t_off * NR, j0, j1, acc);
+    column_stream_m<F, NR>(fac + s.a_off + row, s.ld, T + s.t_off * NR, j0, j1, acc);
     __shared__ c128 red[4][64 * NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) red[wv][lane * NR + r] = acc[r];
@@ -256,6 +301,17 @@ __global__ void __launch_bounds__(256) k_qphase_m(const QStrip* __restrict__ str
             Y[(s.y_off + l) * NR + r] = sum;
         }
     }
+}
+
+template <int NR>
+__global__ void __launch_bounds__(256) k_qphase_m(const QStrip* __restrict__ strips, const c128* __restrict__ fac,
+                                                  const c128* __restrict__ T, c128* __restrict__ Y) {
+    qphase_m_body<c128, NR>(strips[blockIdx.x], fac, T, Y);
+}
+template <int NR>
+__global__ void __launch_bounds__(256) k_qphase_m_c64(const QStrip* __restrict__ strips, const float2* __restrict__ fac,
+                                                      const c128* __restrict__ T, c128* __restrict__ Y) {
+    qphase_m_body<float2, NR>(strips[blockIdx.x], fac, T, Y);
 }
 
 // Per particle: Y = Z_pp X + sum_l Y_l for NR interleaved vectors; optionally R = V - Y and
@@ -337,6 +393,46 @@ __global__ void k_deinterleave(int64_t n, const c128* __restrict__ blk, c128* co
 }
 
 }  // namespace
+
+// Round the complex128 panels to complex64 (round to nearest even).
+// Grid-stride, so any panel size fits one launch.
+__global__ void k_to_c64(const c128* __restrict__ in, float2* __restrict__ out, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride)
+        out[e] = make_float2((float)in[e].x, (float)in[e].y);
+}
+
+void launch_to_c64(hipStream_t s, const c128* in, float2* out, int64_t n) {
+    if (n <= 0) return;
+    const int64_t want = (n + 255) / 256, blocks = want < (1 << 20) ? want : (1 << 20);
+    hipLaunchKernelGGL(k_to_c64, dim3((unsigned)blocks), dim3(256), 0, s, in, out, n);
+}
+void launch_rphase_c64(hipStream_t s, const RStrip* st, int64_t n, const float2* fac, const c128* x, c128* t,
+                       const int64_t* tmap) {
+    if (n > 0) hipLaunchKernelGGL(k_rphase_c64<4>, dim3((unsigned)n), dim3(256), 0, s, st, fac, x, t, tmap);
+}
+void launch_qphase_c64(hipStream_t s, const QStrip* st, int64_t n, const float2* fac, const c128* t, c128* y) {
+    if (n > 0) hipLaunchKernelGGL(k_qphase_c64<4>, dim3((unsigned)n), dim3(256), 0, s, st, fac, t, y);
+}
+void launch_rphase_m_c64(hipStream_t s, int nr, const RStrip* st, int64_t n, const float2* fac, const c128* X, c128* T,
+                         const int64_t* tmap) {
+    if (n <= 0) return;
+    dim3 g((unsigned)n);
+    switch (nr) {
+        case 2: hipLaunchKernelGGL(k_rphase_m_c64<2>, g, dim3(256), 0, s, st, fac, X, T, tmap); break;
+        case 4: hipLaunchKernelGGL(k_rphase_m_c64<4>, g, dim3(256), 0, s, st, fac, X, T, tmap); break;
+        default: hipLaunchKernelGGL(k_rphase_m_c64<8>, g, dim3(256), 0, s, st, fac, X, T, tmap); break;
+    }
+}
+void launch_qphase_m_c64(hipStream_t s, int nr, const QStrip* st, int64_t n, const float2* fac, const c128* T, c128* Y) {
+    if (n <= 0) return;
+    dim3 g((unsigned)n);
+    switch (nr) {
+        case 2: hipLaunchKernelGGL(k_qphase_m_c64<2>, g, dim3(256), 0, s, st, fac, T, Y); break;
+        case 4: hipLaunchKernelGGL(k_qphase_m_c64<4>, g, dim3(256), 0, s, st, fac, T, Y); break;
+        default: hipLaunchKernelGGL(k_qphase_m_c64<8>, g, dim3(256), 0, s, st, fac, T, Y); break;
+    }
+}
 
 void launch_rphase_m(hipStream_t s, int nr, const RStrip* st, int64_t n, const c128* fac, const c128* X, c128* T,
                      const int64_t* tmap) {

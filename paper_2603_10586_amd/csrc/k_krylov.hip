@@ -184,6 +184,13 @@ __global__ void k_scale_into(const c128* __restrict__ w, int64_t n, const double
     out[e] = make_double2(w[e].x * inv, w[e].y * inv);
 }
 
+// x += d (the update of an iterative-refinement step)
+__global__ void k_add(const c128* __restrict__ d, int64_t n, c128* __restrict__ x) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    x[e] = make_double2(x[e].x + d[e].x, x[e].y + d[e].y);
+}
+
 // Column j of the Hessenberg matrix: hcol[0..j] from Gram-Schmidt, h_{j+1,j} = sqrt(hnorm2).
 // Apply the previous rotations, build rotation j so that [[c, s], [-conj(s), c]] zeroes
 // h_{j+1,j} (c real), and rotate the right-hand side g.  status = {|g_{j+1}|, h_{j+1,j}}.
@@ -311,6 +318,9 @@ void launch_reorth_gate(hipStream_t s, const double* an2, const double* wn2, int
 }
 void launch_scale_into(hipStream_t s, const c128* w, int64_t n, const double* norm2, c128* out, c128* gslot) {
     hipLaunchKernelGGL(k_scale_into, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w, n, norm2, out, gslot);
+}
+void launch_add(hipStream_t s, const c128* d, int64_t n, c128* x) {
+    hipLaunchKernelGGL(k_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d, n, x);
 }
 void launch_givens(hipStream_t s, int j, c128* hcol, c128* H, int ldh, double* cs, c128* sn, c128* g,
                    const double* hnorm2, double* status) {

@@ -441,7 +441,8 @@ qrvie_status qrvie_op_footprint_estimate(const qrvie_geom* g, const qrvie_compre
     }
     const double self = 2.0 * g->types.size() * kNp * kNp;
     const double vec = 8.0 * (double)g->ndof();
-    *bytes = (size_t)((elems * 1.5 + self + vec) * sizeof(c128));
+    const double copy32 = o->far_prec == QRVIE_PREC_C64 ? 0.5 : 0.0;   // complex64 copy, half the bytes
+    *bytes = (size_t)((elems * (1.5 + copy32) + self + vec) * sizeof(c128));
     return QRVIE_OK;
 }
 
@@ -449,7 +450,8 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
     if (!ctx || !g || !o || !out) return QRVIE_ERR_INVALID_ARG;
     *out = nullptr;
     if (!(o->eps > 0.0) || !(o->eps < 1.0)) { set_err(ctx, "op_create: eps must be in (0, 1)"); return QRVIE_ERR_INVALID_ARG; }
-    if (o->far_prec != QRVIE_PREC_C128 || o->near_prec != QRVIE_PREC_C128 || o->share_transpose != 0 ||
+    if ((o->far_prec != QRVIE_PREC_C128 && o->far_prec != QRVIE_PREC_C64) || o->near_prec != QRVIE_PREC_C128 ||
+        o->share_transpose != 0 ||
         o->max_block_rows < 0) {
         set_err(ctx, "op_create: unsupported precision or option");
         return QRVIE_ERR_INVALID_ARG;
@@ -726,6 +728,14 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
         bld.segments.clear();
         if (st != QRVIE_OK) return fail(st);
     }
+    if (o->far_prec == QRVIE_PREC_C64) {
+        // complex64 copy of the far factors for the reduced-precision inner products
+        keep((void**)&op->d_fac32, sizeof(float2) * (size_t)std::max<int64_t>(op->fac_elems, 1), "complex64 panels");
+        if (st != QRVIE_OK) return fail(st);
+        launch_to_c64(s, op->d_fac, op->d_fac32, op->fac_elems);
+        st = hip_check(ctx, hipStreamSynchronize(s), "complex64 panels");
+        if (st != QRVIE_OK) return fail(st);
+    }
     const double t3 = now_s();
     op->stats.t_compression_s += t3 - t2;
 
@@ -757,6 +767,9 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
     S.max_block_rel_err = maxerr;
     S.apply_bytes = (int64_t)sizeof(c128) * ((nqr - (int64_t)g->N * kNp * kNp) + (int64_t)op->ntypes * kNp * kNp +
                                              2 * n + 2 * sum_r);
+    S.apply_bytes_c64 = op->d_fac32 ? (int64_t)sizeof(float2) * (nqr - (int64_t)g->N * kNp * kNp) +
+                                          (int64_t)sizeof(c128) * ((int64_t)op->ntypes * kNp * kNp + 2 * n + 2 * sum_r)
+                                    : 0;
     for (auto& a : op->allocs) op->dev_bytes += a.second;
     S.device_bytes = (int64_t)op->dev_bytes;
     S.t_assembly_s = 0.0;  // assembly is fused into compression; see t_compression_s

@@ -66,26 +66,35 @@ struct ProdWork {
 
 int round_nr(int na) { return na <= 2 ? 2 : (na <= 4 ? 4 : 8); }
 
-// out_r = v - Z x (or Z x when v is null), out_z = Z_D^-1 out_r (optional); internal order
+// out_r = v - Z x (or Z x when v is null), out_z = Z_D^-1 out_r (optional); internal order.
+// lo: far factors from the complex64 panels (the reduced-precision operator).
 void apply_one(const qrvie_op* op, hipStream_t s, const ProdWork& pw, const c128* x, const c128* v, c128* out_r,
-               c128* out_z) {
+               c128* out_z, bool lo = false) {
     const qrvie_geom* g = op->g;
-    for (const auto& L : op->rlaunch)
-        launch_rphase(s, op->d_rstrips + L.begin, L.count, L.waves, op->d_fac, x, pw.T, op->d_tmap);
-    for (const auto& L : op->qlaunch)
-        launch_qphase(s, op->d_qstrips + L.begin, L.count, L.waves, op->d_fac, pw.T, pw.Y);
+    for (const auto& L : op->rlaunch) {
+        if (lo) launch_rphase_c64(s, op->d_rstrips + L.begin, L.count, op->d_fac32, x, pw.T, op->d_tmap);
+        else launch_rphase(s, op->d_rstrips + L.begin, L.count, L.waves, op->d_fac, x, pw.T, op->d_tmap);
+    }
+    for (const auto& L : op->qlaunch) {
+        if (lo) launch_qphase_c64(s, op->d_qstrips + L.begin, L.count, op->d_fac32, pw.T, pw.Y);
+        else launch_qphase(s, op->d_qstrips + L.begin, L.count, L.waves, op->d_fac, pw.T, pw.Y);
+    }
     launch_final(s, g->N, g->d_ptype, op->d_self, out_z ? op->d_pinv : nullptr, x, pw.Y, op->n_active, g->ndof(), v,
                  out_r, out_z);
 }
 
 // The same for nr RHS-interleaved vectors.
 void apply_multi(const qrvie_op* op, hipStream_t s, const ProdWork& pw, int nr, const c128* X, const c128* V,
-                 c128* out_r, c128* out_z) {
+                 c128* out_r, c128* out_z, bool lo = false) {
     const qrvie_geom* g = op->g;
-    for (const auto& L : op->rlaunch)
-        launch_rphase_m(s, nr, op->d_rstrips + L.begin, L.count, op->d_fac, X, pw.T, op->d_tmap);
-    for (const auto& L : op->qlaunch)
-        launch_qphase_m(s, nr, op->d_qstrips + L.begin, L.count, op->d_fac, pw.T, pw.Y);
+    for (const auto& L : op->rlaunch) {
+        if (lo) launch_rphase_m_c64(s, nr, op->d_rstrips + L.begin, L.count, op->d_fac32, X, pw.T, op->d_tmap);
+        else launch_rphase_m(s, nr, op->d_rstrips + L.begin, L.count, op->d_fac, X, pw.T, op->d_tmap);
+    }
+    for (const auto& L : op->qlaunch) {
+        if (lo) launch_qphase_m_c64(s, nr, op->d_qstrips + L.begin, L.count, op->d_fac32, pw.T, pw.Y);
+        else launch_qphase_m(s, nr, op->d_qstrips + L.begin, L.count, op->d_fac, pw.T, pw.Y);
+    }
     launch_final_m(s, nr, g->N, g->d_ptype, op->d_self, out_z ? op->d_pinv : nullptr, X, pw.Y, op->n_active,
                    g->ndof(), V, out_r, out_z);
 }
@@ -105,6 +114,8 @@ struct Col {
     double *cs, *nrm, *np, *bp;
     int* gate;
     double vnorm = 0, pvnorm = 0, prec_tol = 0;
+    double tol = 0;               // relative true-residual target of this column's system
+    int max_it = 0;               // Arnoldi steps allowed in total
     int iters = 0, j = 0;
     bool active = false, converged = false, start = true;
     double t_apply = 0, t0 = 0;
@@ -128,9 +139,11 @@ struct Group {
     double* hstat = nullptr;      // pinned
     const c128** hcols = nullptr; // pinned
     hipEvent_t ev0{}, ev1{};
+    bool lo = false;              // products with the complex64 panels
 
-    Group(qrvie_ctx* cx, const qrvie_op* p, const qrvie_solve_opts* opt, int count)
-        : ctx(cx), op(p), o(opt), s(cx->stream), n(p->g->ndof()), m(0), nch(0), nblk(0), na(count), w(cx), c(count) {}
+    Group(qrvie_ctx* cx, const qrvie_op* p, const qrvie_solve_opts* opt, int count, bool low)
+        : ctx(cx), op(p), o(opt), s(cx->stream), n(p->g->ndof()), m(0), nch(0), nblk(0), na(count), w(cx), c(count),
+          lo(low) {}
     ~Group() {
         if (hstat) (void)hipHostFree(hstat);
         if (hcols) (void)hipHostFree(hcols);
@@ -160,6 +173,7 @@ struct Group {
             CHECK(w.alloc(&k.np, nch, "norm partials"));
             CHECK(w.alloc(&k.bp, nblk, "update norm partials"));
             CHECK(w.alloc(&k.gate, 2, "gate"));
+            CHECK(hip_check(ctx, hipMemsetAsync(k.gate, 0, 2 * sizeof(int), s), "gate"));
         }
         CHECK(w.alloc(&pd_all, (size_t)nch * (m + 1) * na, "dot partials"));
         CHECK(w.alloc(&status, 2 * (size_t)na, "status"));
@@ -193,11 +207,39 @@ struct Group {
         return ms * 1e-3f;
     }
 
+    qrvie_status finish(c128* const* x, const std::vector<c128*>* src, qrvie_solve_info* info, double t0);
+
+    // Column i's system is k.v with the initial guess in k.x: norms of v and Z_D^-1 v,
+    // target tol on the true relative residual, at most max_it Arnoldi steps in total.
+    qrvie_status prepare(int i, double tol, int max_it) {
+        Col& k = c[i];
+        const qrvie_geom* g = op->g;
+        norm_to(k, k.v, k.nrm + 0);
+        launch_block_apply(s, g->N, g->d_ptype, op->d_pinv, k.v, k.r);
+        norm_to(k, k.r, k.nrm + 1);
+        CHECK(read(k.nrm, 2));
+        k.vnorm = std::sqrt(hstat[0]);
+        k.pvnorm = std::sqrt(hstat[1]);
+        if (!std::isfinite(k.vnorm)) {
+            set_err(ctx, "solve: right-hand side has non-finite entries");
+            return QRVIE_ERR_INVALID_ARG;
+        }
+        k.tol = tol;
+        k.max_it = max_it;
+        k.prec_tol = tol;
+        k.j = 0;
+        k.start = true;
+        k.active = k.vnorm > 0.0;
+        k.converged = !k.active;
+        if (!k.active) CHECK(hip_check(ctx, hipMemsetAsync(k.x, 0, sizeof(c128) * n, s), "zero x"));
+        return QRVIE_OK;
+    }
+
     // r = v - Z x, w = Z_D^-1 r: starts a cycle (or finishes the column)
     qrvie_status start_cycle(int i) {
         Col& k = c[i];
         (void)hipEventRecord(ev0, s);
-        apply_one(op, s, pw, k.x, k.v, k.r, k.w);
+        apply_one(op, s, pw, k.x, k.v, k.r, k.w, lo);
         (void)hipEventRecord(ev1, s);
         k.inf.n_apply++;
         k.inf.n_prec++;
@@ -211,10 +253,10 @@ struct Group {
         k.inf.rel_res_true = tr;
         k.inf.rel_res_prec = beta / k.pvnorm;
         if (k.inf.rel_res_prec <= k.prec_tol) {
-            if (tr <= o->tol) { k.converged = true; k.active = false; return QRVIE_OK; }
-            k.prec_tol = std::max(k.prec_tol * 0.5 * o->tol / tr, 1e-15);
+            if (tr <= k.tol) { k.converged = true; k.active = false; return QRVIE_OK; }
+            k.prec_tol = std::max(k.prec_tol * 0.5 * k.tol / tr, 1e-15);
         }
-        if (k.iters >= o->max_iter) { k.active = false; return QRVIE_OK; }
+        if (k.iters >= k.max_it) { k.active = false; return QRVIE_OK; }
         launch_scale_into(s, k.w, n, k.nrm + 1, k.V, k.g);       // V0 = w / beta, g0 = beta
         k.j = 0;
         k.start = false;
@@ -248,7 +290,7 @@ struct Group {
         CHECK(hip_check(ctx, hipMemcpyAsync(k.xc, k.x, sizeof(c128) * n, hipMemcpyDeviceToDevice, s), "x_c"));
         launch_gemv_add(s, k.V, n, kused, k.y, k.xc, n);
         (void)hipEventRecord(ev0, s);
-        apply_one(op, s, pw, k.xc, k.v, k.r, nullptr);
+        apply_one(op, s, pw, k.xc, k.v, k.r, nullptr, lo);
         (void)hipEventRecord(ev1, s);
         k.inf.n_apply++;
         norm_to(k, k.r, k.nrm + 0);
@@ -256,9 +298,9 @@ struct Group {
         k.t_apply += elapsed();
         const double tr = std::sqrt(hstat[0]) / k.vnorm;
         k.inf.rel_res_true = tr;
-        accepted = tr <= o->tol;
+        accepted = tr <= k.tol;
         if (accepted) CHECK(hip_check(ctx, hipMemcpyAsync(k.x, k.xc, sizeof(c128) * n, hipMemcpyDeviceToDevice, s), "x"));
-        else k.prec_tol = std::max(k.prec_tol * 0.5 * o->tol / tr, 1e-15);
+        else k.prec_tol = std::max(k.prec_tol * 0.5 * k.tol / tr, 1e-15);
         return QRVIE_OK;
     }
 
@@ -274,7 +316,7 @@ struct Group {
             (void)hipEventRecord(ev0, s);
             if (act.size() == 1) {
                 Col& k = c[act[0]];
-                apply_one(op, s, pw, k.V + (size_t)k.j * n, nullptr, nullptr, k.w);
+                apply_one(op, s, pw, k.V + (size_t)k.j * n, nullptr, nullptr, k.w, lo);
             } else {
                 const int nr = round_nr((int)act.size());
                 for (size_t a = 0; a < act.size(); ++a) hcols[a] = c[act[a]].V + (size_t)c[act[a]].j * n;
@@ -282,7 +324,7 @@ struct Group {
                 CHECK(hip_check(ctx, hipMemcpyAsync(dcolsX, hcols, sizeof(void*) * act.size(), hipMemcpyHostToDevice, s), "cols"));
                 CHECK(hip_check(ctx, hipMemcpyAsync(dcolsW, hcols + 8, sizeof(void*) * act.size(), hipMemcpyHostToDevice, s), "cols"));
                 launch_interleave(s, nr, n, dcolsX, X, (int)act.size());
-                apply_multi(op, s, pw, nr, X, nullptr, nullptr, Z);
+                apply_multi(op, s, pw, nr, X, nullptr, nullptr, Z, lo);
                 launch_deinterleave(s, nr, n, Z, dcolsW, (int)act.size());
             }
             (void)hipEventRecord(ev1, s);
@@ -302,7 +344,7 @@ struct Group {
                 const double est = st[2 * i] / k.pvnorm;
                 const bool breakdown = st[2 * i + 1] == 0.0;
                 k.inf.rel_res_prec = est;
-                bool end_cycle = kused >= m || k.iters >= o->max_iter;
+                bool end_cycle = kused >= m || k.iters >= k.max_it;
                 if (est <= k.prec_tol || breakdown) {
                     bool ok = false;
                     CHECK(candidate(i, kused, ok));
@@ -320,43 +362,15 @@ struct Group {
     }
 };
 
-qrvie_status solve_group(qrvie_ctx* ctx, const qrvie_op* op, int na, const c128* const* v, c128* const* x,
-                         const qrvie_solve_opts* o, qrvie_solve_info* info) {
-    const double t0 = now_s();
-    Group G(ctx, op, o, na);
-    CHECK(G.init());
-    hipStream_t s = ctx->stream;
+// Unpermute the solutions (from src[i], else each column's x) and fill info.
+qrvie_status Group::finish(c128* const* x, const std::vector<c128*>* src, qrvie_solve_info* info, double t0) {
+    qrvie_status overall = QRVIE_OK;
     const qrvie_geom* g = op->g;
     for (int i = 0; i < na; ++i) {
-        Col& k = G.c[i];
-        launch_permute(s, g->N, g->d_i2c, v[i], k.v, 1);
-        if (o->use_x0) launch_permute(s, g->N, g->d_i2c, x[i], k.x, 1);
-        else CHECK(hip_check(ctx, hipMemsetAsync(k.x, 0, sizeof(c128) * G.n, s), "x0"));
-        CHECK(hip_check(ctx, hipMemsetAsync(k.gate, 0, 2 * sizeof(int), s), "gate"));
-        G.norm_to(k, k.v, k.nrm + 0);
-        launch_block_apply(s, g->N, g->d_ptype, op->d_pinv, k.v, k.r);
-        G.norm_to(k, k.r, k.nrm + 1);
-        CHECK(G.read(k.nrm, 2));
-        k.vnorm = std::sqrt(G.hstat[0]);
-        k.pvnorm = std::sqrt(G.hstat[1]);
-        if (!std::isfinite(k.vnorm)) {
-            set_err(ctx, "solve: right-hand side has non-finite entries");
-            return QRVIE_ERR_INVALID_ARG;
-        }
-        k.prec_tol = o->tol;
-        k.active = k.vnorm > 0.0;
-        if (!k.active) {
-            CHECK(hip_check(ctx, hipMemsetAsync(k.x, 0, sizeof(c128) * G.n, s), "zero x"));
-            k.converged = true;
-        }
-    }
-    CHECK(G.run());
-    qrvie_status overall = QRVIE_OK;
-    for (int i = 0; i < na; ++i) {
-        Col& k = G.c[i];
+        Col& k = c[i];
         int hg[2] = {0, 0};
         CHECK(hip_check(ctx, hipMemcpyAsync(hg, k.gate, sizeof hg, hipMemcpyDeviceToHost, s), "gate"));
-        launch_permute(s, g->N, g->d_i2c, k.x, x[i], 0);
+        launch_permute(s, g->N, g->d_i2c, src ? (*src)[i] : k.x, x[i], 0);
         CHECK(hip_check(ctx, hipStreamSynchronize(s), "solve"));
         k.inf.iterations = k.iters;
         k.inf.converged = k.converged ? 1 : 0;
@@ -371,13 +385,115 @@ qrvie_status solve_group(qrvie_ctx* ctx, const qrvie_op* op, int na, const c128*
     return overall;
 }
 
+qrvie_status solve_group(qrvie_ctx* ctx, const qrvie_op* op, int na, const c128* const* v, c128* const* x,
+                         const qrvie_solve_opts* o, qrvie_solve_info* info) {
+    const double t0 = now_s();
+    Group G(ctx, op, o, na, false);
+    CHECK(G.init());
+    hipStream_t s = ctx->stream;
+    const qrvie_geom* g = op->g;
+    for (int i = 0; i < na; ++i) {
+        Col& k = G.c[i];
+        launch_permute(s, g->N, g->d_i2c, v[i], k.v, 1);
+        if (o->use_x0) launch_permute(s, g->N, g->d_i2c, x[i], k.x, 1);
+        else CHECK(hip_check(ctx, hipMemsetAsync(k.x, 0, sizeof(c128) * G.n, s), "x0"));
+        CHECK(G.prepare(i, o->tol, o->max_iter));
+    }
+    CHECK(G.run());
+    return G.finish(x, nullptr, info, t0);
+}
+
+// Mixed-precision iterative refinement (one group of right-hand sides).  Outer step:
+// r = v - Z_QR x with the complex128 factors; if ||r|| <= tol ||v|| the column is done.
+// Otherwise the correction d of Z_lo d = r comes from the same preconditioned GMRES run
+// on the complex64 factors (FP64 accumulation and Krylov algebra), to the relative
+// target 0.25 tol ||v|| / ||r||, and x += d.  Since ||r - Z_QR d|| <= ||r - Z_lo d|| +
+// ||(Z_lo - Z_QR) d||, one refinement leaves the rounding of the factors, amplified by
+// the conditioning, as the remaining residual; the next refinement removes most of it.
+constexpr int kMaxRefine = 12;
+
+qrvie_status solve_group_ir(qrvie_ctx* ctx, const qrvie_op* op, int na, const c128* const* v, c128* const* x,
+                            const qrvie_solve_opts* o, qrvie_solve_info* info) {
+    const double t0 = now_s();
+    Group G(ctx, op, o, na, true);
+    CHECK(G.init());
+    hipStream_t s = ctx->stream;
+    const qrvie_geom* g = op->g;
+    const int64_t n = G.n;
+    std::vector<c128*> vin(na), xh(na);
+    std::vector<double> vn(na, 0.0), rel(na, 0.0);
+    std::vector<int> state(na, 0);   // 0 refining, 1 converged, 2 stopped
+    for (int i = 0; i < na; ++i) {
+        Col& k = G.c[i];
+        CHECK(G.w.alloc(&vin[i], n, "refinement v"));
+        CHECK(G.w.alloc(&xh[i], n, "refinement x"));
+        launch_permute(s, g->N, g->d_i2c, v[i], vin[i], 1);
+        if (o->use_x0) launch_permute(s, g->N, g->d_i2c, x[i], xh[i], 1);
+        else CHECK(hip_check(ctx, hipMemsetAsync(xh[i], 0, sizeof(c128) * n, s), "x0"));
+        G.norm_to(k, vin[i], k.nrm + 0);
+        CHECK(G.read(k.nrm, 1));
+        vn[i] = std::sqrt(G.hstat[0]);
+        if (!std::isfinite(vn[i])) {
+            set_err(ctx, "solve: right-hand side has non-finite entries");
+            return QRVIE_ERR_INVALID_ARG;
+        }
+        if (vn[i] == 0.0) {
+            CHECK(hip_check(ctx, hipMemsetAsync(xh[i], 0, sizeof(c128) * n, s), "zero x"));
+            state[i] = 1;
+        }
+    }
+    for (int it = 0;; ++it) {
+        std::vector<int> refine;
+        for (int i = 0; i < na; ++i) {
+            if (state[i] != 0) continue;
+            Col& k = G.c[i];
+            (void)hipEventRecord(G.ev0, s);
+            apply_one(op, s, G.pw, xh[i], vin[i], k.v, nullptr, false);   // inner right-hand side r
+            (void)hipEventRecord(G.ev1, s);
+            k.inf.n_apply++;
+            G.norm_to(k, k.v, k.nrm + 0);
+            CHECK(G.read(k.nrm, 1));
+            k.t_apply += G.elapsed();
+            const double r = std::sqrt(G.hstat[0]) / vn[i];
+            if (!std::isfinite(r)) { set_err(ctx, "solve: non-finite residual"); return QRVIE_ERR_DEVICE; }
+            const bool stalled = it > 0 && r > 0.5 * rel[i];
+            rel[i] = r;
+            k.inf.rel_res_true = r;
+            if (r <= o->tol) { state[i] = 1; continue; }
+            if (it >= kMaxRefine || k.iters >= o->max_iter || stalled) { state[i] = 2; continue; }
+            CHECK(hip_check(ctx, hipMemsetAsync(k.x, 0, sizeof(c128) * n, s), "correction"));
+            CHECK(G.prepare(i, std::min(0.5, std::max(0.25 * o->tol / r, 1e-14)), o->max_iter));
+            k.inf.n_refine++;
+            refine.push_back(i);
+        }
+        if (refine.empty()) break;
+        CHECK(G.run());
+        for (int i : refine) launch_add(s, G.c[i].x, n, xh[i]);
+    }
+    for (int i = 0; i < na; ++i) {
+        G.c[i].converged = state[i] == 1;
+        if (state[i] == 1 && vn[i] == 0.0) G.c[i].inf.rel_res_true = 0.0;
+    }
+    return G.finish(x, &xh, info, t0);
+}
+
 }  // namespace
 
 extern "C" {
 
 qrvie_status qrvie_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const qrvie_c128* x, int64_t ldx,
                          qrvie_c128* y, int64_t ldy) {
+    return qrvie_apply_prec(ctx, op, QRVIE_PREC_C128, nrhs, x, ldx, y, ldy);
+}
+
+qrvie_status qrvie_apply_prec(qrvie_ctx* ctx, const qrvie_op* op, int32_t prec, int32_t nrhs, const qrvie_c128* x,
+                              int64_t ldx, qrvie_c128* y, int64_t ldy) {
     CHECK(check_vec_args(ctx, op, nrhs, x, ldx, y, ldy, "apply"));
+    if (prec != QRVIE_PREC_C128 && !(prec == QRVIE_PREC_C64 && op->d_fac32)) {
+        set_err(ctx, "apply: the operator holds no far factors of the requested precision");
+        return QRVIE_ERR_INVALID_ARG;
+    }
+    const bool lo = prec == QRVIE_PREC_C64;
     const int64_t n = op->g->ndof();
     hipStream_t s = ctx->stream;
     Work w(ctx);
@@ -389,7 +505,7 @@ qrvie_status qrvie_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const
     CHECK(w.alloc(&yi, (size_t)n * nrmax, "apply work"));
     if (nrhs == 1) {
         launch_permute(s, op->g->N, op->g->d_i2c, (const c128*)x, xi, 1);
-        apply_one(op, s, pw, xi, nullptr, yi, nullptr);
+        apply_one(op, s, pw, xi, nullptr, yi, nullptr, lo);
         launch_permute(s, op->g->N, op->g->d_i2c, yi, (c128*)y, 0);
     } else {
         CHECK(w.alloc(&X, (size_t)n * kGroup, "apply block"));
@@ -401,7 +517,7 @@ qrvie_status qrvie_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const
             const int cnt = std::min(kGroup, nrhs - r0);
             if (cnt == 1) {
                 launch_permute(s, op->g->N, op->g->d_i2c, (const c128*)x + r0 * ldx, xi, 1);
-                apply_one(op, s, pw, xi, nullptr, yi, nullptr);
+                apply_one(op, s, pw, xi, nullptr, yi, nullptr, lo);
                 launch_permute(s, op->g->N, op->g->d_i2c, yi, (c128*)y + r0 * ldy, 0);
                 continue;
             }
@@ -414,7 +530,7 @@ qrvie_status qrvie_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const
             CHECK(hip_check(ctx, hipMemcpyAsync(dcols, hc.data(), sizeof(void*) * 2 * kGroup, hipMemcpyHostToDevice, s), "cols"));
             CHECK(hip_check(ctx, hipStreamSynchronize(s), "cols"));   // hc is reused next pass
             launch_interleave(s, nr, n, (const c128* const*)dcols, X, cnt);
-            apply_multi(op, s, pw, nr, X, nullptr, Y, nullptr);
+            apply_multi(op, s, pw, nr, X, nullptr, Y, nullptr, lo);
             launch_deinterleave(s, nr, n, Y, dcols + kGroup, cnt);
             for (int a = 0; a < cnt; ++a)
                 launch_permute(s, op->g->N, op->g->d_i2c, yi + (size_t)a * n, (c128*)y + (r0 + a) * ldy, 0);
@@ -424,8 +540,14 @@ qrvie_status qrvie_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const
     return hip_check(ctx, hipStreamSynchronize(s), "apply");
 }
 
-qrvie_status qrvie_op_profile_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t reps, double* ms, int64_t* bytes) {
+qrvie_status qrvie_op_profile_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t prec, int32_t reps, double* ms,
+                                    int64_t* bytes) {
     if (!ctx || !op || reps < 1 || !ms || !bytes) return QRVIE_ERR_INVALID_ARG;
+    if (prec != QRVIE_PREC_C128 && !(prec == QRVIE_PREC_C64 && op->d_fac32)) {
+        set_err(ctx, "profile: the operator holds no far factors of the requested precision");
+        return QRVIE_ERR_INVALID_ARG;
+    }
+    const bool lo = prec == QRVIE_PREC_C64;
     const qrvie_geom* g = op->g;
     const int64_t n = g->ndof();
     hipStream_t s = ctx->stream;
@@ -441,11 +563,15 @@ qrvie_status qrvie_op_profile_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t 
     double acc[4] = {0, 0, 0, 0};
     for (int r = 0; r < reps; ++r) {
         (void)hipEventRecord(ev[0], s);
-        for (const auto& L : op->rlaunch)
-            launch_rphase(s, op->d_rstrips + L.begin, L.count, L.waves, op->d_fac, xi, pw.T, op->d_tmap);
+        for (const auto& L : op->rlaunch) {
+            if (lo) launch_rphase_c64(s, op->d_rstrips + L.begin, L.count, op->d_fac32, xi, pw.T, op->d_tmap);
+            else launch_rphase(s, op->d_rstrips + L.begin, L.count, L.waves, op->d_fac, xi, pw.T, op->d_tmap);
+        }
         (void)hipEventRecord(ev[1], s);
-        for (const auto& L : op->qlaunch)
-            launch_qphase(s, op->d_qstrips + L.begin, L.count, L.waves, op->d_fac, pw.T, pw.Y);
+        for (const auto& L : op->qlaunch) {
+            if (lo) launch_qphase_c64(s, op->d_qstrips + L.begin, L.count, op->d_fac32, pw.T, pw.Y);
+            else launch_qphase(s, op->d_qstrips + L.begin, L.count, L.waves, op->d_fac, pw.T, pw.Y);
+        }
         (void)hipEventRecord(ev[2], s);
         launch_final(s, g->N, g->d_ptype, op->d_self, nullptr, xi, pw.Y, op->n_active, n, nullptr, yi, nullptr);
         (void)hipEventRecord(ev[3], s);
@@ -467,9 +593,9 @@ qrvie_status qrvie_op_profile_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t 
         mr += r * op->blocks[b].rn * (int64_t)kNp;
         sr += r;
     }
-    const int64_t cb = (int64_t)sizeof(c128);
-    bytes[0] = cb * (rn + sr + n);
-    bytes[1] = cb * (mr + sr);
+    const int64_t cb = (int64_t)sizeof(c128), fb = lo ? (int64_t)sizeof(float2) : cb;
+    bytes[0] = fb * rn + cb * (sr + n);
+    bytes[1] = fb * mr + cb * sr;
     bytes[2] = cb * ((int64_t)op->ntypes * kNp * kNp + n);
     bytes[3] = bytes[0] + bytes[1] + bytes[2];
     return hip_check(ctx, hipGetLastError(), "profile");
@@ -537,7 +663,8 @@ qrvie_status qrvie_solve_footprint_estimate(const qrvie_geom* g, const qrvie_op*
     const int64_t nr = na > 1 ? round_nr((int)na) : 1;
     const int64_t nch = krylov_nchunks(n), nblk = krylov_nblocks(n);
     // per column: basis, six vectors, Hessenberg data, partials
-    const int64_t col = n * (m + 1) + 6 * n + (m + 1) * m + 4 * (m + 2) + nch * (m + 1) + nch + nblk;
+    const int64_t col = n * (m + 1) + (o->mode == QRVIE_SOLVE_MIXED_IR ? 8 : 6) * n + (m + 1) * m + 4 * (m + 2) +
+                        nch * (m + 1) + nch + nblk;
     // product workspace: rank-space block (sum of ranks <= 2 x 64 per block side when unknown) and level partials
     const int64_t tlen = op ? op->t_len : (int64_t)g->blocks.size() * 64;
     const int64_t nlev = op ? std::max(op->n_active, 1) : std::max(g->L, 1);
@@ -549,8 +676,13 @@ qrvie_status qrvie_solve_footprint_estimate(const qrvie_geom* g, const qrvie_op*
 qrvie_status qrvie_solve(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const qrvie_c128* v, int64_t ldv,
                          qrvie_c128* x, int64_t ldx, const qrvie_solve_opts* o, qrvie_solve_info* info) {
     CHECK(check_vec_args(ctx, op, nrhs, v, ldv, x, ldx, "solve"));
-    if (!o || o->restart < 1 || o->restart > 16384 || o->max_iter < 1 || !(o->tol > 0.0) || o->mode != QRVIE_SOLVE_FP64) {
+    if (!o || o->restart < 1 || o->restart > 16384 || o->max_iter < 1 || !(o->tol > 0.0) ||
+        (o->mode != QRVIE_SOLVE_FP64 && o->mode != QRVIE_SOLVE_MIXED_IR)) {
         set_err(ctx, "solve: invalid options");
+        return QRVIE_ERR_INVALID_ARG;
+    }
+    if (o->mode == QRVIE_SOLVE_MIXED_IR && !op->d_fac32) {
+        set_err(ctx, "solve: QRVIE_SOLVE_MIXED_IR needs an operator built with far_prec = QRVIE_PREC_C64");
         return QRVIE_ERR_INVALID_ARG;
     }
     qrvie_status overall = QRVIE_OK;
@@ -562,7 +694,10 @@ qrvie_status qrvie_solve(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const
             vv[a] = (const c128*)v + (r0 + a) * ldv;
             xx[a] = (c128*)x + (r0 + a) * ldx;
         }
-        const qrvie_status st = solve_group(ctx, op, cnt, vv.data(), xx.data(), o, info ? info + r0 : nullptr);
+        qrvie_solve_info* inf = info ? info + r0 : nullptr;
+        const qrvie_status st = o->mode == QRVIE_SOLVE_MIXED_IR
+                                    ? solve_group_ir(ctx, op, cnt, vv.data(), xx.data(), o, inf)
+                                    : solve_group(ctx, op, cnt, vv.data(), xx.data(), o, inf);
         if (st == QRVIE_NOT_CONVERGED) overall = st;
         else if (st != QRVIE_OK) return st;
     }

@@ -30,16 +30,16 @@ ARRAYS = {
 
 
 class Case:
-    def __init__(self, name: str, eps: float = 1e-6, max_block_rows: int = 0):
+    def __init__(self, name: str, eps: float = 1e-6, max_block_rows: int = 0, far_prec: int = 0):
         import paper_2603_10586_amd as q
-        print(f"[gpu case] building {name} eps={eps} cap={max_block_rows}", flush=True)
+        print(f"[gpu case] building {name} eps={eps} cap={max_block_rows} far_prec={far_prec}", flush=True)
         self.name = name
         self.eps = eps
         self.array = ARRAYS[name]()
         self.disc = discretise.Discretisation(self.array)
         self.ctx = ctx()
         self.geom = q.Geometry(self.ctx, self.array)
-        self.op = q.Operator(self.ctx, self.geom, eps=eps, max_block_rows=max_block_rows)
+        self.op = q.Operator(self.ctx, self.geom, eps=eps, max_block_rows=max_block_rows, far_prec=far_prec)
         self.order = self.geom.order()
         self._Z = None
         self._factors = None
@@ -69,10 +69,10 @@ class Case:
         return grouping.build_blocks(self.array.lattice_ij, self.array.nx, self.array.ny)
 
 
-def case(name: str, eps: float = 1e-6, max_block_rows: int = 0) -> Case:
-    key = (name, eps, max_block_rows)
+def case(name: str, eps: float = 1e-6, max_block_rows: int = 0, far_prec: int = 0) -> Case:
+    key = (name, eps, max_block_rows, far_prec)
     if key not in _CACHE:
-        _CACHE[key] = Case(name, eps, max_block_rows)
+        _CACHE[key] = Case(name, eps, max_block_rows, far_prec)
     return _CACHE[key]
 
 
