@@ -205,8 +205,12 @@ def main() -> int:
     n = geom.ndof
     prec_bytes = st["apply_bytes"] + st["n_self_types"] * 144 * 144 * 16
     if args.product_only:
-        prof = op.profile_apply(reps=20)
-        print(json.dumps({k: dict(ms=round(p["ms"], 4), bytes=p["bytes"]) for k, p in prof.items()}))
+        for prec in ((q.PREC_C128, q.PREC_C64) if args.mixed_ir else (q.PREC_C128,)):
+            prof = op.profile_apply(reps=20, prec=prec)
+            print(json.dumps({"prec": "c64" if prec == q.PREC_C64 else "c128",
+                              **{k: dict(ms=round(p["ms"], 4), bytes=p["bytes"],
+                                         gbs=round(p["bytes"] / (p["ms"] * 1e-3) / 1e9, 1))
+                                 for k, p in prof.items()}}))
         return 0
 
     for _ in range(args.warmup):

@@ -7,7 +7,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/qrvie.h"
+#include "qrvie.h"
 
 namespace qrvie {
 
@@ -226,15 +226,15 @@ void launch_deinterleave(hipStream_t s, int nr, int64_t n, const c128* blk, c128
 // Krylov helpers (k_krylov.hip)
 int krylov_nchunks(int64_t n);      // multidot / norm2 partial count
 int krylov_nblocks(int64_t n);      // gemv_sub partial count
-void launch_multidot(hipStream_t s, const c128* V, int64_t ldv, int ncols, const c128* w, int64_t n,
-                     c128* partial, double* wpart, const int* gate);
-void launch_reduce_dots(hipStream_t s, const c128* partial, int nchunks, int ncols, c128* h, int accumulate,
-                        const int* gate);
+void launch_multidot(hipStream_t s, const c128* V, int64_t ldv, int ncols, const c128* w, const c128* u, int64_t n,
+                     c128* partial, c128* upartial);
+void launch_reduce_dots(hipStream_t s, const c128* partial, int nchunks, int ncols, c128* h, c128* mirror,
+                        int64_t mstride);
+void launch_cgs2_coeffs(hipStream_t s, const c128* partial, int nchunks, int ncols, c128* h);
 void launch_gemv_sub(hipStream_t s, const c128* V, int64_t ldv, int ncols, const c128* h, c128* w, int64_t n,
-                     double* npart, const int* gate);
+                     double* npart);
 void launch_norm2(hipStream_t s, const c128* w, int64_t n, double* partial);
-void launch_reduce_norm(hipStream_t s, const double* partial, int count, double* out, const int* gate);
-void launch_reorth_gate(hipStream_t s, const double* an2, const double* wn2, int* gate);
+void launch_reduce_norm(hipStream_t s, const double* partial, int count, double* out);
 void launch_scale_into(hipStream_t s, const c128* w, int64_t n, const double* norm2, c128* out, c128* gslot);
 void launch_givens(hipStream_t s, int j, c128* hcol, c128* H, int ldh, double* cs, c128* sn, c128* gvec,
                    const double* hnorm2, double* status);

@@ -14,65 +14,48 @@
 //    preconditioned product costs one pass.
 // Every lane streams 16-byte complex loads down a column (coalesced 1 KiB per wave
 // per column); no atomics, so results are bitwise reproducible.
-#include "internal.h"
+#include "stream.h"
 
 namespace qrvie {
 
 namespace {
 
-__device__ __forceinline__ void cfma(c128& acc, c128 a, c128 b) {
-    acc.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
-    acc.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
-}
-
-typedef double v2d __attribute__((ext_vector_type(2)));
-typedef float v2f __attribute__((ext_vector_type(2)));
-
-// Streaming loads: the factors are read once per product, so keep them out of the caches.
-// Complex64 factors (the reduced-precision panels) are widened to FP64 on load; the
-// accumulation is FP64 either way.
-__device__ __forceinline__ c128 load_stream(const c128* p) {
-    const v2d v = __builtin_nontemporal_load(reinterpret_cast<const v2d*>(p));
-    return make_double2(v.x, v.y);
-}
-__device__ __forceinline__ c128 load_stream(const float2* p) {
-    const v2f v = __builtin_nontemporal_load(reinterpret_cast<const v2f*>(p));
-    return make_double2((double)v.x, (double)v.y);
-}
-__device__ __forceinline__ c128 load_plain(const c128* p) { return *p; }
-__device__ __forceinline__ c128 load_plain(const float2* p) { return make_double2((double)p->x, (double)p->y); }
-
-// Columns loaded per batch: the same bytes in flight for 16- and 8-byte entries.
+// Columns per batch: the same bytes in flight for 16- and 8-byte entries.
 template <typename F> struct Unroll { static constexpr int U = sizeof(F) == 16 ? 8 : 16; };
 
-// acc += sum_{j in [j0, j1)} A[j*ld] * v[j]   (A already offset to this lane's row)
+template <int U>
+__device__ __forceinline__ void wave_columns(int ncols, int waves, int wv, int& j0, int& j1) {
+    const int per = (ncols + waves * U - 1) / (waves * U) * U;
+    j0 = min(ncols, wv * per);
+    j1 = min(ncols, j0 + per);
+}
+
+// acc += sum_{j in [j0, j1)} A[j*ld] * v[j]   (A already offset to this lane's row).
 template <typename F>
 __device__ __forceinline__ c128 column_stream(const F* __restrict__ A, int64_t ld, const c128* __restrict__ v,
                                               int j0, int j1) {
     constexpr int U = Unroll<F>::U;
     c128 acc0 = make_double2(0.0, 0.0), acc1 = acc0;
-    int j = j0;
-    for (; j + U <= j1; j += U) {
-        c128 a[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) a[u] = load_stream(A + (int64_t)(j + u) * ld);
+    const int nb = (j1 - j0) / U;
+    stream_batches<F, U>(A + (int64_t)j0 * ld, ld, nb, [&](const F* w, int k) {
+        const c128* vv = v + j0 + k * U;
 #pragma unroll
         for (int u = 0; u < U; u += 2) {
-            cfma(acc0, a[u], v[j + u]);
-            cfma(acc1, a[u + 1], v[j + u + 1]);
+            cfma(acc0, widen(w[u]), vv[u]);
+            cfma(acc1, widen(w[u + 1]), vv[u + 1]);
         }
-    }
-    for (; j < j1; ++j) cfma(acc0, load_plain(A + (int64_t)j * ld), v[j]);
+    });
+    for (int j = j0 + nb * U; j < j1; ++j) cfma(acc0, widen(A[(int64_t)j * ld]), v[j]);
     return make_double2(acc0.x + acc1.x, acc0.y + acc1.y);
 }
 
 template <typename F, int WAVES>
 __device__ __forceinline__ void rphase_body(const RStrip& s, const F* __restrict__ fac, const c128* __restrict__ x,
                                             c128* __restrict__ t, const int64_t* __restrict__ tmap) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = wave_id();
     const int row = min(lane, s.nrows - 1);
-    const int per = (s.ncols + WAVES - 1) / WAVES;
-    const int j0 = min(s.ncols, wv * per), j1 = min(s.ncols, j0 + per);
+    int j0, j1;
+    wave_columns<Unroll<F>::U>(s.ncols, WAVES, wv, j0, j1);
     const c128 acc = column_stream<F>(fac + s.a_off + row, s.ld, x + s.x_off, j0, j1);
     if (WAVES == 1) {
         if (lane < s.nrows) t[tmap[s.tmap_off + lane]] = acc;
@@ -92,10 +75,10 @@ __device__ __forceinline__ void rphase_body(const RStrip& s, const F* __restrict
 template <typename F, int WAVES>
 __device__ __forceinline__ void qphase_body(const QStrip& s, const F* __restrict__ fac, const c128* __restrict__ t,
                                             c128* __restrict__ y) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = wave_id();
     const int row = min(lane, max(s.nrows - 1, 0));
-    const int per = (s.ncols + WAVES - 1) / WAVES;
-    const int j0 = min(s.ncols, wv * per), j1 = min(s.ncols, j0 + per);
+    int j0, j1;
+    wave_columns<Unroll<F>::U>(s.ncols, WAVES, wv, j0, j1);
     const c128 acc = column_stream<F>(fac + s.a_off + row, s.ld, t + s.t_off, j0, j1);
     if (WAVES == 1) {
         if (lane < s.nrows) y[s.y_off + lane] = acc;
@@ -218,33 +201,36 @@ __global__ void __launch_bounds__(kNp * kGroups) k_block_apply(const int32_t* __
 // NR entries a lane needs for one column are one contiguous wave-uniform row.  Each
 // factor element is loaded once and applied to all NR vectors: the streaming pattern and
 // the HBM bytes of the factors are those of the single-RHS product.
+template <typename F> struct UnrollM { static constexpr int U = sizeof(F) == 16 ? 4 : 8; };
+
 template <typename F, int NR>
 __device__ __forceinline__ void column_stream_m(const F* __restrict__ A, int64_t ld, const c128* __restrict__ v,
                                                 int j0, int j1, c128 acc[NR]) {
-    int j = j0;
-    for (; j + 4 <= j1; j += 4) {
-        c128 a[4];
+    constexpr int U = UnrollM<F>::U;
+    const int nb = (j1 - j0) / U;
+    stream_batches<F, U>(A + (int64_t)j0 * ld, ld, nb, [&](const F* w, int k) {
+        const c128* vv = v + (int64_t)(j0 + k * U) * NR;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) a[u] = load_stream(A + (int64_t)(j + u) * ld);
+        for (int u = 0; u < U; ++u) {
+            const c128 m = widen(w[u]);
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+            for (int r = 0; r < NR; ++r) cfma(acc[r], m, vv[u * NR + r]);
+        }
+    });
+    for (int j = j0 + nb * U; j < j1; ++j) {
+        const c128 m = widen(A[(int64_t)j * ld]);
 #pragma unroll
-            for (int r = 0; r < NR; ++r) cfma(acc[r], a[u], v[(int64_t)(j + u) * NR + r]);
-    }
-    for (; j < j1; ++j) {
-        const c128 a = load_plain(A + (int64_t)j * ld);
-#pragma unroll
-        for (int r = 0; r < NR; ++r) cfma(acc[r], a, v[(int64_t)j * NR + r]);
+        for (int r = 0; r < NR; ++r) cfma(acc[r], m, v[(int64_t)j * NR + r]);
     }
 }
 
 template <typename F, int NR>
 __device__ __forceinline__ void rphase_m_body(const RStrip& s, const F* __restrict__ fac, const c128* __restrict__ X,
                                               c128* __restrict__ T, const int64_t* __restrict__ tmap) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = wave_id();
     const int row = min(lane, s.nrows - 1);
-    const int per = (s.ncols + 3) / 4;
-    const int j0 = min(s.ncols, wv * per), j1 = min(s.ncols, j0 + per);
+    int j0, j1;
+    wave_columns<UnrollM<F>::U>(s.ncols, 4, wv, j0, j1);
     c128 acc[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[r] = make_double2(0.0, 0.0);
@@ -280,10 +266,10 @@ __global__ void __launch_bounds__(256) k_rphase_m_c64(const RStrip* __restrict__
 template <typename F, int NR>
 __device__ __forceinline__ void qphase_m_body(const QStrip& s, const F* __restrict__ fac, const c128* __restrict__ T,
                                               c128* __restrict__ Y) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = wave_id();
     const int row = min(lane, max(s.nrows - 1, 0));
-    const int per = (s.ncols + 3) / 4;
-    const int j0 = min(s.ncols, wv * per), j1 = min(s.ncols, j0 + per);
+    int j0, j1;
+    wave_columns<UnrollM<F>::U>(s.ncols, 4, wv, j0, j1);
     c128 acc[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[r] = make_double2(0.0, 0.0);

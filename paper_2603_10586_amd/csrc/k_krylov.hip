@@ -1,15 +1,17 @@
 // Krylov building blocks of left-preconditioned GMRES (the paper's solver of §6 with
 // the preconditioner of §4): Gram-Schmidt projections as multi-dot / multi-axpy kernels
-// over the column-major basis V (n x (m+1)) with the vector norms fused in, a device-side
-// reorthogonalisation gate, and the Hessenberg least-squares update by complex Givens
-// rotations, all in FP64 on the device.  Reductions are two-stage with a fixed order, so
-// results are bitwise reproducible.
+// over the column-major basis V (n x (m+1)) with the vector norms fused in, and the
+// Hessenberg least-squares update by complex Givens rotations, all in FP64 on the device.
+// Reductions are two-stage with a fixed order, so results are bitwise reproducible.
 //
-// Orthogonalisation: one classical Gram-Schmidt pass, then a second pass only when the
-// projection removed most of the vector (||w'|| < ||w|| / sqrt 2, the Daniel-Gragg-
-// Kaufman-Stewart criterion).  The gate is evaluated on the device and the second pass's
-// kernels return immediately when it is closed, so the host never waits for it.
-#include "internal.h"
+// Orthogonalisation is classical Gram-Schmidt with one reorthogonalisation (CGS2) in two
+// passes over the basis instead of four.  With h1 = V^H w, the second projection
+// V^H (w - V h1) equals h1 - G h1 for the Gram matrix G = V^H V of the stored basis, so
+// CGS2's coefficients are h = 2 h1 - G h1 and its vector is w - V h.  G gains one column
+// per step (V^H v_j, computed in the same pass as V^H w), and G h1 is a small
+// (j+1) x (j+1) product.  The result equals CGS2 up to rounding: in both, the component
+// of the new vector left along the basis is (I - G)^2 h1.
+#include "stream.h"
 
 namespace qrvie {
 
@@ -30,58 +32,61 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     return (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-__device__ __forceinline__ bool closed(const int* gate) { return gate && *gate == 0; }
-
-// partial[c * ncols + i] = sum_{e in chunk c} conj(V_i[e]) w[e];  wpart[c] = ||w_chunk||^2.
-// Grid: (row chunks of 1024, groups of 64 basis vectors).  Each lane keeps its 16 elements
-// of the w chunk in registers; a wave streams one basis vector's chunk per step.
+// partial[c * ncols + i] = sum_{e in chunk c} conj(V_i[e]) w[e], and the same with u into
+// upartial when u is given (two projections per pass over V).  Grid: (row chunks of 1024,
+// groups of 64 basis vectors).  The w (and u) chunk is staged in LDS, zero past n; a wave
+// issues all 16 loads of one basis vector's chunk before its FMAs (rows past n re-read
+// row n-1 and meet a zero).
 constexpr int kPerLane = kChunk / 64;
 constexpr int kVecGroup = 64;
 
+template <bool TWO>
 __global__ void __launch_bounds__(256) k_multidot(const c128* __restrict__ V, int64_t ldv, int ncols,
-                                                  const c128* __restrict__ w, int64_t n, c128* __restrict__ partial,
-                                                  double* __restrict__ wpart, const int* gate) {
-    if (closed(gate)) return;
+                                                  const c128* __restrict__ w, const c128* __restrict__ u, int64_t n,
+                                                  c128* __restrict__ partial, c128* __restrict__ upartial) {
+    __shared__ c128 ws[kChunk];
+    __shared__ c128 us[TWO ? kChunk : 1];
     const int c = blockIdx.x;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t e0 = (int64_t)c * kChunk;
     const int cnt = (n - e0) < kChunk ? (int)(n - e0) : kChunk;
-    c128 wr[kPerLane];
-#pragma unroll
-    for (int t = 0; t < kPerLane; ++t) {
-        const int o = lane + 64 * t;
-        wr[t] = o < cnt ? w[e0 + o] : make_double2(0.0, 0.0);
+    for (int o = threadIdx.x; o < kChunk; o += 256) {
+        ws[o] = o < cnt ? w[e0 + o] : make_double2(0.0, 0.0);
+        if (TWO) us[o] = o < cnt ? u[e0 + o] : make_double2(0.0, 0.0);
     }
+    __syncthreads();
     const int i1 = min(ncols, (int)(blockIdx.y + 1) * kVecGroup);
     for (int i = blockIdx.y * kVecGroup + wv; i < i1; i += 4) {
         const c128* vi = V + (int64_t)i * ldv + e0;
+        c128 a[kPerLane];
+#pragma unroll
+        for (int t = 0; t < kPerLane; ++t) a[t] = load_stream(vi + min(lane + 64 * t, cnt - 1));
+        __builtin_amdgcn_sched_barrier(0);
         double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
 #pragma unroll
-        for (int t = 0; t < kPerLane; t += 2) {
-            const int o0 = lane + 64 * t, o1 = o0 + 64;
-            const c128 a0 = o0 < cnt ? vi[o0] : make_double2(0.0, 0.0);
-            const c128 a1 = o1 < cnt ? vi[o1] : make_double2(0.0, 0.0);
-            re0 = fma(a0.x, wr[t].x, fma(a0.y, wr[t].y, re0));
-            im0 = fma(a0.x, wr[t].y, fma(-a0.y, wr[t].x, im0));
-            re1 = fma(a1.x, wr[t + 1].x, fma(a1.y, wr[t + 1].y, re1));
-            im1 = fma(a1.x, wr[t + 1].y, fma(-a1.y, wr[t + 1].x, im1));
+        for (int t = 0; t < kPerLane; ++t) {
+            const c128 x = ws[lane + 64 * t];
+            re0 = fma(a[t].x, x.x, fma(a[t].y, x.y, re0));
+            im0 = fma(a[t].x, x.y, fma(-a[t].y, x.x, im0));
+            if (TWO) {
+                const c128 y = us[lane + 64 * t];
+                re1 = fma(a[t].x, y.x, fma(a[t].y, y.y, re1));
+                im1 = fma(a[t].x, y.y, fma(-a[t].y, y.x, im1));
+            }
         }
-        const double re = wave_sum(re0 + re1), im = wave_sum(im0 + im1);
+        const double re = wave_sum(re0), im = wave_sum(im0);
         if (lane == 0) partial[(int64_t)c * ncols + i] = make_double2(re, im);
-    }
-    if (wpart && blockIdx.y == 0) {
-        __shared__ double red[4];
-        double s = 0.0;
-#pragma unroll
-        for (int t = 0; t < kPerLane; ++t) s = fma(wr[t].x, wr[t].x, fma(wr[t].y, wr[t].y, s));
-        s = block_sum(s, red);
-        if (threadIdx.x == 0) wpart[c] = s;
+        if (TWO) {
+            const double ur = wave_sum(re1), ui = wave_sum(im1);
+            if (lane == 0) upartial[(int64_t)c * ncols + i] = make_double2(ur, ui);
+        }
     }
 }
 
-__global__ void k_reduce_dots(const c128* __restrict__ partial, int nchunks, int ncols, c128* h, int accumulate,
-                              const int* gate) {
-    if (closed(gate)) return;
+// h[i] = sum_c partial[c * ncols + i]; when mirror is given, also mirror[i * mstride] =
+// conj(h[i]) for i < ncols - 1 (the row of a Hermitian matrix whose column is h).
+__global__ void k_reduce_dots(const c128* __restrict__ partial, int nchunks, int ncols, c128* h, c128* mirror,
+                              int64_t mstride) {
     const int i = threadIdx.x + blockIdx.x * blockDim.x;
     if (i >= ncols) return;
     double re = 0.0, im = 0.0;
@@ -91,46 +96,50 @@ __global__ void k_reduce_dots(const c128* __restrict__ partial, int nchunks, int
         re += p.x;
         im += p.y;
     }
-    if (accumulate) { re += h[i].x; im += h[i].y; }
     h[i] = make_double2(re, im);
+    if (mirror && i < ncols - 1) mirror[(int64_t)i * mstride] = make_double2(re, -im);
 }
 
-// w += SIGN * V h (coefficients staged through LDS 512 at a time); npart[block] = ||w_block||^2 after.
+// h[i] = 2 h1[i] - sum_c partial[c * ncols + i]  (CGS2 coefficients from G h1 partials)
+__global__ void k_cgs2_coeffs(const c128* __restrict__ partial, int nchunks, int ncols, c128* h) {
+    const int i = threadIdx.x + blockIdx.x * blockDim.x;
+    if (i >= ncols) return;
+    double re = 0.0, im = 0.0;
+    for (int c = 0; c < nchunks; ++c) {
+        const c128 p = partial[(int64_t)c * ncols + i];
+        re += p.x;
+        im += p.y;
+    }
+    h[i] = make_double2(2.0 * h[i].x - re, 2.0 * h[i].y - im);
+}
+
+// w += SIGN * V h; npart[block] = ||w_block||^2 after (when given).  One row per lane; the
+// coefficients are wave-uniform scalar loads and the basis columns stream in
+// double-buffered batches of 8 (rows past n re-read row n-1 and are not stored).
 template <int SIGN>
 __global__ void __launch_bounds__(256) k_gemv_acc(const c128* __restrict__ V, int64_t ldv, int ncols,
                                                   const c128* __restrict__ h, c128* __restrict__ w, int64_t n,
-                                                  double* __restrict__ npart, const int* gate) {
-    if (closed(gate)) return;
-    __shared__ c128 hs[512];
+                                                  double* __restrict__ npart) {
+    constexpr int U = 8;
     __shared__ double red[4];
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = e < n;
-    double re = live ? w[e].x : 0.0, im = live ? w[e].y : 0.0;
-    for (int c0 = 0; c0 < ncols; c0 += 512) {
-        const int cn = min(512, ncols - c0);
-        __syncthreads();
-        for (int i = threadIdx.x; i < cn; i += blockDim.x) hs[i] = make_double2(SIGN * h[c0 + i].x, SIGN * h[c0 + i].y);
-        __syncthreads();
-        if (live) {
-            const c128* vp = V + e + (int64_t)c0 * ldv;
-            int i = 0;
-            for (; i + 8 <= cn; i += 8) {
-                c128 a[8];
+    const int64_t row = live ? e : n - 1;
+    c128 acc0 = live ? w[e] : make_double2(0.0, 0.0), acc1 = make_double2(0.0, 0.0);
+    const int nb = ncols / U;
+    stream_batches<c128, U>(V + row, ldv, nb, [&](const c128* a, int k) {
+        const c128* hh = h + k * U;
 #pragma unroll
-                for (int u = 0; u < 8; ++u) a[u] = vp[(int64_t)(i + u) * ldv];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    re = fma(a[u].x, hs[i + u].x, fma(-a[u].y, hs[i + u].y, re));
-                    im = fma(a[u].x, hs[i + u].y, fma(a[u].y, hs[i + u].x, im));
-                }
-            }
-            for (; i < cn; ++i) {
-                const c128 a = vp[(int64_t)i * ldv];
-                re = fma(a.x, hs[i].x, fma(-a.y, hs[i].y, re));
-                im = fma(a.x, hs[i].y, fma(a.y, hs[i].x, im));
-            }
+        for (int u = 0; u < U; u += 2) {
+            const c128 h0 = make_double2(SIGN * hh[u].x, SIGN * hh[u].y);
+            const c128 h1 = make_double2(SIGN * hh[u + 1].x, SIGN * hh[u + 1].y);
+            cfma(acc0, a[u], h0);
+            cfma(acc1, a[u + 1], h1);
         }
-    }
+    });
+    for (int i = nb * U; i < ncols; ++i)
+        cfma(acc0, V[row + (int64_t)i * ldv], make_double2(SIGN * h[i].x, SIGN * h[i].y));
+    const double re = acc0.x + acc1.x, im = acc0.y + acc1.y;
     if (live) w[e] = make_double2(re, im);
     if (npart) {
         const double s = block_sum(live ? re * re + im * im : 0.0, red);
@@ -148,9 +157,7 @@ __global__ void __launch_bounds__(256) k_norm2(const c128* __restrict__ w, int64
     if (threadIdx.x == 0) partial[c] = s;
 }
 
-__global__ void __launch_bounds__(256) k_reduce_norm(const double* __restrict__ partial, int count, double* out,
-                                                     const int* gate) {
-    if (closed(gate)) return;
+__global__ void __launch_bounds__(256) k_reduce_norm(const double* __restrict__ partial, int count, double* out) {
     __shared__ double red[256];
     const int tid = threadIdx.x;
     double s = 0.0;
@@ -162,15 +169,6 @@ __global__ void __launch_bounds__(256) k_reduce_norm(const double* __restrict__ 
         __syncthreads();
     }
     if (tid == 0) out[0] = red[0];
-}
-
-// gate[0] = 1 when the projected norm fell below 1/sqrt(2) of the original; gate[1] counts openings
-__global__ void k_reorth_gate(const double* an2, const double* wn2, int* gate) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        const int open = (an2[0] < 0.5 * wn2[0]) ? 1 : 0;
-        gate[0] = open;
-        gate[1] += open;
-    }
 }
 
 // out = w / sqrt(norm2); gslot (optional) = sqrt(norm2)
@@ -289,32 +287,32 @@ __global__ void __launch_bounds__(256) k_trisolve(int k, const c128* H, int ldh,
 int krylov_nchunks(int64_t n) { return (int)((n + kChunk - 1) / kChunk); }
 int krylov_nblocks(int64_t n) { return (int)((n + 255) / 256); }
 
-void launch_multidot(hipStream_t s, const c128* V, int64_t ldv, int ncols, const c128* w, int64_t n, c128* partial,
-                     double* wpart, const int* gate) {
+void launch_multidot(hipStream_t s, const c128* V, int64_t ldv, int ncols, const c128* w, const c128* u, int64_t n,
+                     c128* partial, c128* upartial) {
     dim3 grid(krylov_nchunks(n), (ncols + kVecGroup - 1) / kVecGroup);
-    hipLaunchKernelGGL(k_multidot, grid, dim3(256), 0, s, V, ldv, ncols, w, n, partial, wpart, gate);
+    if (u) hipLaunchKernelGGL(k_multidot<true>, grid, dim3(256), 0, s, V, ldv, ncols, w, u, n, partial, upartial);
+    else hipLaunchKernelGGL(k_multidot<false>, grid, dim3(256), 0, s, V, ldv, ncols, w, u, n, partial, upartial);
 }
-void launch_reduce_dots(hipStream_t s, const c128* partial, int nchunks, int ncols, c128* h, int accumulate,
-                        const int* gate) {
-    hipLaunchKernelGGL(k_reduce_dots, dim3((ncols + 255) / 256), dim3(256), 0, s, partial, nchunks, ncols, h,
-                       accumulate, gate);
+void launch_reduce_dots(hipStream_t s, const c128* partial, int nchunks, int ncols, c128* h, c128* mirror,
+                        int64_t mstride) {
+    hipLaunchKernelGGL(k_reduce_dots, dim3((ncols + 255) / 256), dim3(256), 0, s, partial, nchunks, ncols, h, mirror,
+                       mstride);
+}
+void launch_cgs2_coeffs(hipStream_t s, const c128* partial, int nchunks, int ncols, c128* h) {
+    hipLaunchKernelGGL(k_cgs2_coeffs, dim3((ncols + 255) / 256), dim3(256), 0, s, partial, nchunks, ncols, h);
 }
 void launch_gemv_sub(hipStream_t s, const c128* V, int64_t ldv, int ncols, const c128* h, c128* w, int64_t n,
-                     double* npart, const int* gate) {
-    hipLaunchKernelGGL(k_gemv_acc<-1>, dim3(krylov_nblocks(n)), dim3(256), 0, s, V, ldv, ncols, h, w, n, npart, gate);
+                     double* npart) {
+    hipLaunchKernelGGL(k_gemv_acc<-1>, dim3(krylov_nblocks(n)), dim3(256), 0, s, V, ldv, ncols, h, w, n, npart);
 }
 void launch_gemv_add(hipStream_t s, const c128* V, int64_t ldv, int ncols, const c128* y, c128* x, int64_t n) {
-    hipLaunchKernelGGL(k_gemv_acc<1>, dim3(krylov_nblocks(n)), dim3(256), 0, s, V, ldv, ncols, y, x, n, nullptr,
-                       nullptr);
+    hipLaunchKernelGGL(k_gemv_acc<1>, dim3(krylov_nblocks(n)), dim3(256), 0, s, V, ldv, ncols, y, x, n, nullptr);
 }
 void launch_norm2(hipStream_t s, const c128* w, int64_t n, double* partial) {
     hipLaunchKernelGGL(k_norm2, dim3(krylov_nchunks(n)), dim3(256), 0, s, w, n, partial);
 }
-void launch_reduce_norm(hipStream_t s, const double* partial, int count, double* out, const int* gate) {
-    hipLaunchKernelGGL(k_reduce_norm, dim3(1), dim3(256), 0, s, partial, count, out, gate);
-}
-void launch_reorth_gate(hipStream_t s, const double* an2, const double* wn2, int* gate) {
-    hipLaunchKernelGGL(k_reorth_gate, dim3(1), dim3(64), 0, s, an2, wn2, gate);
+void launch_reduce_norm(hipStream_t s, const double* partial, int count, double* out) {
+    hipLaunchKernelGGL(k_reduce_norm, dim3(1), dim3(256), 0, s, partial, count, out);
 }
 void launch_scale_into(hipStream_t s, const c128* w, int64_t n, const double* norm2, c128* out, c128* gslot) {
     hipLaunchKernelGGL(k_scale_into, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w, n, norm2, out, gslot);

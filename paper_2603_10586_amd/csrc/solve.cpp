@@ -6,8 +6,9 @@
 // and the preconditioner to all of them in one multi-RHS product, so the factor panels
 // are streamed from HBM once per step for the whole group.
 //
-// Per Arnoldi step and RHS: one classical Gram-Schmidt pass with the norms fused in, a
-// second pass when the device-side gate opens, and a device-side Givens update.  The host
+// Per Arnoldi step and RHS: classical Gram-Schmidt with one reorthogonalisation in two
+// passes over the basis (the second projection through the Gram matrix of the basis),
+// the new vector's norm fused into the update, and a device-side Givens update.  The host
 // reads two numbers per RHS and step.  A column is converged when its preconditioned
 // estimate is <= tol ||Z_D^-1 v|| and its true residual ||v - Z_QR x|| / ||v|| <= tol.
 // When only the estimate meets its target, the target is tightened and the same Krylov
@@ -111,8 +112,8 @@ qrvie_status check_vec_args(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, co
 // ------------------------------------------------------------------ GMRES group engine
 struct Col {
     c128 *V, *w, *x, *xc, *v, *r, *h, *H, *sn, *g, *y;
+    c128* G;                      // Gram matrix V^H V of the basis, (m+1) x (m+1)
     double *cs, *nrm, *np, *bp;
-    int* gate;
     double vnorm = 0, pvnorm = 0, prec_tol = 0;
     double tol = 0;               // relative true-residual target of this column's system
     int max_it = 0;               // Arnoldi steps allowed in total
@@ -172,10 +173,12 @@ struct Group {
             CHECK(w.alloc(&k.nrm, 4, "norms"));
             CHECK(w.alloc(&k.np, nch, "norm partials"));
             CHECK(w.alloc(&k.bp, nblk, "update norm partials"));
-            CHECK(w.alloc(&k.gate, 2, "gate"));
-            CHECK(hip_check(ctx, hipMemsetAsync(k.gate, 0, 2 * sizeof(int), s), "gate"));
+            CHECK(w.alloc(&k.G, (size_t)(m + 1) * (m + 1), "gram matrix"));
         }
+        nchg = krylov_nchunks(m + 1);
         CHECK(w.alloc(&pd_all, (size_t)nch * (m + 1) * na, "dot partials"));
+        CHECK(w.alloc(&pu_all, (size_t)nch * (m + 1) * na, "gram partials"));
+        CHECK(w.alloc(&pg_all, (size_t)nchg * (m + 1) * na, "gram product partials"));
         CHECK(w.alloc(&status, 2 * (size_t)na, "status"));
         if (na > 1) {
             const int nr = round_nr(na);
@@ -190,8 +193,11 @@ struct Group {
         (void)hipEventCreate(&ev1);
         return QRVIE_OK;
     }
-    c128* pd_all = nullptr;
+    c128 *pd_all = nullptr, *pu_all = nullptr, *pg_all = nullptr;
+    int nchg = 0;
     c128* pd(int k) { return pd_all + (size_t)k * nch * (m + 1); }
+    c128* pu(int k) { return pu_all + (size_t)k * nch * (m + 1); }
+    c128* pg(int k) { return pg_all + (size_t)k * nchg * (m + 1); }
 
     qrvie_status read(const double* d, int cnt) {
         CHECK(hip_check(ctx, hipMemcpyAsync(hstat, d, sizeof(double) * cnt, hipMemcpyDeviceToHost, s), "read"));
@@ -199,7 +205,7 @@ struct Group {
     }
     void norm_to(Col& k, const c128* vec, double* dst) {
         launch_norm2(s, vec, n, k.np);
-        launch_reduce_norm(s, k.np, nch, dst, nullptr);
+        launch_reduce_norm(s, k.np, nch, dst);
     }
     float elapsed() {
         float ms = 0.f;
@@ -263,22 +269,21 @@ struct Group {
         return QRVIE_OK;
     }
 
-    // Gram-Schmidt + Givens of column i's step j (w already holds Z_D^-1 Z v_j)
+    // Gram-Schmidt + Givens of column i's step j (w already holds Z_D^-1 Z v_j).
+    // Pass 1: h1 = V^H w and G[:, j] = V^H v_j (G[j, :] mirrored); h = 2 h1 - G h1;
+    // pass 2: w -= V h with ||w||^2 fused; then the Givens update and v_{j+1} = w / ||w||.
     void arnoldi_tail(int i) {
         Col& k = c[i];
         const int j = k.j;
-        c128* P = pd(i);
-        launch_multidot(s, k.V, n, j + 1, k.w, n, P, k.np, nullptr);
-        launch_reduce_dots(s, P, nch, j + 1, k.h, 0, nullptr);
-        launch_reduce_norm(s, k.np, nch, k.nrm + 3, nullptr);
-        launch_gemv_sub(s, k.V, n, j + 1, k.h, k.w, n, k.bp, nullptr);
-        launch_reduce_norm(s, k.bp, nblk, k.nrm + 2, nullptr);
-        launch_reorth_gate(s, k.nrm + 2, k.nrm + 3, k.gate);
-        launch_multidot(s, k.V, n, j + 1, k.w, n, P, nullptr, k.gate);
-        launch_reduce_dots(s, P, nch, j + 1, k.y, 0, k.gate);
-        launch_reduce_dots(s, P, nch, j + 1, k.h, 1, k.gate);
-        launch_gemv_sub(s, k.V, n, j + 1, k.y, k.w, n, k.bp, k.gate);
-        launch_reduce_norm(s, k.bp, nblk, k.nrm + 2, k.gate);
+        const int64_t ldg = m + 1;
+        c128* gcol = k.G + (int64_t)j * ldg;
+        launch_multidot(s, k.V, n, j + 1, k.w, k.V + (size_t)j * n, n, pd(i), pu(i));
+        launch_reduce_dots(s, pd(i), nch, j + 1, k.h, nullptr, 0);
+        launch_reduce_dots(s, pu(i), nch, j + 1, gcol, k.G + j, ldg);
+        launch_multidot(s, k.G, ldg, j + 1, k.h, nullptr, j + 1, pg(i), nullptr);
+        launch_cgs2_coeffs(s, pg(i), krylov_nchunks(j + 1), j + 1, k.h);
+        launch_gemv_sub(s, k.V, n, j + 1, k.h, k.w, n, k.bp);
+        launch_reduce_norm(s, k.bp, nblk, k.nrm + 2);
         launch_givens(s, j, k.h, k.H, m + 1, k.cs, k.sn, k.g, k.nrm + 2, status + 2 * i);
         launch_scale_into(s, k.w, n, k.nrm + 2, k.V + (size_t)(j + 1) * n, nullptr);
     }
@@ -368,13 +373,11 @@ qrvie_status Group::finish(c128* const* x, const std::vector<c128*>* src, qrvie_
     const qrvie_geom* g = op->g;
     for (int i = 0; i < na; ++i) {
         Col& k = c[i];
-        int hg[2] = {0, 0};
-        CHECK(hip_check(ctx, hipMemcpyAsync(hg, k.gate, sizeof hg, hipMemcpyDeviceToHost, s), "gate"));
         launch_permute(s, g->N, g->d_i2c, src ? (*src)[i] : k.x, x[i], 0);
         CHECK(hip_check(ctx, hipStreamSynchronize(s), "solve"));
         k.inf.iterations = k.iters;
         k.inf.converged = k.converged ? 1 : 0;
-        k.inf.n_reorth = hg[1];
+        k.inf.n_reorth = k.iters;   // every step carries the second projection
         k.inf.t_apply_s = k.t_apply;
         k.inf.t_prec_s = 0.0;   // fused into the product pass
         k.inf.t_total_s = now_s() - t0;
@@ -662,9 +665,9 @@ qrvie_status qrvie_solve_footprint_estimate(const qrvie_geom* g, const qrvie_op*
     const int64_t na = std::min(nrhs, kGroup);
     const int64_t nr = na > 1 ? round_nr((int)na) : 1;
     const int64_t nch = krylov_nchunks(n), nblk = krylov_nblocks(n);
-    // per column: basis, six vectors, Hessenberg data, partials
-    const int64_t col = n * (m + 1) + (o->mode == QRVIE_SOLVE_MIXED_IR ? 8 : 6) * n + (m + 1) * m + 4 * (m + 2) +
-                        nch * (m + 1) + nch + nblk;
+    // per column: basis, six vectors, Hessenberg and Gram matrices, partials
+    const int64_t col = n * (m + 1) + (o->mode == QRVIE_SOLVE_MIXED_IR ? 8 : 6) * n + (m + 1) * m + (m + 1) * (m + 1) +
+                        4 * (m + 2) + 2 * nch * (m + 1) + krylov_nchunks(m + 1) * (m + 1) + nch + nblk;
     // product workspace: rank-space block (sum of ranks <= 2 x 64 per block side when unknown) and level partials
     const int64_t tlen = op ? op->t_len : (int64_t)g->blocks.size() * 64;
     const int64_t nlev = op ? std::max(op->n_active, 1) : std::max(g->L, 1);
