@@ -50,10 +50,10 @@ def cpu_model() -> str:
 KERNEL_SYMBOL = {"rphase": "k_rphase<4>", "qphase": "k_qphase<4>", "final": "k_final"}
 KERNEL_SYMBOL_C64 = {"rphase": "k_rphase_c64<4>", "qphase": "k_qphase_c64<4>", "final": "k_final"}
 COUNTERS = os.path.join(ROOT, "profiles", "product_mid32x32_counters.txt")
-PRODUCT_SOURCES = [os.path.join(ROOT, "paper_2603_10586_amd", "csrc", f) for f in ("k_apply.hip", "op.cpp")]
+PRODUCT_SOURCES = [os.path.join(ROOT, "paper_2603_10586_amd", "csrc", f) for f in ("k_apply.hip", "stream.h", "op.cpp")]
 
 
-def measured_traffic(stage: str):
+def measured_traffic(stage: str, suffix: str = ""):
     """HBM bytes per dispatch of a product kernel from the committed rocprofv3 counter
     summary, or None if the kernel sources changed since those counters were taken."""
     import hashlib
@@ -64,7 +64,7 @@ def measured_traffic(stage: str):
     h = hashlib.sha256(b"".join(open(p, "rb").read() for p in PRODUCT_SOURCES)).hexdigest()[:16]
     if kv.get("source_sha256_16") != h:
         return None
-    v = kv.get(f"k_{stage}.traffic_bytes")
+    v = kv.get(f"k_{stage}{suffix if stage != 'final' else ''}.traffic_bytes")
     return int(float(v)) if v else None
 
 
@@ -175,7 +175,15 @@ def main() -> int:
         for _ in range(5):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes_each_way": src.numel() * 8, "launches": 5}))
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(5):
+            dst.copy_(src)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / 5
+        print(json.dumps({"copy_probe_bytes_each_way": src.numel() * 8, "launches": 10, "ms_per_copy": round(ms, 4),
+                          "read_plus_write_gbs": round(2 * src.numel() * 8 / (ms * 1e-3) / 1e9, 1)}))
         return 0
 
     import paper_2603_10586_amd as q
@@ -243,7 +251,7 @@ def main() -> int:
     dom = max(("rphase", "qphase", "final"), key=lambda k: prof[k]["ms"])
     ach = prof[dom]["bytes"] / (prof[dom]["ms"] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None if args.mixed_ir else measured_traffic(dom),
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom, "_c64" if args.mixed_ir else ""),
                 "algorithmic_bytes": prof[dom]["bytes"],
                 "kernel": KERNEL_SYMBOL_C64[dom] if args.mixed_ir else KERNEL_SYMBOL[dom],
                 "stages_ms": {k: round(prof[k]["ms"], 4) for k in prof},

@@ -249,6 +249,9 @@ typedef struct {
     double  tol;          /* relative residual; converged when both the preconditioned
                              estimate and the true residual ||v - Z_QR x||/||v|| meet it */
     int32_t use_x0;       /* 1: x holds the initial guess on entry; 0: x0 = 0 */
+    double  inner_tol;    /* MIXED_IR: relative tolerance of each correction solve, in (0, 1);
+                             0 = automatic, 0.25 tol ||v|| / ||r|| (one correction reaches tol
+                             unless the factor rounding dominates).  Ignored in FP64 mode. */
 } qrvie_solve_opts;
 
 typedef struct {

@@ -47,7 +47,7 @@ class BlockInfo(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_iter", C.c_int32), ("mode", C.c_int32), ("tol", C.c_double),
-                ("use_x0", C.c_int32)]
+                ("use_x0", C.c_int32), ("inner_tol", C.c_double)]
 
 
 class SolveInfo(C.Structure):

@@ -254,11 +254,12 @@ class Operator:
         return z
 
     def solve(self, v, restart: int = 30, tol: float = 1e-8, max_iter: int = 10000, x0=None,
-              mode: int = L.SOLVE_FP64):
+              mode: int = L.SOLVE_FP64, inner_tol: float = 0.0):
         torch = _torch()
         pv, ld, nrhs = _cols(v, self.geom.ndof)
         x = torch.zeros_like(v) if x0 is None else x0.clone()
-        o = L.SolveOpts(restart=restart, max_iter=max_iter, mode=mode, tol=tol, use_x0=0 if x0 is None else 1)
+        o = L.SolveOpts(restart=restart, max_iter=max_iter, mode=mode, tol=tol, use_x0=0 if x0 is None else 1,
+                        inner_tol=inner_tol)
         infos = (L.SolveInfo * nrhs)()
         self.ctx.order()
         st = self.ctx.check(self.ctx.lib.qrvie_solve(self.ctx.h, self.h, nrhs, pv, ld, C.c_void_p(x.data_ptr()), ld,

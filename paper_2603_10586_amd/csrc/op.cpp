@@ -112,7 +112,7 @@ constexpr int kDirectMaxParticles = 2;   // both sides at most this many particl
 constexpr int kSketchStart = 128;
 constexpr int kMaxSketch = 512;          // widest sketch the CGS2 kernel orthonormalises
 constexpr int kPhaseWaves = 4;           // waves per strip in the product kernels
-constexpr int64_t kAlign = 8;            // panel alignment in complex128 elements (128 B)
+constexpr int64_t kAlign = 16;           // R-panel leading dimension multiple: 128 B in complex64, 256 B in complex128
 
 struct Builder {
     qrvie_op* op;
@@ -643,8 +643,9 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
             const int64_t nJ = (int64_t)b0.cn * kNp;
             int64_t Kp = 0;
             for (size_t b : kv.second) Kp += op->rank[b];
-            // leading dimension padded to 8 complex (128 B) so every wave's 64-row column
-            // segment starts on a cache-line boundary
+            // leading dimension padded to 16 entries so every wave's 64-row column segment
+            // starts on a 128-byte cache-line boundary in the complex128 panels and in
+            // their complex64 copy
             const int64_t ldp = (Kp + kAlign - 1) / kAlign * kAlign;
             const int64_t base = fcur;
             fcur += ldp * nJ;

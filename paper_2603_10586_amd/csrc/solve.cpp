@@ -465,7 +465,8 @@ qrvie_status solve_group_ir(qrvie_ctx* ctx, const qrvie_op* op, int na, const c1
             if (r <= o->tol) { state[i] = 1; continue; }
             if (it >= kMaxRefine || k.iters >= o->max_iter || stalled) { state[i] = 2; continue; }
             CHECK(hip_check(ctx, hipMemsetAsync(k.x, 0, sizeof(c128) * n, s), "correction"));
-            CHECK(G.prepare(i, std::min(0.5, std::max(0.25 * o->tol / r, 1e-14)), o->max_iter));
+            const double eta = o->inner_tol > 0.0 ? o->inner_tol : std::min(0.5, std::max(0.25 * o->tol / r, 1e-14));
+            CHECK(G.prepare(i, eta, o->max_iter));
             k.inf.n_refine++;
             refine.push_back(i);
         }
@@ -680,7 +681,7 @@ qrvie_status qrvie_solve(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const
                          qrvie_c128* x, int64_t ldx, const qrvie_solve_opts* o, qrvie_solve_info* info) {
     CHECK(check_vec_args(ctx, op, nrhs, v, ldv, x, ldx, "solve"));
     if (!o || o->restart < 1 || o->restart > 16384 || o->max_iter < 1 || !(o->tol > 0.0) ||
-        (o->mode != QRVIE_SOLVE_FP64 && o->mode != QRVIE_SOLVE_MIXED_IR)) {
+        (o->mode != QRVIE_SOLVE_FP64 && o->mode != QRVIE_SOLVE_MIXED_IR) || !(o->inner_tol >= 0.0 && o->inner_tol < 1.0)) {
         set_err(ctx, "solve: invalid options");
         return QRVIE_ERR_INVALID_ARG;
     }
