@@ -238,14 +238,22 @@ qrvie_status qrvie_rhs_plane_waves(qrvie_ctx* ctx, const qrvie_geom* g, int32_t 
  *                       factors (FP64 accumulation and Krylov algebra), x += d, until
  *                       ||r|| <= tol ||v||.  Needs an operator built with
  *                       far_prec = QRVIE_PREC_C64; otherwise QRVIE_ERR_INVALID_ARG.
+ * QRVIE_SOLVE_BLOCK     block GMRES: up to 64 right-hand sides at a time share one block
+ *                       Krylov space; every block step applies the operator to the whole
+ *                       block on FP64 matrix cores.  `restart` bounds the basis vectors per
+ *                       cycle (restart / block width block steps); `max_iter` bounds the
+ *                       block steps.  info: iterations = block steps, n_apply = block
+ *                       products, t_apply_s = product time of the whole block.  A
+ *                       numerically rank-deficient block (repeated right-hand sides) is
+ *                       finished column by column in FP64 mode from the block iterate.
  */
-enum { QRVIE_SOLVE_FP64 = 0, QRVIE_SOLVE_MIXED_IR = 1 };
+enum { QRVIE_SOLVE_FP64 = 0, QRVIE_SOLVE_MIXED_IR = 1, QRVIE_SOLVE_BLOCK = 2 };
 
 typedef struct {
     int32_t restart;      /* GMRES(m) restart length, 1..16384 (m >= max_iter: unrestarted, as in §6);
                              the basis takes (m + 1) x n complex128 of device memory */
     int32_t max_iter;     /* total Arnoldi steps per right-hand side */
-    int32_t mode;         /* QRVIE_SOLVE_FP64 or QRVIE_SOLVE_MIXED_IR */
+    int32_t mode;         /* QRVIE_SOLVE_FP64, QRVIE_SOLVE_MIXED_IR or QRVIE_SOLVE_BLOCK */
     double  tol;          /* relative residual; converged when both the preconditioned
                              estimate and the true residual ||v - Z_QR x||/||v|| meet it */
     int32_t use_x0;       /* 1: x holds the initial guess on entry; 0: x0 = 0 */

@@ -43,6 +43,16 @@ struct RStrip {                     // t[tmap[tmap_off + i]] = sum_j A[i + j*ld]
     int32_t x_off;                  // DoF start of the column node
     int64_t tmap_off;
 };
+// One 64-row strip of a column-major panel applied to an RHS-interleaved block of P
+// right-hand sides (element (row e, rhs r) at e * P + r): out rows = A_strip in rows.
+struct MStrip {
+    int64_t a_off;                  // element offset of the strip's first row, column 0
+    int32_t ld, ncols, nrows, pad;
+    int64_t in_off;                 // input row of panel column 0
+    int64_t out_off;                // output row of strip row 0 (when tmap_off < 0)
+    int64_t tmap_off;               // >= 0: strip row i goes to output row tmap[tmap_off + i]
+};
+
 struct QStrip {                     // y[y_off + i] = sum_j A[i + j*ld] t[t_off + j]
     int64_t a_off;
     int32_t ld, ncols, nrows;
@@ -106,6 +116,7 @@ struct qrvie_ctx {
     size_t budget = 0;
     size_t in_use = 0;
     std::string err;
+    void* blas = nullptr;           // rocBLAS handle of the block solver, created on first use
 };
 
 struct qrvie_geom {
@@ -148,6 +159,10 @@ struct qrvie_op {
     int64_t tmap_len = 0;
     qrvie::RStrip* d_rstrips = nullptr;
     qrvie::QStrip* d_qstrips = nullptr;
+    qrvie::MStrip* d_mr = nullptr;            // R, Q and self-block strips for blocks of right-hand sides
+    qrvie::MStrip* d_mq = nullptr;
+    qrvie::MStrip* d_ms = nullptr;            // offsets into d_self and d_pinv (same layout)
+    int64_t n_mr = 0, n_mq = 0, n_ms = 0;
     struct Launch { int level; int64_t begin, count; int waves; };
     std::vector<Launch> rlaunch, qlaunch;
     int32_t n_active = 0;
@@ -169,6 +184,7 @@ bool set_err(qrvie_ctx* ctx, const std::string& msg);
 qrvie_status hip_check(qrvie_ctx* ctx, hipError_t e, const char* what);
 qrvie_status dalloc(qrvie_ctx* ctx, void** p, size_t bytes, const char* what);
 void dfree(qrvie_ctx* ctx, void* p, size_t bytes);
+void blas_release(qrvie_ctx* ctx);
 
 // ---------------------------------------------------------------- launchers
 // assembly (k_assemble.hip)
@@ -241,5 +257,24 @@ void launch_givens(hipStream_t s, int j, c128* hcol, c128* H, int ldh, double* c
 void launch_trisolve(hipStream_t s, int k, const c128* H, int ldh, const c128* gvec, c128* y);
 void launch_gemv_add(hipStream_t s, const c128* V, int64_t ldv, int ncols, const c128* y, c128* x, int64_t n);
 void launch_add(hipStream_t s, const c128* d, int64_t n, c128* x);
+
+// blocks of right-hand sides (k_block.hip); nt = P / 16 tiles of 16 right-hand sides, 1..4
+constexpr int kMaxBlockRhs = 64;
+void launch_strip_mfma(hipStream_t s, int nt, const MStrip* st, int64_t n, const c128* fac, const c128* in,
+                       c128* out, const int64_t* tmap);
+void launch_block_combine(hipStream_t s, int nt, int64_t n, const c128* ylev, int nlev, const c128* yself,
+                          const c128* V, c128* out);
+void launch_gather_block(hipStream_t s, int nt, int32_t N, const int32_t* i2c, const c128* src, int64_t ld,
+                         int ncols, c128* blk);
+void launch_scatter_block(hipStream_t s, int nt, int32_t N, const int32_t* i2c, const c128* blk, c128* dst,
+                          int64_t ld, int ncols);
+void launch_gram_store(hipStream_t s, int k, int p, const c128* C, int64_t ldc, c128* G, int64_t ldg);
+void launch_cholesky(hipStream_t s, int p, const c128* S, int64_t lds, double rel, c128* out, int64_t ldo, int* flag);
+void launch_trmm_upper(hipStream_t s, int p, const c128* A, int64_t lda, const c128* B, int64_t ldb, c128* C,
+                       int64_t ldc, const int* flag);
+void launch_ls_apply(hipStream_t s, int j0, int j1, int p, const c128* Y, const c128* T, c128* C, int64_t ldc,
+                     int ncols);
+void launch_ls_factor(hipStream_t s, int k, int p, c128* C, int64_t ldc, c128* Yk, c128* Tk);
+void launch_col_norms(hipStream_t s, int rows, const c128* C, int64_t ldc, int ncols, double* out);
 
 }  // namespace qrvie

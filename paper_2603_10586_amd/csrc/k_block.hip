@@ -1,0 +1,479 @@
+// Blocks of right-hand sides: the compressed product Z_QR X and the preconditioner for
+// up to 64 right-hand sides at once (§5.2 products, §4 preconditioner), on FP64 MFMA.
+//
+// With P right-hand sides every factor entry meets P complex multiply-adds, so the product
+// turns from HBM-bound (one right-hand side) into a sequence of small dense GEMMs: each
+// 64-row strip of a column-major panel (R panel, Q panel, self block or its inverse) is
+// multiplied into an RHS-interleaved block (element (row e, rhs r) at e * P + r).  A
+// workgroup takes one strip; each of its four waves owns 16 rows and all P columns, as
+// P/16 tiles of v_mfma_f64_16x16x4f64.  A complex product is four real MFMAs:
+// re += a.re b.re - a.im b.im, im += a.re b.im + a.im b.re.  The factor stream is read
+// once per product; the interleaved input rows are shared by the strip's waves through
+// the caches.  Accumulation is FP64 and the order is fixed, so results are reproducible.
+#include "stream.h"
+
+namespace qrvie {
+
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// Operand layout of the 16x16x4 FP64 MFMA on gfx950 (checked on the device):
+//   A (16 x 4): lane l holds A[l % 16][l / 16];   B (4 x 16): lane l holds B[l / 16][l % 16];
+//   D (16 x 16): lane l, slot i holds D[l / 16 + 4 i][l % 16].
+__device__ __forceinline__ void cmfma(v4d& re, v4d& im, c128 a, c128 b) {
+    re = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, re, 0, 0, 0);
+    re = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, re, 0, 0, 0);
+    im = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, im, 0, 0, 0);
+    im = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, im, 0, 0, 0);
+}
+
+template <int NT>
+__global__ void __launch_bounds__(256) k_strip_mfma(const MStrip* __restrict__ strips, const c128* __restrict__ fac,
+                                                    const c128* __restrict__ in, c128* __restrict__ out,
+                                                    const int64_t* __restrict__ tmap) {
+    constexpr int P = 16 * NT;
+    constexpr int U = 2;                                   // 4-column steps per batch
+    const MStrip s = strips[blockIdx.x];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int r0 = 16 * w;
+    if (r0 >= s.nrows) return;
+    const int rl = lane & 15, kq = lane >> 4;
+    const c128* A = fac + s.a_off + min(r0 + rl, s.nrows - 1);
+    const c128* X = in + s.in_off * P + rl;
+    v4d re[NT], im[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) re[t] = im[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    const int nsteps = s.ncols / 4;
+    int c = 0;
+    for (; c + U <= nsteps; c += U) {
+        c128 a[U], b[U][NT];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t col = 4 * (c + u) + kq;
+            a[u] = load_stream(A + col * s.ld);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) b[u][t] = X[col * P + 16 * t];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) cmfma(re[t], im[t], a[u], b[u][t]);
+    }
+    for (; 4 * c < s.ncols; ++c) {                      // remaining steps, the last possibly partial
+        const int64_t col = 4 * c + kq;
+        const bool ok = col < s.ncols;
+        const c128 z = make_double2(0.0, 0.0);
+        const c128 a = ok ? A[col * s.ld] : z;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) cmfma(re[t], im[t], a, ok ? X[col * P + 16 * t] : z);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int row = r0 + kq + 4 * i;
+        if (row >= s.nrows) continue;
+        const int64_t orow = s.tmap_off >= 0 ? tmap[s.tmap_off + row] : s.out_off + row;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) out[orow * P + 16 * t + rl] = make_double2(re[t][i], im[t][i]);
+    }
+}
+
+// out = (V ? V - y : y), y = yself + sum_l ylev[l]; all n x P interleaved
+template <int NT>
+__global__ void k_block_combine(int64_t n, const c128* __restrict__ ylev, int nlev, const c128* __restrict__ yself,
+                                const c128* __restrict__ V, c128* __restrict__ out) {
+    constexpr int P = 16 * NT;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * P) return;
+    c128 y = yself[e];
+    for (int l = 0; l < nlev; ++l) {
+        const c128 a = ylev[(int64_t)l * n * P + e];
+        y = make_double2(y.x + a.x, y.y + a.y);
+    }
+    if (V) y = make_double2(V[e].x - y.x, V[e].y - y.y);
+    out[e] = y;
+}
+
+// blk[(p*144 + d) * P + r] = src[r * ld + c * 144 + d], c = i2c ? i2c[p] : p (zero for r >= ncols)
+template <int NT>
+__global__ void k_gather_block(int32_t N, const int32_t* __restrict__ i2c, const c128* __restrict__ src, int64_t ld,
+                               int ncols, c128* __restrict__ blk) {
+    constexpr int P = 16 * NT;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // internal DoF
+    if (e >= (int64_t)N * kNp) return;
+    const int64_t p = e / kNp, d = e % kNp;
+    const int64_t ce = (i2c ? (int64_t)i2c[p] : p) * kNp + d;
+#pragma unroll 4
+    for (int r = 0; r < P; ++r) blk[e * P + r] = r < ncols ? src[r * ld + ce] : make_double2(0.0, 0.0);
+}
+
+template <int NT>
+__global__ void k_scatter_block(int32_t N, const int32_t* __restrict__ i2c, const c128* __restrict__ blk,
+                                c128* __restrict__ dst, int64_t ld, int ncols) {
+    constexpr int P = 16 * NT;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)N * kNp) return;
+    const int64_t p = e / kNp, d = e % kNp;
+    const int64_t ce = (i2c ? (int64_t)i2c[p] : p) * kNp + d;
+    for (int r = 0; r < ncols; ++r) dst[r * ld + ce] = blk[e * P + r];
+}
+
+// ---------------------------------------------------------------- block Arnoldi helpers
+// Gram matrix of the block basis: G[0:(k+1)p, kp:(k+1)p] = C (the new block column, from
+// V^H V_k) and the mirrored block row G[kp:(k+1)p, 0:kp] = C[0:kp, :]^H.
+__global__ void k_gram_store(int k, int p, const c128* __restrict__ C, int64_t ldc, c128* __restrict__ G,
+                             int64_t ldg) {
+    const int64_t rows = (int64_t)(k + 1) * p;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= rows * p) return;
+    const int64_t i = e % rows, j = e / rows;
+    const c128 v = C[i + j * ldc];
+    G[i + ((int64_t)k * p + j) * ldg] = v;
+    if (i < (int64_t)k * p) G[(int64_t)k * p + j + i * ldg] = make_double2(v.x, -v.y);
+}
+
+// Cholesky S = R^H R of a Hermitian p x p matrix (p <= 64, column-major, upper triangle
+// used), one workgroup.  R (upper, zeros below) is written to out; flag[0] = 1 when a pivot
+// falls below rel * (largest diagonal entry of S), i.e. the block is numerically rank
+// deficient, and the factor is then not usable.
+__global__ void __launch_bounds__(256) k_cholesky(int p, const c128* __restrict__ S, int64_t lds, double rel,
+                                                  c128* __restrict__ out, int64_t ldo, int* flag) {
+    __shared__ c128 A[64][65];
+    __shared__ double dmax;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < p * p; e += blockDim.x) {
+        const int i = e % p, j = e / p;
+        A[i][j] = i <= j ? S[i + j * lds] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double m = 0.0;
+        for (int j = 0; j < p; ++j) m = fmax(m, A[j][j].x);
+        dmax = m;
+        flag[0] = 0;
+    }
+    __syncthreads();
+    for (int j = 0; j < p; ++j) {
+        const double d = A[j][j].x;
+        const bool bad = !(d > rel * dmax);
+        const double r = bad ? 1.0 : sqrt(d);
+        __syncthreads();
+        if (tid == 0) {
+            if (bad) flag[0] = 1;
+            A[j][j] = make_double2(r, 0.0);
+        }
+        for (int c = j + 1 + tid; c < p; c += blockDim.x) A[j][c] = make_double2(A[j][c].x / r, A[j][c].y / r);
+        __syncthreads();
+        // trailing update: A[i][c] -= conj(R[j][i]) R[j][c], j < i <= c
+        for (int e = tid; e < p * p; e += blockDim.x) {
+            const int i = e % p, c = e / p;
+            if (i > j && i <= c) {
+                const c128 a = A[j][i], b = A[j][c];
+                A[i][c] = make_double2(A[i][c].x - (a.x * b.x + a.y * b.y), A[i][c].y - (a.x * b.y - a.y * b.x));
+            }
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < p * p; e += blockDim.x) {
+        const int i = e % p, j = e / p;
+        out[i + j * ldo] = i <= j ? A[i][j] : make_double2(0.0, 0.0);
+    }
+}
+
+// C = A B for upper-triangular p x p A, B (column-major); C may not alias A or B.  C = 0
+// when either Cholesky flag is set (a rank-deficient block contributes nothing).
+__global__ void k_trmm_upper(int p, const c128* __restrict__ A, int64_t lda, const c128* __restrict__ B,
+                             int64_t ldb, c128* __restrict__ C, int64_t ldc, const int* __restrict__ flag) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= p * p) return;
+    const int i = e % p, j = e / p;
+    if (flag && (flag[0] || flag[1])) {
+        C[i + (int64_t)j * ldc] = make_double2(0.0, 0.0);
+        return;
+    }
+    double re = 0.0, im = 0.0;
+    for (int l = i; l <= j; ++l) {
+        const c128 a = A[i + (int64_t)l * lda], b = B[l + (int64_t)j * ldb];
+        re += a.x * b.x - a.y * b.y;
+        im += a.x * b.y + a.y * b.x;
+    }
+    C[i + (int64_t)j * ldc] = make_double2(re, im);
+}
+
+// Least squares of block GMRES.  The block Hessenberg matrix is reduced to upper triangular
+// form by one compact-WY block reflector per block column: Q_j = I - Y_j T_j Y_j^H acting on
+// rows [jp, jp + 2p) (Y_j: 2p x p, unit lower trapezoidal; T_j: p x p upper triangular).
+//
+// Apply Q_j^H for j in [j0, j1), in order, to every column of C (rows indexed from 0, ld
+// ldc): one workgroup per column, the 2p-row segment staged in LDS.
+__global__ void __launch_bounds__(256) k_ls_apply(int j0, int j1, int p, const c128* __restrict__ Y,
+                                                  const c128* __restrict__ T, c128* __restrict__ C, int64_t ldc) {
+    __shared__ c128 seg[128];
+    __shared__ c128 w[64], w2[64];
+    __shared__ c128 part[256];
+    const int tid = threadIdx.x;
+    c128* col = C + (int64_t)blockIdx.x * ldc;
+    const int m = 2 * p;
+    for (int j = j0; j < j1; ++j) {
+        const c128* Yj = Y + (int64_t)j * m * p;
+        const c128* Tj = T + (int64_t)j * p * p;
+        c128* sg = col + (int64_t)j * p;
+        for (int e = tid; e < m; e += blockDim.x) seg[e] = sg[e];
+        __syncthreads();
+        // w = Y_j^H seg: 4 threads per entry
+        {
+            const int i = tid >> 2, q = tid & 3;
+            double re = 0.0, im = 0.0;
+            if (i < p)
+                for (int e = q; e < m; e += 4) {
+                    const c128 y = Yj[e + (int64_t)i * m], x = seg[e];
+                    re += y.x * x.x + y.y * x.y;
+                    im += y.x * x.y - y.y * x.x;
+                }
+            part[tid] = make_double2(re, im);
+        }
+        __syncthreads();
+        if (tid < p) {
+            const c128 a = part[4 * tid], b = part[4 * tid + 1], c = part[4 * tid + 2], d = part[4 * tid + 3];
+            w[tid] = make_double2((a.x + b.x) + (c.x + d.x), (a.y + b.y) + (c.y + d.y));
+        }
+        __syncthreads();
+        // w2 = T_j^H w: w2[i] = sum_{l <= i} conj(T[l][i]) w[l]
+        if (tid < p) {
+            double re = 0.0, im = 0.0;
+            for (int l = 0; l <= tid; ++l) {
+                const c128 t = Tj[l + (int64_t)tid * p], x = w[l];
+                re += t.x * x.x + t.y * x.y;
+                im += t.x * x.y - t.y * x.x;
+            }
+            w2[tid] = make_double2(re, im);
+        }
+        __syncthreads();
+        // seg -= Y_j w2: 2 threads per row
+        {
+            const int e = tid >> 1, q = tid & 1;
+            double re = 0.0, im = 0.0;
+            if (e < m)
+                for (int i = q; i < p; i += 2) {
+                    const c128 y = Yj[e + (int64_t)i * m], x = w2[i];
+                    re += y.x * x.x - y.y * x.y;
+                    im += y.x * x.y + y.y * x.x;
+                }
+            part[tid] = make_double2(re, im);
+        }
+        __syncthreads();
+        for (int e = tid; e < m; e += blockDim.x) {
+            const c128 a = part[2 * e], b = part[2 * e + 1];
+            sg[e] = make_double2(seg[e].x - (a.x + b.x), seg[e].y - (a.y + b.y));
+        }
+        __syncthreads();
+    }
+}
+
+// Householder QR of the 2p x p block M = C[kp : kp + 2p, 0 : p] (ld ldc), one workgroup:
+// M becomes [R_kk; 0], Y_k and T_k are written for k_ls_apply.  Reflector i maps
+// (alpha, x) to (beta, 0) with real beta = -sign(Re alpha) ||(alpha, x)||,
+// tau = (beta - alpha) / beta, v = (1, x / (alpha - beta)); H_i = I - tau v v^H and the
+// block is reduced by H_i^H.  T follows the forward column-wise recurrence
+// T[0:i, i] = -tau_i T[0:i, 0:i] (Y[:, 0:i]^H v_i), T[i][i] = tau_i.
+__global__ void __launch_bounds__(256) k_ls_factor(int k, int p, c128* __restrict__ C, int64_t ldc,
+                                                   c128* __restrict__ Yk, c128* __restrict__ Tk) {
+    __shared__ c128 M[128][64];
+    __shared__ c128 tau_s[64];
+    __shared__ c128 part[256];
+    __shared__ c128 z[64];
+    __shared__ double red[256];
+    __shared__ c128 beta_s, scale_s;
+    const int tid = threadIdx.x;
+    const int m = 2 * p;
+    c128* base = C + (int64_t)k * p;
+    for (int e = tid; e < m * p; e += blockDim.x) {
+        const int r = e % m, c = e / m;
+        M[r][c] = base[r + (int64_t)c * ldc];
+    }
+    __syncthreads();
+    for (int i = 0; i < p; ++i) {
+        // norm of x = M[i+1:m, i]
+        double s = 0.0;
+        for (int r = i + 1 + tid; r < m; r += blockDim.x) s += M[r][i].x * M[r][i].x + M[r][i].y * M[r][i].y;
+        red[tid] = s;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (tid < o) red[tid] += red[tid + o];
+            __syncthreads();
+        }
+        if (tid == 0) {
+            const c128 alpha = M[i][i];
+            const double xn2 = red[0];
+            if (xn2 == 0.0 && alpha.y == 0.0) {
+                tau_s[i] = make_double2(0.0, 0.0);
+                beta_s = alpha;
+                scale_s = make_double2(0.0, 0.0);
+            } else {
+                const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2);
+                const double beta = alpha.x >= 0.0 ? -nrm : nrm;
+                tau_s[i] = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+                const double dr = alpha.x - beta, di = alpha.y, den = dr * dr + di * di;
+                scale_s = make_double2(dr / den, -di / den);                 // 1 / (alpha - beta)
+                beta_s = make_double2(beta, 0.0);
+            }
+        }
+        __syncthreads();
+        for (int r = i + 1 + tid; r < m; r += blockDim.x) {
+            const c128 x = M[r][i], sc = scale_s;
+            M[r][i] = make_double2(x.x * sc.x - x.y * sc.y, x.x * sc.y + x.y * sc.x);
+        }
+        if (tid == 0) M[i][i] = beta_s;
+        __syncthreads();
+        // apply H_i^H = I - conj(tau) v v^H to columns c > i; v = (1, M[i+1:m, i])
+        {
+            const int c = i + 1 + (tid >> 2), q = tid & 3;
+            double re = 0.0, im = 0.0;
+            if (c < p)
+                for (int r = i + q; r < m; r += 4) {
+                    const c128 v = r == i ? make_double2(1.0, 0.0) : M[r][i], x = M[r][c];
+                    re += v.x * x.x + v.y * x.y;
+                    im += v.x * x.y - v.y * x.x;
+                }
+            part[tid] = make_double2(re, im);
+        }
+        __syncthreads();
+        {
+            const int c = i + 1 + (tid >> 2), q = tid & 3;
+            const c128 ta = tau_s[i];
+            if (c < p) {
+                const c128 a = part[tid & ~3], b = part[(tid & ~3) + 1], cc = part[(tid & ~3) + 2],
+                           d = part[(tid & ~3) + 3];
+                const c128 sv = make_double2((a.x + b.x) + (cc.x + d.x), (a.y + b.y) + (cc.y + d.y));
+                // f = conj(tau) * sv
+                const c128 f = make_double2(ta.x * sv.x + ta.y * sv.y, ta.x * sv.y - ta.y * sv.x);
+                for (int r = i + q; r < m; r += 4) {
+                    const c128 v = r == i ? make_double2(1.0, 0.0) : M[r][i];
+                    M[r][c] = make_double2(M[r][c].x - (v.x * f.x - v.y * f.y), M[r][c].y - (v.x * f.y + v.y * f.x));
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // Y_k (unit lower trapezoidal) and R_kk back into C (zeros below the diagonal)
+    for (int e = tid; e < m * p; e += blockDim.x) {
+        const int r = e % m, c = e / m;
+        Yk[r + (int64_t)c * m] = r < c ? make_double2(0.0, 0.0) : (r == c ? make_double2(1.0, 0.0) : M[r][c]);
+        base[r + (int64_t)c * ldc] = r <= c ? M[r][c] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    // T_k, column by column
+    for (int i = 0; i < p; ++i) {
+        // z[l] = Y[:, l]^H v_i for l < i (v_i = Y[:, i], zero above row i)
+        {
+            const int l = tid >> 2, q = tid & 3;
+            double re = 0.0, im = 0.0;
+            if (l < i)
+                for (int r = i + q; r < m; r += 4) {
+                    const c128 a = r == l ? make_double2(1.0, 0.0) : M[r][l];
+                    const c128 v = r == i ? make_double2(1.0, 0.0) : M[r][i];
+                    re += a.x * v.x + a.y * v.y;
+                    im += a.x * v.y - a.y * v.x;
+                }
+            part[tid] = make_double2(re, im);
+        }
+        __syncthreads();
+        if (tid < i) {
+            const c128 a = part[4 * tid], b = part[4 * tid + 1], cc = part[4 * tid + 2], d = part[4 * tid + 3];
+            z[tid] = make_double2((a.x + b.x) + (cc.x + d.x), (a.y + b.y) + (cc.y + d.y));
+        }
+        __syncthreads();
+        // T[0:i, i] = -tau_i T[0:i, 0:i] z
+        if (tid < p) {
+            c128 out = make_double2(0.0, 0.0);
+            if (tid < i) {
+                double re = 0.0, im = 0.0;
+                for (int l = tid; l < i; ++l) {
+                    const c128 t = Tk[tid + (int64_t)l * p], x = z[l];
+                    re += t.x * x.x - t.y * x.y;
+                    im += t.x * x.y + t.y * x.x;
+                }
+                const c128 ta = tau_s[i];
+                out = make_double2(-(ta.x * re - ta.y * im), -(ta.x * im + ta.y * re));
+            } else if (tid == i) {
+                out = tau_s[i];
+            }
+            Tk[tid + (int64_t)i * p] = out;
+        }
+        __syncthreads();
+    }
+}
+
+// out[c] = ||C[0:rows, c]|| for c < ncols
+__global__ void __launch_bounds__(256) k_col_norms(int rows, const c128* __restrict__ C, int64_t ldc, double* out) {
+    __shared__ double red[256];
+    const c128* col = C + (int64_t)blockIdx.x * ldc;
+    double s = 0.0;
+    for (int r = threadIdx.x; r < rows; r += blockDim.x) s += col[r].x * col[r].x + col[r].y * col[r].y;
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = sqrt(red[0]);
+}
+
+}  // namespace
+
+void launch_gram_store(hipStream_t s, int k, int p, const c128* C, int64_t ldc, c128* G, int64_t ldg) {
+    const int64_t tot = (int64_t)(k + 1) * p * p;
+    hipLaunchKernelGGL(k_gram_store, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, k, p, C, ldc, G, ldg);
+}
+void launch_cholesky(hipStream_t s, int p, const c128* S, int64_t lds, double rel, c128* out, int64_t ldo, int* flag) {
+    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(256), 0, s, p, S, lds, rel, out, ldo, flag);
+}
+void launch_trmm_upper(hipStream_t s, int p, const c128* A, int64_t lda, const c128* B, int64_t ldb, c128* C,
+                       int64_t ldc, const int* flag) {
+    hipLaunchKernelGGL(k_trmm_upper, dim3((p * p + 255) / 256), dim3(256), 0, s, p, A, lda, B, ldb, C, ldc, flag);
+}
+void launch_ls_apply(hipStream_t s, int j0, int j1, int p, const c128* Y, const c128* T, c128* C, int64_t ldc,
+                     int ncols) {
+    if (j1 <= j0 || ncols <= 0) return;
+    hipLaunchKernelGGL(k_ls_apply, dim3(ncols), dim3(256), 0, s, j0, j1, p, Y, T, C, ldc);
+}
+void launch_ls_factor(hipStream_t s, int k, int p, c128* C, int64_t ldc, c128* Yk, c128* Tk) {
+    hipLaunchKernelGGL(k_ls_factor, dim3(1), dim3(256), 0, s, k, p, C, ldc, Yk, Tk);
+}
+void launch_col_norms(hipStream_t s, int rows, const c128* C, int64_t ldc, int ncols, double* out) {
+    hipLaunchKernelGGL(k_col_norms, dim3(ncols), dim3(256), 0, s, rows, C, ldc, out);
+}
+
+#define QRVIE_NT_SWITCH(nt, KERNEL, ...)                                              \
+    switch (nt) {                                                                      \
+        case 1: hipLaunchKernelGGL(KERNEL<1>, __VA_ARGS__); break;                     \
+        case 2: hipLaunchKernelGGL(KERNEL<2>, __VA_ARGS__); break;                     \
+        case 3: hipLaunchKernelGGL(KERNEL<3>, __VA_ARGS__); break;                     \
+        default: hipLaunchKernelGGL(KERNEL<4>, __VA_ARGS__); break;                    \
+    }
+
+void launch_strip_mfma(hipStream_t s, int nt, const MStrip* st, int64_t n, const c128* fac, const c128* in,
+                       c128* out, const int64_t* tmap) {
+    if (n <= 0) return;
+    QRVIE_NT_SWITCH(nt, k_strip_mfma, dim3((unsigned)n), dim3(256), 0, s, st, fac, in, out, tmap);
+}
+void launch_block_combine(hipStream_t s, int nt, int64_t n, const c128* ylev, int nlev, const c128* yself,
+                          const c128* V, c128* out) {
+    const int64_t tot = n * 16 * nt;
+    QRVIE_NT_SWITCH(nt, k_block_combine, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, ylev, nlev, yself, V,
+                    out);
+}
+void launch_gather_block(hipStream_t s, int nt, int32_t N, const int32_t* i2c, const c128* src, int64_t ld,
+                         int ncols, c128* blk) {
+    const int64_t tot = (int64_t)N * kNp;
+    QRVIE_NT_SWITCH(nt, k_gather_block, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, N, i2c, src, ld, ncols,
+                    blk);
+}
+void launch_scatter_block(hipStream_t s, int nt, int32_t N, const int32_t* i2c, const c128* blk, c128* dst,
+                          int64_t ld, int ncols) {
+    const int64_t tot = (int64_t)N * kNp;
+    QRVIE_NT_SWITCH(nt, k_scatter_block, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, N, i2c, blk, dst, ld,
+                    ncols);
+}
+
+}  // namespace qrvie

@@ -682,6 +682,24 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
     op->t_len = tcur;
     op->tmap_len = (int64_t)tmap.size();
 
+    // The same strips for blocks of right-hand sides, plus three strips per particle over
+    // its self block (and, with the same offsets, its inverse).
+    std::vector<MStrip> mr, mq, ms;
+    mr.reserve(rstr.size());
+    mq.reserve(qstr.size());
+    for (const RStrip& r : rstr) mr.push_back(MStrip{r.a_off, r.ld, r.ncols, r.nrows, 0, r.x_off, 0, r.tmap_off});
+    for (const QStrip& q : qstr) mq.push_back(MStrip{q.a_off, q.ld, q.ncols, q.nrows, 0, q.t_off, q.y_off, -1});
+    for (int32_t p = 0; p < g->N; ++p)
+        for (int r0 = 0; r0 < kNp; r0 += kStrip)
+            ms.push_back(MStrip{(int64_t)g->ptype[p] * kNp * kNp + r0, kNp, kNp, std::min(kStrip, kNp - r0), 0,
+                                (int64_t)p * kNp, (int64_t)p * kNp + r0, -1});
+    op->n_mr = (int64_t)mr.size();
+    op->n_mq = (int64_t)mq.size();
+    op->n_ms = (int64_t)ms.size();
+    keep((void**)&op->d_mr, sizeof(MStrip) * std::max<size_t>(mr.size(), 1), "block R strips");
+    keep((void**)&op->d_mq, sizeof(MStrip) * std::max<size_t>(mq.size(), 1), "block Q strips");
+    keep((void**)&op->d_ms, sizeof(MStrip) * std::max<size_t>(ms.size(), 1), "block self strips");
+
     keep((void**)&op->d_fac, sizeof(c128) * (size_t)std::max<int64_t>(fcur, 1), "factor panels");
     keep((void**)&op->d_tmap, sizeof(int64_t) * std::max<size_t>(tmap.size(), 1), "rank map");
     keep((void**)&op->d_rstrips, sizeof(RStrip) * std::max<size_t>(rstr.size(), 1), "R strips");
@@ -693,6 +711,9 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
     if (!tmap.empty()) (void)hipMemcpyAsync(op->d_tmap, tmap.data(), sizeof(int64_t) * tmap.size(), hipMemcpyHostToDevice, s);
     if (!rstr.empty()) (void)hipMemcpyAsync(op->d_rstrips, rstr.data(), sizeof(RStrip) * rstr.size(), hipMemcpyHostToDevice, s);
     if (!qstr.empty()) (void)hipMemcpyAsync(op->d_qstrips, qstr.data(), sizeof(QStrip) * qstr.size(), hipMemcpyHostToDevice, s);
+    if (st == QRVIE_OK && !mr.empty()) (void)hipMemcpyAsync(op->d_mr, mr.data(), sizeof(MStrip) * mr.size(), hipMemcpyHostToDevice, s);
+    if (st == QRVIE_OK && !mq.empty()) (void)hipMemcpyAsync(op->d_mq, mq.data(), sizeof(MStrip) * mq.size(), hipMemcpyHostToDevice, s);
+    if (st == QRVIE_OK && !ms.empty()) (void)hipMemcpyAsync(op->d_ms, ms.data(), sizeof(MStrip) * ms.size(), hipMemcpyHostToDevice, s);
     st = hip_check(ctx, hipStreamSynchronize(s), "upload layout");   // the host vectors die at return
     if (st != QRVIE_OK) {
         for (auto& sg : bld.segments) dfree(ctx, sg.first, sg.second);

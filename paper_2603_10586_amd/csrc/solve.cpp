@@ -19,40 +19,13 @@
 #include <cstring>
 #include <vector>
 
-#include "internal.h"
+#include "work.h"
 
 using namespace qrvie;
 
 namespace {
 
 constexpr int kGroup = 8;   // right-hand sides advanced together
-
-double now_s() {
-    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
-}
-
-struct Work {
-    qrvie_ctx* ctx;
-    std::vector<std::pair<void*, size_t>> bufs;
-    explicit Work(qrvie_ctx* c) : ctx(c) {}
-    ~Work() {
-        (void)hipStreamSynchronize(ctx->stream);
-        for (auto& b : bufs) dfree(ctx, b.first, b.second);
-    }
-    template <class T>
-    qrvie_status alloc(T** p, size_t count, const char* what) {
-        *p = nullptr;
-        qrvie_status st = dalloc(ctx, (void**)p, sizeof(T) * std::max<size_t>(count, 1), what);
-        if (st == QRVIE_OK) bufs.push_back({(void*)*p, sizeof(T) * std::max<size_t>(count, 1)});
-        return st;
-    }
-};
-
-#define CHECK(x)                       \
-    do {                               \
-        qrvie_status _s = (x);         \
-        if (_s != QRVIE_OK) return _s; \
-    } while (0)
 
 // Rank-space and level-partial buffers of the product, owned by the caller of a product
 // so that one operator can be applied from several streams at once.
@@ -501,6 +474,23 @@ qrvie_status qrvie_apply_prec(qrvie_ctx* ctx, const qrvie_op* op, int32_t prec, 
     const int64_t n = op->g->ndof();
     hipStream_t s = ctx->stream;
     Work w(ctx);
+    if (!lo && nrhs >= 16) {
+        // blocks of up to 64 right-hand sides on the MFMA kernels
+        BlockWork bw;
+        CHECK(bw.init(w, op));
+        c128 *X, *Y;
+        CHECK(w.alloc(&X, (size_t)n * kMaxBlockRhs, "apply block"));
+        CHECK(w.alloc(&Y, (size_t)n * kMaxBlockRhs, "apply block"));
+        for (int r0 = 0; r0 < nrhs; r0 += kMaxBlockRhs) {
+            const int cnt = std::min(kMaxBlockRhs, nrhs - r0);
+            const int nt = (cnt + 15) / 16;
+            launch_gather_block(s, nt, op->g->N, op->g->d_i2c, (const c128*)x + (int64_t)r0 * ldx, ldx, cnt, X);
+            block_product(op, s, bw, nt, X, nullptr, Y, nullptr);
+            launch_scatter_block(s, nt, op->g->N, op->g->d_i2c, Y, (c128*)y + (int64_t)r0 * ldy, ldy, cnt);
+        }
+        CHECK(hip_check(ctx, hipGetLastError(), "apply launch"));
+        return hip_check(ctx, hipStreamSynchronize(s), "apply");
+    }
     ProdWork pw;
     const int nrmax = nrhs > 1 ? kGroup : 1;
     CHECK(pw.init(w, op, nrmax));
@@ -681,7 +671,8 @@ qrvie_status qrvie_solve(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const
                          qrvie_c128* x, int64_t ldx, const qrvie_solve_opts* o, qrvie_solve_info* info) {
     CHECK(check_vec_args(ctx, op, nrhs, v, ldv, x, ldx, "solve"));
     if (!o || o->restart < 1 || o->restart > 16384 || o->max_iter < 1 || !(o->tol > 0.0) ||
-        (o->mode != QRVIE_SOLVE_FP64 && o->mode != QRVIE_SOLVE_MIXED_IR) || !(o->inner_tol >= 0.0 && o->inner_tol < 1.0)) {
+        (o->mode != QRVIE_SOLVE_FP64 && o->mode != QRVIE_SOLVE_MIXED_IR && o->mode != QRVIE_SOLVE_BLOCK) ||
+        !(o->inner_tol >= 0.0 && o->inner_tol < 1.0)) {
         set_err(ctx, "solve: invalid options");
         return QRVIE_ERR_INVALID_ARG;
     }
@@ -690,6 +681,27 @@ qrvie_status qrvie_solve(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const
         return QRVIE_ERR_INVALID_ARG;
     }
     qrvie_status overall = QRVIE_OK;
+    if (o->mode == QRVIE_SOLVE_BLOCK) {
+        for (int r0 = 0; r0 < nrhs; r0 += kMaxBlockRhs) {
+            const int cnt = std::min(kMaxBlockRhs, nrhs - r0);
+            bool broke = false;
+            qrvie_solve_info* inf = info ? info + r0 : nullptr;
+            qrvie_status st = solve_block(ctx, op, cnt, (const c128*)v + (int64_t)r0 * ldv, ldv,
+                                          (c128*)x + (int64_t)r0 * ldx, ldx, o, inf, &broke);
+            if (broke) {
+                // rank-deficient block (e.g. repeated right-hand sides): finish each column with
+                // the single-vector solver, starting from the block iterate
+                qrvie_solve_opts o1 = *o;
+                o1.mode = QRVIE_SOLVE_FP64;
+                o1.use_x0 = 1;
+                st = qrvie_solve(ctx, op, cnt, (const qrvie_c128*)((const c128*)v + (int64_t)r0 * ldv), ldv,
+                                 (qrvie_c128*)((c128*)x + (int64_t)r0 * ldx), ldx, &o1, inf);
+            }
+            if (st == QRVIE_NOT_CONVERGED) overall = st;
+            else if (st != QRVIE_OK) return st;
+        }
+        return overall;
+    }
     for (int r0 = 0; r0 < nrhs; r0 += kGroup) {
         const int cnt = std::min(kGroup, nrhs - r0);
         std::vector<const c128*> vv(cnt);

@@ -1,0 +1,72 @@
+// Host-side helpers shared by the solver drivers: a device workspace arena charged to the
+// context's HBM budget, and the block product over up to 64 interleaved right-hand sides.
+#pragma once
+
+#include <algorithm>
+#include <chrono>
+#include <utility>
+#include <vector>
+
+#include "internal.h"
+
+namespace qrvie {
+
+#define CHECK(x)                       \
+    do {                               \
+        qrvie_status _s = (x);         \
+        if (_s != QRVIE_OK) return _s; \
+    } while (0)
+
+inline double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Work {
+    qrvie_ctx* ctx;
+    std::vector<std::pair<void*, size_t>> bufs;
+    explicit Work(qrvie_ctx* c) : ctx(c) {}
+    ~Work() {
+        (void)hipStreamSynchronize(ctx->stream);
+        for (auto& b : bufs) dfree(ctx, b.first, b.second);
+    }
+    template <class T>
+    qrvie_status alloc(T** p, size_t count, const char* what) {
+        *p = nullptr;
+        qrvie_status st = dalloc(ctx, (void**)p, sizeof(T) * std::max<size_t>(count, 1), what);
+        if (st == QRVIE_OK) bufs.push_back({(void*)*p, sizeof(T) * std::max<size_t>(count, 1)});
+        return st;
+    }
+};
+
+
+// Workspaces of the block product (up to kMaxBlockRhs interleaved right-hand sides).
+struct BlockWork {
+    c128 *T = nullptr, *Ylev = nullptr, *Yself = nullptr;
+    qrvie_status init(Work& w, const qrvie_op* op) {
+        const int64_t n = op->g->ndof(), P = kMaxBlockRhs;
+        CHECK(w.alloc(&T, (size_t)std::max<int64_t>(op->t_len, 1) * P, "block rank space"));
+        CHECK(w.alloc(&Ylev, (size_t)std::max(op->n_active, 1) * n * P, "block level partials"));
+        return w.alloc(&Yself, (size_t)n * P, "block self product");
+    }
+};
+
+// out = V - Z X (or Z X when V is null), Z_out = Z_D^-1 out (optional); X, V, out, Z_out are
+// n x P interleaved blocks, P = 16 nt, internal order (FP64 MFMA kernels).
+inline void block_product(const qrvie_op* op, hipStream_t s, const BlockWork& bw, int nt, const c128* X, const c128* V,
+                   c128* out, c128* zout) {
+    const int64_t n = op->g->ndof();
+    launch_strip_mfma(s, nt, op->d_mr, op->n_mr, op->d_fac, X, bw.T, op->d_tmap);
+    launch_strip_mfma(s, nt, op->d_mq, op->n_mq, op->d_fac, bw.T, bw.Ylev, nullptr);
+    launch_strip_mfma(s, nt, op->d_ms, op->n_ms, op->d_self, X, bw.Yself, nullptr);
+    launch_block_combine(s, nt, n, bw.Ylev, op->n_active, bw.Yself, V, out);
+    if (zout) launch_strip_mfma(s, nt, op->d_ms, op->n_ms, op->d_pinv, out, zout, nullptr);
+}
+
+
+// Block GMRES over up to kMaxBlockRhs right-hand sides (block.cpp).  `broke` is set when the
+// block of right-hand sides (or of residuals at a restart) is numerically rank deficient; x
+// then holds the best iterate and the caller finishes those columns another way.
+qrvie_status solve_block(qrvie_ctx* ctx, const qrvie_op* op, int na, const c128* v, int64_t ldv, c128* x,
+                         int64_t ldx, const qrvie_solve_opts* o, qrvie_solve_info* info, bool* broke);
+
+}  // namespace qrvie

@@ -1,0 +1,104 @@
+"""Block GMRES over blocks of up to 64 right-hand sides (GPU).
+
+Solutions are compared with the oracle's direct solve of the exported operator Z_QR
+(same operator, so the bound is the solver tolerance times a modest conditioning
+factor), and with the single-vector GMRES of the same library.
+"""
+import numpy as np
+import pytest
+
+from oracle import compressed, greens
+
+from gpu_cases import case, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+BLOCK = 2
+
+
+def _zqr(c):
+    sb = greens.self_blocks(c.disc)
+    return compressed.dense_from_factors(sb, [(f[0], f[1], f[2], f[3]) for f in c.factors()])
+
+
+def _rhs(c, nrhs, seed=0):
+    import paper_2603_10586_amd as q
+    rng = np.random.default_rng(seed)
+    th = rng.uniform(-60, 60, nrhs)
+    ph = rng.uniform(0, 360, nrhs)
+    return q.rhs_plane_waves(c.ctx, c.geom, th, ph, [r % 2 for r in range(nrhs)])
+
+
+@pytest.mark.parametrize("name,nrhs", [("rand6x7", 10), ("rand5x3", 64), ("rand6x7", 70)])
+def test_block_solve_matches_lu(name, nrhs):
+    c = case(name)
+    v = _rhs(c, nrhs, seed=nrhs)
+    x, info, st = c.op.solve(v, restart=4000, tol=1e-10, max_iter=2000, mode=BLOCK)
+    assert st == 0
+    ZQR = _zqr(c)
+    vh, xh = to_host(v), to_host(x)
+    ref = np.linalg.solve(ZQR, vh.T).T
+    for r in range(nrhs):
+        assert info[r]["converged"] and info[r]["rel_res_true"] <= 1e-10
+        assert np.linalg.norm(vh[r] - ZQR @ xh[r]) <= 2e-10 * np.linalg.norm(vh[r])
+        assert np.linalg.norm(xh[r] - ref[r]) <= 1e-7 * np.linalg.norm(ref[r])
+    # one block of width min(nrhs, 64) takes far fewer steps than a single vector
+    x1, info1, _ = c.op.solve(v[:1].contiguous(), restart=2000, tol=1e-10, max_iter=2000)
+    assert info[0]["iterations"] < info1[0]["iterations"]
+
+
+def test_block_solve_with_restarts_converges():
+    c = case("rand6x7")
+    v = _rhs(c, 16, seed=3)
+    x, info, st = c.op.solve(v, restart=48, tol=1e-9, max_iter=3000, mode=BLOCK)   # 3 block steps per cycle
+    assert st == 0 and all(i["converged"] for i in info)
+    assert info[0]["restarts"] >= 1
+    ZQR = _zqr(c)
+    vh, xh = to_host(v), to_host(x)
+    for r in range(16):
+        assert np.linalg.norm(vh[r] - ZQR @ xh[r]) <= 2e-9 * np.linalg.norm(vh[r])
+
+
+def test_block_agrees_with_single_vector_gmres():
+    c = case("rand8x8")
+    v = _rhs(c, 20, seed=5)
+    xb, ib, sb = c.op.solve(v, restart=4000, tol=1e-8, max_iter=2000, mode=BLOCK)
+    xs, isv, ss = c.op.solve(v, restart=2000, tol=1e-8, max_iter=2000)
+    assert sb == 0 and ss == 0
+    xb, xs = to_host(xb), to_host(xs)
+    for r in range(20):
+        assert np.linalg.norm(xb[r] - xs[r]) <= 1e-6 * np.linalg.norm(xs[r])
+
+
+def test_zero_and_repeated_right_hand_sides():
+    """A zero column gives x = 0; a repeated column makes the block rank deficient and the
+    block is finished column by column (same solutions)."""
+    c = case("rand5x3")
+    v = _rhs(c, 6, seed=9)
+    v[2] = 0
+    v[4] = v[1]
+    x, info, st = c.op.solve(v, restart=2000, tol=1e-10, max_iter=2000, mode=BLOCK)
+    assert st == 0 and all(i["converged"] for i in info)
+    xh, vh = to_host(x), to_host(v)
+    assert np.abs(xh[2]).max() == 0.0
+    ZQR = _zqr(c)
+    for r in (0, 1, 3, 4, 5):
+        assert np.linalg.norm(vh[r] - ZQR @ xh[r]) <= 2e-10 * np.linalg.norm(vh[r])
+    assert np.linalg.norm(xh[4] - xh[1]) <= 1e-8 * np.linalg.norm(xh[1])
+
+
+def test_block_step_limit_reports_not_converged():
+    c = case("rand6x7")
+    v = _rhs(c, 8, seed=11)
+    x, info, st = c.op.solve(v, restart=4000, tol=1e-12, max_iter=3, mode=BLOCK)
+    assert st == 5
+    assert all(i["iterations"] == 3 and not i["converged"] for i in info)
+    assert all(np.isfinite(i["rel_res_true"]) and i["rel_res_true"] < 1.0 for i in info)
+
+
+def test_block_warm_start_from_the_solution():
+    c = case("rand5x3")
+    v = _rhs(c, 5, seed=13)
+    x, info, st = c.op.solve(v, restart=2000, tol=1e-10, max_iter=2000, mode=BLOCK)
+    x2, info2, st2 = c.op.solve(v, restart=2000, tol=1e-9, max_iter=2000, mode=BLOCK, x0=x)
+    assert st2 == 0 and all(i["iterations"] == 0 for i in info2)
