@@ -217,6 +217,16 @@ qrvie_status qrvie_apply_prec(qrvie_ctx* ctx, const qrvie_op* op, int32_t prec, 
  */
 qrvie_status qrvie_op_profile_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t prec, int32_t reps, double* ms,
                                     int64_t* bytes);
+/*
+ * Stage timers of the block product used by QRVIE_SOLVE_BLOCK and by qrvie_apply with 16 or
+ * more right-hand sides, for nrhs (1..64) right-hand sides padded to a multiple of 16:
+ * ms[0] R-phase, ms[1] Q-phase, ms[2] self blocks + level sum, ms[3] block preconditioner,
+ * averages over `reps` products of a zero block.  flops[0..3]: real floating-point
+ * operations of the same stages (8 per complex multiply-add of a factor or self-block entry
+ * with each padded right-hand side).  Host arrays of 4.
+ */
+qrvie_status qrvie_op_profile_block(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, int32_t reps, double* ms,
+                                    int64_t* flops);
 /* z = Z_D^-1 y, the block-diagonal left preconditioner (§4, eq. 4.2). */
 qrvie_status qrvie_precondition(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs,
                                 const qrvie_c128* y, int64_t ldy, qrvie_c128* z, int64_t ldz);

@@ -244,6 +244,15 @@ class Operator:
         names = ("rphase", "qphase", "final", "product")
         return {k: dict(ms=ms[i], bytes=by[i]) for i, k in enumerate(names)}
 
+    def profile_block(self, nrhs: int = 64, reps: int = 5) -> dict:
+        """Per-stage device time (ms) and flops of one block product of nrhs right-hand sides."""
+        ms = (C.c_double * 4)()
+        fl = (C.c_int64 * 4)()
+        self.ctx.order()
+        self.ctx.check(self.ctx.lib.qrvie_op_profile_block(self.ctx.h, self.h, nrhs, reps, ms, fl), "profile block")
+        names = ("rphase", "qphase", "self", "precond")
+        return {k: dict(ms=ms[i], flops=fl[i]) for i, k in enumerate(names)}
+
     def precondition(self, y):
         torch = _torch()
         py, ld, nrhs = _cols(y, self.geom.ndof)

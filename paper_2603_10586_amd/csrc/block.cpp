@@ -58,9 +58,20 @@ qrvie_status blas_handle(qrvie_ctx* ctx, rocblas_handle* h) {
     return blas_check(ctx, rocblas_set_stream(*h, ctx->stream), "rocblas stream");
 }
 
-// Relative pivot floor of the Cholesky QR: a block whose Gram matrix has a pivot below
-// 1e-20 of its largest diagonal entry (condition number above 1e10) counts as rank deficient.
-constexpr double kCholFloor = 1e-20;
+// Pivot floors (relative to the largest diagonal entry of a Gram matrix).  The first block
+// of a cycle keeps the directions whose singular values exceed 1e-7 of the largest (a
+// rank-revealing pivoted Cholesky): plane waves at nearby angles are numerically dependent,
+// and what is dropped stays in the residual and returns at the next cycle.  A new Arnoldi
+// block whose Cholesky QR meets a pivot below 1e-15 (condition above 3e7, where Cholesky QR
+// twice no longer orthogonalises reliably) ends the cycle.
+constexpr double kDeflateFloor = 1e-14;
+constexpr double kCholFloor = 1e-15;
+
+// Split-K projections: at most 256 row chunks of at least 512 rows, partial products within
+// 32 M complex entries (512 MB).
+constexpr int64_t kMaxChunks = 256;
+constexpr int64_t kMinChunkRows = 512;
+constexpr int64_t kPartialElems = (int64_t)32 << 20;
 
 struct BlockSolver {
     qrvie_ctx* ctx;
@@ -69,17 +80,20 @@ struct BlockSolver {
     rocblas_handle hb = nullptr;
     hipStream_t s;
     int64_t n;
-    int p = 0, nt = 0, Kc = 0;
-    int64_t ldh = 0;
+    int p = 0, ntB = 0;          // right-hand sides and their tile count
+    int q = 0, ntK = 0, Kc = 0;  // block width of the current cycle, tiles, block steps per cycle
+    int64_t ldh = 0;             // rows of the least-squares arrays: (block steps + 1) x width <= ldh
     Work w;
     BlockWork bw;
-    c128 *Bc = nullptr, *X = nullptr, *Xc = nullptr, *Rc = nullptr, *Vb = nullptr;
+    c128 *Bc = nullptr, *X = nullptr, *Xc = nullptr, *Rc = nullptr, *Zc = nullptr, *Vb = nullptr;
     c128 *Bi = nullptr, *Xi = nullptr, *Ri = nullptr, *Zi = nullptr;
     c128 *Cb = nullptr, *Hb = nullptr, *G = nullptr, *Rl = nullptr, *gl = nullptr, *Yb = nullptr;
     c128 *Yr = nullptr, *Tr = nullptr, *S = nullptr, *R1 = nullptr, *R2 = nullptr;
-    int* dflag = nullptr;
+    c128* Pk = nullptr;          // split-K partial products
+    int* dflag = nullptr;        // [0..1] Cholesky flags, [2] rank q, [3..] pivot order
     double* dnrm = nullptr;
-    double* hbuf = nullptr;   // pinned
+    double* hbuf = nullptr;      // pinned
+    int* hint = nullptr;         // pinned
     hipEvent_t ev0{}, ev1{};
     double t_apply = 0.0;
     int products = 0;
@@ -88,22 +102,23 @@ struct BlockSolver {
         : ctx(c), op(p_), o(o_), s(c->stream), n(p_->g->ndof()), w(c) {}
     ~BlockSolver() {
         if (hbuf) (void)hipHostFree(hbuf);
+        if (hint) (void)hipHostFree(hint);
         (void)hipEventDestroy(ev0);
         (void)hipEventDestroy(ev1);
     }
 
     qrvie_status init(int ncols) {
         p = ncols;
-        nt = (p + 15) / 16;
-        Kc = std::max(1, std::min(o->restart / p, o->max_iter));
-        ldh = (int64_t)(Kc + 1) * p;
-        const int64_t P = 16 * nt;
+        ntB = (p + 15) / 16;
+        ldh = (int64_t)(std::max(1, std::min(o->restart / p, o->max_iter)) + 1) * p;
+        const int64_t P = 16 * ntB;
         CHECK(blas_handle(ctx, &hb));
         CHECK(bw.init(w, op));
         CHECK(w.alloc(&Bc, (size_t)n * p, "block rhs"));
         CHECK(w.alloc(&X, (size_t)n * p, "block x"));
         CHECK(w.alloc(&Xc, (size_t)n * p, "block candidate"));
         CHECK(w.alloc(&Rc, (size_t)n * p, "block residual"));
+        CHECK(w.alloc(&Zc, (size_t)n * p, "block preconditioned residual"));
         CHECK(w.alloc(&Vb, (size_t)n * ldh, "block krylov basis"));
         CHECK(w.alloc(&Bi, (size_t)n * P, "interleaved rhs"));
         CHECK(w.alloc(&Xi, (size_t)n * P, "interleaved x"));
@@ -112,70 +127,152 @@ struct BlockSolver {
         CHECK(w.alloc(&Cb, (size_t)ldh * 2 * p, "block projections"));
         CHECK(w.alloc(&Hb, (size_t)ldh * p, "block coefficients"));
         CHECK(w.alloc(&G, (size_t)ldh * ldh, "block gram matrix"));
-        CHECK(w.alloc(&Rl, (size_t)ldh * Kc * p, "block hessenberg"));
+        CHECK(w.alloc(&Rl, (size_t)ldh * ldh, "block hessenberg"));
         CHECK(w.alloc(&gl, (size_t)ldh * p, "block least-squares rhs"));
         CHECK(w.alloc(&Yb, (size_t)ldh * p, "block least-squares solution"));
-        CHECK(w.alloc(&Yr, (size_t)Kc * 2 * p * p, "block reflectors"));
-        CHECK(w.alloc(&Tr, (size_t)Kc * p * p, "block reflector factors"));
+        CHECK(w.alloc(&Yr, (size_t)2 * p * ldh, "block reflectors"));
+        CHECK(w.alloc(&Tr, (size_t)p * ldh, "block reflector factors"));
         CHECK(w.alloc(&S, (size_t)p * p, "gram block"));
         CHECK(w.alloc(&R1, (size_t)p * p, "cholesky factor"));
         CHECK(w.alloc(&R2, (size_t)p * p, "cholesky factor"));
-        CHECK(w.alloc(&dflag, 2, "cholesky flags"));
+        CHECK(w.alloc(&Pk, (size_t)kPartialElems, "split-k partials"));
+        CHECK(w.alloc(&dflag, 3 + (size_t)p, "cholesky flags"));
         CHECK(w.alloc(&dnrm, 2 * (size_t)p, "block norms"));
-        CHECK(hip_check(ctx, hipHostMalloc((void**)&hbuf, sizeof(double) * (2 * p + 2), hipHostMallocDefault), "pinned"));
+        CHECK(hip_check(ctx, hipHostMalloc((void**)&hbuf, sizeof(double) * 2 * p, hipHostMallocDefault), "pinned"));
+        CHECK(hip_check(ctx, hipHostMalloc((void**)&hint, sizeof(int) * (3 + p), hipHostMallocDefault), "pinned"));
         (void)hipEventCreate(&ev0);
         (void)hipEventCreate(&ev1);
         return QRVIE_OK;
     }
 
-    // host copy of `count` doubles (and optionally the two Cholesky flags), then sync
-    qrvie_status read(const double* d, int count, bool flags, int hf[2]) {
-        CHECK(hip_check(ctx, hipMemcpyAsync(hbuf, d, sizeof(double) * count, hipMemcpyDeviceToHost, s), "read"));
-        if (flags)
-            CHECK(hip_check(ctx, hipMemcpyAsync(hbuf + 2 * p, dflag, sizeof(int) * 2, hipMemcpyDeviceToHost, s),
-                            "read"));
-        CHECK(hip_check(ctx, hipStreamSynchronize(s), "sync"));
-        if (flags) std::memcpy(hf, hbuf + 2 * p, sizeof(int) * 2);
-        return QRVIE_OK;
+    // host copies of `count` doubles and `nint` flag words, then sync
+    qrvie_status read(const double* d, int count, int nint) {
+        if (count > 0)
+            CHECK(hip_check(ctx, hipMemcpyAsync(hbuf, d, sizeof(double) * count, hipMemcpyDeviceToHost, s), "read"));
+        if (nint > 0)
+            CHECK(hip_check(ctx, hipMemcpyAsync(hint, dflag, sizeof(int) * nint, hipMemcpyDeviceToHost, s), "read"));
+        return hip_check(ctx, hipStreamSynchronize(s), "sync");
     }
 
-    // out = B - Z_QR Xcol (col-major n x p) and, optionally, zcol = Z_D^-1 out; both col-major
+    // out = B - Z_QR Xcol and, optionally, zcol = Z_D^-1 out (col-major n x p)
     void residual(const c128* Xcol, c128* out, c128* zcol) {
-        launch_gather_block(s, nt, op->g->N, nullptr, Xcol, n, p, Xi);
+        launch_gather_block(s, ntB, op->g->N, nullptr, Xcol, n, p, Xi);
         (void)hipEventRecord(ev0, s);
-        block_product(op, s, bw, nt, Xi, Bi, Ri, zcol ? Zi : nullptr);
+        block_product(op, s, bw, ntB, Xi, Bi, Ri, zcol ? Zi : nullptr);
         (void)hipEventRecord(ev1, s);
         ++products;
-        launch_scatter_block(s, nt, op->g->N, nullptr, Ri, out, n, p);
-        if (zcol) launch_scatter_block(s, nt, op->g->N, nullptr, Zi, zcol, n, p);
+        launch_scatter_block(s, ntB, op->g->N, nullptr, Ri, out, n, p);
+        if (zcol) launch_scatter_block(s, ntB, op->g->N, nullptr, Zi, zcol, n, p);
     }
     void add_product_time() {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, ev0, ev1) == hipSuccess) t_apply += ms * 1e-3;
     }
 
-    // W (n x p, ld n) = Q R with orthonormal Q (in place) and R (p x p upper) at out;
-    // Cholesky QR twice.  Returns the pivot flags of both passes through hf after a read.
-    qrvie_status cholqr2(c128* Wp, c128* out, int64_t ldo) {
-        const double one = 1.0, zero = 0.0;
-        const zc zone = {1.0, 0.0};
-        c128* Rs[2] = {R1, R2};
-        for (int pass = 0; pass < 2; ++pass) {
-            CHECK(blas_check(ctx, rocblas_zherk(hb, rocblas_fill_upper, rocblas_operation_conjugate_transpose, p, (int)n,
-                                                &one, Z(Wp), (int)n, &zero, Z(S), p), "zherk"));
-            launch_cholesky(s, p, S, p, kCholFloor, Rs[pass], p, dflag + pass);
-            CHECK(blas_check(ctx, rocblas_ztrsm(hb, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
-                                                rocblas_diagonal_non_unit, (int)n, p, &zone, Z(Rs[pass]), p, Z(Wp),
-                                                (int)n), "ztrsm"));
+    // C (m x c, ldc) = A^H B for n-row A (ld lda) and B (ld ldb).  The outputs of the basis
+    // projections are small (m x c with c <= 128) against a 10^5-10^6 long reduction, so the
+    // rows are split into chunks: a strided-batched GEMM writes one partial product per chunk
+    // and a fixed-order reduction sums them (deterministic, and the whole device is busy).
+    qrvie_status gemm_hn(const c128* A, int64_t lda, int m, const c128* Bm, int64_t ldb, int c, c128* C, int64_t ldc) {
+        const zc zone = {1.0, 0.0}, zzero = {0.0, 0.0};
+        const int64_t per = (int64_t)m * c;
+        if (per == 0) return QRVIE_OK;
+        int64_t nb = std::min<int64_t>({kMaxChunks, kPartialElems / per - 1, n / kMinChunkRows});
+        if (nb < 2) {
+            return blas_check(ctx, rocblas_zgemm(hb, rocblas_operation_conjugate_transpose, rocblas_operation_none, m, c,
+                                                 (int)n, &zone, Z(A), (int)lda, Z(Bm), (int)ldb, &zzero, Z(C), (int)ldc),
+                              "zgemm");
         }
-        launch_trmm_upper(s, p, R2, p, R1, p, out, ldo, dflag);
+        const int64_t L = n / nb, rem = n - nb * L;
+        CHECK(blas_check(ctx, rocblas_zgemm_strided_batched(hb, rocblas_operation_conjugate_transpose,
+                                                            rocblas_operation_none, m, c, (int)L, &zone, Z(A), (int)lda,
+                                                            L, Z(Bm), (int)ldb, L, &zzero, Z(Pk), m, per, (int)nb),
+                         "zgemm batched"));
+        if (rem > 0)
+            CHECK(blas_check(ctx, rocblas_zgemm(hb, rocblas_operation_conjugate_transpose, rocblas_operation_none, m, c,
+                                                (int)rem, &zone, Z(A + nb * L), (int)lda, Z(Bm + nb * L), (int)ldb,
+                                                &zzero, Z(Pk + nb * per), m), "zgemm"));
+        launch_sum_batches(s, m, c, (int)(nb + (rem > 0 ? 1 : 0)), Pk, C, ldc);
         return QRVIE_OK;
     }
 
-    // X_out = X_in + V[:, 0:(k+1)p] R^-1 gl[0:(k+1)p]
+    qrvie_status gram(const c128* Wp, int cols) { return gemm_hn(Wp, n, cols, Wp, n, cols, S, cols); }
+    qrvie_status right_solve(c128* Wp, int cols, const c128* R, int64_t ldr) {
+        const zc zone = {1.0, 0.0};
+        return blas_check(ctx, rocblas_ztrsm(hb, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
+                                             rocblas_diagonal_non_unit, (int)n, cols, &zone, Z(R), (int)ldr, Z(Wp),
+                                             (int)n), "ztrsm");
+    }
+
+    // W (n x cols, ld n) = Q R, Q in place, R (cols x cols upper) at out; Cholesky QR twice.
+    // Sets the two flag words (read later); R = 0 when either pass met a pivot below kCholFloor.
+    qrvie_status cholqr2(c128* Wp, int cols, c128* out, int64_t ldo) {
+        c128* Rs[2] = {R1, R2};
+        for (int pass = 0; pass < 2; ++pass) {
+            CHECK(gram(Wp, cols));
+            launch_cholesky(s, cols, S, cols, kCholFloor, Rs[pass], cols, dflag + pass);
+            CHECK(right_solve(Wp, cols, Rs[pass], cols));
+        }
+        launch_trmm_upper(s, cols, R2, cols, R1, cols, out, ldo, dflag);
+        return QRVIE_OK;
+    }
+
+    // First block of a cycle from the preconditioned residuals Zc (n x p).  Repeatedly: take
+    // the dominant directions of the remainder E (rank-revealing pivoted Cholesky of E^H E,
+    // relative to E's own scale), orthogonalise them against the directions already kept
+    // (twice) and normalise them (Cholesky QR twice); then S0 = V_0^H Zc and E = Zc - V_0 S0,
+    // until every column's remainder is below 1e-3 tol ||Z_D^-1 b|| or the block is full.
+    // Rows 0:q of gl receive S0.  q = 0 means the residuals have no usable direction.
+    qrvie_status first_block(const std::vector<double>& pvnorm) {
+        const zc zone = {1.0, 0.0}, zmone = {-1.0, 0.0}, zzero = {0.0, 0.0};
+        q = 0;
+        c128* E = Rc;
+        CHECK(hip_check(ctx, hipMemcpyAsync(E, Zc, sizeof(c128) * n * p, hipMemcpyDeviceToDevice, s), "remainder"));
+        CHECK(hip_check(ctx, hipMemsetAsync(gl, 0, sizeof(c128) * ldh * p, s), "ls rhs"));
+        for (int pass = 0; pass < 4 && q < p; ++pass) {
+            CHECK(gram(E, p));
+            launch_cholesky_piv(s, p, S, p, kDeflateFloor, R1, p, dflag + 3, dflag + 2);
+            CHECK(read(nullptr, 0, 3 + p));
+            const int q2 = std::min(hint[2], p - q);
+            if (q2 == 0) break;
+            c128* Vn = Vb + (int64_t)q * n;
+            for (int c = 0; c < q2; ++c)
+                CHECK(hip_check(ctx, hipMemcpyAsync(Vn + (int64_t)c * n, E + (int64_t)hint[3 + c] * n,
+                                                    sizeof(c128) * n, hipMemcpyDeviceToDevice, s), "first block"));
+            CHECK(right_solve(Vn, q2, R1, p));
+            for (int it = 0; q > 0 && it < 2; ++it) {     // against the kept directions, twice
+                CHECK(gemm_hn(Vb, n, q, Vn, n, q2, Cb, q));
+                CHECK(blas_check(ctx, rocblas_zgemm(hb, rocblas_operation_none, rocblas_operation_none, (int)n, q2, q,
+                                                    &zmone, Z(Vb), (int)n, Z(Cb), q, &zone, Z(Vn), (int)n),
+                                 "zgemm deflation"));
+            }
+            CHECK(cholqr2(Vn, q2, Hb, q2));
+            CHECK(read(nullptr, 0, 2));
+            if (hint[0] || hint[1]) break;                // not independent after all: keep what we have
+            q += q2;
+            // S0 = V_0^H Zc and the remainder E = Zc - V_0 S0
+            CHECK(gemm_hn(Vb, n, q, Zc, n, p, gl, ldh));
+            CHECK(hip_check(ctx, hipMemcpyAsync(E, Zc, sizeof(c128) * n * p, hipMemcpyDeviceToDevice, s), "remainder"));
+            CHECK(blas_check(ctx, rocblas_zgemm(hb, rocblas_operation_none, rocblas_operation_none, (int)n, p, q,
+                                                &zmone, Z(Vb), (int)n, Z(gl), (int)ldh, &zone, Z(E), (int)n),
+                             "zgemm remainder"));
+            launch_col_norms(s, (int)n, E, n, p, dnrm);
+            CHECK(read(dnrm, p, 0));
+            bool small = true;
+            for (int c = 0; c < p; ++c) small = small && hbuf[c] <= 1e-3 * o->tol * pvnorm[c];
+            if (small) break;
+        }
+        if (q > 0) {
+            ntK = (q + 15) / 16;
+            Kc = std::max(1, std::min((int)(ldh / q) - 1, o->max_iter));
+        }
+        return QRVIE_OK;
+    }
+
+    // X_out = X_in + V[:, 0:steps q] R^-1 gl[0:steps q, :]
     qrvie_status update(int steps, const c128* Xin, c128* Xout) {
         const zc zone = {1.0, 0.0};
-        const int64_t m = (int64_t)steps * p;
+        const int64_t m = (int64_t)steps * q;
         if (Xout != Xin)
             CHECK(hip_check(ctx, hipMemcpyAsync(Xout, Xin, sizeof(c128) * n * p, hipMemcpyDeviceToDevice, s), "x"));
         if (steps == 0) return QRVIE_OK;
@@ -190,6 +287,57 @@ struct BlockSolver {
 };
 
 }  // namespace
+
+// Stage timers of the block product for nrhs (<= 64) interleaved right-hand sides.
+qrvie_status profile_block(qrvie_ctx* ctx, const qrvie_op* op, int nrhs, int reps, double* ms, int64_t* flops) {
+    const qrvie_geom* g = op->g;
+    const int64_t n = g->ndof();
+    const int nt = (nrhs + 15) / 16, P = 16 * nt;
+    hipStream_t s = ctx->stream;
+    Work w(ctx);
+    BlockWork bw;
+    CHECK(bw.init(w, op));
+    c128 *X, *Y, *Zp;
+    CHECK(w.alloc(&X, (size_t)n * P, "profile block"));
+    CHECK(w.alloc(&Y, (size_t)n * P, "profile block"));
+    CHECK(w.alloc(&Zp, (size_t)n * P, "profile block"));
+    CHECK(hip_check(ctx, hipMemsetAsync(X, 0, sizeof(c128) * n * P, s), "profile block"));
+    hipEvent_t ev[5];
+    for (auto& e : ev) (void)hipEventCreate(&e);
+    double acc[4] = {0, 0, 0, 0};
+    for (int r = 0; r < reps; ++r) {
+        (void)hipEventRecord(ev[0], s);
+        launch_strip_mfma(s, nt, op->d_mr, op->n_mr, op->d_fac, X, bw.T, op->d_tmap);
+        (void)hipEventRecord(ev[1], s);
+        launch_strip_mfma(s, nt, op->d_mq, op->n_mq, op->d_fac, bw.T, bw.Ylev, nullptr);
+        (void)hipEventRecord(ev[2], s);
+        launch_strip_mfma(s, nt, op->d_ms, op->n_ms, op->d_self, X, bw.Yself, nullptr);
+        launch_block_combine(s, nt, n, bw.Ylev, op->n_active, bw.Yself, X, Y);
+        (void)hipEventRecord(ev[3], s);
+        launch_strip_mfma(s, nt, op->d_ms, op->n_ms, op->d_pinv, Y, Zp, nullptr);
+        (void)hipEventRecord(ev[4], s);
+        CHECK(hip_check(ctx, hipEventSynchronize(ev[4]), "profile block"));
+        for (int k = 0; k < 4; ++k) {
+            float t = 0.f;
+            (void)hipEventElapsedTime(&t, ev[k], ev[k + 1]);
+            acc[k] += t;
+        }
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    for (int k = 0; k < 4; ++k) ms[k] = acc[k] / reps;
+    // 8 real flops per complex multiply-add, P right-hand sides (the padded width)
+    int64_t rn = 0, mr = 0;
+    for (size_t b = 0; b < op->blocks.size(); ++b) {
+        rn += (int64_t)op->rank[b] * op->blocks[b].cn * kNp;
+        mr += (int64_t)op->rank[b] * op->blocks[b].rn * kNp;
+    }
+    const int64_t self = (int64_t)g->N * kNp * kNp;
+    flops[0] = 8 * P * rn;
+    flops[1] = 8 * P * mr;
+    flops[2] = 8 * P * self;
+    flops[3] = 8 * P * self;
+    return hip_check(ctx, hipGetLastError(), "profile block");
+}
 
 qrvie_status solve_block(qrvie_ctx* ctx, const qrvie_op* op, int na, const c128* v, int64_t ldv, c128* x,
                          int64_t ldx, const qrvie_solve_opts* o, qrvie_solve_info* info, bool* broke) {
@@ -237,13 +385,12 @@ qrvie_status solve_block(qrvie_ctx* ctx, const qrvie_op* op, int na, const c128*
         if (o->use_x0) launch_permute(s, g->N, g->d_i2c, x + (int64_t)cols[c] * ldx, B.X + (int64_t)c * n, 1);
     }
     if (!o->use_x0) CHECK(hip_check(ctx, hipMemsetAsync(B.X, 0, sizeof(c128) * n * p, s), "x0"));
-    launch_gather_block(s, B.nt, g->N, nullptr, B.Bc, n, p, B.Bi);
+    launch_gather_block(s, B.ntB, g->N, nullptr, B.Bc, n, p, B.Bi);
     // ||Z_D^-1 b|| per column: the scale of the preconditioned estimates
-    launch_strip_mfma(s, B.nt, op->d_ms, op->n_ms, op->d_pinv, B.Bi, B.Zi, nullptr);
-    launch_scatter_block(s, B.nt, g->N, nullptr, B.Zi, B.Rc, n, p);
+    launch_strip_mfma(s, B.ntB, op->d_ms, op->n_ms, op->d_pinv, B.Bi, B.Zi, nullptr);
+    launch_scatter_block(s, B.ntB, g->N, nullptr, B.Zi, B.Rc, n, p);
     launch_col_norms(s, (int)n, B.Rc, n, p, B.dnrm);
-    int hf[2] = {0, 0};
-    CHECK(B.read(B.dnrm, p, false, hf));
+    CHECK(B.read(B.dnrm, p, 0));
     std::vector<double> bnorm(p), pvnorm(p), ptol(p, o->tol), est(p, 0.0), tres(p, 0.0);
     for (int c = 0; c < p; ++c) {
         bnorm[c] = vnorm[cols[c]];
@@ -252,66 +399,61 @@ qrvie_status solve_block(qrvie_ctx* ctx, const qrvie_op* op, int na, const c128*
 
     const zc zone = {1.0, 0.0}, zmone = {-1.0, 0.0}, ztwo = {2.0, 0.0}, zzero = {0.0, 0.0};
     int steps_total = 0, cycles = 0;
-    bool done = false, converged = false;
-    while (!done) {
-        // cycle start: true residual of X and the first block V_0 S0 = Z_D^-1 (B - Z_QR X)
-        B.residual(B.X, B.Rc, B.Vb);
+    for (;;) {
+        // cycle start: true residual of X and the first block from Z_D^-1 (B - Z_QR X)
+        B.residual(B.X, B.Rc, B.Zc);
         launch_col_norms(s, (int)n, B.Rc, n, p, B.dnrm);
-        CHECK(B.read(B.dnrm, p, false, hf));
+        CHECK(B.read(B.dnrm, p, 0));
         B.add_product_time();
         bool all = true;
         for (int c = 0; c < p; ++c) {
             tres[c] = B.hbuf[c] / bnorm[c];
             all = all && tres[c] <= o->tol;
         }
-        if (all) { converged = true; break; }
-        if (steps_total >= o->max_iter) break;
-        CHECK(hip_check(ctx, hipMemsetAsync(B.gl, 0, sizeof(c128) * B.ldh * p, s), "ls rhs"));
-        CHECK(B.cholqr2(B.Vb, B.gl, B.ldh));
-        CHECK(B.read(B.dnrm, 0, true, hf));
-        if (hf[0] || hf[1]) { *broke = true; break; }
+        if (all || steps_total >= o->max_iter) break;
+        CHECK(B.first_block(pvnorm));
+        if (B.q == 0) { *broke = true; break; }
+        const int q = B.q;
         int k = 0;
-        bool end_cycle = false;
+        bool end_cycle = false, done = false;
         for (; k < B.Kc && !end_cycle; ++k) {
-            const int64_t m = (int64_t)(k + 1) * p;
-            c128* Vk = B.Vb + (int64_t)k * p * n;
-            c128* W = Vk + (int64_t)p * n;
+            const int64_t m = (int64_t)(k + 1) * q;
+            c128* Vk = B.Vb + (int64_t)k * q * n;
+            c128* W = Vk + (int64_t)q * n;
             // W = Z_D^-1 Z_QR V_k
-            launch_gather_block(s, B.nt, g->N, nullptr, Vk, n, p, B.Xi);
+            launch_gather_block(s, B.ntK, g->N, nullptr, Vk, n, q, B.Xi);
             (void)hipEventRecord(B.ev0, s);
-            block_product(op, s, B.bw, B.nt, B.Xi, nullptr, B.Ri, B.Zi);
+            block_product(op, s, B.bw, B.ntK, B.Xi, nullptr, B.Ri, B.Zi);
             (void)hipEventRecord(B.ev1, s);
             ++B.products;
-            launch_scatter_block(s, B.nt, g->N, nullptr, B.Zi, W, n, p);
+            launch_scatter_block(s, B.ntK, g->N, nullptr, B.Zi, W, n, q);
             // pass 1: [V^H V_k, V^H W]; Gram block; H = 2 H1 - G H1; pass 2: W -= V H
-            CHECK(blas_check(ctx, rocblas_zgemm(B.hb, rocblas_operation_conjugate_transpose, rocblas_operation_none,
-                                                (int)m, 2 * p, (int)n, &zone, Z(B.Vb), (int)n, Z(Vk), (int)n, &zzero,
-                                                Z(B.Cb), (int)B.ldh), "zgemm projections"));
-            launch_gram_store(s, k, p, B.Cb, B.ldh, B.G, B.ldh);
-            const c128* H1 = B.Cb + (int64_t)p * B.ldh;
+            CHECK(B.gemm_hn(B.Vb, n, (int)m, Vk, n, 2 * q, B.Cb, B.ldh));
+            launch_gram_store(s, k, q, B.Cb, B.ldh, B.G, B.ldh);
+            const c128* H1 = B.Cb + (int64_t)q * B.ldh;
             CHECK(hip_check(ctx, hipMemcpy2DAsync(B.Hb, sizeof(c128) * B.ldh, H1, sizeof(c128) * B.ldh,
-                                                  sizeof(c128) * m, p, hipMemcpyDeviceToDevice, s), "h1"));
-            CHECK(blas_check(ctx, rocblas_zgemm(B.hb, rocblas_operation_none, rocblas_operation_none, (int)m, p, (int)m,
+                                                  sizeof(c128) * m, q, hipMemcpyDeviceToDevice, s), "h1"));
+            CHECK(blas_check(ctx, rocblas_zgemm(B.hb, rocblas_operation_none, rocblas_operation_none, (int)m, q, (int)m,
                                                 &zmone, Z(B.G), (int)B.ldh, Z(H1), (int)B.ldh, &ztwo, Z(B.Hb),
                                                 (int)B.ldh), "zgemm gram"));
-            CHECK(blas_check(ctx, rocblas_zgemm(B.hb, rocblas_operation_none, rocblas_operation_none, (int)n, p, (int)m,
+            CHECK(blas_check(ctx, rocblas_zgemm(B.hb, rocblas_operation_none, rocblas_operation_none, (int)n, q, (int)m,
                                                 &zmone, Z(B.Vb), (int)n, Z(B.Hb), (int)B.ldh, &zone, Z(W), (int)n),
                              "zgemm update"));
             // block Hessenberg column k: [H; H_{k+1,k}] with W = V_{k+1} H_{k+1,k}
-            c128* col = B.Rl + (int64_t)k * p * B.ldh;
+            c128* col = B.Rl + (int64_t)k * q * B.ldh;
             CHECK(hip_check(ctx, hipMemcpy2DAsync(col, sizeof(c128) * B.ldh, B.Hb, sizeof(c128) * B.ldh,
-                                                  sizeof(c128) * m, p, hipMemcpyDeviceToDevice, s), "hcol"));
-            CHECK(B.cholqr2(W, col + m, B.ldh));
-            // least squares: previous reflectors, the new one, and the transformed right-hand side
-            launch_ls_apply(s, 0, k, p, B.Yr, B.Tr, col, B.ldh, p);
-            launch_ls_factor(s, k, p, col, B.ldh, B.Yr + (int64_t)k * 2 * p * p, B.Tr + (int64_t)k * p * p);
-            launch_ls_apply(s, k, k + 1, p, B.Yr, B.Tr, B.gl, B.ldh, p);
-            launch_col_norms(s, p, B.gl + m, B.ldh, p, B.dnrm);
+                                                  sizeof(c128) * m, q, hipMemcpyDeviceToDevice, s), "hcol"));
+            CHECK(B.cholqr2(W, q, col + m, B.ldh));
+            // least squares: previous reflectors, the new one, and the transformed right-hand sides
+            launch_ls_apply(s, 0, k, q, B.Yr, B.Tr, col, B.ldh, q);
+            launch_ls_factor(s, k, q, col, B.ldh, B.Yr + (int64_t)k * 2 * q * q, B.Tr + (int64_t)k * q * q);
+            launch_ls_apply(s, k, k + 1, q, B.Yr, B.Tr, B.gl, B.ldh, p);
+            launch_col_norms(s, q, B.gl + m, B.ldh, p, B.dnrm);
             CHECK(hip_check(ctx, hipGetLastError(), "block step"));
-            CHECK(B.read(B.dnrm, p, true, hf));
+            CHECK(B.read(B.dnrm, p, 2));
             B.add_product_time();
             ++steps_total;
-            const bool breakdown = hf[0] || hf[1];
+            const bool breakdown = B.hint[0] || B.hint[1];
             bool met = true;
             for (int c = 0; c < p; ++c) {
                 est[c] = B.hbuf[c] / pvnorm[c];
@@ -322,7 +464,7 @@ qrvie_status solve_block(qrvie_ctx* ctx, const qrvie_op* op, int na, const c128*
                 CHECK(B.update(k + 1, B.X, B.Xc));
                 B.residual(B.Xc, B.Rc, nullptr);
                 launch_col_norms(s, (int)n, B.Rc, n, p, B.dnrm);
-                CHECK(B.read(B.dnrm, p, false, hf));
+                CHECK(B.read(B.dnrm, p, 0));
                 B.add_product_time();
                 bool ok = true;
                 for (int c = 0; c < p; ++c) {
@@ -335,9 +477,7 @@ qrvie_status solve_block(qrvie_ctx* ctx, const qrvie_op* op, int na, const c128*
                 if (ok) {
                     CHECK(hip_check(ctx, hipMemcpyAsync(B.X, B.Xc, sizeof(c128) * n * p, hipMemcpyDeviceToDevice, s),
                                     "x"));
-                    converged = true;
                     done = true;
-                    ++k;
                     break;
                 }
                 if (breakdown) end_cycle = true;   // the basis cannot grow: restart from the candidate
@@ -345,16 +485,9 @@ qrvie_status solve_block(qrvie_ctx* ctx, const qrvie_op* op, int na, const c128*
             if (steps_total >= o->max_iter) end_cycle = true;
         }
         if (done) break;
-        // end of the cycle: X += V Y, then restart (or stop at the step limit)
+        // end of the cycle: X += V Y, then restart (the next cycle starts with the true residual)
         CHECK(B.update(k, B.X, B.X));
         ++cycles;
-        if (steps_total >= o->max_iter) {
-            B.residual(B.X, B.Rc, nullptr);
-            launch_col_norms(s, (int)n, B.Rc, n, p, B.dnrm);
-            CHECK(B.read(B.dnrm, p, false, hf));
-            for (int c = 0; c < p; ++c) tres[c] = B.hbuf[c] / bnorm[c];
-            break;
-        }
     }
     for (int c = 0; c < p; ++c)
         launch_permute(s, g->N, g->d_i2c, B.X + (int64_t)c * n, x + (int64_t)cols[c] * ldx, 0);
@@ -377,7 +510,6 @@ qrvie_status solve_block(qrvie_ctx* ctx, const qrvie_op* op, int na, const c128*
         f.n_refine = 0;
     }
     if (info) std::copy(inf.begin(), inf.end(), info);
-    (void)converged;
     for (int c = 0; c < p; ++c)
         if (!inf[cols[c]].converged) return QRVIE_NOT_CONVERGED;
     return QRVIE_OK;

@@ -272,9 +272,14 @@ void launch_gram_store(hipStream_t s, int k, int p, const c128* C, int64_t ldc, 
 void launch_cholesky(hipStream_t s, int p, const c128* S, int64_t lds, double rel, c128* out, int64_t ldo, int* flag);
 void launch_trmm_upper(hipStream_t s, int p, const c128* A, int64_t lda, const c128* B, int64_t ldb, c128* C,
                        int64_t ldc, const int* flag);
+void launch_cholesky_piv(hipStream_t s, int p, const c128* S, int64_t lds, double rel, c128* out, int64_t ldo,
+                         int* perm, int* qout);
+void launch_trmm_perm(hipStream_t s, int q, int p, const c128* A, int64_t lda, const c128* B, int64_t ldb,
+                      const int* perm, c128* out, int64_t ldo);
 void launch_ls_apply(hipStream_t s, int j0, int j1, int p, const c128* Y, const c128* T, c128* C, int64_t ldc,
                      int ncols);
 void launch_ls_factor(hipStream_t s, int k, int p, c128* C, int64_t ldc, c128* Yk, c128* Tk);
 void launch_col_norms(hipStream_t s, int rows, const c128* C, int64_t ldc, int ncols, double* out);
+void launch_sum_batches(hipStream_t s, int m, int c, int nb, const c128* P, c128* C, int64_t ldc);
 
 }  // namespace qrvie

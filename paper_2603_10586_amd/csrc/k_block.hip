@@ -180,6 +180,93 @@ __global__ void __launch_bounds__(256) k_cholesky(int p, const c128* __restrict_
     }
 }
 
+// Rank-revealing Cholesky with diagonal pivoting of a Hermitian p x p Gram matrix S (p <= 64,
+// upper triangle used): S[perm, perm] = R^H R with R upper trapezoidal of rank q, stopping
+// at the first pivot below rel * (largest diagonal entry).  out (ld ldo) receives R in its
+// first q rows and zeros below; perm[0:p] the pivot order; qout[0] = q.
+__global__ void __launch_bounds__(256) k_cholesky_piv(int p, const c128* __restrict__ S, int64_t lds, double rel,
+                                                      c128* __restrict__ out, int64_t ldo, int* perm, int* qout) {
+    __shared__ c128 A[64][65];
+    __shared__ int pv[64];
+    __shared__ double dmax;
+    __shared__ int sel, q;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < p * p; e += blockDim.x) {
+        const int i = e % p, j = e / p;
+        const c128 v = i <= j ? S[i + j * lds] : S[j + i * lds];
+        A[i][j] = i <= j ? v : make_double2(v.x, -v.y);
+    }
+    if (tid < p) pv[tid] = tid;
+    __syncthreads();
+    if (tid == 0) {
+        double m = 0.0;
+        for (int j = 0; j < p; ++j) m = fmax(m, A[j][j].x);
+        dmax = m;
+        q = p;
+    }
+    __syncthreads();
+    for (int j = 0; j < p; ++j) {
+        if (tid == 0) {
+            int m = j;
+            for (int i = j + 1; i < p; ++i)
+                if (A[i][i].x > A[m][m].x) m = i;
+            sel = m;
+            if (!(A[m][m].x > rel * dmax)) q = j;
+        }
+        __syncthreads();
+        if (q <= j) break;                       // uniform: q is shared
+        const int m = sel;
+        if (m != j) {                            // symmetric swap of rows/columns j and m
+            for (int c = tid; c < p; c += blockDim.x) {
+                const c128 t = A[j][c]; A[j][c] = A[m][c]; A[m][c] = t;
+            }
+            __syncthreads();
+            for (int r = tid; r < p; r += blockDim.x) {
+                const c128 t = A[r][j]; A[r][j] = A[r][m]; A[r][m] = t;
+            }
+            if (tid == 0) { const int t = pv[j]; pv[j] = pv[m]; pv[m] = t; }
+            __syncthreads();
+        }
+        const double r = sqrt(A[j][j].x);
+        __syncthreads();
+        if (tid == 0) A[j][j] = make_double2(r, 0.0);
+        for (int c = j + 1 + tid; c < p; c += blockDim.x) A[j][c] = make_double2(A[j][c].x / r, A[j][c].y / r);
+        __syncthreads();
+        for (int e = tid; e < p * p; e += blockDim.x) {          // A[i][c] -= conj(R[j][i]) R[j][c], i, c > j
+            const int i = e % p, c = e / p;
+            if (i > j && c > j) {
+                const c128 a = A[j][i], b = A[j][c];
+                A[i][c] = make_double2(A[i][c].x - (a.x * b.x + a.y * b.y), A[i][c].y - (a.x * b.y - a.y * b.x));
+            }
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    const int qq = q;
+    for (int e = tid; e < p * p; e += blockDim.x) {
+        const int i = e % p, j = e / p;
+        out[i + j * ldo] = (i < qq && i <= j) ? A[i][j] : make_double2(0.0, 0.0);
+    }
+    if (tid < p) perm[tid] = pv[tid];
+    if (tid == 0) qout[0] = qq;
+}
+
+// out[0:q, perm[c]] = (A B)[0:q, c] for upper-triangular q x q A and upper-trapezoidal
+// q x p B (column-major): the deflated block's S0 in the original column order.
+__global__ void k_trmm_perm(int q, int p, const c128* __restrict__ A, int64_t lda, const c128* __restrict__ B,
+                            int64_t ldb, const int* __restrict__ perm, c128* __restrict__ out, int64_t ldo) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= q * p) return;
+    const int i = e % q, j = e / q;
+    double re = 0.0, im = 0.0;
+    for (int l = i; l < q && l <= j; ++l) {
+        const c128 a = A[i + (int64_t)l * lda], b = B[l + (int64_t)j * ldb];
+        re += a.x * b.x - a.y * b.y;
+        im += a.x * b.y + a.y * b.x;
+    }
+    out[i + (int64_t)perm[j] * ldo] = make_double2(re, im);
+}
+
 // C = A B for upper-triangular p x p A, B (column-major); C may not alias A or B.  C = 0
 // when either Cholesky flag is set (a rank-deficient block contributes nothing).
 __global__ void k_trmm_upper(int p, const c128* __restrict__ A, int64_t lda, const c128* __restrict__ B,
@@ -404,6 +491,22 @@ __global__ void __launch_bounds__(256) k_ls_factor(int k, int p, c128* __restric
     }
 }
 
+// C[i + j ldc] = sum_b P[b per + i + j m] for i < m, j < c, b < nb (fixed order): the
+// reduction of split-K partial products.
+__global__ void k_sum_batches(int m, int c, int nb, const c128* __restrict__ P, c128* __restrict__ C, int64_t ldc) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per = (int64_t)m * c;
+    if (e >= per) return;
+    const int64_t i = e % m, j = e / m;
+    double re = 0.0, im = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        const c128 v = P[(int64_t)b * per + e];
+        re += v.x;
+        im += v.y;
+    }
+    C[i + j * ldc] = make_double2(re, im);
+}
+
 // out[c] = ||C[0:rows, c]|| for c < ncols
 __global__ void __launch_bounds__(256) k_col_norms(int rows, const c128* __restrict__ C, int64_t ldc, double* out) {
     __shared__ double red[256];
@@ -432,6 +535,15 @@ void launch_trmm_upper(hipStream_t s, int p, const c128* A, int64_t lda, const c
                        int64_t ldc, const int* flag) {
     hipLaunchKernelGGL(k_trmm_upper, dim3((p * p + 255) / 256), dim3(256), 0, s, p, A, lda, B, ldb, C, ldc, flag);
 }
+void launch_cholesky_piv(hipStream_t s, int p, const c128* S, int64_t lds, double rel, c128* out, int64_t ldo,
+                         int* perm, int* qout) {
+    hipLaunchKernelGGL(k_cholesky_piv, dim3(1), dim3(256), 0, s, p, S, lds, rel, out, ldo, perm, qout);
+}
+void launch_trmm_perm(hipStream_t s, int q, int p, const c128* A, int64_t lda, const c128* B, int64_t ldb,
+                      const int* perm, c128* out, int64_t ldo) {
+    if (q * p <= 0) return;
+    hipLaunchKernelGGL(k_trmm_perm, dim3((q * p + 255) / 256), dim3(256), 0, s, q, p, A, lda, B, ldb, perm, out, ldo);
+}
 void launch_ls_apply(hipStream_t s, int j0, int j1, int p, const c128* Y, const c128* T, c128* C, int64_t ldc,
                      int ncols) {
     if (j1 <= j0 || ncols <= 0) return;
@@ -439,6 +551,11 @@ void launch_ls_apply(hipStream_t s, int j0, int j1, int p, const c128* Y, const 
 }
 void launch_ls_factor(hipStream_t s, int k, int p, c128* C, int64_t ldc, c128* Yk, c128* Tk) {
     hipLaunchKernelGGL(k_ls_factor, dim3(1), dim3(256), 0, s, k, p, C, ldc, Yk, Tk);
+}
+void launch_sum_batches(hipStream_t s, int m, int c, int nb, const c128* P, c128* C, int64_t ldc) {
+    const int64_t per = (int64_t)m * c;
+    if (per <= 0) return;
+    hipLaunchKernelGGL(k_sum_batches, dim3((unsigned)((per + 255) / 256)), dim3(256), 0, s, m, c, nb, P, C, ldc);
 }
 void launch_col_norms(hipStream_t s, int rows, const c128* C, int64_t ldc, int ncols, double* out) {
     hipLaunchKernelGGL(k_col_norms, dim3(ncols), dim3(256), 0, s, rows, C, ldc, out);

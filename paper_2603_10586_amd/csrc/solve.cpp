@@ -595,6 +595,12 @@ qrvie_status qrvie_op_profile_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t 
     return hip_check(ctx, hipGetLastError(), "profile");
 }
 
+qrvie_status qrvie_op_profile_block(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, int32_t reps, double* ms,
+                                    int64_t* flops) {
+    if (!ctx || !op || reps < 1 || nrhs < 1 || nrhs > kMaxBlockRhs || !ms || !flops) return QRVIE_ERR_INVALID_ARG;
+    return profile_block(ctx, op, nrhs, reps, ms, flops);
+}
+
 qrvie_status qrvie_precondition(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const qrvie_c128* y, int64_t ldy,
                                 qrvie_c128* z, int64_t ldz) {
     CHECK(check_vec_args(ctx, op, nrhs, y, ldy, z, ldz, "precondition"));

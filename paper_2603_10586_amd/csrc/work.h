@@ -69,4 +69,6 @@ inline void block_product(const qrvie_op* op, hipStream_t s, const BlockWork& bw
 qrvie_status solve_block(qrvie_ctx* ctx, const qrvie_op* op, int na, const c128* v, int64_t ldv, c128* x,
                          int64_t ldx, const qrvie_solve_opts* o, qrvie_solve_info* info, bool* broke);
 
+qrvie_status profile_block(qrvie_ctx* ctx, const qrvie_op* op, int nrhs, int reps, double* ms, int64_t* flops);
+
 }  // namespace qrvie

@@ -71,8 +71,8 @@ def test_block_agrees_with_single_vector_gmres():
 
 
 def test_zero_and_repeated_right_hand_sides():
-    """A zero column gives x = 0; a repeated column makes the block rank deficient and the
-    block is finished column by column (same solutions)."""
+    """A zero column gives x = 0 and stays out of the block; a repeated column is deflated
+    from the first block (rank-revealing Cholesky) and gets the same solution."""
     c = case("rand5x3")
     v = _rhs(c, 6, seed=9)
     v[2] = 0
@@ -94,6 +94,23 @@ def test_block_step_limit_reports_not_converged():
     assert st == 5
     assert all(i["iterations"] == 3 and not i["converged"] for i in info)
     assert all(np.isfinite(i["rel_res_true"]) and i["rel_res_true"] < 1.0 for i in info)
+
+
+def test_nearby_plane_waves_are_deflated_not_abandoned():
+    """64 plane waves at angles 0.25 deg apart are numerically dependent: the block keeps
+    fewer directions than right-hand sides and still converges every column."""
+    import paper_2603_10586_amd as q
+    c = case("rand8x8")
+    th = np.concatenate([np.linspace(0, 8, 32)] * 2)
+    v = q.rhs_plane_waves(c.ctx, c.geom, th, np.zeros(64), [0] * 32 + [1] * 32)
+    x, info, st = c.op.solve(v, restart=4000, tol=1e-8, max_iter=2000, mode=BLOCK)
+    assert st == 0 and all(i["converged"] for i in info)
+    xs, isv, _ = c.op.solve(v[:1].contiguous(), restart=2000, tol=1e-8, max_iter=2000)
+    assert info[0]["iterations"] < isv[0]["iterations"]
+    ZQR = _zqr(c)
+    vh, xh = to_host(v), to_host(x)
+    for r in (0, 17, 40, 63):
+        assert np.linalg.norm(vh[r] - ZQR @ xh[r]) <= 2e-8 * np.linalg.norm(vh[r])
 
 
 def test_block_warm_start_from_the_solution():
