@@ -1,0 +1,121 @@
+"""Parity at the full mid-size workload (32 x 32 disks, 147,456 unknowns), on sampled outputs.
+
+The oracle recomputes the product rows of a few particles from the exported factors of
+the blocks whose rows contain them (plus the particle's own self block), i.e. the same
+operator Z_QR the library applies, so the bound is accumulated FP64 rounding (1e-12).
+This covers the single-RHS kernels that the benchmark times, the 64-RHS matrix-core path,
+and the true residuals of full-size solves; operator symmetry is checked on the whole
+vector.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import compressed, discretise, greens
+
+from gpu_cases import ctx, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+_MID = {}
+
+
+def mid():
+    if not _MID:
+        import paper_2603_10586_amd as q
+        print("[gpu case] building mid 32x32 eps=1e-6", flush=True)
+        arr = W.mid(0)
+        c = ctx()
+        geom = q.Geometry(c, arr)
+        op = q.Operator(c, geom, eps=1e-6)
+        order = geom.order()
+        infos = [op.export_block(b, factors=False)[0] for b in range(op.num_blocks())]
+        _MID.update(arr=arr, disc=discretise.Discretisation(arr), geom=geom, op=op, order=order, infos=infos,
+                    internal=np.argsort(order))
+    return _MID
+
+
+SAMPLED = (0, 531, 1023)          # caller particle indices: a corner, an interior disk, the far corner
+
+
+def oracle_rows(m, p, x):
+    """(Z_QR x) restricted to the 144 rows of caller particle p (x: n or n x k)."""
+    pi = m["internal"][p]
+    order, op = m["order"], m["op"]
+    x2 = x.reshape(x.shape[0], -1)
+    y = greens.particle_self_block(m["disc"], p) @ x2[p * 144:(p + 1) * 144]
+    fac = []
+    for b, info in enumerate(m["infos"]):
+        r0, rn = info["row_first"], info["row_count"]
+        if not (r0 <= pi < r0 + rn) or info["rank"] == 0:
+            continue
+        _, Q, R = op.export_block(b)
+        local = pi - r0
+        cols = order[info["col_first"]:info["col_first"] + info["col_count"]]
+        fac.append(([p], cols, Q[local * 144:(local + 1) * 144], R))
+    out = np.zeros((x2.shape[0], x2.shape[1]), complex)
+    compressed.factor_apply(fac, x2, out)
+    return (y + out[p * 144:(p + 1) * 144]).reshape((144,) + x.shape[1:])
+
+
+def test_full_size_product_rows_match_the_oracle():
+    m = mid()
+    n = m["geom"].ndof
+    x = np.random.default_rng(21).standard_normal(n) + 1j * np.random.default_rng(22).standard_normal(n)
+    y = to_host(m["op"].apply(to_dev(x)))
+    for p in SAMPLED:
+        ref = oracle_rows(m, p, x)
+        assert np.linalg.norm(y[p * 144:(p + 1) * 144] - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_full_size_block_product_rows_match_the_oracle():
+    m = mid()
+    n = m["geom"].ndof
+    rng = np.random.default_rng(23)
+    x = rng.standard_normal((64, n)) + 1j * rng.standard_normal((64, n))
+    y = to_host(m["op"].apply(to_dev(x)))                   # 64 columns: the MFMA block path
+    for p in SAMPLED[:2]:
+        ref = oracle_rows(m, p, x.T)                         # (144, 64)
+        for r in (0, 31, 63):
+            got = y[r, p * 144:(p + 1) * 144]
+            assert np.linalg.norm(got - ref[:, r]) <= 1e-12 * np.linalg.norm(ref[:, r])
+
+
+def test_full_size_product_is_complex_symmetric():
+    """Z_QR = Z_QR^T exactly (mirrored blocks hold transposed factors): x^T Z y = y^T Z x."""
+    m = mid()
+    n = m["geom"].ndof
+    rng = np.random.default_rng(24)
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    yv = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    Zx = to_host(m["op"].apply(to_dev(x)))
+    Zy = to_host(m["op"].apply(to_dev(yv)))
+    a, b = x @ Zy, yv @ Zx
+    assert abs(a - b) <= 1e-12 * np.linalg.norm(x) * np.linalg.norm(Zy)
+
+
+def test_full_size_solves_meet_the_tolerance_on_sampled_rows():
+    """The benchmark's solve (unrestarted GMRES, one TM wave at 10 deg) and the 64-wave block
+    solve: the oracle's residual rows v_p - (Z_QR x)_p stay within tol ||v||."""
+    import paper_2603_10586_amd as q
+    m = mid()
+    inc = W.mid_incidence()
+    v = q.rhs_plane_waves(ctx(), m["geom"], inc.theta_deg, inc.phi_deg, inc.pol)
+    x, info, st = m["op"].solve(v, restart=5000, tol=1e-6, max_iter=5000)
+    assert st == 0 and info[0]["converged"] and info[0]["rel_res_true"] <= 1e-6
+    vh, xh = to_host(v)[0], to_host(x)[0]
+    for p in SAMPLED:
+        r = vh[p * 144:(p + 1) * 144] - oracle_rows(m, p, xh)
+        assert np.linalg.norm(r) <= 1e-6 * np.linalg.norm(vh)
+    sw = W.sweep(32)
+    vb = q.rhs_plane_waves(ctx(), m["geom"], sw.theta_deg, sw.phi_deg, sw.pol)
+    xb, ib, sb = m["op"].solve(vb, restart=16384, tol=1e-6, max_iter=5000, mode=q.SOLVE_BLOCK)
+    assert sb == 0 and all(i["converged"] for i in ib)
+    vbh, xbh = to_host(vb), to_host(xb)
+    for r in (0, 40):
+        res = vbh[r, 1023 * 144:] - oracle_rows(m, 1023, xbh[r])
+        assert np.linalg.norm(res) <= 1e-6 * np.linalg.norm(vbh[r])
+    # the block solution agrees with the single-vector solution of the same wave (within tol)
+    k = int(np.argmin(np.abs(sw.theta_deg - inc.theta_deg[0]) + 1e3 * (sw.pol != inc.pol[0])))
+    if abs(sw.theta_deg[k] - inc.theta_deg[0]) < 1e-12 and sw.pol[k] == inc.pol[0]:
+        assert np.linalg.norm(xbh[k] - xh) <= 1e-4 * np.linalg.norm(xh)
