@@ -123,14 +123,19 @@ qrvie_status qrvie_assemble(qrvie_ctx* ctx, const qrvie_geom* g, int32_t nr, con
                             int32_t nc, const int32_t* cols, qrvie_c128* B, int64_t ldb);
 
 /* ----------------------------------------------------------------- operator */
-enum { QRVIE_PREC_C128 = 0, QRVIE_PREC_C64 = 1, QRVIE_PREC_BF16X2 = 2 };
+enum { QRVIE_PREC_C128 = 0, QRVIE_PREC_C64 = 1, QRVIE_PREC_BF16X2 = 2, QRVIE_PREC_C64_ONLY = 3 };
 
 /*
  *   eps              per-block relative Frobenius tolerance of the low-rank
  *                    factors, ||B - Q R||_F <= eps ||B||_F (§5.2, eq. 5.3); > 0
  *   far_prec         QRVIE_PREC_C128: complex128 far factors; QRVIE_PREC_C64: in addition a
  *                    complex64 copy (rounded to nearest) used by the inner solves of
- *                    QRVIE_SOLVE_MIXED_IR, which streams half the factor bytes
+ *                    QRVIE_SOLVE_MIXED_IR, which streams half the factor bytes;
+ *                    QRVIE_PREC_C64_ONLY: only complex64 far factors (half the memory), used
+ *                    by every product with FP64 accumulation (the rounding, 2^-24 relative
+ *                    per entry, is far below eps); MIXED_IR and complex128 products are
+ *                    then refused, and exports return the complex64 values widened.
+ *                    QRVIE_PREC_BF16X2 is reserved.
  *   near_prec        storage of the self blocks: QRVIE_PREC_C128 only for now
  *   max_block_rows   far blocks with more rows are split into their child
  *                    pairs (always far); 0 = no cap (the paper's scheme)

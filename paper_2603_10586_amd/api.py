@@ -223,12 +223,13 @@ class Operator:
                                                          C.c_void_p(Zi.ctypes.data)), "export_self")
         return Z.reshape(144, 144).T, Zi.reshape(144, 144).T
 
-    def apply(self, x, prec: int = L.PREC_C128):
+    def apply(self, x, prec=None):
+        """y = Z_QR x with the operator's own far factors, or those of precision `prec`."""
         torch = _torch()
         px, ld, nrhs = _cols(x, self.geom.ndof)
         y = torch.empty_like(x)
         self.ctx.order()
-        if prec == L.PREC_C128:
+        if prec is None:
             st = self.ctx.lib.qrvie_apply(self.ctx.h, self.h, nrhs, px, ld, C.c_void_p(y.data_ptr()), ld)
         else:
             st = self.ctx.lib.qrvie_apply_prec(self.ctx.h, self.h, prec, nrhs, px, ld, C.c_void_p(y.data_ptr()), ld)

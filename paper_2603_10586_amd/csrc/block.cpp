@@ -307,9 +307,11 @@ qrvie_status profile_block(qrvie_ctx* ctx, const qrvie_op* op, int nrhs, int rep
     double acc[4] = {0, 0, 0, 0};
     for (int r = 0; r < reps; ++r) {
         (void)hipEventRecord(ev[0], s);
-        launch_strip_mfma(s, nt, op->d_mr, op->n_mr, op->d_fac, X, bw.T, op->d_tmap);
+        if (op->d_fac) launch_strip_mfma(s, nt, op->d_mr, op->n_mr, op->d_fac, X, bw.T, op->d_tmap);
+        else launch_strip_mfma(s, nt, op->d_mr, op->n_mr, op->d_fac32, X, bw.T, op->d_tmap);
         (void)hipEventRecord(ev[1], s);
-        launch_strip_mfma(s, nt, op->d_mq, op->n_mq, op->d_fac, bw.T, bw.Ylev, nullptr);
+        if (op->d_fac) launch_strip_mfma(s, nt, op->d_mq, op->n_mq, op->d_fac, bw.T, bw.Ylev, nullptr);
+        else launch_strip_mfma(s, nt, op->d_mq, op->n_mq, op->d_fac32, bw.T, bw.Ylev, nullptr);
         (void)hipEventRecord(ev[2], s);
         launch_strip_mfma(s, nt, op->d_ms, op->n_ms, op->d_self, X, bw.Yself, nullptr);
         launch_block_combine(s, nt, n, bw.Ylev, op->n_active, bw.Yself, X, Y);

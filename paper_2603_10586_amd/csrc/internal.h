@@ -100,6 +100,7 @@ struct Cgs2Desc {                   // orthonormalise the columns of Y (m x k) i
 struct PackDesc {                   // copy compact factors into panel layouts
     const c128* src; int32_t rows, cols, lds; // src (rows x cols), column-major
     c128* dst; int64_t ldd; int32_t transpose; // dst(i,j) = src(i,j) or src(j,i)
+    float2* dst32;                  // when set: complex64 panel, rounded to nearest (dst unused)
 };
 struct AsmDesc {                    // far block assembly: rows of particles r0.., cols c0..
     c128* B; int64_t ldb;
@@ -261,6 +262,8 @@ void launch_add(hipStream_t s, const c128* d, int64_t n, c128* x);
 // blocks of right-hand sides (k_block.hip); nt = P / 16 tiles of 16 right-hand sides, 1..4
 constexpr int kMaxBlockRhs = 64;
 void launch_strip_mfma(hipStream_t s, int nt, const MStrip* st, int64_t n, const c128* fac, const c128* in,
+                       c128* out, const int64_t* tmap);
+void launch_strip_mfma(hipStream_t s, int nt, const MStrip* st, int64_t n, const float2* fac, const c128* in,
                        c128* out, const int64_t* tmap);
 void launch_block_combine(hipStream_t s, int nt, int64_t n, const c128* ylev, int nlev, const c128* yself,
                           const c128* V, c128* out);

@@ -1,5 +1,6 @@
 // Blocks of right-hand sides: the compressed product Z_QR X and the preconditioner for
 // up to 64 right-hand sides at once (§5.2 products, §4 preconditioner), on FP64 MFMA.
+// Complex64 factor panels are widened to FP64 on load.
 //
 // With P right-hand sides every factor entry meets P complex multiply-adds, so the product
 // turns from HBM-bound (one right-hand side) into a sequence of small dense GEMMs: each
@@ -28,8 +29,8 @@ __device__ __forceinline__ void cmfma(v4d& re, v4d& im, c128 a, c128 b) {
     im = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, im, 0, 0, 0);
 }
 
-template <int NT>
-__global__ void __launch_bounds__(256) k_strip_mfma(const MStrip* __restrict__ strips, const c128* __restrict__ fac,
+template <int NT, typename F>
+__global__ void __launch_bounds__(256) k_strip_mfma(const MStrip* __restrict__ strips, const F* __restrict__ fac,
                                                     const c128* __restrict__ in, c128* __restrict__ out,
                                                     const int64_t* __restrict__ tmap) {
     constexpr int P = 16 * NT;
@@ -39,7 +40,7 @@ __global__ void __launch_bounds__(256) k_strip_mfma(const MStrip* __restrict__ s
     const int r0 = 16 * w;
     if (r0 >= s.nrows) return;
     const int rl = lane & 15, kq = lane >> 4;
-    const c128* A = fac + s.a_off + min(r0 + rl, s.nrows - 1);
+    const F* A = fac + s.a_off + min(r0 + rl, s.nrows - 1);
     const c128* X = in + s.in_off * P + rl;
     v4d re[NT], im[NT];
 #pragma unroll
@@ -51,7 +52,7 @@ __global__ void __launch_bounds__(256) k_strip_mfma(const MStrip* __restrict__ s
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t col = 4 * (c + u) + kq;
-            a[u] = load_stream(A + col * s.ld);
+            a[u] = widen(load_stream(A + col * s.ld));
 #pragma unroll
             for (int t = 0; t < NT; ++t) b[u][t] = X[col * P + 16 * t];
         }
@@ -64,7 +65,7 @@ __global__ void __launch_bounds__(256) k_strip_mfma(const MStrip* __restrict__ s
         const int64_t col = 4 * c + kq;
         const bool ok = col < s.ncols;
         const c128 z = make_double2(0.0, 0.0);
-        const c128 a = ok ? A[col * s.ld] : z;
+        const c128 a = ok ? widen(A[col * s.ld]) : z;
 #pragma unroll
         for (int t = 0; t < NT; ++t) cmfma(re[t], im[t], a, ok ? X[col * P + 16 * t] : z);
     }
@@ -572,7 +573,22 @@ void launch_col_norms(hipStream_t s, int rows, const c128* C, int64_t ldc, int n
 void launch_strip_mfma(hipStream_t s, int nt, const MStrip* st, int64_t n, const c128* fac, const c128* in,
                        c128* out, const int64_t* tmap) {
     if (n <= 0) return;
-    QRVIE_NT_SWITCH(nt, k_strip_mfma, dim3((unsigned)n), dim3(256), 0, s, st, fac, in, out, tmap);
+    switch (nt) {
+        case 1: hipLaunchKernelGGL((k_strip_mfma<1, c128>), dim3((unsigned)n), dim3(256), 0, s, st, fac, in, out, tmap); break;
+        case 2: hipLaunchKernelGGL((k_strip_mfma<2, c128>), dim3((unsigned)n), dim3(256), 0, s, st, fac, in, out, tmap); break;
+        case 3: hipLaunchKernelGGL((k_strip_mfma<3, c128>), dim3((unsigned)n), dim3(256), 0, s, st, fac, in, out, tmap); break;
+        default: hipLaunchKernelGGL((k_strip_mfma<4, c128>), dim3((unsigned)n), dim3(256), 0, s, st, fac, in, out, tmap); break;
+    }
+}
+void launch_strip_mfma(hipStream_t s, int nt, const MStrip* st, int64_t n, const float2* fac, const c128* in,
+                       c128* out, const int64_t* tmap) {
+    if (n <= 0) return;
+    switch (nt) {
+        case 1: hipLaunchKernelGGL((k_strip_mfma<1, float2>), dim3((unsigned)n), dim3(256), 0, s, st, fac, in, out, tmap); break;
+        case 2: hipLaunchKernelGGL((k_strip_mfma<2, float2>), dim3((unsigned)n), dim3(256), 0, s, st, fac, in, out, tmap); break;
+        case 3: hipLaunchKernelGGL((k_strip_mfma<3, float2>), dim3((unsigned)n), dim3(256), 0, s, st, fac, in, out, tmap); break;
+        default: hipLaunchKernelGGL((k_strip_mfma<4, float2>), dim3((unsigned)n), dim3(256), 0, s, st, fac, in, out, tmap); break;
+    }
 }
 void launch_block_combine(hipStream_t s, int nt, int64_t n, const c128* ylev, int nlev, const c128* yself,
                           const c128* V, c128* out) {

@@ -374,16 +374,12 @@ __global__ void __launch_bounds__(256) k_cgs2(const Cgs2Desc* descs) {
 __global__ void __launch_bounds__(256) k_pack(const PackDesc* descs) {
     const PackDesc d = descs[blockIdx.x];
     const int64_t tot = (int64_t)d.rows * d.cols;
-    if (!d.transpose) {
-        for (int64_t e = threadIdx.x; e < tot; e += 256) {
-            const int i = (int)(e % d.rows), j = (int)(e / d.rows);
-            d.dst[i + j * d.ldd] = d.src[i + (int64_t)j * d.lds];
-        }
-    } else {
-        for (int64_t e = threadIdx.x; e < tot; e += 256) {
-            const int i = (int)(e % d.rows), j = (int)(e / d.rows);
-            d.dst[j + i * d.ldd] = d.src[i + (int64_t)j * d.lds];
-        }
+    for (int64_t e = threadIdx.x; e < tot; e += 256) {
+        const int i = (int)(e % d.rows), j = (int)(e / d.rows);
+        const int64_t o = d.transpose ? j + i * d.ldd : i + j * d.ldd;
+        const c128 v = d.src[i + (int64_t)j * d.lds];
+        if (d.dst32) d.dst32[o] = make_float2((float)v.x, (float)v.y);
+        else d.dst[o] = v;
     }
 }
 

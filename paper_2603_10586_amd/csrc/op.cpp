@@ -450,7 +450,8 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
     if (!ctx || !g || !o || !out) return QRVIE_ERR_INVALID_ARG;
     *out = nullptr;
     if (!(o->eps > 0.0) || !(o->eps < 1.0)) { set_err(ctx, "op_create: eps must be in (0, 1)"); return QRVIE_ERR_INVALID_ARG; }
-    if ((o->far_prec != QRVIE_PREC_C128 && o->far_prec != QRVIE_PREC_C64) || o->near_prec != QRVIE_PREC_C128 ||
+    if ((o->far_prec != QRVIE_PREC_C128 && o->far_prec != QRVIE_PREC_C64 && o->far_prec != QRVIE_PREC_C64_ONLY) ||
+        o->near_prec != QRVIE_PREC_C128 ||
         o->share_transpose != 0 ||
         o->max_block_rows < 0) {
         set_err(ctx, "op_create: unsupported precision or option");
@@ -700,7 +701,9 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
     keep((void**)&op->d_mq, sizeof(MStrip) * std::max<size_t>(mq.size(), 1), "block Q strips");
     keep((void**)&op->d_ms, sizeof(MStrip) * std::max<size_t>(ms.size(), 1), "block self strips");
 
-    keep((void**)&op->d_fac, sizeof(c128) * (size_t)std::max<int64_t>(fcur, 1), "factor panels");
+    const bool only32 = o->far_prec == QRVIE_PREC_C64_ONLY;
+    if (only32) keep((void**)&op->d_fac32, sizeof(float2) * (size_t)std::max<int64_t>(fcur, 1), "complex64 panels");
+    else keep((void**)&op->d_fac, sizeof(c128) * (size_t)std::max<int64_t>(fcur, 1), "factor panels");
     keep((void**)&op->d_tmap, sizeof(int64_t) * std::max<size_t>(tmap.size(), 1), "rank map");
     keep((void**)&op->d_rstrips, sizeof(RStrip) * std::max<size_t>(rstr.size(), 1), "R strips");
     keep((void**)&op->d_qstrips, sizeof(QStrip) * std::max<size_t>(qstr.size(), 1), "Q strips");
@@ -729,10 +732,19 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
             const Factor& f = bld.fac[i];
             const int32_t mm = b.rn * kNp, nn = b.cn * kNp, r = f.rank;
             const size_t j = (size_t)b.mirror;
-            pd.push_back(PackDesc{f.Q, mm, r, mm, op->d_fac + op->q_off[i], mm, 0});           // Q_IJ
-            pd.push_back(PackDesc{f.R, r, nn, r, op->d_fac + op->r_off[i], op->r_ld[i], 0});   // R_IJ
-            pd.push_back(PackDesc{f.R, r, nn, r, op->d_fac + op->q_off[j], nn, 1});            // Q_JI = R_IJ^T
-            pd.push_back(PackDesc{f.Q, mm, r, mm, op->d_fac + op->r_off[j], op->r_ld[j], 1});  // R_JI = Q_IJ^T
+            // destination: complex128 panels, or their complex64 rounding when only those are kept
+            auto at = [&](int64_t off, int64_t ld, int32_t tr) {
+                return only32 ? PackDesc{nullptr, 0, 0, 0, nullptr, ld, tr, op->d_fac32 + off}
+                              : PackDesc{nullptr, 0, 0, 0, op->d_fac + off, ld, tr, nullptr};
+            };
+            auto with = [](PackDesc d, const c128* src, int32_t rows, int32_t cols, int32_t lds) {
+                d.src = src; d.rows = rows; d.cols = cols; d.lds = lds;
+                return d;
+            };
+            pd.push_back(with(at(op->q_off[i], mm, 0), f.Q, mm, r, mm));            // Q_IJ
+            pd.push_back(with(at(op->r_off[i], op->r_ld[i], 0), f.R, r, nn, r));    // R_IJ
+            pd.push_back(with(at(op->q_off[j], nn, 1), f.R, r, nn, r));             // Q_JI = R_IJ^T
+            pd.push_back(with(at(op->r_off[j], op->r_ld[j], 1), f.Q, mm, r, mm));   // R_JI = Q_IJ^T
         }
         PackDesc* dpd = nullptr;
         if (!pd.empty()) {

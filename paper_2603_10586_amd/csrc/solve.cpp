@@ -364,7 +364,7 @@ qrvie_status Group::finish(c128* const* x, const std::vector<c128*>* src, qrvie_
 qrvie_status solve_group(qrvie_ctx* ctx, const qrvie_op* op, int na, const c128* const* v, c128* const* x,
                          const qrvie_solve_opts* o, qrvie_solve_info* info) {
     const double t0 = now_s();
-    Group G(ctx, op, o, na, false);
+    Group G(ctx, op, o, na, !op->d_fac);   // an operator with only complex64 panels uses them
     CHECK(G.init());
     hipStream_t s = ctx->stream;
     const qrvie_geom* g = op->g;
@@ -460,13 +460,13 @@ extern "C" {
 
 qrvie_status qrvie_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const qrvie_c128* x, int64_t ldx,
                          qrvie_c128* y, int64_t ldy) {
-    return qrvie_apply_prec(ctx, op, QRVIE_PREC_C128, nrhs, x, ldx, y, ldy);
+    return qrvie_apply_prec(ctx, op, op && !op->d_fac ? QRVIE_PREC_C64 : QRVIE_PREC_C128, nrhs, x, ldx, y, ldy);
 }
 
 qrvie_status qrvie_apply_prec(qrvie_ctx* ctx, const qrvie_op* op, int32_t prec, int32_t nrhs, const qrvie_c128* x,
                               int64_t ldx, qrvie_c128* y, int64_t ldy) {
     CHECK(check_vec_args(ctx, op, nrhs, x, ldx, y, ldy, "apply"));
-    if (prec != QRVIE_PREC_C128 && !(prec == QRVIE_PREC_C64 && op->d_fac32)) {
+    if (!((prec == QRVIE_PREC_C128 && op->d_fac) || (prec == QRVIE_PREC_C64 && op->d_fac32))) {
         set_err(ctx, "apply: the operator holds no far factors of the requested precision");
         return QRVIE_ERR_INVALID_ARG;
     }
@@ -474,7 +474,7 @@ qrvie_status qrvie_apply_prec(qrvie_ctx* ctx, const qrvie_op* op, int32_t prec, 
     const int64_t n = op->g->ndof();
     hipStream_t s = ctx->stream;
     Work w(ctx);
-    if (!lo && nrhs >= 16) {
+    if (nrhs >= 16) {
         // blocks of up to 64 right-hand sides on the MFMA kernels
         BlockWork bw;
         CHECK(bw.init(w, op));
@@ -485,7 +485,7 @@ qrvie_status qrvie_apply_prec(qrvie_ctx* ctx, const qrvie_op* op, int32_t prec, 
             const int cnt = std::min(kMaxBlockRhs, nrhs - r0);
             const int nt = (cnt + 15) / 16;
             launch_gather_block(s, nt, op->g->N, op->g->d_i2c, (const c128*)x + (int64_t)r0 * ldx, ldx, cnt, X);
-            block_product(op, s, bw, nt, X, nullptr, Y, nullptr);
+            block_product(op, s, bw, nt, X, nullptr, Y, nullptr, lo);
             launch_scatter_block(s, nt, op->g->N, op->g->d_i2c, Y, (c128*)y + (int64_t)r0 * ldy, ldy, cnt);
         }
         CHECK(hip_check(ctx, hipGetLastError(), "apply launch"));
@@ -537,7 +537,7 @@ qrvie_status qrvie_apply_prec(qrvie_ctx* ctx, const qrvie_op* op, int32_t prec, 
 qrvie_status qrvie_op_profile_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t prec, int32_t reps, double* ms,
                                     int64_t* bytes) {
     if (!ctx || !op || reps < 1 || !ms || !bytes) return QRVIE_ERR_INVALID_ARG;
-    if (prec != QRVIE_PREC_C128 && !(prec == QRVIE_PREC_C64 && op->d_fac32)) {
+    if (!((prec == QRVIE_PREC_C128 && op->d_fac) || (prec == QRVIE_PREC_C64 && op->d_fac32))) {
         set_err(ctx, "profile: the operator holds no far factors of the requested precision");
         return QRVIE_ERR_INVALID_ARG;
     }
@@ -634,6 +634,19 @@ qrvie_status qrvie_op_export_block(const qrvie_op* op, int64_t b, qrvie_block_in
         info->col_first = e.c0; info->col_count = e.cn;
         info->rel_err = op->relerr[b];
     }
+    if (!op->d_fac && (Q || R) && r > 0) {
+        // complex64 panels: copy down, widen on the host
+        std::vector<float2> tq(Q ? (size_t)m * r : 0), tr(R ? (size_t)r * n : 0);
+        if (Q) CHECK(hip_check(ctx, hipMemcpyAsync(tq.data(), op->d_fac32 + op->q_off[b], sizeof(float2) * m * r,
+                                                   hipMemcpyDeviceToHost, ctx->stream), "export Q"));
+        if (R) CHECK(hip_check(ctx, hipMemcpy2DAsync(tr.data(), sizeof(float2) * r, op->d_fac32 + op->r_off[b],
+                                                     sizeof(float2) * op->r_ld[b], sizeof(float2) * r, (size_t)n,
+                                                     hipMemcpyDeviceToHost, ctx->stream), "export R"));
+        CHECK(hip_check(ctx, hipStreamSynchronize(ctx->stream), "export"));
+        for (size_t e = 0; e < tq.size(); ++e) Q[e] = qrvie_c128{(double)tq[e].x, (double)tq[e].y};
+        for (size_t e = 0; e < tr.size(); ++e) R[e] = qrvie_c128{(double)tr[e].x, (double)tr[e].y};
+        return QRVIE_OK;
+    }
     if (Q && r > 0)
         CHECK(hip_check(ctx, hipMemcpyAsync(Q, op->d_fac + op->q_off[b], sizeof(c128) * m * r, hipMemcpyDeviceToHost,
                                             ctx->stream), "export Q"));
@@ -682,7 +695,7 @@ qrvie_status qrvie_solve(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const
         set_err(ctx, "solve: invalid options");
         return QRVIE_ERR_INVALID_ARG;
     }
-    if (o->mode == QRVIE_SOLVE_MIXED_IR && !op->d_fac32) {
+    if (o->mode == QRVIE_SOLVE_MIXED_IR && !(op->d_fac32 && op->d_fac)) {
         set_err(ctx, "solve: QRVIE_SOLVE_MIXED_IR needs an operator built with far_prec = QRVIE_PREC_C64");
         return QRVIE_ERR_INVALID_ARG;
     }

@@ -52,11 +52,17 @@ struct BlockWork {
 
 // out = V - Z X (or Z X when V is null), Z_out = Z_D^-1 out (optional); X, V, out, Z_out are
 // n x P interleaved blocks, P = 16 nt, internal order (FP64 MFMA kernels).
+// lo: far factors from the complex64 panels (always so when the operator keeps only those).
 inline void block_product(const qrvie_op* op, hipStream_t s, const BlockWork& bw, int nt, const c128* X, const c128* V,
-                   c128* out, c128* zout) {
+                          c128* out, c128* zout, bool lo = false) {
     const int64_t n = op->g->ndof();
-    launch_strip_mfma(s, nt, op->d_mr, op->n_mr, op->d_fac, X, bw.T, op->d_tmap);
-    launch_strip_mfma(s, nt, op->d_mq, op->n_mq, op->d_fac, bw.T, bw.Ylev, nullptr);
+    if (lo || !op->d_fac) {
+        launch_strip_mfma(s, nt, op->d_mr, op->n_mr, op->d_fac32, X, bw.T, op->d_tmap);
+        launch_strip_mfma(s, nt, op->d_mq, op->n_mq, op->d_fac32, bw.T, bw.Ylev, nullptr);
+    } else {
+        launch_strip_mfma(s, nt, op->d_mr, op->n_mr, op->d_fac, X, bw.T, op->d_tmap);
+        launch_strip_mfma(s, nt, op->d_mq, op->n_mq, op->d_fac, bw.T, bw.Ylev, nullptr);
+    }
     launch_strip_mfma(s, nt, op->d_ms, op->n_ms, op->d_self, X, bw.Yself, nullptr);
     launch_block_combine(s, nt, n, bw.Ylev, op->n_active, bw.Yself, V, out);
     if (zout) launch_strip_mfma(s, nt, op->d_ms, op->n_ms, op->d_pinv, out, zout, nullptr);

@@ -101,3 +101,58 @@ def test_reduced_precision_requests_without_a_c64_copy_are_refused():
     with pytest.raises(q.QrvieError) as e:
         c.op.apply(v, prec=PREC_C64)
     assert e.value.status == 1
+
+
+C64_ONLY = 3
+
+
+@pytest.mark.parametrize("nrhs", [1, 3, 16, 37])
+def test_c64_only_operator_products_match_the_oracle(nrhs):
+    """Only complex64 panels are kept; every product path (single, grouped, MFMA block)
+    uses them, and exports return those values widened."""
+    c = case("rand6x7", far_prec=C64_ONLY)
+    n = c.geom.ndof
+    rng = np.random.default_rng(60 + nrhs)
+    x = rng.standard_normal((nrhs, n)) + 1j * rng.standard_normal((nrhs, n))
+    y = to_host(c.op.apply(to_dev(x)))
+    sb = greens.self_blocks(c.disc)
+    ref = compressed.compressed_apply(sb, [(f[0], f[1], f[2], f[3]) for f in c.factors()], x.T).T
+    for r in range(nrhs):
+        assert np.linalg.norm(y[r] - ref[r]) <= 1e-12 * np.linalg.norm(ref[r])
+
+
+def test_c64_only_panels_equal_the_rounded_complex128_panels():
+    """The same compression packed straight to complex64 gives the copy's values exactly."""
+    a = case("rand6x7", far_prec=C64_ONLY)
+    b = case("rand6x7", far_prec=PREC_C64)
+    x = to_dev(np.random.default_rng(70).standard_normal(a.geom.ndof) * (1 - 1j))
+    assert np.array_equal(to_host(a.op.apply(x)), to_host(b.op.apply(x, prec=PREC_C64)))
+    assert a.op.stats()["device_bytes"] < b.op.stats()["device_bytes"]
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+def test_c64_only_solves_match_lu_of_the_stored_operator(mode):
+    import paper_2603_10586_amd as q
+    c = case("rand6x7", far_prec=C64_ONLY)
+    th = np.linspace(-30, 30, 6)
+    v = q.rhs_plane_waves(c.ctx, c.geom, th, np.zeros(6), [0, 1] * 3)
+    x, info, st = c.op.solve(v, restart=500, tol=1e-10, max_iter=2000, mode=mode)
+    assert st == 0 and all(i["converged"] for i in info)
+    sb = greens.self_blocks(c.disc)
+    ZQR = compressed.dense_from_factors(sb, [(f[0], f[1], f[2], f[3]) for f in c.factors()])
+    vh, xh = to_host(v), to_host(x)
+    ref = np.linalg.solve(ZQR, vh.T).T
+    for r in range(6):
+        assert np.linalg.norm(xh[r] - ref[r]) <= 1e-7 * np.linalg.norm(ref[r])
+
+
+def test_c64_only_refuses_complex128_requests():
+    import paper_2603_10586_amd as q
+    c = case("rand6x7", far_prec=C64_ONLY)
+    v = q.rhs_plane_waves(c.ctx, c.geom, [0.0], [0.0], [1])
+    with pytest.raises(q.QrvieError) as e:
+        c.op.solve(v, mode=MIXED_IR)
+    assert e.value.status == 1
+    with pytest.raises(q.QrvieError) as e:
+        c.op.apply(v, prec=0)
+    assert e.value.status == 1
