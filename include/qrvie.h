@@ -141,6 +141,7 @@ enum { QRVIE_PREC_C128 = 0, QRVIE_PREC_C64 = 1, QRVIE_PREC_BF16X2 = 2, QRVIE_PRE
  *                    pairs (always far); 0 = no cap (the paper's scheme)
  *   share_transpose  reserved, must be 0
  *   seed             seed of the random sketches used by compression
+ *   verbose          1: print one progress line per compression chunk to stderr
  */
 typedef struct {
     double eps;
@@ -149,6 +150,7 @@ typedef struct {
     int64_t max_block_rows;
     int32_t share_transpose;
     uint64_t seed;
+    int32_t verbose;
 } qrvie_compress_opts;
 
 #define QRVIE_MAX_LEVELS 24
@@ -275,6 +277,12 @@ typedef struct {
     double  inner_tol;    /* MIXED_IR: relative tolerance of each correction solve, in (0, 1);
                              0 = automatic, 0.25 tol ||v|| / ||r|| (one correction reaches tol
                              unless the factor rounding dominates).  Ignored in FP64 mode. */
+    int32_t verbose;      /* BLOCK: 1 prints one progress line per 10 block steps and per cycle
+                             to stderr */
+    int32_t block_width;  /* BLOCK: right-hand sides per block, 1..64 (0 = 64).  Narrower blocks
+                             need fewer basis vectors in total for the same accuracy, so a
+                             block that must fit a fixed basis without restarting can be
+                             split. */
 } qrvie_solve_opts;
 
 typedef struct {

@@ -26,7 +26,8 @@ class ArrayDescC(C.Structure):
 
 class CompressOpts(C.Structure):
     _fields_ = [("eps", C.c_double), ("far_prec", C.c_int32), ("near_prec", C.c_int32),
-                ("max_block_rows", C.c_int64), ("share_transpose", C.c_int32), ("seed", C.c_uint64)]
+                ("max_block_rows", C.c_int64), ("share_transpose", C.c_int32), ("seed", C.c_uint64),
+                ("verbose", C.c_int32)]
 
 
 class OpStats(C.Structure):
@@ -47,7 +48,8 @@ class BlockInfo(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_iter", C.c_int32), ("mode", C.c_int32), ("tol", C.c_double),
-                ("use_x0", C.c_int32), ("inner_tol", C.c_double)]
+                ("use_x0", C.c_int32), ("inner_tol", C.c_double), ("verbose", C.c_int32),
+                ("block_width", C.c_int32)]
 
 
 class SolveInfo(C.Structure):

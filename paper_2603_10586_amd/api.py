@@ -161,10 +161,10 @@ class Operator:
     """The compressed interaction operator Z_QR with its block-diagonal preconditioner."""
 
     def __init__(self, ctx: Context, geom: Geometry, eps: float = 1e-6, max_block_rows: int = 0, seed: int = 0,
-                 far_prec: int = L.PREC_C128):
+                 far_prec: int = L.PREC_C128, verbose: bool = False):
         self.ctx, self.geom = ctx, geom
         o = L.CompressOpts(eps=eps, far_prec=far_prec, near_prec=L.PREC_C128, max_block_rows=max_block_rows,
-                           share_transpose=0, seed=seed)
+                           share_transpose=0, seed=seed, verbose=1 if verbose else 0)
         self.opts = o
         h = C.c_void_p()
         ctx.check(ctx.lib.qrvie_op_create(ctx.h, geom.h, C.byref(o), C.byref(h)), "op_create")
@@ -264,12 +264,12 @@ class Operator:
         return z
 
     def solve(self, v, restart: int = 30, tol: float = 1e-8, max_iter: int = 10000, x0=None,
-              mode: int = L.SOLVE_FP64, inner_tol: float = 0.0):
+              mode: int = L.SOLVE_FP64, inner_tol: float = 0.0, verbose: bool = False, block_width: int = 0):
         torch = _torch()
         pv, ld, nrhs = _cols(v, self.geom.ndof)
         x = torch.zeros_like(v) if x0 is None else x0.clone()
         o = L.SolveOpts(restart=restart, max_iter=max_iter, mode=mode, tol=tol, use_x0=0 if x0 is None else 1,
-                        inner_tol=inner_tol)
+                        inner_tol=inner_tol, verbose=1 if verbose else 0, block_width=block_width)
         infos = (L.SolveInfo * nrhs)()
         self.ctx.order()
         st = self.ctx.check(self.ctx.lib.qrvie_solve(self.ctx.h, self.h, nrhs, pv, ld, C.c_void_p(x.data_ptr()), ld,

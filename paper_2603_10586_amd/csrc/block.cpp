@@ -19,6 +19,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -412,6 +413,13 @@ qrvie_status solve_block(qrvie_ctx* ctx, const qrvie_op* op, int na, const c128*
             tres[c] = B.hbuf[c] / bnorm[c];
             all = all && tres[c] <= o->tol;
         }
+        if (o->verbose) {
+            double worst = 0.0;
+            for (int c = 0; c < p; ++c) worst = std::max(worst, tres[c]);
+            std::fprintf(stderr, "[qrvie] cycle %d start after %d block steps: worst true residual %.3e, %.1f s\n",
+                         cycles, steps_total, worst, now_s() - t0);
+            std::fflush(stderr);
+        }
         if (all || steps_total >= o->max_iter) break;
         CHECK(B.first_block(pvnorm));
         if (B.q == 0) { *broke = true; break; }
@@ -457,9 +465,16 @@ qrvie_status solve_block(qrvie_ctx* ctx, const qrvie_op* op, int na, const c128*
             ++steps_total;
             const bool breakdown = B.hint[0] || B.hint[1];
             bool met = true;
+            double worst = 0.0;
             for (int c = 0; c < p; ++c) {
                 est[c] = B.hbuf[c] / pvnorm[c];
                 met = met && est[c] <= ptol[c];
+                worst = std::max(worst, est[c]);
+            }
+            if (o->verbose && (steps_total % 10 == 0 || met || breakdown)) {
+                std::fprintf(stderr, "[qrvie] block step %d (cycle %d, width %d): worst estimate %.3e, %.1f s\n",
+                             steps_total, cycles, q, worst, now_s() - t0);
+                std::fflush(stderr);
             }
             if (met || breakdown) {
                 // candidate X + V Y, accepted when every true residual meets tol

@@ -12,6 +12,7 @@
 // misses eps is redone with a wider sketch.  Only the pairs (I, J) with I before J are
 // compressed; (J, I) stores the transposed factors, so Z_QR is exactly symmetric like Z.
 #include <algorithm>
+#include <cstdio>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -544,6 +545,8 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
     {
         std::vector<int32_t> ids, kw;
         int64_t acc = 0;
+        size_t nprim = 0, ndone = 0;
+        for (const BlockRec& b : bld.blocks) nprim += b.primary ? 1 : 0;
         for (size_t i = 0; i <= NB; ++i) {
             bool flush = (i == NB);
             if (!flush) {
@@ -564,6 +567,11 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
                 if (st != QRVIE_OK) {
                     for (auto& sg : bld.segments) dfree(ctx, sg.first, sg.second);
                     return fail(st);
+                }
+                ndone += ids.size();
+                if (o->verbose) {
+                    std::fprintf(stderr, "[qrvie] compressed %zu / %zu blocks (%.1f s)\n", ndone, nprim, now_s() - t1);
+                    std::fflush(stderr);
                 }
             }
             ids.clear();

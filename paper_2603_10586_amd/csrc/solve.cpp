@@ -691,7 +691,7 @@ qrvie_status qrvie_solve(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const
     CHECK(check_vec_args(ctx, op, nrhs, v, ldv, x, ldx, "solve"));
     if (!o || o->restart < 1 || o->restart > 16384 || o->max_iter < 1 || !(o->tol > 0.0) ||
         (o->mode != QRVIE_SOLVE_FP64 && o->mode != QRVIE_SOLVE_MIXED_IR && o->mode != QRVIE_SOLVE_BLOCK) ||
-        !(o->inner_tol >= 0.0 && o->inner_tol < 1.0)) {
+        !(o->inner_tol >= 0.0 && o->inner_tol < 1.0) || o->block_width < 0 || o->block_width > kMaxBlockRhs) {
         set_err(ctx, "solve: invalid options");
         return QRVIE_ERR_INVALID_ARG;
     }
@@ -701,8 +701,9 @@ qrvie_status qrvie_solve(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const
     }
     qrvie_status overall = QRVIE_OK;
     if (o->mode == QRVIE_SOLVE_BLOCK) {
-        for (int r0 = 0; r0 < nrhs; r0 += kMaxBlockRhs) {
-            const int cnt = std::min(kMaxBlockRhs, nrhs - r0);
+        const int width = o->block_width > 0 ? o->block_width : kMaxBlockRhs;
+        for (int r0 = 0; r0 < nrhs; r0 += width) {
+            const int cnt = std::min(width, nrhs - r0);
             bool broke = false;
             qrvie_solve_info* inf = info ? info + r0 : nullptr;
             qrvie_status st = solve_block(ctx, op, cnt, (const c128*)v + (int64_t)r0 * ldv, ldv,
