@@ -226,15 +226,30 @@ struct Builder {
             CHECK(ar.upload(&dtd, td, "gemm tiles"));
             CHECK(ar.upload(&dtmn, tmn, "gemm tiles"));
             launch_gemm(s, 2, dgd, dtd, dtmn, (int64_t)td.size());
-            // ||B||^2
+            // ||B||^2: every block split into pieces of at most 1 M entries (one workgroup each),
+            // then a fixed-order sum per block
             std::vector<const c128*> ptr;
             std::vector<int64_t> len;
-            for (size_t i : sk) { ptr.push_back(dB + boff[i]); len.push_back(m[i] * n[i]); }
-            const c128** dptr; int64_t* dlen; double* dn2;
+            std::vector<int32_t> pfirst, pcount;
+            constexpr int64_t kPiece = (int64_t)1 << 20;
+            for (size_t i : sk) {
+                pfirst.push_back((int32_t)ptr.size());
+                const int64_t tot = m[i] * n[i];
+                for (int64_t o = 0; o < tot; o += kPiece) {
+                    ptr.push_back(dB + boff[i] + o);
+                    len.push_back(std::min(kPiece, tot - o));
+                }
+                pcount.push_back((int32_t)ptr.size() - pfirst.back());
+            }
+            const c128** dptr; int64_t* dlen; double *dpn2, *dn2; int32_t *dpf, *dpc;
             CHECK(ar.upload(&dptr, ptr, "frob ptrs"));
             CHECK(ar.upload(&dlen, len, "frob lens"));
+            CHECK(ar.upload(&dpf, pfirst, "frob pieces"));
+            CHECK(ar.upload(&dpc, pcount, "frob pieces"));
+            CHECK(ar.alloc(&dpn2, ptr.size(), "frob partials"));
             CHECK(ar.alloc(&dn2, sk.size(), "frob out"));
-            launch_frob2(s, dptr, dlen, dn2, (int)sk.size());
+            launch_frob2(s, dptr, dlen, dpn2, (int)ptr.size());
+            launch_sum_partials(s, dpn2, dpf, dpc, dn2, (int)sk.size());
             // orthonormal basis of Y
             std::vector<Cgs2Desc> cd;
             int32_t* dkept;
@@ -539,9 +554,17 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
     bld.fac.resize(NB);
 
     // compress primary blocks in chunks bounded by the materialised block bytes
-    const int64_t chunk_elems = (int64_t)(std::min<double>(8.0 * (1ull << 30),
-                                          ctx->budget ? std::max<double>(2.56e8, (double)(ctx->budget - ctx->in_use) / 4.0)
-                                                      : 8.0 * (1ull << 30)) / sizeof(c128));
+    // (an eighth of the free device memory, or of the remaining budget, at most 48 GiB: the
+    // one-workgroup-per-block kernels of the sketch path are better used with many blocks,
+    // and concurrent builds on one device still leave room for each other)
+    double room = 8.0 * (1ull << 30);
+    {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) room = (double)free_b;
+        if (ctx->budget) room = std::min(room, (double)(ctx->budget - ctx->in_use));
+    }
+    const int64_t chunk_elems =
+        (int64_t)(std::min(48.0 * (1ull << 30), std::max(2.56e8, room / 8.0)) / sizeof(c128));
     {
         std::vector<int32_t> ids, kw;
         int64_t acc = 0;
