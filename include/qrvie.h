@@ -311,6 +311,79 @@ qrvie_status qrvie_solve(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs,
                          const qrvie_c128* v, int64_t ldv, qrvie_c128* x, int64_t ldx,
                          const qrvie_solve_opts* opts, qrvie_solve_info* info);
 
+/* ------------------------------------------------------------------ server */
+/*
+ * Continuous-batching solve server on one device.  Requests (an array, 1..64 plane waves
+ * and a tolerance) may be submitted at any time from any thread.  A request is admitted
+ * when one of `slots` workers is free and its device footprint (operator + solver, from
+ * qrvie_op_footprint_estimate and qrvie_solve_footprint_estimate, computed before
+ * anything else is allocated) fits `hbm_budget` next to the admitted requests and the
+ * cached operators; requests are taken in arrival order, but one that does not fit yet
+ * does not block later ones that do.  Each worker has its own context and default-
+ * priority stream, so admitted requests run concurrently on the device.  Operators are
+ * compressed once per geometry (same centres, radii, heights, permittivities, lattice
+ * sites and wavelength) and kept resident, at most `op_cache` of them, evicted least
+ * recently used when their bytes are needed.  A request's result does not depend on what
+ * else runs (the kernels are deterministic and share no mutable state).
+ */
+typedef struct qrvie_server qrvie_server;
+
+typedef struct {
+    int32_t  slots;          /* concurrent requests, 1..16 */
+    size_t   hbm_budget;     /* bytes that admitted requests and cached operators may hold */
+    double   eps;            /* compression tolerance of every operator (qrvie_compress_opts.eps) */
+    int32_t  restart;        /* solve options of every request (qrvie_solve_opts) */
+    int32_t  max_iter;
+    int32_t  mode;           /* QRVIE_SOLVE_FP64 or QRVIE_SOLVE_BLOCK */
+    int32_t  block_width;
+    int32_t  op_cache;       /* operators kept resident after their request, >= 0 */
+    uint64_t seed;           /* compression sketch seed */
+} qrvie_server_opts;
+
+typedef struct {
+    int64_t submitted, completed, failed, refused, running, queued;
+    int64_t ops_built, cache_hits, evictions, rhs_solved;
+    double  latency_p50_s, latency_p99_s;     /* arrival (submit) to completion, completed requests */
+    double  queue_wait_p50_s;                  /* arrival to admission */
+    double  makespan_s;                        /* first arrival to last completion */
+    double  requests_per_s, rhs_solves_per_s;  /* completed over the makespan */
+    size_t  peak_bytes, in_use_bytes;          /* admitted + cached footprint (estimates) */
+} qrvie_server_stats;
+
+/* Start the workers on HIP device `hip_device`.  Invalid options: QRVIE_ERR_INVALID_ARG. */
+qrvie_status qrvie_server_create(int hip_device, const qrvie_server_opts* opts, qrvie_server** out);
+/*
+ * Submit a request; the array description and angle arrays are HOST data copied during the
+ * call.  *ticket identifies it.  A request whose footprint exceeds hbm_budget is refused
+ * (QRVIE_ERR_QUEUE_FULL, no ticket); invalid input gives the status of qrvie_geom_create or
+ * QRVIE_ERR_INVALID_ARG.
+ */
+qrvie_status qrvie_server_submit(qrvie_server* srv, const qrvie_array_desc* array, int32_t nrhs,
+                                 const double* theta_deg, const double* phi_deg, const int32_t* pol,
+                                 double tol, uint64_t* ticket);
+/* *done = 1 when the request has finished (successfully or not). */
+qrvie_status qrvie_server_poll(qrvie_server* srv, uint64_t ticket, int32_t* done);
+/* Block until the request finishes or timeout_s passes (< 0: no limit); *done as in poll. */
+qrvie_status qrvie_server_wait(qrvie_server* srv, uint64_t ticket, double timeout_s, int32_t* done);
+/*
+ * Copy a finished request's solution to the HOST buffer x (n x nrhs column-major, ldx >= n,
+ * n = 144 x particles, caller order) and its per-RHS info (host array of nrhs, may be NULL),
+ * then release the request.  Returns the request's own status (QRVIE_OK, QRVIE_NOT_CONVERGED
+ * or the error that ended it); QRVIE_ERR_INVALID_ARG for an unknown, released or unfinished
+ * ticket.
+ */
+qrvie_status qrvie_server_fetch(qrvie_server* srv, uint64_t ticket, qrvie_c128* x, int64_t ldx,
+                                qrvie_solve_info* info);
+qrvie_status qrvie_server_get_stats(qrvie_server* srv, qrvie_server_stats* out);
+/* Arrival (submission), admission and completion times of a request not yet fetched, in
+ * seconds on the server's steady clock (admitted/done are -1 until they happen). */
+qrvie_status qrvie_server_request_times(qrvie_server* srv, uint64_t ticket, double* arrival_s,
+                                        double* admitted_s, double* done_s);
+/* Last error text of the server (submission or request failures). */
+const char*  qrvie_server_last_error(qrvie_server* srv);
+/* Finish the running requests, cancel the queued ones, free every operator and context. */
+void         qrvie_server_destroy(qrvie_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -60,6 +60,21 @@ class SolveInfo(C.Structure):
                 ("n_refine", C.c_int32)]
 
 
+class ServerOptsC(C.Structure):
+    _fields_ = [("slots", C.c_int32), ("hbm_budget", C.c_size_t), ("eps", C.c_double), ("restart", C.c_int32),
+                ("max_iter", C.c_int32), ("mode", C.c_int32), ("block_width", C.c_int32), ("op_cache", C.c_int32),
+                ("seed", C.c_uint64)]
+
+
+class ServerStatsC(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64), ("refused", C.c_int64),
+                ("running", C.c_int64), ("queued", C.c_int64), ("ops_built", C.c_int64), ("cache_hits", C.c_int64),
+                ("evictions", C.c_int64), ("rhs_solved", C.c_int64), ("latency_p50_s", C.c_double),
+                ("latency_p99_s", C.c_double), ("queue_wait_p50_s", C.c_double), ("makespan_s", C.c_double),
+                ("requests_per_s", C.c_double), ("rhs_solves_per_s", C.c_double), ("peak_bytes", C.c_size_t),
+                ("in_use_bytes", C.c_size_t)]
+
+
 P = C.c_void_p
 PP = C.POINTER(C.c_void_p)
 I32 = C.c_int32
@@ -94,9 +109,32 @@ SIGNATURES = {
     "qrvie_rhs_plane_waves": (ST, [P, P, I32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(I32), P, I64]),
     "qrvie_solve": (ST, [P, P, I32, P, I64, P, I64, C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),
     "qrvie_solve_footprint_estimate": (ST, [P, P, I32, C.POINTER(SolveOpts), C.POINTER(C.c_size_t)]),
+    "qrvie_server_create": (ST, [C.c_int, C.POINTER(ServerOptsC), PP]),
+    "qrvie_server_submit": (ST, [P, C.POINTER(ArrayDescC), I32, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                 C.POINTER(I32), C.c_double, C.POINTER(C.c_uint64)]),
+    "qrvie_server_poll": (ST, [P, C.c_uint64, C.POINTER(I32)]),
+    "qrvie_server_wait": (ST, [P, C.c_uint64, C.c_double, C.POINTER(I32)]),
+    "qrvie_server_fetch": (ST, [P, C.c_uint64, P, I64, C.POINTER(SolveInfo)]),
+    "qrvie_server_get_stats": (ST, [P, C.POINTER(ServerStatsC)]),
+    "qrvie_server_request_times": (ST, [P, C.c_uint64, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double)]),
+    "qrvie_server_last_error": (C.c_char_p, [P]),
+    "qrvie_server_destroy": (None, [P]),
 }
 
 _lib = None
+
+
+def _torch_runtime_first():
+    """PyTorch ships its own HIP runtime next to the one this library links.  Both can serve
+    one process, but only if torch's initialises first (otherwise torch reports no device),
+    so a GPU-enabled torch is initialised before the library can make any HIP call."""
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        torch.cuda.init()
 
 
 def load() -> C.CDLL:
@@ -104,6 +142,7 @@ def load() -> C.CDLL:
     global _lib
     if _lib is not None:
         return _lib
+    _torch_runtime_first()
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2603_10586_amd.build`")
     lib = C.CDLL(LIB_PATH)

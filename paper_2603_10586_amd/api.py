@@ -67,6 +67,29 @@ def _dptr(a: np.ndarray, ctype):
     return a.ctypes.data_as(C.POINTER(ctype))
 
 
+def array_desc(array):
+    """qrvie_array_desc of an array object, and the numpy buffers it points into (keep them)."""
+    keep = dict(
+        centers=np.ascontiguousarray(array.centers, dtype=np.float64),
+        radius=np.ascontiguousarray(array.radius, dtype=np.float64),
+        height=np.ascontiguousarray(array.height, dtype=np.float64),
+        eps=np.ascontiguousarray(np.asarray(array.eps_r, dtype=np.complex128).reshape(-1)),
+        ij=np.ascontiguousarray(array.lattice_ij, dtype=np.int32),
+    )
+    d = L.ArrayDescC()
+    d.n = int(keep["centers"].shape[0])
+    d.centers = _dptr(keep["centers"], C.c_double)
+    d.radius = _dptr(keep["radius"], C.c_double)
+    d.height = _dptr(keep["height"], C.c_double)
+    d.eps_r = keep["eps"].ctypes.data_as(C.POINTER(L.C128))
+    d.n_eps = int(keep["eps"].shape[0])
+    d.lattice_ij = _dptr(keep["ij"], C.c_int32)
+    d.pitch = float(getattr(array, "pitch", 0.0))
+    d.wavelength = float(getattr(array, "wavelength", 1.0))
+    d.cells_per_particle = int(getattr(array, "cells_per_particle", 48))
+    return d, keep
+
+
 class Geometry:
     """An array of disks: any object with centers, radius, height, eps_r, lattice_ij,
     pitch, wavelength and cells_per_particle attributes (numpy arrays)."""
@@ -74,25 +97,7 @@ class Geometry:
     def __init__(self, ctx: Context, array):
         self.ctx = ctx
         lib = ctx.lib
-        self._keep = dict(
-            centers=np.ascontiguousarray(array.centers, dtype=np.float64),
-            radius=np.ascontiguousarray(array.radius, dtype=np.float64),
-            height=np.ascontiguousarray(array.height, dtype=np.float64),
-            eps=np.ascontiguousarray(np.asarray(array.eps_r, dtype=np.complex128).reshape(-1)),
-            ij=np.ascontiguousarray(array.lattice_ij, dtype=np.int32),
-        )
-        k = self._keep
-        d = L.ArrayDescC()
-        d.n = int(k["centers"].shape[0])
-        d.centers = _dptr(k["centers"], C.c_double)
-        d.radius = _dptr(k["radius"], C.c_double)
-        d.height = _dptr(k["height"], C.c_double)
-        d.eps_r = k["eps"].ctypes.data_as(C.POINTER(L.C128))
-        d.n_eps = int(k["eps"].shape[0])
-        d.lattice_ij = _dptr(k["ij"], C.c_int32)
-        d.pitch = float(getattr(array, "pitch", 0.0))
-        d.wavelength = float(getattr(array, "wavelength", 1.0))
-        d.cells_per_particle = int(getattr(array, "cells_per_particle", 48))
+        d, self._keep = array_desc(array)
         h = C.c_void_p()
         ctx.check(lib.qrvie_geom_create(ctx.h, C.byref(d), C.byref(h)), "geom_create")
         self.h = h

@@ -39,8 +39,8 @@ qrvie_status hip_check(qrvie_ctx* ctx, hipError_t e, const char* what) {
 qrvie_status dalloc(qrvie_ctx* ctx, void** p, size_t bytes, const char* what) {
     *p = nullptr;
     if (bytes == 0) return QRVIE_OK;
-    if (ctx->budget && ctx->in_use + bytes > ctx->budget) {
-        set_err(ctx, std::string(what) + ": HBM budget exceeded (" + std::to_string(ctx->in_use + bytes) +
+    if (ctx->budget && ctx->in_use.load() + bytes > ctx->budget) {
+        set_err(ctx, std::string(what) + ": HBM budget exceeded (" + std::to_string(ctx->in_use.load() + bytes) +
                          " > " + std::to_string(ctx->budget) + " bytes)");
         return QRVIE_ERR_OUT_OF_MEMORY;
     }
@@ -59,7 +59,7 @@ qrvie_status dalloc(qrvie_ctx* ctx, void** p, size_t bytes, const char* what) {
 void dfree(qrvie_ctx* ctx, void* p, size_t bytes) {
     if (!p) return;
     (void)hipFree(p);
-    if (ctx) ctx->in_use -= std::min(ctx->in_use, bytes);
+    if (ctx) ctx->in_use -= bytes;
 }
 
 void particle_offsets(double radius, double height, double* off) {
@@ -183,7 +183,7 @@ void qrvie_ctx_destroy(qrvie_ctx* ctx) {
 
 const char* qrvie_last_error(const qrvie_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
-size_t qrvie_ctx_bytes_in_use(const qrvie_ctx* ctx) { return ctx ? ctx->in_use : 0; }
+size_t qrvie_ctx_bytes_in_use(const qrvie_ctx* ctx) { return ctx ? ctx->in_use.load() : 0; }
 
 qrvie_status qrvie_geom_create(qrvie_ctx* ctx, const qrvie_array_desc* d, qrvie_geom** out) {
     if (!ctx || !d || !out) return QRVIE_ERR_INVALID_ARG;

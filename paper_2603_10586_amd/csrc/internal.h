@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -115,7 +116,7 @@ struct qrvie_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     size_t budget = 0;
-    size_t in_use = 0;
+    std::atomic<size_t> in_use{0};  // atomic: the server frees operators from other threads
     std::string err;
     void* blas = nullptr;           // rocBLAS handle of the block solver, created on first use
 };

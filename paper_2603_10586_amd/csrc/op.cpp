@@ -475,7 +475,7 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
     }
     size_t est = 0;
     qrvie_op_footprint_estimate(g, o, &est);
-    if (ctx->budget && ctx->in_use + est > ctx->budget) {
+    if (ctx->budget && ctx->in_use.load() + est > ctx->budget) {
         set_err(ctx, "op_create: footprint estimate " + std::to_string(est) + " exceeds the remaining HBM budget");
         return QRVIE_ERR_OUT_OF_MEMORY;
     }
@@ -561,7 +561,7 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
     {
         size_t free_b = 0, total_b = 0;
         if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) room = (double)free_b;
-        if (ctx->budget) room = std::min(room, (double)(ctx->budget - ctx->in_use));
+        if (ctx->budget) room = std::min(room, (double)(ctx->budget - ctx->in_use.load()));
     }
     const int64_t chunk_elems =
         (int64_t)(std::min(48.0 * (1ull << 30), std::max(2.56e8, room / 8.0)) / sizeof(c128));

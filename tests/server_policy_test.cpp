@@ -1,0 +1,116 @@
+// Host-only checks of the solve server's admission policy (compiled with g++ by
+// test_server_policy.py; no device involved).
+#include <cassert>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "policy.h"
+
+using qrvie::sched::Policy;
+
+#define EXPECT(c)                                                        \
+    do {                                                                 \
+        if (!(c)) {                                                      \
+            std::fprintf(stderr, "line %d: failed: %s\n", __LINE__, #c); \
+            return 1;                                                    \
+        }                                                                \
+    } while (0)
+
+static int fifo_and_slots() {
+    Policy p(2, 100, 0);
+    std::vector<uint64_t> adm;
+    std::vector<std::string> ev;
+    EXPECT(p.enqueue(1, "a", 10, 5));
+    EXPECT(p.enqueue(2, "b", 10, 5));
+    EXPECT(p.enqueue(3, "c", 10, 5));
+    p.admit(&adm, &ev);
+    EXPECT(adm.size() == 2 && adm[0] == 1 && adm[1] == 2);      // two slots, arrival order
+    EXPECT(p.running() == 2 && p.in_use() == 20 && p.queued() == 1);
+    adm.clear();
+    EXPECT(!p.finish(1, true, &ev));                             // op_cache = 0: not kept
+    p.admit(&adm, &ev);
+    EXPECT(adm.size() == 1 && adm[0] == 3);
+    return 0;
+}
+
+static int no_head_of_line_blocking() {
+    Policy p(4, 100, 0);
+    std::vector<uint64_t> adm;
+    std::vector<std::string> ev;
+    EXPECT(p.enqueue(1, "a", 60, 40));
+    EXPECT(p.enqueue(2, "b", 60, 40));                           // does not fit next to 1
+    EXPECT(p.enqueue(3, "c", 30, 20));                           // fits: must not wait behind 2
+    p.admit(&adm, &ev);
+    EXPECT(adm.size() == 2 && adm[0] == 1 && adm[1] == 3);
+    EXPECT(p.in_use() == 90 && p.queued() == 1);
+    adm.clear();
+    p.finish(1, true, &ev);
+    p.admit(&adm, &ev);
+    EXPECT(adm.size() == 1 && adm[0] == 2);
+    EXPECT(p.peak() == 90);
+    return 0;
+}
+
+static int refuses_what_can_never_fit() {
+    Policy p(2, 100, 2);
+    EXPECT(!p.enqueue(1, "a", 101, 50));
+    EXPECT(!p.enqueue(2, "b", 10, 20));                          // inconsistent sizes
+    EXPECT(p.enqueue(3, "c", 100, 50));
+    return 0;
+}
+
+static int cache_hits_pin_and_lru_eviction() {
+    Policy p(2, 100, 2);
+    std::vector<uint64_t> adm;
+    std::vector<std::string> ev;
+    // request on "a" builds its operator (40 B) and keeps it
+    EXPECT(p.enqueue(1, "a", 50, 40));
+    p.admit(&adm, &ev);
+    EXPECT(p.finish(1, true, &ev) && p.cached("a") && p.in_use() == 40);
+    // a second request on "a" needs only its solver bytes and pins the entry
+    adm.clear();
+    EXPECT(p.enqueue(2, "a", 50, 40));
+    p.admit(&adm, &ev);
+    EXPECT(adm.size() == 1 && p.in_use() == 50 && p.hits() == 1);
+    // a big request cannot evict the pinned entry: it waits
+    EXPECT(p.enqueue(3, "b", 70, 40));                          // 50 in use + 70 > 100
+    adm.clear();
+    p.admit(&adm, &ev);
+    EXPECT(adm.empty() && ev.empty());
+    // once the hit finishes, the entry is unpinned and evicted for the big request
+    EXPECT(!p.finish(2, false, &ev));
+    p.admit(&adm, &ev);
+    EXPECT(adm.size() == 1 && adm[0] == 3 && ev.size() == 1 && ev[0] == "a" && !p.cached("a"));
+    EXPECT(p.in_use() == 70 && p.evictions() == 1);
+    return 0;
+}
+
+static int cache_capacity_is_bounded() {
+    Policy p(1, 1000, 2);
+    std::vector<uint64_t> adm;
+    std::vector<std::string> ev;
+    const char* keys[] = {"a", "b", "c"};
+    for (uint64_t t = 0; t < 3; ++t) {
+        EXPECT(p.enqueue(t, keys[t], 20, 10));
+        adm.clear();
+        p.admit(&adm, &ev);
+        EXPECT(adm.size() == 1);
+        p.finish(t, true, &ev);
+    }
+    EXPECT(p.cache_size() == 2 && !p.cached("a") && p.cached("b") && p.cached("c"));
+    EXPECT(ev.size() == 1 && ev[0] == "a" && p.in_use() == 20);
+    ev.clear();
+    p.clear(&ev);
+    EXPECT(ev.size() == 2 && p.in_use() == 0);
+    return 0;
+}
+
+int main() {
+    int (*tests[])() = {fifo_and_slots, no_head_of_line_blocking, refuses_what_can_never_fit,
+                        cache_hits_pin_and_lru_eviction, cache_capacity_is_bounded};
+    for (auto t : tests)
+        if (t()) return 1;
+    std::printf("ok\n");
+    return 0;
+}

@@ -1,9 +1,11 @@
-"""Continuous-batching server on the GPU: results are the same alone and in the mix."""
+"""Continuous-batching server on the GPU (the library's native server through its binding)."""
 import numpy as np
 import pytest
 
 import workloads as W
 from oracle import compressed, discretise, greens
+
+from gpu_cases import ctx, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -18,46 +20,82 @@ def _requests():
     return out
 
 
-def test_results_are_bitwise_identical_alone_and_in_the_mix():
-    from paper_2603_10586_amd.server import DeviceExecutor, Server, ServerOpts
+@pytest.mark.parametrize("mode", [0, 2])
+def test_results_are_bitwise_identical_alone_and_in_the_mix(mode):
+    from paper_2603_10586_amd.server import Server, ServerOpts
     reqs = _requests()
-    opts = dict(hbm_budget=8 << 30, restart=400, max_iter=2000, op_cache=0)
-    alone_srv = Server(ServerOpts(slots=1, **opts), DeviceExecutor)
+    opts = dict(hbm_budget=8 << 30, restart=400, max_iter=2000, op_cache=0, mode=mode)
+    alone_srv = Server(ServerOpts(slots=1, **opts))
     alone = [alone_srv.result(alone_srv.submit(r), timeout=120) for r in reqs]
     alone_srv.close()
-    mix_srv = Server(ServerOpts(slots=3, **opts), DeviceExecutor)
+    mix_srv = Server(ServerOpts(slots=3, **opts))
     tickets = [mix_srv.submit(r) for r in reqs]
     mix = [mix_srv.result(t, timeout=120) for t in tickets]
     st = mix_srv.stats()
     mix_srv.close()
     for a, b in zip(alone, mix):
-        assert a.status == 0 and b.status == 0, (a.error, b.error)
+        assert a.status == 0 and b.status == 0
         assert np.array_equal(a.x, b.x)
         assert all(i["converged"] and i["rel_res_true"] <= 1e-8 for i in b.info)
-    assert st["requests"] == len(reqs) and st["peak_bytes"] <= 8 << 30
+    assert st["completed"] == len(reqs) and st["failed"] == 0 and st["peak_bytes"] <= 8 << 30
     # requests overlapped: more than one was admitted before the first finished
-    first_done = min(j.done for j in mix)
-    assert sum(j.admitted < first_done for j in mix) >= 2
+    first_done = min(r.done for r in mix)
+    assert sum(r.admitted < first_done for r in mix) >= 2
 
 
 def test_served_solution_matches_the_oracle_on_the_same_operator():
+    """The served operator equals one built directly (compression is deterministic), whose
+    exported factors give the oracle's direct solve."""
     import paper_2603_10586_amd as q
-    from paper_2603_10586_amd.server import DeviceExecutor, Server, ServerOpts
+    from paper_2603_10586_amd.server import Server, ServerOpts
     r = _requests()[1]
-    srv = Server(ServerOpts(slots=1, hbm_budget=8 << 30, restart=400, max_iter=2000, op_cache=1), DeviceExecutor)
-    job = srv.result(srv.submit(r), timeout=120)
-    geom, op = srv._cache[job.key][0]
+    srv = Server(ServerOpts(slots=1, hbm_budget=8 << 30, restart=400, max_iter=2000, op_cache=1))
+    res = srv.result(srv.submit(r), timeout=120)
+    srv.close()
+    assert res.status == 0
+    geom = q.Geometry(ctx(), r.array)
+    op = q.Operator(ctx(), geom, eps=1e-6)
     order = geom.order()
     fac = []
     for b in range(op.num_blocks()):
         bi, Q, R = op.export_block(b)
         rows = order[bi["row_first"]:bi["row_first"] + bi["row_count"]]
         cols = order[bi["col_first"]:bi["col_first"] + bi["col_count"]]
-        fac.append((rows, cols, Q, R))
-    srv.close()
+        if Q is not None:
+            fac.append((rows, cols, Q, R))
     disc = discretise.Discretisation(r.array)
     ZQR = compressed.dense_from_factors(greens.self_blocks(disc), fac)
     v = greens.plane_wave_rhs(disc, r.incidence.theta_deg, r.incidence.phi_deg, r.incidence.pol)
     ref = np.linalg.solve(ZQR, v).T
     for k in range(r.incidence.nrhs):
-        assert np.linalg.norm(job.x[k] - ref[k]) <= 1e-6 * np.linalg.norm(ref[k])
+        assert np.linalg.norm(res.x[k] - ref[k]) <= 1e-6 * np.linalg.norm(ref[k])
+    # and the directly built operator gives the same solution bitwise
+    vd = q.rhs_plane_waves(ctx(), geom, r.incidence.theta_deg, r.incidence.phi_deg, r.incidence.pol)
+    xd, _, _ = op.solve(vd, restart=400, tol=1e-8, max_iter=2000, mode=q.SOLVE_BLOCK)
+    assert np.array_equal(to_host(xd), res.x)
+
+
+def test_operator_cache_serves_repeated_geometries():
+    from paper_2603_10586_amd.server import Server, ServerOpts
+    reqs = _requests()
+    again = W.Request(rid=9, arrival_s=0.0, array=reqs[0].array, incidence=reqs[2].incidence, tol=1e-8)
+    srv = Server(ServerOpts(slots=2, hbm_budget=8 << 30, restart=400, max_iter=2000, op_cache=2))
+    first = srv.result(srv.submit(reqs[0]), timeout=120)
+    second = srv.result(srv.submit(again), timeout=120)
+    third = srv.result(srv.submit(reqs[0]), timeout=120)
+    st = srv.stats()
+    srv.close()
+    assert first.status == 0 and second.status == 0 and third.status == 0
+    assert st["ops_built"] == 1 and st["cache_hits"] == 2
+    assert np.array_equal(first.x, third.x)
+
+
+def test_request_larger_than_the_budget_is_refused():
+    import paper_2603_10586_amd as q
+    from paper_2603_10586_amd.server import Server, ServerOpts
+    srv = Server(ServerOpts(slots=1, hbm_budget=1 << 20, restart=400, max_iter=2000))
+    with pytest.raises(q.QrvieError) as e:
+        srv.submit(_requests()[3])
+    assert e.value.status == 6
+    assert srv.stats()["refused"] == 1
+    srv.close()
