@@ -118,7 +118,7 @@ def serving(args) -> int:
                       max_iter=args.max_iter)
     srv = Server(opts)
     t0 = time.perf_counter()
-    res = replay(srv, reqs)
+    res = replay(srv, reqs, report=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
     wall = time.perf_counter() - t0
     st = srv.stats()
     srv.close()
@@ -242,6 +242,8 @@ def main() -> int:
     ap.add_argument("--serving-slots", type=int, default=3)
     ap.add_argument("--block", action="store_true",
                     help="block GMRES on 64 plane waves (FP64 matrix-core products)")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the block and mixed-precision forms in the default line")
     ap.add_argument("--graded", action="store_true", help="block mode on the 64 x 64 graded metalens array")
     ap.add_argument("--c64-only", action="store_true", help="block mode with complex64 far factors only")
     ap.add_argument("--block-basis", type=int, default=16384, help="block mode: basis vectors per cycle")
@@ -290,7 +292,9 @@ def main() -> int:
     ctx = q.Context(0)
     t0 = time.perf_counter()
     geom = q.Geometry(ctx, arr)
-    op = q.Operator(ctx, geom, eps=args.eps, far_prec=q.PREC_C64 if args.mixed_ir else q.PREC_C128)
+    # the complex64 copy of the far factors serves the mixed-precision line; the FP64 solves
+    # and products read only the complex128 panels
+    op = q.Operator(ctx, geom, eps=args.eps, far_prec=q.PREC_C64 if (args.mixed_ir or not args.no_forms) else q.PREC_C128)
     mode = q.SOLVE_MIXED_IR if args.mixed_ir else q.SOLVE_FP64
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
@@ -374,10 +378,44 @@ def main() -> int:
         "mean_rank_level": [round(r, 1) for r in st["mean_rank_level"]],
         "roofline": roofline,
     }
+    if not args.mixed_ir and not args.no_forms and args.nrhs == 1:
+        out["forms"] = other_forms(q, W, ctx, geom, op, v, args, out["solves_per_s"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(op, geom, seconds=args.cpu_seconds)
     print(json.dumps(out))
     return 0
+
+
+def other_forms(q, W, ctx, geom, op, v, args, plain_solves_per_s: float) -> dict:
+    """The batched (block GMRES over 64 plane waves) and mixed-precision forms on the same
+    operator and tolerance, beside the plain single-solve FP64 form timed above."""
+    import torch
+    sw = W.sweep(32)
+    vb = q.rhs_plane_waves(ctx, geom, sw.theta_deg, sw.phi_deg, sw.pol)
+    op.solve(vb, restart=16384, tol=args.tol, max_iter=args.max_iter, mode=q.SOLVE_BLOCK)     # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, ib, sb = op.solve(vb, restart=16384, tol=args.tol, max_iter=args.max_iter, mode=q.SOLVE_BLOCK)
+    tb = time.perf_counter() - t
+    print(f"[bench] block form: {tb:.2f} s for 64 waves, {ib[0]['iterations']} block steps", file=sys.stderr,
+          flush=True)
+    t = time.perf_counter()
+    _, ii, si = op.solve(v, restart=args.restart, tol=args.tol, max_iter=args.max_iter, mode=q.SOLVE_MIXED_IR)
+    ti = time.perf_counter() - t
+    print(f"[bench] mixed-precision form: {ti:.2f} s, {ii[0]['iterations']} inner steps", file=sys.stderr,
+          flush=True)
+    block_sps = 64 / tb
+    return {
+        "plain_fp64_single_solves_per_s": plain_solves_per_s,
+        "block_64_waves": {"solves_per_s": round(block_sps, 3), "s_per_64": round(tb, 3),
+                           "block_steps": ib[0]["iterations"], "converged": all(i["converged"] for i in ib),
+                           "worst_true_residual": max(i["rel_res_true"] for i in ib),
+                           "vs_plain": round(block_sps / plain_solves_per_s, 1)},
+        "mixed_precision_refinement": {"solves_per_s": round(1.0 / ti, 3), "inner_steps": ii[0]["iterations"],
+                                       "refinements": ii[0]["n_refine"], "converged": bool(ii[0]["converged"]),
+                                       "true_residual": ii[0]["rel_res_true"],
+                                       "vs_plain": round((1.0 / ti) / plain_solves_per_s, 2)},
+    }
 
 
 if __name__ == "__main__":

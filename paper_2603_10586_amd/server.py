@@ -117,14 +117,33 @@ class Server:
             pass
 
 
-def replay(server: Server, requests, time_scale: float = 1.0, timeout: float | None = None) -> list[Result]:
+def replay(server: Server, requests, time_scale: float = 1.0, timeout: float | None = None,
+           report=None) -> list[Result]:
     """Submit requests at their arrival times (seconds x time_scale after the start) and wait
-    for all of them; returns the results in submission order."""
+    for all of them; returns the results in submission order.  `report(text)`, if given, is
+    called for every submission and every finished request."""
     t0 = time.perf_counter()
-    tickets = []
+    tickets, results = [], {}
+
+    def collect():
+        for t in tickets:
+            if t not in results and server.poll(t):
+                results[t] = server.result(t)
+                if report:
+                    r = results[t]
+                    report(f"finished ticket {t}: status {r.status}, latency {r.latency:.2f} s, "
+                           f"{len(results)}/{len(requests)} done")
+
     for req in requests:
         due = t0 + req.arrival_s * time_scale
         while time.perf_counter() < due:
-            time.sleep(min(due - time.perf_counter(), 0.05))
+            collect()
+            time.sleep(min(max(due - time.perf_counter(), 0.0), 0.05))
         tickets.append(server.submit(req))
-    return [server.result(t, timeout=timeout) for t in tickets]
+        if report:
+            report(f"submitted request {len(tickets)}/{len(requests)} ({req.array.n_particles} particles, "
+                   f"{len(req.incidence.theta_deg)} waves)")
+    while len(results) < len(tickets):
+        collect()
+        time.sleep(0.05)
+    return [results[t] for t in tickets]
