@@ -162,6 +162,7 @@ def block(args) -> int:
     sw = W.sweep((nrhs + 1) // 2)
     v = q.rhs_plane_waves(ctx, geom, sw.theta_deg[:nrhs], sw.phi_deg[:nrhs], sw.pol[:nrhs])
     print(f"[bench] block: {arr.name}, {nrhs} right-hand sides, setup {setup_s:.1f} s", file=sys.stderr, flush=True)
+    tiles = None if args.no_tune else tune_tiles(op)
     restart = args.block_basis
     for _ in range(args.warmup):
         op.solve(v, restart=restart, tol=args.tol, max_iter=args.max_iter, mode=q.SOLVE_BLOCK)
@@ -210,6 +211,7 @@ def block(args) -> int:
                           "krylov_and_host": round(lat[-1] - last["t_apply_s"], 3)},
         "setup_s": round(setup_s, 2),
         "block_product_ms": round(pt, 3), "block_product_stage_ms": {k: round(p["ms"], 3) for k, p in prof.items()},
+        "tile_tuning": tiles,
         "roofline": {"bound": "mfma", "achieved": round(ach, 2), "peak": FP64_MFMA_PEAK_TFS, "unit": "TF/s",
                      "frac": round(ach / FP64_MFMA_PEAK_TFS, 4), "traffic": None, "kernel": "k_strip_mfma<4>",
                      "stage": dom, "algorithmic_flops": prof[dom]["flops"]},
@@ -242,6 +244,7 @@ def main() -> int:
     ap.add_argument("--serving-slots", type=int, default=3)
     ap.add_argument("--block", action="store_true",
                     help="block GMRES on 64 plane waves (FP64 matrix-core products)")
+    ap.add_argument("--no-tune", action="store_true", help="block mode without the tile autotuner")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the block and mixed-precision forms in the default line")
     ap.add_argument("--graded", action="store_true", help="block mode on the 64 x 64 graded metalens array")
@@ -386,12 +389,33 @@ def main() -> int:
     return 0
 
 
+def tune_tiles(op, prec=None) -> dict:
+    """Autotune the block product's tile shapes for 16, 32, 48 and 64 right-hand sides (the
+    widths a block solve uses before and after deflation); per width and strip group the
+    kept shape and the default/kept launch times."""
+    out = {}
+    for w in (16, 32, 48, 64):
+        t = op.tune_block(nrhs=w, reps=3, prec=prec)
+        g = {}
+        for k, ms in t["ms"].items():
+            c = t["chosen"][k]
+            g[k] = {"u": t["variants"][c]["u"], "rows_per_wave": t["variants"][c]["rows_per_wave"],
+                    "default_ms": round(ms[0], 4), "tuned_ms": round(ms[c], 4),
+                    "all_ms": [round(m, 4) for m in ms]}
+        out[str(w)] = g
+    print(f"[bench] tile tuning (64 RHS): " + ", ".join(
+        f"{k} u{v['u']}/r{v['rows_per_wave']} {v['default_ms']:.3f}->{v['tuned_ms']:.3f} ms"
+        for k, v in out["64"].items()), file=sys.stderr, flush=True)
+    return out
+
+
 def other_forms(q, W, ctx, geom, op, v, args, plain_solves_per_s: float) -> dict:
     """The batched (block GMRES over 64 plane waves) and mixed-precision forms on the same
     operator and tolerance, beside the plain single-solve FP64 form timed above."""
     import torch
     sw = W.sweep(32)
     vb = q.rhs_plane_waves(ctx, geom, sw.theta_deg, sw.phi_deg, sw.pol)
+    tiles = tune_tiles(op)
     op.solve(vb, restart=16384, tol=args.tol, max_iter=args.max_iter, mode=q.SOLVE_BLOCK)     # warm-up
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -410,7 +434,7 @@ def other_forms(q, W, ctx, geom, op, v, args, plain_solves_per_s: float) -> dict
         "block_64_waves": {"solves_per_s": round(block_sps, 3), "s_per_64": round(tb, 3),
                            "block_steps": ib[0]["iterations"], "converged": all(i["converged"] for i in ib),
                            "worst_true_residual": max(i["rel_res_true"] for i in ib),
-                           "vs_plain": round(block_sps / plain_solves_per_s, 1)},
+                           "vs_plain": round(block_sps / plain_solves_per_s, 1), "tile_tuning": tiles["64"]},
         "mixed_precision_refinement": {"solves_per_s": round(1.0 / ti, 3), "inner_steps": ii[0]["iterations"],
                                        "refinements": ii[0]["n_refine"], "converged": bool(ii[0]["converged"]),
                                        "true_residual": ii[0]["rel_res_true"],

@@ -234,6 +234,32 @@ qrvie_status qrvie_op_profile_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t 
  */
 qrvie_status qrvie_op_profile_block(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, int32_t reps, double* ms,
                                     int64_t* flops);
+/*
+ * Autotuner of the block product's tile shapes (the rank-grouped strip GEMMs of the
+ * multi-right-hand-side product, §5.2).  The strips fall in three groups: R panels, Q panels
+ * and the self blocks (whose choice also serves the block preconditioner).  For each group
+ * every tile shape (variant v: u[v] 4-column steps per load batch, rows_per_wave[v] rows per
+ * wavefront) is timed over `reps` launches (1..100) on a fixed pseudo-random block of
+ * 16 * ceil(nrhs / 16) right-hand sides (nrhs 1..64) and compared bitwise with variant 0, the
+ * untuned default; the fastest variant with no differing entry is kept in the operator and
+ * used from then on by every block product with that tile count and factor precision
+ * (prec QRVIE_PREC_C128 or QRVIE_PREC_C64; an operator holding only complex64 panels tunes
+ * those either way).  All variants accumulate in the same order, so tuning never changes a
+ * result.  Tuning writes to `op`: no product on the same operator may run concurrently with
+ * it.  Synchronises the context stream; `out` (host) receives the measurements.
+ */
+#define QRVIE_TUNE_VARIANTS 8
+typedef struct {
+    int32_t nrhs_tile;                          /* right-hand sides per product, 16 * tiles */
+    int32_t n_variants;                         /* variants measured (<= QRVIE_TUNE_VARIANTS) */
+    int32_t u[QRVIE_TUNE_VARIANTS];             /* 4-column steps per load batch */
+    int32_t rows_per_wave[QRVIE_TUNE_VARIANTS]; /* rows of a strip per wavefront */
+    double ms[3][QRVIE_TUNE_VARIANTS];          /* average launch time: R group, Q group, self group */
+    int64_t mismatches[3][QRVIE_TUNE_VARIANTS]; /* entries differing bitwise from variant 0 */
+    int32_t chosen[3];                          /* kept variant per group */
+} qrvie_block_tune;
+qrvie_status qrvie_op_tune_block(qrvie_ctx* ctx, qrvie_op* op, int32_t prec, int32_t nrhs, int32_t reps,
+                                 qrvie_block_tune* out);
 /* z = Z_D^-1 y, the block-diagonal left preconditioner (§4, eq. 4.2). */
 qrvie_status qrvie_precondition(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs,
                                 const qrvie_c128* y, int64_t ldy, qrvie_c128* z, int64_t ldz);
@@ -338,6 +364,7 @@ typedef struct {
     int32_t  block_width;
     int32_t  op_cache;       /* operators kept resident after their request, >= 0 */
     uint64_t seed;           /* compression sketch seed */
+    int32_t  tune_tiles;     /* 1: autotune the block product tiles of each new operator (block mode) */
 } qrvie_server_opts;
 
 typedef struct {

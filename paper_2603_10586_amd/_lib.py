@@ -63,7 +63,16 @@ class SolveInfo(C.Structure):
 class ServerOptsC(C.Structure):
     _fields_ = [("slots", C.c_int32), ("hbm_budget", C.c_size_t), ("eps", C.c_double), ("restart", C.c_int32),
                 ("max_iter", C.c_int32), ("mode", C.c_int32), ("block_width", C.c_int32), ("op_cache", C.c_int32),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("tune_tiles", C.c_int32)]
+
+
+TUNE_VARIANTS = 8
+
+
+class BlockTune(C.Structure):
+    _fields_ = [("nrhs_tile", C.c_int32), ("n_variants", C.c_int32), ("u", C.c_int32 * TUNE_VARIANTS),
+                ("rows_per_wave", C.c_int32 * TUNE_VARIANTS), ("ms", (C.c_double * TUNE_VARIANTS) * 3),
+                ("mismatches", (C.c_int64 * TUNE_VARIANTS) * 3), ("chosen", C.c_int32 * 3)]
 
 
 class ServerStatsC(C.Structure):
@@ -105,6 +114,7 @@ SIGNATURES = {
     "qrvie_apply_prec": (ST, [P, P, I32, I32, P, I64, P, I64]),
     "qrvie_op_profile_apply": (ST, [P, P, I32, I32, C.POINTER(C.c_double), C.POINTER(I64)]),
     "qrvie_op_profile_block": (ST, [P, P, I32, I32, C.POINTER(C.c_double), C.POINTER(I64)]),
+    "qrvie_op_tune_block": (ST, [P, P, I32, I32, I32, C.POINTER(BlockTune)]),
     "qrvie_precondition": (ST, [P, P, I32, P, I64, P, I64]),
     "qrvie_rhs_plane_waves": (ST, [P, P, I32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(I32), P, I64]),
     "qrvie_solve": (ST, [P, P, I32, P, I64, P, I64, C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),

@@ -167,7 +167,7 @@ class Operator:
 
     def __init__(self, ctx: Context, geom: Geometry, eps: float = 1e-6, max_block_rows: int = 0, seed: int = 0,
                  far_prec: int = L.PREC_C128, verbose: bool = False):
-        self.ctx, self.geom = ctx, geom
+        self.ctx, self.geom, self.far_prec = ctx, geom, far_prec
         o = L.CompressOpts(eps=eps, far_prec=far_prec, near_prec=L.PREC_C128, max_block_rows=max_block_rows,
                            share_transpose=0, seed=seed, verbose=1 if verbose else 0)
         self.opts = o
@@ -258,6 +258,26 @@ class Operator:
         self.ctx.check(self.ctx.lib.qrvie_op_profile_block(self.ctx.h, self.h, nrhs, reps, ms, fl), "profile block")
         names = ("rphase", "qphase", "self", "precond")
         return {k: dict(ms=ms[i], flops=fl[i]) for i, k in enumerate(names)}
+
+    def tune_block(self, nrhs: int = 64, reps: int = 5, prec: int = None) -> dict:
+        """Autotune the block product's tile shape per strip group (R panels, Q panels, self
+        blocks) for nrhs right-hand sides; the operator keeps the fastest bitwise-identical
+        shape.  Returns the per-variant timings, mismatch counts and the choices."""
+        if prec is None:
+            prec = L.PREC_C128 if self.far_prec != L.PREC_C64_ONLY else L.PREC_C64
+        t = L.BlockTune()
+        self.ctx.order()
+        self.ctx.check(self.ctx.lib.qrvie_op_tune_block(self.ctx.h, self.h, prec, nrhs, reps, C.byref(t)),
+                       "tune block")
+        nv = t.n_variants
+        groups = ("rphase", "qphase", "self")
+        return {
+            "nrhs_tile": t.nrhs_tile,
+            "variants": [dict(u=t.u[v], rows_per_wave=t.rows_per_wave[v]) for v in range(nv)],
+            "ms": {g: [t.ms[i][v] for v in range(nv)] for i, g in enumerate(groups)},
+            "mismatches": {g: [t.mismatches[i][v] for v in range(nv)] for i, g in enumerate(groups)},
+            "chosen": {g: t.chosen[i] for i, g in enumerate(groups)},
+        }
 
     def precondition(self, y):
         torch = _torch()

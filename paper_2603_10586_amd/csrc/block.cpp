@@ -306,18 +306,20 @@ qrvie_status profile_block(qrvie_ctx* ctx, const qrvie_op* op, int nrhs, int rep
     hipEvent_t ev[5];
     for (auto& e : ev) (void)hipEventCreate(&e);
     double acc[4] = {0, 0, 0, 0};
+    const bool l = !op->d_fac;
+    const int vr = op->tile_of(l, nt, 0), vq = op->tile_of(l, nt, 1), vs = op->tile_of(l, nt, 2);
     for (int r = 0; r < reps; ++r) {
         (void)hipEventRecord(ev[0], s);
-        if (op->d_fac) launch_strip_mfma(s, nt, op->d_mr, op->n_mr, op->d_fac, X, bw.T, op->d_tmap);
-        else launch_strip_mfma(s, nt, op->d_mr, op->n_mr, op->d_fac32, X, bw.T, op->d_tmap);
+        if (op->d_fac) launch_strip_mfma(s, nt, op->d_mr, op->n_mr, op->d_fac, X, bw.T, op->d_tmap, vr);
+        else launch_strip_mfma(s, nt, op->d_mr, op->n_mr, op->d_fac32, X, bw.T, op->d_tmap, vr);
         (void)hipEventRecord(ev[1], s);
-        if (op->d_fac) launch_strip_mfma(s, nt, op->d_mq, op->n_mq, op->d_fac, bw.T, bw.Ylev, nullptr);
-        else launch_strip_mfma(s, nt, op->d_mq, op->n_mq, op->d_fac32, bw.T, bw.Ylev, nullptr);
+        if (op->d_fac) launch_strip_mfma(s, nt, op->d_mq, op->n_mq, op->d_fac, bw.T, bw.Ylev, nullptr, vq);
+        else launch_strip_mfma(s, nt, op->d_mq, op->n_mq, op->d_fac32, bw.T, bw.Ylev, nullptr, vq);
         (void)hipEventRecord(ev[2], s);
-        launch_strip_mfma(s, nt, op->d_ms, op->n_ms, op->d_self, X, bw.Yself, nullptr);
+        launch_strip_mfma(s, nt, op->d_ms, op->n_ms, op->d_self, X, bw.Yself, nullptr, vs);
         launch_block_combine(s, nt, n, bw.Ylev, op->n_active, bw.Yself, X, Y);
         (void)hipEventRecord(ev[3], s);
-        launch_strip_mfma(s, nt, op->d_ms, op->n_ms, op->d_pinv, Y, Zp, nullptr);
+        launch_strip_mfma(s, nt, op->d_ms, op->n_ms, op->d_pinv, Y, Zp, nullptr, vs);
         (void)hipEventRecord(ev[4], s);
         CHECK(hip_check(ctx, hipEventSynchronize(ev[4]), "profile block"));
         for (int k = 0; k < 4; ++k) {
@@ -340,6 +342,103 @@ qrvie_status profile_block(qrvie_ctx* ctx, const qrvie_op* op, int nrhs, int rep
     flops[2] = 8 * P * self;
     flops[3] = 8 * P * self;
     return hip_check(ctx, hipGetLastError(), "profile block");
+}
+
+// Autotuner of the strip tile shapes, one choice per strip group (R panels, Q panels, self
+// blocks) for this operator, tile count and panel precision.  Each group's output is
+// cleared before every launch so that entries no strip writes compare equal.
+qrvie_status tune_block(qrvie_ctx* ctx, qrvie_op* op, int prec, int nrhs, int reps, qrvie_block_tune* out) {
+    const qrvie_geom* g = op->g;
+    const int64_t n = g->ndof();
+    const int nt = (nrhs + 15) / 16, P = 16 * nt;
+    const bool l = prec == QRVIE_PREC_C64 || !op->d_fac;
+    hipStream_t s = ctx->stream;
+    Work w(ctx);
+    BlockWork bw;
+    CHECK(bw.init(w, op));
+    // a fixed pseudo-random input block (64-bit LCG, uniform in [-1, 1) per component)
+    std::vector<c128> hx((size_t)n * P);
+    uint64_t st = 0x9E3779B97F4A7C15ull;
+    auto next = [&st]() {
+        st = st * 6364136223846793005ull + 1442695040888963407ull;
+        return (double)(st >> 11) * 0x1.0p-52 - 1.0;
+    };
+    for (auto& e : hx) { e.x = next(); e.y = next(); }
+    c128* X;
+    unsigned long long* dmis;
+    CHECK(w.alloc(&X, hx.size(), "tune input"));
+    CHECK(w.alloc(&dmis, 3 * kStripVariants, "tune counts"));
+    CHECK(hip_check(ctx, hipMemcpyAsync(X, hx.data(), sizeof(c128) * hx.size(), hipMemcpyHostToDevice, s), "tune"));
+    CHECK(hip_check(ctx, hipMemsetAsync(dmis, 0, sizeof(unsigned long long) * 3 * kStripVariants, s), "tune"));
+    const size_t out_len[3] = {(size_t)std::max<int64_t>(op->t_len, 1) * P,
+                               (size_t)std::max(op->n_active, 1) * n * P, (size_t)n * P};
+    c128* outs[3] = {bw.T, bw.Ylev, bw.Yself};
+    c128* ref;
+    CHECK(w.alloc(&ref, std::max({out_len[0], out_len[1], out_len[2]}), "tune reference"));
+    auto run = [&](int grp, int v) {
+        switch (grp) {
+            case 0:
+                if (l) launch_strip_mfma(s, nt, op->d_mr, op->n_mr, op->d_fac32, X, bw.T, op->d_tmap, v);
+                else launch_strip_mfma(s, nt, op->d_mr, op->n_mr, op->d_fac, X, bw.T, op->d_tmap, v);
+                break;
+            case 1:
+                if (l) launch_strip_mfma(s, nt, op->d_mq, op->n_mq, op->d_fac32, bw.T, bw.Ylev, nullptr, v);
+                else launch_strip_mfma(s, nt, op->d_mq, op->n_mq, op->d_fac, bw.T, bw.Ylev, nullptr, v);
+                break;
+            default: launch_strip_mfma(s, nt, op->d_ms, op->n_ms, op->d_self, X, bw.Yself, nullptr, v); break;
+        }
+    };
+    hipEvent_t e0, e1;
+    CHECK(hip_check(ctx, hipEventCreate(&e0), "tune events"));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_check(ctx, hipErrorOutOfMemory, "tune events");
+    }
+    qrvie_status status = QRVIE_OK;
+    std::memset(out, 0, sizeof(*out));
+    out->nrhs_tile = P;
+    out->n_variants = kStripVariants;
+    for (int v = 0; v < kStripVariants; ++v) {
+        out->u[v] = strip_variant_u(v);
+        out->rows_per_wave[v] = strip_variant_rows(v);
+    }
+    const int64_t count[3] = {op->n_mr, op->n_mq, op->n_ms};
+    for (int grp = 0; grp < 3 && status == QRVIE_OK; ++grp) {
+        if (grp == 1) {   // the Q group reads the rank-space block the R group produced
+            run(0, 0);
+        }
+        for (int v = 0; v < kStripVariants && status == QRVIE_OK; ++v) {
+            if (count[grp] == 0) break;
+            const size_t bytes = sizeof(c128) * out_len[grp];
+            status = hip_check(ctx, hipMemsetAsync(outs[grp], 0, bytes, s), "tune clear");
+            if (status != QRVIE_OK) break;
+            run(grp, v);
+            if (v == 0) status = hip_check(ctx, hipMemcpyAsync(ref, outs[grp], bytes, hipMemcpyDeviceToDevice, s), "tune ref");
+            else launch_count_neq(s, 2 * (int64_t)out_len[grp], outs[grp], ref, dmis + grp * kStripVariants + v);
+            (void)hipEventRecord(e0, s);
+            for (int r = 0; r < reps; ++r) run(grp, v);
+            (void)hipEventRecord(e1, s);
+            status = hip_check(ctx, hipEventSynchronize(e1), "tune");
+            float t = 0.f;
+            if (status == QRVIE_OK) status = hip_check(ctx, hipEventElapsedTime(&t, e0, e1), "tune timer");
+            out->ms[grp][v] = t / reps;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    CHECK(status);
+    unsigned long long hm[3 * kStripVariants];
+    CHECK(hip_check(ctx, hipMemcpy(hm, dmis, sizeof(hm), hipMemcpyDeviceToHost), "tune counts"));
+    for (int grp = 0; grp < 3; ++grp) {
+        int best = 0;
+        for (int v = 0; v < kStripVariants; ++v) {
+            out->mismatches[grp][v] = (int64_t)hm[grp * kStripVariants + v];
+            if (count[grp] > 0 && hm[grp * kStripVariants + v] == 0 && out->ms[grp][v] < out->ms[grp][best]) best = v;
+        }
+        out->chosen[grp] = best;
+        op->tile[l ? 1 : 0][nt - 1][grp].store(best, std::memory_order_relaxed);
+    }
+    return hip_check(ctx, hipGetLastError(), "tune");
 }
 
 qrvie_status solve_block(qrvie_ctx* ctx, const qrvie_op* op, int na, const c128* v, int64_t ldv, c128* x,

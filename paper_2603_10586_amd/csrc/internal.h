@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cstdint>
 #include <string>
@@ -165,6 +166,12 @@ struct qrvie_op {
     qrvie::MStrip* d_mq = nullptr;
     qrvie::MStrip* d_ms = nullptr;            // offsets into d_self and d_pinv (same layout)
     int64_t n_mr = 0, n_mq = 0, n_ms = 0;
+    // strip product tile variant per (complex64 panels?, nt - 1, group R / Q / self), set by
+    // qrvie_op_tune_block; 0 (the default shape) until tuned
+    std::atomic<int> tile[2][4][3]{};
+    int tile_of(bool lo, int nt, int group) const {
+        return tile[lo ? 1 : 0][std::min(std::max(nt, 1), 4) - 1][group].load(std::memory_order_relaxed);
+    }
     struct Launch { int level; int64_t begin, count; int waves; };
     std::vector<Launch> rlaunch, qlaunch;
     int32_t n_active = 0;
@@ -262,10 +269,17 @@ void launch_add(hipStream_t s, const c128* d, int64_t n, c128* x);
 
 // blocks of right-hand sides (k_block.hip); nt = P / 16 tiles of 16 right-hand sides, 1..4
 constexpr int kMaxBlockRhs = 64;
+// Strip product tile shapes: variant v loads strip_variant_u(v) 4-column steps per batch and
+// gives each wave strip_variant_rows(v) rows; 0 is the untuned default.  All variants give
+// bitwise-identical results.
+constexpr int kStripVariants = 6;
+int strip_variant_u(int v);
+int strip_variant_rows(int v);
 void launch_strip_mfma(hipStream_t s, int nt, const MStrip* st, int64_t n, const c128* fac, const c128* in,
-                       c128* out, const int64_t* tmap);
+                       c128* out, const int64_t* tmap, int variant = 0);
 void launch_strip_mfma(hipStream_t s, int nt, const MStrip* st, int64_t n, const float2* fac, const c128* in,
-                       c128* out, const int64_t* tmap);
+                       c128* out, const int64_t* tmap, int variant = 0);
+void launch_count_neq(hipStream_t s, int64_t n, const void* a, const void* b, unsigned long long* count);
 void launch_block_combine(hipStream_t s, int nt, int64_t n, const c128* ylev, int nlev, const c128* yself,
                           const c128* V, c128* out);
 void launch_gather_block(hipStream_t s, int nt, int32_t N, const int32_t* i2c, const c128* src, int64_t ld,

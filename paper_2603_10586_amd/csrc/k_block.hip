@@ -29,53 +29,88 @@ __device__ __forceinline__ void cmfma(v4d& re, v4d& im, c128 a, c128 b) {
     im = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, im, 0, 0, 0);
 }
 
-template <int NT, typename F>
+// Tile shape (chosen per strip group by the autotuner): U 4-column steps are loaded per batch
+// (loads in flight against MFMAs), and each wave owns RT tiles of 16 rows, so a 64-row strip
+// takes 4 / RT waves and every loaded right-hand-side tile feeds RT row tiles.  Every
+// accumulator sees its columns in ascending order in every variant, so all shapes give
+// bitwise-identical results.
+template <int NT, int U, int RT, typename F>
 __global__ void __launch_bounds__(256) k_strip_mfma(const MStrip* __restrict__ strips, const F* __restrict__ fac,
                                                     const c128* __restrict__ in, c128* __restrict__ out,
                                                     const int64_t* __restrict__ tmap) {
     constexpr int P = 16 * NT;
-    constexpr int U = 2;                                   // 4-column steps per batch
     const MStrip s = strips[blockIdx.x];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int r0 = 16 * w;
+    const int r0 = 16 * RT * w;
     if (r0 >= s.nrows) return;
     const int rl = lane & 15, kq = lane >> 4;
-    const F* A = fac + s.a_off + min(r0 + rl, s.nrows - 1);
-    const c128* X = in + s.in_off * P + rl;
-    v4d re[NT], im[NT];
+    const F* A[RT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) re[t] = im[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < RT; ++q) A[q] = fac + s.a_off + min(r0 + 16 * q + rl, s.nrows - 1);
+    const c128* X = in + s.in_off * P + rl;
+    v4d re[RT][NT], im[RT][NT];
+#pragma unroll
+    for (int q = 0; q < RT; ++q)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) re[q][t] = im[q][t] = v4d{0.0, 0.0, 0.0, 0.0};
     const int nsteps = s.ncols / 4;
     int c = 0;
     for (; c + U <= nsteps; c += U) {
-        c128 a[U], b[U][NT];
+        c128 a[U][RT], b[U][NT];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t col = 4 * (c + u) + kq;
-            a[u] = widen(load_stream(A + col * s.ld));
+#pragma unroll
+            for (int q = 0; q < RT; ++q) a[u][q] = widen(load_stream(A[q] + col * s.ld));
 #pragma unroll
             for (int t = 0; t < NT; ++t) b[u][t] = X[col * P + 16 * t];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int t = 0; t < NT; ++t) cmfma(re[t], im[t], a[u], b[u][t]);
+            for (int q = 0; q < RT; ++q)
+#pragma unroll
+                for (int t = 0; t < NT; ++t) cmfma(re[q][t], im[q][t], a[u][q], b[u][t]);
     }
     for (; 4 * c < s.ncols; ++c) {                      // remaining steps, the last possibly partial
         const int64_t col = 4 * c + kq;
         const bool ok = col < s.ncols;
         const c128 z = make_double2(0.0, 0.0);
-        const c128 a = ok ? widen(A[col * s.ld]) : z;
+        c128 b[NT];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) cmfma(re[t], im[t], a, ok ? X[col * P + 16 * t] : z);
+        for (int t = 0; t < NT; ++t) b[t] = ok ? X[col * P + 16 * t] : z;
+#pragma unroll
+        for (int q = 0; q < RT; ++q) {
+            const c128 a = ok ? widen(A[q][col * s.ld]) : z;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) cmfma(re[q][t], im[q][t], a, b[t]);
+        }
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int row = r0 + kq + 4 * i;
-        if (row >= s.nrows) continue;
-        const int64_t orow = s.tmap_off >= 0 ? tmap[s.tmap_off + row] : s.out_off + row;
+    for (int q = 0; q < RT; ++q)
 #pragma unroll
-        for (int t = 0; t < NT; ++t) out[orow * P + 16 * t + rl] = make_double2(re[t][i], im[t][i]);
+        for (int i = 0; i < 4; ++i) {
+            const int row = r0 + 16 * q + kq + 4 * i;
+            if (row >= s.nrows) continue;
+            const int64_t orow = s.tmap_off >= 0 ? tmap[s.tmap_off + row] : s.out_off + row;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) out[orow * P + 16 * t + rl] = make_double2(re[q][t][i], im[q][t][i]);
+        }
+}
+
+// number of positions where two arrays of doubles differ bitwise (accumulated into *count)
+__global__ void __launch_bounds__(256) k_count_neq(int64_t n, const unsigned long long* __restrict__ a,
+                                                   const unsigned long long* __restrict__ b,
+                                                   unsigned long long* count) {
+    __shared__ int red[4];
+    int c = 0;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) c += a[e] != b[e];
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int t = red[0] + red[1] + red[2] + red[3];
+        if (t) atomicAdd(count, (unsigned long long)t);
     }
 }
 
@@ -570,25 +605,54 @@ void launch_col_norms(hipStream_t s, int rows, const c128* C, int64_t ldc, int n
         default: hipLaunchKernelGGL(KERNEL<4>, __VA_ARGS__); break;                    \
     }
 
-void launch_strip_mfma(hipStream_t s, int nt, const MStrip* st, int64_t n, const c128* fac, const c128* in,
-                       c128* out, const int64_t* tmap) {
-    if (n <= 0) return;
-    switch (nt) {
-        case 1: hipLaunchKernelGGL((k_strip_mfma<1, c128>), dim3((unsigned)n), dim3(256), 0, s, st, fac, in, out, tmap); break;
-        case 2: hipLaunchKernelGGL((k_strip_mfma<2, c128>), dim3((unsigned)n), dim3(256), 0, s, st, fac, in, out, tmap); break;
-        case 3: hipLaunchKernelGGL((k_strip_mfma<3, c128>), dim3((unsigned)n), dim3(256), 0, s, st, fac, in, out, tmap); break;
-        default: hipLaunchKernelGGL((k_strip_mfma<4, c128>), dim3((unsigned)n), dim3(256), 0, s, st, fac, in, out, tmap); break;
+namespace {
+// the tile-shape table, in the order the autotuner reports it
+constexpr int kTileU[kStripVariants] = {2, 1, 4, 1, 2, 4};
+constexpr int kTileRT[kStripVariants] = {1, 1, 1, 2, 2, 2};
+
+template <int NT, typename F>
+void strip_nt(hipStream_t s, int v, const MStrip* st, int64_t n, const F* fac, const c128* in, c128* out,
+              const int64_t* tmap) {
+    const dim3 g((unsigned)n);
+    switch (v) {
+        case 1: hipLaunchKernelGGL((k_strip_mfma<NT, 1, 1, F>), g, dim3(256), 0, s, st, fac, in, out, tmap); break;
+        case 2: hipLaunchKernelGGL((k_strip_mfma<NT, 4, 1, F>), g, dim3(256), 0, s, st, fac, in, out, tmap); break;
+        case 3: hipLaunchKernelGGL((k_strip_mfma<NT, 1, 2, F>), g, dim3(128), 0, s, st, fac, in, out, tmap); break;
+        case 4: hipLaunchKernelGGL((k_strip_mfma<NT, 2, 2, F>), g, dim3(128), 0, s, st, fac, in, out, tmap); break;
+        case 5: hipLaunchKernelGGL((k_strip_mfma<NT, 4, 2, F>), g, dim3(128), 0, s, st, fac, in, out, tmap); break;
+        default: hipLaunchKernelGGL((k_strip_mfma<NT, 2, 1, F>), g, dim3(256), 0, s, st, fac, in, out, tmap); break;
     }
 }
-void launch_strip_mfma(hipStream_t s, int nt, const MStrip* st, int64_t n, const float2* fac, const c128* in,
-                       c128* out, const int64_t* tmap) {
+
+template <typename F>
+void strip_any(hipStream_t s, int nt, int v, const MStrip* st, int64_t n, const F* fac, const c128* in, c128* out,
+               const int64_t* tmap) {
     if (n <= 0) return;
     switch (nt) {
-        case 1: hipLaunchKernelGGL((k_strip_mfma<1, float2>), dim3((unsigned)n), dim3(256), 0, s, st, fac, in, out, tmap); break;
-        case 2: hipLaunchKernelGGL((k_strip_mfma<2, float2>), dim3((unsigned)n), dim3(256), 0, s, st, fac, in, out, tmap); break;
-        case 3: hipLaunchKernelGGL((k_strip_mfma<3, float2>), dim3((unsigned)n), dim3(256), 0, s, st, fac, in, out, tmap); break;
-        default: hipLaunchKernelGGL((k_strip_mfma<4, float2>), dim3((unsigned)n), dim3(256), 0, s, st, fac, in, out, tmap); break;
+        case 1: strip_nt<1>(s, v, st, n, fac, in, out, tmap); break;
+        case 2: strip_nt<2>(s, v, st, n, fac, in, out, tmap); break;
+        case 3: strip_nt<3>(s, v, st, n, fac, in, out, tmap); break;
+        default: strip_nt<4>(s, v, st, n, fac, in, out, tmap); break;
     }
+}
+}  // namespace
+
+int strip_variant_u(int v) { return v >= 0 && v < kStripVariants ? kTileU[v] : 0; }
+int strip_variant_rows(int v) { return v >= 0 && v < kStripVariants ? 16 * kTileRT[v] : 0; }
+
+void launch_strip_mfma(hipStream_t s, int nt, const MStrip* st, int64_t n, const c128* fac, const c128* in,
+                       c128* out, const int64_t* tmap, int variant) {
+    strip_any(s, nt, variant, st, n, fac, in, out, tmap);
+}
+void launch_strip_mfma(hipStream_t s, int nt, const MStrip* st, int64_t n, const float2* fac, const c128* in,
+                       c128* out, const int64_t* tmap, int variant) {
+    strip_any(s, nt, variant, st, n, fac, in, out, tmap);
+}
+void launch_count_neq(hipStream_t s, int64_t n, const void* a, const void* b, unsigned long long* count) {
+    if (n <= 0) return;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_count_neq, dim3((unsigned)blocks), dim3(256), 0, s, n, (const unsigned long long*)a,
+                       (const unsigned long long*)b, count);
 }
 void launch_block_combine(hipStream_t s, int nt, int64_t n, const c128* ylev, int nlev, const c128* yself,
                           const c128* V, c128* out) {

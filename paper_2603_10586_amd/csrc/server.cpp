@@ -227,6 +227,13 @@ void worker(qrvie_server* s, int slot) {
             st = qrvie_op_create(ctx, r->geom, &co, &op);
             built = st == QRVIE_OK;
             if (!built) msg = qrvie_last_error(ctx);
+            // the new operator is private to this worker until it is cached: tune its tiles
+            // for this request's width (other widths keep the default shape)
+            if (built && s->o.mode == QRVIE_SOLVE_BLOCK && s->o.tune_tiles) {
+                const int w = std::min(r->nrhs, s->o.block_width > 0 ? s->o.block_width : kMaxBlockRhs);
+                qrvie_block_tune t;   // an optimisation only: on failure the default shapes stay
+                (void)qrvie_op_tune_block(ctx, op, op->d_fac ? QRVIE_PREC_C128 : QRVIE_PREC_C64, w, 2, &t);
+            }
         }
         if (st == QRVIE_OK) {
             st = run_request(ctx, op, is_hit ? hit.geom : r->geom, r, r->tol, s);
@@ -296,7 +303,7 @@ qrvie_status qrvie_server_create(int hip_device, const qrvie_server_opts* o, qrv
     if (!o || !out || o->slots < 1 || o->slots > 16 || o->hbm_budget == 0 || !(o->eps > 0.0 && o->eps < 1.0) ||
         o->restart < 1 || o->max_iter < 1 || o->op_cache < 0 ||
         (o->mode != QRVIE_SOLVE_FP64 && o->mode != QRVIE_SOLVE_BLOCK) || o->block_width < 0 ||
-        o->block_width > kMaxBlockRhs)
+        o->block_width > kMaxBlockRhs || (o->tune_tiles != 0 && o->tune_tiles != 1))
         return QRVIE_ERR_INVALID_ARG;
     *out = nullptr;
     std::unique_ptr<qrvie_server> s(new qrvie_server(*o, hip_device));

@@ -601,6 +601,17 @@ qrvie_status qrvie_op_profile_block(qrvie_ctx* ctx, const qrvie_op* op, int32_t 
     return profile_block(ctx, op, nrhs, reps, ms, flops);
 }
 
+qrvie_status qrvie_op_tune_block(qrvie_ctx* ctx, qrvie_op* op, int32_t prec, int32_t nrhs, int32_t reps,
+                                 qrvie_block_tune* out) {
+    if (!ctx || !op || !out || reps < 1 || reps > 100 || nrhs < 1 || nrhs > kMaxBlockRhs) return QRVIE_ERR_INVALID_ARG;
+    if (prec != QRVIE_PREC_C128 && prec != QRVIE_PREC_C64) return QRVIE_ERR_INVALID_ARG;
+    if (prec == QRVIE_PREC_C64 && !op->d_fac32) {
+        set_err(ctx, "qrvie_op_tune_block: the operator holds no complex64 panels");
+        return QRVIE_ERR_INVALID_ARG;
+    }
+    return tune_block(ctx, op, prec, nrhs, reps, out);
+}
+
 qrvie_status qrvie_precondition(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const qrvie_c128* y, int64_t ldy,
                                 qrvie_c128* z, int64_t ldz) {
     CHECK(check_vec_args(ctx, op, nrhs, y, ldy, z, ldz, "precondition"));

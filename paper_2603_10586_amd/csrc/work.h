@@ -56,16 +56,18 @@ struct BlockWork {
 inline void block_product(const qrvie_op* op, hipStream_t s, const BlockWork& bw, int nt, const c128* X, const c128* V,
                           c128* out, c128* zout, bool lo = false) {
     const int64_t n = op->g->ndof();
-    if (lo || !op->d_fac) {
-        launch_strip_mfma(s, nt, op->d_mr, op->n_mr, op->d_fac32, X, bw.T, op->d_tmap);
-        launch_strip_mfma(s, nt, op->d_mq, op->n_mq, op->d_fac32, bw.T, bw.Ylev, nullptr);
+    const bool l = lo || !op->d_fac;
+    const int vr = op->tile_of(l, nt, 0), vq = op->tile_of(l, nt, 1), vs = op->tile_of(l, nt, 2);
+    if (l) {
+        launch_strip_mfma(s, nt, op->d_mr, op->n_mr, op->d_fac32, X, bw.T, op->d_tmap, vr);
+        launch_strip_mfma(s, nt, op->d_mq, op->n_mq, op->d_fac32, bw.T, bw.Ylev, nullptr, vq);
     } else {
-        launch_strip_mfma(s, nt, op->d_mr, op->n_mr, op->d_fac, X, bw.T, op->d_tmap);
-        launch_strip_mfma(s, nt, op->d_mq, op->n_mq, op->d_fac, bw.T, bw.Ylev, nullptr);
+        launch_strip_mfma(s, nt, op->d_mr, op->n_mr, op->d_fac, X, bw.T, op->d_tmap, vr);
+        launch_strip_mfma(s, nt, op->d_mq, op->n_mq, op->d_fac, bw.T, bw.Ylev, nullptr, vq);
     }
-    launch_strip_mfma(s, nt, op->d_ms, op->n_ms, op->d_self, X, bw.Yself, nullptr);
+    launch_strip_mfma(s, nt, op->d_ms, op->n_ms, op->d_self, X, bw.Yself, nullptr, vs);
     launch_block_combine(s, nt, n, bw.Ylev, op->n_active, bw.Yself, V, out);
-    if (zout) launch_strip_mfma(s, nt, op->d_ms, op->n_ms, op->d_pinv, out, zout, nullptr);
+    if (zout) launch_strip_mfma(s, nt, op->d_ms, op->n_ms, op->d_pinv, out, zout, nullptr, vs);
 }
 
 
@@ -76,5 +78,6 @@ qrvie_status solve_block(qrvie_ctx* ctx, const qrvie_op* op, int na, const c128*
                          int64_t ldx, const qrvie_solve_opts* o, qrvie_solve_info* info, bool* broke);
 
 qrvie_status profile_block(qrvie_ctx* ctx, const qrvie_op* op, int nrhs, int reps, double* ms, int64_t* flops);
+qrvie_status tune_block(qrvie_ctx* ctx, qrvie_op* op, int prec, int nrhs, int reps, qrvie_block_tune* out);
 
 }  // namespace qrvie

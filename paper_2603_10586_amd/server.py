@@ -30,6 +30,7 @@ class ServerOpts:
     block_width: int = 0
     op_cache: int = 4                 # operators kept resident after their request
     seed: int = 0
+    tune_tiles: bool = True           # autotune each new operator's block product tiles
 
 
 @dataclass
@@ -53,7 +54,7 @@ class Server:
         self.opts = opts
         o = L.ServerOptsC(slots=opts.slots, hbm_budget=opts.hbm_budget, eps=opts.eps, restart=opts.restart,
                           max_iter=opts.max_iter, mode=opts.mode, block_width=opts.block_width,
-                          op_cache=opts.op_cache, seed=opts.seed)
+                          op_cache=opts.op_cache, seed=opts.seed, tune_tiles=1 if opts.tune_tiles else 0)
         h = C.c_void_p()
         st = self.lib.qrvie_server_create(device, C.byref(o), C.byref(h))
         if st != L.OK:

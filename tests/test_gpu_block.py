@@ -119,3 +119,40 @@ def test_block_warm_start_from_the_solution():
     x, info, st = c.op.solve(v, restart=2000, tol=1e-10, max_iter=2000, mode=BLOCK)
     x2, info2, st2 = c.op.solve(v, restart=2000, tol=1e-9, max_iter=2000, mode=BLOCK, x0=x)
     assert st2 == 0 and all(i["iterations"] == 0 for i in info2)
+
+
+@pytest.mark.parametrize("name,nrhs,far_prec", [("rand8x8", 64, 0), ("rand6x7", 24, 1), ("rand5x3", 40, 3)])
+def test_tile_autotuner_keeps_results_bitwise(name, nrhs, far_prec):
+    """The autotuner times every strip tile shape per group (R panels, Q panels, self blocks),
+    keeps only shapes whose output equals the default shape's bit for bit, and the block
+    product after tuning reproduces the untuned one exactly (§8 a8)."""
+    import paper_2603_10586_amd as q
+    c = case(name, far_prec=far_prec)
+    n = c.geom.ndof
+    rng = np.random.default_rng(7 + nrhs)
+    x = to_dev(rng.standard_normal((nrhs, n)) + 1j * rng.standard_normal((nrhs, n)))
+    y0 = to_host(c.op.apply(x))
+    precs = [q.PREC_C64] if far_prec == q.PREC_C64_ONLY else [q.PREC_C128] + ([q.PREC_C64] if far_prec else [])
+    for prec in precs:
+        t = c.op.tune_block(nrhs=nrhs, reps=2, prec=prec)
+        assert t["nrhs_tile"] == 16 * ((nrhs + 15) // 16)
+        assert len(t["variants"]) == 6 and t["variants"][0] == dict(u=2, rows_per_wave=16)
+        for g in ("rphase", "qphase", "self"):
+            assert all(m == 0 for m in t["mismatches"][g]), (g, t["mismatches"][g])
+            assert all(ms > 0 for ms in t["ms"][g])
+            assert 0 <= t["chosen"][g] < 6
+            assert t["ms"][g][t["chosen"][g]] == min(t["ms"][g])
+    y1 = to_host(c.op.apply(x))
+    assert np.array_equal(y0, y1)
+    if far_prec == q.PREC_C64:
+        y2 = to_host(c.op.apply(x, prec=q.PREC_C64))
+        y3 = to_host(c.op.apply(x, prec=q.PREC_C64))
+        assert np.array_equal(y2, y3)
+
+
+def test_tile_autotuner_rejects_bad_arguments():
+    import paper_2603_10586_amd as q
+    c = case("rand5x3")
+    for kw in (dict(nrhs=0), dict(nrhs=65), dict(reps=0), dict(reps=101), dict(prec=q.PREC_C64)):
+        with pytest.raises(q.QrvieError):
+            c.op.tune_block(**{**dict(nrhs=16, reps=1, prec=q.PREC_C128), **kw})
