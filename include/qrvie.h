@@ -142,6 +142,9 @@ enum { QRVIE_PREC_C128 = 0, QRVIE_PREC_C64 = 1, QRVIE_PREC_BF16X2 = 2, QRVIE_PRE
  *   share_transpose  reserved, must be 0
  *   seed             seed of the random sketches used by compression
  *   verbose          1: print one progress line per compression chunk to stderr
+ *   chunk_bytes      device bytes of materialised blocks compressed together; 0 = a
+ *                    quarter of the free device memory (or of the context's remaining
+ *                    budget), at most 64 GiB.  Larger chunks keep more blocks in flight.
  */
 typedef struct {
     double eps;
@@ -151,6 +154,7 @@ typedef struct {
     int32_t share_transpose;
     uint64_t seed;
     int32_t verbose;
+    int64_t chunk_bytes;
 } qrvie_compress_opts;
 
 #define QRVIE_MAX_LEVELS 24

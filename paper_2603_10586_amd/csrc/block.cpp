@@ -12,9 +12,10 @@
 //
 // Orthogonalisation is CGS2 through the Gram matrix of the basis (as in the single-vector
 // solver): C = V^H [V_k, W] in one GEMM, H = 2 H1 - G H1 with G = V^H V, W -= V H; the new
-// block is factorised by Cholesky QR twice.  The basis GEMMs and triangular solves are
-// plain dense BLAS (rocBLAS); the product, the Cholesky factor and the least-squares
-// reflectors are this library's kernels.
+// block is factorised by Cholesky QR twice.  The projections (split-K strided-batched
+// GEMMs), the small Gram correction and the triangular solves are rocBLAS; the basis and
+// solution updates W += V H are this library's FP64 MFMA kernel, like the product, the
+// Cholesky factor and the least-squares reflectors.
 #include <rocblas/rocblas.h>
 
 #include <algorithm>
@@ -225,7 +226,6 @@ struct BlockSolver {
     // until every column's remainder is below 1e-3 tol ||Z_D^-1 b|| or the block is full.
     // Rows 0:q of gl receive S0.  q = 0 means the residuals have no usable direction.
     qrvie_status first_block(const std::vector<double>& pvnorm) {
-        const zc zone = {1.0, 0.0}, zmone = {-1.0, 0.0}, zzero = {0.0, 0.0};
         q = 0;
         c128* E = Rc;
         CHECK(hip_check(ctx, hipMemcpyAsync(E, Zc, sizeof(c128) * n * p, hipMemcpyDeviceToDevice, s), "remainder"));
@@ -243,9 +243,7 @@ struct BlockSolver {
             CHECK(right_solve(Vn, q2, R1, p));
             for (int it = 0; q > 0 && it < 2; ++it) {     // against the kept directions, twice
                 CHECK(gemm_hn(Vb, n, q, Vn, n, q2, Cb, q));
-                CHECK(blas_check(ctx, rocblas_zgemm(hb, rocblas_operation_none, rocblas_operation_none, (int)n, q2, q,
-                                                    &zmone, Z(Vb), (int)n, Z(Cb), q, &zone, Z(Vn), (int)n),
-                                 "zgemm deflation"));
+                launch_gemm_nn_acc(s, n, q, q2, Vb, n, Cb, q, -1.0, Vn, n);
             }
             CHECK(cholqr2(Vn, q2, Hb, q2));
             CHECK(read(nullptr, 0, 2));
@@ -254,9 +252,7 @@ struct BlockSolver {
             // S0 = V_0^H Zc and the remainder E = Zc - V_0 S0
             CHECK(gemm_hn(Vb, n, q, Zc, n, p, gl, ldh));
             CHECK(hip_check(ctx, hipMemcpyAsync(E, Zc, sizeof(c128) * n * p, hipMemcpyDeviceToDevice, s), "remainder"));
-            CHECK(blas_check(ctx, rocblas_zgemm(hb, rocblas_operation_none, rocblas_operation_none, (int)n, p, q,
-                                                &zmone, Z(Vb), (int)n, Z(gl), (int)ldh, &zone, Z(E), (int)n),
-                             "zgemm remainder"));
+            launch_gemm_nn_acc(s, n, q, p, Vb, n, gl, ldh, -1.0, E, n);
             launch_col_norms(s, (int)n, E, n, p, dnrm);
             CHECK(read(dnrm, p, 0));
             bool small = true;
@@ -282,8 +278,8 @@ struct BlockSolver {
         CHECK(blas_check(ctx, rocblas_ztrsm(hb, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
                                             rocblas_diagonal_non_unit, (int)m, p, &zone, Z(Rl), (int)ldh, Z(Yb),
                                             (int)ldh), "ztrsm"));
-        return blas_check(ctx, rocblas_zgemm(hb, rocblas_operation_none, rocblas_operation_none, (int)n, p, (int)m,
-                                             &zone, Z(Vb), (int)n, Z(Yb), (int)ldh, &zone, Z(Xout), (int)n), "zgemm");
+        launch_gemm_nn_acc(s, n, (int)m, p, Vb, n, Yb, ldh, 1.0, Xout, n);
+        return hip_check(ctx, hipGetLastError(), "solution update");
     }
 };
 
@@ -545,9 +541,7 @@ qrvie_status solve_block(qrvie_ctx* ctx, const qrvie_op* op, int na, const c128*
             CHECK(blas_check(ctx, rocblas_zgemm(B.hb, rocblas_operation_none, rocblas_operation_none, (int)m, q, (int)m,
                                                 &zmone, Z(B.G), (int)B.ldh, Z(H1), (int)B.ldh, &ztwo, Z(B.Hb),
                                                 (int)B.ldh), "zgemm gram"));
-            CHECK(blas_check(ctx, rocblas_zgemm(B.hb, rocblas_operation_none, rocblas_operation_none, (int)n, q, (int)m,
-                                                &zmone, Z(B.Vb), (int)n, Z(B.Hb), (int)B.ldh, &zone, Z(W), (int)n),
-                             "zgemm update"));
+            launch_gemm_nn_acc(s, n, (int)m, q, B.Vb, n, B.Hb, B.ldh, -1.0, W, n);
             // block Hessenberg column k: [H; H_{k+1,k}] with W = V_{k+1} H_{k+1,k}
             c128* col = B.Rl + (int64_t)k * q * B.ldh;
             CHECK(hip_check(ctx, hipMemcpy2DAsync(col, sizeof(c128) * B.ldh, B.Hb, sizeof(c128) * B.ldh,

@@ -208,12 +208,12 @@ void launch_permute(hipStream_t s, int32_t N, const int32_t* d_i2c, const c128* 
 // dense linear algebra (k_linalg.hip)
 void launch_gemm(hipStream_t s, int mode, const GemmDesc* d_descs, const int32_t* d_tile_desc,
                  const int32_t* d_tile_mn, int64_t ntiles);
-void launch_qrcp(hipStream_t s, const QrcpDesc* d, int n, int maxrows);
+void launch_qrcp(hipStream_t s, const QrcpDesc* d, int n, int maxrows, bool wide = false);
 void launch_form_q(hipStream_t s, const FormQDesc* d, int n, int maxrows);
 void launch_gemm_residual(hipStream_t s, const GemmDesc* d, const int32_t* td, const int32_t* tmn, int64_t nt,
                           double* partial);
 void launch_extract_r(hipStream_t s, const ExtractRDesc* d, int n);
-void launch_cgs2(hipStream_t s, const Cgs2Desc* d, int n);
+void launch_cgs2(hipStream_t s, const Cgs2Desc* d, int n, int kmax);   // kmax: widest sketch, <= 512
 void launch_pack(hipStream_t s, const PackDesc* d, int n);
 void launch_frob2(hipStream_t s, const c128* const* d_ptr, const int64_t* d_len, double* out, int n);
 void launch_invert(hipStream_t s, c128* A, int nmat, int* d_info);
@@ -299,5 +299,8 @@ void launch_ls_apply(hipStream_t s, int j0, int j1, int p, const c128* Y, const 
 void launch_ls_factor(hipStream_t s, int k, int p, c128* C, int64_t ldc, c128* Yk, c128* Tk);
 void launch_col_norms(hipStream_t s, int rows, const c128* C, int64_t ldc, int ncols, double* out);
 void launch_sum_batches(hipStream_t s, int m, int c, int nb, const c128* P, c128* C, int64_t ldc);
+// W (n x q, q <= 64) += sign V H (V: n x m, H: m x q).  FP64 MFMA, fixed accumulation order.
+void launch_gemm_nn_acc(hipStream_t s, int64_t n, int m, int q, const c128* V, int64_t ldv, const c128* H,
+                        int64_t ldh, double sign, c128* W, int64_t ldw);
 
 }  // namespace qrvie

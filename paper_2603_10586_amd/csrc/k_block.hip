@@ -114,6 +114,67 @@ __global__ void __launch_bounds__(256) k_count_neq(int64_t n, const unsigned lon
     }
 }
 
+// ----------------------------------------------------------------- basis updates on FP64 MFMA
+// W (n x q) += sign * V H for V: n x m, H: m x q (q <= 64): the basis update of block CGS2
+// and the solution update (a long, thin product that rocBLAS runs at about half the FP64
+// matrix rate).  Each wave owns 16 rows of W and all q columns (NT tiles of 16); the m
+// columns of V are visited in ascending batches of U 4-column steps (fixed order).  V is
+// streamed once; H stays in cache.
+template <int NT>
+__global__ void __launch_bounds__(256) k_gemm_nn_acc(int64_t n, int m, int q, const c128* __restrict__ V,
+                                                     int64_t ldv, const c128* __restrict__ H, int64_t ldh,
+                                                     double sign, c128* __restrict__ W, int64_t ldw) {
+    constexpr int U = 4;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int64_t r0 = 64 * (int64_t)blockIdx.x + 16 * w;
+    if (r0 >= n) return;
+    const int rl = lane & 15, kq = lane >> 4;
+    const c128* Vp = V + min(r0 + rl, n - 1);                        // clamped lanes are discarded
+    const c128* Hp[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) Hp[t] = H + (int64_t)min(16 * t + rl, q - 1) * ldh;
+    v4d re[NT], im[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) re[t] = im[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    int i = 0;
+    for (; i + 4 * U <= m; i += 4 * U) {
+        c128 a[U], b[U][NT];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int col = i + 4 * u + kq;
+            a[u] = load_stream(Vp + (int64_t)col * ldv);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) b[u][t] = Hp[t][col];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) cmfma(re[t], im[t], a[u], b[u][t]);
+    }
+    for (; i < m; i += 4) {                                           // remaining steps, the last possibly partial
+        const int col = i + kq;
+        const bool ok = col < m;
+        const c128 z = make_double2(0.0, 0.0);
+        const c128 a = ok ? Vp[(int64_t)col * ldv] : z;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) cmfma(re[t], im[t], a, ok ? Hp[t][col] : z);
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int64_t row = r0 + kq + 4 * s;
+        if (row >= n) continue;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int j = 16 * t + rl;
+            if (j < q) {
+                c128* o = W + row + (int64_t)j * ldw;
+                const c128 v = *o;
+                *o = make_double2(v.x + sign * re[t][s], v.y + sign * im[t][s]);
+            }
+        }
+    }
+}
+
 // out = (V ? V - y : y), y = yself + sum_l ylev[l]; all n x P interleaved
 template <int NT>
 __global__ void k_block_combine(int64_t n, const c128* __restrict__ ylev, int nlev, const c128* __restrict__ yself,
@@ -592,6 +653,17 @@ void launch_sum_batches(hipStream_t s, int m, int c, int nb, const c128* P, c128
     const int64_t per = (int64_t)m * c;
     if (per <= 0) return;
     hipLaunchKernelGGL(k_sum_batches, dim3((unsigned)((per + 255) / 256)), dim3(256), 0, s, m, c, nb, P, C, ldc);
+}
+void launch_gemm_nn_acc(hipStream_t s, int64_t n, int m, int q, const c128* V, int64_t ldv, const c128* H,
+                        int64_t ldh, double sign, c128* W, int64_t ldw) {
+    if (n <= 0 || m <= 0 || q <= 0) return;
+    const dim3 g((unsigned)((n + 63) / 64));
+    switch ((q + 15) / 16) {
+        case 1: hipLaunchKernelGGL(k_gemm_nn_acc<1>, g, dim3(256), 0, s, n, m, q, V, ldv, H, ldh, sign, W, ldw); break;
+        case 2: hipLaunchKernelGGL(k_gemm_nn_acc<2>, g, dim3(256), 0, s, n, m, q, V, ldv, H, ldh, sign, W, ldw); break;
+        case 3: hipLaunchKernelGGL(k_gemm_nn_acc<3>, g, dim3(256), 0, s, n, m, q, V, ldv, H, ldh, sign, W, ldw); break;
+        default: hipLaunchKernelGGL(k_gemm_nn_acc<4>, g, dim3(256), 0, s, n, m, q, V, ldv, H, ldh, sign, W, ldw); break;
+    }
 }
 void launch_col_norms(hipStream_t s, int rows, const c128* C, int64_t ldc, int ncols, double* out) {
     hipLaunchKernelGGL(k_col_norms, dim3(ncols), dim3(256), 0, s, rows, C, ldc, out);

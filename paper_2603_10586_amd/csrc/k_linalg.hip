@@ -10,8 +10,9 @@
 //               rows are recomputed exactly in the same pass as the reflector update.
 //  * k_form_q   explicit orthonormal Q from the stored reflectors.
 //  * k_extract_r  R with the column permutation undone.
-//  * k_cgs2     classical Gram-Schmidt with one reorthogonalisation, dropping
-//               numerically dependent columns (range basis of a sketch).
+//  * k_cgs2     block classical Gram-Schmidt with one reorthogonalisation (FP64 MFMA
+//               panel projections), dropping numerically dependent columns (range
+//               basis of a sketch).
 //  * k_invert   Gauss-Jordan inversion with partial pivoting of 144 x 144 blocks.
 // All reductions run in a fixed order: results do not depend on scheduling.
 #include "internal.h"
@@ -37,6 +38,19 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 __device__ __forceinline__ c128 wave_sum(c128 v) {
     return make_double2(wave_sum(v.x), wave_sum(v.y));
+}
+
+// Block-wide sum of one double per thread over NW waves, fixed order.
+template <int NW>
+__device__ double block_sum(double v, double* red) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) red[wv] = v;
+    __syncthreads();
+    double r = red[0];
+    for (int w = 1; w < NW; ++w) r += red[w];
+    return r;
 }
 
 // Block-wide sum of one double per thread (256 threads), fixed order.
@@ -154,20 +168,21 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc* descs, const int32
 }
 
 // --------------------------------------------------------------------- QRCP
-template <int MAXR>
-__global__ void __launch_bounds__(256) k_qrcp(const QrcpDesc* descs) {
+template <int MAXR, int NTH>
+__global__ void __launch_bounds__(NTH) k_qrcp(const QrcpDesc* descs) {
+    constexpr int NW = NTH / 64;
     const QrcpDesc d = descs[blockIdx.x];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int m = d.m, n = d.n;
     const int64_t lda = d.lda;
     const int kmax = min(d.kmax, min(m, n));
     __shared__ c128 wl[64 * MAXR];
-    __shared__ double rsum[256];
-    __shared__ double rmax[256];
-    __shared__ int rarg[256];
+    __shared__ double rsum[NTH];
+    __shared__ double rmax[NTH];
+    __shared__ int rarg[NTH];
     __shared__ double s_tau;
 
-    for (int j = wv; j < n; j += 4) {
+    for (int j = wv; j < n; j += NW) {
         double s = 0.0;
         for (int i = lane; i < m; i += 64) s += cabs2(d.A[i + j * lda]);
         s = wave_sum(s);
@@ -182,14 +197,14 @@ __global__ void __launch_bounds__(256) k_qrcp(const QrcpDesc* descs) {
         // trailing sum and pivot over j in [s, n)
         double sum = 0.0, best = -1.0;
         int bj = n;
-        for (int j = s + tid; j < n; j += 256) {
+        for (int j = s + tid; j < n; j += NTH) {
             const double v = d.colnorm2[j];
             sum += v;
             if (v > best) { best = v; bj = j; }
         }
         rsum[tid] = sum; rmax[tid] = best; rarg[tid] = bj;
         __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
+        for (int o = NTH / 2; o > 0; o >>= 1) {
             if (tid < o) {
                 rsum[tid] += rsum[tid + o];
                 const double b2 = rmax[tid + o];
@@ -209,7 +224,7 @@ __global__ void __launch_bounds__(256) k_qrcp(const QrcpDesc* descs) {
         }
         if (total <= tol2 || s >= kmax) { rank = s; trail = total; break; }
         if (p != s) {
-            for (int i = tid; i < m; i += 256) {
+            for (int i = tid; i < m; i += NTH) {
                 const c128 a = d.A[i + s * lda];
                 d.A[i + s * lda] = d.A[i + p * lda];
                 d.A[i + p * lda] = a;
@@ -239,35 +254,54 @@ __global__ void __launch_bounds__(256) k_qrcp(const QrcpDesc* descs) {
                 wl[0] = w0;
             }
         }
-        for (int i = 1 + tid; i < m - s; i += 256) wl[i] = d.A[s + i + s * lda];
+        for (int i = 1 + tid; i < m - s; i += NTH) wl[i] = d.A[s + i + s * lda];
         __syncthreads();
         const double tau = s_tau;
-        for (int j = s + 1 + wv; j < n; j += 4) {
-            c128 a[MAXR];
-            c128 dot = make_double2(0.0, 0.0);
+        // trailing columns, each wave taking every NW-th one; CJ columns at a time so that
+        // their independent wave reductions overlap
+        constexpr int CJ = MAXR <= 4 ? 4 : (MAXR <= 10 ? 2 : 1);
+        for (int j0 = s + 1 + wv; j0 < n; j0 += NW * CJ) {
+            c128 a[CJ][MAXR];
+            c128 dot[CJ];
 #pragma unroll
-            for (int q = 0; q < MAXR; ++q) {
-                const int i = lane + 64 * q;
-                a[q] = make_double2(0.0, 0.0);
-                if (s + i < m) {
-                    a[q] = d.A[s + i + j * lda];
-                    dot = cadd(dot, cmulc(wl[i], a[q]));
+            for (int c = 0; c < CJ; ++c) {
+                const int j = j0 + NW * c;
+                dot[c] = make_double2(0.0, 0.0);
+#pragma unroll
+                for (int q = 0; q < MAXR; ++q) {
+                    const int i = lane + 64 * q;
+                    a[c][q] = make_double2(0.0, 0.0);
+                    if (j < n && s + i < m) {
+                        a[c][q] = d.A[s + i + (int64_t)j * lda];
+                        dot[c] = cadd(dot[c], cmulc(wl[i], a[c][q]));
+                    }
                 }
             }
-            dot = wave_sum(dot);
-            const c128 f = make_double2(tau * dot.x, tau * dot.y);
-            double nrm = 0.0;
 #pragma unroll
-            for (int q = 0; q < MAXR; ++q) {
-                const int i = lane + 64 * q;
-                if (s + i < m) {
-                    a[q] = csub(a[q], cmul(wl[i], f));
-                    d.A[s + i + j * lda] = a[q];
-                    if (i >= 1) nrm += cabs2(a[q]);
+            for (int c = 0; c < CJ; ++c) dot[c] = wave_sum(dot[c]);
+            double nrm[CJ];
+#pragma unroll
+            for (int c = 0; c < CJ; ++c) {
+                const int j = j0 + NW * c;
+                const c128 f = make_double2(tau * dot[c].x, tau * dot[c].y);
+                nrm[c] = 0.0;
+#pragma unroll
+                for (int q = 0; q < MAXR; ++q) {
+                    const int i = lane + 64 * q;
+                    if (j < n && s + i < m) {
+                        a[c][q] = csub(a[c][q], cmul(wl[i], f));
+                        d.A[s + i + (int64_t)j * lda] = a[c][q];
+                        if (i >= 1) nrm[c] += cabs2(a[c][q]);
+                    }
                 }
             }
-            nrm = wave_sum(nrm);
-            if (lane == 0) d.colnorm2[j] = nrm;
+#pragma unroll
+            for (int c = 0; c < CJ; ++c) nrm[c] = wave_sum(nrm[c]);
+            if (lane == 0) {
+#pragma unroll
+                for (int c = 0; c < CJ; ++c)
+                    if (j0 + NW * c < n) d.colnorm2[j0 + NW * c] = nrm[c];
+            }
         }
         __syncthreads();
     }
@@ -327,46 +361,142 @@ __global__ void __launch_bounds__(256) k_extract_r(const ExtractRDesc* descs) {
     }
 }
 
-// CGS2 with dropping; the kept columns are compacted to the front of Y.
-__global__ void __launch_bounds__(256) k_cgs2(const Cgs2Desc* descs) {
+// Block CGS2 with dropping; the kept columns are compacted to the front of Y.  The sketch is
+// taken in panels of 16 columns.  Each panel is projected against all kept columns Q twice
+// (H = Q^H P, P -= Q H) on FP64 MFMA: the waves split the 16-column tiles of Q for H and
+// the 16-row tiles of P for the update, with H in LDS.  The panel's columns are then
+// orthogonalised one by one against the panel's earlier kept columns, twice (one sweep over
+// the rows per pass for all dot products), and a column is kept when its remaining norm
+// exceeds drop_rel times its norm before any projection.  Every reduction has a fixed order.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// Operand layout of the 16x16x4 FP64 MFMA: A (16 x 4): lane l holds A[l % 16][l / 16];
+// B (4 x 16): lane l holds B[l / 16][l % 16]; D (16 x 16): lane l, slot i holds
+// D[l / 16 + 4 i][l % 16].  A complex product is four real MFMAs.
+__device__ __forceinline__ void cmfma(v4d& re, v4d& im, c128 a, c128 b) {
+    re = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, re, 0, 0, 0);
+    re = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, re, 0, 0, 0);
+    im = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, im, 0, 0, 0);
+    im = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, im, 0, 0, 0);
+}
+
+constexpr int kPanel = 16;
+
+template <int KMAX, int NTH>
+__global__ void __launch_bounds__(NTH) k_cgs2(const Cgs2Desc* descs) {
+    constexpr int NW = NTH / 64;
     const Cgs2Desc d = descs[blockIdx.x];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int rl = lane & 15, kq = lane >> 4;
     const int m = d.m;
     const int64_t ld = d.ldy;
-    __shared__ c128 h[512];
-    __shared__ double red[4];
+    c128* Y = d.Y;
+    __shared__ c128 Hs[KMAX * kPanel];          // H = Q^H P, row q at Hs[q * 16]
+    __shared__ c128 red16[NW][kPanel];
+    __shared__ c128 hcol[kPanel];
+    __shared__ double n0s[kPanel];
+    __shared__ double red[NW];
+    const c128 z = make_double2(0.0, 0.0);
     int kept = 0;
-    for (int c = 0; c < d.k; ++c) {
-        c128* y = d.Y + (int64_t)c * ld;
-        double n0 = 0.0;
-        for (int i = tid; i < m; i += 256) n0 += cabs2(y[i]);
-        n0 = block_sum256(n0, red);
-        for (int pass = 0; pass < 2; ++pass) {
-            for (int q = wv; q < kept; q += 4) {
-                const c128* qc = d.Y + (int64_t)q * ld;
-                c128 s = make_double2(0.0, 0.0);
-                for (int i = lane; i < m; i += 64) s = cadd(s, cmulc(qc[i], y[i]));
-                s = wave_sum(s);
-                if (lane == 0) h[q] = s;
-            }
-            __syncthreads();
-            for (int i = tid; i < m; i += 256) {
-                c128 v = y[i];
-                for (int q = 0; q < kept; ++q) v = csub(v, cmul(d.Y[i + (int64_t)q * ld], h[q]));
-                y[i] = v;
-            }
-            __syncthreads();
-        }
-        double nr = 0.0;
-        for (int i = tid; i < m; i += 256) nr += cabs2(y[i]);
-        nr = block_sum256(nr, red);
-        if (nr > 0.0 && nr > d.drop_rel * d.drop_rel * n0 && kept < 512) {
-            const double inv = 1.0 / sqrt(nr);
-            c128* dst = d.Y + (int64_t)kept * ld;
-            for (int i = tid; i < m; i += 256) dst[i] = make_double2(y[i].x * inv, y[i].y * inv);
-            ++kept;
+    for (int c0 = 0; c0 < d.k; c0 += kPanel) {
+        const int pc = min(kPanel, d.k - c0);
+        c128* P = Y + (int64_t)c0 * ld;
+        for (int j = wv; j < pc; j += NW) {
+            double s = 0.0;
+            for (int i = lane; i < m; i += 64) s += cabs2(P[i + j * ld]);
+            s = wave_sum(s);
+            if (lane == 0) n0s[j] = s;
         }
         __syncthreads();
+        for (int pass = 0; pass < 2 && kept > 0; ++pass) {
+            // H = Q^H P: tile t of 16 kept columns per wave, 4-row steps over m
+            const int pj = min(rl, pc - 1);
+            for (int t = wv; 16 * t < kept; t += NW) {
+                const int qa = min(16 * t + rl, kept - 1);
+                v4d re = v4d{0.0, 0.0, 0.0, 0.0}, im = re;
+                for (int i = 0; i < m; i += 4) {
+                    const int row = i + kq;
+                    const bool ok = row < m;
+                    c128 a = ok ? Y[row + qa * ld] : z;
+                    a.y = -a.y;
+                    cmfma(re, im, a, ok ? P[row + pj * ld] : z);
+                }
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int q = 16 * t + kq + 4 * s;
+                    if (q < kept) Hs[q * kPanel + rl] = make_double2(re[s], im[s]);
+                }
+            }
+            __syncthreads();
+            // P -= Q H: row tile r of 16 rows per wave, 4-column steps over the kept columns
+            for (int r = wv; 16 * r < m; r += NW) {
+                const int r0 = 16 * r;
+                const int ra = min(r0 + rl, m - 1);
+                v4d re = v4d{0.0, 0.0, 0.0, 0.0}, im = re;
+                for (int q = 0; q < kept; q += 4) {
+                    const int qq = q + kq;
+                    const bool ok = qq < kept;
+                    cmfma(re, im, ok ? Y[ra + qq * ld] : z, ok ? Hs[qq * kPanel + rl] : z);
+                }
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int row = r0 + kq + 4 * s;
+                    if (row < m && rl < pc) {
+                        const c128 v = P[row + rl * ld];
+                        P[row + rl * ld] = make_double2(v.x - re[s], v.y - im[s]);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        // within the panel, column by column
+        const int kept0 = kept;
+        for (int j = 0; j < pc; ++j) {
+            c128* y = P + (int64_t)j * ld;
+            const int np = kept - kept0;
+            for (int pass = 0; pass < 2 && np > 0; ++pass) {
+                c128 part[kPanel - 1];
+#pragma unroll
+                for (int q = 0; q < kPanel - 1; ++q) part[q] = z;
+                for (int i = tid; i < m; i += NTH) {
+                    const c128 v = y[i];
+#pragma unroll
+                    for (int q = 0; q < kPanel - 1; ++q)
+                        if (q < np) part[q] = cadd(part[q], cmulc(Y[i + (int64_t)(kept0 + q) * ld], v));
+                }
+#pragma unroll
+                for (int q = 0; q < kPanel - 1; ++q)
+                    if (q < np) {
+                        const c128 w = wave_sum(part[q]);
+                        if (lane == 0) red16[wv][q] = w;
+                    }
+                __syncthreads();
+                if (tid < np) {
+                    c128 h = red16[0][tid];
+                    for (int w = 1; w < NW; ++w) h = cadd(h, red16[w][tid]);
+                    hcol[tid] = h;
+                }
+                __syncthreads();
+                for (int i = tid; i < m; i += NTH) {
+                    c128 v = y[i];
+#pragma unroll
+                    for (int q = 0; q < kPanel - 1; ++q)
+                        if (q < np) v = csub(v, cmul(Y[i + (int64_t)(kept0 + q) * ld], hcol[q]));
+                    y[i] = v;
+                }
+                __syncthreads();
+            }
+            double nr = 0.0;
+            for (int i = tid; i < m; i += NTH) nr += cabs2(y[i]);
+            nr = block_sum<NW>(nr, red);
+            if (nr > 0.0 && nr > d.drop_rel * d.drop_rel * n0s[j] && kept < KMAX) {
+                const double inv = 1.0 / sqrt(nr);
+                c128* dst = Y + (int64_t)kept * ld;
+                for (int i = tid; i < m; i += NTH) dst[i] = make_double2(y[i].x * inv, y[i].y * inv);
+                ++kept;
+            }
+            __syncthreads();
+        }
     }
     if (tid == 0) *d.kept_out = kept;
 }
@@ -485,12 +615,20 @@ void launch_gemm_residual(hipStream_t s, const GemmDesc* d, const int32_t* td, c
     hipLaunchKernelGGL(k_gemm<3>, dim3((unsigned)nt), dim3(256), 0, s, d, td, tmn, partial);
 }
 
-void launch_qrcp(hipStream_t s, const QrcpDesc* d, int n, int maxrows) {
+void launch_qrcp(hipStream_t s, const QrcpDesc* d, int n, int maxrows, bool wide) {
     if (n <= 0) return;
-    if (maxrows <= 192) hipLaunchKernelGGL(k_qrcp<3>, dim3(n), dim3(256), 0, s, d);
-    else if (maxrows <= 256) hipLaunchKernelGGL(k_qrcp<4>, dim3(n), dim3(256), 0, s, d);
-    else if (maxrows <= 640) hipLaunchKernelGGL(k_qrcp<10>, dim3(n), dim3(256), 0, s, d);
-    else hipLaunchKernelGGL(k_qrcp<16>, dim3(n), dim3(256), 0, s, d);
+    // wide: few, long matrices (the projected sketches of large blocks) get 512 threads each
+    if (wide) {
+        if (maxrows <= 192) hipLaunchKernelGGL((k_qrcp<3, 512>), dim3(n), dim3(512), 0, s, d);
+        else if (maxrows <= 256) hipLaunchKernelGGL((k_qrcp<4, 512>), dim3(n), dim3(512), 0, s, d);
+        else if (maxrows <= 640) hipLaunchKernelGGL((k_qrcp<10, 512>), dim3(n), dim3(512), 0, s, d);
+        else hipLaunchKernelGGL((k_qrcp<16, 512>), dim3(n), dim3(512), 0, s, d);
+        return;
+    }
+    if (maxrows <= 192) hipLaunchKernelGGL((k_qrcp<3, 256>), dim3(n), dim3(256), 0, s, d);
+    else if (maxrows <= 256) hipLaunchKernelGGL((k_qrcp<4, 256>), dim3(n), dim3(256), 0, s, d);
+    else if (maxrows <= 640) hipLaunchKernelGGL((k_qrcp<10, 256>), dim3(n), dim3(256), 0, s, d);
+    else hipLaunchKernelGGL((k_qrcp<16, 256>), dim3(n), dim3(256), 0, s, d);
 }
 
 void launch_form_q(hipStream_t s, const FormQDesc* d, int n, int maxrows) {
@@ -504,8 +642,10 @@ void launch_form_q(hipStream_t s, const FormQDesc* d, int n, int maxrows) {
 void launch_extract_r(hipStream_t s, const ExtractRDesc* d, int n) {
     if (n > 0) hipLaunchKernelGGL(k_extract_r, dim3(n), dim3(256), 0, s, d);
 }
-void launch_cgs2(hipStream_t s, const Cgs2Desc* d, int n) {
-    if (n > 0) hipLaunchKernelGGL(k_cgs2, dim3(n), dim3(256), 0, s, d);
+void launch_cgs2(hipStream_t s, const Cgs2Desc* d, int n, int kmax) {
+    if (n <= 0) return;
+    if (kmax <= 128) hipLaunchKernelGGL((k_cgs2<128, 512>), dim3(n), dim3(512), 0, s, d);
+    else hipLaunchKernelGGL((k_cgs2<512, 512>), dim3(n), dim3(512), 0, s, d);
 }
 void launch_pack(hipStream_t s, const PackDesc* d, int n) {
     if (n > 0) hipLaunchKernelGGL(k_pack, dim3(n), dim3(256), 0, s, d);

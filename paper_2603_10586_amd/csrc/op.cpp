@@ -123,6 +123,38 @@ struct Builder {
     std::vector<Factor> fac;                        // per block (primary only filled)
     std::vector<std::pair<void*, size_t>> segments; // compact factor storage
     double eps;
+    // The materialised blocks of a chunk and the direct blocks' working copies live in two
+    // grow-only buffers kept across chunks: allocating and releasing tens of GB per chunk
+    // cost about as much host time as the chunk's kernels.
+    c128* pool[2] = {nullptr, nullptr};
+    size_t pool_elems[2] = {0, 0};
+
+    qrvie_status pooled(int which, size_t elems, c128** p, const char* what) {
+        *p = nullptr;
+        if (elems == 0) return QRVIE_OK;
+        if (elems > pool_elems[which]) {
+            if (pool[which]) {
+                (void)hipStreamSynchronize(ctx->stream);
+                dfree(ctx, pool[which], pool_elems[which] * sizeof(c128));
+            }
+            pool[which] = nullptr;
+            pool_elems[which] = 0;
+            CHECK(dalloc(ctx, (void**)&pool[which], elems * sizeof(c128), what));
+            pool_elems[which] = elems;
+        }
+        *p = pool[which];
+        return QRVIE_OK;
+    }
+    void release_pools() {
+        if (!pool[0] && !pool[1]) return;
+        (void)hipStreamSynchronize(ctx->stream);
+        for (int w = 0; w < 2; ++w) {
+            if (pool[w]) dfree(ctx, pool[w], pool_elems[w] * sizeof(c128));
+            pool[w] = nullptr;
+            pool_elems[w] = 0;
+        }
+    }
+    ~Builder() { release_pools(); }
 
     qrvie_status new_segment(size_t elems, c128** p) {
         *p = nullptr;
@@ -147,7 +179,7 @@ struct Builder {
             btot += m[i] * n[i];
         }
         c128* dB;
-        CHECK(ar.alloc(&dB, btot, "block buffer"));
+        CHECK(pooled(0, (size_t)btot, &dB, "block buffer"));
         {   // assembly
             std::vector<AsmDesc> ad(nb);
             std::vector<int32_t> wb, wc;
@@ -178,7 +210,7 @@ struct Builder {
                 aoff[i] = atot;
                 atot += m[i] * n[i];
             }
-            CHECK(ar.alloc(&dA, atot, "factorisation buffer"));
+            CHECK(pooled(1, (size_t)atot, &dA, "factorisation buffer"));
             for (size_t i : dir) {
                 const BlockRec& b = blocks[ids[i]];
                 ad.push_back(AsmDesc{dA + aoff[i], m[i], b.r0, b.rn, b.c0, b.cn});
@@ -260,7 +292,9 @@ struct Builder {
             }
             Cgs2Desc* dcd;
             CHECK(ar.upload(&dcd, cd, "cgs2 descs"));
-            launch_cgs2(s, dcd, (int)cd.size());
+            int kmax = 0;
+            for (const Cgs2Desc& c : cd) kmax = std::max(kmax, c.k);
+            launch_cgs2(s, dcd, (int)cd.size(), kmax);
             CHECK(hip_check(ctx, hipGetLastError(), "sketch"));
             std::vector<int32_t> hk;
             std::vector<double> hn2;
@@ -327,7 +361,7 @@ struct Builder {
         CHECK(ar.upload(&dqdir, qdir, "qrcp descs"));
         CHECK(ar.upload(&dqsk, qsk, "qrcp descs"));
         launch_qrcp(s, dqdir, (int)qdir.size(), maxrows_dir);
-        launch_qrcp(s, dqsk, (int)qsk.size(), maxrows_sk);
+        launch_qrcp(s, dqsk, (int)qsk.size(), maxrows_sk, true);
         CHECK(hip_check(ctx, hipGetLastError(), "qrcp"));
         std::vector<int32_t> rank;
         std::vector<double> n2;
@@ -469,7 +503,7 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
     if ((o->far_prec != QRVIE_PREC_C128 && o->far_prec != QRVIE_PREC_C64 && o->far_prec != QRVIE_PREC_C64_ONLY) ||
         o->near_prec != QRVIE_PREC_C128 ||
         o->share_transpose != 0 ||
-        o->max_block_rows < 0) {
+        o->max_block_rows < 0 || o->chunk_bytes < 0) {
         set_err(ctx, "op_create: unsupported precision or option");
         return QRVIE_ERR_INVALID_ARG;
     }
@@ -554,7 +588,7 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
     bld.fac.resize(NB);
 
     // compress primary blocks in chunks bounded by the materialised block bytes
-    // (an eighth of the free device memory, or of the remaining budget, at most 48 GiB: the
+    // (a quarter of the free device memory, or of the remaining budget, at most 64 GiB: the
     // one-workgroup-per-block kernels of the sketch path are better used with many blocks,
     // and concurrent builds on one device still leave room for each other)
     double room = 8.0 * (1ull << 30);
@@ -564,7 +598,8 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
         if (ctx->budget) room = std::min(room, (double)(ctx->budget - ctx->in_use.load()));
     }
     const int64_t chunk_elems =
-        (int64_t)(std::min(48.0 * (1ull << 30), std::max(2.56e8, room / 8.0)) / sizeof(c128));
+        o->chunk_bytes > 0 ? std::max<int64_t>(1, o->chunk_bytes / (int64_t)sizeof(c128))
+                           : (int64_t)(std::min(64.0 * (1ull << 30), std::max(2.56e8, room / 4.0)) / sizeof(c128));
     {
         std::vector<int32_t> ids, kw;
         int64_t acc = 0;
@@ -603,6 +638,7 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
             if (i < NB) --i;   // re-visit the block that did not fit
         }
     }
+    bld.release_pools();
     (void)hipStreamSynchronize(s);
     const double t2 = now_s();
     op->stats.t_compression_s = t2 - t1;

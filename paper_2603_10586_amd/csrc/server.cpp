@@ -145,15 +145,23 @@ void admit_locked(qrvie_server* s, std::vector<Cached>& drops) {
     if (!adm.empty()) s->cv.notify_all();
 }
 
+// Far blocks of more rows are split into child pairs: materialised blocks stay at most
+// 1.36 GB, so a build's compression chunks hold many blocks for the one-workgroup-per-block
+// kernels (the largest arrays otherwise compress 21.7 GB blocks one at a time).
+constexpr int64_t kServerMaxBlockRows = 9216;
+// Concurrent builds share the device: each compresses at most 16 GiB of blocks at a time.
+constexpr int64_t kServerChunkBytes = (int64_t)16 << 30;
+
 qrvie_compress_opts compress_opts(const qrvie_server* s) {
     qrvie_compress_opts co{};
     co.eps = s->o.eps;
     co.far_prec = QRVIE_PREC_C128;
     co.near_prec = QRVIE_PREC_C128;
-    co.max_block_rows = 0;
+    co.max_block_rows = kServerMaxBlockRows;
     co.share_transpose = 0;
     co.seed = s->o.seed;
     co.verbose = 0;
+    co.chunk_bytes = kServerChunkBytes;
     return co;
 }
 
