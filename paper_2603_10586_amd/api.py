@@ -166,10 +166,10 @@ class Operator:
     """The compressed interaction operator Z_QR with its block-diagonal preconditioner."""
 
     def __init__(self, ctx: Context, geom: Geometry, eps: float = 1e-6, max_block_rows: int = 0, seed: int = 0,
-                 far_prec: int = L.PREC_C128, verbose: bool = False):
+                 far_prec: int = L.PREC_C128, verbose: bool = False, chunk_bytes: int = 0):
         self.ctx, self.geom, self.far_prec = ctx, geom, far_prec
         o = L.CompressOpts(eps=eps, far_prec=far_prec, near_prec=L.PREC_C128, max_block_rows=max_block_rows,
-                           share_transpose=0, seed=seed, verbose=1 if verbose else 0)
+                           share_transpose=0, seed=seed, verbose=1 if verbose else 0, chunk_bytes=chunk_bytes)
         self.opts = o
         h = C.c_void_p()
         ctx.check(ctx.lib.qrvie_op_create(ctx.h, geom.h, C.byref(o), C.byref(h)), "op_create")

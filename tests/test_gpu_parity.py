@@ -276,3 +276,23 @@ def test_gain_and_stats_are_consistent():
     assert abs(s["gain"] - n * n / nqr) <= 1e-12 * s["gain"]
     assert s["max_block_rel_err"] <= c.eps
     assert s["n_blocks"] == len(c.factors())
+
+
+def test_factors_do_not_depend_on_the_compression_chunking():
+    """Sketches are seeded per block and every reduction has a fixed order, so compressing
+    the blocks in small chunks (several launches, retries per chunk) gives bitwise the
+    factors of one large chunk (§5.2 compression, scheduled in chunks of device memory)."""
+    import paper_2603_10586_amd as q
+    c = case("rand8x8")
+    small = q.Operator(c.ctx, c.geom, eps=c.eps, chunk_bytes=8 << 20)
+    assert small.num_blocks() == c.op.num_blocks()
+    for b in range(small.num_blocks()):
+        i1, Q1, R1 = small.export_block(b)
+        i0, Q0, R0 = c.op.export_block(b)
+        assert i1 == i0
+        if Q0 is None:
+            assert Q1 is None
+            continue
+        assert np.array_equal(Q1, Q0) and np.array_equal(R1, R0)
+    with pytest.raises(q.QrvieError):
+        q.Operator(c.ctx, c.geom, eps=c.eps, chunk_bytes=-1)
