@@ -134,7 +134,11 @@ def serving(args) -> int:
         "latency_ms_p50": round(st["latency_p50_s"] * 1e3, 1), "latency_ms_p99": round(st["latency_p99_s"] * 1e3, 1),
         "requests_per_s": round(st["requests_per_s"], 4), "queue_wait_ms_p50": round(st["queue_wait_p50_s"] * 1e3, 1),
         "peak_admitted_bytes": st["peak_bytes"], "operators_built": st["ops_built"], "cache_hits": st["cache_hits"],
-        "all_converged": ok, "worst_true_residual": worst, "rhs_solved": st["rhs_solved"], "wall_s": round(wall, 1)}))
+        "all_converged": ok, "worst_true_residual": worst, "rhs_solved": st["rhs_solved"], "wall_s": round(wall, 1),
+        "requests": {"fields": ["particles", "waves", "status", "latency_s", "queue_s", "block_steps"],
+                     "rows": [[q.array.n_particles, len(q.incidence.theta_deg), r.status, round(r.latency, 2),
+                               round(r.admitted - r.arrival, 2), max(i["iterations"] for i in r.info)]
+                              for q, r in zip(reqs, res)]}}))
     return 0
 
 
@@ -245,6 +249,8 @@ def main() -> int:
     ap.add_argument("--block", action="store_true",
                     help="block GMRES on 64 plane waves (FP64 matrix-core products)")
     ap.add_argument("--no-tune", action="store_true", help="block mode without the tile autotuner")
+    ap.add_argument("--ir-reference", action="store_true",
+                    help="with --mixed-ir: also solve in plain FP64 and report per-RHS differences")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the block and mixed-precision forms in the default line")
     ap.add_argument("--graded", action="store_true", help="block mode on the 64 x 64 graded metalens array")
@@ -297,7 +303,8 @@ def main() -> int:
     geom = q.Geometry(ctx, arr)
     # the complex64 copy of the far factors serves the mixed-precision line; the FP64 solves
     # and products read only the complex128 panels
-    op = q.Operator(ctx, geom, eps=args.eps, far_prec=q.PREC_C64 if (args.mixed_ir or not args.no_forms) else q.PREC_C128)
+    op = q.Operator(ctx, geom, eps=args.eps, far_prec=q.PREC_C64 if (args.mixed_ir or not args.no_forms) else q.PREC_C128,
+                    max_block_rows=args.max_block_rows, verbose=arr.n_particles > 1024)
     mode = q.SOLVE_MIXED_IR if args.mixed_ir else q.SOLVE_FP64
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
@@ -383,10 +390,29 @@ def main() -> int:
     }
     if not args.mixed_ir and not args.no_forms and args.nrhs == 1:
         out["forms"] = other_forms(q, W, ctx, geom, op, v, args, out["solves_per_s"])
+    if args.mixed_ir and args.ir_reference:
+        out["fp64_reference"] = ir_reference(q, op, v, x, args, total_s / args.steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(op, geom, seconds=args.cpu_seconds)
     print(json.dumps(out))
     return 0
+
+
+def ir_reference(q, op, v, x_ir, args, s_ir: float) -> dict:
+    """The plain FP64 solve of the same right-hand sides on the same operator (complex128
+    factors), its time, and each right-hand side's relative difference between the
+    mixed-precision and the FP64 solutions."""
+    import torch
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    x64, info, _ = op.solve(v, restart=args.restart, tol=args.tol, max_iter=args.max_iter, mode=q.SOLVE_FP64)
+    torch.cuda.synchronize()
+    s64 = time.perf_counter() - t
+    err = [float(torch.linalg.norm(x_ir[r] - x64[r]) / torch.linalg.norm(x64[r])) for r in range(x64.shape[0])]
+    print(f"[bench] FP64 reference: {s64:.2f} s, per-RHS difference {max(err):.2e}", file=sys.stderr, flush=True)
+    return {"s_per_solve": round(s64, 3), "iterations": [i["iterations"] for i in info],
+            "rel_res_true": [i["rel_res_true"] for i in info], "converged": all(i["converged"] for i in info),
+            "rel_diff_per_rhs": err, "mixed_precision_speedup": round(s64 / s_ir, 2)}
 
 
 def tune_tiles(op, prec=None) -> dict:

@@ -327,7 +327,11 @@ typedef struct {
 
 /* Upper bound of the device bytes qrvie_solve allocates for nrhs right-hand sides
  * (Krylov bases, Hessenberg data and product workspaces), for admission control by
- * callers that share one device; `op` may be NULL before the operator exists. */
+ * callers that share one device; `op` may be NULL before the operator exists.  The
+ * estimate follows opts->mode: one group of up to 8 columns with `restart` basis vectors
+ * each (FP64, MIXED_IR), or one block of up to block_width columns sharing `restart` basis
+ * vectors (BLOCK; a rank-deficient block is finished by the single-vector solver with the
+ * same total of basis vectors, restart / min(columns, 8) per column). */
 qrvie_status qrvie_solve_footprint_estimate(const qrvie_geom* g, const qrvie_op* op, int32_t nrhs,
                                             const qrvie_solve_opts* opts, size_t* bytes);
 

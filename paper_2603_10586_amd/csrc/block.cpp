@@ -73,7 +73,7 @@ constexpr double kCholFloor = 1e-15;
 // 32 M complex entries (512 MB).
 constexpr int64_t kMaxChunks = 256;
 constexpr int64_t kMinChunkRows = 512;
-constexpr int64_t kPartialElems = (int64_t)32 << 20;
+constexpr int64_t kPartialElems = kBlockPartialElems;
 
 struct BlockSolver {
     qrvie_ctx* ctx;

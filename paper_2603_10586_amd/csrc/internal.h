@@ -83,6 +83,7 @@ struct QrcpDesc {                   // truncated column-pivoted QR of A (m x n),
     int32_t* rank_out;
     double* trail2_out;
     double* norm2_out;
+    double* tol2_state;             // stepped QRCP: the tolerance, kept between launches
 };
 struct FormQDesc {                  // Q (m x r) = P_0 ... P_{r-1} [I_r; 0] from QRCP reflectors
     const c128* A; int32_t m, lda, r;
@@ -208,7 +209,9 @@ void launch_permute(hipStream_t s, int32_t N, const int32_t* d_i2c, const c128* 
 // dense linear algebra (k_linalg.hip)
 void launch_gemm(hipStream_t s, int mode, const GemmDesc* d_descs, const int32_t* d_tile_desc,
                  const int32_t* d_tile_mn, int64_t ntiles);
-void launch_qrcp(hipStream_t s, const QrcpDesc* d, int n, int maxrows, bool wide = false);
+void launch_qrcp(hipStream_t s, const QrcpDesc* d, int n, int maxrows);
+// maxrows / maxcols / maxsteps: largest m, n and min(kmax, m, n) over the matrices
+void launch_qrcp_stepped(hipStream_t s, const QrcpDesc* d, int n, int maxrows, int maxcols, int maxsteps);
 void launch_form_q(hipStream_t s, const FormQDesc* d, int n, int maxrows);
 void launch_gemm_residual(hipStream_t s, const GemmDesc* d, const int32_t* td, const int32_t* tmn, int64_t nt,
                           double* partial);

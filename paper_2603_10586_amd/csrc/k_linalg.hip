@@ -311,6 +311,167 @@ __global__ void __launch_bounds__(NTH) k_qrcp(const QrcpDesc* descs) {
     }
 }
 
+// Stepped QRCP for the projected sketches W (at most a few hundred rows, up to 10^4
+// columns, few matrices per chunk): the same truncated column-pivoted Householder QR, but
+// each pivot step is two launches over all matrices, so one matrix's trailing update is
+// spread over many workgroups.  k_qrcp_begin computes the column norms and the tolerance;
+// k_qrcp_pivot (one workgroup per matrix) picks the pivot, stops at the tolerance, swaps
+// and forms the reflector; k_qrcp_apply (workgroups over 128-column chunks) applies it to
+// the trailing columns and recomputes their exact trailing norms.  A finished matrix has
+// rank_out >= 0 and its workgroups return at once.
+constexpr int kQrcpChunk = 128;
+
+__global__ void __launch_bounds__(256) k_qrcp_begin(const QrcpDesc* descs) {
+    const QrcpDesc d = descs[blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    __shared__ double red[4];
+    double part = 0.0;
+    for (int j = wv; j < d.n; j += 4) {
+        double sj = 0.0;
+        for (int i = lane; i < d.m; i += 64) sj += cabs2(d.A[i + (int64_t)j * d.lda]);
+        sj = wave_sum(sj);
+        if (lane == 0) { d.colnorm2[j] = sj; d.perm[j] = j; }
+        part += sj;                     // wave-uniform
+    }
+    const double total = block_sum<4>(lane == 0 ? part : 0.0, red);
+    if (tid == 0) {
+        const double base = d.base2 > 0.0 ? d.base2 : total;
+        const double sub = d.sub2 < 0.0 ? fmax(0.0, base - total) : d.sub2;
+        *d.tol2_state = d.rel2 * base - sub;
+        if (d.norm2_out) *d.norm2_out = total;
+        *d.rank_out = -1;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_qrcp_pivot(const QrcpDesc* descs, int s) {
+    const QrcpDesc d = descs[blockIdx.x];
+    if (*d.rank_out >= 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int m = d.m, n = d.n;
+    const int64_t lda = d.lda;
+    const int kmax = min(d.kmax, min(m, n));
+    __shared__ double rsum[256];
+    __shared__ double rmax[256];
+    __shared__ int rarg[256];
+    __shared__ double red[4];
+    double sum = 0.0, best = -1.0;
+    int bj = n;
+    for (int j = s + tid; j < n; j += 256) {
+        const double v = d.colnorm2[j];
+        sum += v;
+        if (v > best) { best = v; bj = j; }
+    }
+    rsum[tid] = sum; rmax[tid] = best; rarg[tid] = bj;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) {
+            rsum[tid] += rsum[tid + o];
+            const double b2 = rmax[tid + o];
+            const int a2 = rarg[tid + o];
+            if (b2 > rmax[tid] || (b2 == rmax[tid] && a2 < rarg[tid])) { rmax[tid] = b2; rarg[tid] = a2; }
+        }
+        __syncthreads();
+    }
+    const double total = rsum[0];
+    const int p = rarg[0];
+    if (total <= *d.tol2_state || s >= kmax) {
+        if (tid == 0) {
+            *d.rank_out = s;
+            if (d.trail2_out) *d.trail2_out = total;
+        }
+        return;
+    }
+    if (p != s) {
+        for (int i = tid; i < m; i += 256) {
+            const c128 a = d.A[i + s * lda];
+            d.A[i + s * lda] = d.A[i + p * lda];
+            d.A[i + p * lda] = a;
+        }
+        if (tid == 0) {
+            const double t = d.colnorm2[s]; d.colnorm2[s] = d.colnorm2[p]; d.colnorm2[p] = t;
+            const int q = d.perm[s]; d.perm[s] = d.perm[p]; d.perm[p] = q;
+        }
+    }
+    __syncthreads();
+    // reflector P = I - tau w w^H with P x = beta e1 for x = A[s:m, s]; w[0] = wtop[s], the
+    // rest of w stays in A[s+1:m, s]
+    double xn2 = 0.0;
+    for (int i = s + tid; i < m; i += 256) xn2 += cabs2(d.A[i + s * lda]);
+    xn2 = block_sum<4>(xn2, red);
+    if (tid == 0) {
+        const c128 x0 = d.A[s + s * lda];
+        const double xn = sqrt(xn2);
+        const double ax0 = sqrt(cabs2(x0));
+        const c128 ph = ax0 > 0.0 ? make_double2(x0.x / ax0, x0.y / ax0) : make_double2(1.0, 0.0);
+        d.tau[s] = xn > 0.0 ? 1.0 / (xn * (xn + ax0)) : 0.0;
+        d.wtop[s] = make_double2(x0.x + ph.x * xn, x0.y + ph.y * xn);
+        d.A[s + s * lda] = make_double2(-ph.x * xn, -ph.y * xn);
+    }
+    (void)wv;
+    (void)lane;
+}
+
+template <int MAXR>
+__global__ void __launch_bounds__(256) k_qrcp_apply(const QrcpDesc* descs, int s) {
+    const QrcpDesc d = descs[blockIdx.y];
+    if (*d.rank_out >= 0) return;
+    const int n = d.n;
+    const int c0 = s + 1 + blockIdx.x * kQrcpChunk;
+    if (c0 >= n) return;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int m = d.m;
+    const int64_t lda = d.lda;
+    __shared__ c128 wl[64 * MAXR];
+    for (int i = tid; i < m - s; i += 256) wl[i] = i == 0 ? d.wtop[s] : d.A[s + i + s * lda];
+    __syncthreads();
+    const double tau = d.tau[s];
+    const int c1 = min(n, c0 + kQrcpChunk);
+    constexpr int CJ = MAXR <= 4 ? 4 : (MAXR <= 10 ? 2 : 1);
+    for (int j0 = c0 + wv; j0 < c1; j0 += 4 * CJ) {
+        c128 a[CJ][MAXR];
+        c128 dot[CJ];
+#pragma unroll
+        for (int c = 0; c < CJ; ++c) {
+            const int j = j0 + 4 * c;
+            dot[c] = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int q = 0; q < MAXR; ++q) {
+                const int i = lane + 64 * q;
+                a[c][q] = make_double2(0.0, 0.0);
+                if (j < c1 && s + i < m) {
+                    a[c][q] = d.A[s + i + (int64_t)j * lda];
+                    dot[c] = cadd(dot[c], cmulc(wl[i], a[c][q]));
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CJ; ++c) dot[c] = wave_sum(dot[c]);
+        double nrm[CJ];
+#pragma unroll
+        for (int c = 0; c < CJ; ++c) {
+            const int j = j0 + 4 * c;
+            const c128 f = make_double2(tau * dot[c].x, tau * dot[c].y);
+            nrm[c] = 0.0;
+#pragma unroll
+            for (int q = 0; q < MAXR; ++q) {
+                const int i = lane + 64 * q;
+                if (j < c1 && s + i < m) {
+                    a[c][q] = csub(a[c][q], cmul(wl[i], f));
+                    d.A[s + i + (int64_t)j * lda] = a[c][q];
+                    if (i >= 1) nrm[c] += cabs2(a[c][q]);
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CJ; ++c) nrm[c] = wave_sum(nrm[c]);
+        if (lane == 0) {
+#pragma unroll
+            for (int c = 0; c < CJ; ++c)
+                if (j0 + 4 * c < c1) d.colnorm2[j0 + 4 * c] = nrm[c];
+        }
+    }
+}
+
 // Q = P_0 ... P_{r-1} [I_r; 0]
 template <int MAXR>
 __global__ void __launch_bounds__(256) k_form_q(const FormQDesc* descs) {
@@ -615,20 +776,27 @@ void launch_gemm_residual(hipStream_t s, const GemmDesc* d, const int32_t* td, c
     hipLaunchKernelGGL(k_gemm<3>, dim3((unsigned)nt), dim3(256), 0, s, d, td, tmn, partial);
 }
 
-void launch_qrcp(hipStream_t s, const QrcpDesc* d, int n, int maxrows, bool wide) {
+void launch_qrcp(hipStream_t s, const QrcpDesc* d, int n, int maxrows) {
     if (n <= 0) return;
-    // wide: few, long matrices (the projected sketches of large blocks) get 512 threads each
-    if (wide) {
-        if (maxrows <= 192) hipLaunchKernelGGL((k_qrcp<3, 512>), dim3(n), dim3(512), 0, s, d);
-        else if (maxrows <= 256) hipLaunchKernelGGL((k_qrcp<4, 512>), dim3(n), dim3(512), 0, s, d);
-        else if (maxrows <= 640) hipLaunchKernelGGL((k_qrcp<10, 512>), dim3(n), dim3(512), 0, s, d);
-        else hipLaunchKernelGGL((k_qrcp<16, 512>), dim3(n), dim3(512), 0, s, d);
-        return;
-    }
     if (maxrows <= 192) hipLaunchKernelGGL((k_qrcp<3, 256>), dim3(n), dim3(256), 0, s, d);
     else if (maxrows <= 256) hipLaunchKernelGGL((k_qrcp<4, 256>), dim3(n), dim3(256), 0, s, d);
     else if (maxrows <= 640) hipLaunchKernelGGL((k_qrcp<10, 256>), dim3(n), dim3(256), 0, s, d);
     else hipLaunchKernelGGL((k_qrcp<16, 256>), dim3(n), dim3(256), 0, s, d);
+}
+
+void launch_qrcp_stepped(hipStream_t s, const QrcpDesc* d, int n, int maxrows, int maxcols, int maxsteps) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_qrcp_begin, dim3(n), dim3(256), 0, s, d);
+    const unsigned chunks = (unsigned)((maxcols + kQrcpChunk - 1) / kQrcpChunk);
+    for (int st = 0; st <= maxsteps; ++st) {
+        hipLaunchKernelGGL(k_qrcp_pivot, dim3(n), dim3(256), 0, s, d, st);
+        if (st == maxsteps) break;
+        const dim3 g(chunks, (unsigned)n);
+        if (maxrows <= 192) hipLaunchKernelGGL(k_qrcp_apply<3>, g, dim3(256), 0, s, d, st);
+        else if (maxrows <= 256) hipLaunchKernelGGL(k_qrcp_apply<4>, g, dim3(256), 0, s, d, st);
+        else if (maxrows <= 640) hipLaunchKernelGGL(k_qrcp_apply<10>, g, dim3(256), 0, s, d, st);
+        else hipLaunchKernelGGL(k_qrcp_apply<16>, g, dim3(256), 0, s, d, st);
+    }
 }
 
 void launch_form_q(hipStream_t s, const FormQDesc* d, int n, int maxrows) {

@@ -328,13 +328,14 @@ struct Builder {
             wsn[i] = tot_n; tot_n += an[i];
             wsk[i] = tot_k; tot_k += std::min(am[i], an[i]);
         }
-        double* dcn; int32_t* dperm; double* dtau; c128* dwtop;
+        double* dcn; int32_t* dperm; double* dtau; c128* dwtop; double* dtol2;
         CHECK(ar.alloc(&dcn, std::max<int64_t>(tot_n, 1), "qrcp norms"));
         CHECK(ar.alloc(&dperm, std::max<int64_t>(tot_n, 1), "qrcp perm"));
         CHECK(ar.alloc(&dtau, std::max<int64_t>(tot_k, 1), "qrcp tau"));
         CHECK(ar.alloc(&dwtop, std::max<int64_t>(tot_k, 1), "qrcp w"));
+        CHECK(ar.alloc(&dtol2, std::max<size_t>(nb, 1), "qrcp tolerances"));
         const double rel2 = (0.95 * eps) * (0.95 * eps);
-        int maxrows_dir = 0, maxrows_sk = 0;
+        int maxrows_dir = 0, maxrows_sk = 0, maxcols_sk = 0, maxsteps_sk = 0;
         std::vector<QrcpDesc> qdir, qsk;
         for (size_t i = 0; i < nb; ++i) {
             QrcpDesc q{};
@@ -353,15 +354,23 @@ struct Builder {
             q.rank_out = d_rank + i;
             q.trail2_out = d_trail + i;
             q.norm2_out = d_norm2 + i;
+            q.tol2_state = dtol2 + i;
             qd[i] = q;
-            if (kw[i] == 0) { qdir.push_back(q); maxrows_dir = std::max<int>(maxrows_dir, q.m); }
-            else { qsk.push_back(q); maxrows_sk = std::max<int>(maxrows_sk, q.m); }
+            if (kw[i] == 0) {
+                qdir.push_back(q);
+                maxrows_dir = std::max<int>(maxrows_dir, q.m);
+            } else {
+                qsk.push_back(q);
+                maxrows_sk = std::max<int>(maxrows_sk, q.m);
+                maxcols_sk = std::max<int>(maxcols_sk, q.n);
+                maxsteps_sk = std::max<int>(maxsteps_sk, std::min(q.kmax, std::min(q.m, q.n)));
+            }
         }
         QrcpDesc *dqdir, *dqsk;
         CHECK(ar.upload(&dqdir, qdir, "qrcp descs"));
         CHECK(ar.upload(&dqsk, qsk, "qrcp descs"));
         launch_qrcp(s, dqdir, (int)qdir.size(), maxrows_dir);
-        launch_qrcp(s, dqsk, (int)qsk.size(), maxrows_sk, true);
+        launch_qrcp_stepped(s, dqsk, (int)qsk.size(), maxrows_sk, maxcols_sk, maxsteps_sk);
         CHECK(hip_check(ctx, hipGetLastError(), "qrcp"));
         std::vector<int32_t> rank;
         std::vector<double> n2;

@@ -693,7 +693,25 @@ qrvie_status qrvie_solve_footprint_estimate(const qrvie_geom* g, const qrvie_op*
     const int64_t tlen = op ? op->t_len : (int64_t)g->blocks.size() * 64;
     const int64_t nlev = op ? std::max(op->n_active, 1) : std::max(g->L, 1);
     const int64_t prod = tlen * nr + nlev * n * nr + (na > 1 ? 2 * n * nr : 0);
-    *bytes = (size_t)((na * col + prod) * (int64_t)sizeof(c128)) + (size_t)(1 << 20);
+    int64_t elems = na * col + prod;
+    if (o->mode == QRVIE_SOLVE_BLOCK) {
+        // one block of up to block_width right-hand sides at a time (the BlockSolver buffers,
+        // the block product workspace, which is sized for 64 right-hand sides, and the split-K
+        // partials); a rank-deficient block is finished by the single-vector solver with the
+        // same total number of basis vectors, so the larger of the two is the peak
+        const int64_t width = o->block_width > 0 ? o->block_width : kMaxBlockRhs;
+        const int64_t pb = std::min<int64_t>(nrhs, width), P = 16 * ((pb + 15) / 16);
+        const int64_t ldh = (std::max<int64_t>(1, std::min<int64_t>(o->restart / pb, o->max_iter)) + 1) * pb;
+        const int64_t blk = n * (5 * pb + ldh + 4 * P) + ldh * (8 * pb + 2 * ldh) + 3 * pb * pb + kBlockPartialElems +
+                            tlen * kMaxBlockRhs + (nlev + 1) * n * kMaxBlockRhs;
+        qrvie_solve_opts o1 = *o;
+        o1.mode = QRVIE_SOLVE_FP64;
+        o1.restart = block_fallback_restart(o->restart, (int)pb);
+        size_t fb = 0;
+        CHECK(qrvie_solve_footprint_estimate(g, op, (int32_t)pb, &o1, &fb));
+        elems = std::max<int64_t>(blk, (int64_t)(fb / sizeof(c128)));
+    }
+    *bytes = (size_t)(elems * (int64_t)sizeof(c128)) + (size_t)(1 << 20);
     return QRVIE_OK;
 }
 
@@ -725,6 +743,7 @@ qrvie_status qrvie_solve(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const
                 qrvie_solve_opts o1 = *o;
                 o1.mode = QRVIE_SOLVE_FP64;
                 o1.use_x0 = 1;
+                o1.restart = block_fallback_restart(o->restart, cnt);   // the block path's basis budget
                 st = qrvie_solve(ctx, op, cnt, (const qrvie_c128*)((const c128*)v + (int64_t)r0 * ldv), ldv,
                                  (qrvie_c128*)((c128*)x + (int64_t)r0 * ldx), ldx, &o1, inf);
             }

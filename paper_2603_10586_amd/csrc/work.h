@@ -71,6 +71,15 @@ inline void block_product(const qrvie_op* op, hipStream_t s, const BlockWork& bw
 }
 
 
+// Split-K partial products of the block solver's basis projections (512 MB).
+constexpr int64_t kBlockPartialElems = (int64_t)32 << 20;
+
+// Basis vectors per column when a rank-deficient block of `cnt` right-hand sides is finished
+// by the single-vector solver (groups of up to 8 columns), keeping the block path's total.
+inline int32_t block_fallback_restart(int32_t restart, int cnt) {
+    return std::max<int32_t>(1, restart / std::max(1, std::min(cnt, 8)));
+}
+
 // Block GMRES over up to kMaxBlockRhs right-hand sides (block.cpp).  `broke` is set when the
 // block of right-hand sides (or of residuals at a restart) is numerically rank deficient; x
 // then holds the best iterate and the caller finishes those columns another way.
