@@ -575,12 +575,21 @@ __global__ void __launch_bounds__(NTH) k_cgs2(const Cgs2Desc* descs) {
             for (int t = wv; 16 * t < kept; t += NW) {
                 const int qa = min(16 * t + rl, kept - 1);
                 v4d re = v4d{0.0, 0.0, 0.0, 0.0}, im = re;
-                for (int i = 0; i < m; i += 4) {
-                    const int row = i + kq;
-                    const bool ok = row < m;
-                    c128 a = ok ? Y[row + qa * ld] : z;
-                    a.y = -a.y;
-                    cmfma(re, im, a, ok ? P[row + pj * ld] : z);
+                // batches of 4 four-row steps: the loads of a batch are issued together
+                for (int i = 0; i < m; i += 16) {
+                    c128 a[4], b[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int row = i + 4 * u + kq;
+                        const bool ok = row < m;
+                        a[u] = ok ? Y[row + qa * ld] : z;
+                        b[u] = ok ? P[row + pj * ld] : z;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        a[u].y = -a[u].y;
+                        cmfma(re, im, a[u], b[u]);
+                    }
                 }
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
@@ -594,10 +603,17 @@ __global__ void __launch_bounds__(NTH) k_cgs2(const Cgs2Desc* descs) {
                 const int r0 = 16 * r;
                 const int ra = min(r0 + rl, m - 1);
                 v4d re = v4d{0.0, 0.0, 0.0, 0.0}, im = re;
-                for (int q = 0; q < kept; q += 4) {
-                    const int qq = q + kq;
-                    const bool ok = qq < kept;
-                    cmfma(re, im, ok ? Y[ra + qq * ld] : z, ok ? Hs[qq * kPanel + rl] : z);
+                for (int q = 0; q < kept; q += 16) {
+                    c128 a[4], b[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int qq = q + 4 * u + kq;
+                        const bool ok = qq < kept;
+                        a[u] = ok ? Y[ra + qq * ld] : z;
+                        b[u] = ok ? Hs[qq * kPanel + rl] : z;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) cmfma(re, im, a[u], b[u]);
                 }
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
