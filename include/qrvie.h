@@ -293,14 +293,19 @@ qrvie_status qrvie_rhs_plane_waves(qrvie_ctx* ctx, const qrvie_geom* g, int32_t 
  *                       products, t_apply_s = product time of the whole block.  A
  *                       numerically rank-deficient block (repeated right-hand sides) is
  *                       finished column by column in FP64 mode from the block iterate.
+ * QRVIE_SOLVE_BLOCK_IR  iterative refinement as MIXED_IR, with each correction from block
+ *                       GMRES (as BLOCK) on the complex64 copy of the far factors, for all
+ *                       unconverged columns together; residuals use the complex128
+ *                       factors.  Needs far_prec = QRVIE_PREC_C64.  info: iterations =
+ *                       block steps over all corrections, n_refine = corrections.
  */
-enum { QRVIE_SOLVE_FP64 = 0, QRVIE_SOLVE_MIXED_IR = 1, QRVIE_SOLVE_BLOCK = 2 };
+enum { QRVIE_SOLVE_FP64 = 0, QRVIE_SOLVE_MIXED_IR = 1, QRVIE_SOLVE_BLOCK = 2, QRVIE_SOLVE_BLOCK_IR = 3 };
 
 typedef struct {
     int32_t restart;      /* GMRES(m) restart length, 1..16384 (m >= max_iter: unrestarted, as in §6);
                              the basis takes (m + 1) x n complex128 of device memory */
     int32_t max_iter;     /* total Arnoldi steps per right-hand side */
-    int32_t mode;         /* QRVIE_SOLVE_FP64, QRVIE_SOLVE_MIXED_IR or QRVIE_SOLVE_BLOCK */
+    int32_t mode;         /* QRVIE_SOLVE_FP64, _MIXED_IR, _BLOCK or _BLOCK_IR */
     double  tol;          /* relative residual; converged when both the preconditioned
                              estimate and the true residual ||v - Z_QR x||/||v|| meet it */
     int32_t use_x0;       /* 1: x holds the initial guess on entry; 0: x0 = 0 */

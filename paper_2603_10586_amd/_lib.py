@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(HERE, "libqrvie.so")
 MAX_LEVELS = 24
 OK, ERR_INVALID_ARG, ERR_GEOMETRY, ERR_OUT_OF_MEMORY, ERR_DEVICE, NOT_CONVERGED, ERR_QUEUE_FULL = range(7)
 PREC_C128, PREC_C64, PREC_BF16X2, PREC_C64_ONLY = 0, 1, 2, 3
-SOLVE_FP64, SOLVE_MIXED_IR, SOLVE_BLOCK = 0, 1, 2
+SOLVE_FP64, SOLVE_MIXED_IR, SOLVE_BLOCK, SOLVE_BLOCK_IR = 0, 1, 2, 3
 
 
 class C128(C.Structure):

@@ -99,9 +99,10 @@ struct BlockSolver {
     hipEvent_t ev0{}, ev1{};
     double t_apply = 0.0;
     int products = 0;
+    bool lo = false;             // products (and residuals) on the complex64 panels
 
-    BlockSolver(qrvie_ctx* c, const qrvie_op* p_, const qrvie_solve_opts* o_)
-        : ctx(c), op(p_), o(o_), s(c->stream), n(p_->g->ndof()), w(c) {}
+    BlockSolver(qrvie_ctx* c, const qrvie_op* p_, const qrvie_solve_opts* o_, bool lo_)
+        : ctx(c), op(p_), o(o_), s(c->stream), n(p_->g->ndof()), w(c), lo(lo_) {}
     ~BlockSolver() {
         if (hbuf) (void)hipHostFree(hbuf);
         if (hint) (void)hipHostFree(hint);
@@ -160,7 +161,7 @@ struct BlockSolver {
     void residual(const c128* Xcol, c128* out, c128* zcol) {
         launch_gather_block(s, ntB, op->g->N, nullptr, Xcol, n, p, Xi);
         (void)hipEventRecord(ev0, s);
-        block_product(op, s, bw, ntB, Xi, Bi, Ri, zcol ? Zi : nullptr);
+        block_product(op, s, bw, ntB, Xi, Bi, Ri, zcol ? Zi : nullptr, lo);
         (void)hipEventRecord(ev1, s);
         ++products;
         launch_scatter_block(s, ntB, op->g->N, nullptr, Ri, out, n, p);
@@ -438,7 +439,7 @@ qrvie_status tune_block(qrvie_ctx* ctx, qrvie_op* op, int prec, int nrhs, int re
 }
 
 qrvie_status solve_block(qrvie_ctx* ctx, const qrvie_op* op, int na, const c128* v, int64_t ldv, c128* x,
-                         int64_t ldx, const qrvie_solve_opts* o, qrvie_solve_info* info, bool* broke) {
+                         int64_t ldx, const qrvie_solve_opts* o, qrvie_solve_info* info, bool* broke, bool lo) {
     *broke = false;
     const double t0 = now_s();
     const qrvie_geom* g = op->g;
@@ -475,7 +476,7 @@ qrvie_status solve_block(qrvie_ctx* ctx, const qrvie_op* op, int na, const c128*
         return hip_check(ctx, hipStreamSynchronize(s), "solve");
     }
 
-    BlockSolver B(ctx, op, o);
+    BlockSolver B(ctx, op, o, lo);
     CHECK(B.init((int)cols.size()));
     const int p = B.p;
     for (int c = 0; c < p; ++c) {
@@ -528,7 +529,7 @@ qrvie_status solve_block(qrvie_ctx* ctx, const qrvie_op* op, int na, const c128*
             // W = Z_D^-1 Z_QR V_k
             launch_gather_block(s, B.ntK, g->N, nullptr, Vk, n, q, B.Xi);
             (void)hipEventRecord(B.ev0, s);
-            block_product(op, s, B.bw, B.ntK, B.Xi, nullptr, B.Ri, B.Zi);
+            block_product(op, s, B.bw, B.ntK, B.Xi, nullptr, B.Ri, B.Zi, B.lo);
             (void)hipEventRecord(B.ev1, s);
             ++B.products;
             launch_scatter_block(s, B.ntK, g->N, nullptr, B.Zi, W, n, q);

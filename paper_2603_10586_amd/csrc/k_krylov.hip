@@ -183,6 +183,12 @@ __global__ void k_scale_into(const c128* __restrict__ w, int64_t n, const double
 }
 
 // x += d (the update of an iterative-refinement step)
+// y = a - y
+__global__ void k_rsub(const c128* __restrict__ a, int64_t n, c128* __restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = make_double2(a[i].x - y[i].x, a[i].y - y[i].y);
+}
+
 __global__ void k_add(const c128* __restrict__ d, int64_t n, c128* __restrict__ x) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
@@ -316,6 +322,9 @@ void launch_reduce_norm(hipStream_t s, const double* partial, int count, double*
 }
 void launch_scale_into(hipStream_t s, const c128* w, int64_t n, const double* norm2, c128* out, c128* gslot) {
     hipLaunchKernelGGL(k_scale_into, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w, n, norm2, out, gslot);
+}
+void launch_rsub(hipStream_t s, const c128* a, int64_t n, c128* y) {
+    hipLaunchKernelGGL(k_rsub, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, n, y);
 }
 void launch_add(hipStream_t s, const c128* d, int64_t n, c128* x) {
     hipLaunchKernelGGL(k_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d, n, x);

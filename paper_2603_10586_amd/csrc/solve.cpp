@@ -454,6 +454,108 @@ qrvie_status solve_group_ir(qrvie_ctx* ctx, const qrvie_op* op, int na, const c1
     return G.finish(x, &xh, info, t0);
 }
 
+// Mixed-precision refinement with block corrections (QRVIE_SOLVE_BLOCK_IR): the residuals
+// of all columns with the complex128 factors, then one block GMRES solve on the complex64
+// panels for all unconverged columns together (inner tolerance as in solve_group_ir, the
+// tightest of the columns), x += d, until every column meets tol, stalls (a correction
+// that does not halve its residual), or the limits are reached.  Caller order throughout.
+qrvie_status solve_block_ir(qrvie_ctx* ctx, const qrvie_op* op, int nrhs, const c128* v, int64_t ldv, c128* x,
+                            int64_t ldx, const qrvie_solve_opts* o, qrvie_solve_info* info) {
+    const double t0 = now_s();
+    const int64_t n = op->g->ndof();
+    hipStream_t s = ctx->stream;
+    Work w(ctx);
+    c128 *R, *Ra, *D;
+    double* dn;
+    CHECK(w.alloc(&R, (size_t)n * nrhs, "refinement residuals"));
+    CHECK(w.alloc(&Ra, (size_t)n * nrhs, "refinement right-hand sides"));
+    CHECK(w.alloc(&D, (size_t)n * nrhs, "refinement corrections"));
+    CHECK(w.alloc(&dn, (size_t)nrhs, "refinement norms"));
+    std::vector<qrvie_solve_info> inf(nrhs);
+    for (auto& i : inf) i = qrvie_solve_info{};
+    auto norms = [&](const c128* a, int64_t lda, std::vector<double>& out) -> qrvie_status {
+        out.assign(nrhs, 0.0);
+        launch_col_norms(s, (int)n, a, lda, nrhs, dn);
+        CHECK(hip_check(ctx, hipMemcpyAsync(out.data(), dn, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s), "norms"));
+        return hip_check(ctx, hipStreamSynchronize(s), "norms");
+    };
+    if (!o->use_x0)
+        for (int c = 0; c < nrhs; ++c)
+            CHECK(hip_check(ctx, hipMemsetAsync(x + (int64_t)c * ldx, 0, sizeof(c128) * n, s), "x0"));
+    std::vector<double> vn, rn, rel(nrhs, 0.0);
+    CHECK(norms(v, ldv, vn));
+    std::vector<int> state(nrhs, 0);   // 0 refining, 1 converged, 2 stopped
+    for (int c = 0; c < nrhs; ++c) {
+        if (!std::isfinite(vn[c])) {
+            set_err(ctx, "solve: right-hand side has non-finite entries");
+            return QRVIE_ERR_INVALID_ARG;
+        }
+        if (vn[c] == 0.0) {
+            CHECK(hip_check(ctx, hipMemsetAsync(x + (int64_t)c * ldx, 0, sizeof(c128) * n, s), "zero x"));
+            state[c] = 1;
+        }
+    }
+    const int width = o->block_width > 0 ? o->block_width : kMaxBlockRhs;
+    for (int it = 0;; ++it) {
+        CHECK(qrvie_apply_prec(ctx, op, QRVIE_PREC_C128, nrhs, (const qrvie_c128*)x, ldx, (qrvie_c128*)R, n));
+        for (int c = 0; c < nrhs; ++c) launch_rsub(s, v + (int64_t)c * ldv, n, R + (int64_t)c * n);
+        CHECK(norms(R, n, rn));
+        std::vector<int> act;
+        double eta = 0.5;
+        for (int c = 0; c < nrhs; ++c) {
+            if (state[c] != 0) continue;
+            const double r = rn[c] / vn[c];
+            if (!std::isfinite(r)) { set_err(ctx, "solve: non-finite residual"); return QRVIE_ERR_DEVICE; }
+            const bool stalled = it > 0 && r > 0.5 * rel[c];
+            rel[c] = r;
+            inf[c].rel_res_true = r;
+            if (r <= o->tol) { state[c] = 1; continue; }
+            if (it >= kMaxRefine || inf[c].iterations >= o->max_iter || stalled) { state[c] = 2; continue; }
+            act.push_back(c);
+            eta = std::min(eta, o->inner_tol > 0.0 ? o->inner_tol : std::max(0.25 * o->tol / r, 1e-14));
+        }
+        if (act.empty()) break;
+        for (size_t j = 0; j < act.size(); ++j)
+            CHECK(hip_check(ctx, hipMemcpyAsync(Ra + (int64_t)j * n, R + (int64_t)act[j] * n, sizeof(c128) * n,
+                                                hipMemcpyDeviceToDevice, s), "refinement rhs"));
+        qrvie_solve_opts oi = *o;
+        oi.mode = QRVIE_SOLVE_BLOCK;
+        oi.tol = eta;
+        oi.use_x0 = 0;
+        for (size_t r0 = 0; r0 < act.size(); r0 += (size_t)width) {
+            const int cnt = (int)std::min(act.size() - r0, (size_t)width);
+            std::vector<qrvie_solve_info> ii(cnt);
+            bool broke = false;
+            const qrvie_status st = solve_block(ctx, op, cnt, Ra + (int64_t)r0 * n, n, D + (int64_t)r0 * n, n, &oi,
+                                                ii.data(), &broke, true);
+            if (st != QRVIE_OK && st != QRVIE_NOT_CONVERGED) return st;
+            for (int j = 0; j < cnt; ++j) {
+                qrvie_solve_info& f = inf[act[r0 + j]];
+                f.iterations += ii[j].iterations;
+                f.restarts += ii[j].restarts;
+                f.n_apply += ii[j].n_apply;
+                f.n_prec += ii[j].n_prec;
+                f.t_apply_s += ii[j].t_apply_s;
+                f.rel_res_prec = ii[j].rel_res_prec;
+                f.n_refine++;
+                if (broke) state[act[r0 + j]] = 2;   // rank-deficient correction block: keep what it gave
+            }
+        }
+        for (size_t j = 0; j < act.size(); ++j) launch_add(s, D + (int64_t)j * n, n, x + (int64_t)act[j] * ldx);
+    }
+    CHECK(hip_check(ctx, hipStreamSynchronize(s), "solve"));
+    const double t1 = now_s();
+    qrvie_status overall = QRVIE_OK;
+    for (int c = 0; c < nrhs; ++c) {
+        inf[c].converged = state[c] == 1;
+        if (state[c] == 1 && vn[c] == 0.0) inf[c].rel_res_true = 0.0;
+        inf[c].t_total_s = t1 - t0;
+        if (!inf[c].converged) overall = QRVIE_NOT_CONVERGED;
+    }
+    if (info) std::copy(inf.begin(), inf.end(), info);
+    return overall;
+}
+
 }  // namespace
 
 extern "C" {
@@ -694,7 +796,7 @@ qrvie_status qrvie_solve_footprint_estimate(const qrvie_geom* g, const qrvie_op*
     const int64_t nlev = op ? std::max(op->n_active, 1) : std::max(g->L, 1);
     const int64_t prod = tlen * nr + nlev * n * nr + (na > 1 ? 2 * n * nr : 0);
     int64_t elems = na * col + prod;
-    if (o->mode == QRVIE_SOLVE_BLOCK) {
+    if (o->mode == QRVIE_SOLVE_BLOCK || o->mode == QRVIE_SOLVE_BLOCK_IR) {
         // one block of up to block_width right-hand sides at a time (the BlockSolver buffers,
         // the block product workspace, which is sized for 64 right-hand sides, and the split-K
         // partials); a rank-deficient block is finished by the single-vector solver with the
@@ -710,6 +812,7 @@ qrvie_status qrvie_solve_footprint_estimate(const qrvie_geom* g, const qrvie_op*
         size_t fb = 0;
         CHECK(qrvie_solve_footprint_estimate(g, op, (int32_t)pb, &o1, &fb));
         elems = std::max<int64_t>(blk, (int64_t)(fb / sizeof(c128)));
+        if (o->mode == QRVIE_SOLVE_BLOCK_IR) elems += 3 * n * (int64_t)nrhs;   // residuals, their copy, corrections
     }
     *bytes = (size_t)(elems * (int64_t)sizeof(c128)) + (size_t)(1 << 20);
     return QRVIE_OK;
@@ -719,15 +822,17 @@ qrvie_status qrvie_solve(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const
                          qrvie_c128* x, int64_t ldx, const qrvie_solve_opts* o, qrvie_solve_info* info) {
     CHECK(check_vec_args(ctx, op, nrhs, v, ldv, x, ldx, "solve"));
     if (!o || o->restart < 1 || o->restart > 16384 || o->max_iter < 1 || !(o->tol > 0.0) ||
-        (o->mode != QRVIE_SOLVE_FP64 && o->mode != QRVIE_SOLVE_MIXED_IR && o->mode != QRVIE_SOLVE_BLOCK) ||
+        (o->mode != QRVIE_SOLVE_FP64 && o->mode != QRVIE_SOLVE_MIXED_IR && o->mode != QRVIE_SOLVE_BLOCK &&
+         o->mode != QRVIE_SOLVE_BLOCK_IR) ||
         !(o->inner_tol >= 0.0 && o->inner_tol < 1.0) || o->block_width < 0 || o->block_width > kMaxBlockRhs) {
         set_err(ctx, "solve: invalid options");
         return QRVIE_ERR_INVALID_ARG;
     }
-    if (o->mode == QRVIE_SOLVE_MIXED_IR && !(op->d_fac32 && op->d_fac)) {
-        set_err(ctx, "solve: QRVIE_SOLVE_MIXED_IR needs an operator built with far_prec = QRVIE_PREC_C64");
+    if ((o->mode == QRVIE_SOLVE_MIXED_IR || o->mode == QRVIE_SOLVE_BLOCK_IR) && !(op->d_fac32 && op->d_fac)) {
+        set_err(ctx, "solve: mixed-precision refinement needs an operator built with far_prec = QRVIE_PREC_C64");
         return QRVIE_ERR_INVALID_ARG;
     }
+    if (o->mode == QRVIE_SOLVE_BLOCK_IR) return solve_block_ir(ctx, op, nrhs, (const c128*)v, ldv, (c128*)x, ldx, o, info);
     qrvie_status overall = QRVIE_OK;
     if (o->mode == QRVIE_SOLVE_BLOCK) {
         const int width = o->block_width > 0 ? o->block_width : kMaxBlockRhs;

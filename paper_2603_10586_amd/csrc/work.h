@@ -83,8 +83,10 @@ inline int32_t block_fallback_restart(int32_t restart, int cnt) {
 // Block GMRES over up to kMaxBlockRhs right-hand sides (block.cpp).  `broke` is set when the
 // block of right-hand sides (or of residuals at a restart) is numerically rank deficient; x
 // then holds the best iterate and the caller finishes those columns another way.
+// lo: products and residuals on the complex64 panels (the corrections of BLOCK_IR).
 qrvie_status solve_block(qrvie_ctx* ctx, const qrvie_op* op, int na, const c128* v, int64_t ldv, c128* x,
-                         int64_t ldx, const qrvie_solve_opts* o, qrvie_solve_info* info, bool* broke);
+                         int64_t ldx, const qrvie_solve_opts* o, qrvie_solve_info* info, bool* broke,
+                         bool lo = false);
 
 qrvie_status profile_block(qrvie_ctx* ctx, const qrvie_op* op, int nrhs, int reps, double* ms, int64_t* flops);
 qrvie_status tune_block(qrvie_ctx* ctx, qrvie_op* op, int prec, int nrhs, int reps, qrvie_block_tune* out);

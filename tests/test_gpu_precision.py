@@ -156,3 +156,52 @@ def test_c64_only_refuses_complex128_requests():
     with pytest.raises(q.QrvieError) as e:
         c.op.apply(v, prec=0)
     assert e.value.status == 1
+
+
+BLOCK_IR = 3
+
+
+@pytest.mark.parametrize("name,nrhs", [("rand5x3", 1), ("rand6x7", 10), ("rand6x7", 70)])
+def test_block_ir_reaches_the_c128_solution(name, nrhs):
+    """Refinement with block corrections on the complex64 panels: every column's true
+    residual of Z_QR (complex128 factors, recomputed by the oracle) meets tol."""
+    import paper_2603_10586_amd as q
+    c = case(name, far_prec=PREC_C64)
+    rng = np.random.default_rng(nrhs)
+    th = rng.uniform(-40, 40, nrhs)
+    v = q.rhs_plane_waves(c.ctx, c.geom, th, rng.uniform(0, 360, nrhs), [r % 2 for r in range(nrhs)])
+    x, info, st = c.op.solve(v, restart=4000, tol=1e-10, max_iter=2000, mode=BLOCK_IR)
+    assert st == 0
+    sb = greens.self_blocks(c.disc)
+    ZQR = compressed.dense_from_factors(sb, [(f[0], f[1], f[2], f[3]) for f in c.factors()])
+    vh, xh = to_host(v), to_host(x)
+    ref = np.linalg.solve(ZQR, vh.T).T
+    for r in range(nrhs):
+        assert info[r]["converged"] and info[r]["rel_res_true"] <= 1e-10
+        assert info[r]["n_refine"] >= 1
+        res = np.linalg.norm(vh[r] - ZQR @ xh[r]) / np.linalg.norm(vh[r])
+        assert res <= 2e-10
+        assert np.linalg.norm(xh[r] - ref[r]) <= 1e-7 * np.linalg.norm(ref[r])
+
+
+def test_block_ir_matches_block_fp64_at_the_working_tolerance():
+    import paper_2603_10586_amd as q
+    c = case("rand8x8", far_prec=PREC_C64)
+    th = np.linspace(-30, 30, 8)
+    v = q.rhs_plane_waves(c.ctx, c.geom, th, np.zeros(8), [r % 2 for r in range(8)])
+    x, info, st = c.op.solve(v, restart=4000, tol=1e-6, max_iter=2000, mode=BLOCK_IR)
+    x64, info64, st64 = c.op.solve(v, restart=4000, tol=1e-6, max_iter=2000, mode=q.SOLVE_BLOCK)
+    assert st == 0 and st64 == 0
+    xh, x64h = to_host(x), to_host(x64)
+    for r in range(8):
+        assert info[r]["rel_res_true"] <= 1e-6 and 1 <= info[r]["n_refine"] <= 3
+        assert np.linalg.norm(xh[r] - x64h[r]) <= 1e-4 * np.linalg.norm(x64h[r])
+
+
+def test_block_ir_needs_the_c64_copy():
+    import paper_2603_10586_amd as q
+    c = case("rand5x3")
+    v = q.rhs_plane_waves(c.ctx, c.geom, [0.0], [0.0], [1])
+    with pytest.raises(q.QrvieError) as e:
+        c.op.solve(v, mode=BLOCK_IR)
+    assert e.value.status == 1
