@@ -358,8 +358,9 @@ qrvie_status qrvie_solve(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs,
  * qrvie_op_footprint_estimate and qrvie_solve_footprint_estimate, computed before
  * anything else is allocated) fits `hbm_budget` next to the admitted requests and the
  * cached operators; requests are taken in arrival order, but one that does not fit yet
- * does not block later ones that do.  Each worker has its own context and default-
- * priority stream, so admitted requests run concurrently on the device.  Operators are
+ * does not block later ones that do, until `max_bypass` of them have started ahead of
+ * it.  Each worker has its own context and default-priority stream, so admitted
+ * requests run concurrently on the device.  Operators are
  * compressed once per geometry (same centres, radii, heights, permittivities, lattice
  * sites and wavelength) and kept resident, at most `op_cache` of them, evicted least
  * recently used when their bytes are needed.  A request's result does not depend on what
@@ -378,6 +379,8 @@ typedef struct {
     int32_t  op_cache;       /* operators kept resident after their request, >= 0 */
     uint64_t seed;           /* compression sketch seed */
     int32_t  tune_tiles;     /* 1: autotune the block product tiles of each new operator (block mode) */
+    int32_t  max_bypass;     /* a queued request is overtaken by at most this many later
+                                admissions, then nothing behind it starts before it (0: no limit) */
 } qrvie_server_opts;
 
 typedef struct {

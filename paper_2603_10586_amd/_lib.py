@@ -63,7 +63,7 @@ class SolveInfo(C.Structure):
 class ServerOptsC(C.Structure):
     _fields_ = [("slots", C.c_int32), ("hbm_budget", C.c_size_t), ("eps", C.c_double), ("restart", C.c_int32),
                 ("max_iter", C.c_int32), ("mode", C.c_int32), ("block_width", C.c_int32), ("op_cache", C.c_int32),
-                ("seed", C.c_uint64), ("tune_tiles", C.c_int32)]
+                ("seed", C.c_uint64), ("tune_tiles", C.c_int32), ("max_bypass", C.c_int32)]
 
 
 TUNE_VARIANTS = 8

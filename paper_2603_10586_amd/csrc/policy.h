@@ -3,7 +3,9 @@
 // before anything is allocated) and the key of their geometry.  A request is admitted
 // when a slot is free and its footprint fits the HBM budget next to the admitted requests
 // and the cached operators; requests are considered in arrival order, but one that does not
-// fit yet does not hold back later ones that do (no head-of-line blocking).  Cached
+// fit yet does not hold back later ones that do (no head-of-line blocking), until it has
+// been overtaken by `max_bypass` later admissions (0: no limit): from then on nothing
+// behind it is admitted before it, so a large request cannot starve.  Cached
 // operators that no admitted request uses are evicted least recently used when a request
 // needs their bytes.  A request whose operator is cached needs only its solver bytes and
 // pins the cache entry until it finishes.  A request that cannot fit even in an empty
@@ -22,13 +24,14 @@ namespace sched {
 
 class Policy {
 public:
-    Policy(int slots, size_t budget, int op_cache) : slots_(slots), budget_(budget), op_cache_(op_cache) {}
+    Policy(int slots, size_t budget, int op_cache, int max_bypass = 0)
+        : slots_(slots), budget_(budget), op_cache_(op_cache), max_bypass_(max_bypass) {}
 
     // Queue a request; false (refused) when it cannot fit an otherwise empty budget (its
     // operator may be evicted before it starts, so the whole footprint must fit).
     bool enqueue(uint64_t ticket, const std::string& key, size_t footprint, size_t op_bytes) {
         if (footprint > budget_ || op_bytes > footprint) return false;
-        jobs_[ticket] = Job{key, footprint, op_bytes, 0, false};
+        jobs_[ticket] = Job{key, footprint, op_bytes, 0, false, 0};
         queue_.push_back(ticket);
         return true;
     }
@@ -36,13 +39,22 @@ public:
     // Admit every queued request that fits now, in arrival order; evicted cache keys are
     // appended to `evicted` (their operators are to be destroyed by the caller).
     void admit(std::vector<uint64_t>* admitted, std::vector<std::string>* evicted) {
+        std::vector<Job*> waiting;          // passed over in this round, still queued
         for (auto it = queue_.begin(); it != queue_.end() && running_ < slots_;) {
             Job& j = jobs_.at(*it);
             const bool hit = cached(j.key);
             const size_t need = hit ? j.footprint - j.op_bytes : j.footprint;
             while (in_use_ + need > budget_ && evict_one(evicted)) {
             }
-            if (in_use_ + need > budget_) { ++it; continue; }
+            if (in_use_ + need > budget_) {
+                waiting.push_back(&j);
+                ++it;
+                continue;
+            }
+            bool starved = false;           // an earlier request may not be overtaken again
+            for (Job* w : waiting) starved = starved || (max_bypass_ > 0 && w->bypassed >= max_bypass_);
+            if (starved) break;
+            for (Job* w : waiting) ++w->bypassed;
             in_use_ += need;
             peak_ = in_use_ > peak_ ? in_use_ : peak_;
             j.need = need;
@@ -101,6 +113,7 @@ private:
         std::string key;
         size_t footprint, op_bytes, need;
         bool pinned;
+        int bypassed;                       // later requests admitted while this one waited
     };
     struct Entry {
         size_t bytes;
@@ -125,6 +138,7 @@ private:
     int slots_;
     size_t budget_;
     int op_cache_;
+    int max_bypass_;
     int running_ = 0;
     size_t in_use_ = 0, peak_ = 0;
     int64_t hits_ = 0, evictions_ = 0;

@@ -110,7 +110,7 @@ struct qrvie_server {
     std::string err;
 
     qrvie_server(const qrvie_server_opts& op, int dev)
-        : o(op), device(dev), pol(op.slots, op.hbm_budget, op.op_cache) {}
+        : o(op), device(dev), pol(op.slots, op.hbm_budget, op.op_cache, op.max_bypass) {}
 };
 
 namespace {
@@ -311,7 +311,7 @@ qrvie_status qrvie_server_create(int hip_device, const qrvie_server_opts* o, qrv
     if (!o || !out || o->slots < 1 || o->slots > 16 || o->hbm_budget == 0 || !(o->eps > 0.0 && o->eps < 1.0) ||
         o->restart < 1 || o->max_iter < 1 || o->op_cache < 0 ||
         (o->mode != QRVIE_SOLVE_FP64 && o->mode != QRVIE_SOLVE_BLOCK) || o->block_width < 0 ||
-        o->block_width > kMaxBlockRhs || (o->tune_tiles != 0 && o->tune_tiles != 1))
+        o->block_width > kMaxBlockRhs || (o->tune_tiles != 0 && o->tune_tiles != 1) || o->max_bypass < 0)
         return QRVIE_ERR_INVALID_ARG;
     *out = nullptr;
     std::unique_ptr<qrvie_server> s(new qrvie_server(*o, hip_device));

@@ -31,6 +31,7 @@ class ServerOpts:
     op_cache: int = 4                 # operators kept resident after their request
     seed: int = 0
     tune_tiles: bool = True           # autotune each new operator's block product tiles
+    max_bypass: int = 6               # later admissions that may overtake a waiting request
 
 
 @dataclass
@@ -54,7 +55,8 @@ class Server:
         self.opts = opts
         o = L.ServerOptsC(slots=opts.slots, hbm_budget=opts.hbm_budget, eps=opts.eps, restart=opts.restart,
                           max_iter=opts.max_iter, mode=opts.mode, block_width=opts.block_width,
-                          op_cache=opts.op_cache, seed=opts.seed, tune_tiles=1 if opts.tune_tiles else 0)
+                          op_cache=opts.op_cache, seed=opts.seed, tune_tiles=1 if opts.tune_tiles else 0,
+                          max_bypass=opts.max_bypass)
         h = C.c_void_p()
         st = self.lib.qrvie_server_create(device, C.byref(o), C.byref(h))
         if st != L.OK:

@@ -106,9 +106,45 @@ static int cache_capacity_is_bounded() {
     return 0;
 }
 
+static int bypass_limit_prevents_starvation() {
+    Policy p(4, 100, 0, 2);
+    std::vector<uint64_t> adm;
+    std::vector<std::string> ev;
+    EXPECT(p.enqueue(1, "a", 60, 40));
+    p.admit(&adm, &ev);                                          // 1 runs (60)
+    EXPECT(p.enqueue(2, "big", 80, 40));                         // waits for 1
+    EXPECT(p.enqueue(3, "s1", 10, 5));
+    EXPECT(p.enqueue(4, "s2", 10, 5));
+    EXPECT(p.enqueue(5, "s3", 10, 5));
+    adm.clear();
+    p.admit(&adm, &ev);
+    EXPECT(adm.size() == 2 && adm[0] == 3 && adm[1] == 4);       // two overtakes, then 2 blocks
+    EXPECT(p.queued() == 2);
+    adm.clear();
+    p.finish(3, true, &ev);
+    p.admit(&adm, &ev);
+    EXPECT(adm.empty());                                         // 5 would fit but must wait behind 2
+    p.finish(4, true, &ev);
+    p.finish(1, true, &ev);
+    p.admit(&adm, &ev);
+    EXPECT(adm.size() == 2 && adm[0] == 2 && adm[1] == 5);       // 2 first, then 5 next to it
+    // without a limit the small request is admitted ahead of the big one
+    Policy q(4, 100, 0);
+    std::vector<uint64_t> a2;
+    EXPECT(q.enqueue(1, "a", 60, 40));
+    q.admit(&a2, &ev);
+    EXPECT(q.enqueue(2, "big", 80, 40));
+    for (uint64_t t = 3; t < 6; ++t) EXPECT(q.enqueue(t, "s", 10, 5));
+    a2.clear();
+    q.admit(&a2, &ev);
+    EXPECT(a2.size() == 3);
+    return 0;
+}
+
 int main() {
     int (*tests[])() = {fifo_and_slots, no_head_of_line_blocking, refuses_what_can_never_fit,
-                        cache_hits_pin_and_lru_eviction, cache_capacity_is_bounded};
+                        cache_hits_pin_and_lru_eviction, cache_capacity_is_bounded,
+                        bypass_limit_prevents_starvation};
     for (auto t : tests)
         if (t()) return 1;
     std::printf("ok\n");

@@ -28,7 +28,7 @@ def test_server_rejects_invalid_options():
     lib = L.load()
     h = C.c_void_p()
     for bad in (dict(slots=0), dict(slots=17), dict(hbm_budget=0), dict(eps=0.0), dict(mode=1),
-                dict(block_width=65), dict(op_cache=-1), dict(restart=0), dict(tune_tiles=2)):
+                dict(block_width=65), dict(op_cache=-1), dict(restart=0), dict(tune_tiles=2), dict(max_bypass=-1)):
         o = dict(slots=2, hbm_budget=1 << 30, eps=1e-6, restart=100, max_iter=100, mode=L.SOLVE_BLOCK,
                  block_width=0, op_cache=1, seed=0)
         o.update(bad)
