@@ -266,7 +266,7 @@ def main() -> int:
                     help="iterative refinement: complex64 far factors inside, complex128 residuals outside")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
+        print(f"bench.py runs on one GPU only: multi-GPU execution is not implemented (asked for --gpus {args.gpus})",
               file=sys.stderr)
         return 2
 
