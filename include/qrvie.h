@@ -292,7 +292,8 @@ qrvie_status qrvie_rhs_plane_waves(qrvie_ctx* ctx, const qrvie_geom* g, int32_t 
  *                       block steps.  info: iterations = block steps, n_apply = block
  *                       products, t_apply_s = product time of the whole block.  A
  *                       numerically rank-deficient block (repeated right-hand sides) is
- *                       finished column by column in FP64 mode from the block iterate.
+ *                       finished column by column in FP64 mode from the block iterate; a
+ *                       block of one column is solved in FP64 mode (the same Krylov space).
  * QRVIE_SOLVE_BLOCK_IR  iterative refinement as MIXED_IR, with each correction from block
  *                       GMRES (as BLOCK) on the complex64 copy of the far factors, for all
  *                       unconverged columns together; residuals use the complex128

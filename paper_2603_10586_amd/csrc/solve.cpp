@@ -840,6 +840,17 @@ qrvie_status qrvie_solve(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const
             const int cnt = std::min(width, nrhs - r0);
             bool broke = false;
             qrvie_solve_info* inf = info ? info + r0 : nullptr;
+            if (cnt == 1) {
+                // a block of one column spans the same Krylov space as GMRES, whose HBM-bound
+                // single-vector kernels are faster (1729 steps at mid: 6.7 s against 12.5 s)
+                qrvie_solve_opts o1 = *o;
+                o1.mode = QRVIE_SOLVE_FP64;
+                const qrvie_status st = qrvie_solve(ctx, op, 1, (const qrvie_c128*)((const c128*)v + (int64_t)r0 * ldv),
+                                                    ldv, (qrvie_c128*)((c128*)x + (int64_t)r0 * ldx), ldx, &o1, inf);
+                if (st == QRVIE_NOT_CONVERGED) overall = st;
+                else if (st != QRVIE_OK) return st;
+                continue;
+            }
             qrvie_status st = solve_block(ctx, op, cnt, (const c128*)v + (int64_t)r0 * ldv, ldv,
                                           (c128*)x + (int64_t)r0 * ldx, ldx, o, inf, &broke);
             if (broke) {

@@ -156,3 +156,17 @@ def test_tile_autotuner_rejects_bad_arguments():
     for kw in (dict(nrhs=0), dict(nrhs=65), dict(reps=0), dict(reps=101), dict(prec=q.PREC_C64)):
         with pytest.raises(q.QrvieError):
             c.op.tune_block(**{**dict(nrhs=16, reps=1, prec=q.PREC_C128), **kw})
+
+
+def test_one_column_blocks_use_the_single_vector_solver():
+    """A block of one column spans the GMRES Krylov space; it is solved by the single-vector
+    solver, so the result is bitwise the FP64 mode's (alone, and as the 65th column)."""
+    c = case("rand6x7")
+    v = _rhs(c, 65, seed=21)
+    x1, i1, s1 = c.op.solve(v[64:].contiguous(), restart=3000, tol=1e-9, max_iter=2000, mode=BLOCK)
+    xf, iff, sf = c.op.solve(v[64:].contiguous(), restart=3000, tol=1e-9, max_iter=2000, mode=0)
+    assert s1 == 0 and sf == 0
+    assert np.array_equal(to_host(x1), to_host(xf)) and i1[0]["iterations"] == iff[0]["iterations"]
+    x, info, st = c.op.solve(v, restart=3000, tol=1e-9, max_iter=2000, mode=BLOCK)
+    assert st == 0 and all(i["converged"] for i in info)
+    assert np.array_equal(to_host(x)[64], to_host(x1)[0])
