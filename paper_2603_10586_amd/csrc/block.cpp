@@ -244,7 +244,7 @@ struct BlockSolver {
             CHECK(right_solve(Vn, q2, R1, p));
             for (int it = 0; q > 0 && it < 2; ++it) {     // against the kept directions, twice
                 CHECK(gemm_hn(Vb, n, q, Vn, n, q2, Cb, q));
-                launch_gemm_nn_acc(s, n, q, q2, Vb, n, Cb, q, -1.0, Vn, n);
+                launch_gemm_nn_acc(s, n, q, q2, Vb, n, Cb, q, 1.0, -1.0, Vn, n);
             }
             CHECK(cholqr2(Vn, q2, Hb, q2));
             CHECK(read(nullptr, 0, 2));
@@ -253,7 +253,7 @@ struct BlockSolver {
             // S0 = V_0^H Zc and the remainder E = Zc - V_0 S0
             CHECK(gemm_hn(Vb, n, q, Zc, n, p, gl, ldh));
             CHECK(hip_check(ctx, hipMemcpyAsync(E, Zc, sizeof(c128) * n * p, hipMemcpyDeviceToDevice, s), "remainder"));
-            launch_gemm_nn_acc(s, n, q, p, Vb, n, gl, ldh, -1.0, E, n);
+            launch_gemm_nn_acc(s, n, q, p, Vb, n, gl, ldh, 1.0, -1.0, E, n);
             launch_col_norms(s, (int)n, E, n, p, dnrm);
             CHECK(read(dnrm, p, 0));
             bool small = true;
@@ -279,7 +279,7 @@ struct BlockSolver {
         CHECK(blas_check(ctx, rocblas_ztrsm(hb, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
                                             rocblas_diagonal_non_unit, (int)m, p, &zone, Z(Rl), (int)ldh, Z(Yb),
                                             (int)ldh), "ztrsm"));
-        launch_gemm_nn_acc(s, n, (int)m, p, Vb, n, Yb, ldh, 1.0, Xout, n);
+        launch_gemm_nn_acc(s, n, (int)m, p, Vb, n, Yb, ldh, 1.0, 1.0, Xout, n);
         return hip_check(ctx, hipGetLastError(), "solution update");
     }
 };
@@ -496,7 +496,6 @@ qrvie_status solve_block(qrvie_ctx* ctx, const qrvie_op* op, int na, const c128*
         pvnorm[c] = B.hbuf[c];
     }
 
-    const zc zone = {1.0, 0.0}, zmone = {-1.0, 0.0}, ztwo = {2.0, 0.0}, zzero = {0.0, 0.0};
     int steps_total = 0, cycles = 0;
     for (;;) {
         // cycle start: true residual of X and the first block from Z_D^-1 (B - Z_QR X)
@@ -539,10 +538,8 @@ qrvie_status solve_block(qrvie_ctx* ctx, const qrvie_op* op, int na, const c128*
             const c128* H1 = B.Cb + (int64_t)q * B.ldh;
             CHECK(hip_check(ctx, hipMemcpy2DAsync(B.Hb, sizeof(c128) * B.ldh, H1, sizeof(c128) * B.ldh,
                                                   sizeof(c128) * m, q, hipMemcpyDeviceToDevice, s), "h1"));
-            CHECK(blas_check(ctx, rocblas_zgemm(B.hb, rocblas_operation_none, rocblas_operation_none, (int)m, q, (int)m,
-                                                &zmone, Z(B.G), (int)B.ldh, Z(H1), (int)B.ldh, &ztwo, Z(B.Hb),
-                                                (int)B.ldh), "zgemm gram"));
-            launch_gemm_nn_acc(s, n, (int)m, q, B.Vb, n, B.Hb, B.ldh, -1.0, W, n);
+            launch_gemm_nn_acc(s, m, (int)m, q, B.G, B.ldh, H1, B.ldh, 2.0, -1.0, B.Hb, B.ldh);
+            launch_gemm_nn_acc(s, n, (int)m, q, B.Vb, n, B.Hb, B.ldh, 1.0, -1.0, W, n);
             // block Hessenberg column k: [H; H_{k+1,k}] with W = V_{k+1} H_{k+1,k}
             c128* col = B.Rl + (int64_t)k * q * B.ldh;
             CHECK(hip_check(ctx, hipMemcpy2DAsync(col, sizeof(c128) * B.ldh, B.Hb, sizeof(c128) * B.ldh,

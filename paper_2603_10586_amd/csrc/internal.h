@@ -303,8 +303,8 @@ void launch_ls_apply(hipStream_t s, int j0, int j1, int p, const c128* Y, const 
 void launch_ls_factor(hipStream_t s, int k, int p, c128* C, int64_t ldc, c128* Yk, c128* Tk);
 void launch_col_norms(hipStream_t s, int rows, const c128* C, int64_t ldc, int ncols, double* out);
 void launch_sum_batches(hipStream_t s, int m, int c, int nb, const c128* P, c128* C, int64_t ldc);
-// W (n x q, q <= 64) += sign V H (V: n x m, H: m x q).  FP64 MFMA, fixed accumulation order.
+// W (n x q, q <= 64) = beta W + sign V H (V: n x m, H: m x q).  FP64 MFMA, fixed accumulation order.
 void launch_gemm_nn_acc(hipStream_t s, int64_t n, int m, int q, const c128* V, int64_t ldv, const c128* H,
-                        int64_t ldh, double sign, c128* W, int64_t ldw);
+                        int64_t ldh, double beta, double sign, c128* W, int64_t ldw);
 
 }  // namespace qrvie

@@ -115,15 +115,17 @@ __global__ void __launch_bounds__(256) k_count_neq(int64_t n, const unsigned lon
 }
 
 // ----------------------------------------------------------------- basis updates on FP64 MFMA
-// W (n x q) += sign * V H for V: n x m, H: m x q (q <= 64): the basis update of block CGS2
-// and the solution update (a long, thin product that rocBLAS runs at about half the FP64
-// matrix rate).  Each wave owns 16 rows of W and all q columns (NT tiles of 16); the m
+// W (n x q) = beta W + sign * V H for V: n x m, H: m x q (q <= 64): the basis update of
+// block CGS2, the solution update (long, thin products that rocBLAS runs at about half the
+// FP64 matrix rate) and the Gram correction 2 H1 - G H1 (square, small: rocBLAS picked a
+// tile shape that ran it at a few TF/s).  Each wave owns 16 rows of W and all q columns (NT tiles of 16); the m
 // columns of V are visited in ascending batches of U 4-column steps (fixed order).  V is
 // streamed once; H stays in cache.
 template <int NT>
 __global__ void __launch_bounds__(256) k_gemm_nn_acc(int64_t n, int m, int q, const c128* __restrict__ V,
                                                      int64_t ldv, const c128* __restrict__ H, int64_t ldh,
-                                                     double sign, c128* __restrict__ W, int64_t ldw) {
+                                                     double beta, double sign, c128* __restrict__ W,
+                                                     int64_t ldw) {
     constexpr int U = 4;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t r0 = 64 * (int64_t)blockIdx.x + 16 * w;
@@ -169,7 +171,7 @@ __global__ void __launch_bounds__(256) k_gemm_nn_acc(int64_t n, int m, int q, co
             if (j < q) {
                 c128* o = W + row + (int64_t)j * ldw;
                 const c128 v = *o;
-                *o = make_double2(v.x + sign * re[t][s], v.y + sign * im[t][s]);
+                *o = make_double2(beta * v.x + sign * re[t][s], beta * v.y + sign * im[t][s]);
             }
         }
     }
@@ -655,14 +657,14 @@ void launch_sum_batches(hipStream_t s, int m, int c, int nb, const c128* P, c128
     hipLaunchKernelGGL(k_sum_batches, dim3((unsigned)((per + 255) / 256)), dim3(256), 0, s, m, c, nb, P, C, ldc);
 }
 void launch_gemm_nn_acc(hipStream_t s, int64_t n, int m, int q, const c128* V, int64_t ldv, const c128* H,
-                        int64_t ldh, double sign, c128* W, int64_t ldw) {
+                        int64_t ldh, double beta, double sign, c128* W, int64_t ldw) {
     if (n <= 0 || m <= 0 || q <= 0) return;
     const dim3 g((unsigned)((n + 63) / 64));
     switch ((q + 15) / 16) {
-        case 1: hipLaunchKernelGGL(k_gemm_nn_acc<1>, g, dim3(256), 0, s, n, m, q, V, ldv, H, ldh, sign, W, ldw); break;
-        case 2: hipLaunchKernelGGL(k_gemm_nn_acc<2>, g, dim3(256), 0, s, n, m, q, V, ldv, H, ldh, sign, W, ldw); break;
-        case 3: hipLaunchKernelGGL(k_gemm_nn_acc<3>, g, dim3(256), 0, s, n, m, q, V, ldv, H, ldh, sign, W, ldw); break;
-        default: hipLaunchKernelGGL(k_gemm_nn_acc<4>, g, dim3(256), 0, s, n, m, q, V, ldv, H, ldh, sign, W, ldw); break;
+        case 1: hipLaunchKernelGGL(k_gemm_nn_acc<1>, g, dim3(256), 0, s, n, m, q, V, ldv, H, ldh, beta, sign, W, ldw); break;
+        case 2: hipLaunchKernelGGL(k_gemm_nn_acc<2>, g, dim3(256), 0, s, n, m, q, V, ldv, H, ldh, beta, sign, W, ldw); break;
+        case 3: hipLaunchKernelGGL(k_gemm_nn_acc<3>, g, dim3(256), 0, s, n, m, q, V, ldv, H, ldh, beta, sign, W, ldw); break;
+        default: hipLaunchKernelGGL(k_gemm_nn_acc<4>, g, dim3(256), 0, s, n, m, q, V, ldv, H, ldh, beta, sign, W, ldw); break;
     }
 }
 void launch_col_norms(hipStream_t s, int rows, const c128* C, int64_t ldc, int ncols, double* out) {
