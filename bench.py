@@ -239,6 +239,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--product-only", action="store_true",
                     help="build the operator and time products only (for hardware-counter runs)")
+    ap.add_argument("--read-probe-mib", type=int, default=0,
+                    help="time the library's streaming-read probe over this many MiB and exit")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device copy of this many MiB five times (counter calibration)")
     ap.add_argument("--serving", type=int, default=0,
@@ -290,6 +292,13 @@ def main() -> int:
         return 0
 
     import paper_2603_10586_amd as q
+
+    if args.read_probe_mib:
+        buf = torch.ones(args.read_probe_mib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        gbs = q.Context(0).probe_read(buf, reps=10)
+        print(json.dumps({"read_probe_bytes": buf.numel() * 8, "best_read_gbs": round(gbs, 1),
+                          "of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}))
+        return 0
     import workloads as W
 
     if args.serving:

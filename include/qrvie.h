@@ -264,6 +264,13 @@ typedef struct {
 } qrvie_block_tune;
 qrvie_status qrvie_op_tune_block(qrvie_ctx* ctx, qrvie_op* op, int32_t prec, int32_t nrhs, int32_t reps,
                                  qrvie_block_tune* out);
+/*
+ * Streaming-read reference for the product's roofline: reads `bytes` (a multiple of 16) of
+ * device memory at `d` with the product kernels' nontemporal 16-byte loads over a few grid
+ * sizes and load depths, `reps` (1..100) times each, and returns the best read rate in GB/s
+ * (host double).  A measurement helper, not a step of the method.
+ */
+qrvie_status qrvie_probe_read(qrvie_ctx* ctx, const void* d, size_t bytes, int32_t reps, double* gbs);
 /* z = Z_D^-1 y, the block-diagonal left preconditioner (§4, eq. 4.2). */
 qrvie_status qrvie_precondition(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs,
                                 const qrvie_c128* y, int64_t ldy, qrvie_c128* z, int64_t ldz);

@@ -42,6 +42,15 @@ class Context:
         if cur.cuda_stream != self.stream.cuda_stream:
             self.stream.wait_stream(cur)
 
+    def probe_read(self, buf, reps: int = 5) -> float:
+        """Best streaming-read rate (GB/s) of the library's read probe over a device tensor."""
+        nbytes = buf.numel() * buf.element_size() // 16 * 16
+        out = C.c_double()
+        self.order()
+        self.check(self.lib.qrvie_probe_read(self.h, C.c_void_p(buf.data_ptr()), nbytes, reps, C.byref(out)),
+                   "probe read")
+        return out.value
+
     def check(self, st: int, what: str = "") -> int:
         if st not in (L.OK, L.NOT_CONVERGED):
             msg = self.lib.qrvie_last_error(self.h).decode()

@@ -183,6 +183,24 @@ __global__ void k_scale_into(const c128* __restrict__ w, int64_t n, const double
 }
 
 // x += d (the update of an iterative-refinement step)
+// Streaming read of n 16-byte entries with the product kernels' nontemporal loads, U loads
+// in flight per lane, grid-stride; the sum is kept only so that the loads are not removed.
+template <int U>
+__global__ void __launch_bounds__(256) k_read_probe(const c128* __restrict__ p, int64_t n, double* out) {
+    double acc = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    for (; i + (U - 1) * stride < n; i += U * stride) {
+        c128 a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) a[u] = load_stream(p + i + u * stride);
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc += a[u].x + a[u].y;
+    }
+    for (; i < n; i += stride) acc += p[i].x + p[i].y;
+    if (acc == -1.0) out[0] = acc;       // practically never: keeps the reads live
+}
+
 // y = a - y
 __global__ void k_rsub(const c128* __restrict__ a, int64_t n, c128* __restrict__ y) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -322,6 +340,10 @@ void launch_reduce_norm(hipStream_t s, const double* partial, int count, double*
 }
 void launch_scale_into(hipStream_t s, const c128* w, int64_t n, const double* norm2, c128* out, c128* gslot) {
     hipLaunchKernelGGL(k_scale_into, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w, n, norm2, out, gslot);
+}
+void launch_read_probe(hipStream_t s, const c128* p, int64_t n, int grid, int u, double* out) {
+    if (u >= 16) hipLaunchKernelGGL(k_read_probe<16>, dim3(grid), dim3(256), 0, s, p, n, out);
+    else hipLaunchKernelGGL(k_read_probe<8>, dim3(grid), dim3(256), 0, s, p, n, out);
 }
 void launch_rsub(hipStream_t s, const c128* a, int64_t n, c128* y) {
     hipLaunchKernelGGL(k_rsub, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, n, y);

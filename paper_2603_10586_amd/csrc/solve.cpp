@@ -703,6 +703,40 @@ qrvie_status qrvie_op_profile_block(qrvie_ctx* ctx, const qrvie_op* op, int32_t 
     return profile_block(ctx, op, nrhs, reps, ms, flops);
 }
 
+qrvie_status qrvie_probe_read(qrvie_ctx* ctx, const void* d, size_t bytes, int32_t reps, double* gbs) {
+    if (!ctx || !d || !gbs || bytes < 16 || bytes % 16 != 0 || reps < 1 || reps > 100) return QRVIE_ERR_INVALID_ARG;
+    hipStream_t s = ctx->stream;
+    Work w(ctx);
+    double* out;
+    CHECK(w.alloc(&out, 1, "probe"));
+    hipEvent_t e0, e1;
+    CHECK(hip_check(ctx, hipEventCreate(&e0), "probe events"));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_check(ctx, hipErrorOutOfMemory, "probe events");
+    }
+    const int64_t n = (int64_t)(bytes / 16);
+    double best = 0.0;
+    qrvie_status st = QRVIE_OK;
+    for (int grid : {2048, 8192, 16384})
+        for (int u : {8, 16}) {
+            if (st != QRVIE_OK) break;
+            launch_read_probe(s, (const c128*)d, n, grid, u, out);
+            (void)hipEventRecord(e0, s);
+            for (int r = 0; r < reps; ++r) launch_read_probe(s, (const c128*)d, n, grid, u, out);
+            (void)hipEventRecord(e1, s);
+            st = hip_check(ctx, hipEventSynchronize(e1), "probe");
+            float ms = 0.f;
+            if (st == QRVIE_OK) st = hip_check(ctx, hipEventElapsedTime(&ms, e0, e1), "probe timer");
+            if (st == QRVIE_OK && ms > 0.f) best = std::max(best, (double)bytes * reps / (ms * 1e-3) / 1e9);
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    CHECK(st);
+    *gbs = best;
+    return hip_check(ctx, hipGetLastError(), "probe");
+}
+
 qrvie_status qrvie_op_tune_block(qrvie_ctx* ctx, qrvie_op* op, int32_t prec, int32_t nrhs, int32_t reps,
                                  qrvie_block_tune* out) {
     if (!ctx || !op || !out || reps < 1 || reps > 100 || nrhs < 1 || nrhs > kMaxBlockRhs) return QRVIE_ERR_INVALID_ARG;

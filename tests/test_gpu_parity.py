@@ -296,3 +296,14 @@ def test_factors_do_not_depend_on_the_compression_chunking():
         assert np.array_equal(Q1, Q0) and np.array_equal(R1, R0)
     with pytest.raises(q.QrvieError):
         q.Operator(c.ctx, c.geom, eps=c.eps, chunk_bytes=-1)
+
+
+def test_read_probe_reports_a_rate_below_the_hbm_peak():
+    import torch
+    import paper_2603_10586_amd as q
+    c = case("tiny")
+    buf = torch.ones(1 << 25, dtype=torch.float64, device="cuda")        # 256 MiB
+    gbs = c.ctx.probe_read(buf, reps=2)
+    assert 100.0 < gbs < 8000.0
+    with pytest.raises(q.QrvieError):
+        c.ctx.check(c.ctx.lib.qrvie_probe_read(c.ctx.h, None, 16, 1, None), "probe")
