@@ -236,8 +236,9 @@ void worker(qrvie_server* s, int slot) {
             built = st == QRVIE_OK;
             if (!built) msg = qrvie_last_error(ctx);
             // the new operator is private to this worker until it is cached: tune its tiles
-            // for this request's width (other widths keep the default shape)
-            if (built && s->o.mode == QRVIE_SOLVE_BLOCK && s->o.tune_tiles) {
+            // for this request's width (other widths keep the default shape; one wave is
+            // solved by the single-vector solver, which has no tiles)
+            if (built && s->o.mode == QRVIE_SOLVE_BLOCK && s->o.tune_tiles && r->nrhs > 1) {
                 const int w = std::min(r->nrhs, s->o.block_width > 0 ? s->o.block_width : kMaxBlockRhs);
                 qrvie_block_tune t;   // an optimisation only: on failure the default shapes stay
                 (void)qrvie_op_tune_block(ctx, op, op->d_fac ? QRVIE_PREC_C128 : QRVIE_PREC_C64, w, 2, &t);
