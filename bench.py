@@ -240,7 +240,8 @@ def main() -> int:
     ap.add_argument("--product-only", action="store_true",
                     help="build the operator and time products only (for hardware-counter runs)")
     ap.add_argument("--read-probe-mib", type=int, default=0,
-                    help="time the library's streaming-read probe over this many MiB and exit")
+                    help="time the library's streaming-read probe over this many MiB and its FP64/FP32 "
+                         "matrix-core probes, then exit")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device copy of this many MiB five times (counter calibration)")
     ap.add_argument("--serving", type=int, default=0,
@@ -296,8 +297,11 @@ def main() -> int:
     if args.read_probe_mib:
         buf = torch.ones(args.read_probe_mib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
         gbs = q.Context(0).probe_read(buf, reps=10)
+        ctx = q.Context(0)
+        f64, f32 = ctx.probe_mfma(True), ctx.probe_mfma(False)
         print(json.dumps({"read_probe_bytes": buf.numel() * 8, "best_read_gbs": round(gbs, 1),
-                          "of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}))
+                          "of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+                          "mfma_f64_16x16x4_tfs": round(f64, 1), "mfma_f32_16x16x4_tfs": round(f32, 1)}))
         return 0
     import workloads as W
 

@@ -271,6 +271,11 @@ qrvie_status qrvie_op_tune_block(qrvie_ctx* ctx, qrvie_op* op, int32_t prec, int
  * (host double).  A measurement helper, not a step of the method.
  */
 qrvie_status qrvie_probe_read(qrvie_ctx* ctx, const void* d, size_t bytes, int32_t reps, double* gbs);
+/*
+ * Matrix-core rate reference: back-to-back 16x16x4 MFMAs (f64 = 1: FP64, 0: FP32) on
+ * register data over the whole device; *tfs (host) receives TFLOP/s.  A measurement helper.
+ */
+qrvie_status qrvie_probe_mfma(qrvie_ctx* ctx, int32_t f64, double* tfs);
 /* z = Z_D^-1 y, the block-diagonal left preconditioner (§4, eq. 4.2). */
 qrvie_status qrvie_precondition(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs,
                                 const qrvie_c128* y, int64_t ldy, qrvie_c128* z, int64_t ldz);

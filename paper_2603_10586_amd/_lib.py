@@ -116,6 +116,7 @@ SIGNATURES = {
     "qrvie_op_profile_block": (ST, [P, P, I32, I32, C.POINTER(C.c_double), C.POINTER(I64)]),
     "qrvie_op_tune_block": (ST, [P, P, I32, I32, I32, C.POINTER(BlockTune)]),
     "qrvie_probe_read": (ST, [P, P, C.c_size_t, I32, C.POINTER(C.c_double)]),
+    "qrvie_probe_mfma": (ST, [P, I32, C.POINTER(C.c_double)]),
     "qrvie_precondition": (ST, [P, P, I32, P, I64, P, I64]),
     "qrvie_rhs_plane_waves": (ST, [P, P, I32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(I32), P, I64]),
     "qrvie_solve": (ST, [P, P, I32, P, I64, P, I64, C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),

@@ -51,6 +51,13 @@ class Context:
                    "probe read")
         return out.value
 
+    def probe_mfma(self, f64: bool = True) -> float:
+        """Measured 16x16x4 matrix-core rate (TFLOP/s), FP64 or FP32."""
+        out = C.c_double()
+        self.order()
+        self.check(self.lib.qrvie_probe_mfma(self.h, 1 if f64 else 0, C.byref(out)), "probe mfma")
+        return out.value
+
     def check(self, st: int, what: str = "") -> int:
         if st not in (L.OK, L.NOT_CONVERGED):
             msg = self.lib.qrvie_last_error(self.h).decode()

@@ -271,6 +271,7 @@ void launch_gemv_add(hipStream_t s, const c128* V, int64_t ldv, int ncols, const
 void launch_add(hipStream_t s, const c128* d, int64_t n, c128* x);
 void launch_rsub(hipStream_t s, const c128* a, int64_t n, c128* y);   // y = a - y
 void launch_read_probe(hipStream_t s, const c128* p, int64_t n, int grid, int u, double* out);
+void launch_mfma_probe(hipStream_t s, bool f64, int grid, int iters, double* out);
 
 // blocks of right-hand sides (k_block.hip); nt = P / 16 tiles of 16 right-hand sides, 1..4
 constexpr int kMaxBlockRhs = 64;

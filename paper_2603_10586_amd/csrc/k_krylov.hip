@@ -201,6 +201,38 @@ __global__ void __launch_bounds__(256) k_read_probe(const c128* __restrict__ p, 
     if (acc == -1.0) out[0] = acc;       // practically never: keeps the reads live
 }
 
+// Matrix-core rate reference: every wave runs `iters` rounds of four independent 16x16x4
+// MFMA chains (FP64 when F64, else FP32) on register data; 2048 flops per instruction.
+typedef double p4d __attribute__((ext_vector_type(4)));
+typedef float p4f __attribute__((ext_vector_type(4)));
+template <bool F64>
+__global__ void __launch_bounds__(256) k_mfma_probe(int iters, double* out) {
+    const int lane = threadIdx.x & 63;
+    if (F64) {
+        p4d c0 = {0, 0, 0, 0}, c1 = c0, c2 = c0, c3 = c0;
+        const double a = 1.0 + 1e-9 * lane, b = 1.0 - 1e-9 * lane;
+        for (int i = 0; i < iters; ++i) {
+            c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(b, a, c1, 0, 0, 0);
+            c2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, a, c2, 0, 0, 0);
+            c3 = __builtin_amdgcn_mfma_f64_16x16x4f64(b, b, c3, 0, 0, 0);
+        }
+        const double t = c0[0] + c1[1] + c2[2] + c3[3];
+        if (t == -1.0) out[0] = t;
+    } else {
+        p4f c0 = {0, 0, 0, 0}, c1 = c0, c2 = c0, c3 = c0;
+        const float a = 1.0f + 1e-6f * lane, b = 1.0f - 1e-6f * lane;
+        for (int i = 0; i < iters; ++i) {
+            c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(b, a, c1, 0, 0, 0);
+            c2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, a, c2, 0, 0, 0);
+            c3 = __builtin_amdgcn_mfma_f32_16x16x4f32(b, b, c3, 0, 0, 0);
+        }
+        const float t = c0[0] + c1[1] + c2[2] + c3[3];
+        if (t == -1.0f) out[0] = t;
+    }
+}
+
 // y = a - y
 __global__ void k_rsub(const c128* __restrict__ a, int64_t n, c128* __restrict__ y) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -340,6 +372,10 @@ void launch_reduce_norm(hipStream_t s, const double* partial, int count, double*
 }
 void launch_scale_into(hipStream_t s, const c128* w, int64_t n, const double* norm2, c128* out, c128* gslot) {
     hipLaunchKernelGGL(k_scale_into, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w, n, norm2, out, gslot);
+}
+void launch_mfma_probe(hipStream_t s, bool f64, int grid, int iters, double* out) {
+    if (f64) hipLaunchKernelGGL(k_mfma_probe<true>, dim3(grid), dim3(256), 0, s, iters, out);
+    else hipLaunchKernelGGL(k_mfma_probe<false>, dim3(grid), dim3(256), 0, s, iters, out);
 }
 void launch_read_probe(hipStream_t s, const c128* p, int64_t n, int grid, int u, double* out) {
     if (u >= 16) hipLaunchKernelGGL(k_read_probe<16>, dim3(grid), dim3(256), 0, s, p, n, out);

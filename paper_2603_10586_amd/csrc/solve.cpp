@@ -737,6 +737,34 @@ qrvie_status qrvie_probe_read(qrvie_ctx* ctx, const void* d, size_t bytes, int32
     return hip_check(ctx, hipGetLastError(), "probe");
 }
 
+qrvie_status qrvie_probe_mfma(qrvie_ctx* ctx, int32_t f64, double* tfs) {
+    if (!ctx || !tfs || (f64 != 0 && f64 != 1)) return QRVIE_ERR_INVALID_ARG;
+    hipStream_t s = ctx->stream;
+    Work w(ctx);
+    double* out;
+    CHECK(w.alloc(&out, 1, "probe"));
+    hipEvent_t e0, e1;
+    CHECK(hip_check(ctx, hipEventCreate(&e0), "probe events"));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_check(ctx, hipErrorOutOfMemory, "probe events");
+    }
+    constexpr int kGrid = 256 * 16, kIters = 4096;
+    launch_mfma_probe(s, f64 != 0, kGrid, 64, out);
+    (void)hipEventRecord(e0, s);
+    launch_mfma_probe(s, f64 != 0, kGrid, kIters, out);
+    (void)hipEventRecord(e1, s);
+    qrvie_status st = hip_check(ctx, hipEventSynchronize(e1), "probe");
+    float ms = 0.f;
+    if (st == QRVIE_OK) st = hip_check(ctx, hipEventElapsedTime(&ms, e0, e1), "probe timer");
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    CHECK(st);
+    const double flops = (double)kGrid * 4 /* waves */ * kIters * 4 /* chains */ * 2048.0;
+    *tfs = ms > 0.f ? flops / (ms * 1e-3) / 1e12 : 0.0;
+    return hip_check(ctx, hipGetLastError(), "probe");
+}
+
 qrvie_status qrvie_op_tune_block(qrvie_ctx* ctx, qrvie_op* op, int32_t prec, int32_t nrhs, int32_t reps,
                                  qrvie_block_tune* out) {
     if (!ctx || !op || !out || reps < 1 || reps > 100 || nrhs < 1 || nrhs > kMaxBlockRhs) return QRVIE_ERR_INVALID_ARG;

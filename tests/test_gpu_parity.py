@@ -307,3 +307,9 @@ def test_read_probe_reports_a_rate_below_the_hbm_peak():
     assert 100.0 < gbs < 8000.0
     with pytest.raises(q.QrvieError):
         c.ctx.check(c.ctx.lib.qrvie_probe_read(c.ctx.h, None, 16, 1, None), "probe")
+
+
+def test_matrix_core_probe_reports_plausible_rates():
+    c = case("tiny")
+    f64, f32 = c.ctx.probe_mfma(True), c.ctx.probe_mfma(False)
+    assert 5.0 < f64 < 200.0 and 5.0 < f32 < 400.0
