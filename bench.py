@@ -103,7 +103,32 @@ def cpu_baseline(op, geom, seconds: float = 15.0, seed: int = 0) -> dict:
     gbs = fbytes * reps / t / 1e9
     return {"value": round(gbs, 3), "unit": "GB/s", "cores": len(os.sched_getaffinity(0)), "kind": "oracle",
             "sample": f"oracle compressed product over {len(factors)} exported blocks stratified by level "
-                      f"({fbytes / 1e9:.2f} GB of factors), {reps} passes in {t:.1f} s; CPU {cpu_model()}"}
+                      f"({fbytes / 1e9:.2f} GB of factors), {reps} passes in {t:.1f} s; CPU {cpu_model()}",
+            "tiny_dense_context_s": oracle_tiny_timings()}
+
+
+def oracle_tiny_timings() -> dict:
+    """The oracle's dense path on the 4 x 4 array (2304 unknowns) on the host cores: dense
+    assembly, one dense product and preconditioned GMRES(30) on the dense matrix to 1e-8
+    (seconds each), as context for the compressed GPU path.  The oracle's loop LU (about
+    30 s here) is left out to keep the run short."""
+    import workloads as W
+    from oracle import discretise, greens, solvers
+    disc = discretise.Discretisation(W.tiny())
+    out = {}
+    t = time.perf_counter()
+    Z = greens.assemble_dense(disc)
+    out["dense_assembly"] = time.perf_counter() - t
+    v = greens.plane_wave_rhs(disc, [0.0], [0.0], [1])[:, 0]
+    t = time.perf_counter()
+    Z @ v
+    out["dense_product"] = time.perf_counter() - t
+    pre = solvers.BlockDiagPreconditioner(greens.self_blocks(disc))
+    t = time.perf_counter()
+    _, info = solvers.gmres(lambda x: Z @ x, v, apply_M=pre.apply, restart=30, tol=1e-8)
+    out["gmres30_dense"] = time.perf_counter() - t
+    out["gmres_iterations"] = info.iterations
+    return {k: (round(x, 3) if isinstance(x, float) else x) for k, x in out.items()}
 
 
 def serving(args) -> int:
