@@ -146,6 +146,7 @@ def serving(args) -> int:
     res = replay(srv, reqs, report=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
     wall = time.perf_counter() - t0
     st = srv.stats()
+    last_error = srv.last_error() if any(r.status not in (0, 5) for r in res) else ""
     srv.close()
     ok = all(r.status == 0 for r in res)
     worst = max(i["rel_res_true"] for r in res for i in r.info)
@@ -160,6 +161,7 @@ def serving(args) -> int:
         "requests_per_s": round(st["requests_per_s"], 4), "queue_wait_ms_p50": round(st["queue_wait_p50_s"] * 1e3, 1),
         "peak_admitted_bytes": st["peak_bytes"], "operators_built": st["ops_built"], "cache_hits": st["cache_hits"],
         "all_converged": ok, "worst_true_residual": worst, "rhs_solved": st["rhs_solved"], "wall_s": round(wall, 1),
+        "last_error": last_error,
         "requests": {"fields": ["particles", "waves", "status", "latency_s", "queue_s", "block_steps"],
                      "rows": [[q.array.n_particles, len(q.incidence.theta_deg), r.status, round(r.latency, 2),
                                round(r.admitted - r.arrival, 2), max(i["iterations"] for i in r.info)]

@@ -103,6 +103,10 @@ class Server:
         info = [{f: getattr(i, f) for f, _ in L.SolveInfo._fields_} for i in infos]
         return Result(ticket, st, x, info, a.value, b.value, c.value)
 
+    def last_error(self) -> str:
+        """The server's most recent error message (a failed request or call)."""
+        return self.lib.qrvie_server_last_error(self.h).decode()
+
     def stats(self) -> dict:
         s = L.ServerStatsC()
         self._check(self.lib.qrvie_server_get_stats(self.h, C.byref(s)), "stats")
@@ -135,7 +139,8 @@ def replay(server: Server, requests, time_scale: float = 1.0, timeout: float | N
                 if report:
                     r = results[t]
                     report(f"finished ticket {t}: status {r.status}, latency {r.latency:.2f} s, "
-                           f"{len(results)}/{len(requests)} done")
+                           f"{len(results)}/{len(requests)} done"
+                           + (f" ({server.last_error()})" if r.status not in (0, 5) else ""))
 
     for req in requests:
         due = t0 + req.arrival_s * time_scale
