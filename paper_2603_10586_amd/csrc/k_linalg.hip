@@ -1,8 +1,8 @@
 // Dense complex FP64 kernels behind the low-rank compression of far blocks (§5.2,
 // eq. 5.3) and the preconditioner setup (§4, eq. 4.2).
 //
-//  * k_gemm     batched 64x64-tiled complex GEMM on FP64 MFMA (op(A) = A or A^H; B
-//               stored or a generated random sketch), plus a residual mode that returns
+//  * k_gemm     batched 64x64-tiled complex GEMM (op(A) = A or A^H; B stored or a
+//               generated random sketch), plus a residual mode that returns
 //               per-tile partials of ||C - A B||_F^2 for certification.
 //  * k_qrcp     truncated column-pivoted Householder QR, one workgroup per matrix,
 //               stopping at the first rank whose exact trailing Frobenius norm meets
@@ -78,18 +78,6 @@ __device__ __forceinline__ c128 rand_c(uint64_t seed, int64_t i, int64_t j) {
     return make_double2((double)(h >> 11) * s * 2.0 - 1.0, (double)(h2 >> 11) * s * 2.0 - 1.0);
 }
 
-typedef double v4d __attribute__((ext_vector_type(4)));
-
-// Operand layout of the 16x16x4 FP64 MFMA: A (16 x 4): lane l holds A[l % 16][l / 16];
-// B (4 x 16): lane l holds B[l / 16][l % 16]; D (16 x 16): lane l, slot i holds
-// D[l / 16 + 4 i][l % 16].  A complex product is four real MFMAs.
-__device__ __forceinline__ void cmfma(v4d& re, v4d& im, c128 a, c128 b) {
-    re = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, re, 0, 0, 0);
-    re = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, re, 0, 0, 0);
-    im = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, im, 0, 0, 0);
-    im = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, im, 0, 0, 0);
-}
-
 // --------------------------------------------------------------------- GEMM
 // mode 0: C = A B        mode 1: C = A^H B      mode 2: C = A Omega(seed)
 // mode 3: partial[tile] = ||C - A B||^2 over the tile (C is read, not written)
@@ -102,17 +90,14 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc* descs, const int32
     const int tm = tmn[blockIdx.x] >> 16, tn = tmn[blockIdx.x] & 0xFFFF;
     const int m0 = tm * TM, n0 = tn * TN;
     const int tid = threadIdx.x;
-    // each wave owns a 32 x 32 quadrant of the tile as 2 x 2 FP64 MFMA tiles of 16 x 16
-    const int lane = tid & 63, wv = tid >> 6;
-    const int rl = lane & 15, kq = lane >> 4;
-    const int qr = 32 * (wv & 1), qc = 32 * (wv >> 1);
+    const int tx = tid & 15, ty = tid >> 4;
     __shared__ c128 As[TK][TM + 1];
     __shared__ c128 Bs[TK][TN + 1];
-    v4d re[2][2], im[2][2];
+    c128 acc[4][4];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) re[a][b] = im[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int b = 0; b < 4; ++b) acc[a][b] = make_double2(0.0, 0.0);
 
     for (int k0 = 0; k0 < d.k; k0 += TK) {
         // A tile: op(A)(i, kk), i in [m0, m0+64), kk in [k0, k0+16)
@@ -142,47 +127,44 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc* descs, const int32
             Bs[kk][j] = v;
         }
         __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < TK; ++kk) {
+            c128 av[4], bv[4];
 #pragma unroll
-        for (int k4 = 0; k4 < TK; k4 += 4) {
-            c128 av[2], bv[2];
+            for (int a = 0; a < 4; ++a) av[a] = As[kk][ty + 16 * a];
 #pragma unroll
-            for (int a = 0; a < 2; ++a) av[a] = As[k4 + kq][qr + 16 * a + rl];
+            for (int b = 0; b < 4; ++b) bv[b] = Bs[kk][tx + 16 * b];
 #pragma unroll
-            for (int b = 0; b < 2; ++b) bv[b] = Bs[k4 + kq][qc + 16 * b + rl];
+            for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < 2; ++b) cmfma(re[a][b], im[a][b], av[a], bv[b]);
+                for (int b = 0; b < 4; ++b) {
+                    acc[a][b].x = fma(av[a].x, bv[b].x, fma(-av[a].y, bv[b].y, acc[a][b].x));
+                    acc[a][b].y = fma(av[a].x, bv[b].y, fma(av[a].y, bv[b].x, acc[a][b].y));
+                }
         }
         __syncthreads();
     }
-    // lane l, slot i of a 16 x 16 MFMA tile holds row l / 16 + 4 i, column l % 16
     if (MODE == 3) {
         double s = 0.0;
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int gi = m0 + qr + 16 * a + kq + 4 * i, gj = n0 + qc + 16 * b + rl;
-                    if (gi < d.m && gj < d.n)
-                        s += cabs2(csub(d.C[(int64_t)gi + (int64_t)gj * d.ldc], make_double2(re[a][b][i], im[a][b][i])));
-                }
+            for (int b = 0; b < 4; ++b) {
+                const int gi = m0 + ty + 16 * a, gj = n0 + tx + 16 * b;
+                if (gi < d.m && gj < d.n) s += cabs2(csub(d.C[(int64_t)gi + (int64_t)gj * d.ldc], acc[a][b]));
+            }
         __shared__ double red[4];
         s = block_sum256(s, red);
         if (tid == 0) partial[blockIdx.x] = s;
         return;
     }
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int gi = m0 + qr + 16 * a + kq + 4 * i, gj = n0 + qc + 16 * b + rl;
-                if (gi < d.m && gj < d.n) d.C[(int64_t)gi + (int64_t)gj * d.ldc] = make_double2(re[a][b][i], im[a][b][i]);
-            }
+        for (int b = 0; b < 4; ++b) {
+            const int gi = m0 + ty + 16 * a, gj = n0 + tx + 16 * b;
+            if (gi < d.m && gj < d.n) d.C[(int64_t)gi + (int64_t)gj * d.ldc] = acc[a][b];
+        }
 }
 
 // --------------------------------------------------------------------- QRCP
@@ -547,6 +529,18 @@ __global__ void __launch_bounds__(256) k_extract_r(const ExtractRDesc* descs) {
 // orthogonalised one by one against the panel's earlier kept columns, twice (one sweep over
 // the rows per pass for all dot products), and a column is kept when its remaining norm
 // exceeds drop_rel times its norm before any projection.  Every reduction has a fixed order.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// Operand layout of the 16x16x4 FP64 MFMA: A (16 x 4): lane l holds A[l % 16][l / 16];
+// B (4 x 16): lane l holds B[l / 16][l % 16]; D (16 x 16): lane l, slot i holds
+// D[l / 16 + 4 i][l % 16].  A complex product is four real MFMAs.
+__device__ __forceinline__ void cmfma(v4d& re, v4d& im, c128 a, c128 b) {
+    re = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, re, 0, 0, 0);
+    re = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, re, 0, 0, 0);
+    im = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, im, 0, 0, 0);
+    im = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, im, 0, 0, 0);
+}
+
 constexpr int kPanel = 16;
 
 template <int KMAX, int NTH>

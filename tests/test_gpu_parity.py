@@ -313,3 +313,19 @@ def test_matrix_core_probe_reports_plausible_rates():
     c = case("tiny")
     f64, f32 = c.ctx.probe_mfma(True), c.ctx.probe_mfma(False)
     assert 5.0 < f64 < 200.0 and 5.0 < f32 < 400.0
+
+
+def test_edge_blocks_of_an_odd_lattice_compress():
+    """A 33 x 33 lattice has one-particle nodes at its edge, so it has tall far blocks of one
+    particle's columns (2304 x 144) whose sketch is retried at full width; every block must
+    still be certified (a GEMM variant that failed here is not used)."""
+    import paper_2603_10586_amd as q
+    import workloads as W
+    arr = W.serving_requests(n=8, seed=0, rate_per_s=1.0, side_lo=8, side_hi=48)[7].array
+    assert arr.n_particles == 1089
+    c = case("tiny")
+    geom = q.Geometry(c.ctx, arr)
+    op = q.Operator(c.ctx, geom, eps=1e-6, max_block_rows=9216)
+    assert op.num_blocks() == 42714
+    worst = max(op.export_block(b, factors=False)[0]["rel_err"] for b in range(op.num_blocks()))
+    assert worst <= 1e-6
