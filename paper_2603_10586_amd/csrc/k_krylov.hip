@@ -201,7 +201,7 @@ __global__ void __launch_bounds__(256) k_read_probe(const c128* __restrict__ p, 
     if (acc == -1.0) out[0] = acc;       // practically never: keeps the reads live
 }
 
-// Matrix-core rate reference: every wave runs `iters` rounds of four independent 16x16x4
+// Matrix-core rate reference: every wave runs `iters` rounds of eight independent 16x16x4
 // MFMA chains (FP64 when F64, else FP32) on register data; 2048 flops per instruction.
 typedef double p4d __attribute__((ext_vector_type(4)));
 typedef float p4f __attribute__((ext_vector_type(4)));
@@ -209,26 +209,30 @@ template <bool F64>
 __global__ void __launch_bounds__(256) k_mfma_probe(int iters, double* out) {
     const int lane = threadIdx.x & 63;
     if (F64) {
-        p4d c0 = {0, 0, 0, 0}, c1 = c0, c2 = c0, c3 = c0;
+        p4d c[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) c[j] = p4d{0, 0, 0, 0};
         const double a = 1.0 + 1e-9 * lane, b = 1.0 - 1e-9 * lane;
         for (int i = 0; i < iters; ++i) {
-            c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c0, 0, 0, 0);
-            c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(b, a, c1, 0, 0, 0);
-            c2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, a, c2, 0, 0, 0);
-            c3 = __builtin_amdgcn_mfma_f64_16x16x4f64(b, b, c3, 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) c[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(j & 1 ? a : b, j & 2 ? a : b, c[j], 0, 0, 0);
         }
-        const double t = c0[0] + c1[1] + c2[2] + c3[3];
+        double t = 0.0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) t += c[j][j & 3];
         if (t == -1.0) out[0] = t;
     } else {
-        p4f c0 = {0, 0, 0, 0}, c1 = c0, c2 = c0, c3 = c0;
+        p4f c[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) c[j] = p4f{0, 0, 0, 0};
         const float a = 1.0f + 1e-6f * lane, b = 1.0f - 1e-6f * lane;
         for (int i = 0; i < iters; ++i) {
-            c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c0, 0, 0, 0);
-            c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(b, a, c1, 0, 0, 0);
-            c2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, a, c2, 0, 0, 0);
-            c3 = __builtin_amdgcn_mfma_f32_16x16x4f32(b, b, c3, 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) c[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(j & 1 ? a : b, j & 2 ? a : b, c[j], 0, 0, 0);
         }
-        const float t = c0[0] + c1[1] + c2[2] + c3[3];
+        float t = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) t += c[j][j & 3];
         if (t == -1.0f) out[0] = t;
     }
 }

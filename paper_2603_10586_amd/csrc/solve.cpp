@@ -760,7 +760,7 @@ qrvie_status qrvie_probe_mfma(qrvie_ctx* ctx, int32_t f64, double* tfs) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     CHECK(st);
-    const double flops = (double)kGrid * 4 /* waves */ * kIters * 4 /* chains */ * 2048.0;
+    const double flops = (double)kGrid * 4 /* waves */ * kIters * 8 /* chains */ * 2048.0;
     *tfs = ms > 0.f ? flops / (ms * 1e-3) / 1e12 : 0.0;
     return hip_check(ctx, hipGetLastError(), "probe");
 }
