@@ -51,3 +51,19 @@ def test_context_creation_fails_cleanly_without_a_gpu():
     h = ctypes.c_void_p()
     st = lib.qrvie_ctx_create(0, None, 0, ctypes.byref(h))
     assert st == _lib.ERR_DEVICE and not h.value
+
+
+def test_entry_points_reject_null_handles_without_a_device():
+    """Argument checks run before any device work: null handles give QRVIE_ERR_INVALID_ARG."""
+    import ctypes
+    from paper_2603_10586_amd import _lib
+    lib = _lib.load()
+    out = ctypes.c_double()
+    assert lib.qrvie_probe_read(None, None, 16, 1, ctypes.byref(out)) == _lib.ERR_INVALID_ARG
+    assert lib.qrvie_probe_mfma(None, 1, ctypes.byref(out)) == _lib.ERR_INVALID_ARG
+    t = _lib.BlockTune()
+    assert lib.qrvie_op_tune_block(None, None, 0, 16, 1, ctypes.byref(t)) == _lib.ERR_INVALID_ARG
+    ms = (ctypes.c_double * 4)()
+    fl = (ctypes.c_int64 * 4)()
+    assert lib.qrvie_op_profile_block(None, None, 16, 1, ms, fl) == _lib.ERR_INVALID_ARG
+    assert lib.qrvie_solve(None, None, 1, None, 1, None, 1, None, None) == _lib.ERR_INVALID_ARG
