@@ -39,7 +39,7 @@ public:
     // Admit every queued request that fits now, in arrival order; evicted cache keys are
     // appended to `evicted` (their operators are to be destroyed by the caller).
     void admit(std::vector<uint64_t>* admitted, std::vector<std::string>* evicted) {
-        std::vector<Job*> waiting;          // passed over in this round, still queued
+        std::vector<Job*> waiting;          // passed over in this admission pass, still queued
         for (auto it = queue_.begin(); it != queue_.end() && running_ < slots_;) {
             Job& j = jobs_.at(*it);
             const bool hit = cached(j.key);
