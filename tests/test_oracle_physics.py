@@ -128,6 +128,28 @@ def test_plane_wave_normal_x_polarised(tiny_oracle):
     assert np.allclose(v[:, 0], vol * np.exp(-1j * d.k * pos[:, 2]), rtol=1e-15, atol=0)
 
 
+@pytest.mark.parametrize("theta,phi", [(25.0, 0.0), (-30.0, 40.0), (60.0, 200.0)])
+def test_plane_wave_oblique_is_a_transverse_right_handed_wave(tiny_oracle, theta, phi):
+    # Reference triad from rotations of the z-directed wave: k^ = Rz(phi) Ry(theta) z^,
+    # TM = Rz(phi) Ry(theta) x^ (in the plane of incidence), TE = Rz(phi) y^ (horizontal).
+    t, f = math.radians(theta), math.radians(phi)
+    Ry = np.array([[math.cos(t), 0, math.sin(t)], [0, 1, 0], [-math.sin(t), 0, math.cos(t)]])
+    Rz = np.array([[math.cos(f), -math.sin(f), 0], [math.sin(f), math.cos(f), 0], [0, 0, 1]])
+    k_ref, tm_ref, te_ref = Rz @ Ry @ [0, 0, 1], Rz @ Ry @ [1, 0, 0], Rz @ [0, 1, 0]
+    assert np.allclose(np.cross(tm_ref, te_ref), k_ref, atol=1e-15)
+    d = tiny_oracle["disc"]
+    pos, vol, _, _ = d.cell_arrays()
+    v = greens.plane_wave_rhs(d, [theta, theta], [phi, phi], [0, 1])
+    for col, e_ref in ((0, te_ref), (1, tm_ref)):
+        e = v[:, col].reshape(-1, 3) / vol[:, None]
+        # every cell carries the same polarisation up to its phase exp(-j k k^.r)
+        ph = np.exp(-1j * d.k * (pos @ k_ref))
+        assert np.allclose(e, ph[:, None] * e_ref[None, :], rtol=0, atol=1e-14)
+        # transverse, unit amplitude
+        assert np.allclose(e @ k_ref, 0, atol=1e-14)
+        assert np.allclose(np.linalg.norm(e, axis=1), 1.0, rtol=1e-14)
+
+
 def test_matrix_free_product_equals_dense(tiny_oracle):
     d, Z = tiny_oracle["disc"], tiny_oracle["Z"]
     x = np.random.default_rng(1).standard_normal(Z.shape[0]) + 0j
