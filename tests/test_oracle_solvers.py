@@ -1,5 +1,6 @@
 """Pins of the oracle's direct and iterative solvers (no GPU)."""
 import numpy as np
+import pytest
 
 import workloads as W
 from oracle import compressed, discretise, greens, grouping, solvers
@@ -96,6 +97,10 @@ def test_compressed_operator_accuracy_bounds(tiny_oracle):
         ZQR = compressed.dense_from_factors(sb, fac)
         errs.append(np.linalg.norm(np.linalg.solve(ZQR, v) - xlu) / np.linalg.norm(xlu))
         gains.append(compressed.gain(Z.shape[0], 16 * 144 * 144, ranks))
+        # N_QR is the number of complex entries actually stored: self blocks plus Q and R
+        stored = sb.size + sum(Q.size + R.size for _, _, Q, R in fac)
+        assert gains[-1] == pytest.approx(Z.shape[0] ** 2 / stored, rel=1e-15)
+        assert ZQR.shape == Z.shape and stored < Z.size
     # tighter eps: lower gain, higher solution accuracy (the trend of §6.2)
     assert gains[0] > gains[1] > 1.0
     assert errs[0] > errs[1]
