@@ -43,11 +43,10 @@ public:
         for (auto it = queue_.begin(); it != queue_.end() && running_ < slots_;) {
             Job& j = jobs_.at(*it);
             const bool hit = cached(j.key);
+            const std::string* keep = hit ? &j.key : nullptr;   // a hit never evicts its own operator
             const size_t need = hit ? j.footprint - j.op_bytes : j.footprint;
-            while (in_use_ + need > budget_ && evict_one(evicted)) {
-            }
-            if (in_use_ + need > budget_) {
-                waiting.push_back(&j);
+            if (in_use_ + need > budget_ + evictable(keep)) {
+                waiting.push_back(&j);      // does not fit even after evictions: evict nothing
                 ++it;
                 continue;
             }
@@ -55,6 +54,8 @@ public:
             for (Job* w : waiting) starved = starved || (max_bypass_ > 0 && w->bypassed >= max_bypass_);
             if (starved) break;
             for (Job* w : waiting) ++w->bypassed;
+            while (in_use_ + need > budget_ && evict_one(evicted, keep)) {
+            }
             in_use_ += need;
             peak_ = in_use_ > peak_ ? in_use_ : peak_;
             j.need = need;
@@ -100,6 +101,11 @@ public:
     }
 
     bool cached(const std::string& key) const { return cache_.count(key) != 0; }
+    // Whether an admitted (not yet finished) request holds a pin on its cached operator.
+    bool pinned(uint64_t ticket) const {
+        auto it = jobs_.find(ticket);
+        return it != jobs_.end() && it->second.pinned;
+    }
     size_t in_use() const { return in_use_; }
     size_t peak() const { return peak_; }
     int running() const { return running_; }
@@ -121,10 +127,19 @@ private:
         std::list<std::string>::iterator pos;
     };
 
-    bool evict_one(std::vector<std::string>* evicted) {
+    // Bytes held by cached operators that no admitted request pins, other than `keep`.
+    size_t evictable(const std::string* keep) const {
+        size_t b = 0;
+        for (const auto& kv : cache_)
+            if (kv.second.pins == 0 && !(keep && kv.first == *keep)) b += kv.second.bytes;
+        return b;
+    }
+
+    // Evict the least recently used unpinned operator other than `keep`; false if none.
+    bool evict_one(std::vector<std::string>* evicted, const std::string* keep = nullptr) {
         for (auto it = lru_.begin(); it != lru_.end(); ++it) {
             Entry& e = cache_.at(*it);
-            if (e.pins > 0) continue;
+            if (e.pins > 0 || (keep && *it == *keep)) continue;
             in_use_ -= e.bytes;
             evicted->push_back(*it);
             cache_.erase(*it);

@@ -64,6 +64,11 @@ struct Key {
     }
 };
 
+struct Cached {
+    qrvie_geom* geom = nullptr;
+    qrvie_op* op = nullptr;
+};
+
 struct Request {
     uint64_t ticket = 0;
     std::string key;
@@ -80,11 +85,7 @@ struct Request {
     qrvie_status status = QRVIE_OK;
     std::vector<qrvie_c128> x;
     std::vector<qrvie_solve_info> info;
-};
-
-struct Cached {
-    qrvie_geom* geom = nullptr;
-    qrvie_op* op = nullptr;
+    Cached hit;                       // cached operator pinned for it at admission (op null: build)
 };
 
 }  // namespace
@@ -139,7 +140,14 @@ void admit_locked(qrvie_server* s, std::vector<Cached>& drops) {
     }
     const double now = clock_s();
     for (uint64_t t : adm) {
-        s->reqs.at(t)->admitted = now;
+        Request* r = s->reqs.at(t).get();
+        r->admitted = now;
+        // only an operator the policy pinned for this request is safe from eviction while it
+        // runs: one cached after admission is not used (the request builds its own)
+        if (s->pol.pinned(t)) {
+            auto it = s->cache.find(r->key);
+            if (it != s->cache.end()) r->hit = it->second;
+        }
         s->ready.push_back(t);
     }
     if (!adm.empty()) s->cv.notify_all();
@@ -210,20 +218,15 @@ void worker(qrvie_server* s, int slot) {
     qrvie_ctx* ctx = s->ctx[slot];
     for (;;) {
         Request* r = nullptr;
-        Cached hit{};
-        bool is_hit = false;
         {
             std::unique_lock<std::mutex> lk(s->mu);
             s->cv.wait(lk, [&] { return !s->ready.empty() || s->closing; });
             if (s->ready.empty()) return;
             r = s->reqs.at(s->ready.front()).get();
             s->ready.pop_front();
-            auto it = s->cache.find(r->key);
-            if (it != s->cache.end()) {       // pinned by the policy at admission
-                hit = it->second;
-                is_hit = true;
-            }
         }
+        const Cached hit = r->hit;
+        const bool is_hit = hit.op != nullptr;
         qrvie_op* op = nullptr;
         bool built = false;
         qrvie_status st = QRVIE_OK;

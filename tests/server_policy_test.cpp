@@ -141,10 +141,92 @@ static int bypass_limit_prevents_starvation() {
     return 0;
 }
 
+static int cache_hit_never_evicts_its_own_operator() {
+    Policy p(2, 100, 2);
+    std::vector<uint64_t> adm;
+    std::vector<std::string> ev;
+    EXPECT(p.enqueue(1, "a", 50, 40));
+    p.admit(&adm, &ev);
+    EXPECT(p.finish(1, true, &ev) && p.cached("a") && p.in_use() == 40);
+    EXPECT(p.enqueue(2, "x", 50, 10));
+    p.admit(&adm, &ev);
+    EXPECT(p.in_use() == 90 && p.running() == 1);
+    // a hit on "a" needs 20 more bytes; the only evictable entry is its own operator
+    EXPECT(p.enqueue(3, "a", 60, 40));
+    adm.clear();
+    p.admit(&adm, &ev);
+    EXPECT(adm.empty() && ev.empty() && p.cached("a") && p.in_use() == 90);
+    EXPECT(p.finish(2, true, &ev) && p.in_use() == 50);          // "x" kept (10 B)
+    p.admit(&adm, &ev);
+    EXPECT(adm.size() == 1 && adm[0] == 3 && ev.empty() && p.hits() == 1 && p.in_use() == 70);
+    return 0;
+}
+
+static int no_eviction_for_a_request_that_still_waits() {
+    Policy p(2, 100, 2);
+    std::vector<uint64_t> adm;
+    std::vector<std::string> ev;
+    EXPECT(p.enqueue(1, "a", 30, 20));
+    p.admit(&adm, &ev);
+    EXPECT(p.finish(1, true, &ev) && p.in_use() == 20);
+    EXPECT(p.enqueue(2, "x", 70, 10));
+    p.admit(&adm, &ev);
+    EXPECT(p.in_use() == 90);
+    // even with "a" evicted, 70 + 50 > 100: "a" stays cached
+    EXPECT(p.enqueue(3, "b", 50, 20));
+    adm.clear();
+    p.admit(&adm, &ev);
+    EXPECT(adm.empty() && ev.empty() && p.cached("a"));
+
+    // a request held back by the bypass limit evicts nothing either
+    Policy q(3, 100, 2, 1);
+    adm.clear();
+    EXPECT(q.enqueue(1, "a", 30, 20));
+    q.admit(&adm, &ev);
+    EXPECT(q.finish(1, true, &ev) && q.in_use() == 20);
+    EXPECT(q.enqueue(2, "x", 50, 10));
+    q.admit(&adm, &ev);
+    EXPECT(q.in_use() == 70);
+    EXPECT(q.enqueue(3, "b", 60, 20));                           // 130 > 100 + 20: waits
+    EXPECT(q.enqueue(4, "y", 10, 5));                            // fits: overtakes 3 once
+    EXPECT(q.enqueue(5, "c", 30, 20));                           // fits only by evicting "a"
+    adm.clear();
+    q.admit(&adm, &ev);
+    EXPECT(adm.size() == 1 && adm[0] == 4 && ev.empty() && q.cached("a") && q.in_use() == 80);
+    return 0;
+}
+
+static int a_miss_stays_unpinned_when_its_key_is_cached_later() {
+    Policy p(3, 100, 2);
+    std::vector<uint64_t> adm;
+    std::vector<std::string> ev;
+    EXPECT(p.enqueue(1, "a", 40, 20));
+    EXPECT(p.enqueue(2, "a", 40, 20));
+    p.admit(&adm, &ev);                                          // both miss and build
+    EXPECT(adm.size() == 2 && !p.pinned(1) && !p.pinned(2));
+    EXPECT(p.finish(1, true, &ev) && p.cached("a") && p.in_use() == 60);
+    EXPECT(!p.pinned(2));                                        // still charged as a miss
+    // so the entry may be evicted while 2 runs: 2 must keep using the operator it built
+    EXPECT(p.enqueue(3, "b", 50, 20));
+    adm.clear();
+    p.admit(&adm, &ev);
+    EXPECT(adm.size() == 1 && adm[0] == 3 && ev.size() == 1 && ev[0] == "a" && p.in_use() == 90);
+    EXPECT(p.finish(2, true, &ev) && p.cached("a"));             // its own operator is kept now
+    // a request admitted on a cached key is pinned until it finishes
+    EXPECT(p.enqueue(4, "a", 30, 20));
+    adm.clear();
+    p.admit(&adm, &ev);
+    EXPECT(adm.size() == 1 && p.pinned(4));
+    EXPECT(!p.finish(4, false, &ev) && !p.pinned(4));
+    return 0;
+}
+
 int main() {
     int (*tests[])() = {fifo_and_slots, no_head_of_line_blocking, refuses_what_can_never_fit,
                         cache_hits_pin_and_lru_eviction, cache_capacity_is_bounded,
-                        bypass_limit_prevents_starvation};
+                        bypass_limit_prevents_starvation, cache_hit_never_evicts_its_own_operator,
+                        no_eviction_for_a_request_that_still_waits,
+                        a_miss_stays_unpinned_when_its_key_is_cached_later};
     for (auto t : tests)
         if (t()) return 1;
     std::printf("ok\n");
