@@ -419,7 +419,8 @@ qrvie_status qrvie_server_submit(qrvie_server* srv, const qrvie_array_desc* arra
                                  double tol, uint64_t* ticket);
 /* *done = 1 when the request has finished (successfully or not). */
 qrvie_status qrvie_server_poll(qrvie_server* srv, uint64_t ticket, int32_t* done);
-/* Block until the request finishes or timeout_s passes (< 0: no limit); *done as in poll. */
+/* Block until the request finishes or timeout_s passes (< 0: no limit); *done as in poll.
+ * QRVIE_ERR_INVALID_ARG for an unknown ticket, or one that another thread fetched meanwhile. */
 qrvie_status qrvie_server_wait(qrvie_server* srv, uint64_t ticket, double timeout_s, int32_t* done);
 /*
  * Copy a finished request's solution to the HOST buffer x (n x nrhs column-major, ldx >= n,

@@ -430,15 +430,25 @@ qrvie_status qrvie_server_poll(qrvie_server* s, uint64_t t, int32_t* done) {
 qrvie_status qrvie_server_wait(qrvie_server* s, uint64_t t, double timeout_s, int32_t* done) {
     if (!s || !done) return QRVIE_ERR_INVALID_ARG;
     std::unique_lock<std::mutex> lk(s->mu);
-    auto it = s->reqs.find(t);
-    if (it == s->reqs.end()) return QRVIE_ERR_INVALID_ARG;
-    Request* r = it->second.get();
+    // -1: unknown or released, 0: queued or running, 1: finished.  Looked up again after every
+    // wake-up, since another thread may fetch (and so free) the request meanwhile.
+    auto state = [&]() -> int {
+        auto it = s->reqs.find(t);
+        return it == s->reqs.end() ? -1 : it->second->done ? 1 : 0;
+    };
+    if (state() < 0) return QRVIE_ERR_INVALID_ARG;
+    auto settled = [&] { return state() != 0; };
     if (timeout_s < 0) {
-        s->cv.wait(lk, [&] { return r->done; });
+        s->cv.wait(lk, settled);
     } else {
-        s->cv.wait_for(lk, std::chrono::duration<double>(timeout_s), [&] { return r->done; });
+        s->cv.wait_for(lk, std::chrono::duration<double>(timeout_s), settled);
     }
-    *done = r->done ? 1 : 0;
+    const int now = state();
+    if (now < 0) {
+        s->err = "wait: the ticket was released by another thread";
+        return QRVIE_ERR_INVALID_ARG;
+    }
+    *done = now;
     return QRVIE_OK;
 }
 

@@ -90,6 +90,35 @@ def test_operator_cache_serves_repeated_geometries():
     assert np.array_equal(first.x, third.x)
 
 
+def test_concurrent_misses_on_one_geometry_and_a_waiter_racing_a_fetch():
+    import ctypes as C
+    import threading
+    from paper_2603_10586_amd import _lib as L
+    from paper_2603_10586_amd.server import Server, ServerOpts
+    reqs = _requests()
+    srv = Server(ServerOpts(slots=2, hbm_budget=8 << 30, restart=400, max_iter=2000, op_cache=1))
+    # the second is admitted before the first has cached the operator (submission takes far
+    # less than a build): each builds and runs on its own, and the third hits the cache
+    t1, t2 = srv.submit(reqs[1]), srv.submit(reqs[1])
+    seen = []
+
+    def waiter():
+        done = C.c_int32()
+        seen.append(srv.lib.qrvie_server_wait(srv.h, t1, 120.0, C.byref(done)))
+
+    th = threading.Thread(target=waiter, daemon=True)
+    th.start()
+    a, b = srv.result(t1, timeout=120), srv.result(t2, timeout=120)
+    th.join(timeout=150)
+    c = srv.result(srv.submit(reqs[1]), timeout=120)       # now a cache hit
+    st = srv.stats()
+    srv.close()
+    assert not th.is_alive() and seen and seen[0] in (L.OK, L.ERR_INVALID_ARG)
+    assert a.status == 0 and b.status == 0 and c.status == 0
+    assert st["ops_built"] + st["cache_hits"] == 3 and st["cache_hits"] >= 1 and st["failed"] == 0
+    assert np.array_equal(a.x, b.x) and np.array_equal(a.x, c.x)
+
+
 def test_request_larger_than_the_budget_is_refused():
     import paper_2603_10586_amd as q
     from paper_2603_10586_amd.server import Server, ServerOpts
