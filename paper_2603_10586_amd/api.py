@@ -44,6 +44,7 @@ class Context:
 
     def probe_read(self, buf, reps: int = 5) -> float:
         """Best streaming-read rate (GB/s) of the library's read probe over a device tensor."""
+        _device_tensor(buf, self.device, "probe read")
         nbytes = buf.numel() * buf.element_size() // 16 * 16
         out = C.c_double()
         self.order()
@@ -144,10 +145,26 @@ class Geometry:
             pass
 
 
-def _cols(t, n: int):
-    """(nrhs, n) contiguous complex128 device tensor -> (ptr, ld, nrhs)."""
+def _device_tensor(t, device: int, what: str):
+    """Refuse anything but a contiguous tensor on cuda:`device`: the library takes its
+    address as a raw device pointer."""
     torch = _torch()
-    assert t.dtype == torch.complex128 and t.is_cuda and t.is_contiguous() and t.shape[-1] == n
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what}: expected a torch tensor, got {type(t).__name__}")
+    if not t.is_cuda or t.device.index != device:
+        raise ValueError(f"{what}: tensor is on {t.device}, the context on cuda:{device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: tensor must be contiguous")
+
+
+def _cols(t, n: int, device: int, what: str):
+    """(nrhs, n) or (n,) contiguous complex128 tensor on cuda:`device` -> (ptr, ld, nrhs)."""
+    torch = _torch()
+    _device_tensor(t, device, what)
+    if t.dtype != torch.complex128:
+        raise TypeError(f"{what}: expected complex128, got {t.dtype}")
+    if t.dim() not in (1, 2) or t.shape[-1] != n:
+        raise ValueError(f"{what}: expected shape (nrhs, {n}) or ({n},), got {tuple(t.shape)}")
     nrhs = 1 if t.dim() == 1 else t.shape[0]
     return C.c_void_p(t.data_ptr()), n, nrhs
 
@@ -247,7 +264,7 @@ class Operator:
     def apply(self, x, prec=None):
         """y = Z_QR x with the operator's own far factors, or those of precision `prec`."""
         torch = _torch()
-        px, ld, nrhs = _cols(x, self.geom.ndof)
+        px, ld, nrhs = _cols(x, self.geom.ndof, self.ctx.device, "apply")
         y = torch.empty_like(x)
         self.ctx.order()
         if prec is None:
@@ -297,7 +314,7 @@ class Operator:
 
     def precondition(self, y):
         torch = _torch()
-        py, ld, nrhs = _cols(y, self.geom.ndof)
+        py, ld, nrhs = _cols(y, self.geom.ndof, self.ctx.device, "precondition")
         z = torch.empty_like(y)
         self.ctx.order()
         self.ctx.check(self.ctx.lib.qrvie_precondition(self.ctx.h, self.h, nrhs, py, ld, C.c_void_p(z.data_ptr()), ld),
@@ -307,7 +324,11 @@ class Operator:
     def solve(self, v, restart: int = 30, tol: float = 1e-8, max_iter: int = 10000, x0=None,
               mode: int = L.SOLVE_FP64, inner_tol: float = 0.0, verbose: bool = False, block_width: int = 0):
         torch = _torch()
-        pv, ld, nrhs = _cols(v, self.geom.ndof)
+        pv, ld, nrhs = _cols(v, self.geom.ndof, self.ctx.device, "solve")
+        if x0 is not None:
+            _cols(x0, self.geom.ndof, self.ctx.device, "solve x0")
+            if x0.shape != v.shape:
+                raise ValueError(f"solve: x0 has shape {tuple(x0.shape)}, v {tuple(v.shape)}")
         x = torch.zeros_like(v) if x0 is None else x0.clone()
         o = L.SolveOpts(restart=restart, max_iter=max_iter, mode=mode, tol=tol, use_x0=0 if x0 is None else 1,
                         inner_tol=inner_tol, verbose=1 if verbose else 0, block_width=block_width)

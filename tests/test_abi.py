@@ -67,3 +67,15 @@ def test_entry_points_reject_null_handles_without_a_device():
     fl = (ctypes.c_int64 * 4)()
     assert lib.qrvie_op_profile_block(None, None, 16, 1, ms, fl) == _lib.ERR_INVALID_ARG
     assert lib.qrvie_solve(None, None, 1, None, 1, None, 1, None, None) == _lib.ERR_INVALID_ARG
+
+
+def test_binding_refuses_host_tensors_before_any_library_call():
+    import torch
+    from paper_2603_10586_amd import api
+    n = 144
+    with pytest.raises(TypeError):
+        api._cols([0j] * n, n, 0, "apply")
+    with pytest.raises(ValueError):
+        api._cols(torch.zeros(2, n, dtype=torch.complex128), n, 0, "apply")        # host memory
+    with pytest.raises(ValueError):
+        api._device_tensor(torch.zeros(16, dtype=torch.float64), 0, "probe read")

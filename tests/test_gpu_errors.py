@@ -55,6 +55,31 @@ def test_invalid_operator_and_solve_options():
     assert st == 0 and info[0]["converged"] and float(x.abs().max()) == 0.0
 
 
+def test_binding_refuses_tensors_the_kernels_cannot_take():
+    import torch
+    import paper_2603_10586_amd as q
+    c = ctx()
+    g = q.Geometry(c, W.random_lattice(3, 3, seed=1))
+    op = q.Operator(c, g, eps=1e-6)
+    v = q.rhs_plane_waves(c, g, [0.0, 10.0], [0.0, 0.0], [1, 0])
+    n = g.ndof
+    with pytest.raises(TypeError):
+        op.apply(v.to(torch.complex64))                                    # wrong dtype
+    with pytest.raises(ValueError):
+        op.apply(v[:, : n - 1])                                            # wrong length
+    with pytest.raises(ValueError):
+        op.precondition(torch.zeros(n, 2, dtype=torch.complex128, device=v.device).t())   # strided
+    with pytest.raises(ValueError):
+        op.solve(v, x0=torch.zeros(1, n, dtype=torch.complex128, device=v.device))    # x0 too small
+    with pytest.raises(ValueError):
+        op.apply(v.cpu())                                                  # host memory
+    with pytest.raises(ValueError):
+        c.probe_read(torch.ones(1024, dtype=torch.float64))                # host memory
+    # the valid call still works after the refusals
+    x, info, st = op.solve(v, x0=torch.zeros_like(v), tol=1e-8, restart=200, max_iter=400)
+    assert st == 0 and all(i["converged"] for i in info)
+
+
 def test_hbm_budget_refuses_an_operator_that_does_not_fit():
     import paper_2603_10586_amd as q
     tight = q.Context(0, hbm_budget=4 << 20)
