@@ -93,8 +93,15 @@ def array_desc(array):
         eps=np.ascontiguousarray(np.asarray(array.eps_r, dtype=np.complex128).reshape(-1)),
         ij=np.ascontiguousarray(array.lattice_ij, dtype=np.int32),
     )
+    # the library reads n entries of each (n_eps = 1 or n): refuse mismatched lengths here
+    n = int(keep["centers"].shape[0]) if keep["centers"].ndim == 2 else -1
+    if (keep["centers"].shape != (n, 3) or keep["radius"].shape != (n,) or keep["height"].shape != (n,)
+            or keep["ij"].shape != (n, 2) or keep["eps"].shape[0] not in (1, n)):
+        raise ValueError("array: expected centers (n, 3), radius (n,), height (n,), lattice_ij (n, 2) and "
+                         f"eps_r (1,) or (n,); got {keep['centers'].shape}, {keep['radius'].shape}, "
+                         f"{keep['height'].shape}, {keep['ij'].shape}, {keep['eps'].shape}")
     d = L.ArrayDescC()
-    d.n = int(keep["centers"].shape[0])
+    d.n = n
     d.centers = _dptr(keep["centers"], C.c_double)
     d.radius = _dptr(keep["radius"], C.c_double)
     d.height = _dptr(keep["height"], C.c_double)

@@ -79,3 +79,21 @@ def test_binding_refuses_host_tensors_before_any_library_call():
         api._cols(torch.zeros(2, n, dtype=torch.complex128), n, 0, "apply")        # host memory
     with pytest.raises(ValueError):
         api._device_tensor(torch.zeros(16, dtype=torch.float64), 0, "probe read")
+
+
+def test_array_descriptor_refuses_mismatched_lengths():
+    import numpy as np
+    import workloads as W
+    from paper_2603_10586_amd import api
+    a = W.random_lattice(3, seed=1)
+    d, keep = api.array_desc(a)
+    assert d.n == 9 and d.n_eps in (1, 9)
+    for field, bad in (("radius", a.radius[:-1]), ("height", a.height[:4]), ("lattice_ij", a.lattice_ij[:, :1]),
+                       ("eps_r", a.eps_r[:2]), ("centers", a.centers[:, :2])):
+        b = W.random_lattice(3, seed=1)
+        setattr(b, field, bad)
+        with pytest.raises(ValueError):
+            api.array_desc(b)
+    one_eps = W.random_lattice(3, seed=1)
+    one_eps.eps_r = np.asarray([12 + 0.1j])
+    assert api.array_desc(one_eps)[0].n_eps == 1

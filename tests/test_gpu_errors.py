@@ -33,6 +33,11 @@ def test_invalid_geometry_inputs():
     e = W.lattice(2, 2)
     e.cells_per_particle = 40
     assert _status(lambda: q.Geometry(c, e)) == 1
+    empty = W.lattice(2, 2)                                            # no particles at all
+    for f, shape in (("centers", (0, 3)), ("lattice_ij", (0, 2)), ("radius", (0,)), ("height", (0,)),
+                     ("eps_r", (0,))):
+        setattr(empty, f, np.zeros(shape, dtype=getattr(empty, f).dtype))
+    assert _status(lambda: q.Geometry(c, empty)) == 1
 
 
 def test_invalid_operator_and_solve_options():
@@ -75,6 +80,9 @@ def test_binding_refuses_tensors_the_kernels_cannot_take():
         op.apply(v.cpu())                                                  # host memory
     with pytest.raises(ValueError):
         c.probe_read(torch.ones(1024, dtype=torch.float64))                # host memory
+    # no right-hand sides: refused by the library, not launched
+    assert _status(lambda: op.apply(torch.zeros(0, n, dtype=torch.complex128, device=v.device))) == 1
+    assert _status(lambda: op.solve(torch.zeros(0, n, dtype=torch.complex128, device=v.device))) == 1
     # the valid call still works after the refusals
     x, info, st = op.solve(v, x0=torch.zeros_like(v), tol=1e-8, restart=200, max_iter=400)
     assert st == 0 and all(i["converged"] for i in info)
