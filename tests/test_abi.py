@@ -97,3 +97,36 @@ def test_array_descriptor_refuses_mismatched_lengths():
     one_eps = W.random_lattice(3, seed=1)
     one_eps.eps_r = np.asarray([12 + 0.1j])
     assert api.array_desc(one_eps)[0].n_eps == 1
+
+
+C_CLIENT = r"""
+#include <stdio.h>
+#include <string.h>
+#include "qrvie.h"
+int main(void) {
+    if (strcmp(qrvie_status_string(QRVIE_OK), "ok") != 0) return 1;
+    if (qrvie_geom_ndof(NULL) != 0) return 2;
+    if (qrvie_solve(NULL, NULL, 1, NULL, 0, NULL, 0, NULL, NULL) != QRVIE_ERR_INVALID_ARG) return 3;
+    if (qrvie_apply(NULL, NULL, 1, NULL, 0, NULL, 0) != QRVIE_ERR_INVALID_ARG) return 4;
+    printf("ok\n");
+    return 0;
+}
+"""
+
+
+def test_header_is_plain_c_and_a_c_program_links_the_library(tmp_path):
+    import shutil
+    import subprocess
+    from paper_2603_10586_amd import _lib
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "client.c"
+    src.write_text(C_CLIENT)
+    exe = tmp_path / "client"
+    libdir = os.path.dirname(_lib.LIB_PATH)
+    subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I", os.path.join(ROOT, "include"),
+                    str(src), "-L", libdir, "-lqrvie", f"-Wl,-rpath,{libdir}", "-Wl,-rpath-link,/opt/rocm/lib",
+                    "-o", str(exe)], check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0 and r.stdout.strip() == "ok", (r.returncode, r.stderr)
