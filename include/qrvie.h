@@ -431,6 +431,8 @@ qrvie_status qrvie_server_wait(qrvie_server* srv, uint64_t ticket, double timeou
  */
 qrvie_status qrvie_server_fetch(qrvie_server* srv, uint64_t ticket, qrvie_c128* x, int64_t ldx,
                                 qrvie_solve_info* info);
+/* Snapshot of the server's counters, latency percentiles (finished requests) and admitted
+ * bytes into the caller's *out; QRVIE_ERR_INVALID_ARG for a null argument. */
 qrvie_status qrvie_server_get_stats(qrvie_server* srv, qrvie_server_stats* out);
 /* Arrival (submission), admission and completion times of a request not yet fetched, in
  * seconds on the server's steady clock (admitted/done are -1 until they happen). */
