@@ -2,6 +2,8 @@
 // test_server_policy.py; no device involved).
 #include <cassert>
 #include <cstdio>
+#include <map>
+#include <random>
 #include <string>
 #include <vector>
 
@@ -221,12 +223,76 @@ static int a_miss_stays_unpinned_when_its_key_is_cached_later() {
     return 0;
 }
 
+// Random submissions and completions against a shadow model of what the policy must keep:
+// bytes in use = needs of the running requests + bytes of the cached operators, within the
+// budget; at most `slots` running; a running cache hit keeps its operator cached; no waiting
+// request overtaken more than max_bypass times.
+static int random_sequences_keep_the_invariants() {
+    const size_t budget = 100;
+    const int slots = 3, op_cache = 2, max_bypass = 3;
+    for (uint32_t seed = 1; seed <= 20; ++seed) {
+        Policy p(slots, budget, op_cache, max_bypass);
+        std::mt19937 rng(seed);
+        auto op_bytes = [](int k) { return (size_t)(5 + 3 * k); };
+        struct Sh { int key; size_t fp; bool running; int bypass; };
+        std::map<uint64_t, Sh> jobs;                              // ordered by ticket = arrival
+        std::vector<uint64_t> adm;
+        std::vector<std::string> ev;
+        uint64_t next = 1;
+        for (int step = 0; step < 20000; ++step) {
+            std::vector<uint64_t> run;
+            for (auto& kv : jobs)
+                if (kv.second.running) run.push_back(kv.first);
+            if (run.empty() || (p.queued() < 12 && rng() % 2 == 0)) {   // bounded queue
+                const int k = (int)(rng() % 6);
+                const size_t fp = op_bytes(k) + 1 + rng() % 40;
+                if (p.enqueue(next, "k" + std::to_string(k), fp, op_bytes(k))) jobs[next] = Sh{k, fp, false, 0};
+                ++next;
+            } else {
+                const uint64_t t = run[rng() % run.size()];
+                p.finish(t, !p.pinned(t), &ev);
+                jobs.erase(t);
+            }
+            adm.clear();
+            p.admit(&adm, &ev);
+            for (uint64_t t : adm) {
+                jobs.at(t).running = true;
+                for (auto& kv : jobs)                             // every earlier request still queued
+                    if (kv.first < t && !kv.second.running) ++kv.second.bypass;
+            }
+            size_t expect = 0;
+            int nrun = 0;
+            size_t nq = 0;
+            for (auto& kv : jobs) {
+                const Sh& j = kv.second;
+                const std::string key = "k" + std::to_string(j.key);
+                if (j.running) {
+                    ++nrun;
+                    const bool pin = p.pinned(kv.first);
+                    expect += pin ? j.fp - op_bytes(j.key) : j.fp;
+                    EXPECT(!pin || p.cached(key));
+                } else {
+                    ++nq;
+                    EXPECT(j.bypass <= max_bypass);
+                }
+            }
+            for (int k = 0; k < 6; ++k)
+                if (p.cached("k" + std::to_string(k))) expect += op_bytes(k);
+            EXPECT(p.in_use() == expect && p.in_use() <= budget);
+            EXPECT(p.running() == nrun && nrun <= slots && p.queued() == nq);
+            EXPECT((int)p.cache_size() <= op_cache);
+        }
+    }
+    return 0;
+}
+
 int main() {
     int (*tests[])() = {fifo_and_slots, no_head_of_line_blocking, refuses_what_can_never_fit,
                         cache_hits_pin_and_lru_eviction, cache_capacity_is_bounded,
                         bypass_limit_prevents_starvation, cache_hit_never_evicts_its_own_operator,
                         no_eviction_for_a_request_that_still_waits,
-                        a_miss_stays_unpinned_when_its_key_is_cached_later};
+                        a_miss_stays_unpinned_when_its_key_is_cached_later,
+                        random_sequences_keep_the_invariants};
     for (auto t : tests)
         if (t()) return 1;
     std::printf("ok\n");
