@@ -818,8 +818,8 @@ qrvie_status qrvie_op_export_block(const qrvie_op* op, int64_t b, qrvie_block_in
                                                      sizeof(float2) * op->r_ld[b], sizeof(float2) * r, (size_t)n,
                                                      hipMemcpyDeviceToHost, ctx->stream), "export R"));
         CHECK(hip_check(ctx, hipStreamSynchronize(ctx->stream), "export"));
-        for (size_t e = 0; e < tq.size(); ++e) Q[e] = qrvie_c128{(double)tq[e].x, (double)tq[e].y};
-        for (size_t e = 0; e < tr.size(); ++e) R[e] = qrvie_c128{(double)tr[e].x, (double)tr[e].y};
+        for (size_t i = 0; i < tq.size(); ++i) Q[i] = qrvie_c128{(double)tq[i].x, (double)tq[i].y};
+        for (size_t i = 0; i < tr.size(); ++i) R[i] = qrvie_c128{(double)tr[i].x, (double)tr[i].y};
         return QRVIE_OK;
     }
     if (Q && r > 0)
