@@ -384,7 +384,8 @@ def main() -> int:
               f"true res {max(i['rel_res_true'] for i in info):.2e}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     total_s = time.perf_counter() - t_start
-    assert all(i["converged"] for i in infos), "a timed solve did not converge"
+    if not all(i["converged"] for i in infos):
+        raise SystemExit("a timed solve did not converge: no throughput is reported")
 
     n_apply = sum(i["n_apply"] for i in infos)
     t_apply = sum(i["t_apply_s"] for i in infos)
