@@ -11,6 +11,7 @@ It shares no code with the HIP library and never imports it.  Only the tests,
 the smoke entry point and the benchmark's CPU-baseline leg may import it; the
 product path must never route through it.
 
-Parity status per function is listed in each module header.
+Each module header lists the tests that pin its functions against the paper or the
+mathematics (closed forms, invariants, brute force, special cases).
 """
 from . import discretise, greens, grouping, solvers, compressed  # noqa: F401

@@ -14,7 +14,8 @@
 
 Pins (tests): own LU == numpy.linalg.solve; GMRES == LU on small systems;
 one particle converges in one iteration (preconditioner exact for an isolated
-meta-atom, §4); Givens estimate equals the explicit preconditioned residual.
+meta-atom, §4); after one cycle the Givens estimate equals the explicit preconditioned
+residual of the returned iterate; estimates are monotone within a cycle.
 """
 from __future__ import annotations
 

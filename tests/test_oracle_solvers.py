@@ -34,6 +34,19 @@ def test_gmres_matches_lu_on_tiny(tiny_oracle):
     assert np.all(np.diff(h) <= 1e-14)
 
 
+def test_givens_estimate_equals_the_explicit_preconditioned_residual(tiny_oracle):
+    """After one cycle of m steps, the rotated right-hand side |g_(m+1)| / ||M b|| is the
+    preconditioned residual of the iterate the cycle returns (a GMRES identity)."""
+    Z, v = tiny_oracle["Z"], tiny_oracle["v"]
+    P = solvers.BlockDiagPreconditioner(tiny_oracle["self_blocks"])
+    mb = np.linalg.norm(P.apply(v))
+    for m in (1, 5, 10, 17):
+        x, info = solvers.gmres(lambda u: Z @ u, v, P.apply, restart=m, tol=1e-14, max_iter=m)
+        explicit = np.linalg.norm(P.apply(v - Z @ x)) / mb
+        assert len(info.history) == m
+        assert abs(info.history[-1] - explicit) <= 1e-8 * explicit
+
+
 def test_single_particle_converges_in_one_iteration():
     """The preconditioner is the exact inverse for an isolated meta-atom (§4)."""
     arr = W.lattice(1, radius=0.2)
