@@ -15,7 +15,8 @@ is the oracle's reading of that rule:
 * canonical order: layer (lower, upper), then b ascending, then a ascending;
   DoF index = (cell * 3 + component), component x, y, z fastest.
 
-Pins (tests): 24 squares, volume exactness, symmetry of the offset set.
+Pins (tests): 24 squares, volume exactness, symmetry of the offset set; the
+equal-volume sphere radius of a cell in closed form, (r^2 t / 64)^(1/3).
 Unknowns are ordered particle by particle (§4, eq. 4.1).
 """
 from __future__ import annotations

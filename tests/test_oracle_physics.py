@@ -100,6 +100,23 @@ def test_single_cell_polarisability_clausius_mossotti_and_radiation_reaction():
     assert abs(corr.imag - k ** 3 / (6 * math.pi)) / (k ** 3 / (6 * math.pi)) < 1e-3
 
 
+def test_cell_sphere_radius_and_diagonal_entry_closed_form():
+    """48 cells of volume pi r^2 t / 48: the equal-volume sphere has radius (r^2 t / 64)^(1/3),
+    and each diagonal entry is V (1/chi - s(a)) with that radius (no other term)."""
+    r, t, eps = 0.23, 0.1, 12.0 + 0.1j
+    arr = W.lattice(1, radius=r, height=t, eps_r=eps)
+    d = discretise.Discretisation(arr)
+    a = (r * r * t / 64.0) ** (1.0 / 3.0)
+    assert abs(d.a_eq[0] - a) <= 1e-15 * a
+    Z = greens.assemble_dense(d)
+    V = math.pi * r * r * t / 48.0
+    want = V * (1.0 / (eps - 1.0) - greens.self_term(a, d.k))
+    diag = np.diag(Z)
+    assert np.allclose(diag, want, rtol=1e-13, atol=0)
+    # the 3 x 3 block of one cell is diagonal
+    assert np.all(Z[0:3, 0:3][~np.eye(3, dtype=bool)] == 0)
+
+
 def test_matrix_is_complex_symmetric(tiny_oracle):
     Z = tiny_oracle["Z"]
     assert np.max(np.abs(Z - Z.T)) <= 1e-15 * np.max(np.abs(Z))
