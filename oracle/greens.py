@@ -25,7 +25,9 @@ Pins (tests): exact symmetry Z = Z^T; finite-difference check of G against
 (I + grad grad / k^2) g; far-field limit G -> g (I - d^ d^); the small-ka series
 s(a) = -1/3 + (ka)^2/3 - j (2/9)(ka)^3; the static single-cell
 Clausius-Mossotti limit p = 3 (eps - 1)/(eps + 2) E0; oblique TE/TM plane waves equal
-the polarisation triad rotated from the z-directed wave.
+the polarisation triad rotated from the z-directed wave; for any p, the imaginary part
+of the off-diagonal form plus the point-dipole self radiation equals the power the cell
+dipoles radiate (an independent far-field quadrature).
 """
 from __future__ import annotations
 

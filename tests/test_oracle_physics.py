@@ -117,6 +117,34 @@ def test_cell_sphere_radius_and_diagonal_entry_closed_form():
     assert np.all(Z[0:3, 0:3][~np.eye(3, dtype=bool)] == 0)
 
 
+def test_off_diagonal_imaginary_part_is_the_radiated_power_of_the_cell_dipoles():
+    """For any p, Im(p^H Z_off p) + k^3/(6 pi) sum V_m^2 |p_m|^2 is the power radiated by the
+    dipoles V_n p_n: k^3/(16 pi^2) times the integral over directions of
+    |(I - r^ r^) sum_n V_n p_n exp(-j k r^.r_n)|^2 (exp(+j omega t) convention).  The far
+    field is summed here with its own Gauss-Legendre x trapezoid quadrature."""
+    arr = W.random_lattice(2, 2, seed=3)
+    d = discretise.Discretisation(arr)
+    Z = greens.assemble_dense(d)
+    pos, vol, _, _ = d.cell_arrays()
+    nc, k = pos.shape[0], d.k
+    Zoff = Z.copy()
+    for m in range(nc):
+        Zoff[3 * m:3 * m + 3, 3 * m:3 * m + 3] = 0
+    rng = np.random.default_rng(7)
+    p = rng.standard_normal(3 * nc) + 1j * rng.standard_normal(3 * nc)
+    lhs = np.vdot(p, Zoff @ p).imag + k ** 3 / (6 * math.pi) * np.sum(vol ** 2 * np.sum(np.abs(p.reshape(-1, 3)) ** 2, 1))
+    mu, wmu = np.polynomial.legendre.leggauss(48)
+    nphi = 96
+    phi = np.arange(nphi) * 2 * math.pi / nphi
+    st = np.sqrt(1 - mu ** 2)
+    rh = np.stack([np.outer(st, np.cos(phi)).ravel(), np.outer(st, np.sin(phi)).ravel(), np.repeat(mu, nphi)], 1)
+    w = np.repeat(wmu, nphi) * (2 * math.pi / nphi)
+    F = np.exp(-1j * k * rh @ pos.T) @ (vol[:, None] * p.reshape(-1, 3))
+    Ft = F - rh * np.sum(rh * F, 1)[:, None]
+    rhs = k ** 3 / (16 * math.pi ** 2) * np.sum(w * np.sum(np.abs(Ft) ** 2, 1))
+    assert rhs > 0 and abs(lhs - rhs) <= 1e-12 * rhs
+
+
 def test_matrix_is_complex_symmetric(tiny_oracle):
     Z = tiny_oracle["Z"]
     assert np.max(np.abs(Z - Z.T)) <= 1e-15 * np.max(np.abs(Z))
