@@ -440,7 +440,9 @@ qrvie_status qrvie_server_request_times(qrvie_server* srv, uint64_t ticket, doub
                                         double* admitted_s, double* done_s);
 /* Last error text of the server (submission or request failures). */
 const char*  qrvie_server_last_error(qrvie_server* srv);
-/* Finish the running requests, cancel the queued ones, free every operator and context. */
+/* Finish the running requests, cancel the queued ones, free every operator and context.
+ * No other call on the server may be in progress (a pending qrvie_server_wait included)
+ * or follow: the handle is freed. */
 void         qrvie_server_destroy(qrvie_server* srv);
 
 #ifdef __cplusplus
