@@ -19,10 +19,13 @@ in tests by ``qrcp_truncate``) and checks them against its own re-assembly:
 through scipy, truncated at the smallest rank meeting the tolerance); it is the
 reference the GPU's ranks and solution accuracy are compared with.
 
-Pins (tests): per-block eps met with orthonormal Q and ranks at or above the SVD bound;
-the global product bound ||(Z_QR - Z) x|| <= eps ||Z_off||_F ||x||; eps_prod < eps;
-G equals N_dof^2 over the entries actually stored; tighter eps lowers G and raises the
-solution accuracy (the trends of §6.2).
+Pins (tests): ``svd_rank`` on blocks with prescribed singular values, at and around
+every tail threshold, and as the Eckart-Young minimum of the truncated SVD;
+``dense_from_factors`` against blocks placed by hand particle by particle;
+``compressed_apply`` equals that dense operator; ``eps_prod`` and ``gain`` against
+hand-computed cases; per-block eps met with orthonormal Q and ranks at or above the SVD
+bound; the global product bound ||(Z_QR - Z) x|| <= eps ||Z_off||_F ||x||; eps_prod < eps;
+tighter eps lowers G and raises the solution accuracy (the trends of §6.2).
 """
 from __future__ import annotations
 

@@ -15,7 +15,9 @@
 Pins (tests): own LU == numpy.linalg.solve; GMRES == LU on small systems;
 one particle converges in one iteration (preconditioner exact for an isolated
 meta-atom, §4); after one cycle the Givens estimate equals the explicit preconditioned
-residual of the returned iterate; estimates are monotone within a cycle.
+residual of the returned iterate; estimates are monotone within a cycle; GMRES(m)
+stopped after m steps equals the least-squares minimiser over the Krylov space built
+from explicit matrix powers.
 """
 from __future__ import annotations
 
