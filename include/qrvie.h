@@ -68,6 +68,9 @@ void         qrvie_ctx_destroy(qrvie_ctx* ctx);
 const char*  qrvie_last_error(const qrvie_ctx* ctx);
 /* Bytes currently allocated by the library on this context. */
 size_t       qrvie_ctx_bytes_in_use(const qrvie_ctx* ctx);
+/* High-water mark of the library's bytes on this context since its creation or the last
+ * reset; reset != 0 then restarts the mark at the bytes currently in use. */
+size_t       qrvie_ctx_peak_bytes(qrvie_ctx* ctx, int32_t reset);
 
 /* ----------------------------------------------------------------- geometry */
 /*
@@ -184,15 +187,26 @@ typedef struct {
     double rel_err;                 /* certified ||B - QR||_F / ||B||_F */
 } qrvie_block_info;
 
-/* Upper bound of the operator's device bytes before it is built. */
+/*
+ * Estimate, before the build, of the peak device bytes of qrvie_op_create with options o: the
+ * operator once built (factor panels of the precision o->far_prec, self blocks and their
+ * inverses, strip lists) plus the build's transient buffers (the compact factors before they
+ * are packed; the largest compression chunk of materialised blocks with its direct-QR copies
+ * and sketches, chunk_bytes = 0 counted as its 64 GiB maximum).  It follows the same block
+ * list as the build (o->max_block_rows applied).  Ranks are not known before compression: the
+ * estimate assumes per block min(m, n, r_model) with r_model above the largest ranks measured
+ * for each block size at eps = 1e-6 (80 up to 2304 rows, 100 up to 9216, 128 up to 36,864, 160
+ * beyond) plus 14 per decade below 1e-6.  It is therefore an estimate, not a guarantee: an
+ * array whose ranks exceed the model needs more.  QRVIE_ERR_INVALID_ARG for invalid options.
+ */
 qrvie_status qrvie_op_footprint_estimate(const qrvie_geom* g, const qrvie_compress_opts* o, size_t* bytes);
 /*
  * Build the compressed operator Z_QR: self blocks Z_pp and the preconditioner
  * Z_D^-1 (§4, eq. 4.2), then every far/finest pair block of the recursive
  * grouping as certified low-rank factors Q R (§5.2-5.4).  Z_QR is exactly
  * complex-symmetric: the pair (J, I) stores the transpose of the factors of
- * (I, J).  Fails with QRVIE_ERR_OUT_OF_MEMORY if the estimate exceeds the
- * context's remaining budget.
+ * (I, J).  Fails with QRVIE_ERR_OUT_OF_MEMORY if the footprint estimate (at the chunk size
+ * the build will use) exceeds the context's remaining budget.
  */
 qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_compress_opts* o, qrvie_op** out);
 qrvie_status qrvie_op_stats_get(const qrvie_op* op, qrvie_op_stats* out);
@@ -338,9 +352,16 @@ typedef struct {
     double  rel_res_prec, rel_res_true;
     int32_t n_apply, n_prec;
     double  t_apply_s, t_prec_s, t_krylov_s, t_total_s;
-    int32_t n_reorth;     /* Arnoldi steps that needed the second Gram-Schmidt pass */
+    int32_t n_reorth;     /* Arnoldi steps whose projection carries the second Gram-Schmidt
+                             correction.  The single-vector solver computes it through the Gram
+                             matrix G = V^H V of the stored basis (coefficients 2 h1 - G h1, one
+                             pass over the basis), not as a second pass; basis_ortho measures
+                             what that leaves */
     int32_t n_refine;     /* MIXED_IR: correction solves (iterations and n_apply count all of
                              them; rel_res_prec is the last correction's own estimate) */
+    double  basis_ortho;  /* FP64 and MIXED_IR: max_ij |(V^H V - I)_ij| over the Krylov basis of
+                             every cycle (the largest), from the Gram matrix of the stored basis;
+                             0 in the block modes */
 } qrvie_solve_info;
 
 /* Upper bound of the device bytes qrvie_solve allocates for nrhs right-hand sides

@@ -57,7 +57,7 @@ class SolveInfo(C.Structure):
                 ("rel_res_prec", C.c_double), ("rel_res_true", C.c_double), ("n_apply", C.c_int32),
                 ("n_prec", C.c_int32), ("t_apply_s", C.c_double), ("t_prec_s", C.c_double),
                 ("t_krylov_s", C.c_double), ("t_total_s", C.c_double), ("n_reorth", C.c_int32),
-                ("n_refine", C.c_int32)]
+                ("n_refine", C.c_int32), ("basis_ortho", C.c_double)]
 
 
 class ServerOptsC(C.Structure):
@@ -96,6 +96,7 @@ SIGNATURES = {
     "qrvie_ctx_destroy": (None, [P]),
     "qrvie_last_error": (C.c_char_p, [P]),
     "qrvie_ctx_bytes_in_use": (C.c_size_t, [P]),
+    "qrvie_ctx_peak_bytes": (C.c_size_t, [P, I32]),
     "qrvie_geom_create": (ST, [P, C.POINTER(ArrayDescC), PP]),
     "qrvie_geom_ndof": (I64, [P]),
     "qrvie_geom_nlevels": (I32, [P]),

@@ -68,6 +68,10 @@ class Context:
     def bytes_in_use(self) -> int:
         return int(self.lib.qrvie_ctx_bytes_in_use(self.h))
 
+    def peak_bytes(self, reset: bool = False) -> int:
+        """High-water mark of the library's device bytes on this context (then reset it)."""
+        return int(self.lib.qrvie_ctx_peak_bytes(self.h, 1 if reset else 0))
+
     def close(self):
         if getattr(self, "h", None):
             self.lib.qrvie_ctx_destroy(self.h)
@@ -216,8 +220,9 @@ class Operator:
         self.h = h
 
     @staticmethod
-    def footprint_estimate(geom: Geometry, eps: float = 1e-6, max_block_rows: int = 0) -> int:
-        o = L.CompressOpts(eps=eps, max_block_rows=max_block_rows)
+    def footprint_estimate(geom: Geometry, eps: float = 1e-6, max_block_rows: int = 0, far_prec: int = L.PREC_C128,
+                           chunk_bytes: int = 0) -> int:
+        o = L.CompressOpts(eps=eps, far_prec=far_prec, max_block_rows=max_block_rows, chunk_bytes=chunk_bytes)
         out = C.c_size_t()
         st = geom.ctx.lib.qrvie_op_footprint_estimate(geom.h, C.byref(o), C.byref(out))
         geom.ctx.check(st, "footprint")

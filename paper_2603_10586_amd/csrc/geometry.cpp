@@ -52,7 +52,10 @@ qrvie_status dalloc(qrvie_ctx* ctx, void** p, size_t bytes, const char* what) {
                          hipGetErrorString(e));
         return e == hipErrorOutOfMemory ? QRVIE_ERR_OUT_OF_MEMORY : QRVIE_ERR_DEVICE;
     }
-    ctx->in_use += bytes;
+    const size_t now = (ctx->in_use += bytes);
+    size_t pk = ctx->peak.load();
+    while (now > pk && !ctx->peak.compare_exchange_weak(pk, now)) {
+    }
     return QRVIE_OK;
 }
 
@@ -184,6 +187,13 @@ void qrvie_ctx_destroy(qrvie_ctx* ctx) {
 const char* qrvie_last_error(const qrvie_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
 size_t qrvie_ctx_bytes_in_use(const qrvie_ctx* ctx) { return ctx ? ctx->in_use.load() : 0; }
+
+size_t qrvie_ctx_peak_bytes(qrvie_ctx* ctx, int32_t reset) {
+    if (!ctx) return 0;
+    const size_t pk = ctx->peak.load();
+    if (reset) ctx->peak.store(ctx->in_use.load());
+    return pk;
+}
 
 qrvie_status qrvie_geom_create(qrvie_ctx* ctx, const qrvie_array_desc* d, qrvie_geom** out) {
     if (!ctx || !d || !out) return QRVIE_ERR_INVALID_ARG;

@@ -119,6 +119,7 @@ struct qrvie_ctx {
     bool own_stream = false;
     size_t budget = 0;
     std::atomic<size_t> in_use{0};  // atomic: the server frees operators from other threads
+    std::atomic<size_t> peak{0};    // high-water mark of in_use since creation or the last reset
     std::string err;
     void* blas = nullptr;           // rocBLAS handle of the block solver, created on first use
 };
@@ -196,6 +197,17 @@ qrvie_status dalloc(qrvie_ctx* ctx, void** p, size_t bytes, const char* what);
 void dfree(qrvie_ctx* ctx, void* p, size_t bytes);
 void blas_release(qrvie_ctx* ctx);
 
+// The compressed pair blocks of an operator: the grouping's far/finest pairs with far pairs of
+// more than `cap` rows or columns split into their child pairs (0 = no cap), sorted by
+// (level, r0, c0), with mirrors set.
+std::vector<BlockRec> split_blocks(const qrvie_geom* g, int64_t cap);
+// Device bytes of an operator built with options o: `resident` once built (panels, self
+// blocks, preconditioner, strip lists) and `transient` during the build (compact factors
+// before packing, the largest chunk of materialised blocks with its sketches).  Ranks follow
+// a model bounded by the largest ranks measured per block size; chunk_bytes = 0 is taken as
+// its automatic maximum of 64 GiB.
+void op_footprint(const qrvie_geom* g, const qrvie_compress_opts* o, size_t* resident, size_t* transient);
+
 // ---------------------------------------------------------------- launchers
 // assembly (k_assemble.hip)
 void launch_assemble_self(hipStream_t s, const qrvie_geom* g, c128* out, int ntypes);
@@ -267,6 +279,8 @@ void launch_scale_into(hipStream_t s, const c128* w, int64_t n, const double* no
 void launch_givens(hipStream_t s, int j, c128* hcol, c128* H, int ldh, double* cs, c128* sn, c128* gvec,
                    const double* hnorm2, double* status);
 void launch_trisolve(hipStream_t s, int k, const c128* H, int ldh, const c128* gvec, c128* y);
+// *out = max(*out, max_ij |G_ij - delta_ij|) over the leading k x k block (out >= 0 on entry)
+void launch_gram_deviation(hipStream_t s, const c128* G, int64_t ldg, int k, double* out);
 void launch_gemv_add(hipStream_t s, const c128* V, int64_t ldv, int ncols, const c128* y, c128* x, int64_t n);
 void launch_add(hipStream_t s, const c128* d, int64_t n, c128* x);
 void launch_rsub(hipStream_t s, const c128* a, int64_t n, c128* y);   // y = a - y

@@ -182,6 +182,24 @@ __global__ void k_scale_into(const c128* __restrict__ w, int64_t n, const double
     out[e] = make_double2(w[e].x * inv, w[e].y * inv);
 }
 
+// Loss of orthogonality of the first k basis vectors, max_ij |G_ij - delta_ij| over the Gram
+// matrix G = V^H V that the projections maintain, folded into *out (a non-negative double
+// kept as its bit pattern, so the maximum is an exact, order-independent integer max).
+__global__ void __launch_bounds__(256) k_gram_deviation(const c128* __restrict__ G, int64_t ldg, int k,
+                                                        unsigned long long* out) {
+    double m = 0.0;
+    const int64_t tot = (int64_t)k * k;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256) {
+        const int64_t i = e % k, j = e / k;
+        const c128 g = G[i + j * ldg];
+        const double re = g.x - (i == j ? 1.0 : 0.0);
+        m = fmax(m, sqrt(re * re + g.y * g.y));
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
+}
+
 // x += d (the update of an iterative-refinement step)
 // Streaming read of n 16-byte entries with the product kernels' nontemporal loads, U loads
 // in flight per lane, grid-stride; the sum is kept only so that the loads are not removed.
@@ -376,6 +394,13 @@ void launch_reduce_norm(hipStream_t s, const double* partial, int count, double*
 }
 void launch_scale_into(hipStream_t s, const c128* w, int64_t n, const double* norm2, c128* out, c128* gslot) {
     hipLaunchKernelGGL(k_scale_into, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w, n, norm2, out, gslot);
+}
+void launch_gram_deviation(hipStream_t s, const c128* G, int64_t ldg, int k, double* out) {
+    if (k <= 0) return;
+    const int64_t tot = (int64_t)k * k;
+    const unsigned grid = (unsigned)std::min<int64_t>(1024, (tot + 255) / 256);
+    hipLaunchKernelGGL(k_gram_deviation, dim3(grid), dim3(256), 0, s, G, ldg, k,
+                       reinterpret_cast<unsigned long long*>(out));
 }
 void launch_mfma_probe(hipStream_t s, bool f64, int grid, int iters, double* out) {
     if (f64) hipLaunchKernelGGL(k_mfma_probe<true>, dim3(grid), dim3(256), 0, s, iters, out);

@@ -485,23 +485,118 @@ struct Builder {
     }
 };
 
+// Chunk size of the build when chunk_bytes = 0: a quarter of the free device memory (or of
+// the context's remaining budget), between 256 MB and 64 GiB.
+size_t auto_chunk_bytes(qrvie_ctx* ctx) {
+    double room = 8.0 * (1ull << 30);
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) room = (double)free_b;
+    if (ctx->budget) room = std::min(room, (double)(ctx->budget - std::min(ctx->budget, ctx->in_use.load())));
+    return (size_t)std::min(64.0 * (1ull << 30), std::max(2.56e8, room / 4.0));
+}
+
+// Rank model of the footprint estimate: above the largest ranks measured per block size at
+// eps = 1e-6 (144 rows: 70; 576: 50; 2304: 66; 9216: 89), growing by 14 per decade of a
+// tighter eps (QRCP ranks on the 4 x 4 array rise by 11-12 per decade).
+double rank_model(double rows, double eps) {
+    const double base = rows <= 2304 ? 80.0 : rows <= 9216 ? 100.0 : rows <= 36864 ? 128.0 : 160.0;
+    return base + 14.0 * std::max(0.0, -std::log10(eps) - 6.0);
+}
+
 }  // namespace
+
+namespace qrvie {
+
+std::vector<BlockRec> split_blocks(const qrvie_geom* g, int64_t cap) {
+    std::vector<BlockRec> out;
+    std::vector<BlockRec> work(g->blocks.begin(), g->blocks.end());
+    while (!work.empty()) {
+        BlockRec b = work.back();
+        work.pop_back();
+        if (cap > 0 && b.level < g->L && ((int64_t)b.rn * kNp > cap || (int64_t)b.cn * kNp > cap)) {
+            for (int32_t ci : node_children(g, b.rnode))
+                for (int32_t cj : node_children(g, b.cnode)) {
+                    const auto& a = g->nodes[ci];
+                    const auto& c = g->nodes[cj];
+                    work.push_back(BlockRec{b.level + 1, a.first, a.count, c.first, c.count, -1,
+                                            a.first < c.first ? 1 : 0, ci, cj});
+                }
+        } else {
+            out.push_back(b);
+        }
+    }
+    std::sort(out.begin(), out.end(), [](const BlockRec& a, const BlockRec& b) {
+        if (a.level != b.level) return a.level < b.level;
+        if (a.r0 != b.r0) return a.r0 < b.r0;
+        return a.c0 < b.c0;
+    });
+    std::map<std::tuple<int, int, int>, int32_t> idx;
+    for (size_t i = 0; i < out.size(); ++i) idx[{out[i].level, out[i].r0, out[i].c0}] = (int32_t)i;
+    for (auto& b : out) b.mirror = idx.at({b.level, b.c0, b.r0});
+    return out;
+}
+
+void op_footprint(const qrvie_geom* g, const qrvie_compress_opts* o, size_t* resident, size_t* transient) {
+    const std::vector<BlockRec> blocks = split_blocks(g, o->max_block_rows);
+    const int64_t chunk_elems =
+        std::max<int64_t>(1, (o->chunk_bytes > 0 ? o->chunk_bytes : ((int64_t)64 << 30)) / (int64_t)sizeof(c128));
+    double fac = 0.0, prim = 0.0, tlen = 0.0, rpad = 0.0, qstrips = 0.0;
+    std::map<std::pair<int, int>, int> rpanels;
+    // materialised bytes per chunk, in the build's chunk order: block, direct work copy,
+    // sketch and projected sketch (doubled for the retries of a wider sketch)
+    double acc = 0.0, dir = 0.0, sk = 0.0, best = 0.0;
+    auto flush = [&]() {
+        best = std::max(best, acc + dir + 2.0 * sk);
+        acc = dir = sk = 0.0;
+    };
+    for (const BlockRec& b : blocks) {
+        const double m = (double)b.rn * kNp, n = (double)b.cn * kNp;
+        const double r = std::min(rank_model(std::max(m, n), o->eps), std::min(m, n));
+        fac += (m + n) * r;
+        tlen += r;
+        rpanels[{b.level, b.c0}] = b.cn;
+        if (!b.primary) continue;
+        prim += (m + n) * r;
+        const double e = m * n;
+        if (acc > 0.0 && acc + e > (double)chunk_elems) flush();
+        acc += e;
+        if (b.rn <= kDirectMaxParticles && b.cn <= kDirectMaxParticles) dir += e;
+        else {
+            const double k = std::min<double>(kSketchStart, std::min(m, n));
+            sk += k * (m + n);
+        }
+    }
+    flush();
+    for (const auto& kv : rpanels) rpad += (double)(kAlign - 1) * kv.second * kNp;
+    for (int32_t id = 0; id < (int32_t)g->nodes.size(); ++id) qstrips += std::ceil(g->nodes[id].count * kNp / 64.0);
+    const double panel_elems = fac + rpad;
+    double panels = 0.0, panels_final = 0.0;        // bytes while packing, and once built
+    if (o->far_prec == QRVIE_PREC_C64_ONLY) panels = panels_final = 8.0 * panel_elems;
+    else {
+        panels = 16.0 * panel_elems;
+        panels_final = panels + (o->far_prec == QRVIE_PREC_C64 ? 8.0 * panel_elems : 0.0);
+    }
+    const double seg = 16.0 * prim;                 // compact factors until they are packed
+    const double pools = 16.0 * best;
+    const double nstrips = tlen / 64.0 + (double)rpanels.size() + qstrips;
+    const double other = 2.0 * (double)g->types.size() * kNp * kNp * 16.0 + 8.0 * tlen +
+                         nstrips * (double)(sizeof(RStrip) + sizeof(QStrip) + sizeof(MStrip)) +
+                         (double)g->N * 3 * sizeof(MStrip) + (1 << 20);
+    const double peak = std::max({seg + pools, seg + panels, panels_final}) + other;
+    *resident = (size_t)(panels_final + other);
+    *transient = (size_t)(peak - panels_final - other);
+}
+
+}  // namespace qrvie
 
 extern "C" {
 
 qrvie_status qrvie_op_footprint_estimate(const qrvie_geom* g, const qrvie_compress_opts* o, size_t* bytes) {
-    if (!g || !o || !bytes) return QRVIE_ERR_INVALID_ARG;
-    // rank model: r ~ 64 per block side (mid-size arrays at eps = 1e-6 measure 27-89)
-    double elems = 0.0;
-    const double rmodel = 64.0 + 8.0 * std::max(0.0, -std::log10(o->eps) - 6.0);
-    for (const BlockRec& b : g->blocks) {
-        const double mm = (double)b.rn * kNp, nn = (double)b.cn * kNp;
-        elems += std::min(mm * nn, (mm + nn) * std::min(rmodel, std::min(mm, nn)));
-    }
-    const double self = 2.0 * g->types.size() * kNp * kNp;
-    const double vec = 8.0 * (double)g->ndof();
-    const double copy32 = o->far_prec == QRVIE_PREC_C64 ? 0.5 : 0.0;   // complex64 copy, half the bytes
-    *bytes = (size_t)((elems * (1.5 + copy32) + self + vec) * sizeof(c128));
+    if (!g || !o || !bytes || !(o->eps > 0.0) || o->max_block_rows < 0 || o->chunk_bytes < 0)
+        return QRVIE_ERR_INVALID_ARG;
+    size_t resident = 0, transient = 0;
+    op_footprint(g, o, &resident, &transient);
+    *bytes = resident + transient;
     return QRVIE_OK;
 }
 
@@ -516,11 +611,17 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
         set_err(ctx, "op_create: unsupported precision or option");
         return QRVIE_ERR_INVALID_ARG;
     }
-    size_t est = 0;
-    qrvie_op_footprint_estimate(g, o, &est);
-    if (ctx->budget && ctx->in_use.load() + est > ctx->budget) {
-        set_err(ctx, "op_create: footprint estimate " + std::to_string(est) + " exceeds the remaining HBM budget");
-        return QRVIE_ERR_OUT_OF_MEMORY;
+    {
+        // resident operator plus the build's transient buffers at the chunk size it will use
+        qrvie_compress_opts oc = *o;
+        if (oc.chunk_bytes == 0) oc.chunk_bytes = (int64_t)auto_chunk_bytes(ctx);
+        size_t resident = 0, transient = 0;
+        op_footprint(g, &oc, &resident, &transient);
+        if (ctx->budget && ctx->in_use.load() + resident + transient > ctx->budget) {
+            set_err(ctx, "op_create: footprint estimate " + std::to_string(resident + transient) +
+                             " exceeds the remaining HBM budget");
+            return QRVIE_ERR_OUT_OF_MEMORY;
+        }
     }
     hipStream_t s = ctx->stream;
     auto* op = new qrvie_op;
@@ -564,35 +665,7 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
     op->stats.t_precond_setup_s = t1 - t0;
 
     // block list, with the optional row cap splitting far pairs into child pairs
-    Builder bld{op, ctx, g, {}, {}, {}, o->eps};
-    {
-        std::vector<BlockRec> work(g->blocks.begin(), g->blocks.end());
-        const int64_t cap = o->max_block_rows;
-        while (!work.empty()) {
-            BlockRec b = work.back();
-            work.pop_back();
-            if (cap > 0 && b.level < g->L && ((int64_t)b.rn * kNp > cap || (int64_t)b.cn * kNp > cap)) {
-                for (int32_t ci : node_children(g, b.rnode))
-                    for (int32_t cj : node_children(g, b.cnode)) {
-                        const auto& a = g->nodes[ci];
-                        const auto& c = g->nodes[cj];
-                        work.push_back(BlockRec{b.level + 1, a.first, a.count, c.first, c.count, -1,
-                                                a.first < c.first ? 1 : 0, ci, cj});
-                    }
-            } else {
-                bld.blocks.push_back(b);
-            }
-        }
-        std::sort(bld.blocks.begin(), bld.blocks.end(), [](const BlockRec& a, const BlockRec& b) {
-            if (a.level != b.level) return a.level < b.level;
-            if (a.r0 != b.r0) return a.r0 < b.r0;
-            return a.c0 < b.c0;
-        });
-        std::map<std::tuple<int, int, int>, int32_t> idx;
-        for (size_t i = 0; i < bld.blocks.size(); ++i)
-            idx[{bld.blocks[i].level, bld.blocks[i].r0, bld.blocks[i].c0}] = (int32_t)i;
-        for (auto& b : bld.blocks) b.mirror = idx.at({b.level, b.c0, b.r0});
-    }
+    Builder bld{op, ctx, g, split_blocks(g, o->max_block_rows), {}, {}, o->eps};
     const size_t NB = bld.blocks.size();
     bld.fac.resize(NB);
 
@@ -600,15 +673,8 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
     // (a quarter of the free device memory, or of the remaining budget, at most 64 GiB: the
     // one-workgroup-per-block kernels of the sketch path are better used with many blocks,
     // and concurrent builds on one device still leave room for each other)
-    double room = 8.0 * (1ull << 30);
-    {
-        size_t free_b = 0, total_b = 0;
-        if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) room = (double)free_b;
-        if (ctx->budget) room = std::min(room, (double)(ctx->budget - ctx->in_use.load()));
-    }
     const int64_t chunk_elems =
-        o->chunk_bytes > 0 ? std::max<int64_t>(1, o->chunk_bytes / (int64_t)sizeof(c128))
-                           : (int64_t)(std::min(64.0 * (1ull << 30), std::max(2.56e8, room / 4.0)) / sizeof(c128));
+        std::max<int64_t>(1, (o->chunk_bytes > 0 ? o->chunk_bytes : (int64_t)auto_chunk_bytes(ctx)) / (int64_t)sizeof(c128));
     {
         std::vector<int32_t> ids, kw;
         int64_t acc = 0;

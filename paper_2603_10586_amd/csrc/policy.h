@@ -28,10 +28,13 @@ public:
         : slots_(slots), budget_(budget), op_cache_(op_cache), max_bypass_(max_bypass) {}
 
     // Queue a request; false (refused) when it cannot fit an otherwise empty budget (its
-    // operator may be evicted before it starts, so the whole footprint must fit).
-    bool enqueue(uint64_t ticket, const std::string& key, size_t footprint, size_t op_bytes) {
-        if (footprint > budget_ || op_bytes > footprint) return false;
-        jobs_[ticket] = Job{key, footprint, op_bytes, 0, false, 0};
+    // operator may be evicted before it starts, so the whole footprint must fit).  The
+    // footprint of a request that builds its operator includes op_bytes (what a cached
+    // operator keeps) and build_bytes (the build's transient buffers); a cache hit needs
+    // neither.
+    bool enqueue(uint64_t ticket, const std::string& key, size_t footprint, size_t op_bytes, size_t build_bytes = 0) {
+        if (footprint > budget_ || op_bytes + build_bytes > footprint) return false;
+        jobs_[ticket] = Job{key, footprint, op_bytes, build_bytes, 0, false, 0};
         queue_.push_back(ticket);
         return true;
     }
@@ -44,7 +47,7 @@ public:
             Job& j = jobs_.at(*it);
             const bool hit = cached(j.key);
             const std::string* keep = hit ? &j.key : nullptr;   // a hit never evicts its own operator
-            const size_t need = hit ? j.footprint - j.op_bytes : j.footprint;
+            const size_t need = hit ? j.footprint - j.op_bytes - j.build_bytes : j.footprint;
             if (in_use_ + need > budget_ + evictable(keep)) {
                 waiting.push_back(&j);      // does not fit even after evictions: evict nothing
                 ++it;
@@ -117,7 +120,7 @@ public:
 private:
     struct Job {
         std::string key;
-        size_t footprint, op_bytes, need;
+        size_t footprint, op_bytes, build_bytes, need;
         bool pinned;
         int bypassed;                       // later requests admitted while this one waited
     };

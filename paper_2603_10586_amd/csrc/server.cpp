@@ -46,22 +46,12 @@ struct ArrayCopy {
     }
 };
 
-// 64-bit FNV-1a over the bytes that define an operator; two independent streams make the
-// geometry key 128 bits.
+// The bytes that define an operator, appended into one string.  The string itself is the
+// cache key, so two requests share an operator only when these bytes are equal (the hash of
+// the key only picks a bucket).
 struct Key {
-    uint64_t a = 1469598103934665603ull, b = 0x84222325cbf29ce4ull;
-    void add(const void* p, size_t bytes) {
-        const unsigned char* c = static_cast<const unsigned char*>(p);
-        for (size_t i = 0; i < bytes; ++i) {
-            a = (a ^ c[i]) * 1099511628211ull;
-            b = (b ^ c[i]) * 0x100000001b3ull + 0x9E3779B97F4A7C15ull;
-        }
-    }
-    std::string hex() const {
-        char s[40];
-        std::snprintf(s, sizeof s, "%016llx%016llx", (unsigned long long)a, (unsigned long long)b);
-        return s;
-    }
+    std::string bytes;
+    void add(const void* p, size_t n) { bytes.append(static_cast<const char*>(p), n); }
 };
 
 struct Cached {
@@ -79,7 +69,7 @@ struct Request {
     double tol = 0;
     qrvie_geom* geom = nullptr;       // planning geometry (owned until handed to the cache)
     int64_t n = 0;
-    size_t footprint = 0, op_bytes = 0;
+    size_t footprint = 0, op_bytes = 0, build_bytes = 0;
     double arrival = 0, admitted = -1, done_at = -1;
     bool done = false;
     qrvie_status status = QRVIE_OK;
@@ -368,8 +358,8 @@ qrvie_status qrvie_server_submit(qrvie_server* s, const qrvie_array_desc* a, int
     k.add(&c.wavelength, sizeof c.wavelength);
     k.add(&s->o.eps, sizeof s->o.eps);
     k.add(&s->o.seed, sizeof s->o.seed);
-    r->key = k.hex();
-    size_t op_b = 0, sol_b = 0;
+    r->key = std::move(k.bytes);
+    size_t op_b = 0, build_b = 0, sol_b = 0;
     {
         std::lock_guard<std::mutex> g(s->plan_mu);
         const qrvie_array_desc d = c.desc();
@@ -377,16 +367,19 @@ qrvie_status qrvie_server_submit(qrvie_server* s, const qrvie_array_desc* a, int
         if (st != QRVIE_OK) return bad(s, std::string("submit: ") + qrvie_last_error(s->plan), st);
         const qrvie_compress_opts co = compress_opts(s);
         const qrvie_solve_opts so = solve_opts(s, tol);
-        st = qrvie_op_footprint_estimate(r->geom, &co, &op_b);
-        if (st == QRVIE_OK) st = qrvie_solve_footprint_estimate(r->geom, nullptr, nrhs, &so, &sol_b);
+        op_footprint(r->geom, &co, &op_b, &build_b);
+        st = qrvie_solve_footprint_estimate(r->geom, nullptr, nrhs, &so, &sol_b);
         if (st != QRVIE_OK) {
             qrvie_geom_destroy(r->geom);
             return bad(s, "submit: footprint estimate failed", st);
         }
         r->n = qrvie_geom_ndof(r->geom);
     }
+    // a request that builds its operator holds the build's transient buffers as well; the
+    // policy charges a cache hit only its solver bytes
     r->op_bytes = op_b;
-    r->footprint = op_b + sol_b + 2 * sizeof(c128) * (size_t)r->n * nrhs;
+    r->build_bytes = build_b;
+    r->footprint = op_b + build_b + sol_b + 2 * sizeof(c128) * (size_t)r->n * nrhs;
     std::vector<Cached> drops;
     qrvie_status result = QRVIE_OK;
     {
@@ -399,7 +392,7 @@ qrvie_status qrvie_server_submit(qrvie_server* s, const qrvie_array_desc* a, int
             const uint64_t t = s->next++;
             r->ticket = t;
             r->arrival = clock_s();
-            if (!s->pol.enqueue(t, r->key, r->footprint, r->op_bytes)) {
+            if (!s->pol.enqueue(t, r->key, r->footprint, r->op_bytes, r->build_bytes)) {
                 ++s->refused;
                 drops.push_back(Cached{r->geom, nullptr});
                 s->err = "submit: the request's footprint (" + std::to_string(r->footprint) +

@@ -144,6 +144,7 @@ struct Group {
             CHECK(w.alloc(&k.y, std::max(m, 1), "lsq solution"));
             CHECK(w.alloc(&k.cs, m, "givens c"));
             CHECK(w.alloc(&k.nrm, 4, "norms"));
+            CHECK(hip_check(ctx, hipMemsetAsync(k.nrm, 0, sizeof(double) * 4, s), "norms"));
             CHECK(w.alloc(&k.np, nch, "norm partials"));
             CHECK(w.alloc(&k.bp, nblk, "update norm partials"));
             CHECK(w.alloc(&k.G, (size_t)(m + 1) * (m + 1), "gram matrix"));
@@ -326,10 +327,16 @@ struct Group {
                 if (est <= k.prec_tol || breakdown) {
                     bool ok = false;
                     CHECK(candidate(i, kused, ok));
-                    if (ok) { k.converged = true; k.active = false; continue; }
+                    if (ok) {
+                        launch_gram_deviation(s, k.G, m + 1, kused, k.nrm + 3);
+                        k.converged = true;
+                        k.active = false;
+                        continue;
+                    }
                     if (breakdown) end_cycle = true;
                 }
                 if (end_cycle) {
+                    launch_gram_deviation(s, k.G, m + 1, kused, k.nrm + 3);
                     launch_trisolve(s, kused, k.H, m + 1, k.g, k.y);
                     launch_gemv_add(s, k.V, n, kused, k.y, k.x, n);
                     k.inf.restarts++;
@@ -347,10 +354,11 @@ qrvie_status Group::finish(c128* const* x, const std::vector<c128*>* src, qrvie_
     for (int i = 0; i < na; ++i) {
         Col& k = c[i];
         launch_permute(s, g->N, g->d_i2c, src ? (*src)[i] : k.x, x[i], 0);
-        CHECK(hip_check(ctx, hipStreamSynchronize(s), "solve"));
+        CHECK(read(k.nrm + 3, 1));
+        k.inf.basis_ortho = hstat[0];
         k.inf.iterations = k.iters;
         k.inf.converged = k.converged ? 1 : 0;
-        k.inf.n_reorth = k.iters;   // every step carries the second projection
+        k.inf.n_reorth = k.iters;   // every step carries the second projection (through G)
         k.inf.t_apply_s = k.t_apply;
         k.inf.t_prec_s = 0.0;   // fused into the product pass
         k.inf.t_total_s = now_s() - t0;

@@ -26,6 +26,10 @@ ARRAYS = {
     "rand5x3": lambda: W.random_lattice(5, 3, seed=11),
     "rand8x8": lambda: W.random_lattice(8, 8, seed=2),
     "rand6x7": lambda: W.random_lattice(6, 7, seed=5),
+    "rand16x16": lambda: W.random_lattice(16, 16, seed=7),
+    # a 33 x 33 request of the seeded serving stream: a ragged quadtree whose edge nodes hold
+    # one particle, so it has tall far blocks of one particle's columns (2304 x 144)
+    "serving33": lambda: W.serving_requests(n=8, seed=0, rate_per_s=1.0, side_lo=8, side_hi=48)[7].array,
 }
 
 
@@ -83,3 +87,30 @@ def to_dev(a: np.ndarray):
 
 def to_host(t) -> np.ndarray:
     return t.detach().cpu().numpy()
+
+
+_MID = {}
+
+
+def mid():
+    """The mid-size workload (32 x 32 disks, 147,456 unknowns, eps = 1e-6) on the GPU, with the
+    oracle's discretisation, the internal order and every block's export record."""
+    if not _MID:
+        import paper_2603_10586_amd as q
+        print("[gpu case] building mid 32x32 eps=1e-6", flush=True)
+        arr = W.mid(0)
+        c = ctx()
+        geom = q.Geometry(c, arr)
+        op = q.Operator(c, geom, eps=1e-6)
+        order = geom.order()
+        infos = [op.export_block(b, factors=False)[0] for b in range(op.num_blocks())]
+        _MID.update(arr=arr, disc=discretise.Discretisation(arr), geom=geom, op=op, order=order, infos=infos,
+                    internal=np.argsort(order))
+    return _MID
+
+
+def block_particles(order, info):
+    """Caller particle lists (rows, cols) of an exported block, in the block's DoF order."""
+    rows = order[info["row_first"]:info["row_first"] + info["row_count"]]
+    cols = order[info["col_first"]:info["col_first"] + info["col_count"]]
+    return rows, cols
