@@ -2,6 +2,7 @@
 from __future__ import annotations
 
 import ctypes as C
+import weakref
 
 import numpy as np
 
@@ -29,6 +30,7 @@ class Context:
         if stream is None:
             stream = torch.cuda.Stream(device)      # default priority
         self.stream = stream
+        self._children = []                      # weak references to geometries and operators
         h = C.c_void_p()
         st = self.lib.qrvie_ctx_create(device, C.c_void_p(stream.cuda_stream), hbm_budget, C.byref(h))
         if st != L.OK:
@@ -72,8 +74,23 @@ class Context:
         """High-water mark of the library's device bytes on this context (then reset it)."""
         return int(self.lib.qrvie_ctx_peak_bytes(self.h, 1 if reset else 0))
 
+    def _adopt(self, obj):
+        if len(self._children) >= 64:
+            self._children = [r for r in self._children if r() is not None]
+        self._children.append(weakref.ref(obj))
+
     def close(self):
+        """Destroy the context; operators and geometries still open on it are closed first
+        (operators before geometries), since the library frees them through the context."""
         if getattr(self, "h", None):
+            alive = [r() for r in getattr(self, "_children", [])]
+            for o in alive:
+                if isinstance(o, Operator):
+                    o.close()
+            for o in alive:
+                if o is not None and not isinstance(o, Operator):
+                    o.close()
+            self._children = []
             self.lib.qrvie_ctx_destroy(self.h)
             self.h = None
 
@@ -129,6 +146,7 @@ class Geometry:
         h = C.c_void_p()
         ctx.check(lib.qrvie_geom_create(ctx.h, C.byref(d), C.byref(h)), "geom_create")
         self.h = h
+        ctx._adopt(self)
         self.n_particles = d.n
         self.ndof = int(lib.qrvie_geom_ndof(h))
         self.n_levels = int(lib.qrvie_geom_nlevels(h))
@@ -146,7 +164,8 @@ class Geometry:
 
     def close(self):
         if getattr(self, "h", None):
-            self.ctx.lib.qrvie_geom_destroy(self.h)
+            if getattr(self.ctx, "h", None):
+                self.ctx.lib.qrvie_geom_destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -218,6 +237,7 @@ class Operator:
         h = C.c_void_p()
         ctx.check(ctx.lib.qrvie_op_create(ctx.h, geom.h, C.byref(o), C.byref(h)), "op_create")
         self.h = h
+        ctx._adopt(self)
 
     @staticmethod
     def footprint_estimate(geom: Geometry, eps: float = 1e-6, max_block_rows: int = 0, far_prec: int = L.PREC_C128,
@@ -353,7 +373,8 @@ class Operator:
 
     def close(self):
         if getattr(self, "h", None):
-            self.ctx.lib.qrvie_op_destroy(self.h)
+            if getattr(self.ctx, "h", None):
+                self.ctx.lib.qrvie_op_destroy(self.h)
             self.h = None
 
     def __del__(self):

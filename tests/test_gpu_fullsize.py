@@ -87,7 +87,7 @@ def test_full_size_solves_meet_the_tolerance_on_sampled_rows():
     assert st == 0 and info[0]["converged"] and info[0]["rel_res_true"] <= 1e-6
     vh, xh = to_host(v)[0], to_host(x)[0]
     print(f"[mid solve] {info[0]['iterations']} steps, basis orthogonality {info[0]['basis_ortho']:.2e}", flush=True)
-    assert info[0]["basis_ortho"] <= 1e-6
+    assert info[0]["basis_ortho"] <= 1e-12          # measured 2.6e-15 after 1729 steps
     allp = np.arange(m["arr"].n_particles)
     for p in SAMPLED:
         r = vh[p * 144:(p + 1) * 144] - oracle_rows(m, p, xh)
