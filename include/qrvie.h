@@ -290,6 +290,21 @@ qrvie_status qrvie_probe_read(qrvie_ctx* ctx, const void* d, size_t bytes, int32
  * register data over the whole device; *tfs (host) receives TFLOP/s.  A measurement helper.
  */
 qrvie_status qrvie_probe_mfma(qrvie_ctx* ctx, int32_t f64, double* tfs);
+/*
+ * y = Z_QR x for ONE right-hand side without allocating any device memory: for callers that
+ * cannot allocate (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The same kernels and result as qrvie_apply with nrhs = 1.  x and y are device
+ * vectors of n entries (caller order), y must not overlap x.  Stream-ordered on the context's
+ * stream and asynchronous: the call neither synchronises nor allocates; y is valid once the
+ * stream reaches this point.  Workspaces come from a fixed device array of 64 MiB per device,
+ * held from the first context created on that device until the process ends; the product
+ * needs 16 (2 n + sum of ranks + n x active levels) bytes (the mid-size 32 x 32 array fits,
+ * a 48 x 48 array does not), and larger operators are refused with QRVIE_ERR_INVALID_ARG (use
+ * qrvie_apply).  Every call on one device shares that array and leaves its contents behind:
+ * calls that overlap on a device (other streams, threads or contexts) race, so serialise them.
+ * QRVIE_ERR_DEVICE if the array's address could not be looked up at context creation.
+ */
+qrvie_status qrvie_apply_noalloc(qrvie_ctx* ctx, const qrvie_op* op, const qrvie_c128* x, qrvie_c128* y);
 /* z = Z_D^-1 y, the block-diagonal left preconditioner (§4, eq. 4.2). */
 qrvie_status qrvie_precondition(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs,
                                 const qrvie_c128* y, int64_t ldy, qrvie_c128* z, int64_t ldz);

@@ -113,6 +113,7 @@ SIGNATURES = {
     "qrvie_op_destroy": (None, [P]),
     "qrvie_apply": (ST, [P, P, I32, P, I64, P, I64]),
     "qrvie_apply_prec": (ST, [P, P, I32, I32, P, I64, P, I64]),
+    "qrvie_apply_noalloc": (ST, [P, P, P, P]),
     "qrvie_op_profile_apply": (ST, [P, P, I32, I32, C.POINTER(C.c_double), C.POINTER(I64)]),
     "qrvie_op_profile_block": (ST, [P, P, I32, I32, C.POINTER(C.c_double), C.POINTER(I64)]),
     "qrvie_op_tune_block": (ST, [P, P, I32, I32, I32, C.POINTER(BlockTune)]),

@@ -306,6 +306,17 @@ class Operator:
         self.ctx.check(st, "apply")
         return y
 
+    def apply_noalloc(self, x, y):
+        """y = Z_QR x for one vector into the caller's y, with the library's fixed scratch
+        (no device allocation, asynchronous on the context stream)."""
+        px, _, nrhs = _cols(x, self.geom.ndof, self.ctx.device, "apply_noalloc x")
+        py, _, nry = _cols(y, self.geom.ndof, self.ctx.device, "apply_noalloc y")
+        if nrhs != 1 or nry != 1:
+            raise ValueError("apply_noalloc: one vector of shape (n,) or (1, n)")
+        self.ctx.order()
+        self.ctx.check(self.ctx.lib.qrvie_apply_noalloc(self.ctx.h, self.h, px, py), "apply_noalloc")
+        return y
+
     def profile_apply(self, reps: int = 10, prec: int = L.PREC_C128) -> dict:
         """Per-stage device time (ms) and algorithmic bytes of one single-RHS product."""
         ms = (C.c_double * 4)()

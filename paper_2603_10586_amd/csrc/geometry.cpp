@@ -160,6 +160,7 @@ qrvie_status qrvie_ctx_create(int hip_device, void* hip_stream, size_t hbm_budge
     auto* c = new qrvie_ctx;
     c->device = hip_device;
     c->budget = hbm_budget;
+    if (!scratch_setup(hip_device, &c->scratch, &c->scratch_err)) c->scratch = nullptr;
     if (hip_stream) {
         c->stream = (hipStream_t)hip_stream;
     } else {

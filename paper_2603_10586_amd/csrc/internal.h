@@ -122,6 +122,8 @@ struct qrvie_ctx {
     std::atomic<size_t> peak{0};    // high-water mark of in_use since creation or the last reset
     std::string err;
     void* blas = nullptr;           // rocBLAS handle of the block solver, created on first use
+    void* scratch = nullptr;        // device address of this device's fixed product scratch
+    std::string scratch_err;        // why it is missing, when it is
 };
 
 struct qrvie_geom {
@@ -207,6 +209,15 @@ std::vector<BlockRec> split_blocks(const qrvie_geom* g, int64_t cap);
 // a model bounded by the largest ranks measured per block size; chunk_bytes = 0 is taken as
 // its automatic maximum of 64 GiB.
 void op_footprint(const qrvie_geom* g, const qrvie_compress_opts* o, size_t* resident, size_t* transient);
+
+// Look up (once per device, with that device current) the device address of the library's
+// fixed scratch array used by qrvie_apply_noalloc; false with a message on failure.
+bool scratch_setup(int device, void** ptr, std::string* err);
+// y = Z_QR x for one caller-order vector on stream s, with caller-provided workspaces: the
+// rank-space vector T (t_len), the level partials Ylev (n_active x n) and two permuted
+// vectors xi, yi (n each).  Launches only.
+void apply_single_into(const qrvie_op* op, hipStream_t s, c128* T, c128* Ylev, c128* xi, c128* yi, const c128* x,
+                       c128* y);
 
 // ---------------------------------------------------------------- launchers
 // assembly (k_assemble.hip)

@@ -566,6 +566,20 @@ qrvie_status solve_block_ir(qrvie_ctx* ctx, const qrvie_op* op, int nrhs, const 
 
 }  // namespace
 
+namespace qrvie {
+
+void apply_single_into(const qrvie_op* op, hipStream_t s, c128* T, c128* Ylev, c128* xi, c128* yi, const c128* x,
+                       c128* y) {
+    ProdWork pw;
+    pw.T = T;
+    pw.Y = Ylev;
+    launch_permute(s, op->g->N, op->g->d_i2c, x, xi, 1);
+    apply_one(op, s, pw, xi, nullptr, yi, nullptr, !op->d_fac);
+    launch_permute(s, op->g->N, op->g->d_i2c, yi, y, 0);
+}
+
+}  // namespace qrvie
+
 extern "C" {
 
 qrvie_status qrvie_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const qrvie_c128* x, int64_t ldx,
