@@ -142,7 +142,14 @@ enum { QRVIE_PREC_C128 = 0, QRVIE_PREC_C64 = 1, QRVIE_PREC_BF16X2 = 2, QRVIE_PRE
  *   near_prec        storage of the self blocks: QRVIE_PREC_C128 only for now
  *   max_block_rows   far blocks with more rows are split into their child
  *                    pairs (always far); 0 = no cap (the paper's scheme)
- *   share_transpose  reserved, must be 0
+ *   share_transpose  0: every ordered far block (I, J) and its mirror (J, I) keep their own
+ *                    panels (the mirror holds the transposed factors).  1: one Q, R per
+ *                    unordered pair, the mirror applied as R^T (Q^T x_I) (Z = Z^T, the symmetric
+ *                    weak form, §2 eq. 2.5): half the factor memory, and a single-RHS product
+ *                    streams each pair's Q twice and its R once instead of both twice.  Products
+ *                    and the FP64 / MIXED_IR solvers take shared operators (several right-hand
+ *                    sides one product per column); the block modes, qrvie_op_profile_block and
+ *                    qrvie_op_tune_block refuse them (QRVIE_ERR_INVALID_ARG).
  *   seed             seed of the random sketches used by compression
  *   verbose          1: print one progress line per compression chunk to stderr
  *   chunk_bytes      device bytes of materialised blocks compressed together; 0 = a
@@ -232,13 +239,14 @@ qrvie_status qrvie_apply_prec(qrvie_ctx* ctx, const qrvie_op* op, int32_t prec, 
 /*
  * Stage timers of the single-RHS product (the product stage of the paper's timing
  * table, §6.5), measured with HIP events on the context stream over `reps` products
- * of a fixed internal test vector.  ms[0] R-phase (t = R x for every block), ms[1]
- * Q-phase (y_l = Q t per level), ms[2] final pass (self blocks Z_pp x + level sum),
- * ms[3] whole product; averages per product.  bytes[0..3]: algorithmic HBM bytes of
- * the same stages per product (factor, self-block and vector traffic; the per-level
- * partial vectors are counted as overhead, not algorithmic bytes).  Host arrays of 4.
- * prec selects the far factors as in qrvie_apply_prec (complex64 factors count 8 bytes
- * per entry).
+ * of a fixed internal test vector.  ms[0] R-phase (t = R x for every block; with shared
+ * factors also the mirror partials R^T s), ms[1] Q-phase (y_l = Q t per level, with shared
+ * factors plus the mirror partials), ms[2] final pass (self blocks Z_pp x + level sum), ms[3]
+ * whole product, ms[4] the Q^T pass s = Q^T x of shared factors (0 otherwise), ms[5] = 0;
+ * averages per product.  bytes[0..5]: algorithmic HBM bytes of the same stages per product
+ * (factor, self-block and vector traffic, x counted once; the per-level and mirror partial
+ * vectors are counted as overhead, not algorithmic bytes).  Host arrays of 6.  prec selects
+ * the far factors as in qrvie_apply_prec (complex64 factors count 8 bytes per entry).
  */
 qrvie_status qrvie_op_profile_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t prec, int32_t reps, double* ms,
                                     int64_t* bytes);

@@ -229,10 +229,13 @@ class Operator:
     """The compressed interaction operator Z_QR with its block-diagonal preconditioner."""
 
     def __init__(self, ctx: Context, geom: Geometry, eps: float = 1e-6, max_block_rows: int = 0, seed: int = 0,
-                 far_prec: int = L.PREC_C128, verbose: bool = False, chunk_bytes: int = 0):
+                 far_prec: int = L.PREC_C128, verbose: bool = False, chunk_bytes: int = 0,
+                 share_transpose: bool = False):
         self.ctx, self.geom, self.far_prec = ctx, geom, far_prec
+        self.shared = bool(share_transpose)
         o = L.CompressOpts(eps=eps, far_prec=far_prec, near_prec=L.PREC_C128, max_block_rows=max_block_rows,
-                           share_transpose=0, seed=seed, verbose=1 if verbose else 0, chunk_bytes=chunk_bytes)
+                           share_transpose=1 if share_transpose else 0, seed=seed, verbose=1 if verbose else 0,
+                           chunk_bytes=chunk_bytes)
         self.opts = o
         h = C.c_void_p()
         ctx.check(ctx.lib.qrvie_op_create(ctx.h, geom.h, C.byref(o), C.byref(h)), "op_create")
@@ -241,8 +244,9 @@ class Operator:
 
     @staticmethod
     def footprint_estimate(geom: Geometry, eps: float = 1e-6, max_block_rows: int = 0, far_prec: int = L.PREC_C128,
-                           chunk_bytes: int = 0) -> int:
-        o = L.CompressOpts(eps=eps, far_prec=far_prec, max_block_rows=max_block_rows, chunk_bytes=chunk_bytes)
+                           chunk_bytes: int = 0, share_transpose: bool = False) -> int:
+        o = L.CompressOpts(eps=eps, far_prec=far_prec, max_block_rows=max_block_rows, chunk_bytes=chunk_bytes,
+                           share_transpose=1 if share_transpose else 0)
         out = C.c_size_t()
         st = geom.ctx.lib.qrvie_op_footprint_estimate(geom.h, C.byref(o), C.byref(out))
         geom.ctx.check(st, "footprint")
@@ -319,11 +323,11 @@ class Operator:
 
     def profile_apply(self, reps: int = 10, prec: int = L.PREC_C128) -> dict:
         """Per-stage device time (ms) and algorithmic bytes of one single-RHS product."""
-        ms = (C.c_double * 4)()
-        by = (C.c_int64 * 4)()
+        ms = (C.c_double * 6)()
+        by = (C.c_int64 * 6)()
         self.ctx.order()
         self.ctx.check(self.ctx.lib.qrvie_op_profile_apply(self.ctx.h, self.h, prec, reps, ms, by), "profile")
-        names = ("rphase", "qphase", "final", "product")
+        names = ("rphase", "qphase", "final", "product", "qtphase")
         return {k: dict(ms=ms[i], bytes=by[i]) for i, k in enumerate(names)}
 
     def profile_block(self, nrhs: int = 64, reps: int = 5) -> dict:

@@ -6,8 +6,9 @@
 // per device.  Its device address is looked up once per device (hipGetSymbolAddress, with the
 // device current) when a context is created on that device; host code uses only that
 // address.  Layout per call, in complex128 entries, each part aligned to 256 bytes: the
-// permuted input (n), the permuted output (n), the rank-space vector (the sum of the ranks)
-// and one partial vector per active level (n each).  Every part is written before it is read
+// permuted input (n), the permuted output (n), the rank-space vector (the sum of the ranks),
+// one partial vector per active level (n each) and, for transpose-shared factors, the
+// rank-space Q^T x and the mirror blocks' partial rows.  Every part is written before it is read
 // within one product, so nothing needs clearing between calls.  All calls on one device share
 // the array: calls that overlap on the device (several streams, threads or contexts) race.
 #include <mutex>
@@ -33,8 +34,9 @@ int64_t round16(int64_t e) { return (e + 15) / 16 * 16; }
 // Scratch bytes one product of `op` takes.
 size_t scratch_need(const qrvie_op* op) {
     const int64_t n = op->g->ndof();
-    const int64_t need = 2 * round16(n) + round16(std::max<int64_t>(op->t_len, 1)) +
-                         (int64_t)std::max(op->n_active, 1) * round16(n);
+    int64_t need = 2 * round16(n) + round16(std::max<int64_t>(op->t_len, 1)) +
+                   (int64_t)std::max(op->n_active, 1) * round16(n);
+    if (op->shared) need += round16(std::max<int64_t>(op->t_len, 1)) + round16(std::max<int64_t>(op->p_len, 1));
     return (size_t)need * sizeof(c128);
 }
 
@@ -89,7 +91,10 @@ qrvie_status qrvie_apply_noalloc(qrvie_ctx* ctx, const qrvie_op* op, const qrvie
     c128* yi = xi + round16(n);
     c128* T = yi + round16(n);
     c128* Ylev = T + round16(std::max<int64_t>(op->t_len, 1));
-    apply_single_into(op, ctx->stream, T, Ylev, xi, yi, reinterpret_cast<const c128*>(x), reinterpret_cast<c128*>(y));
+    c128* Sq = Ylev + (int64_t)std::max(op->n_active, 1) * round16(n);
+    c128* P = Sq + round16(std::max<int64_t>(op->t_len, 1));
+    apply_single_into(op, ctx->stream, T, Ylev, op->shared ? Sq : nullptr, op->shared ? P : nullptr, xi, yi,
+                      reinterpret_cast<const c128*>(x), reinterpret_cast<c128*>(y));
     return hip_check(ctx, hipGetLastError(), "apply_noalloc launch");
 }
 

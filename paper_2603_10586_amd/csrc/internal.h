@@ -44,6 +44,9 @@ struct RStrip {                     // t[tmap[tmap_off + i]] = sum_j A[i + j*ld]
     int32_t ld, ncols, nrows;
     int32_t x_off;                  // DoF start of the column node
     int64_t tmap_off;
+    int64_t p_off;                  // shared factors: this strip's row of partials P[p_off + j] =
+                                    // sum_i A[i + j*ld] s[tmap[tmap_off + i]] (the mirror blocks'
+                                    // R^T s); -1 otherwise
 };
 // One 64-row strip of a column-major panel applied to an RHS-interleaved block of P
 // right-hand sides (element (row e, rhs r) at e * P + r): out rows = A_strip in rows.
@@ -59,6 +62,16 @@ struct QStrip {                     // y[y_off + i] = sum_j A[i + j*ld] t[t_off 
     int64_t a_off;
     int32_t ld, ncols, nrows;
     int64_t y_off;                  // level partial index of the strip's first row
+    int64_t t_off;
+    int64_t p_off;                  // shared factors: plus sum_{k < p_cnt} P[p_off + k*p_ld + i]
+    int32_t p_cnt, p_ld;            // (the mirror blocks of this row node); p_cnt = 0 otherwise
+};
+// Shared factors, first pass: s[t_off + c] = sum_i A[i + c*ld] x[x_off + i] for the ncols
+// (<= 8) columns c of a Q panel starting at a_off (s = Q^T x of the pairs whose Q it holds).
+struct QtItem {
+    int64_t a_off;
+    int32_t ld, nrows, ncols;
+    int32_t x_off;
     int64_t t_off;
 };
 
@@ -166,6 +179,14 @@ struct qrvie_op {
     int64_t tmap_len = 0;
     qrvie::RStrip* d_rstrips = nullptr;
     qrvie::QStrip* d_qstrips = nullptr;
+    // Transpose-shared factors (share_transpose): one Q, R per unordered pair; the mirror block
+    // (J, I) is applied as R^T (Q^T x_I).  The product then runs three passes: s = Q^T x over the
+    // Q panels (d_qt), t = R x with the mirror partials R^T s over the R panels, y = Q t plus
+    // those partials over the Q panels.
+    bool shared = false;
+    qrvie::QtItem* d_qt = nullptr;
+    int64_t n_qt = 0;
+    int64_t p_len = 0;                        // mirror partials per product (complex entries)
     qrvie::MStrip* d_mr = nullptr;            // R, Q and self-block strips for blocks of right-hand sides
     qrvie::MStrip* d_mq = nullptr;
     qrvie::MStrip* d_ms = nullptr;            // offsets into d_self and d_pinv (same layout)
@@ -214,10 +235,11 @@ void op_footprint(const qrvie_geom* g, const qrvie_compress_opts* o, size_t* res
 // fixed scratch array used by qrvie_apply_noalloc; false with a message on failure.
 bool scratch_setup(int device, void** ptr, std::string* err);
 // y = Z_QR x for one caller-order vector on stream s, with caller-provided workspaces: the
-// rank-space vector T (t_len), the level partials Ylev (n_active x n) and two permuted
-// vectors xi, yi (n each).  Launches only.
-void apply_single_into(const qrvie_op* op, hipStream_t s, c128* T, c128* Ylev, c128* xi, c128* yi, const c128* x,
-                       c128* y);
+// rank-space vector T (t_len), the level partials Ylev (n_active x n), for shared factors the
+// rank-space Q^T x Sq (t_len) and the mirror partials P (p_len), and two permuted vectors xi,
+// yi (n each).  Launches only.
+void apply_single_into(const qrvie_op* op, hipStream_t s, c128* T, c128* Ylev, c128* Sq, c128* P, c128* xi, c128* yi,
+                       const c128* x, c128* y);
 
 // ---------------------------------------------------------------- launchers
 // assembly (k_assemble.hip)
@@ -251,6 +273,18 @@ void launch_rphase(hipStream_t s, const RStrip* st, int64_t n, int waves, const 
                    const c128* x, c128* t, const int64_t* tmap);
 void launch_qphase(hipStream_t s, const QStrip* st, int64_t n, int waves, const c128* fac,
                    const c128* t, c128* y);
+// shared factors: s = Q^T x, then t = R x with the mirror partials P (R^T s), then the Q phase
+// (whose strips add the partials)
+void launch_qtphase(hipStream_t s, const QtItem* it, int64_t n, const c128* fac, const c128* x, c128* S);
+void launch_qtphase(hipStream_t s, const QtItem* it, int64_t n, const float2* fac, const c128* x, c128* S);
+void launch_rphase_sh(hipStream_t s, const RStrip* st, int64_t n, const c128* fac, const c128* x, c128* t,
+                      const int64_t* tmap, const c128* S, c128* P);
+void launch_rphase_sh(hipStream_t s, const RStrip* st, int64_t n, const float2* fac, const c128* x, c128* t,
+                      const int64_t* tmap, const c128* S, c128* P);
+void launch_qphase_sh(hipStream_t s, const QStrip* st, int64_t n, const c128* fac, const c128* t, const c128* P,
+                      c128* y);
+void launch_qphase_sh(hipStream_t s, const QStrip* st, int64_t n, const float2* fac, const c128* t, const c128* P,
+                      c128* y);
 void launch_final(hipStream_t s, int32_t N, const int32_t* ptype, const c128* self, const c128* pinv,
                   const c128* x, const c128* ylev, int nlev, int64_t n, const c128* v,
                   c128* out_r, c128* out_z);

@@ -119,6 +119,180 @@ __global__ void __launch_bounds__(64 * WAVES) k_qphase_c64(const QStrip* __restr
     qphase_body<float2, WAVES>(strips[blockIdx.x], fac, t, y);
 }
 
+// ------------------------------------------------------------------ transpose-shared factors
+// One Q (m x r) and R (r x n) per unordered pair (I, J); the mirror block (J, I) = R^T Q^T
+// (symmetric weak form, Z = Z^T).  Three passes per product:
+//  1. s = Q^T x_I for every Q panel column (column dot products: each wave owns 8 columns of a
+//     panel, lanes own rows, one transposed reduction at the end);
+//  2. one pass over every R panel strip computes both t = R x_J (per row, as the plain R
+//     phase) and the strip's share of the mirror product R^T s (per column: each lane's
+//     products are reduced over the wave, 8 columns at a time), written as one row of partials;
+//  3. the Q phase y_I = Q t, whose strips add the partials of their rows in a fixed order.
+// Q is streamed twice and R once, against twice each for stored mirror factors.
+
+__device__ __forceinline__ c128 shfl_xor_c(c128 v, int m) {
+    return make_double2(__shfl_xor(v.x, m, 64), __shfl_xor(v.y, m, 64));
+}
+__device__ __forceinline__ c128 cadd(c128 a, c128 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ c128 cmul(c128 a, c128 b) {
+    return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+
+// Sums of 8 values per lane over the 64 lanes of a wave: every lane L returns the total of
+// v[L >> 3].  Each exchange step halves the values a lane keeps (10 exchanges instead of 48).
+__device__ __forceinline__ c128 transpose_sum8(const c128 v[8], int lane) {
+    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+    c128 w4[4], w2[2];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) w4[u] = cadd(b5 ? v[4 + u] : v[u], shfl_xor_c(b5 ? v[u] : v[4 + u], 32));
+#pragma unroll
+    for (int u = 0; u < 2; ++u) w2[u] = cadd(b4 ? w4[2 + u] : w4[u], shfl_xor_c(b4 ? w4[u] : w4[2 + u], 16));
+    c128 w = cadd(b3 ? w2[1] : w2[0], shfl_xor_c(b3 ? w2[0] : w2[1], 8));
+    w = cadd(w, shfl_xor_c(w, 4));
+    w = cadd(w, shfl_xor_c(w, 2));
+    return cadd(w, shfl_xor_c(w, 1));
+}
+
+__device__ __forceinline__ c128 wave_sum_c(c128 w) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) w = cadd(w, shfl_xor_c(w, o));
+    return w;
+}
+
+// Pass 1: one wave per item (8 columns of a Q panel), four items per workgroup.  Rows past the
+// panel re-read its last row and meet x = 0; columns past ncols re-read the last column and are
+// not stored.  The next 64-row chunk's loads are issued before the current chunk's FMAs.
+template <typename F>
+__global__ void __launch_bounds__(256) k_qtphase(const QtItem* __restrict__ items, int64_t nitems,
+                                                 const F* __restrict__ fac, const c128* __restrict__ x,
+                                                 c128* __restrict__ S) {
+    const int lane = threadIdx.x & 63;
+    const int64_t it = (int64_t)blockIdx.x * 4 + wave_id();
+    if (it >= nitems) return;
+    const QtItem q = items[it];
+    const F* col[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) col[u] = fac + q.a_off + (int64_t)min(u, q.ncols - 1) * q.ld;
+    const int nch = (q.nrows + 63) / 64;
+    const c128* xv = x + q.x_off;
+    c128 acc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] = make_double2(0.0, 0.0);
+    auto load = [&](int ch, F a[8], c128& xr) {
+        const int row = ch * 64 + lane;
+        const int rr = min(row, q.nrows - 1);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = load_stream(col[u] + rr);
+        xr = row < q.nrows ? xv[rr] : make_double2(0.0, 0.0);
+    };
+    auto fmas = [&](const F a[8], c128 xr) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) cfma(acc[u], widen(a[u]), xr);
+    };
+    F a[8], b[8];
+    c128 xa, xb;
+    load(0, a, xa);
+    int ch = 0;
+    for (; ch + 2 < nch; ch += 2) {
+        load(ch + 1, b, xb);
+        __builtin_amdgcn_sched_barrier(0);
+        fmas(a, xa);
+        load(ch + 2, a, xa);
+        __builtin_amdgcn_sched_barrier(0);
+        fmas(b, xb);
+    }
+    if (ch + 1 < nch) {
+        load(ch + 1, b, xb);
+        __builtin_amdgcn_sched_barrier(0);
+        fmas(a, xa);
+        fmas(b, xb);
+    } else {
+        fmas(a, xa);
+    }
+    const c128 tot = transpose_sum8(acc, lane);
+    const int c = lane >> 3;
+    if ((lane & 7) == 0 && c < q.ncols) S[q.t_off + c] = tot;
+}
+
+// Pass 2: a strip of an R panel, four waves splitting its columns in whole batches of U.  Per
+// batch: t += A x (per lane) and, per column, the wave's sum of A s (the strip's partial of the
+// mirror product), reduced 8 columns at a time and stored by lanes 0, 8, ..., 56.
+template <typename F, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES) k_rphase_sh(const RStrip* __restrict__ strips,
+                                                          const F* __restrict__ fac, const c128* __restrict__ x,
+                                                          c128* __restrict__ t, const int64_t* __restrict__ tmap,
+                                                          const c128* __restrict__ S, c128* __restrict__ P) {
+    constexpr int U = Unroll<F>::U;                  // 8 or 16: whole groups of 8 columns
+    const RStrip s = strips[blockIdx.x];
+    const int lane = threadIdx.x & 63, wv = wave_id();
+    const int row = min(lane, s.nrows - 1);
+    const c128 sv = lane < s.nrows ? S[tmap[s.tmap_off + lane]] : make_double2(0.0, 0.0);
+    int j0, j1;
+    wave_columns<U>(s.ncols, WAVES, wv, j0, j1);
+    const F* A = fac + s.a_off + row;
+    const c128* xv = x + s.x_off;
+    c128* pr = P + s.p_off;
+    c128 acc0 = make_double2(0.0, 0.0), acc1 = acc0;
+    const int nb = (j1 - j0) / U;
+    stream_batches<F, U>(A + (int64_t)j0 * s.ld, s.ld, nb, [&](const F* w, int k) {
+        const int jb = j0 + k * U;
+        const c128* vv = xv + jb;
+#pragma unroll
+        for (int h = 0; h < U; h += 8) {
+            c128 q[8];
+#pragma unroll
+            for (int u = 0; u < 8; u += 2) {
+                const c128 a0 = widen(w[h + u]), a1 = widen(w[h + u + 1]);
+                cfma(acc0, a0, vv[h + u]);
+                cfma(acc1, a1, vv[h + u + 1]);
+                q[u] = cmul(a0, sv);
+                q[u + 1] = cmul(a1, sv);
+            }
+            const c128 tot = transpose_sum8(q, lane);
+            if ((lane & 7) == 0) pr[jb + h + (lane >> 3)] = tot;
+        }
+    });
+    for (int j = j0 + nb * U; j < j1; ++j) {          // columns past whole batches (not for 144-wide nodes)
+        const c128 a = widen(A[(int64_t)j * s.ld]);
+        cfma(acc0, a, xv[j]);
+        const c128 tot = wave_sum_c(cmul(a, sv));
+        if (lane == 0) pr[j] = tot;
+    }
+    const c128 acc = make_double2(acc0.x + acc1.x, acc0.y + acc1.y);
+    __shared__ c128 red[WAVES][64];
+    red[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0 && lane < s.nrows) {
+        c128 sum = red[0][lane];
+#pragma unroll
+        for (int w = 1; w < WAVES; ++w) sum = cadd(sum, red[w][lane]);
+        t[tmap[s.tmap_off + lane]] = sum;
+    }
+}
+
+// Pass 3: the Q phase with the mirror partials of the strip's rows added in a fixed order.
+template <typename F, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES) k_qphase_sh(const QStrip* __restrict__ strips,
+                                                          const F* __restrict__ fac, const c128* __restrict__ t,
+                                                          const c128* __restrict__ P, c128* __restrict__ y) {
+    const QStrip s = strips[blockIdx.x];
+    const int lane = threadIdx.x & 63, wv = wave_id();
+    const int row = min(lane, max(s.nrows - 1, 0));
+    int j0, j1;
+    wave_columns<Unroll<F>::U>(s.ncols, WAVES, wv, j0, j1);
+    const c128 acc = column_stream<F>(fac + s.a_off + row, s.ld, t + s.t_off, j0, j1);
+    __shared__ c128 red[WAVES][64];
+    red[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0 && lane < s.nrows) {
+        c128 sum = red[0][lane];
+#pragma unroll
+        for (int w = 1; w < WAVES; ++w) sum = cadd(sum, red[w][lane]);
+        for (int k = 0; k < s.p_cnt; ++k) sum = cadd(sum, P[s.p_off + (int64_t)k * s.p_ld + lane]);
+        y[s.y_off + lane] = sum;
+    }
+}
+
 // 576 threads per particle: thread -> (row = tid % 144, column group = tid / 144).
 constexpr int kGroups = 4;
 constexpr int kColsPerGroup = kNp / kGroups;
@@ -488,6 +662,31 @@ void launch_qphase(hipStream_t s, const QStrip* st, int64_t n, int waves, const 
         case 8: hipLaunchKernelGGL(k_qphase<8>, g, dim3(512), 0, s, st, fac, t, y); break;
         default: hipLaunchKernelGGL(k_qphase<16>, g, dim3(1024), 0, s, st, fac, t, y); break;
     }
+}
+
+void launch_qtphase(hipStream_t s, const QtItem* it, int64_t n, const c128* fac, const c128* x, c128* S) {
+    if (n > 0) hipLaunchKernelGGL(k_qtphase<c128>, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, it, n, fac, x, S);
+}
+void launch_qtphase(hipStream_t s, const QtItem* it, int64_t n, const float2* fac, const c128* x, c128* S) {
+    if (n > 0) hipLaunchKernelGGL(k_qtphase<float2>, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, it, n, fac, x, S);
+}
+void launch_rphase_sh(hipStream_t s, const RStrip* st, int64_t n, const c128* fac, const c128* x, c128* t,
+                      const int64_t* tmap, const c128* S, c128* P) {
+    if (n > 0)
+        hipLaunchKernelGGL((k_rphase_sh<c128, 4>), dim3((unsigned)n), dim3(256), 0, s, st, fac, x, t, tmap, S, P);
+}
+void launch_rphase_sh(hipStream_t s, const RStrip* st, int64_t n, const float2* fac, const c128* x, c128* t,
+                      const int64_t* tmap, const c128* S, c128* P) {
+    if (n > 0)
+        hipLaunchKernelGGL((k_rphase_sh<float2, 4>), dim3((unsigned)n), dim3(256), 0, s, st, fac, x, t, tmap, S, P);
+}
+void launch_qphase_sh(hipStream_t s, const QStrip* st, int64_t n, const c128* fac, const c128* t, const c128* P,
+                      c128* y) {
+    if (n > 0) hipLaunchKernelGGL((k_qphase_sh<c128, 4>), dim3((unsigned)n), dim3(256), 0, s, st, fac, t, P, y);
+}
+void launch_qphase_sh(hipStream_t s, const QStrip* st, int64_t n, const float2* fac, const c128* t, const c128* P,
+                      c128* y) {
+    if (n > 0) hipLaunchKernelGGL((k_qphase_sh<float2, 4>), dim3((unsigned)n), dim3(256), 0, s, st, fac, t, P, y);
 }
 
 void launch_final(hipStream_t s, int32_t N, const int32_t* ptype, const c128* self, const c128* pinv, const c128* x,

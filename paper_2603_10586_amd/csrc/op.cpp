@@ -552,6 +552,7 @@ void op_footprint(const qrvie_geom* g, const qrvie_compress_opts* o, size_t* res
     for (const BlockRec& b : blocks) {
         const double m = (double)b.rn * kNp, n = (double)b.cn * kNp;
         const double r = std::min(rank_model(std::max(m, n), o->eps), std::min(m, n));
+        if (!b.primary && o->share_transpose) continue;   // shared: the pair's factors are stored once
         fac += (m + n) * r;
         tlen += r;
         rpanels[{b.level, b.c0}] = b.cn;
@@ -606,7 +607,7 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
     if (!(o->eps > 0.0) || !(o->eps < 1.0)) { set_err(ctx, "op_create: eps must be in (0, 1)"); return QRVIE_ERR_INVALID_ARG; }
     if ((o->far_prec != QRVIE_PREC_C128 && o->far_prec != QRVIE_PREC_C64 && o->far_prec != QRVIE_PREC_C64_ONLY) ||
         o->near_prec != QRVIE_PREC_C128 ||
-        o->share_transpose != 0 ||
+        (o->share_transpose != 0 && o->share_transpose != 1) ||
         o->max_block_rows < 0 || o->chunk_bytes < 0) {
         set_err(ctx, "op_create: unsupported precision or option");
         return QRVIE_ERR_INVALID_ARG;
@@ -729,7 +730,12 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
         op->relerr[i] = f.rel_err;
     }
 
-    // panel layout
+    // panel layout.  With shared factors only the compressed block of each pair (its primary)
+    // enters the panels: its Q in the row node's Q panel, its R in the column node's R panel;
+    // the mirror (J, I) is applied through the same panels transposed.
+    const bool sh = o->share_transpose != 0;
+    op->shared = sh;
+    auto stored = [&](size_t b) { return !sh || bld.blocks[b].primary; };
     const int64_t n = g->ndof();
     std::vector<int> active(g->L + 2, -1);
     for (const auto& b : bld.blocks) active[b.level] = 1;
@@ -743,13 +749,14 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
     std::vector<int64_t> toff(NB, 0);
     std::vector<RStrip> rstr;
     std::vector<QStrip> qstr;
+    std::vector<QtItem> qts;
     std::vector<int64_t> tmap;
-    int64_t fcur = 0, tcur = 0;
+    int64_t fcur = 0, tcur = 0, pcur = 0;
     for (int l = 0; l <= g->L; ++l) {
         if (active[l] < 0) continue;
         // Q panels over every occupied node of the level
         int64_t qbegin = (int64_t)qstr.size();
-        int maxK = 0;
+        std::map<int32_t, std::vector<std::pair<size_t, int64_t>>> qstrips_of;   // node first -> (strip, row)
         size_t bi = 0;
         while (bi < NB && bld.blocks[bi].level != l) ++bi;
         for (int32_t I : g->level_nodes[l]) {
@@ -759,28 +766,35 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
             while (b0 < NB && bld.blocks[b0].level == l && bld.blocks[b0].r0 < nd.first) ++b0;
             size_t b1 = b0;
             int64_t K = 0;
-            while (b1 < NB && bld.blocks[b1].level == l && bld.blocks[b1].r0 == nd.first) { K += op->rank[b1]; ++b1; }
+            while (b1 < NB && bld.blocks[b1].level == l && bld.blocks[b1].r0 == nd.first) {
+                if (stored(b1)) K += op->rank[b1];
+                ++b1;
+            }
             const int64_t base = fcur;
             fcur += mI * K;
             int64_t col = 0;
             for (size_t b = b0; b < b1; ++b) {
+                if (!stored(b)) continue;
                 op->q_off[b] = base + mI * col;
                 toff[b] = tcur + col;
                 col += op->rank[b];
             }
-            for (int64_t r0 = 0; r0 < mI; r0 += kStrip)
+            for (int64_t r0 = 0; r0 < mI; r0 += kStrip) {
+                qstrips_of[nd.first].push_back({qstr.size(), r0});
                 qstr.push_back(QStrip{base + r0, (int32_t)mI, (int32_t)K, (int32_t)std::min<int64_t>(kStrip, mI - r0),
-                                      (int64_t)active[l] * n + (int64_t)nd.first * kNp + r0, tcur});
+                                      (int64_t)active[l] * n + (int64_t)nd.first * kNp + r0, tcur, -1, 0, 0});
+            }
+            if (sh)
+                for (int64_t c0 = 0; c0 < K; c0 += 8)
+                    qts.push_back(QtItem{base + mI * c0, (int32_t)mI, (int32_t)mI, (int32_t)std::min<int64_t>(8, K - c0),
+                                         nd.first * kNp, tcur + c0});
             tcur += K;
-            maxK = std::max<int>(maxK, (int)K);
             bi = b1;
         }
         // R panels per column node
         std::map<int32_t, std::vector<size_t>> bycol;
-        int maxN = 0;
         for (size_t b = 0; b < NB; ++b)
-            if (bld.blocks[b].level == l) bycol[bld.blocks[b].c0].push_back(b);
-        int64_t rbegin = (int64_t)rstr.size();
+            if (bld.blocks[b].level == l && stored(b)) bycol[bld.blocks[b].c0].push_back(b);
         for (auto& kv : bycol) {
             const BlockRec& b0 = bld.blocks[kv.second.front()];
             const int64_t nJ = (int64_t)b0.cn * kNp;
@@ -800,18 +814,22 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
                 for (int k = 0; k < op->rank[b]; ++k) tmap.push_back(toff[b] + k);
                 row += op->rank[b];
             }
+            const int64_t nstrip = (Kp + kStrip - 1) / kStrip;
             for (int64_t r0 = 0; r0 < Kp; r0 += kStrip)
                 rstr.push_back(RStrip{base + r0, (int32_t)ldp, (int32_t)nJ, (int32_t)std::min<int64_t>(kStrip, Kp - r0),
-                                      b0.c0 * kNp, tbase + r0});
-            maxN = std::max<int>(maxN, (int)nJ);
+                                      b0.c0 * kNp, tbase + r0, sh ? pcur + (r0 / kStrip) * nJ : -1});
+            if (sh && nstrip > 0) {
+                // the column node's rows at this level also receive the mirror partials
+                for (const auto& sr : qstrips_of.at(b0.c0)) {
+                    QStrip& q = qstr[sr.first];
+                    q.p_off = pcur + sr.second;
+                    q.p_cnt = (int32_t)nstrip;
+                    q.p_ld = (int32_t)nJ;
+                }
+                pcur += nstrip * nJ;
+            }
         }
-        auto waves_for = [](int cols, int per) {
-            int w = 1;
-            while (w < 16 && w * per < cols) w *= 2;
-            return w;
-        };
-        op->qlaunch.push_back({l, qbegin, (int64_t)qstr.size() - qbegin, waves_for(maxK, 384)});
-        op->rlaunch.push_back({l, rbegin, (int64_t)rstr.size() - rbegin, waves_for(maxN, 512)});
+        (void)qbegin;
     }
     // One launch per phase over all levels: four waves per strip split its columns, and the
     // strips are issued longest first so the long coarse-level strips overlap the many
@@ -824,14 +842,18 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
     op->fac_elems = fcur;
     op->t_len = tcur;
     op->tmap_len = (int64_t)tmap.size();
+    op->p_len = pcur;
+    op->n_qt = (int64_t)qts.size();
 
     // The same strips for blocks of right-hand sides, plus three strips per particle over
     // its self block (and, with the same offsets, its inverse).
     std::vector<MStrip> mr, mq, ms;
     mr.reserve(rstr.size());
     mq.reserve(qstr.size());
-    for (const RStrip& r : rstr) mr.push_back(MStrip{r.a_off, r.ld, r.ncols, r.nrows, 0, r.x_off, 0, r.tmap_off});
-    for (const QStrip& q : qstr) mq.push_back(MStrip{q.a_off, q.ld, q.ncols, q.nrows, 0, q.t_off, q.y_off, -1});
+    if (!sh) {   // the block products stream stored factors of every ordered block
+        for (const RStrip& r : rstr) mr.push_back(MStrip{r.a_off, r.ld, r.ncols, r.nrows, 0, r.x_off, 0, r.tmap_off});
+        for (const QStrip& q : qstr) mq.push_back(MStrip{q.a_off, q.ld, q.ncols, q.nrows, 0, q.t_off, q.y_off, -1});
+    }
     for (int32_t p = 0; p < g->N; ++p)
         for (int r0 = 0; r0 < kNp; r0 += kStrip)
             ms.push_back(MStrip{(int64_t)g->ptype[p] * kNp * kNp + r0, kNp, kNp, std::min(kStrip, kNp - r0), 0,
@@ -849,6 +871,7 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
     keep((void**)&op->d_tmap, sizeof(int64_t) * std::max<size_t>(tmap.size(), 1), "rank map");
     keep((void**)&op->d_rstrips, sizeof(RStrip) * std::max<size_t>(rstr.size(), 1), "R strips");
     keep((void**)&op->d_qstrips, sizeof(QStrip) * std::max<size_t>(qstr.size(), 1), "Q strips");
+    if (sh) keep((void**)&op->d_qt, sizeof(QtItem) * std::max<size_t>(qts.size(), 1), "Q^T items");
     if (st != QRVIE_OK) {
         for (auto& sg : bld.segments) dfree(ctx, sg.first, sg.second);
         return fail(st);
@@ -856,6 +879,7 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
     if (!tmap.empty()) (void)hipMemcpyAsync(op->d_tmap, tmap.data(), sizeof(int64_t) * tmap.size(), hipMemcpyHostToDevice, s);
     if (!rstr.empty()) (void)hipMemcpyAsync(op->d_rstrips, rstr.data(), sizeof(RStrip) * rstr.size(), hipMemcpyHostToDevice, s);
     if (!qstr.empty()) (void)hipMemcpyAsync(op->d_qstrips, qstr.data(), sizeof(QStrip) * qstr.size(), hipMemcpyHostToDevice, s);
+    if (sh && !qts.empty()) (void)hipMemcpyAsync(op->d_qt, qts.data(), sizeof(QtItem) * qts.size(), hipMemcpyHostToDevice, s);
     if (st == QRVIE_OK && !mr.empty()) (void)hipMemcpyAsync(op->d_mr, mr.data(), sizeof(MStrip) * mr.size(), hipMemcpyHostToDevice, s);
     if (st == QRVIE_OK && !mq.empty()) (void)hipMemcpyAsync(op->d_mq, mq.data(), sizeof(MStrip) * mq.size(), hipMemcpyHostToDevice, s);
     if (st == QRVIE_OK && !ms.empty()) (void)hipMemcpyAsync(op->d_ms, ms.data(), sizeof(MStrip) * ms.size(), hipMemcpyHostToDevice, s);
@@ -885,6 +909,7 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
             };
             pd.push_back(with(at(op->q_off[i], mm, 0), f.Q, mm, r, mm));            // Q_IJ
             pd.push_back(with(at(op->r_off[i], op->r_ld[i], 0), f.R, r, nn, r));    // R_IJ
+            if (sh) continue;                                                       // mirrors read these
             pd.push_back(with(at(op->q_off[j], nn, 1), f.R, r, nn, r));             // Q_JI = R_IJ^T
             pd.push_back(with(at(op->r_off[j], op->r_ld[j], 1), f.Q, mm, r, mm));   // R_JI = Q_IJ^T
         }
@@ -941,11 +966,18 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
     S.n_qr_entries = nqr;
     S.gain = (double)n * (double)n / (double)nqr;
     S.max_block_rel_err = maxerr;
-    S.apply_bytes = (int64_t)sizeof(c128) * ((nqr - (int64_t)g->N * kNp * kNp) + (int64_t)op->ntypes * kNp * kNp +
-                                             2 * n + 2 * sum_r);
-    S.apply_bytes_c64 = op->d_fac32 ? (int64_t)sizeof(float2) * (nqr - (int64_t)g->N * kNp * kNp) +
-                                          (int64_t)sizeof(c128) * ((int64_t)op->ntypes * kNp * kNp + 2 * n + 2 * sum_r)
-                                    : 0;
+    // factor entries one product streams: every ordered block's Q and R, or with shared factors
+    // each pair's Q twice (Q^T x, then Q t) and its R once (R x and R^T s in one pass)
+    int64_t streamed = 0;
+    for (size_t i = 0; i < NB; ++i) {
+        const BlockRec& b = bld.blocks[i];
+        const int64_t r = op->rank[i], m = (int64_t)b.rn * kNp, nn = (int64_t)b.cn * kNp;
+        if (!sh) streamed += (m + nn) * r;
+        else if (b.primary) streamed += (2 * m + nn) * r;
+    }
+    const int64_t vec = (int64_t)op->ntypes * kNp * kNp + 2 * n + 2 * sum_r;
+    S.apply_bytes = (int64_t)sizeof(c128) * (streamed + vec);
+    S.apply_bytes_c64 = op->d_fac32 ? (int64_t)sizeof(float2) * streamed + (int64_t)sizeof(c128) * vec : 0;
     for (auto& a : op->allocs) op->dev_bytes += a.second;
     S.device_bytes = (int64_t)op->dev_bytes;
     S.t_assembly_s = 0.0;  // assembly is fused into compression; see t_compression_s

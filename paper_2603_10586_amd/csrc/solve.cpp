@@ -32,8 +32,14 @@ constexpr int kGroup = 8;   // right-hand sides advanced together
 struct ProdWork {
     c128* T = nullptr;
     c128* Y = nullptr;
+    c128* S = nullptr;            // shared factors: Q^T x (rank space) and the mirror partials
+    c128* P = nullptr;
     qrvie_status init(Work& w, const qrvie_op* op, int nr) {
         CHECK(w.alloc(&T, (size_t)op->t_len * nr, "rank-space vector"));
+        if (op->shared) {
+            CHECK(w.alloc(&S, (size_t)op->t_len, "rank-space Q^T x"));
+            CHECK(w.alloc(&P, (size_t)op->p_len, "mirror partials"));
+        }
         return w.alloc(&Y, (size_t)std::max(op->n_active, 1) * op->g->ndof() * nr, "level partials");
     }
 };
@@ -45,6 +51,20 @@ int round_nr(int na) { return na <= 2 ? 2 : (na <= 4 ? 4 : 8); }
 void apply_one(const qrvie_op* op, hipStream_t s, const ProdWork& pw, const c128* x, const c128* v, c128* out_r,
                c128* out_z, bool lo = false) {
     const qrvie_geom* g = op->g;
+    if (op->shared) {
+        if (lo) {
+            launch_qtphase(s, op->d_qt, op->n_qt, op->d_fac32, x, pw.S);
+            launch_rphase_sh(s, op->d_rstrips, op->rlaunch[0].count, op->d_fac32, x, pw.T, op->d_tmap, pw.S, pw.P);
+            launch_qphase_sh(s, op->d_qstrips, op->qlaunch[0].count, op->d_fac32, pw.T, pw.P, pw.Y);
+        } else {
+            launch_qtphase(s, op->d_qt, op->n_qt, op->d_fac, x, pw.S);
+            launch_rphase_sh(s, op->d_rstrips, op->rlaunch[0].count, op->d_fac, x, pw.T, op->d_tmap, pw.S, pw.P);
+            launch_qphase_sh(s, op->d_qstrips, op->qlaunch[0].count, op->d_fac, pw.T, pw.P, pw.Y);
+        }
+        launch_final(s, g->N, g->d_ptype, op->d_self, out_z ? op->d_pinv : nullptr, x, pw.Y, op->n_active, g->ndof(),
+                     v, out_r, out_z);
+        return;
+    }
     for (const auto& L : op->rlaunch) {
         if (lo) launch_rphase_c64(s, op->d_rstrips + L.begin, L.count, op->d_fac32, x, pw.T, op->d_tmap);
         else launch_rphase(s, op->d_rstrips + L.begin, L.count, L.waves, op->d_fac, x, pw.T, op->d_tmap);
@@ -293,9 +313,9 @@ struct Group {
             if (act.empty()) return QRVIE_OK;
             // one product + preconditioner for every active column
             (void)hipEventRecord(ev0, s);
-            if (act.size() == 1) {
-                Col& k = c[act[0]];
-                apply_one(op, s, pw, k.V + (size_t)k.j * n, nullptr, nullptr, k.w, lo);
+            if (act.size() == 1 || op->shared) {
+                // one column, or shared factors (no multi-vector kernels): a product per column
+                for (int i : act) apply_one(op, s, pw, c[i].V + (size_t)c[i].j * n, nullptr, nullptr, c[i].w, lo);
             } else {
                 const int nr = round_nr((int)act.size());
                 for (size_t a = 0; a < act.size(); ++a) hcols[a] = c[act[a]].V + (size_t)c[act[a]].j * n;
@@ -568,11 +588,13 @@ qrvie_status solve_block_ir(qrvie_ctx* ctx, const qrvie_op* op, int nrhs, const 
 
 namespace qrvie {
 
-void apply_single_into(const qrvie_op* op, hipStream_t s, c128* T, c128* Ylev, c128* xi, c128* yi, const c128* x,
-                       c128* y) {
+void apply_single_into(const qrvie_op* op, hipStream_t s, c128* T, c128* Ylev, c128* Sq, c128* P, c128* xi, c128* yi,
+                       const c128* x, c128* y) {
     ProdWork pw;
     pw.T = T;
     pw.Y = Ylev;
+    pw.S = Sq;
+    pw.P = P;
     launch_permute(s, op->g->N, op->g->d_i2c, x, xi, 1);
     apply_one(op, s, pw, xi, nullptr, yi, nullptr, !op->d_fac);
     launch_permute(s, op->g->N, op->g->d_i2c, yi, y, 0);
@@ -598,7 +620,7 @@ qrvie_status qrvie_apply_prec(qrvie_ctx* ctx, const qrvie_op* op, int32_t prec, 
     const int64_t n = op->g->ndof();
     hipStream_t s = ctx->stream;
     Work w(ctx);
-    if (nrhs >= 16) {
+    if (nrhs >= 16 && !op->shared) {
         // blocks of up to 64 right-hand sides on the MFMA kernels
         BlockWork bw;
         CHECK(bw.init(w, op));
@@ -616,12 +638,19 @@ qrvie_status qrvie_apply_prec(qrvie_ctx* ctx, const qrvie_op* op, int32_t prec, 
         return hip_check(ctx, hipStreamSynchronize(s), "apply");
     }
     ProdWork pw;
-    const int nrmax = nrhs > 1 ? kGroup : 1;
+    const int nrmax = nrhs > 1 && !op->shared ? kGroup : 1;
     CHECK(pw.init(w, op, nrmax));
     c128 *xi, *yi, *X = nullptr, *Y = nullptr;
     CHECK(w.alloc(&xi, (size_t)n * nrmax, "apply work"));
     CHECK(w.alloc(&yi, (size_t)n * nrmax, "apply work"));
-    if (nrhs == 1) {
+    if (op->shared) {
+        // shared factors: one three-pass product per column
+        for (int r0 = 0; r0 < nrhs; ++r0) {
+            launch_permute(s, op->g->N, op->g->d_i2c, (const c128*)x + r0 * ldx, xi, 1);
+            apply_one(op, s, pw, xi, nullptr, yi, nullptr, lo);
+            launch_permute(s, op->g->N, op->g->d_i2c, yi, (c128*)y + r0 * ldy, 0);
+        }
+    } else if (nrhs == 1) {
         launch_permute(s, op->g->N, op->g->d_i2c, (const c128*)x, xi, 1);
         apply_one(op, s, pw, xi, nullptr, yi, nullptr, lo);
         launch_permute(s, op->g->N, op->g->d_i2c, yi, (c128*)y, 0);
@@ -676,52 +705,85 @@ qrvie_status qrvie_op_profile_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t 
     CHECK(w.alloc(&xi, n, "profile x"));
     CHECK(w.alloc(&yi, n, "profile y"));
     CHECK(hip_check(ctx, hipMemsetAsync(xi, 0, sizeof(c128) * n, s), "profile x"));
-    hipEvent_t ev[4];
+    hipEvent_t ev[5];
     for (auto& e : ev) (void)hipEventCreate(&e);
-    double acc[4] = {0, 0, 0, 0};
+    double acc[5] = {0, 0, 0, 0, 0};
     for (int r = 0; r < reps; ++r) {
         (void)hipEventRecord(ev[0], s);
-        for (const auto& L : op->rlaunch) {
-            if (lo) launch_rphase_c64(s, op->d_rstrips + L.begin, L.count, op->d_fac32, xi, pw.T, op->d_tmap);
-            else launch_rphase(s, op->d_rstrips + L.begin, L.count, L.waves, op->d_fac, xi, pw.T, op->d_tmap);
+        if (op->shared) {
+            if (lo) launch_qtphase(s, op->d_qt, op->n_qt, op->d_fac32, xi, pw.S);
+            else launch_qtphase(s, op->d_qt, op->n_qt, op->d_fac, xi, pw.S);
         }
         (void)hipEventRecord(ev[1], s);
-        for (const auto& L : op->qlaunch) {
-            if (lo) launch_qphase_c64(s, op->d_qstrips + L.begin, L.count, op->d_fac32, pw.T, pw.Y);
-            else launch_qphase(s, op->d_qstrips + L.begin, L.count, L.waves, op->d_fac, pw.T, pw.Y);
+        for (const auto& L : op->rlaunch) {
+            if (op->shared) {
+                if (lo) launch_rphase_sh(s, op->d_rstrips, L.count, op->d_fac32, xi, pw.T, op->d_tmap, pw.S, pw.P);
+                else launch_rphase_sh(s, op->d_rstrips, L.count, op->d_fac, xi, pw.T, op->d_tmap, pw.S, pw.P);
+            } else if (lo) {
+                launch_rphase_c64(s, op->d_rstrips + L.begin, L.count, op->d_fac32, xi, pw.T, op->d_tmap);
+            } else {
+                launch_rphase(s, op->d_rstrips + L.begin, L.count, L.waves, op->d_fac, xi, pw.T, op->d_tmap);
+            }
         }
         (void)hipEventRecord(ev[2], s);
-        launch_final(s, g->N, g->d_ptype, op->d_self, nullptr, xi, pw.Y, op->n_active, n, nullptr, yi, nullptr);
+        for (const auto& L : op->qlaunch) {
+            if (op->shared) {
+                if (lo) launch_qphase_sh(s, op->d_qstrips, L.count, op->d_fac32, pw.T, pw.P, pw.Y);
+                else launch_qphase_sh(s, op->d_qstrips, L.count, op->d_fac, pw.T, pw.P, pw.Y);
+            } else if (lo) {
+                launch_qphase_c64(s, op->d_qstrips + L.begin, L.count, op->d_fac32, pw.T, pw.Y);
+            } else {
+                launch_qphase(s, op->d_qstrips + L.begin, L.count, L.waves, op->d_fac, pw.T, pw.Y);
+            }
+        }
         (void)hipEventRecord(ev[3], s);
-        CHECK(hip_check(ctx, hipEventSynchronize(ev[3]), "profile"));
+        launch_final(s, g->N, g->d_ptype, op->d_self, nullptr, xi, pw.Y, op->n_active, n, nullptr, yi, nullptr);
+        (void)hipEventRecord(ev[4], s);
+        CHECK(hip_check(ctx, hipEventSynchronize(ev[4]), "profile"));
         float t = 0.f;
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < 4; ++k) {
             (void)hipEventElapsedTime(&t, ev[k], ev[k + 1]);
             acc[k] += t;
         }
-        (void)hipEventElapsedTime(&t, ev[0], ev[3]);
-        acc[3] += t;
+        (void)hipEventElapsedTime(&t, ev[0], ev[4]);
+        acc[4] += t;
     }
     for (auto& e : ev) (void)hipEventDestroy(e);
-    for (int k = 0; k < 4; ++k) ms[k] = acc[k] / reps;
+    // ms / bytes: [0] R pass, [1] Q pass, [2] final, [3] whole product, [4] Q^T pass (shared), [5] 0
+    ms[0] = acc[1] / reps;
+    ms[1] = acc[2] / reps;
+    ms[2] = acc[3] / reps;
+    ms[3] = acc[4] / reps;
+    ms[4] = acc[0] / reps;
+    ms[5] = 0.0;
     int64_t rn = 0, mr = 0, sr = 0;
     for (size_t b = 0; b < op->blocks.size(); ++b) {
+        if (op->shared && !op->blocks[b].primary) continue;
         const int64_t r = op->rank[b];
         rn += r * op->blocks[b].cn * (int64_t)kNp;
         mr += r * op->blocks[b].rn * (int64_t)kNp;
         sr += r;
     }
     const int64_t cb = (int64_t)sizeof(c128), fb = lo ? (int64_t)sizeof(float2) : cb;
-    bytes[0] = fb * rn + cb * (sr + n);
-    bytes[1] = fb * mr + cb * sr;
+    if (op->shared) {
+        bytes[4] = fb * mr + cb * (n + sr);            // Q, x; writes s
+        bytes[0] = fb * rn + cb * 2 * sr;              // R; reads s, writes t (x counted once, by pass 1)
+        bytes[1] = fb * mr + cb * sr;                  // Q, t
+    } else {
+        bytes[4] = 0;
+        bytes[0] = fb * rn + cb * (sr + n);
+        bytes[1] = fb * mr + cb * sr;
+    }
     bytes[2] = cb * ((int64_t)op->ntypes * kNp * kNp + n);
-    bytes[3] = bytes[0] + bytes[1] + bytes[2];
+    bytes[3] = bytes[0] + bytes[1] + bytes[2] + bytes[4];
+    bytes[5] = 0;
     return hip_check(ctx, hipGetLastError(), "profile");
 }
 
 qrvie_status qrvie_op_profile_block(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, int32_t reps, double* ms,
                                     int64_t* flops) {
-    if (!ctx || !op || reps < 1 || nrhs < 1 || nrhs > kMaxBlockRhs || !ms || !flops) return QRVIE_ERR_INVALID_ARG;
+    if (!ctx || !op || reps < 1 || nrhs < 1 || nrhs > kMaxBlockRhs || !ms || !flops || op->shared)
+        return QRVIE_ERR_INVALID_ARG;
     return profile_block(ctx, op, nrhs, reps, ms, flops);
 }
 
@@ -795,6 +857,10 @@ qrvie_status qrvie_op_tune_block(qrvie_ctx* ctx, qrvie_op* op, int32_t prec, int
         set_err(ctx, "qrvie_op_tune_block: the operator holds no complex64 panels");
         return QRVIE_ERR_INVALID_ARG;
     }
+    if (op->shared) {
+        set_err(ctx, "qrvie_op_tune_block: the block products need an operator built without share_transpose");
+        return QRVIE_ERR_INVALID_ARG;
+    }
     return tune_block(ctx, op, prec, nrhs, reps, out);
 }
 
@@ -830,6 +896,18 @@ qrvie_status qrvie_op_export_block(const qrvie_op* op, int64_t b, qrvie_block_in
         info->row_first = e.r0; info->row_count = e.rn;
         info->col_first = e.c0; info->col_count = e.cn;
         info->rel_err = op->relerr[b];
+    }
+    if (op->shared && !e.primary && (Q || R) && r > 0) {
+        // shared factors: the mirror's Q is the compressed block's R^T and its R that block's Q^T
+        std::vector<qrvie_c128> pq((size_t)n * r), pr((size_t)r * m);
+        CHECK(qrvie_op_export_block(op, e.mirror, nullptr, pq.data(), pr.data()));
+        if (Q)
+            for (int64_t i = 0; i < m; ++i)
+                for (int k = 0; k < r; ++k) Q[i + (int64_t)k * m] = pr[k + i * r];
+        if (R)
+            for (int64_t j = 0; j < n; ++j)
+                for (int k = 0; k < r; ++k) R[k + j * r] = pq[j + (int64_t)k * n];
+        return QRVIE_OK;
     }
     if (!op->d_fac && (Q || R) && r > 0) {
         // complex64 panels: copy down, widen on the host
@@ -914,6 +992,10 @@ qrvie_status qrvie_solve(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const
     }
     if ((o->mode == QRVIE_SOLVE_MIXED_IR || o->mode == QRVIE_SOLVE_BLOCK_IR) && !(op->d_fac32 && op->d_fac)) {
         set_err(ctx, "solve: mixed-precision refinement needs an operator built with far_prec = QRVIE_PREC_C64");
+        return QRVIE_ERR_INVALID_ARG;
+    }
+    if ((o->mode == QRVIE_SOLVE_BLOCK || o->mode == QRVIE_SOLVE_BLOCK_IR) && op->shared) {
+        set_err(ctx, "solve: the block modes need an operator built without share_transpose");
         return QRVIE_ERR_INVALID_ARG;
     }
     if (o->mode == QRVIE_SOLVE_BLOCK_IR) return solve_block_ir(ctx, op, nrhs, (const c128*)v, ldv, (c128*)x, ldx, o, info);

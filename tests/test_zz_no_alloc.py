@@ -17,10 +17,10 @@ import workloads as W
 pytestmark = pytest.mark.gpu
 
 
-def _setup(arr, c, cap=0):
+def _setup(arr, c, cap=0, shared=False):
     import paper_2603_10586_amd as q
     geom = q.Geometry(c, arr)
-    op = q.Operator(c, geom, eps=1e-6, max_block_rows=cap)
+    op = q.Operator(c, geom, eps=1e-6, max_block_rows=cap, share_transpose=shared)
     return geom, op
 
 
@@ -34,9 +34,10 @@ def test_noalloc_product_equals_the_allocating_product_twice_in_a_row():
     import paper_2603_10586_amd as q
     c = q.Context(0)
     cases = []
-    # the mid-size workload (32 x 32), then two smaller arrays
-    for arr, seed in ((W.mid(0), 0), (W.random_lattice(8, 8, seed=2), 1), (W.random_lattice(5, 3, seed=11), 2)):
-        geom, op = _setup(arr, c)
+    # the mid-size workload (32 x 32), then smaller arrays, one with transpose-shared factors
+    for arr, seed, sh in ((W.mid(0), 0, False), (W.random_lattice(8, 8, seed=2), 1, True),
+                          (W.random_lattice(5, 3, seed=11), 2, False)):
+        geom, op = _setup(arr, c, shared=sh)
         rng = np.random.default_rng(seed)
         xh = rng.standard_normal(geom.ndof) + 1j * rng.standard_normal(geom.ndof)
         cases.append((geom, op, torch.from_numpy(xh).to("cuda")))
