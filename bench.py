@@ -7,16 +7,19 @@ tolerance 1e-6, one TM plane wave at 10 degrees, left-preconditioned GMRES to a
 true relative residual of 1e-6, complex128 throughout.
 
 GMRES(50) stagnates on this strongly coupled array (the true residual stalls near
-1e-1), so the solver runs unrestarted (the paper's setting, §6) with at most 5000
-iterations.  A step is one full solve on the resident compressed operator (inputs in HBM when
-the timed region starts).  The operator build (assembly + compression +
-preconditioner factorisation) runs once before the timed region; its time is
-reported as setup_s.
+1e-1; the line's forms.gmres50 leg measures it), so the solver runs unrestarted (the
+paper's setting, §6) with at most 5000 iterations.  The far factors are stored once per pair
+(transpose sharing, Z = Z^T), so each product streams a pair's Q twice and its R once.  A
+step is one full solve on the resident compressed operator (inputs in HBM when the timed
+region starts).  The operator build (assembly + compression + preconditioner
+factorisation) runs once before the timed region; its time is reported as setup_s.
 
-Reported: value = compressed-matvec HBM GB/s (algorithmic bytes of every product
-executed in the timed solves over their device time, HIP events on the library
-stream), solves/s and p50/p99 solve latency, the roofline of the dominant product
-kernel, and the FP64 oracle's compressed product on the host cores.
+Reported: value = compressed-matvec HBM GB/s (algorithmic bytes of every product executed
+in the timed solves, the self-block inverse of the fused preconditioner included, over
+their device time, HIP events on the library stream), solves/s, the roofline of the
+dominant product kernel, the other forms on the same array (block GMRES over 64 waves,
+mixed-precision refinement, GMRES(50)), a bounded serving stream whose arrival-to-result
+p50/p99 are the line's latencies, and the FP64 oracle's compressed product on the host cores.
 """
 from __future__ import annotations
 
@@ -48,24 +51,35 @@ def cpu_model() -> str:
     return platform.processor()
 
 
+# product kernels by stage, as rocprofv3 names them: per-block storage, and shared factors
 KERNEL_SYMBOL = {"rphase": "k_rphase<4>", "qphase": "k_qphase<4>", "final": "k_final"}
 KERNEL_SYMBOL_C64 = {"rphase": "k_rphase_c64<4>", "qphase": "k_qphase_c64<4>", "final": "k_final"}
-COUNTERS = os.path.join(ROOT, "profiles", "product_mid32x32_counters.txt")
+KERNEL_SYMBOL_SH = {"qtphase": "k_qtphase<HIP_vector_type<double, 2u> >",
+                    "rphase": "k_rphase_sh<HIP_vector_type<double, 2u>, 4>",
+                    "qphase": "k_qphase_sh<HIP_vector_type<double, 2u>, 4>", "final": "k_final"}
+KERNEL_SYMBOL_SH_C64 = {"qtphase": "k_qtphase<HIP_vector_type<float, 2u> >",
+                        "rphase": "k_rphase_sh<HIP_vector_type<float, 2u>, 4>",
+                        "qphase": "k_qphase_sh<HIP_vector_type<float, 2u>, 4>", "final": "k_final"}
+COUNTERS = os.path.join(ROOT, "profiles", "product_shared_mid32x32_counters.txt")
 PRODUCT_SOURCES = [os.path.join(ROOT, "paper_2603_10586_amd", "csrc", f) for f in ("k_apply.hip", "stream.h", "op.cpp")]
 
 
-def measured_traffic(stage: str, suffix: str = ""):
-    """HBM bytes per dispatch of a product kernel from the committed rocprofv3 counter
-    summary, or None if the kernel sources changed since those counters were taken."""
+def source_hash() -> str:
     import hashlib
+    return hashlib.sha256(b"".join(open(p, "rb").read() for p in PRODUCT_SOURCES)).hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per dispatch of a product kernel from the committed rocprofv3 counter
+    summary (keyed by the kernel's rocprofv3 name), or None if the product sources changed
+    since those counters were taken."""
     try:
-        kv = dict(line.strip().split("=", 1) for line in open(COUNTERS) if "=" in line and not line.startswith("#"))
+        kv = dict(line.rstrip("\n").split("=", 1) for line in open(COUNTERS) if "=" in line and not line.startswith("#"))
     except OSError:
         return None
-    h = hashlib.sha256(b"".join(open(p, "rb").read() for p in PRODUCT_SOURCES)).hexdigest()[:16]
-    if kv.get("source_sha256_16") != h:
+    if kv.get("source_sha256_16") != source_hash():
         return None
-    v = kv.get(f"k_{stage}{suffix if stage != 'final' else ''}.traffic_bytes")
+    v = kv.get(f"{kernel}.traffic_bytes")
     return int(float(v)) if v else None
 
 
@@ -294,6 +308,14 @@ def main() -> int:
                     help="block mode: also time one single-vector FP64 solve of the first wave")
     ap.add_argument("--mixed-ir", action="store_true",
                     help="iterative refinement: complex64 far factors inside, complex128 residuals outside")
+    ap.add_argument("--no-share", action="store_true",
+                    help="store every ordered far block's factors (no transpose sharing) for the single-vector line")
+    ap.add_argument("--gmres50-steps", type=int, default=2000,
+                    help="default line: Arnoldi steps of the GMRES(50) leg (0 skips it)")
+    ap.add_argument("--serving-leg", type=int, default=24,
+                    help="default line: requests of the bounded serving leg (0 skips it)")
+    ap.add_argument("--serving-leg-rate", type=float, default=0.9, help="serving leg arrival rate (1/s)")
+    ap.add_argument("--serving-leg-side", type=int, nargs=2, default=[8, 24], help="serving leg array sides")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: multi-GPU execution is not implemented (asked for --gpus {args.gpus})",
@@ -344,9 +366,10 @@ def main() -> int:
     t0 = time.perf_counter()
     geom = q.Geometry(ctx, arr)
     # the complex64 copy of the far factors serves the mixed-precision line; the FP64 solves
-    # and products read only the complex128 panels
+    # and products read only the complex128 panels.  Block corrections need per-block storage.
+    share = not args.no_share and not args.block_ir
     op = q.Operator(ctx, geom, eps=args.eps, far_prec=q.PREC_C64 if (args.mixed_ir or not args.no_forms) else q.PREC_C128,
-                    max_block_rows=args.max_block_rows, verbose=arr.n_particles > 1024)
+                    max_block_rows=args.max_block_rows, verbose=arr.n_particles > 1024, share_transpose=share)
     mode = q.SOLVE_BLOCK_IR if args.block_ir else (q.SOLVE_MIXED_IR if args.mixed_ir else q.SOLVE_FP64)
     restart = args.block_basis if args.block_ir else args.restart
     torch.cuda.synchronize()
@@ -400,14 +423,18 @@ def main() -> int:
         value = prec_bytes * n_apply / t_apply / 1e9
 
     prof = op.profile_apply(reps=20, prec=q.PREC_C64 if args.mixed_ir else q.PREC_C128)
-    dom = max(("rphase", "qphase", "final"), key=lambda k: prof[k]["ms"])
+    stages = ("qtphase", "rphase", "qphase", "final") if share else ("rphase", "qphase", "final")
+    dom = max(stages, key=lambda k: prof[k]["ms"])
     ach = prof[dom]["bytes"] / (prof[dom]["ms"] * 1e-3) / 1e9
+    symbols = (KERNEL_SYMBOL_SH_C64 if args.mixed_ir else KERNEL_SYMBOL_SH) if share else \
+        (KERNEL_SYMBOL_C64 if args.mixed_ir else KERNEL_SYMBOL)
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom, "_c64" if args.mixed_ir else ""),
-                "algorithmic_bytes": prof[dom]["bytes"],
-                "kernel": KERNEL_SYMBOL_C64[dom] if args.mixed_ir else KERNEL_SYMBOL[dom],
-                "stages_ms": {k: round(prof[k]["ms"], 4) for k in prof},
-                "stages_gbs": {k: round(prof[k]["bytes"] / (prof[k]["ms"] * 1e-3) / 1e9, 1) for k in prof}}
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(symbols[dom]) if share else None,
+                "algorithmic_bytes": prof[dom]["bytes"], "kernel": symbols[dom],
+                "timing": "HIP events around the kernel's own launch, averaged over 20 products",
+                "stages_ms": {k: round(prof[k]["ms"], 4) for k in stages + ("product",)},
+                "stages_gbs": {k: round(prof[k]["bytes"] / (prof[k]["ms"] * 1e-3) / 1e9, 1)
+                               for k in stages + ("product",)}}
     lat_ms = np.array(lat) * 1e3
     out = {
         "metric": METRIC, "value": round(value, 3 if args.block_ir else 1),
@@ -416,6 +443,7 @@ def main() -> int:
         "scaling": "weak", "vs_baseline": None, "dtype": "f32 factors, f64 accumulation" if args.mixed_ir else "f64",
         "data": "synthetic",
         "config": {"workload": f"{arr.name}: {arr.n_particles} disks, {n} unknowns, eps {args.eps:g}, "
+                               + ("transpose-shared far factors, " if share else "")
                                + (f"GMRES({args.restart})" if args.restart < args.max_iter else "unrestarted GMRES")
                                + f" to {args.tol:g}, "
                                + ("one TM plane wave at 10 deg" if args.nrhs == 1 else
@@ -424,22 +452,31 @@ def main() -> int:
                                + (", block corrections" if args.block_ir else ""),
                    "particles": arr.n_particles, "unknowns": n, "eps": args.eps, "restart": args.restart,
                    "tol": args.tol},
+        "value_bytes": "each product's algorithmic bytes: far factors as streamed (shared: a pair's Q twice, "
+                       "its R once), self blocks, the self-block inverses of the fused preconditioner, x, y and the "
+                       "rank-space vectors",
         "solves_per_s": round(args.steps * args.nrhs / total_s, 3),
         "rhs_per_solve_call": args.nrhs,
-        "latency_ms_p50": round(float(np.percentile(lat_ms, 50)), 2),
-        "latency_ms_p99": round(float(np.percentile(lat_ms, 99)), 2),
+        "solve_ms_p50": round(float(np.percentile(lat_ms, 50)), 2),
+        "solve_ms_p99": round(float(np.percentile(lat_ms, 99)), 2),
         "iterations": infos[-1]["iterations"], "rel_res_true": infos[-1]["rel_res_true"],
-        "reorthogonalised_steps": infos[-1]["n_reorth"], "refinements": infos[-1]["n_refine"],
+        "basis_orthogonality": infos[-1]["basis_ortho"], "refinements": infos[-1]["n_refine"],
         "solve_split_s": {"products": round(infos[-1]["t_apply_s"], 3),
                           "krylov_and_host": round(lat[-1] - infos[-1]["t_apply_s"], 3)},
         "setup_s": round(setup_s, 2), "gain": round(st["gain"], 3), "product_bytes": st["apply_bytes"],
+        "operator_device_bytes": st["device_bytes"], "share_transpose": share,
         "product_ms": round(prof["product"]["ms"], 4),
         "product_gbs": round(prof["product"]["bytes"] / (prof["product"]["ms"] * 1e-3) / 1e9, 1),
         "mean_rank_level": [round(r, 1) for r in st["mean_rank_level"]],
         "roofline": roofline,
     }
     if not args.mixed_ir and not args.no_forms and args.nrhs == 1:
-        out["forms"] = other_forms(q, W, ctx, geom, op, v, args, out["solves_per_s"])
+        out["forms"] = other_forms(q, W, ctx, geom, op, v, args, out["solves_per_s"], share)
+        if args.serving_leg > 0:
+            leg = serving_leg(args)
+            out["forms"]["serving"] = leg
+            out["latency_ms_p50"], out["latency_ms_p99"] = leg["latency_ms_p50"], leg["latency_ms_p99"]
+            out["latency_source"] = "forms.serving: arrival to result over the bounded serving stream"
     if args.mixed_ir and args.ir_reference:
         out["fp64_reference"] = ir_reference(q, op, v, x, args, total_s / args.steps)
     if not args.no_cpu_baseline:
@@ -486,18 +523,22 @@ def tune_tiles(op, prec=None) -> dict:
     return out
 
 
-def other_forms(q, W, ctx, geom, op, v, args, plain_solves_per_s: float) -> dict:
-    """The batched (block GMRES over 64 plane waves) and mixed-precision forms on the same
-    operator and tolerance, beside the plain single-solve FP64 form timed above."""
+def other_forms(q, W, ctx, geom, op, v, args, plain_solves_per_s: float, share: bool) -> dict:
+    """On the same array and tolerance, beside the plain single-solve FP64 form timed above: block
+    GMRES over 64 plane waves (per-block storage, FP64 matrix cores), mixed-precision refinement
+    (complex64 inner products) and the configured GMRES(50) for a bounded step budget."""
     import torch
     sw = W.sweep(32)
     vb = q.rhs_plane_waves(ctx, geom, sw.theta_deg, sw.phi_deg, sw.pol)
-    tiles = tune_tiles(op)
-    op.solve(vb, restart=16384, tol=args.tol, max_iter=args.max_iter, mode=q.SOLVE_BLOCK)     # warm-up
+    opb = q.Operator(ctx, geom, eps=args.eps, max_block_rows=args.max_block_rows) if share else op
+    tiles = tune_tiles(opb)
+    opb.solve(vb, restart=16384, tol=args.tol, max_iter=args.max_iter, mode=q.SOLVE_BLOCK)     # warm-up
     torch.cuda.synchronize()
     t = time.perf_counter()
-    _, ib, sb = op.solve(vb, restart=16384, tol=args.tol, max_iter=args.max_iter, mode=q.SOLVE_BLOCK)
+    _, ib, sb = opb.solve(vb, restart=16384, tol=args.tol, max_iter=args.max_iter, mode=q.SOLVE_BLOCK)
     tb = time.perf_counter() - t
+    if opb is not op:
+        opb.close()
     print(f"[bench] block form: {tb:.2f} s for 64 waves, {ib[0]['iterations']} block steps", file=sys.stderr,
           flush=True)
     t = time.perf_counter()
@@ -506,7 +547,7 @@ def other_forms(q, W, ctx, geom, op, v, args, plain_solves_per_s: float) -> dict
     print(f"[bench] mixed-precision form: {ti:.2f} s, {ii[0]['iterations']} inner steps", file=sys.stderr,
           flush=True)
     block_sps = 64 / tb
-    return {
+    out = {
         "plain_fp64_single_solves_per_s": plain_solves_per_s,
         "block_64_waves": {"solves_per_s": round(block_sps, 3), "s_per_64": round(tb, 3),
                            "block_steps": ib[0]["iterations"], "converged": all(i["converged"] for i in ib),
@@ -517,6 +558,43 @@ def other_forms(q, W, ctx, geom, op, v, args, plain_solves_per_s: float) -> dict
                                        "true_residual": ii[0]["rel_res_true"],
                                        "vs_plain": round((1.0 / ti) / plain_solves_per_s, 2)},
     }
+    if args.gmres50_steps > 0:
+        t = time.perf_counter()
+        _, i50, _ = op.solve(v, restart=50, tol=args.tol, max_iter=args.gmres50_steps)
+        t50 = time.perf_counter() - t
+        print(f"[bench] GMRES(50): {i50[0]['iterations']} steps, true residual {i50[0]['rel_res_true']:.2e}",
+              file=sys.stderr, flush=True)
+        out["gmres50"] = {"steps": i50[0]["iterations"], "restarts": i50[0]["restarts"],
+                          "converged": bool(i50[0]["converged"]), "true_residual": i50[0]["rel_res_true"],
+                          "preconditioned_residual": i50[0]["rel_res_prec"], "s": round(t50, 2),
+                          "note": "the configured restart length, for a bounded step budget; the timed solves run "
+                                  "unrestarted GMRES because GMRES(50) stalls on this array"}
+    return out
+
+
+def serving_leg(args) -> dict:
+    """A bounded stream of the serving workload (the seeded request recipe with array sides in
+    the given range, 1-16 plane waves each, tolerance 1e-6, Poisson arrivals) through the
+    library's native server; latency is arrival (submission) to result."""
+    import workloads as W
+    from paper_2603_10586_amd.server import Server, ServerOpts, replay
+    lo, hi = args.serving_leg_side
+    reqs = W.serving_requests(n=args.serving_leg, seed=0, rate_per_s=args.serving_leg_rate, side_lo=lo, side_hi=hi)
+    srv = Server(ServerOpts(slots=3, hbm_budget=120 << 30, eps=args.eps, restart=8192, max_iter=8000))
+    t0 = time.perf_counter()
+    res = replay(srv, reqs, report=lambda m: print(f"[bench] serving {m}", file=sys.stderr, flush=True))
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    print(f"[bench] serving leg: {len(res)} requests in {wall:.1f} s, p50 {st['latency_p50_s']:.2f} s, "
+          f"p99 {st['latency_p99_s']:.2f} s", file=sys.stderr, flush=True)
+    return {"requests": len(res), "arrival_rate_per_s": args.serving_leg_rate, "array_sides": [lo, hi],
+            "latency_ms_p50": round(st["latency_p50_s"] * 1e3, 1), "latency_ms_p99": round(st["latency_p99_s"] * 1e3, 1),
+            "queue_wait_ms_p50": round(st["queue_wait_p50_s"] * 1e3, 1),
+            "requests_per_s": round(st["requests_per_s"], 4), "rhs_solves_per_s": round(st["rhs_solves_per_s"], 3),
+            "all_converged": all(r.status == 0 for r in res),
+            "worst_true_residual": max(i["rel_res_true"] for r in res for i in r.info),
+            "operators_built": st["ops_built"], "wall_s": round(wall, 1)}
 
 
 if __name__ == "__main__":

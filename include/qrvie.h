@@ -238,8 +238,9 @@ qrvie_status qrvie_apply_prec(qrvie_ctx* ctx, const qrvie_op* op, int32_t prec, 
                               const qrvie_c128* x, int64_t ldx, qrvie_c128* y, int64_t ldy);
 /*
  * Stage timers of the single-RHS product (the product stage of the paper's timing
- * table, §6.5), measured with HIP events on the context stream over `reps` products
- * of a fixed internal test vector.  ms[0] R-phase (t = R x for every block; with shared
+ * table, §6.5), measured with HIP events on the context stream: each stage over `reps`
+ * back-to-back launches of its own kernel (its average launch duration), the whole product
+ * over `reps` products, on a fixed internal test vector.  ms[0] R-phase (t = R x for every block; with shared
  * factors also the mirror partials R^T s), ms[1] Q-phase (y_l = Q t per level, with shared
  * factors plus the mirror partials), ms[2] final pass (self blocks Z_pp x + level sum), ms[3]
  * whole product, ms[4] the Q^T pass s = Q^T x of shared factors (0 otherwise), ms[5] = 0;

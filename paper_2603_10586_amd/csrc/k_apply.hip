@@ -138,19 +138,63 @@ __device__ __forceinline__ c128 cmul(c128 a, c128 b) {
     return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
 }
 
+// Cross-lane exchanges without LDS.  swap32_c: gfx950's v_permlane32_swap on the pair (a, b):
+// lanes 32-63 of a trade places with lanes 0-31 of b.  swap16_c: v_permlane16_swap, odd
+// 16-lane rows of a with even rows of b.  dpp_c: a DPP lane permutation within 16-lane rows.
+__device__ __forceinline__ void swap_halves(double& a, double& b, bool wide) {
+    const unsigned long long ua = (unsigned long long)__double_as_longlong(a);
+    const unsigned long long ub = (unsigned long long)__double_as_longlong(b);
+    const unsigned al = (unsigned)ua, ah = (unsigned)(ua >> 32), bl = (unsigned)ub, bh = (unsigned)(ub >> 32);
+    unsigned rl0, rl1, rh0, rh1;
+    if (wide) {
+        const auto l = __builtin_amdgcn_permlane32_swap(al, bl, false, false);
+        const auto h = __builtin_amdgcn_permlane32_swap(ah, bh, false, false);
+        rl0 = l[0]; rl1 = l[1]; rh0 = h[0]; rh1 = h[1];
+    } else {
+        const auto l = __builtin_amdgcn_permlane16_swap(al, bl, false, false);
+        const auto h = __builtin_amdgcn_permlane16_swap(ah, bh, false, false);
+        rl0 = l[0]; rl1 = l[1]; rh0 = h[0]; rh1 = h[1];
+    }
+    a = __longlong_as_double((long long)(((unsigned long long)rh0 << 32) | rl0));
+    b = __longlong_as_double((long long)(((unsigned long long)rh1 << 32) | rl1));
+}
+// a + (the pair partner's b), where the partner of lane L is L ^ 32 (wide) or L ^ 16; each
+// lane keeps the half the swap leaves in place, so the sum is that of the kept column.
+__device__ __forceinline__ c128 fold_swap(c128 a, c128 b, bool wide) {
+    swap_halves(a.x, b.x, wide);
+    swap_halves(a.y, b.y, wide);
+    return make_double2(a.x + b.x, a.y + b.y);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xf, 0xf, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <int CTRL>
+__device__ __forceinline__ c128 dpp_c(c128 v) { return make_double2(dpp_d<CTRL>(v.x), dpp_d<CTRL>(v.y)); }
+
+constexpr int kDppRor8 = 0x128;        // row_ror:8, lane i of a row reads lane i ^ 8
+constexpr int kDppHalfMirror = 0x141;  // row_half_mirror, lane i of 8 reads lane 7 - i
+constexpr int kDppQuadXor1 = 0xB1;     // quad_perm [1, 0, 3, 2]
+constexpr int kDppQuadXor2 = 0x4E;     // quad_perm [2, 3, 0, 1]
+
 // Sums of 8 values per lane over the 64 lanes of a wave: every lane L returns the total of
-// v[L >> 3].  Each exchange step halves the values a lane keeps (10 exchanges instead of 48).
+// v[L >> 3].  Each of the first three steps halves the values a lane keeps (lanes with bit
+// 5, 4, 3 set keep the upper half), then the 8 lanes of a group reduce their common column.
 __device__ __forceinline__ c128 transpose_sum8(const c128 v[8], int lane) {
-    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
     c128 w4[4], w2[2];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) w4[u] = cadd(b5 ? v[4 + u] : v[u], shfl_xor_c(b5 ? v[u] : v[4 + u], 32));
+    for (int u = 0; u < 4; ++u) w4[u] = fold_swap(v[u], v[4 + u], true);
 #pragma unroll
-    for (int u = 0; u < 2; ++u) w2[u] = cadd(b4 ? w4[2 + u] : w4[u], shfl_xor_c(b4 ? w4[u] : w4[2 + u], 16));
-    c128 w = cadd(b3 ? w2[1] : w2[0], shfl_xor_c(b3 ? w2[0] : w2[1], 8));
-    w = cadd(w, shfl_xor_c(w, 4));
-    w = cadd(w, shfl_xor_c(w, 2));
-    return cadd(w, shfl_xor_c(w, 1));
+    for (int u = 0; u < 2; ++u) w2[u] = fold_swap(w4[u], w4[2 + u], false);
+    const c128 s0 = cadd(w2[0], dpp_c<kDppRor8>(w2[0]));
+    const c128 s1 = cadd(w2[1], dpp_c<kDppRor8>(w2[1]));
+    c128 w = (lane & 8) ? s1 : s0;
+    w = cadd(w, dpp_c<kDppHalfMirror>(w));
+    w = cadd(w, dpp_c<kDppQuadXor1>(w));
+    return cadd(w, dpp_c<kDppQuadXor2>(w));
 }
 
 __device__ __forceinline__ c128 wave_sum_c(c128 w) {

@@ -705,16 +705,15 @@ qrvie_status qrvie_op_profile_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t 
     CHECK(w.alloc(&xi, n, "profile x"));
     CHECK(w.alloc(&yi, n, "profile y"));
     CHECK(hip_check(ctx, hipMemsetAsync(xi, 0, sizeof(c128) * n, s), "profile x"));
-    hipEvent_t ev[5];
-    for (auto& e : ev) (void)hipEventCreate(&e);
-    double acc[5] = {0, 0, 0, 0, 0};
-    for (int r = 0; r < reps; ++r) {
-        (void)hipEventRecord(ev[0], s);
-        if (op->shared) {
-            if (lo) launch_qtphase(s, op->d_qt, op->n_qt, op->d_fac32, xi, pw.S);
-            else launch_qtphase(s, op->d_qt, op->n_qt, op->d_fac, xi, pw.S);
-        }
-        (void)hipEventRecord(ev[1], s);
+    // Each stage is timed over `reps` back-to-back launches of its own kernel (its average
+    // launch duration, as a kernel trace reports it), after one whole product has filled the
+    // intermediate vectors; the whole product is timed over `reps` products.
+    auto qt = [&]() {
+        if (!op->shared) return;
+        if (lo) launch_qtphase(s, op->d_qt, op->n_qt, op->d_fac32, xi, pw.S);
+        else launch_qtphase(s, op->d_qt, op->n_qt, op->d_fac, xi, pw.S);
+    };
+    auto rp = [&]() {
         for (const auto& L : op->rlaunch) {
             if (op->shared) {
                 if (lo) launch_rphase_sh(s, op->d_rstrips, L.count, op->d_fac32, xi, pw.T, op->d_tmap, pw.S, pw.P);
@@ -725,7 +724,8 @@ qrvie_status qrvie_op_profile_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t 
                 launch_rphase(s, op->d_rstrips + L.begin, L.count, L.waves, op->d_fac, xi, pw.T, op->d_tmap);
             }
         }
-        (void)hipEventRecord(ev[2], s);
+    };
+    auto qp = [&]() {
         for (const auto& L : op->qlaunch) {
             if (op->shared) {
                 if (lo) launch_qphase_sh(s, op->d_qstrips, L.count, op->d_fac32, pw.T, pw.P, pw.Y);
@@ -736,26 +736,41 @@ qrvie_status qrvie_op_profile_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t 
                 launch_qphase(s, op->d_qstrips + L.begin, L.count, L.waves, op->d_fac, pw.T, pw.Y);
             }
         }
-        (void)hipEventRecord(ev[3], s);
+    };
+    auto fin = [&]() {
         launch_final(s, g->N, g->d_ptype, op->d_self, nullptr, xi, pw.Y, op->n_active, n, nullptr, yi, nullptr);
-        (void)hipEventRecord(ev[4], s);
-        CHECK(hip_check(ctx, hipEventSynchronize(ev[4]), "profile"));
+    };
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    double acc[5] = {0, 0, 0, 0, 0};   // Q^T, R, Q, final, product
+    auto timed = [&](int k, auto&& fn) -> qrvie_status {
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < reps; ++r) fn();
+        (void)hipEventRecord(e1, s);
+        CHECK(hip_check(ctx, hipEventSynchronize(e1), "profile"));
         float t = 0.f;
-        for (int k = 0; k < 4; ++k) {
-            (void)hipEventElapsedTime(&t, ev[k], ev[k + 1]);
-            acc[k] += t;
-        }
-        (void)hipEventElapsedTime(&t, ev[0], ev[4]);
-        acc[4] += t;
-    }
-    for (auto& e : ev) (void)hipEventDestroy(e);
-    // ms / bytes: [0] R pass, [1] Q pass, [2] final, [3] whole product, [4] Q^T pass (shared), [5] 0
+        (void)hipEventElapsedTime(&t, e0, e1);
+        acc[k] = t;
+        return QRVIE_OK;
+    };
+    qt(); rp(); qp(); fin();
+    qrvie_status pst = QRVIE_OK;
+    if (op->shared) pst = timed(0, qt);
+    if (pst == QRVIE_OK) pst = timed(1, rp);
+    if (pst == QRVIE_OK) pst = timed(2, qp);
+    if (pst == QRVIE_OK) pst = timed(3, fin);
+    if (pst == QRVIE_OK) pst = timed(4, [&]() { qt(); rp(); qp(); fin(); });
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (pst != QRVIE_OK) return pst;
     ms[0] = acc[1] / reps;
     ms[1] = acc[2] / reps;
     ms[2] = acc[3] / reps;
     ms[3] = acc[4] / reps;
     ms[4] = acc[0] / reps;
     ms[5] = 0.0;
+    // bytes: [0] R pass, [1] Q pass, [2] final, [3] whole product, [4] Q^T pass (shared), [5] 0
     int64_t rn = 0, mr = 0, sr = 0;
     for (size_t b = 0; b < op->blocks.size(); ++b) {
         if (op->shared && !op->blocks[b].primary) continue;
