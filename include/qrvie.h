@@ -126,7 +126,8 @@ qrvie_status qrvie_assemble(qrvie_ctx* ctx, const qrvie_geom* g, int32_t nr, con
                             int32_t nc, const int32_t* cols, qrvie_c128* B, int64_t ldb);
 
 /* ----------------------------------------------------------------- operator */
-enum { QRVIE_PREC_C128 = 0, QRVIE_PREC_C64 = 1, QRVIE_PREC_BF16X2 = 2, QRVIE_PREC_C64_ONLY = 3 };
+enum { QRVIE_PREC_C128 = 0, QRVIE_PREC_C64 = 1, QRVIE_PREC_BF16X2 = 2, QRVIE_PREC_C64_ONLY = 3,
+       QRVIE_PREC_C64_F32 = 4 };
 
 /*
  *   eps              per-block relative Frobenius tolerance of the low-rank
@@ -138,7 +139,13 @@ enum { QRVIE_PREC_C128 = 0, QRVIE_PREC_C64 = 1, QRVIE_PREC_BF16X2 = 2, QRVIE_PRE
  *                    by every product with FP64 accumulation (the rounding, 2^-24 relative
  *                    per entry, is far below eps); MIXED_IR and complex128 products are
  *                    then refused, and exports return the complex64 values widened.
- *                    QRVIE_PREC_BF16X2 is reserved.
+ *                    QRVIE_PREC_BF16X2: the complex64 far factors of C64_ONLY (every product and
+ *                    residual with FP64 accumulation) plus a BF16 split-complex copy (real parts,
+ *                    then imaginary parts; FP64 -> FP32 -> BF16, each rounded to nearest even),
+ *                    which the corrections of QRVIE_SOLVE_BLOCK_IR apply on FP32 matrix cores with
+ *                    FP32 accumulation and complex64 self blocks (the precision pattern's inner
+ *                    operator).  Every operator built with complex64 factors also keeps complex64
+ *                    copies of the self blocks and their inverses for the FP32 products.
  *   near_prec        storage of the self blocks: QRVIE_PREC_C128 only for now
  *   max_block_rows   far blocks with more rows are split into their child
  *                    pairs (always far); 0 = no cap (the paper's scheme)
@@ -146,10 +153,11 @@ enum { QRVIE_PREC_C128 = 0, QRVIE_PREC_C64 = 1, QRVIE_PREC_BF16X2 = 2, QRVIE_PRE
  *                    panels (the mirror holds the transposed factors).  1: one Q, R per
  *                    unordered pair, the mirror applied as R^T (Q^T x_I) (Z = Z^T, the symmetric
  *                    weak form, §2 eq. 2.5): half the factor memory, and a single-RHS product
- *                    streams each pair's Q twice and its R once instead of both twice.  Products
- *                    and the FP64 / MIXED_IR solvers take shared operators (several right-hand
- *                    sides one product per column); the block modes, qrvie_op_profile_block and
- *                    qrvie_op_tune_block refuse them (QRVIE_ERR_INVALID_ARG).
+ *                    streams each pair's Q twice and its R once instead of both twice.  Every
+ *                    product and solver mode takes shared operators (2-15 right-hand sides one
+ *                    single-RHS product per column; 16 or more, and the FP32 forms, block products
+ *                    with Q^T and R^T strips); qrvie_op_profile_block and qrvie_op_tune_block
+ *                    refuse them (QRVIE_ERR_INVALID_ARG).
  *   seed             seed of the random sketches used by compression
  *   verbose          1: print one progress line per compression chunk to stderr
  *   chunk_bytes      device bytes of materialised blocks compressed together; 0 = a
@@ -231,9 +239,12 @@ void         qrvie_op_destroy(qrvie_op* op);
  * product Z_D x + sum_b Q_b (R_b x_J) of §5.2. */
 qrvie_status qrvie_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs,
                          const qrvie_c128* x, int64_t ldx, qrvie_c128* y, int64_t ldy);
-/* The same product with the far factors of precision prec: QRVIE_PREC_C128 (as qrvie_apply)
- * or QRVIE_PREC_C64 (the complex64 copy; products accumulate in FP64).  An operator built
- * without a copy of that precision gives QRVIE_ERR_INVALID_ARG. */
+/* The same product with the far factors of precision prec: QRVIE_PREC_C128 (as qrvie_apply),
+ * QRVIE_PREC_C64 (the complex64 factors; products accumulate in FP64), QRVIE_PREC_C64_F32 (the
+ * complex64 factors and self blocks on FP32 matrix cores, right-hand sides rounded to FP32,
+ * FP32 accumulation) or QRVIE_PREC_BF16X2 (the BF16 planes, likewise with FP32 self blocks).
+ * The two FP32 forms run the block product for any nrhs.  An operator built without factors of
+ * that precision gives QRVIE_ERR_INVALID_ARG. */
 qrvie_status qrvie_apply_prec(qrvie_ctx* ctx, const qrvie_op* op, int32_t prec, int32_t nrhs,
                               const qrvie_c128* x, int64_t ldx, qrvie_c128* y, int64_t ldy);
 /*
@@ -345,10 +356,15 @@ qrvie_status qrvie_rhs_plane_waves(qrvie_ctx* ctx, const qrvie_geom* g, int32_t 
  *                       finished column by column in FP64 mode from the block iterate; a
  *                       block of one column is solved in FP64 mode (the same Krylov space).
  * QRVIE_SOLVE_BLOCK_IR  iterative refinement as MIXED_IR, with each correction from block
- *                       GMRES (as BLOCK) on the complex64 copy of the far factors, for all
- *                       unconverged columns together; residuals use the complex128
- *                       factors.  Needs far_prec = QRVIE_PREC_C64.  info: iterations =
- *                       block steps over all corrections, n_refine = corrections.
+ *                       GMRES (as BLOCK) for all unconverged columns together.  Residuals use
+ *                       the complex128 factors (far_prec C64) or the complex64 ones with FP64
+ *                       accumulation (C64_ONLY, BF16X2).  Corrections: the BF16 planes on FP32
+ *                       matrix cores (BF16X2), the complex64 factors on FP32 matrix cores
+ *                       (inner_fp32 = 1), else the complex64 factors widened on FP64 matrix
+ *                       cores (C64).  An FP32 correction aims at a relative residual of at least
+ *                       1e-5 (complex64) or 1e-2 (BF16) and further refinements take the rest.
+ *                       info: iterations = block steps over all corrections, n_refine =
+ *                       corrections.
  */
 enum { QRVIE_SOLVE_FP64 = 0, QRVIE_SOLVE_MIXED_IR = 1, QRVIE_SOLVE_BLOCK = 2, QRVIE_SOLVE_BLOCK_IR = 3 };
 
@@ -369,6 +385,8 @@ typedef struct {
                              need fewer basis vectors in total for the same accuracy, so a
                              block that must fit a fixed basis without restarting can be
                              split. */
+    int32_t inner_fp32;   /* BLOCK_IR: 1 applies the corrections' complex64 factors on FP32 matrix
+                             cores (FP32 accumulation) instead of widening them to FP64; 0 or 1 */
 } qrvie_solve_opts;
 
 typedef struct {

@@ -9,7 +9,7 @@ LIB_PATH = os.path.join(HERE, "libqrvie.so")
 
 MAX_LEVELS = 24
 OK, ERR_INVALID_ARG, ERR_GEOMETRY, ERR_OUT_OF_MEMORY, ERR_DEVICE, NOT_CONVERGED, ERR_QUEUE_FULL = range(7)
-PREC_C128, PREC_C64, PREC_BF16X2, PREC_C64_ONLY = 0, 1, 2, 3
+PREC_C128, PREC_C64, PREC_BF16X2, PREC_C64_ONLY, PREC_C64_F32 = 0, 1, 2, 3, 4
 SOLVE_FP64, SOLVE_MIXED_IR, SOLVE_BLOCK, SOLVE_BLOCK_IR = 0, 1, 2, 3
 
 
@@ -49,7 +49,7 @@ class BlockInfo(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_iter", C.c_int32), ("mode", C.c_int32), ("tol", C.c_double),
                 ("use_x0", C.c_int32), ("inner_tol", C.c_double), ("verbose", C.c_int32),
-                ("block_width", C.c_int32)]
+                ("block_width", C.c_int32), ("inner_fp32", C.c_int32)]
 
 
 class SolveInfo(C.Structure):

@@ -369,7 +369,8 @@ class Operator:
         return z
 
     def solve(self, v, restart: int = 30, tol: float = 1e-8, max_iter: int = 10000, x0=None,
-              mode: int = L.SOLVE_FP64, inner_tol: float = 0.0, verbose: bool = False, block_width: int = 0):
+              mode: int = L.SOLVE_FP64, inner_tol: float = 0.0, verbose: bool = False, block_width: int = 0,
+              inner_fp32: bool = False):
         torch = _torch()
         pv, ld, nrhs = _cols(v, self.geom.ndof, self.ctx.device, "solve")
         if x0 is not None:
@@ -378,7 +379,8 @@ class Operator:
                 raise ValueError(f"solve: x0 has shape {tuple(x0.shape)}, v {tuple(v.shape)}")
         x = torch.zeros_like(v) if x0 is None else x0.clone()
         o = L.SolveOpts(restart=restart, max_iter=max_iter, mode=mode, tol=tol, use_x0=0 if x0 is None else 1,
-                        inner_tol=inner_tol, verbose=1 if verbose else 0, block_width=block_width)
+                        inner_tol=inner_tol, verbose=1 if verbose else 0, block_width=block_width,
+                        inner_fp32=1 if inner_fp32 else 0)
         infos = (L.SolveInfo * nrhs)()
         self.ctx.order()
         st = self.ctx.check(self.ctx.lib.qrvie_solve(self.ctx.h, self.h, nrhs, pv, ld, C.c_void_p(x.data_ptr()), ld,

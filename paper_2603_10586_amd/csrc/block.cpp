@@ -12,12 +12,10 @@
 //
 // Orthogonalisation is CGS2 through the Gram matrix of the basis (as in the single-vector
 // solver): C = V^H [V_k, W] in one GEMM, H = 2 H1 - G H1 with G = V^H V, W -= V H; the new
-// block is factorised by Cholesky QR twice.  The projections (split-K strided-batched
-// GEMMs), the small Gram correction and the triangular solves are rocBLAS; the basis and
-// solution updates W += V H are this library's FP64 MFMA kernel, like the product, the
-// Cholesky factor and the least-squares reflectors.
-#include <rocblas/rocblas.h>
-
+// block is factorised by Cholesky QR twice.  Every step runs on this library's kernels: the
+// projections as split-K FP64 MFMA partial products with a fixed-order reduction, the basis
+// and solution updates W += V H on FP64 MFMA, the right triangular solves of Cholesky QR as a
+// product with the inverted small triangle, and the least-squares back substitution.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -29,36 +27,7 @@
 
 namespace qrvie {
 
-void blas_release(qrvie_ctx* ctx) {
-    if (ctx->blas) {
-        (void)rocblas_destroy_handle((rocblas_handle)ctx->blas);
-        ctx->blas = nullptr;
-    }
-}
-
 namespace {
-
-typedef rocblas_double_complex zc;
-
-inline const zc* Z(const c128* p) { return reinterpret_cast<const zc*>(p); }
-inline zc* Z(c128* p) { return reinterpret_cast<zc*>(p); }
-
-qrvie_status blas_check(qrvie_ctx* ctx, rocblas_status st, const char* what) {
-    if (st == rocblas_status_success) return QRVIE_OK;
-    set_err(ctx, std::string(what) + ": rocBLAS status " + std::to_string((int)st));
-    return QRVIE_ERR_DEVICE;
-}
-
-qrvie_status blas_handle(qrvie_ctx* ctx, rocblas_handle* h) {
-    if (!ctx->blas) {
-        rocblas_handle hh = nullptr;
-        CHECK(blas_check(ctx, rocblas_create_handle(&hh), "rocblas handle"));
-        ctx->blas = hh;
-    }
-    *h = (rocblas_handle)ctx->blas;
-    CHECK(blas_check(ctx, rocblas_set_pointer_mode(*h, rocblas_pointer_mode_host), "rocblas pointer mode"));
-    return blas_check(ctx, rocblas_set_stream(*h, ctx->stream), "rocblas stream");
-}
 
 // Pivot floors (relative to the largest diagonal entry of a Gram matrix).  The first block
 // of a cycle keeps the directions whose singular values exceed 1e-7 of the largest (a
@@ -79,7 +48,6 @@ struct BlockSolver {
     qrvie_ctx* ctx;
     const qrvie_op* op;
     const qrvie_solve_opts* o;
-    rocblas_handle hb = nullptr;
     hipStream_t s;
     int64_t n;
     int p = 0, ntB = 0;          // right-hand sides and their tile count
@@ -92,6 +60,7 @@ struct BlockSolver {
     c128 *Cb = nullptr, *Hb = nullptr, *G = nullptr, *Rl = nullptr, *gl = nullptr, *Yb = nullptr;
     c128 *Yr = nullptr, *Tr = nullptr, *S = nullptr, *R1 = nullptr, *R2 = nullptr;
     c128* Pk = nullptr;          // split-K partial products
+    c128 *Ui = nullptr, *Wt = nullptr;   // inverted triangle and product of a right solve
     int* dflag = nullptr;        // [0..1] Cholesky flags, [2] rank q, [3..] pivot order
     double* dnrm = nullptr;
     double* hbuf = nullptr;      // pinned
@@ -100,9 +69,10 @@ struct BlockSolver {
     double t_apply = 0.0;
     int products = 0;
     bool lo = false;             // products (and residuals) on the complex64 panels
+    int kind = kBlockF64;        // or on FP32 matrix cores (complex64 panels or BF16 planes)
 
-    BlockSolver(qrvie_ctx* c, const qrvie_op* p_, const qrvie_solve_opts* o_, bool lo_)
-        : ctx(c), op(p_), o(o_), s(c->stream), n(p_->g->ndof()), w(c), lo(lo_) {}
+    BlockSolver(qrvie_ctx* c, const qrvie_op* p_, const qrvie_solve_opts* o_, bool lo_, int kind_)
+        : ctx(c), op(p_), o(o_), s(c->stream), n(p_->g->ndof()), w(c), lo(lo_), kind(kind_) {}
     ~BlockSolver() {
         if (hbuf) (void)hipHostFree(hbuf);
         if (hint) (void)hipHostFree(hint);
@@ -115,7 +85,6 @@ struct BlockSolver {
         ntB = (p + 15) / 16;
         ldh = (int64_t)(std::max(1, std::min(o->restart / p, o->max_iter)) + 1) * p;
         const int64_t P = 16 * ntB;
-        CHECK(blas_handle(ctx, &hb));
         CHECK(bw.init(w, op));
         CHECK(w.alloc(&Bc, (size_t)n * p, "block rhs"));
         CHECK(w.alloc(&X, (size_t)n * p, "block x"));
@@ -139,6 +108,8 @@ struct BlockSolver {
         CHECK(w.alloc(&R1, (size_t)p * p, "cholesky factor"));
         CHECK(w.alloc(&R2, (size_t)p * p, "cholesky factor"));
         CHECK(w.alloc(&Pk, (size_t)kPartialElems, "split-k partials"));
+        CHECK(w.alloc(&Ui, (size_t)p * p, "inverted triangle"));
+        CHECK(w.alloc(&Wt, (size_t)n * p, "right-solve product"));
         CHECK(w.alloc(&dflag, 3 + (size_t)p, "cholesky flags"));
         CHECK(w.alloc(&dnrm, 2 * (size_t)p, "block norms"));
         CHECK(hip_check(ctx, hipHostMalloc((void**)&hbuf, sizeof(double) * 2 * p, hipHostMallocDefault), "pinned"));
@@ -161,7 +132,7 @@ struct BlockSolver {
     void residual(const c128* Xcol, c128* out, c128* zcol) {
         launch_gather_block(s, ntB, op->g->N, nullptr, Xcol, n, p, Xi);
         (void)hipEventRecord(ev0, s);
-        block_product(op, s, bw, ntB, Xi, Bi, Ri, zcol ? Zi : nullptr, lo);
+        block_product(op, s, bw, ntB, Xi, Bi, Ri, zcol ? Zi : nullptr, lo, kind);
         (void)hipEventRecord(ev1, s);
         ++products;
         launch_scatter_block(s, ntB, op->g->N, nullptr, Ri, out, n, p);
@@ -174,37 +145,27 @@ struct BlockSolver {
 
     // C (m x c, ldc) = A^H B for n-row A (ld lda) and B (ld ldb).  The outputs of the basis
     // projections are small (m x c with c <= 128) against a 10^5-10^6 long reduction, so the
-    // rows are split into chunks: a strided-batched GEMM writes one partial product per chunk
-    // and a fixed-order reduction sums them (deterministic, and the whole device is busy).
+    // rows are split into chunks: one partial product per chunk (FP64 MFMA) and a fixed-order
+    // reduction sums them (deterministic, and the whole device is busy).
     qrvie_status gemm_hn(const c128* A, int64_t lda, int m, const c128* Bm, int64_t ldb, int c, c128* C, int64_t ldc) {
-        const zc zone = {1.0, 0.0}, zzero = {0.0, 0.0};
         const int64_t per = (int64_t)m * c;
         if (per == 0) return QRVIE_OK;
-        int64_t nb = std::min<int64_t>({kMaxChunks, kPartialElems / per - 1, n / kMinChunkRows});
-        if (nb < 2) {
-            return blas_check(ctx, rocblas_zgemm(hb, rocblas_operation_conjugate_transpose, rocblas_operation_none, m, c,
-                                                 (int)n, &zone, Z(A), (int)lda, Z(Bm), (int)ldb, &zzero, Z(C), (int)ldc),
-                              "zgemm");
-        }
-        const int64_t L = n / nb, rem = n - nb * L;
-        CHECK(blas_check(ctx, rocblas_zgemm_strided_batched(hb, rocblas_operation_conjugate_transpose,
-                                                            rocblas_operation_none, m, c, (int)L, &zone, Z(A), (int)lda,
-                                                            L, Z(Bm), (int)ldb, L, &zzero, Z(Pk), m, per, (int)nb),
-                         "zgemm batched"));
-        if (rem > 0)
-            CHECK(blas_check(ctx, rocblas_zgemm(hb, rocblas_operation_conjugate_transpose, rocblas_operation_none, m, c,
-                                                (int)rem, &zone, Z(A + nb * L), (int)lda, Z(Bm + nb * L), (int)ldb,
-                                                &zzero, Z(Pk + nb * per), m), "zgemm"));
-        launch_sum_batches(s, m, c, (int)(nb + (rem > 0 ? 1 : 0)), Pk, C, ldc);
-        return QRVIE_OK;
+        const int64_t nb = std::max<int64_t>(1, std::min<int64_t>({kMaxChunks, kPartialElems / per, n / kMinChunkRows}));
+        const int64_t L = ((n + nb - 1) / nb + 15) / 16 * 16;
+        const int64_t used = (n + L - 1) / L;
+        launch_gemm_hn_part(s, n, m, c, A, lda, Bm, ldb, (int)used, L, Pk);
+        launch_sum_batches(s, m, c, (int)used, Pk, C, ldc);
+        return hip_check(ctx, hipGetLastError(), "projection");
     }
 
     qrvie_status gram(const c128* Wp, int cols) { return gemm_hn(Wp, n, cols, Wp, n, cols, S, cols); }
+    // W (n x cols) = W R^-1 for the upper triangular R: the inverse of the small triangle, then
+    // one MFMA product into a work block copied back.
     qrvie_status right_solve(c128* Wp, int cols, const c128* R, int64_t ldr) {
-        const zc zone = {1.0, 0.0};
-        return blas_check(ctx, rocblas_ztrsm(hb, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
-                                             rocblas_diagonal_non_unit, (int)n, cols, &zone, Z(R), (int)ldr, Z(Wp),
-                                             (int)n), "ztrsm");
+        launch_tri_inv_upper(s, cols, R, ldr, Ui, cols);
+        launch_gemm_nn_acc(s, n, cols, cols, Wp, n, Ui, cols, 0.0, 1.0, Wt, n);
+        CHECK(hip_check(ctx, hipMemcpyAsync(Wp, Wt, sizeof(c128) * n * cols, hipMemcpyDeviceToDevice, s), "right solve"));
+        return hip_check(ctx, hipGetLastError(), "right solve");
     }
 
     // W (n x cols, ld n) = Q R, Q in place, R (cols x cols upper) at out; Cholesky QR twice.
@@ -269,16 +230,13 @@ struct BlockSolver {
 
     // X_out = X_in + V[:, 0:steps q] R^-1 gl[0:steps q, :]
     qrvie_status update(int steps, const c128* Xin, c128* Xout) {
-        const zc zone = {1.0, 0.0};
         const int64_t m = (int64_t)steps * q;
         if (Xout != Xin)
             CHECK(hip_check(ctx, hipMemcpyAsync(Xout, Xin, sizeof(c128) * n * p, hipMemcpyDeviceToDevice, s), "x"));
         if (steps == 0) return QRVIE_OK;
         CHECK(hip_check(ctx, hipMemcpy2DAsync(Yb, sizeof(c128) * ldh, gl, sizeof(c128) * ldh, sizeof(c128) * m, p,
                                               hipMemcpyDeviceToDevice, s), "y"));
-        CHECK(blas_check(ctx, rocblas_ztrsm(hb, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
-                                            rocblas_diagonal_non_unit, (int)m, p, &zone, Z(Rl), (int)ldh, Z(Yb),
-                                            (int)ldh), "ztrsm"));
+        launch_trsm_upper_left(s, (int)m, p, Rl, ldh, Yb, ldh);
         launch_gemm_nn_acc(s, n, (int)m, p, Vb, n, Yb, ldh, 1.0, 1.0, Xout, n);
         return hip_check(ctx, hipGetLastError(), "solution update");
     }
@@ -439,7 +397,8 @@ qrvie_status tune_block(qrvie_ctx* ctx, qrvie_op* op, int prec, int nrhs, int re
 }
 
 qrvie_status solve_block(qrvie_ctx* ctx, const qrvie_op* op, int na, const c128* v, int64_t ldv, c128* x,
-                         int64_t ldx, const qrvie_solve_opts* o, qrvie_solve_info* info, bool* broke, bool lo) {
+                         int64_t ldx, const qrvie_solve_opts* o, qrvie_solve_info* info, bool* broke, bool lo,
+                         int kind) {
     *broke = false;
     const double t0 = now_s();
     const qrvie_geom* g = op->g;
@@ -476,7 +435,7 @@ qrvie_status solve_block(qrvie_ctx* ctx, const qrvie_op* op, int na, const c128*
         return hip_check(ctx, hipStreamSynchronize(s), "solve");
     }
 
-    BlockSolver B(ctx, op, o, lo);
+    BlockSolver B(ctx, op, o, lo, kind);
     CHECK(B.init((int)cols.size()));
     const int p = B.p;
     for (int c = 0; c < p; ++c) {
@@ -528,7 +487,7 @@ qrvie_status solve_block(qrvie_ctx* ctx, const qrvie_op* op, int na, const c128*
             // W = Z_D^-1 Z_QR V_k
             launch_gather_block(s, B.ntK, g->N, nullptr, Vk, n, q, B.Xi);
             (void)hipEventRecord(B.ev0, s);
-            block_product(op, s, B.bw, B.ntK, B.Xi, nullptr, B.Ri, B.Zi, B.lo);
+            block_product(op, s, B.bw, B.ntK, B.Xi, nullptr, B.Ri, B.Zi, B.lo, B.kind);
             (void)hipEventRecord(B.ev1, s);
             ++B.products;
             launch_scatter_block(s, B.ntK, g->N, nullptr, B.Zi, W, n, q);

@@ -177,7 +177,6 @@ qrvie_status qrvie_ctx_create(int hip_device, void* hip_stream, size_t hbm_budge
 void qrvie_ctx_destroy(qrvie_ctx* ctx) {
     if (!ctx) return;
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-    blas_release(ctx);
     if (ctx->own_stream && ctx->stream) {
         (void)hipStreamSynchronize(ctx->stream);
         (void)hipStreamDestroy(ctx->stream);

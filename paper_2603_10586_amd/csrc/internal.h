@@ -50,9 +50,13 @@ struct RStrip {                     // t[tmap[tmap_off + i]] = sum_j A[i + j*ld]
 };
 // One 64-row strip of a column-major panel applied to an RHS-interleaved block of P
 // right-hand sides (element (row e, rhs r) at e * P + r): out rows = A_strip in rows.
+// MStrip flags (pad): kStripTrans, the strip is the transpose of a stored panel slice (element
+// (row r, column k) at a_off + k + r ld: the Q^T and R^T of transpose-shared factors);
+// kStripAcc, the result is added to the output instead of replacing it.
+constexpr int kStripTrans = 1, kStripAcc = 2;
 struct MStrip {
     int64_t a_off;                  // element offset of the strip's first row, column 0
-    int32_t ld, ncols, nrows, pad;
+    int32_t ld, ncols, nrows, pad;  // pad: flags (1: transposed panel slice, 2: accumulate)
     int64_t in_off;                 // input row of panel column 0
     int64_t out_off;                // output row of strip row 0 (when tmap_off < 0)
     int64_t tmap_off;               // >= 0: strip row i goes to output row tmap[tmap_off + i]
@@ -134,7 +138,6 @@ struct qrvie_ctx {
     std::atomic<size_t> in_use{0};  // atomic: the server frees operators from other threads
     std::atomic<size_t> peak{0};    // high-water mark of in_use since creation or the last reset
     std::string err;
-    void* blas = nullptr;           // rocBLAS handle of the block solver, created on first use
     void* scratch = nullptr;        // device address of this device's fixed product scratch
     std::string scratch_err;        // why it is missing, when it is
 };
@@ -191,6 +194,19 @@ struct qrvie_op {
     qrvie::MStrip* d_mq = nullptr;
     qrvie::MStrip* d_ms = nullptr;            // offsets into d_self and d_pinv (same layout)
     int64_t n_mr = 0, n_mq = 0, n_ms = 0;
+    // shared factors, blocks of right-hand sides: Q^T strips (output through d_tinv, the
+    // inverse of the rank map) and R^T strips over every node's rows (they write the level
+    // partials, which the Q strips then accumulate into)
+    qrvie::MStrip* d_mqt = nullptr;
+    qrvie::MStrip* d_mrt = nullptr;
+    int64_t n_mqt = 0, n_mrt = 0;
+    int64_t* d_tinv = nullptr;
+    // reduced-precision copies: self blocks and inverses in complex64 (the FP32 near part of
+    // the products on FP32 matrix cores) and BF16 split-complex factor planes (far_prec
+    // QRVIE_PREC_BF16X2: the real parts of every panel entry, then the imaginary parts)
+    float2* d_self32 = nullptr;
+    float2* d_pinv32 = nullptr;
+    uint16_t* d_fac16 = nullptr;
     // strip product tile variant per (complex64 panels?, nt - 1, group R / Q / self), set by
     // qrvie_op_tune_block; 0 (the default shape) until tuned
     std::atomic<int> tile[2][4][3]{};
@@ -218,7 +234,6 @@ bool set_err(qrvie_ctx* ctx, const std::string& msg);
 qrvie_status hip_check(qrvie_ctx* ctx, hipError_t e, const char* what);
 qrvie_status dalloc(qrvie_ctx* ctx, void** p, size_t bytes, const char* what);
 void dfree(qrvie_ctx* ctx, void* p, size_t bytes);
-void blas_release(qrvie_ctx* ctx);
 
 // The compressed pair blocks of an operator: the grouping's far/finest pairs with far pairs of
 // more than `cap` rows or columns split into their child pairs (0 = no cap), sorted by
@@ -298,6 +313,8 @@ void launch_final_m(hipStream_t s, int nr, int32_t N, const int32_t* ptype, cons
                     const c128* X, const c128* ylev, int nlev, int64_t n, const c128* V, c128* out_r, c128* out_z);
 // complex64 factor panels (the reduced-precision operator), FP64 accumulation
 void launch_to_c64(hipStream_t s, const c128* in, float2* out, int64_t n);
+// BF16 split-complex planes of complex64 values (round to nearest even): re[i], re[plane + i] = im
+void launch_to_bf16(hipStream_t s, const float2* in, uint16_t* out, int64_t n, int64_t plane);
 void launch_rphase_c64(hipStream_t s, const RStrip* st, int64_t n, const float2* fac, const c128* x, c128* t,
                        const int64_t* tmap);
 void launch_qphase_c64(hipStream_t s, const QStrip* st, int64_t n, const float2* fac, const c128* t, c128* y);
@@ -344,6 +361,12 @@ void launch_strip_mfma(hipStream_t s, int nt, const MStrip* st, int64_t n, const
                        c128* out, const int64_t* tmap, int variant = 0);
 void launch_strip_mfma(hipStream_t s, int nt, const MStrip* st, int64_t n, const float2* fac, const c128* in,
                        c128* out, const int64_t* tmap, int variant = 0);
+// The strip products on FP32 matrix cores with FP32 accumulation: complex64 panels, or BF16
+// split-complex planes (imaginary plane `plane` entries after the real one); one tile shape.
+void launch_strip_mfma32(hipStream_t s, int nt, const MStrip* st, int64_t n, const float2* fac, const c128* in,
+                         c128* out, const int64_t* tmap);
+void launch_strip_mfma32_bf16(hipStream_t s, int nt, const MStrip* st, int64_t n, const uint16_t* fac, int64_t plane,
+                              const c128* in, c128* out, const int64_t* tmap);
 void launch_count_neq(hipStream_t s, int64_t n, const void* a, const void* b, unsigned long long* count);
 void launch_block_combine(hipStream_t s, int nt, int64_t n, const c128* ylev, int nlev, const c128* yself,
                           const c128* V, c128* out);
@@ -364,6 +387,14 @@ void launch_ls_apply(hipStream_t s, int j0, int j1, int p, const c128* Y, const 
 void launch_ls_factor(hipStream_t s, int k, int p, c128* C, int64_t ldc, c128* Yk, c128* Tk);
 void launch_col_norms(hipStream_t s, int rows, const c128* C, int64_t ldc, int ncols, double* out);
 void launch_sum_batches(hipStream_t s, int m, int c, int nb, const c128* P, c128* C, int64_t ldc);
+// Split-K partials of C = A^H B (n-row A: m columns, B: c columns): chunk z < nb covers rows
+// [z L, min(n, (z + 1) L)) and writes P[z m c + i + j m]; launch_sum_batches reduces them.
+void launch_gemm_hn_part(hipStream_t s, int64_t n, int m, int c, const c128* A, int64_t lda, const c128* B, int64_t ldb,
+                         int nb, int64_t L, c128* P);
+// out (k x k) = U^-1 for an upper triangular k x k U, k <= 256
+void launch_tri_inv_upper(hipStream_t s, int k, const c128* U, int64_t ldu, c128* out, int64_t ldo);
+// Y (m x p) = U^-1 Y for an upper triangular m x m U
+void launch_trsm_upper_left(hipStream_t s, int m, int p, const c128* U, int64_t ldu, c128* Y, int64_t ldy);
 // W (n x q, q <= 64) = beta W + sign V H (V: n x m, H: m x q).  FP64 MFMA, fixed accumulation order.
 void launch_gemm_nn_acc(hipStream_t s, int64_t n, int m, int q, const c128* V, int64_t ldv, const c128* H,
                         int64_t ldh, double beta, double sign, c128* W, int64_t ldw);

@@ -606,6 +606,26 @@ __global__ void k_to_c64(const c128* __restrict__ in, float2* __restrict__ out, 
         out[e] = make_float2((float)in[e].x, (float)in[e].y);
 }
 
+// BF16 (8-bit mantissa) of an FP32 value, round to nearest even; NaN stays a quiet NaN.
+__device__ __forceinline__ unsigned short f32_to_bf16(float f) {
+    const unsigned u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (unsigned short)((u >> 16) | 0x40);
+    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__global__ void k_to_bf16(const float2* __restrict__ in, uint16_t* __restrict__ out, int64_t n, int64_t plane) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        const float2 v = in[e];
+        out[e] = f32_to_bf16(v.x);
+        out[plane + e] = f32_to_bf16(v.y);
+    }
+}
+void launch_to_bf16(hipStream_t s, const float2* in, uint16_t* out, int64_t n, int64_t plane) {
+    if (n <= 0) return;
+    const int64_t want = (n + 255) / 256, blocks = want < (1 << 20) ? want : (1 << 20);
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)blocks), dim3(256), 0, s, in, out, n, plane);
+}
+
 void launch_to_c64(hipStream_t s, const c128* in, float2* out, int64_t n) {
     if (n <= 0) return;
     const int64_t want = (n + 255) / 256, blocks = want < (1 << 20) ? want : (1 << 20);

@@ -44,9 +44,11 @@ __global__ void __launch_bounds__(256) k_strip_mfma(const MStrip* __restrict__ s
     const int r0 = 16 * RT * w;
     if (r0 >= s.nrows) return;
     const int rl = lane & 15, kq = lane >> 4;
+    const bool trans = s.pad & kStripTrans;
+    const int64_t rstep = trans ? s.ld : 1, cstep = trans ? 1 : s.ld;
     const F* A[RT];
 #pragma unroll
-    for (int q = 0; q < RT; ++q) A[q] = fac + s.a_off + min(r0 + 16 * q + rl, s.nrows - 1);
+    for (int q = 0; q < RT; ++q) A[q] = fac + s.a_off + min(r0 + 16 * q + rl, s.nrows - 1) * rstep;
     const c128* X = in + s.in_off * P + rl;
     v4d re[RT][NT], im[RT][NT];
 #pragma unroll
@@ -61,7 +63,7 @@ __global__ void __launch_bounds__(256) k_strip_mfma(const MStrip* __restrict__ s
         for (int u = 0; u < U; ++u) {
             const int64_t col = 4 * (c + u) + kq;
 #pragma unroll
-            for (int q = 0; q < RT; ++q) a[u][q] = widen(load_stream(A[q] + col * s.ld));
+            for (int q = 0; q < RT; ++q) a[u][q] = widen(load_stream(A[q] + col * cstep));
 #pragma unroll
             for (int t = 0; t < NT; ++t) b[u][t] = X[col * P + 16 * t];
         }
@@ -81,7 +83,7 @@ __global__ void __launch_bounds__(256) k_strip_mfma(const MStrip* __restrict__ s
         for (int t = 0; t < NT; ++t) b[t] = ok ? X[col * P + 16 * t] : z;
 #pragma unroll
         for (int q = 0; q < RT; ++q) {
-            const c128 a = ok ? widen(A[q][col * s.ld]) : z;
+            const c128 a = ok ? widen(A[q][col * cstep]) : z;
 #pragma unroll
             for (int t = 0; t < NT; ++t) cmfma(re[q][t], im[q][t], a, b[t]);
         }
@@ -94,8 +96,95 @@ __global__ void __launch_bounds__(256) k_strip_mfma(const MStrip* __restrict__ s
             if (row >= s.nrows) continue;
             const int64_t orow = s.tmap_off >= 0 ? tmap[s.tmap_off + row] : s.out_off + row;
 #pragma unroll
-            for (int t = 0; t < NT; ++t) out[orow * P + 16 * t + rl] = make_double2(re[q][t][i], im[q][t][i]);
+            for (int t = 0; t < NT; ++t) {
+                c128* o = out + orow * P + 16 * t + rl;
+                c128 v = make_double2(re[q][t][i], im[q][t][i]);
+                if (s.pad & kStripAcc) v = make_double2(v.x + o->x, v.y + o->y);
+                *o = v;
+            }
         }
+}
+
+// The same strip products on FP32 matrix cores (v_mfma_f32_16x16x4f32: the A and B operand
+// layouts of the FP64 instruction, but lane l, slot i of D holds row 4 (l / 16) + i, as
+// measured on the device) with FP32 accumulation: factors from complex64 panels (KIND 0) or
+// from BF16 split-complex planes (KIND 1: real parts, then the imaginary parts `plane` entries
+// later), the right-hand sides rounded to FP32 on load.  One tile shape (4-column steps in
+// batches of 4, one 16-row tile per wave); results are stored in FP64.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void cmfma32(v4f& re, v4f& im, float2 a, float2 b) {
+    re = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, re, 0, 0, 0);
+    re = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, b.y, re, 0, 0, 0);
+    im = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.y, im, 0, 0, 0);
+    im = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.x, im, 0, 0, 0);
+}
+
+__device__ __forceinline__ float bf16_to_f32(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+template <int KIND>
+__device__ __forceinline__ float2 load_fac32(const void* fac, int64_t plane, int64_t i) {
+    if (KIND == 0) return load_stream(static_cast<const float2*>(fac) + i);
+    const unsigned short* p = static_cast<const unsigned short*>(fac);
+    return make_float2(bf16_to_f32(__builtin_nontemporal_load(p + i)), bf16_to_f32(__builtin_nontemporal_load(p + plane + i)));
+}
+
+__device__ __forceinline__ float2 narrow(c128 v) { return make_float2((float)v.x, (float)v.y); }
+
+template <int NT, int KIND>
+__global__ void __launch_bounds__(256) k_strip_mfma32(const MStrip* __restrict__ strips, const void* __restrict__ fac,
+                                                      int64_t plane, const c128* __restrict__ in,
+                                                      c128* __restrict__ out, const int64_t* __restrict__ tmap) {
+    constexpr int P = 16 * NT, U = 4;
+    const MStrip s = strips[blockIdx.x];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int r0 = 16 * w;
+    if (r0 >= s.nrows) return;
+    const int rl = lane & 15, kq = lane >> 4;
+    const bool trans = s.pad & kStripTrans;
+    const int64_t rstep = trans ? s.ld : 1, cstep = trans ? 1 : s.ld;
+    const int64_t abase = s.a_off + min(r0 + rl, s.nrows - 1) * rstep;
+    const c128* X = in + s.in_off * P + rl;
+    v4f re[NT], im[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) re[t] = im[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    const int nsteps = s.ncols / 4;
+    int c = 0;
+    for (; c + U <= nsteps; c += U) {
+        float2 a[U], b[U][NT];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t col = 4 * (c + u) + kq;
+            a[u] = load_fac32<KIND>(fac, plane, abase + col * cstep);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) b[u][t] = narrow(X[col * P + 16 * t]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) cmfma32(re[t], im[t], a[u], b[u][t]);
+    }
+    for (; 4 * c < s.ncols; ++c) {                      // remaining steps, the last possibly partial
+        const int64_t col = 4 * c + kq;
+        const bool ok = col < s.ncols;
+        const float2 z = make_float2(0.f, 0.f);
+        const float2 a = ok ? load_fac32<KIND>(fac, plane, abase + col * cstep) : z;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) cmfma32(re[t], im[t], a, ok ? narrow(X[col * P + 16 * t]) : z);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int row = r0 + 4 * kq + i;
+        if (row >= s.nrows) continue;
+        const int64_t orow = s.tmap_off >= 0 ? tmap[s.tmap_off + row] : s.out_off + row;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            c128* o = out + orow * P + 16 * t + rl;
+            c128 v = make_double2((double)re[t][i], (double)im[t][i]);
+            if (s.pad & kStripAcc) v = make_double2(v.x + o->x, v.y + o->y);
+            *o = v;
+        }
+    }
 }
 
 // number of positions where two arrays of doubles differ bitwise (accumulated into *count)
@@ -170,7 +259,7 @@ __global__ void __launch_bounds__(256) k_gemm_nn_acc(int64_t n, int m, int q, co
             const int j = 16 * t + rl;
             if (j < q) {
                 c128* o = W + row + (int64_t)j * ldw;
-                const c128 v = *o;
+                const c128 v = beta != 0.0 ? *o : make_double2(0.0, 0.0);     // beta = 0: W may be uninitialised
                 *o = make_double2(beta * v.x + sign * re[t][s], beta * v.y + sign * im[t][s]);
             }
         }
@@ -590,6 +679,143 @@ __global__ void __launch_bounds__(256) k_ls_factor(int k, int p, c128* __restric
     }
 }
 
+// ----------------------------------------------------------------- basis projections
+// Split-K partial products of C = A^H B (A: n x m, B: n x c, both column-major): chunk z of
+// the rows writes P[z m c + i + j m] = sum over its rows e of conj(A[e, i]) B[e, j].  The
+// outputs are small against a reduction over 10^5-10^6 rows, so the rows are split into
+// chunks and a fixed-order kernel sums the partials (deterministic).  A workgroup owns a 64 x 64
+// tile of C for one chunk; each wave a 32 x 32 quadrant as 2 x 2 tiles of the FP64 MFMA.
+// The chunk's rows are consumed 16 at a time: the 16 x 64 slices of A and B are staged in LDS
+// (the next slice is loaded into registers while the MFMAs run on the current one).
+// conj(a) b: re += a.re b.re + a.im b.im, im += a.re b.im - a.im b.re.
+__device__ __forceinline__ void cmfma_conj(v4d& re, v4d& im, c128 a, c128 b) {
+    re = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, re, 0, 0, 0);
+    re = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, re, 0, 0, 0);
+    im = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, im, 0, 0, 0);
+    im = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.x, im, 0, 0, 0);
+}
+
+constexpr int kHnRows = 16;                 // rows per staged slice
+constexpr int kHnPad = kHnRows + 1;         // LDS row pitch of a staged column (bank spread)
+
+__global__ void __launch_bounds__(256) k_gemm_hn_part(int64_t n, int m, int c, const c128* __restrict__ A, int64_t lda,
+                                                      const c128* __restrict__ B, int64_t ldb, int64_t L,
+                                                      c128* __restrict__ P) {
+    __shared__ c128 As[64 * kHnPad];
+    __shared__ c128 Bs[64 * kHnPad];
+    const int t = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63;
+    const int rl = lane & 15, kq = lane >> 4;
+    const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+    const int64_t e0 = (int64_t)blockIdx.z * L, e1 = min(n, e0 + L);
+    const int qi = (w & 1) * 32, qj = (w >> 1) * 32;
+    // staging: thread t moves rows (t % 16) of columns t / 16 + 16 p, p < 4, of both slices
+    const int sr = t & 15, sc = t >> 4;
+    c128 ra[4], rb[4];
+    auto load = [&](int64_t e) {
+        const int64_t row = e + sr;
+        const bool rok = row < e1;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int ci = i0 + sc + 16 * p, cj = j0 + sc + 16 * p;
+            ra[p] = rok && ci < m ? A[row + (int64_t)ci * lda] : make_double2(0.0, 0.0);
+            rb[p] = rok && cj < c ? B[row + (int64_t)cj * ldb] : make_double2(0.0, 0.0);
+        }
+    };
+    v4d re[2][2], im[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) re[a][b] = im[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+    if (e0 < e1) load(e0);
+    for (int64_t e = e0; e < e1; e += kHnRows) {
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            As[(sc + 16 * p) * kHnPad + sr] = ra[p];
+            Bs[(sc + 16 * p) * kHnPad + sr] = rb[p];
+        }
+        __syncthreads();
+        if (e + kHnRows < e1) load(e + kHnRows);
+#pragma unroll
+        for (int ks = 0; ks < kHnRows / 4; ++ks) {
+            c128 a[2], b[2];
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) a[mt] = As[(qi + 16 * mt + rl) * kHnPad + 4 * ks + kq];
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct) b[ct] = Bs[(qj + 16 * ct + rl) * kHnPad + 4 * ks + kq];
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                for (int ct = 0; ct < 2; ++ct) cmfma_conj(re[mt][ct], im[mt][ct], a[mt], b[ct]);
+        }
+    }
+    const int64_t per = (int64_t)m * c;
+    c128* out = P + (int64_t)blockIdx.z * per;
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int i = i0 + qi + 16 * mt + kq + 4 * s, j = j0 + qj + 16 * ct + rl;
+                if (i < m && j < c) out[i + (int64_t)j * m] = make_double2(re[mt][ct][s], im[mt][ct][s]);
+            }
+}
+
+// Inverse of an upper triangular k x k matrix U (k <= 256): thread j solves U x = e_j by back
+// substitution into column j of out (zero below the diagonal).  A zero pivot gives inf / NaN,
+// as a triangular solve would; callers check their Cholesky flags.
+__global__ void __launch_bounds__(256) k_tri_inv_upper(int k, const c128* __restrict__ U, int64_t ldu,
+                                                       c128* __restrict__ out, int64_t ldo) {
+    const int j = threadIdx.x;
+    if (j >= k) return;
+    c128* x = out + (int64_t)j * ldo;
+    for (int i = k - 1; i > j; --i) x[i] = make_double2(0.0, 0.0);
+    for (int i = j; i >= 0; --i) {
+        double re = i == j ? 1.0 : 0.0, im = 0.0;
+        for (int l = i + 1; l <= j; ++l) {
+            const c128 u = U[i + (int64_t)l * ldu], v = x[l];
+            re -= u.x * v.x - u.y * v.y;
+            im -= u.x * v.y + u.y * v.x;
+        }
+        const c128 d = U[i + (int64_t)i * ldu];
+        const double den = d.x * d.x + d.y * d.y;
+        x[i] = make_double2((re * d.x + im * d.y) / den, (im * d.x - re * d.y) / den);
+    }
+}
+
+// Y (m x p, ld ldy) = U^-1 Y for an upper triangular m x m U (ld ldu): one workgroup per column
+// of Y.  Back substitution by columns of U (contiguous): y_k = y_k / u_kk, then y_i -= u_ik y_k
+// for i < k.  Thread t owns the rows i = t (mod 1024), so only the owner of row k touches it;
+// y_k reaches the others through LDS.
+__global__ void __launch_bounds__(1024) k_trsm_upper_left(int m, const c128* __restrict__ U, int64_t ldu,
+                                                          c128* __restrict__ Y, int64_t ldy) {
+    __shared__ c128 yk;
+    c128* y = Y + (int64_t)blockIdx.x * ldy;
+    const int t = threadIdx.x;
+    for (int k = m - 1; k >= 0; --k) {
+        if ((k & 1023) == t) {
+            const c128 d = U[k + (int64_t)k * ldu], v = y[k];
+            const double den = d.x * d.x + d.y * d.y;
+            const c128 r = make_double2((v.x * d.x + v.y * d.y) / den, (v.y * d.x - v.x * d.y) / den);
+            y[k] = r;
+            yk = r;
+        }
+        __syncthreads();
+        const c128 b = yk;
+        const c128* u = U + (int64_t)k * ldu;
+        for (int i = t; i < k; i += 1024) {
+            const c128 a = u[i];
+            c128 v = y[i];
+            v.x -= a.x * b.x - a.y * b.y;
+            v.y -= a.x * b.y + a.y * b.x;
+            y[i] = v;
+        }
+        __syncthreads();
+    }
+}
+
 // C[i + j ldc] = sum_b P[b per + i + j m] for i < m, j < c, b < nb (fixed order): the
 // reduction of split-K partial products.
 __global__ void k_sum_batches(int m, int c, int nb, const c128* __restrict__ P, c128* __restrict__ C, int64_t ldc) {
@@ -656,6 +882,18 @@ void launch_sum_batches(hipStream_t s, int m, int c, int nb, const c128* P, c128
     if (per <= 0) return;
     hipLaunchKernelGGL(k_sum_batches, dim3((unsigned)((per + 255) / 256)), dim3(256), 0, s, m, c, nb, P, C, ldc);
 }
+void launch_gemm_hn_part(hipStream_t s, int64_t n, int m, int c, const c128* A, int64_t lda, const c128* B, int64_t ldb,
+                         int nb, int64_t L, c128* P) {
+    if (n <= 0 || m <= 0 || c <= 0 || nb <= 0) return;
+    const dim3 g((unsigned)((m + 63) / 64), (unsigned)((c + 63) / 64), (unsigned)nb);
+    hipLaunchKernelGGL(k_gemm_hn_part, g, dim3(256), 0, s, n, m, c, A, lda, B, ldb, L, P);
+}
+void launch_tri_inv_upper(hipStream_t s, int k, const c128* U, int64_t ldu, c128* out, int64_t ldo) {
+    if (k > 0) hipLaunchKernelGGL(k_tri_inv_upper, dim3(1), dim3(256), 0, s, k, U, ldu, out, ldo);
+}
+void launch_trsm_upper_left(hipStream_t s, int m, int p, const c128* U, int64_t ldu, c128* Y, int64_t ldy) {
+    if (m > 0 && p > 0) hipLaunchKernelGGL(k_trsm_upper_left, dim3((unsigned)p), dim3(1024), 0, s, m, U, ldu, Y, ldy);
+}
 void launch_gemm_nn_acc(hipStream_t s, int64_t n, int m, int q, const c128* V, int64_t ldv, const c128* H,
                         int64_t ldh, double beta, double sign, c128* W, int64_t ldw) {
     if (n <= 0 || m <= 0 || q <= 0) return;
@@ -710,6 +948,28 @@ void strip_any(hipStream_t s, int nt, int v, const MStrip* st, int64_t n, const 
     }
 }
 }  // namespace
+
+template <int KIND>
+void strip32_any(hipStream_t s, int nt, const MStrip* st, int64_t n, const void* fac, int64_t plane, const c128* in,
+                 c128* out, const int64_t* tmap) {
+    if (n <= 0) return;
+    const dim3 g((unsigned)n);
+    switch (nt) {
+        case 1: hipLaunchKernelGGL((k_strip_mfma32<1, KIND>), g, dim3(256), 0, s, st, fac, plane, in, out, tmap); break;
+        case 2: hipLaunchKernelGGL((k_strip_mfma32<2, KIND>), g, dim3(256), 0, s, st, fac, plane, in, out, tmap); break;
+        case 3: hipLaunchKernelGGL((k_strip_mfma32<3, KIND>), g, dim3(256), 0, s, st, fac, plane, in, out, tmap); break;
+        default: hipLaunchKernelGGL((k_strip_mfma32<4, KIND>), g, dim3(256), 0, s, st, fac, plane, in, out, tmap); break;
+    }
+}
+
+void launch_strip_mfma32(hipStream_t s, int nt, const MStrip* st, int64_t n, const float2* fac, const c128* in,
+                         c128* out, const int64_t* tmap) {
+    strip32_any<0>(s, nt, st, n, fac, 0, in, out, tmap);
+}
+void launch_strip_mfma32_bf16(hipStream_t s, int nt, const MStrip* st, int64_t n, const uint16_t* fac, int64_t plane,
+                              const c128* in, c128* out, const int64_t* tmap) {
+    strip32_any<1>(s, nt, st, n, fac, plane, in, out, tmap);
+}
 
 int strip_variant_u(int v) { return v >= 0 && v < kStripVariants ? kTileU[v] : 0; }
 int strip_variant_rows(int v) { return v >= 0 && v < kStripVariants ? 16 * kTileRT[v] : 0; }

@@ -12,6 +12,7 @@
 // misses eps is redone with a wider sketch.  Only the pairs (I, J) with I before J are
 // compressed; (J, I) stores the transposed factors, so Z_QR is exactly symmetric like Z.
 #include <algorithm>
+#include <array>
 #include <cstdio>
 #include <chrono>
 #include <cmath>
@@ -573,6 +574,7 @@ void op_footprint(const qrvie_geom* g, const qrvie_compress_opts* o, size_t* res
     const double panel_elems = fac + rpad;
     double panels = 0.0, panels_final = 0.0;        // bytes while packing, and once built
     if (o->far_prec == QRVIE_PREC_C64_ONLY) panels = panels_final = 8.0 * panel_elems;
+    else if (o->far_prec == QRVIE_PREC_BF16X2) panels = 8.0 * panel_elems, panels_final = 12.0 * panel_elems;
     else {
         panels = 16.0 * panel_elems;
         panels_final = panels + (o->far_prec == QRVIE_PREC_C64 ? 8.0 * panel_elems : 0.0);
@@ -605,7 +607,8 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
     if (!ctx || !g || !o || !out) return QRVIE_ERR_INVALID_ARG;
     *out = nullptr;
     if (!(o->eps > 0.0) || !(o->eps < 1.0)) { set_err(ctx, "op_create: eps must be in (0, 1)"); return QRVIE_ERR_INVALID_ARG; }
-    if ((o->far_prec != QRVIE_PREC_C128 && o->far_prec != QRVIE_PREC_C64 && o->far_prec != QRVIE_PREC_C64_ONLY) ||
+    if ((o->far_prec != QRVIE_PREC_C128 && o->far_prec != QRVIE_PREC_C64 && o->far_prec != QRVIE_PREC_C64_ONLY &&
+         o->far_prec != QRVIE_PREC_BF16X2) ||
         o->near_prec != QRVIE_PREC_C128 ||
         (o->share_transpose != 0 && o->share_transpose != 1) ||
         o->max_block_rows < 0 || o->chunk_bytes < 0) {
@@ -750,6 +753,7 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
     std::vector<RStrip> rstr;
     std::vector<QStrip> qstr;
     std::vector<QtItem> qts;
+    std::vector<MStrip> mqt, mrt;          // shared factors: Q^T and R^T strips for blocks of RHS
     std::vector<int64_t> tmap;
     int64_t fcur = 0, tcur = 0, pcur = 0;
     for (int l = 0; l <= g->L; ++l) {
@@ -784,14 +788,19 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
                 qstr.push_back(QStrip{base + r0, (int32_t)mI, (int32_t)K, (int32_t)std::min<int64_t>(kStrip, mI - r0),
                                       (int64_t)active[l] * n + (int64_t)nd.first * kNp + r0, tcur, -1, 0, 0});
             }
-            if (sh)
+            if (sh) {
                 for (int64_t c0 = 0; c0 < K; c0 += 8)
                     qts.push_back(QtItem{base + mI * c0, (int32_t)mI, (int32_t)mI, (int32_t)std::min<int64_t>(8, K - c0),
                                          nd.first * kNp, tcur + c0});
+                for (int64_t c0 = 0; c0 < K; c0 += kStrip)   // rows: the panel's columns; output through tinv
+                    mqt.push_back(MStrip{base + mI * c0, (int32_t)mI, (int32_t)mI, (int32_t)std::min<int64_t>(kStrip, K - c0),
+                                         kStripTrans, (int64_t)nd.first * kNp, 0, tcur + c0});
+            }
             tcur += K;
             bi = b1;
         }
         // R panels per column node
+        std::map<int32_t, std::array<int64_t, 4>> rpanel;   // node first -> (base, ld, rows, stacked row base)
         std::map<int32_t, std::vector<size_t>> bycol;
         for (size_t b = 0; b < NB; ++b)
             if (bld.blocks[b].level == l && stored(b)) bycol[bld.blocks[b].c0].push_back(b);
@@ -814,6 +823,7 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
                 for (int k = 0; k < op->rank[b]; ++k) tmap.push_back(toff[b] + k);
                 row += op->rank[b];
             }
+            rpanel[b0.c0] = {base, ldp, Kp, tbase};
             const int64_t nstrip = (Kp + kStrip - 1) / kStrip;
             for (int64_t r0 = 0; r0 < Kp; r0 += kStrip)
                 rstr.push_back(RStrip{base + r0, (int32_t)ldp, (int32_t)nJ, (int32_t)std::min<int64_t>(kStrip, Kp - r0),
@@ -830,6 +840,21 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
             }
         }
         (void)qbegin;
+        if (sh)   // R^T strips over the rows of every node of the level (zero rows where no panel)
+            for (int32_t J : g->level_nodes[l]) {
+                const auto& nd = g->nodes[J];
+                const int64_t nJ = (int64_t)nd.count * kNp;
+                const auto it = rpanel.find(nd.first);
+                for (int64_t j0 = 0; j0 < nJ; j0 += kStrip) {
+                    const int32_t rows = (int32_t)std::min<int64_t>(kStrip, nJ - j0);
+                    const int64_t orow = (int64_t)active[l] * n + (int64_t)nd.first * kNp + j0;
+                    if (it == rpanel.end())
+                        mrt.push_back(MStrip{0, 1, 0, rows, kStripTrans, 0, orow, -1});
+                    else
+                        mrt.push_back(MStrip{it->second[0] + j0 * it->second[1], (int32_t)it->second[1],
+                                             (int32_t)it->second[2], rows, kStripTrans, it->second[3], orow, -1});
+                }
+            }
     }
     // One launch per phase over all levels: four waves per strip split its columns, and the
     // strips are issued longest first so the long coarse-level strips overlap the many
@@ -850,10 +875,17 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
     std::vector<MStrip> mr, mq, ms;
     mr.reserve(rstr.size());
     mq.reserve(qstr.size());
-    if (!sh) {   // the block products stream stored factors of every ordered block
-        for (const RStrip& r : rstr) mr.push_back(MStrip{r.a_off, r.ld, r.ncols, r.nrows, 0, r.x_off, 0, r.tmap_off});
-        for (const QStrip& q : qstr) mq.push_back(MStrip{q.a_off, q.ld, q.ncols, q.nrows, 0, q.t_off, q.y_off, -1});
-    }
+    // (shared factors: the Q strips add to the level partials that the R^T strips wrote)
+    for (const RStrip& r : rstr) mr.push_back(MStrip{r.a_off, r.ld, r.ncols, r.nrows, 0, r.x_off, 0, r.tmap_off});
+    for (const QStrip& q : qstr)
+        mq.push_back(MStrip{q.a_off, q.ld, q.ncols, q.nrows, sh ? kStripAcc : 0, q.t_off, q.y_off, -1});
+    auto longest_first = [](const MStrip& a, const MStrip& b) { return a.ncols > b.ncols; };
+    std::stable_sort(mqt.begin(), mqt.end(), longest_first);
+    std::stable_sort(mrt.begin(), mrt.end(), longest_first);
+    op->n_mqt = (int64_t)mqt.size();
+    op->n_mrt = (int64_t)mrt.size();
+    std::vector<int64_t> tinv(sh ? tmap.size() : 0);
+    for (size_t k = 0; k < tinv.size(); ++k) tinv[tmap[k]] = (int64_t)k;
     for (int32_t p = 0; p < g->N; ++p)
         for (int r0 = 0; r0 < kNp; r0 += kStrip)
             ms.push_back(MStrip{(int64_t)g->ptype[p] * kNp * kNp + r0, kNp, kNp, std::min(kStrip, kNp - r0), 0,
@@ -864,8 +896,13 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
     keep((void**)&op->d_mr, sizeof(MStrip) * std::max<size_t>(mr.size(), 1), "block R strips");
     keep((void**)&op->d_mq, sizeof(MStrip) * std::max<size_t>(mq.size(), 1), "block Q strips");
     keep((void**)&op->d_ms, sizeof(MStrip) * std::max<size_t>(ms.size(), 1), "block self strips");
+    if (sh) {
+        keep((void**)&op->d_mqt, sizeof(MStrip) * std::max<size_t>(mqt.size(), 1), "block Q^T strips");
+        keep((void**)&op->d_mrt, sizeof(MStrip) * std::max<size_t>(mrt.size(), 1), "block R^T strips");
+        keep((void**)&op->d_tinv, sizeof(int64_t) * std::max<size_t>(tinv.size(), 1), "inverse rank map");
+    }
 
-    const bool only32 = o->far_prec == QRVIE_PREC_C64_ONLY;
+    const bool only32 = o->far_prec == QRVIE_PREC_C64_ONLY || o->far_prec == QRVIE_PREC_BF16X2;
     if (only32) keep((void**)&op->d_fac32, sizeof(float2) * (size_t)std::max<int64_t>(fcur, 1), "complex64 panels");
     else keep((void**)&op->d_fac, sizeof(c128) * (size_t)std::max<int64_t>(fcur, 1), "factor panels");
     keep((void**)&op->d_tmap, sizeof(int64_t) * std::max<size_t>(tmap.size(), 1), "rank map");
@@ -883,6 +920,11 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
     if (st == QRVIE_OK && !mr.empty()) (void)hipMemcpyAsync(op->d_mr, mr.data(), sizeof(MStrip) * mr.size(), hipMemcpyHostToDevice, s);
     if (st == QRVIE_OK && !mq.empty()) (void)hipMemcpyAsync(op->d_mq, mq.data(), sizeof(MStrip) * mq.size(), hipMemcpyHostToDevice, s);
     if (st == QRVIE_OK && !ms.empty()) (void)hipMemcpyAsync(op->d_ms, ms.data(), sizeof(MStrip) * ms.size(), hipMemcpyHostToDevice, s);
+    if (st == QRVIE_OK && sh) {
+        if (!mqt.empty()) (void)hipMemcpyAsync(op->d_mqt, mqt.data(), sizeof(MStrip) * mqt.size(), hipMemcpyHostToDevice, s);
+        if (!mrt.empty()) (void)hipMemcpyAsync(op->d_mrt, mrt.data(), sizeof(MStrip) * mrt.size(), hipMemcpyHostToDevice, s);
+        if (!tinv.empty()) (void)hipMemcpyAsync(op->d_tinv, tinv.data(), sizeof(int64_t) * tinv.size(), hipMemcpyHostToDevice, s);
+    }
     st = hip_check(ctx, hipStreamSynchronize(s), "upload layout");   // the host vectors die at return
     if (st != QRVIE_OK) {
         for (auto& sg : bld.segments) dfree(ctx, sg.first, sg.second);
@@ -937,6 +979,23 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
         st = hip_check(ctx, hipStreamSynchronize(s), "complex64 panels");
         if (st != QRVIE_OK) return fail(st);
     }
+    if (o->far_prec == QRVIE_PREC_BF16X2) {
+        // BF16 split-complex planes of the complex64 panels (round to nearest even twice:
+        // FP64 -> FP32 -> BF16)
+        keep((void**)&op->d_fac16, sizeof(uint16_t) * 2 * (size_t)std::max<int64_t>(op->fac_elems, 1), "bf16 planes");
+        if (st != QRVIE_OK) return fail(st);
+        launch_to_bf16(s, op->d_fac32, op->d_fac16, op->fac_elems, op->fac_elems);
+    }
+    if (o->far_prec != QRVIE_PREC_C128) {
+        // complex64 self blocks and inverses: the near part of products on FP32 matrix cores
+        keep((void**)&op->d_self32, sizeof(float2) * (size_t)op->ntypes * kNp * kNp, "complex64 self blocks");
+        keep((void**)&op->d_pinv32, sizeof(float2) * (size_t)op->ntypes * kNp * kNp, "complex64 inverses");
+        if (st != QRVIE_OK) return fail(st);
+        launch_to_c64(s, op->d_self, op->d_self32, (int64_t)op->ntypes * kNp * kNp);
+        launch_to_c64(s, op->d_pinv, op->d_pinv32, (int64_t)op->ntypes * kNp * kNp);
+    }
+    st = hip_check(ctx, hipStreamSynchronize(s), "reduced-precision copies");
+    if (st != QRVIE_OK) return fail(st);
     const double t3 = now_s();
     op->stats.t_compression_s += t3 - t2;
 

@@ -524,8 +524,13 @@ qrvie_status solve_block_ir(qrvie_ctx* ctx, const qrvie_op* op, int nrhs, const 
         }
     }
     const int width = o->block_width > 0 ? o->block_width : kMaxBlockRhs;
+    // corrections: BF16 planes or complex64 panels on FP32 matrix cores, else the complex64
+    // panels widened to FP64
+    const int kind = op->d_fac16 ? kBlockBF16 : o->inner_fp32 ? kBlockF32 : kBlockF64;
     for (int it = 0;; ++it) {
-        CHECK(qrvie_apply_prec(ctx, op, QRVIE_PREC_C128, nrhs, (const qrvie_c128*)x, ldx, (qrvie_c128*)R, n));
+        // residuals with the complex128 factors, or the complex64 ones with FP64 accumulation
+        CHECK(qrvie_apply_prec(ctx, op, op->d_fac ? QRVIE_PREC_C128 : QRVIE_PREC_C64, nrhs, (const qrvie_c128*)x, ldx,
+                               (qrvie_c128*)R, n));
         for (int c = 0; c < nrhs; ++c) launch_rsub(s, v + (int64_t)c * ldv, n, R + (int64_t)c * n);
         CHECK(norms(R, n, rn));
         std::vector<int> act;
@@ -542,6 +547,10 @@ qrvie_status solve_block_ir(qrvie_ctx* ctx, const qrvie_op* op, int nrhs, const 
             act.push_back(c);
             eta = std::min(eta, o->inner_tol > 0.0 ? o->inner_tol : std::max(0.25 * o->tol / r, 1e-14));
         }
+        // corrections on FP32 matrix cores cannot resolve residuals far below their rounding: a
+        // correction aims at no less than 1e-5 (complex64 factors) or 1e-2 (BF16 factors) and
+        // further refinements take the rest
+        if (o->inner_tol <= 0.0) eta = std::max(eta, kind == kBlockBF16 ? 1e-2 : kind == kBlockF32 ? 1e-5 : 0.0);
         if (act.empty()) break;
         for (size_t j = 0; j < act.size(); ++j)
             CHECK(hip_check(ctx, hipMemcpyAsync(Ra + (int64_t)j * n, R + (int64_t)act[j] * n, sizeof(c128) * n,
@@ -555,7 +564,7 @@ qrvie_status solve_block_ir(qrvie_ctx* ctx, const qrvie_op* op, int nrhs, const 
             std::vector<qrvie_solve_info> ii(cnt);
             bool broke = false;
             const qrvie_status st = solve_block(ctx, op, cnt, Ra + (int64_t)r0 * n, n, D + (int64_t)r0 * n, n, &oi,
-                                                ii.data(), &broke, true);
+                                                ii.data(), &broke, true, kind);
             if (st != QRVIE_OK && st != QRVIE_NOT_CONVERGED) return st;
             for (int j = 0; j < cnt; ++j) {
                 qrvie_solve_info& f = inf[act[r0 + j]];
@@ -612,15 +621,17 @@ qrvie_status qrvie_apply(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const
 qrvie_status qrvie_apply_prec(qrvie_ctx* ctx, const qrvie_op* op, int32_t prec, int32_t nrhs, const qrvie_c128* x,
                               int64_t ldx, qrvie_c128* y, int64_t ldy) {
     CHECK(check_vec_args(ctx, op, nrhs, x, ldx, y, ldy, "apply"));
-    if (!((prec == QRVIE_PREC_C128 && op->d_fac) || (prec == QRVIE_PREC_C64 && op->d_fac32))) {
+    if (!((prec == QRVIE_PREC_C128 && op->d_fac) || (prec == QRVIE_PREC_C64 && op->d_fac32) ||
+          (prec == QRVIE_PREC_C64_F32 && op->d_fac32 && op->d_self32) || (prec == QRVIE_PREC_BF16X2 && op->d_fac16))) {
         set_err(ctx, "apply: the operator holds no far factors of the requested precision");
         return QRVIE_ERR_INVALID_ARG;
     }
     const bool lo = prec == QRVIE_PREC_C64;
+    const int kind = prec == QRVIE_PREC_BF16X2 ? kBlockBF16 : prec == QRVIE_PREC_C64_F32 ? kBlockF32 : kBlockF64;
     const int64_t n = op->g->ndof();
     hipStream_t s = ctx->stream;
     Work w(ctx);
-    if (nrhs >= 16 && !op->shared) {
+    if (nrhs >= 16 || kind != kBlockF64) {
         // blocks of up to 64 right-hand sides on the MFMA kernels
         BlockWork bw;
         CHECK(bw.init(w, op));
@@ -631,7 +642,7 @@ qrvie_status qrvie_apply_prec(qrvie_ctx* ctx, const qrvie_op* op, int32_t prec, 
             const int cnt = std::min(kMaxBlockRhs, nrhs - r0);
             const int nt = (cnt + 15) / 16;
             launch_gather_block(s, nt, op->g->N, op->g->d_i2c, (const c128*)x + (int64_t)r0 * ldx, ldx, cnt, X);
-            block_product(op, s, bw, nt, X, nullptr, Y, nullptr, lo);
+            block_product(op, s, bw, nt, X, nullptr, Y, nullptr, lo, kind);
             launch_scatter_block(s, nt, op->g->N, op->g->d_i2c, Y, (c128*)y + (int64_t)r0 * ldy, ldy, cnt);
         }
         CHECK(hip_check(ctx, hipGetLastError(), "apply launch"));
@@ -1001,16 +1012,22 @@ qrvie_status qrvie_solve(qrvie_ctx* ctx, const qrvie_op* op, int32_t nrhs, const
     if (!o || o->restart < 1 || o->restart > 16384 || o->max_iter < 1 || !(o->tol > 0.0) ||
         (o->mode != QRVIE_SOLVE_FP64 && o->mode != QRVIE_SOLVE_MIXED_IR && o->mode != QRVIE_SOLVE_BLOCK &&
          o->mode != QRVIE_SOLVE_BLOCK_IR) ||
-        !(o->inner_tol >= 0.0 && o->inner_tol < 1.0) || o->block_width < 0 || o->block_width > kMaxBlockRhs) {
+        !(o->inner_tol >= 0.0 && o->inner_tol < 1.0) || o->block_width < 0 || o->block_width > kMaxBlockRhs ||
+        (o->inner_fp32 != 0 && o->inner_fp32 != 1)) {
         set_err(ctx, "solve: invalid options");
         return QRVIE_ERR_INVALID_ARG;
     }
-    if ((o->mode == QRVIE_SOLVE_MIXED_IR || o->mode == QRVIE_SOLVE_BLOCK_IR) && !(op->d_fac32 && op->d_fac)) {
+    if (o->mode == QRVIE_SOLVE_MIXED_IR && !(op->d_fac32 && op->d_fac)) {
         set_err(ctx, "solve: mixed-precision refinement needs an operator built with far_prec = QRVIE_PREC_C64");
         return QRVIE_ERR_INVALID_ARG;
     }
-    if ((o->mode == QRVIE_SOLVE_BLOCK || o->mode == QRVIE_SOLVE_BLOCK_IR) && op->shared) {
-        set_err(ctx, "solve: the block modes need an operator built without share_transpose");
+    if (o->mode == QRVIE_SOLVE_BLOCK_IR && !op->d_fac32) {
+        set_err(ctx, "solve: block refinement needs complex64 factors (far_prec C64, C64_ONLY or BF16X2)");
+        return QRVIE_ERR_INVALID_ARG;
+    }
+    if (o->mode == QRVIE_SOLVE_BLOCK_IR && !op->d_fac && !op->d_fac16 && !o->inner_fp32) {
+        set_err(ctx, "solve: block refinement on complex64-only factors needs inner_fp32 = 1 (the corrections "
+                     "would otherwise use the residual operator itself)");
         return QRVIE_ERR_INVALID_ARG;
     }
     if (o->mode == QRVIE_SOLVE_BLOCK_IR) return solve_block_ir(ctx, op, nrhs, (const c128*)v, ldv, (c128*)x, ldx, o, info);
