@@ -201,13 +201,14 @@ def block(args) -> int:
     est = q.Operator.footprint_estimate(geom, eps=args.eps, max_block_rows=args.max_block_rows)
     print(f"[bench] block: {arr.name}, {geom.ndof} unknowns, operator footprint estimate {est / 1e9:.1f} GB "
           f"(complex128 form)", file=sys.stderr, flush=True)
-    op = q.Operator(ctx, geom, eps=args.eps, far_prec=far, max_block_rows=args.max_block_rows, verbose=True)
+    op = q.Operator(ctx, geom, eps=args.eps, far_prec=far, max_block_rows=args.max_block_rows, verbose=True,
+                    share_transpose=args.share)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     sw = W.sweep((nrhs + 1) // 2)
     v = q.rhs_plane_waves(ctx, geom, sw.theta_deg[:nrhs], sw.phi_deg[:nrhs], sw.pol[:nrhs])
     print(f"[bench] block: {arr.name}, {nrhs} right-hand sides, setup {setup_s:.1f} s", file=sys.stderr, flush=True)
-    tiles = None if args.no_tune else tune_tiles(op)
+    tiles = None if (args.no_tune or args.share) else tune_tiles(op)
     restart = args.block_basis
     for _ in range(args.warmup):
         op.solve(v, restart=restart, tol=args.tol, max_iter=args.max_iter, mode=q.SOLVE_BLOCK)
@@ -233,7 +234,10 @@ def block(args) -> int:
         single = {"s_per_solve": round(time.perf_counter() - t, 2), "iterations": inf1[0]["iterations"],
                   "converged": bool(inf1[0]["converged"]), "rel_res_true": inf1[0]["rel_res_true"]}
         print(f"[bench] single-vector FP64 solve: {single}", file=sys.stderr, flush=True)
-    prof = op.profile_block(nrhs=min(nrhs, args.block_width or 64), reps=5)
+    if args.share:      # the stage profiler takes per-block storage only
+        prof = {"product": {"ms": last_product_ms(infos), "flops": 0}}
+    else:
+        prof = op.profile_block(nrhs=min(nrhs, args.block_width or 64), reps=5)
     dom = max(prof, key=lambda k: prof[k]["ms"])
     ach = prof[dom]["flops"] / (prof[dom]["ms"] * 1e-3) / 1e12
     pt = sum(p["ms"] for p in prof.values())
@@ -262,6 +266,90 @@ def block(args) -> int:
                      "stage": dom, "algorithmic_flops": prof[dom]["flops"]},
     }))
     return 0
+
+
+def precision_pattern(args) -> int:
+    """The precision workload: far factors in BF16 split-complex (with the complex64 factors they
+    were rounded from, stored once per pair), corrections by block GMRES with the BF16 factors on
+    FP32 matrix cores and complex64 self blocks, FP64-accumulated residuals of the complex64
+    operator, 8 plane waves (4 angles in [-30, 30] deg x TE/TM).  With --ir-reference the same
+    right-hand sides are then solved by FP64 block GMRES on the complex128 factors of the same
+    array (another operator, built after this one is freed) and each wave's relative difference
+    is reported."""
+    import torch
+    import paper_2603_10586_amd as q
+    import workloads as W
+    if args.graded:
+        arr = W.batching()
+    else:
+        arr = W.precision(0) if args.side == 96 else W.random_lattice(args.side, seed=0)
+    ctx = q.Context(0)
+    geom = q.Geometry(ctx, arr)
+    cap = args.max_block_rows
+    est = q.Operator.footprint_estimate(geom, eps=args.eps, max_block_rows=cap, far_prec=q.PREC_BF16X2,
+                                        share_transpose=True)
+    print(f"[bench] precision: {arr.name}, {geom.ndof} unknowns, footprint estimate {est / 1e9:.1f} GB",
+          file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    op = q.Operator(ctx, geom, eps=args.eps, far_prec=q.PREC_BF16X2, max_block_rows=cap, share_transpose=True,
+                    verbose=True)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    st = op.stats()
+    print(f"[bench] precision: operator {st['device_bytes'] / 1e9:.1f} GB built in {setup:.1f} s", file=sys.stderr,
+          flush=True)
+    th = np.linspace(-30.0, 30.0, 4)
+    thetas, pols = np.concatenate([th, th]), np.array([0] * 4 + [1] * 4, dtype=np.int32)
+    v = q.rhs_plane_waves(ctx, geom, thetas, np.zeros(8), pols)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    x, info, status = op.solve(v, restart=args.block_basis, tol=args.tol, max_iter=args.max_iter,
+                               mode=q.SOLVE_BLOCK_IR, verbose=True)
+    torch.cuda.synchronize()
+    t_ir = time.perf_counter() - t
+    print(f"[bench] precision: BF16 refinement {t_ir:.1f} s, {info[0]['iterations']} block steps, "
+          f"{info[0]['n_refine']} corrections, true residuals {max(i['rel_res_true'] for i in info):.2e}",
+          file=sys.stderr, flush=True)
+    out = {"metric": METRIC, "value": round(8 / t_ir, 4) if all(i["converged"] for i in info) else None,
+           "unit": "RHS solves/s", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": round(t_ir * 1e3, 1),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "bf16 far factors on f32 MFMA (inner), f64-accumulated c64 residuals", "data": "synthetic",
+           "config": {"workload": f"{arr.name}: {arr.n_particles} disks, {geom.ndof} unknowns, eps {args.eps:g}, "
+                                  f"8 plane waves, BF16 split-complex far factors, mixed-precision block refinement "
+                                  f"to {args.tol:g}, transpose-shared factors, block rows <= {cap}",
+                      "particles": arr.n_particles, "unknowns": geom.ndof, "basis_vectors": args.block_basis,
+                      "max_block_steps": args.max_iter},
+           "operator_device_bytes": st["device_bytes"], "footprint_estimate": est, "setup_s": round(setup, 1),
+           "mean_rank_level": [round(r, 1) for r in st["mean_rank_level"]],
+           "converged": [bool(i["converged"]) for i in info], "rel_res_true": [i["rel_res_true"] for i in info],
+           "block_steps": info[0]["iterations"], "corrections": info[0]["n_refine"]}
+    if args.ir_reference:
+        xh = x.cpu()
+        del x
+        op.close()
+        torch.cuda.empty_cache()
+        t0 = time.perf_counter()
+        op64 = q.Operator(ctx, geom, eps=args.eps, max_block_rows=cap, share_transpose=True, verbose=True)
+        t = time.perf_counter()
+        x64, i64, _ = op64.solve(v, restart=args.block_basis, tol=args.tol, max_iter=args.max_iter,
+                                 mode=q.SOLVE_BLOCK, verbose=True)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t
+        x64h = x64.cpu()
+        out["fp64_reference"] = {
+            "s": round(t64, 2), "build_s": round(t - t0, 1), "block_steps": i64[0]["iterations"],
+            "converged": [bool(i["converged"]) for i in i64], "rel_res_true": [i["rel_res_true"] for i in i64],
+            "rel_diff_per_rhs": [float(torch.linalg.norm(xh[r] - x64h[r]) / torch.linalg.norm(x64h[r]))
+                                 for r in range(8)]}
+        print(f"[bench] precision: FP64 reference {t64:.1f} s, per-RHS differences "
+              f"{max(out['fp64_reference']['rel_diff_per_rhs']):.2e}", file=sys.stderr, flush=True)
+    print(json.dumps(out))
+    return 0
+
+
+def last_product_ms(infos) -> float:
+    i = infos[-1][0]
+    return i["t_apply_s"] / max(i["n_apply"], 1) * 1e3
 
 
 def main() -> int:
@@ -299,7 +387,8 @@ def main() -> int:
                     help="with --mixed-ir: also solve in plain FP64 and report per-RHS differences")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the block and mixed-precision forms in the default line")
-    ap.add_argument("--graded", action="store_true", help="block mode on the 64 x 64 graded metalens array")
+    ap.add_argument("--graded", action="store_true",
+                    help="block and precision modes on the 64 x 64 graded metalens array")
     ap.add_argument("--c64-only", action="store_true", help="block mode with complex64 far factors only")
     ap.add_argument("--block-basis", type=int, default=16384, help="block mode: basis vectors per cycle")
     ap.add_argument("--max-block-rows", type=int, default=0, help="split far blocks taller than this")
@@ -308,6 +397,10 @@ def main() -> int:
                     help="block mode: also time one single-vector FP64 solve of the first wave")
     ap.add_argument("--mixed-ir", action="store_true",
                     help="iterative refinement: complex64 far factors inside, complex128 residuals outside")
+    ap.add_argument("--precision", action="store_true",
+                    help="the precision workload (96 x 96 random array by default, --side to change): BF16 "
+                         "corrections on FP32 matrix cores, 8 plane waves")
+    ap.add_argument("--share", action="store_true", help="block mode: transpose-shared far factors")
     ap.add_argument("--no-share", action="store_true",
                     help="store every ordered far block's factors (no transpose sharing) for the single-vector line")
     ap.add_argument("--gmres50-steps", type=int, default=2000,
@@ -358,6 +451,8 @@ def main() -> int:
         return serving(args)
     if args.block:
         return block(args)
+    if args.precision:
+        return precision_pattern(args)
 
     arr = W.mid(0) if args.side == 32 else W.random_lattice(args.side, seed=0)
     inc = W.mid_incidence()

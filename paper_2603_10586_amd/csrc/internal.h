@@ -121,6 +121,7 @@ struct PackDesc {                   // copy compact factors into panel layouts
     const c128* src; int32_t rows, cols, lds; // src (rows x cols), column-major
     c128* dst; int64_t ldd; int32_t transpose; // dst(i,j) = src(i,j) or src(j,i)
     float2* dst32;                  // when set: complex64 panel, rounded to nearest (dst unused)
+    const float2* src32;            // when set: complex64 compact factors (src unused)
 };
 struct AsmDesc {                    // far block assembly: rows of particles r0.., cols c0..
     c128* B; int64_t ldb;

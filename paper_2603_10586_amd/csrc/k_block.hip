@@ -683,10 +683,9 @@ __global__ void __launch_bounds__(256) k_ls_factor(int k, int p, c128* __restric
 // Split-K partial products of C = A^H B (A: n x m, B: n x c, both column-major): chunk z of
 // the rows writes P[z m c + i + j m] = sum over its rows e of conj(A[e, i]) B[e, j].  The
 // outputs are small against a reduction over 10^5-10^6 rows, so the rows are split into
-// chunks and a fixed-order kernel sums the partials (deterministic).  A workgroup owns a 64 x 64
-// tile of C for one chunk; each wave a 32 x 32 quadrant as 2 x 2 tiles of the FP64 MFMA.
-// The chunk's rows are consumed 16 at a time: the 16 x 64 slices of A and B are staged in LDS
-// (the next slice is loaded into registers while the MFMAs run on the current one).
+// chunks and a fixed-order kernel sums the partials (deterministic).  A workgroup owns a
+// tile of C for one chunk (below).  The chunk's rows are consumed 16 at a time: the slices of
+// A and B are staged in LDS.
 // conj(a) b: re += a.re b.re + a.im b.im, im += a.re b.im - a.im b.re.
 __device__ __forceinline__ void cmfma_conj(v4d& re, v4d& im, c128 a, c128 b) {
     re = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, re, 0, 0, 0);
@@ -697,55 +696,62 @@ __device__ __forceinline__ void cmfma_conj(v4d& re, v4d& im, c128 a, c128 b) {
 
 constexpr int kHnRows = 16;                 // rows per staged slice
 constexpr int kHnPad = kHnRows + 1;         // LDS row pitch of a staged column (bank spread)
+constexpr int kHnTM = 128, kHnTC = 64;      // workgroup tile of C
 
+// A workgroup owns a 128 x 64 tile of C for one row chunk; wave w a 64 x 32 block of it (4 x 2
+// FP64 MFMA tiles, so every staged A element feeds 2 and every B element 4 tiles).  The next
+// 16-row slice is loaded into registers while the MFMAs run on the staged one.
 __global__ void __launch_bounds__(256) k_gemm_hn_part(int64_t n, int m, int c, const c128* __restrict__ A, int64_t lda,
                                                       const c128* __restrict__ B, int64_t ldb, int64_t L,
                                                       c128* __restrict__ P) {
-    __shared__ c128 As[64 * kHnPad];
-    __shared__ c128 Bs[64 * kHnPad];
+    __shared__ c128 As[kHnTM * kHnPad];
+    __shared__ c128 Bs[kHnTC * kHnPad];
     const int t = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63;
     const int rl = lane & 15, kq = lane >> 4;
-    const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+    const int i0 = blockIdx.x * kHnTM, j0 = blockIdx.y * kHnTC;
     const int64_t e0 = (int64_t)blockIdx.z * L, e1 = min(n, e0 + L);
-    const int qi = (w & 1) * 32, qj = (w >> 1) * 32;
-    // staging: thread t moves rows (t % 16) of columns t / 16 + 16 p, p < 4, of both slices
+    const int qi = (w & 1) * 64, qj = (w >> 1) * 32;
+    // staging: thread t moves row t % 16 of columns t / 16 + 16 p of both slices
     const int sr = t & 15, sc = t >> 4;
-    c128 ra[4], rb[4];
+    c128 ra[kHnTM / 16], rb[kHnTC / 16];
     auto load = [&](int64_t e) {
         const int64_t row = e + sr;
         const bool rok = row < e1;
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            const int ci = i0 + sc + 16 * p, cj = j0 + sc + 16 * p;
+        for (int p = 0; p < kHnTM / 16; ++p) {
+            const int ci = i0 + sc + 16 * p;
             ra[p] = rok && ci < m ? A[row + (int64_t)ci * lda] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int p = 0; p < kHnTC / 16; ++p) {
+            const int cj = j0 + sc + 16 * p;
             rb[p] = rok && cj < c ? B[row + (int64_t)cj * ldb] : make_double2(0.0, 0.0);
         }
     };
-    v4d re[2][2], im[2][2];
+    v4d re[4][2], im[4][2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) re[a][b] = im[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
     if (e0 < e1) load(e0);
     for (int64_t e = e0; e < e1; e += kHnRows) {
         __syncthreads();
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            As[(sc + 16 * p) * kHnPad + sr] = ra[p];
-            Bs[(sc + 16 * p) * kHnPad + sr] = rb[p];
-        }
+        for (int p = 0; p < kHnTM / 16; ++p) As[(sc + 16 * p) * kHnPad + sr] = ra[p];
+#pragma unroll
+        for (int p = 0; p < kHnTC / 16; ++p) Bs[(sc + 16 * p) * kHnPad + sr] = rb[p];
         __syncthreads();
         if (e + kHnRows < e1) load(e + kHnRows);
 #pragma unroll
         for (int ks = 0; ks < kHnRows / 4; ++ks) {
-            c128 a[2], b[2];
+            c128 a[4], b[2];
 #pragma unroll
-            for (int mt = 0; mt < 2; ++mt) a[mt] = As[(qi + 16 * mt + rl) * kHnPad + 4 * ks + kq];
+            for (int mt = 0; mt < 4; ++mt) a[mt] = As[(qi + 16 * mt + rl) * kHnPad + 4 * ks + kq];
 #pragma unroll
             for (int ct = 0; ct < 2; ++ct) b[ct] = Bs[(qj + 16 * ct + rl) * kHnPad + 4 * ks + kq];
 #pragma unroll
-            for (int mt = 0; mt < 2; ++mt)
+            for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
                 for (int ct = 0; ct < 2; ++ct) cmfma_conj(re[mt][ct], im[mt][ct], a[mt], b[ct]);
         }
@@ -753,7 +759,7 @@ __global__ void __launch_bounds__(256) k_gemm_hn_part(int64_t n, int m, int c, c
     const int64_t per = (int64_t)m * c;
     c128* out = P + (int64_t)blockIdx.z * per;
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
+    for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
@@ -885,7 +891,7 @@ void launch_sum_batches(hipStream_t s, int m, int c, int nb, const c128* P, c128
 void launch_gemm_hn_part(hipStream_t s, int64_t n, int m, int c, const c128* A, int64_t lda, const c128* B, int64_t ldb,
                          int nb, int64_t L, c128* P) {
     if (n <= 0 || m <= 0 || c <= 0 || nb <= 0) return;
-    const dim3 g((unsigned)((m + 63) / 64), (unsigned)((c + 63) / 64), (unsigned)nb);
+    const dim3 g((unsigned)((m + kHnTM - 1) / kHnTM), (unsigned)((c + kHnTC - 1) / kHnTC), (unsigned)nb);
     hipLaunchKernelGGL(k_gemm_hn_part, g, dim3(256), 0, s, n, m, c, A, lda, B, ldb, L, P);
 }
 void launch_tri_inv_upper(hipStream_t s, int k, const c128* U, int64_t ldu, c128* out, int64_t ldo) {

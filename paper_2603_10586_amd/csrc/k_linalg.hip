@@ -684,7 +684,8 @@ __global__ void __launch_bounds__(256) k_pack(const PackDesc* descs) {
     for (int64_t e = threadIdx.x; e < tot; e += 256) {
         const int i = (int)(e % d.rows), j = (int)(e / d.rows);
         const int64_t o = d.transpose ? j + i * d.ldd : i + j * d.ldd;
-        const c128 v = d.src[i + (int64_t)j * d.lds];
+        const int64_t si = i + (int64_t)j * d.lds;
+        const c128 v = d.src32 ? make_double2((double)d.src32[si].x, (double)d.src32[si].y) : d.src[si];
         if (d.dst32) d.dst32[o] = make_float2((float)v.x, (float)v.y);
         else d.dst[o] = v;
     }

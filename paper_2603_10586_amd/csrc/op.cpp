@@ -87,6 +87,8 @@ qrvie_status download(qrvie_ctx* ctx, std::vector<T>& v, const T* d, size_t n, c
 struct Factor {            // compact factors of one primary block
     c128* Q = nullptr;     // m x r, ld m
     c128* R = nullptr;     // r x n, ld r
+    float2* Q32 = nullptr; // the same rounded to complex64 (operators that keep only complex64)
+    float2* R32 = nullptr;
     int32_t rank = 0;
     double rel_err = 0.0;
 };
@@ -124,6 +126,7 @@ struct Builder {
     std::vector<Factor> fac;                        // per block (primary only filled)
     std::vector<std::pair<void*, size_t>> segments; // compact factor storage
     double eps;
+    bool compact32 = false;                         // round each chunk's compact factors to complex64
     // The materialised blocks of a chunk and the direct blocks' working copies live in two
     // grow-only buffers kept across chunks: allocating and releasing tens of GB per chunk
     // cost about as much host time as the chunk's kernels.
@@ -465,6 +468,27 @@ struct Builder {
                 f.rel_err = normB2[i] > 0.0 ? std::sqrt(err2[i] / normB2[i]) : 0.0;
             }
         }
+        if (compact32 && ctot > 0) {
+            // the operator keeps only complex64 factors: round this chunk's compact factors now,
+            // so the complex128 ones never accumulate over the whole build
+            float2* seg32 = nullptr;
+            CHECK(dalloc(ctx, (void**)&seg32, sizeof(float2) * (size_t)ctot, "compact complex64 factors"));
+            segments.push_back({(void*)seg32, sizeof(float2) * (size_t)ctot});
+            launch_to_c64(s, seg, seg32, ctot);
+            CHECK(hip_check(ctx, hipStreamSynchronize(s), "compact complex64 factors"));
+            for (size_t k = 0; k < segments.size(); ++k)
+                if (segments[k].first == (void*)seg) {
+                    dfree(ctx, seg, segments[k].second);
+                    segments.erase(segments.begin() + (int64_t)k);
+                    break;
+                }
+            for (size_t i = 0; i < nb; ++i) {
+                Factor& f = fac[ids[i]];
+                f.Q32 = seg32 + qo[i];
+                f.R32 = seg32 + ro[i];
+                f.Q = f.R = nullptr;
+            }
+        }
         // retry blocks that missed eps with a wider sketch
         std::vector<int32_t> rids, rk;
         for (size_t i = 0; i < nb; ++i) {
@@ -546,9 +570,10 @@ void op_footprint(const qrvie_geom* g, const qrvie_compress_opts* o, size_t* res
     // materialised bytes per chunk, in the build's chunk order: block, direct work copy,
     // sketch and projected sketch (doubled for the retries of a wider sketch)
     double acc = 0.0, dir = 0.0, sk = 0.0, best = 0.0;
+    double cprim = 0.0;                               // compact factors of the chunk
     auto flush = [&]() {
-        best = std::max(best, acc + dir + 2.0 * sk);
-        acc = dir = sk = 0.0;
+        best = std::max(best, acc + dir + 2.0 * sk + cprim);
+        acc = dir = sk = cprim = 0.0;
     };
     for (const BlockRec& b : blocks) {
         const double m = (double)b.rn * kNp, n = (double)b.cn * kNp;
@@ -562,6 +587,7 @@ void op_footprint(const qrvie_geom* g, const qrvie_compress_opts* o, size_t* res
         const double e = m * n;
         if (acc > 0.0 && acc + e > (double)chunk_elems) flush();
         acc += e;
+        cprim += (m + n) * r;
         if (b.rn <= kDirectMaxParticles && b.cn <= kDirectMaxParticles) dir += e;
         else {
             const double k = std::min<double>(kSketchStart, std::min(m, n));
@@ -579,7 +605,10 @@ void op_footprint(const qrvie_geom* g, const qrvie_compress_opts* o, size_t* res
         panels = 16.0 * panel_elems;
         panels_final = panels + (o->far_prec == QRVIE_PREC_C64 ? 8.0 * panel_elems : 0.0);
     }
-    const double seg = 16.0 * prim;                 // compact factors until they are packed
+    // compact factors until they are packed (rounded to complex64 chunk by chunk when the
+    // operator keeps only complex64)
+    const bool c32 = o->far_prec == QRVIE_PREC_C64_ONLY || o->far_prec == QRVIE_PREC_BF16X2;
+    const double seg = (c32 ? 8.0 : 16.0) * prim;
     const double pools = 16.0 * best;
     const double nstrips = tlen / 64.0 + (double)rpanels.size() + qstrips;
     const double other = 2.0 * (double)g->types.size() * kNp * kNp * 16.0 + 8.0 * tlen +
@@ -670,6 +699,7 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
 
     // block list, with the optional row cap splitting far pairs into child pairs
     Builder bld{op, ctx, g, split_blocks(g, o->max_block_rows), {}, {}, o->eps};
+    bld.compact32 = o->far_prec == QRVIE_PREC_C64_ONLY || o->far_prec == QRVIE_PREC_BF16X2;
     const size_t NB = bld.blocks.size();
     bld.fac.resize(NB);
 
@@ -942,18 +972,19 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
             const size_t j = (size_t)b.mirror;
             // destination: complex128 panels, or their complex64 rounding when only those are kept
             auto at = [&](int64_t off, int64_t ld, int32_t tr) {
-                return only32 ? PackDesc{nullptr, 0, 0, 0, nullptr, ld, tr, op->d_fac32 + off}
-                              : PackDesc{nullptr, 0, 0, 0, op->d_fac + off, ld, tr, nullptr};
+                return only32 ? PackDesc{nullptr, 0, 0, 0, nullptr, ld, tr, op->d_fac32 + off, nullptr}
+                              : PackDesc{nullptr, 0, 0, 0, op->d_fac + off, ld, tr, nullptr, nullptr};
             };
-            auto with = [](PackDesc d, const c128* src, int32_t rows, int32_t cols, int32_t lds) {
-                d.src = src; d.rows = rows; d.cols = cols; d.lds = lds;
+            // the compact source: complex128, or complex64 when the build rounded it per chunk
+            auto with = [](PackDesc d, const c128* src, const float2* src32, int32_t rows, int32_t cols, int32_t lds) {
+                d.src = src; d.src32 = src32; d.rows = rows; d.cols = cols; d.lds = lds;
                 return d;
             };
-            pd.push_back(with(at(op->q_off[i], mm, 0), f.Q, mm, r, mm));            // Q_IJ
-            pd.push_back(with(at(op->r_off[i], op->r_ld[i], 0), f.R, r, nn, r));    // R_IJ
-            if (sh) continue;                                                       // mirrors read these
-            pd.push_back(with(at(op->q_off[j], nn, 1), f.R, r, nn, r));             // Q_JI = R_IJ^T
-            pd.push_back(with(at(op->r_off[j], op->r_ld[j], 1), f.Q, mm, r, mm));   // R_JI = Q_IJ^T
+            pd.push_back(with(at(op->q_off[i], mm, 0), f.Q, f.Q32, mm, r, mm));            // Q_IJ
+            pd.push_back(with(at(op->r_off[i], op->r_ld[i], 0), f.R, f.R32, r, nn, r));    // R_IJ
+            if (sh) continue;                                                              // mirrors read these
+            pd.push_back(with(at(op->q_off[j], nn, 1), f.R, f.R32, r, nn, r));             // Q_JI = R_IJ^T
+            pd.push_back(with(at(op->r_off[j], op->r_ld[j], 1), f.Q, f.Q32, mm, r, mm));   // R_JI = Q_IJ^T
         }
         PackDesc* dpd = nullptr;
         if (!pd.empty()) {

@@ -80,15 +80,18 @@ inline void block_product(const qrvie_op* op, hipStream_t s, const BlockWork& bw
     }
     const bool l = lo || !op->d_fac;
     const int vr = op->tile_of(l, nt, 0), vq = op->tile_of(l, nt, 1), vs = op->tile_of(l, nt, 2);
+    // transposed strips read 4 consecutive entries per row and step: batches of 4 steps make
+    // each row's read 16 entries long (tile variant 2)
+    constexpr int kTransVariant = 2;
     if (l) {
-        if (op->shared) launch_strip_mfma(s, nt, op->d_mqt, op->n_mqt, op->d_fac32, X, bw.S, op->d_tinv, 0);
+        if (op->shared) launch_strip_mfma(s, nt, op->d_mqt, op->n_mqt, op->d_fac32, X, bw.S, op->d_tinv, kTransVariant);
         launch_strip_mfma(s, nt, op->d_mr, op->n_mr, op->d_fac32, X, bw.T, op->d_tmap, vr);
-        if (op->shared) launch_strip_mfma(s, nt, op->d_mrt, op->n_mrt, op->d_fac32, bw.S, bw.Ylev, nullptr, 0);
+        if (op->shared) launch_strip_mfma(s, nt, op->d_mrt, op->n_mrt, op->d_fac32, bw.S, bw.Ylev, nullptr, kTransVariant);
         launch_strip_mfma(s, nt, op->d_mq, op->n_mq, op->d_fac32, bw.T, bw.Ylev, nullptr, vq);
     } else {
-        if (op->shared) launch_strip_mfma(s, nt, op->d_mqt, op->n_mqt, op->d_fac, X, bw.S, op->d_tinv, 0);
+        if (op->shared) launch_strip_mfma(s, nt, op->d_mqt, op->n_mqt, op->d_fac, X, bw.S, op->d_tinv, kTransVariant);
         launch_strip_mfma(s, nt, op->d_mr, op->n_mr, op->d_fac, X, bw.T, op->d_tmap, vr);
-        if (op->shared) launch_strip_mfma(s, nt, op->d_mrt, op->n_mrt, op->d_fac, bw.S, bw.Ylev, nullptr, 0);
+        if (op->shared) launch_strip_mfma(s, nt, op->d_mrt, op->n_mrt, op->d_fac, bw.S, bw.Ylev, nullptr, kTransVariant);
         launch_strip_mfma(s, nt, op->d_mq, op->n_mq, op->d_fac, bw.T, bw.Ylev, nullptr, vq);
     }
     launch_strip_mfma(s, nt, op->d_ms, op->n_ms, op->d_self, X, bw.Yself, nullptr, vs);
