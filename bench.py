@@ -183,6 +183,47 @@ def serving(args) -> int:
     return 0
 
 
+def build_leg(args) -> int:
+    """One operator build (untimed elsewhere): wall time, compression time, blocks, ranks and
+    device bytes, for the sketch or the cross-approximation compression."""
+    import torch
+    import paper_2603_10586_amd as q
+    import workloads as W
+    arr = W.batching() if args.graded else (W.mid(0) if args.side == 32 else W.random_lattice(args.side, seed=0))
+    far = q.PREC_C64_ONLY if args.c64_only else q.PREC_C128
+    ctx = q.Context(0)
+    geom = q.Geometry(ctx, arr)
+    est = q.Operator.footprint_estimate(geom, eps=args.eps, max_block_rows=args.max_block_rows, far_prec=far,
+                                        compression=args.compression)
+    print(f"[bench] build: {arr.name}, {geom.ndof} unknowns, {args.compression}, cap {args.max_block_rows}, "
+          f"footprint estimate {est / 1e9:.1f} GB", file=sys.stderr, flush=True)
+    ctx.peak_bytes(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    op = q.Operator(ctx, geom, eps=args.eps, far_prec=far, max_block_rows=args.max_block_rows, verbose=True,
+                    share_transpose=args.share, compression=args.compression)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = op.stats()
+    sizes = {}
+    for b in range(op.num_blocks()):
+        i = op.export_block(b, factors=False)[0]
+        sizes[i["m"]] = max(sizes.get(i["m"], 0), i["rank"])
+    print(json.dumps({
+        "metric": "operator build s", "value": round(wall, 2), "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(wall * 1e3, 1), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{arr.name}: {arr.n_particles} disks, {geom.ndof} unknowns, eps {args.eps:g}",
+                   "compression": args.compression, "max_block_rows": args.max_block_rows,
+                   "far_prec": "c64" if args.c64_only else "c128", "share_transpose": bool(args.share)},
+        "t_compression_s": round(st["t_compression_s"], 2), "blocks": st["n_blocks"],
+        "max_block_rows_built": max(sizes), "max_rank_by_rows": {str(k): v for k, v in sorted(sizes.items())},
+        "mean_rank_level": [round(x, 1) for x in st["mean_rank_level"][:st["n_levels"] + 2]],
+        "max_block_rel_err": st["max_block_rel_err"], "operator_device_bytes": st["device_bytes"],
+        "build_peak_bytes": ctx.peak_bytes(), "footprint_estimate": est}))
+    return 0
+
+
 def block(args) -> int:
     """Block GMRES: 64 plane waves (32 angles x TE/TM) share one block Krylov space; the
     product runs on FP64 matrix cores.  A step is one solve of all right-hand sides."""
@@ -202,7 +243,7 @@ def block(args) -> int:
     print(f"[bench] block: {arr.name}, {geom.ndof} unknowns, operator footprint estimate {est / 1e9:.1f} GB "
           f"(complex128 form)", file=sys.stderr, flush=True)
     op = q.Operator(ctx, geom, eps=args.eps, far_prec=far, max_block_rows=args.max_block_rows, verbose=True,
-                    share_transpose=args.share)
+                    share_transpose=args.share, compression=args.compression)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     sw = W.sweep((nrhs + 1) // 2)
@@ -292,6 +333,7 @@ def precision_pattern(args) -> int:
           file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     op = q.Operator(ctx, geom, eps=args.eps, far_prec=q.PREC_BF16X2, max_block_rows=cap, share_transpose=True,
+                    compression=args.compression,
                     verbose=True)
     torch.cuda.synchronize()
     setup = time.perf_counter() - t0
@@ -329,7 +371,8 @@ def precision_pattern(args) -> int:
         op.close()
         torch.cuda.empty_cache()
         t0 = time.perf_counter()
-        op64 = q.Operator(ctx, geom, eps=args.eps, max_block_rows=cap, share_transpose=True, verbose=True)
+        op64 = q.Operator(ctx, geom, eps=args.eps, max_block_rows=cap, share_transpose=True, verbose=True,
+                          compression=args.compression)
         t = time.perf_counter()
         x64, i64, _ = op64.solve(v, restart=args.block_basis, tol=args.tol, max_iter=args.max_iter,
                                  mode=q.SOLVE_BLOCK, verbose=True)
@@ -392,6 +435,10 @@ def main() -> int:
     ap.add_argument("--c64-only", action="store_true", help="block mode with complex64 far factors only")
     ap.add_argument("--block-basis", type=int, default=16384, help="block mode: basis vectors per cycle")
     ap.add_argument("--max-block-rows", type=int, default=0, help="split far blocks taller than this")
+    ap.add_argument("--compression", choices=["sketch", "aca"], default="sketch",
+                    help="far-block compression: assembled blocks and a randomised sketch, or cross approximation")
+    ap.add_argument("--build", action="store_true",
+                    help="operator build leg: build time, ranks and memory of one operator (--side / --graded)")
     ap.add_argument("--block-width", type=int, default=0, help="block mode: right-hand sides per block (0 = 64)")
     ap.add_argument("--single-compare", action="store_true",
                     help="block mode: also time one single-vector FP64 solve of the first wave")
@@ -449,6 +496,8 @@ def main() -> int:
 
     if args.serving:
         return serving(args)
+    if args.build:
+        return build_leg(args)
     if args.block:
         return block(args)
     if args.precision:
@@ -464,7 +513,8 @@ def main() -> int:
     # and products read only the complex128 panels.  Block corrections need per-block storage.
     share = not args.no_share and not args.block_ir
     op = q.Operator(ctx, geom, eps=args.eps, far_prec=q.PREC_C64 if (args.mixed_ir or not args.no_forms) else q.PREC_C128,
-                    max_block_rows=args.max_block_rows, verbose=arr.n_particles > 1024, share_transpose=share)
+                    max_block_rows=args.max_block_rows, verbose=arr.n_particles > 1024, share_transpose=share,
+                    compression=args.compression)
     mode = q.SOLVE_BLOCK_IR if args.block_ir else (q.SOLVE_MIXED_IR if args.mixed_ir else q.SOLVE_FP64)
     restart = args.block_basis if args.block_ir else args.restart
     torch.cuda.synchronize()

@@ -163,6 +163,19 @@ enum { QRVIE_PREC_C128 = 0, QRVIE_PREC_C64 = 1, QRVIE_PREC_BF16X2 = 2, QRVIE_PRE
  *   chunk_bytes      device bytes of materialised blocks compressed together; 0 = a
  *                    quarter of the free device memory (or of the context's remaining
  *                    budget), at most 64 GiB.  Larger chunks keep more blocks in flight.
+ *                    With compression = 1: the bytes of the cross approximations' working
+ *                    buffers (about 32 (m + n) k per block of k crosses).
+ *   compression      0: blocks of more than 2 x 2 particles are assembled and compressed
+ *                    through a randomised sketch.  1: cross approximation (the compression of
+ *                    §6.5, after Kurz et al. 2002): only the pivot rows and columns of such a
+ *                    block are generated (256 crosses at first, continued up to 512 when all are
+ *                    used, stopping at 0.1 eps), the crosses are recompressed by a truncated pivoted
+ *                    QR at 0.9 eps, and the factors are certified against every entry of the
+ *                    block generated again, so eq. 5.3 holds exactly as with the sketch; a block
+ *                    that misses eps after two tighter rounds is compressed by the sketch path.
+ *                    No far block is materialised, so max_block_rows is only needed above
+ *                    147456 rows (1024 particles), where the operator splits blocks by itself.
+ *                    Blocks of at most 2 x 2 particles use the direct pivoted QR either way.
  */
 typedef struct {
     double eps;
@@ -173,6 +186,7 @@ typedef struct {
     uint64_t seed;
     int32_t verbose;
     int64_t chunk_bytes;
+    int32_t compression;
 } qrvie_compress_opts;
 
 #define QRVIE_MAX_LEVELS 24

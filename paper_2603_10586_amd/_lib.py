@@ -27,7 +27,7 @@ class ArrayDescC(C.Structure):
 class CompressOpts(C.Structure):
     _fields_ = [("eps", C.c_double), ("far_prec", C.c_int32), ("near_prec", C.c_int32),
                 ("max_block_rows", C.c_int64), ("share_transpose", C.c_int32), ("seed", C.c_uint64),
-                ("verbose", C.c_int32), ("chunk_bytes", C.c_int64)]
+                ("verbose", C.c_int32), ("chunk_bytes", C.c_int64), ("compression", C.c_int32)]
 
 
 class OpStats(C.Structure):

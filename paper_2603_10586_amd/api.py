@@ -225,17 +225,25 @@ def rhs_plane_waves(ctx: Context, geom: Geometry, theta_deg, phi_deg, pol):
     return v
 
 
+def _compression(name: str) -> int:
+    """'sketch' (assembled blocks, randomised range sketch) or 'aca' (cross approximation)."""
+    try:
+        return {"sketch": 0, "aca": 1}[name]
+    except KeyError:
+        raise ValueError(f"compression must be 'sketch' or 'aca', not {name!r}") from None
+
+
 class Operator:
     """The compressed interaction operator Z_QR with its block-diagonal preconditioner."""
 
     def __init__(self, ctx: Context, geom: Geometry, eps: float = 1e-6, max_block_rows: int = 0, seed: int = 0,
                  far_prec: int = L.PREC_C128, verbose: bool = False, chunk_bytes: int = 0,
-                 share_transpose: bool = False):
+                 share_transpose: bool = False, compression: str = "sketch"):
         self.ctx, self.geom, self.far_prec = ctx, geom, far_prec
         self.shared = bool(share_transpose)
         o = L.CompressOpts(eps=eps, far_prec=far_prec, near_prec=L.PREC_C128, max_block_rows=max_block_rows,
                            share_transpose=1 if share_transpose else 0, seed=seed, verbose=1 if verbose else 0,
-                           chunk_bytes=chunk_bytes)
+                           chunk_bytes=chunk_bytes, compression=_compression(compression))
         self.opts = o
         h = C.c_void_p()
         ctx.check(ctx.lib.qrvie_op_create(ctx.h, geom.h, C.byref(o), C.byref(h)), "op_create")
@@ -244,9 +252,9 @@ class Operator:
 
     @staticmethod
     def footprint_estimate(geom: Geometry, eps: float = 1e-6, max_block_rows: int = 0, far_prec: int = L.PREC_C128,
-                           chunk_bytes: int = 0, share_transpose: bool = False) -> int:
+                           chunk_bytes: int = 0, share_transpose: bool = False, compression: str = "sketch") -> int:
         o = L.CompressOpts(eps=eps, far_prec=far_prec, max_block_rows=max_block_rows, chunk_bytes=chunk_bytes,
-                           share_transpose=1 if share_transpose else 0)
+                           share_transpose=1 if share_transpose else 0, compression=_compression(compression))
         out = C.c_size_t()
         st = geom.ctx.lib.qrvie_op_footprint_estimate(geom.h, C.byref(o), C.byref(out))
         geom.ctx.check(st, "footprint")

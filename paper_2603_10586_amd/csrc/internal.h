@@ -123,6 +123,29 @@ struct PackDesc {                   // copy compact factors into panel layouts
     float2* dst32;                  // when set: complex64 panel, rounded to nearest (dst unused)
     const float2* src32;            // when set: complex64 compact factors (src unused)
 };
+// Cross approximation of a far block (rows: particles r0.., columns: c0..) without assembling
+// it: U (m x kmax, ld m), V (kmax x n, stored by rows, ld n); the number of crosses goes to
+// *rank_out.
+constexpr int kAcaMaxRows = 147456;        // 1024 particles (used-row flags in LDS)
+constexpr int kAcaMaxRank = 512;
+struct AcaDesc {
+    int32_t r0, rn, c0, cn;
+    c128* U; c128* V;
+    int32_t kmax;
+    double eps;                     // stopping tolerance on the newest cross
+    int32_t* rank_out;
+    int32_t k0;                     // crosses already in U, V (a resumed approximation)
+    int32_t* piv;                   // kmax pivot rows, in order (read for the first k0)
+    double* state;                  // [running Frobenius estimate, next pivot row], kept for a resume
+};
+// Certification of factors Q (m x r, ld ldq) R (r x n, ld ldr) of a far block against its
+// entries generated on the fly (48 x 48 tiles).
+struct CertDesc {
+    int32_t r0, rn, c0, cn;
+    const c128* Q; int32_t ldq;
+    const c128* R; int32_t ldr;
+    int32_t r;
+};
 struct AsmDesc {                    // far block assembly: rows of particles r0.., cols c0..
     c128* B; int64_t ldb;
     int32_t r0, rn, c0, cn;
@@ -265,6 +288,15 @@ void launch_assemble_far(hipStream_t s, const qrvie_geom* g, const AsmDesc* d_de
 void launch_assemble_lists(hipStream_t s, const qrvie_geom* g, const int32_t* d_rows, int32_t nr,
                            const int32_t* d_cols, int32_t nc, c128* B, int64_t ldb);
 void launch_rhs(hipStream_t s, const qrvie_geom* g, int nrhs, const double* d_par, c128* v, int64_t ldv);
+// wide: 1024 threads per block (for blocks of many rows and columns), else 256
+void launch_aca(hipStream_t s, const qrvie_geom* g, const AcaDesc* d, int n, bool wide);
+// Certification of far-block factors against entries generated on the fly: workgroup w of
+// the launch writes partial[w] = ||B - Q R||^2 and partial[nwg + w] = ||B||^2 over its region;
+// the workgroups of descriptor i are [wg_first[i], wg_first[i + 1]), cert_workgroups(rn, cn)
+// of them per block.
+void launch_cert_fused(hipStream_t s, const qrvie_geom* g, const CertDesc* d, const int64_t* wg_first, int nd,
+                       int64_t nwg, double* partial);
+int64_t cert_workgroups(int32_t rn, int32_t cn);
 void launch_permute(hipStream_t s, int32_t N, const int32_t* d_i2c, const c128* in, c128* out, int to_internal);
 
 // dense linear algebra (k_linalg.hip)

@@ -81,6 +81,7 @@ __device__ __forceinline__ c128 rand_c(uint64_t seed, int64_t i, int64_t j) {
 // --------------------------------------------------------------------- GEMM
 // mode 0: C = A B        mode 1: C = A^H B      mode 2: C = A Omega(seed)
 // mode 3: partial[tile] = ||C - A B||^2 over the tile (C is read, not written)
+// mode 4: C = A B with B stored by rows (B(k, j) at B[j + k ldb])
 constexpr int TM = 64, TN = 64, TK = 16;
 
 template <int MODE>
@@ -117,11 +118,14 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc* descs, const int32
         // B tile: B(kk, j)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int kk = tid & 15, j = (tid >> 4) + 16 * q;
+            int kk, j;
+            if (MODE == 4) { j = tid & 63; kk = (tid >> 6) + 4 * q; }
+            else { kk = tid & 15; j = (tid >> 4) + 16 * q; }
             const int gk = k0 + kk, gj = n0 + j;
             c128 v = make_double2(0.0, 0.0);
             if (gk < d.k && gj < d.n) {
                 if (MODE == 2) v = rand_c(d.seed, gk, gj);
+                else if (MODE == 4) v = d.B[(int64_t)gj + (int64_t)gk * d.ldb];
                 else v = d.B[(int64_t)gk + (int64_t)gj * d.ldb];
             }
             Bs[kk][j] = v;
@@ -783,6 +787,7 @@ void launch_gemm(hipStream_t s, int mode, const GemmDesc* d, const int32_t* td, 
         case 0: hipLaunchKernelGGL(k_gemm<0>, g, b, 0, s, d, td, tmn, nullptr); break;
         case 1: hipLaunchKernelGGL(k_gemm<1>, g, b, 0, s, d, td, tmn, nullptr); break;
         case 2: hipLaunchKernelGGL(k_gemm<2>, g, b, 0, s, d, td, tmn, nullptr); break;
+        case 4: hipLaunchKernelGGL(k_gemm<4>, g, b, 0, s, d, td, tmn, nullptr); break;
         default: break;
     }
 }

@@ -115,6 +115,9 @@ void gemm_tiles(const std::vector<GemmDesc>& d, std::vector<int32_t>& td, std::v
 constexpr int kDirectMaxParticles = 2;   // both sides at most this many particles: direct QRCP
 constexpr int kSketchStart = 128;
 constexpr int kMaxSketch = 512;          // widest sketch the CGS2 kernel orthonormalises
+constexpr int kAcaStart = 256;           // crosses per block at first (doubled while all are used)
+constexpr double kAcaEps = 0.1;          // stopping tolerance of the crosses, relative to eps
+constexpr int64_t kAcaWide = 2 * 4608;   // rows plus columns above which a block gets 16 waves
 constexpr int kPhaseWaves = 4;           // waves per strip in the product kernels
 constexpr int64_t kAlign = 16;           // R-panel leading dimension multiple: 128 B in complex64, 256 B in complex128
 
@@ -167,6 +170,35 @@ struct Builder {
         segments.push_back({(void*)*p, elems * sizeof(c128)});
         return QRVIE_OK;
     }
+
+    // When the operator keeps only complex64 factors, round a chunk's compact factors (blocks
+    // `sel` of `ids`, at offsets qo / ro in seg) as soon as they are certified, so the
+    // complex128 ones never accumulate over the whole build.
+    qrvie_status round_segment(c128* seg, int64_t ctot, const std::vector<size_t>& sel, const std::vector<int32_t>& ids,
+                               const std::vector<int64_t>& qo, const std::vector<int64_t>& ro) {
+        if (!compact32 || ctot <= 0) return QRVIE_OK;
+        float2* seg32 = nullptr;
+        CHECK(dalloc(ctx, (void**)&seg32, sizeof(float2) * (size_t)ctot, "compact complex64 factors"));
+        segments.push_back({(void*)seg32, sizeof(float2) * (size_t)ctot});
+        launch_to_c64(ctx->stream, seg, seg32, ctot);
+        CHECK(hip_check(ctx, hipStreamSynchronize(ctx->stream), "compact complex64 factors"));
+        for (size_t k = 0; k < segments.size(); ++k)
+            if (segments[k].first == (void*)seg) {
+                dfree(ctx, seg, segments[k].second);
+                segments.erase(segments.begin() + (int64_t)k);
+                break;
+            }
+        for (size_t i : sel) {
+            Factor& f = fac[ids[i]];
+            f.Q32 = seg32 + qo[i];
+            f.R32 = seg32 + ro[i];
+            f.Q = f.R = nullptr;
+        }
+        return QRVIE_OK;
+    }
+
+    qrvie_status compress_aca(const std::vector<int32_t>& ids, const std::vector<int32_t>& kmx,
+                              const std::vector<double>& eaca, std::vector<int32_t>& fallback);
 
     // Compress the primary blocks `ids`; sketch width k[i] (0 = direct QRCP).
     qrvie_status compress(const std::vector<int32_t>& ids, const std::vector<int32_t>& kw) {
@@ -468,26 +500,10 @@ struct Builder {
                 f.rel_err = normB2[i] > 0.0 ? std::sqrt(err2[i] / normB2[i]) : 0.0;
             }
         }
-        if (compact32 && ctot > 0) {
-            // the operator keeps only complex64 factors: round this chunk's compact factors now,
-            // so the complex128 ones never accumulate over the whole build
-            float2* seg32 = nullptr;
-            CHECK(dalloc(ctx, (void**)&seg32, sizeof(float2) * (size_t)ctot, "compact complex64 factors"));
-            segments.push_back({(void*)seg32, sizeof(float2) * (size_t)ctot});
-            launch_to_c64(s, seg, seg32, ctot);
-            CHECK(hip_check(ctx, hipStreamSynchronize(s), "compact complex64 factors"));
-            for (size_t k = 0; k < segments.size(); ++k)
-                if (segments[k].first == (void*)seg) {
-                    dfree(ctx, seg, segments[k].second);
-                    segments.erase(segments.begin() + (int64_t)k);
-                    break;
-                }
-            for (size_t i = 0; i < nb; ++i) {
-                Factor& f = fac[ids[i]];
-                f.Q32 = seg32 + qo[i];
-                f.R32 = seg32 + ro[i];
-                f.Q = f.R = nullptr;
-            }
+        {
+            std::vector<size_t> all(nb);
+            for (size_t i = 0; i < nb; ++i) all[i] = i;
+            CHECK(round_segment(seg, ctot, all, ids, qo, ro));
         }
         // retry blocks that missed eps with a wider sketch
         std::vector<int32_t> rids, rk;
@@ -509,6 +525,300 @@ struct Builder {
         return QRVIE_OK;
     }
 };
+
+// Working buffers of one chunk of cross-approximated blocks, in complex128 elements: U and V
+// (m + n) kmax, the orthonormalised copy of U (m kmax) and the projected rows (kmax n).
+int64_t aca_elems(const BlockRec& b, int kmax) { return 2 * ((int64_t)b.rn + b.cn) * kNp * kmax; }
+
+// Compression through cross approximation (compression = 1): the block B is never formed.
+//  1. U V ~ B from k pivot rows and columns of B (k_aca, stopping tolerance eps_aca);
+//  2. Y = orth(U) (CGS2), T = Y^H U, W = T V (so Y W = U V);
+//  3. truncated pivoted QR of W at 0.9 eps relative to ||W||_F: W ~ Q_W R, Q = Y Q_W;
+//  4. certification of ||B - Q R||_F against the entries of B generated again, tile by tile.
+// A block that misses eps is redone with a tighter eps_aca (and twice the crosses when it
+// used them all); after that the sketch path compresses it from the assembled block.
+qrvie_status Builder::compress_aca(const std::vector<int32_t>& ids, const std::vector<int32_t>& kmx,
+                                   const std::vector<double>& eaca, std::vector<int32_t>& fallback) {
+    hipStream_t s = ctx->stream;
+    Arena ar(ctx);
+    for (int32_t id : ids)
+        if ((int64_t)blocks[id].rn * kNp > kAcaMaxRows || kmx.empty()) {
+            set_err(ctx, "cross approximation: block rows beyond the row flags");
+            return QRVIE_ERR_INVALID_ARG;
+        }
+    const size_t nb = ids.size();
+    std::vector<int64_t> m(nb), n(nb), uo(nb), vo(nb);
+    int64_t utot = 0, vtot = 0;
+    for (size_t i = 0; i < nb; ++i) {
+        const BlockRec& b = blocks[ids[i]];
+        m[i] = (int64_t)b.rn * kNp;
+        n[i] = (int64_t)b.cn * kNp;
+        uo[i] = utot; utot += m[i] * kmx[i];
+        vo[i] = vtot; vtot += n[i] * kmx[i];
+    }
+    c128 *dU0, *dV0;
+    CHECK(pooled(0, (size_t)utot, &dU0, "cross approximation columns"));
+    CHECK(pooled(1, (size_t)vtot, &dV0, "cross approximation rows"));
+    std::vector<c128*> U(nb), V(nb);                  // per block: m x cap (ld m), cap x n (by rows, ld n)
+    std::vector<int32_t> cap(kmx);
+    for (size_t i = 0; i < nb; ++i) { U[i] = dU0 + uo[i]; V[i] = dV0 + vo[i]; }
+    int32_t *dk, *dpiv; double* dstate;
+    CHECK(ar.alloc(&dk, nb, "cross approximation ranks"));
+    CHECK(ar.alloc(&dpiv, nb * (size_t)kAcaMaxRank, "pivot rows"));
+    CHECK(ar.alloc(&dstate, 2 * nb, "cross approximation state"));
+    std::vector<int32_t> k(nb, 0);
+    std::vector<size_t> run(nb);
+    for (size_t i = 0; i < nb; ++i) run[i] = i;
+    // blocks that use every cross before meeting eps_aca continue in buffers twice as wide
+    while (!run.empty()) {
+        // blocks of more than kAcaWide rows plus columns get 16 waves (their steps stream the
+        // longest rows and columns), the others 4
+        std::vector<AcaDesc> ad[2];
+        for (size_t i : run) {
+            const BlockRec& b = blocks[ids[i]];
+            ad[m[i] + n[i] > kAcaWide].push_back(AcaDesc{b.r0, b.rn, b.c0, b.cn, U[i], V[i], cap[i], eaca[i], dk + i,
+                                                         k[i], dpiv + i * (size_t)kAcaMaxRank, dstate + 2 * i});
+        }
+        for (int w = 0; w < 2; ++w) {
+            AcaDesc* dad;
+            CHECK(ar.upload(&dad, ad[w], "aca descs"));
+            launch_aca(s, g, dad, (int)ad[w].size(), w == 1);
+        }
+        CHECK(hip_check(ctx, hipGetLastError(), "cross approximation"));
+        std::vector<int32_t> hk;
+        CHECK(download(ctx, hk, dk, nb, "cross approximation ranks"));
+        std::vector<size_t> more;
+        for (size_t i : run) {
+            k[i] = hk[i];
+            const int32_t full = (int32_t)std::min<int64_t>(std::min(m[i], n[i]), kAcaMaxRank);
+            if (k[i] >= cap[i] && cap[i] < full) more.push_back(i);
+        }
+        for (size_t i : more) {
+            const int32_t c2 = (int32_t)std::min<int64_t>(2 * (int64_t)cap[i], std::min<int64_t>(std::min(m[i], n[i]), kAcaMaxRank));
+            c128 *u2, *v2;
+            CHECK(ar.alloc(&u2, (size_t)(m[i] * c2), "cross approximation columns"));
+            CHECK(ar.alloc(&v2, (size_t)(n[i] * c2), "cross approximation rows"));
+            CHECK(hip_check(ctx, hipMemcpyAsync(u2, U[i], sizeof(c128) * m[i] * k[i], hipMemcpyDeviceToDevice, s),
+                            "cross approximation columns"));
+            CHECK(hip_check(ctx, hipMemcpyAsync(v2, V[i], sizeof(c128) * n[i] * k[i], hipMemcpyDeviceToDevice, s),
+                            "cross approximation rows"));
+            U[i] = u2;
+            V[i] = v2;
+            cap[i] = c2;
+        }
+        run = more;
+    }
+    std::vector<size_t> act;
+    for (size_t i = 0; i < nb; ++i) {
+        if (k[i] == 0) fallback.push_back(ids[i]);
+        else act.push_back(i);
+    }
+    const size_t na = act.size();
+    std::vector<int64_t> yo(nb, 0), wo(nb, 0);
+    int64_t ytot = 0;
+    for (size_t i : act) { yo[i] = ytot; ytot += m[i] * k[i]; }
+    c128* dY;
+    CHECK(ar.alloc(&dY, ytot, "cross approximation basis"));
+    std::vector<int32_t> kept(nb, 0);
+    if (na) {
+        for (size_t i : act)
+            CHECK(hip_check(ctx, hipMemcpyAsync(dY + yo[i], U[i], sizeof(c128) * m[i] * k[i],
+                                                hipMemcpyDeviceToDevice, s), "basis copy"));
+        std::vector<Cgs2Desc> cd;
+        int32_t* dkept;
+        CHECK(ar.alloc(&dkept, na, "kept"));
+        int kmax = 0;
+        for (size_t a = 0; a < na; ++a) {
+            const size_t i = act[a];
+            cd.push_back(Cgs2Desc{dY + yo[i], (int32_t)m[i], k[i], (int32_t)m[i], 1e-12, dkept + a});
+            kmax = std::max(kmax, k[i]);
+        }
+        Cgs2Desc* dcd;
+        CHECK(ar.upload(&dcd, cd, "cgs2 descs"));
+        launch_cgs2(s, dcd, (int)na, kmax);
+        CHECK(hip_check(ctx, hipGetLastError(), "cross approximation basis"));
+        std::vector<int32_t> hk;
+        CHECK(download(ctx, hk, dkept, na, "kept"));
+        for (size_t a = 0; a < na; ++a) kept[act[a]] = hk[a];
+    }
+    // T = Y^H U (kept x k), then W = T V (kept x n)
+    int64_t ttot = 0, wtot = 0;
+    std::vector<int64_t> to(nb, 0);
+    for (size_t i : act) {
+        to[i] = ttot; ttot += (int64_t)kept[i] * k[i];
+        wo[i] = wtot; wtot += (int64_t)kept[i] * n[i];
+    }
+    c128 *dT, *dW;
+    CHECK(ar.alloc(&dT, ttot, "cross approximation T"));
+    CHECK(ar.alloc(&dW, wtot, "projected rows"));
+    auto gemm = [&](int mode, const std::vector<GemmDesc>& gd) -> qrvie_status {
+        if (gd.empty()) return QRVIE_OK;
+        std::vector<int32_t> td, tmn;
+        gemm_tiles(gd, td, tmn);
+        GemmDesc* dgd; int32_t *dtd, *dtmn;
+        CHECK(ar.upload(&dgd, gd, "gemm descs"));
+        CHECK(ar.upload(&dtd, td, "gemm tiles"));
+        CHECK(ar.upload(&dtmn, tmn, "gemm tiles"));
+        launch_gemm(s, mode, dgd, dtd, dtmn, (int64_t)td.size());
+        return hip_check(ctx, hipGetLastError(), "gemm");
+    };
+    {
+        std::vector<GemmDesc> g1, g0;
+        for (size_t i : act) {
+            if (kept[i] == 0) continue;
+            g1.push_back(GemmDesc{dY + yo[i], m[i], U[i], m[i], dT + to[i], kept[i], kept[i], k[i],
+                                  (int32_t)m[i], 0, nullptr});
+            g0.push_back(GemmDesc{dT + to[i], kept[i], V[i], n[i], dW + wo[i], kept[i], kept[i],
+                                  (int32_t)n[i], k[i], 0, nullptr});
+        }
+        CHECK(gemm(1, g1));
+        CHECK(gemm(4, g0));
+    }
+    // truncated pivoted QR of W
+    std::vector<int64_t> wsn(nb, 0), wsk(nb, 0);
+    int64_t tot_n = 0, tot_k = 0;
+    for (size_t i : act) {
+        wsn[i] = tot_n; tot_n += n[i];
+        wsk[i] = tot_k; tot_k += std::min<int64_t>(kept[i], n[i]);
+    }
+    double *dcn, *dtau, *dtol2, *dtrail, *dn2; int32_t *dperm, *drank; c128* dwtop;
+    CHECK(ar.alloc(&dcn, std::max<int64_t>(tot_n, 1), "qrcp norms"));
+    CHECK(ar.alloc(&dperm, std::max<int64_t>(tot_n, 1), "qrcp perm"));
+    CHECK(ar.alloc(&dtau, std::max<int64_t>(tot_k, 1), "qrcp tau"));
+    CHECK(ar.alloc(&dwtop, std::max<int64_t>(tot_k, 1), "qrcp w"));
+    CHECK(ar.alloc(&dtol2, std::max<size_t>(nb, 1), "qrcp tolerances"));
+    CHECK(ar.alloc(&dtrail, std::max<size_t>(nb, 1), "trail"));
+    CHECK(ar.alloc(&dn2, std::max<size_t>(nb, 1), "norm2"));
+    CHECK(ar.alloc(&drank, std::max<size_t>(nb, 1), "ranks"));
+    CHECK(hip_check(ctx, hipMemsetAsync(drank, 0, sizeof(int32_t) * nb, s), "ranks"));
+    std::vector<QrcpDesc> qd;
+    std::vector<size_t> qi;
+    int maxrows = 0, maxcols = 0, maxsteps = 0;
+    for (size_t i : act) {
+        if (kept[i] == 0) continue;
+        QrcpDesc q{};
+        q.A = dW + wo[i];
+        q.m = kept[i];
+        q.n = (int32_t)n[i];
+        q.lda = kept[i];
+        q.kmax = (int32_t)std::min<int64_t>(kept[i], n[i]);
+        q.colnorm2 = dcn + wsn[i];
+        q.perm = dperm + wsn[i];
+        q.tau = dtau + wsk[i];
+        q.wtop = dwtop + wsk[i];
+        q.rel2 = (0.9 * eps) * (0.9 * eps);
+        q.base2 = 0.0;
+        q.sub2 = 0.0;
+        q.rank_out = drank + i;
+        q.trail2_out = dtrail + i;
+        q.norm2_out = dn2 + i;
+        q.tol2_state = dtol2 + i;
+        qd.push_back(q);
+        qi.push_back(i);
+        maxrows = std::max(maxrows, q.m);
+        maxcols = std::max(maxcols, q.n);
+        maxsteps = std::max(maxsteps, q.kmax);
+    }
+    QrcpDesc* dqd;
+    CHECK(ar.upload(&dqd, qd, "qrcp descs"));
+    launch_qrcp_stepped(s, dqd, (int)qd.size(), maxrows, maxcols, maxsteps);
+    CHECK(hip_check(ctx, hipGetLastError(), "qrcp"));
+    std::vector<int32_t> rank;
+    CHECK(download(ctx, rank, drank, nb, "ranks"));
+    // compact factors: Q = Y Q_W, R from W
+    int64_t ctot = 0;
+    std::vector<int64_t> qo(nb, 0), ro(nb, 0);
+    for (size_t i : act) {
+        qo[i] = ctot; ctot += m[i] * rank[i];
+        ro[i] = ctot; ctot += (int64_t)rank[i] * n[i];
+    }
+    c128* seg;
+    CHECK(new_segment(ctot, &seg));
+    {
+        int64_t qwtot = 0;
+        std::vector<int64_t> qwo(nb, 0);
+        for (size_t i : act) { qwo[i] = qwtot; qwtot += (int64_t)kept[i] * rank[i]; }
+        c128* dQW;
+        CHECK(ar.alloc(&dQW, qwtot, "projected Q"));
+        std::vector<FormQDesc> fd;
+        std::vector<GemmDesc> gd;
+        std::vector<ExtractRDesc> ed;
+        for (size_t a = 0; a < qd.size(); ++a) {
+            const size_t i = qi[a];
+            if (rank[i] == 0) continue;
+            fd.push_back(FormQDesc{dW + wo[i], kept[i], kept[i], rank[i], dtau + wsk[i], dwtop + wsk[i], dQW + qwo[i],
+                                   kept[i]});
+            gd.push_back(GemmDesc{dY + yo[i], m[i], dQW + qwo[i], kept[i], seg + qo[i], m[i], (int32_t)m[i], rank[i],
+                                  kept[i], 0, nullptr});
+            ed.push_back(ExtractRDesc{dW + wo[i], kept[i], rank[i], (int32_t)n[i], dperm + wsn[i], seg + ro[i], rank[i]});
+        }
+        FormQDesc* dfd;
+        ExtractRDesc* ded;
+        CHECK(ar.upload(&dfd, fd, "formq descs"));
+        CHECK(ar.upload(&ded, ed, "extract descs"));
+        launch_form_q(s, dfd, (int)fd.size(), maxrows);
+        CHECK(gemm(0, gd));
+        launch_extract_r(s, ded, (int)ed.size());
+        CHECK(hip_check(ctx, hipGetLastError(), "form factors"));
+    }
+    // certification against regenerated entries
+    std::vector<double> err2(nb, 0.0), nrm2(nb, 0.0);
+    if (na) {
+        std::vector<CertDesc> cd;
+        std::vector<int64_t> first;
+        int64_t nwg = 0;
+        for (size_t i : act) {
+            const BlockRec& b = blocks[ids[i]];
+            cd.push_back(CertDesc{b.r0, b.rn, b.c0, b.cn, seg + qo[i], (int32_t)m[i], seg + ro[i], std::max(rank[i], 1),
+                                  rank[i]});
+            first.push_back(nwg);
+            nwg += cert_workgroups(b.rn, b.cn);
+        }
+        first.push_back(nwg);
+        std::vector<int32_t> pf, pc;
+        for (size_t a = 0; a < na; ++a) {
+            pf.push_back((int32_t)first[a]);
+            pc.push_back((int32_t)(first[a + 1] - first[a]));
+        }
+        for (size_t a = 0; a < na; ++a) pf.push_back((int32_t)(nwg + first[a]));
+        if (2 * nwg >= ((int64_t)1 << 31)) { set_err(ctx, "certification: too many tiles in one chunk"); return QRVIE_ERR_INVALID_ARG; }
+        CertDesc* dcd; int64_t* dfirst; int32_t *dpf, *dpc; double *dpart, *dsum;
+        CHECK(ar.upload(&dcd, cd, "cert descs"));
+        CHECK(ar.upload(&dfirst, first, "cert workgroups"));
+        CHECK(ar.upload(&dpf, pf, "cert partials"));
+        CHECK(ar.upload(&dpc, pc, "cert partials"));
+        CHECK(ar.alloc(&dpart, 2 * (size_t)nwg, "cert partials"));
+        CHECK(ar.alloc(&dsum, 2 * na, "cert sums"));
+        launch_cert_fused(s, g, dcd, dfirst, (int)na, nwg, dpart);
+        launch_sum_partials(s, dpart, dpf, dpc, dsum, (int)na);
+        launch_sum_partials(s, dpart, dpf + na, dpc, dsum + na, (int)na);
+        CHECK(hip_check(ctx, hipGetLastError(), "certify"));
+        std::vector<double> hs;
+        CHECK(download(ctx, hs, dsum, 2 * na, "cert sums"));
+        for (size_t a = 0; a < na; ++a) { err2[act[a]] = hs[a]; nrm2[act[a]] = hs[na + a]; }
+    }
+    std::vector<int32_t> retry_ids, retry_k;
+    std::vector<double> retry_e;
+    for (size_t i : act) {
+        Factor& f = fac[ids[i]];
+        f.Q = seg + qo[i];
+        f.R = seg + ro[i];
+        f.rank = rank[i];
+        f.rel_err = nrm2[i] > 0.0 ? std::sqrt(err2[i] / nrm2[i]) : 0.0;
+        if (f.rel_err <= eps) continue;
+        if (eaca[i] > 5e-4 * eps) {                       // two rounds at a tenth of the tolerance
+            retry_ids.push_back(ids[i]);
+            retry_k.push_back(cap[i]);
+            retry_e.push_back(eaca[i] * 0.1);
+        } else {
+            fallback.push_back(ids[i]);
+        }
+    }
+    CHECK(round_segment(seg, ctot, act, ids, qo, ro));
+    ar.release();
+    if (!retry_ids.empty()) return compress_aca(retry_ids, retry_k, retry_e, fallback);
+    return QRVIE_OK;
+}
 
 // Chunk size of the build when chunk_bytes = 0: a quarter of the free device memory (or of
 // the context's remaining budget), between 256 MB and 64 GiB.
@@ -562,7 +872,10 @@ std::vector<BlockRec> split_blocks(const qrvie_geom* g, int64_t cap) {
 }
 
 void op_footprint(const qrvie_geom* g, const qrvie_compress_opts* o, size_t* resident, size_t* transient) {
-    const std::vector<BlockRec> blocks = split_blocks(g, o->max_block_rows);
+    const bool aca = o->compression == 1;
+    const std::vector<BlockRec> blocks = split_blocks(
+        g, aca ? (o->max_block_rows > 0 ? std::min<int64_t>(o->max_block_rows, kAcaMaxRows) : kAcaMaxRows)
+               : o->max_block_rows);
     const int64_t chunk_elems =
         std::max<int64_t>(1, (o->chunk_bytes > 0 ? o->chunk_bytes : ((int64_t)64 << 30)) / (int64_t)sizeof(c128));
     double fac = 0.0, prim = 0.0, tlen = 0.0, rpad = 0.0, qstrips = 0.0;
@@ -575,6 +888,12 @@ void op_footprint(const qrvie_geom* g, const qrvie_compress_opts* o, size_t* res
         best = std::max(best, acc + dir + 2.0 * sk + cprim);
         acc = dir = sk = cprim = 0.0;
     };
+    // cross approximation: its chunks hold the crosses, their basis and projected rows
+    double aacc = 0.0, acprim = 0.0;
+    auto aflush = [&]() {
+        best = std::max(best, aacc + acprim);
+        aacc = acprim = 0.0;
+    };
     for (const BlockRec& b : blocks) {
         const double m = (double)b.rn * kNp, n = (double)b.cn * kNp;
         const double r = std::min(rank_model(std::max(m, n), o->eps), std::min(m, n));
@@ -584,6 +903,14 @@ void op_footprint(const qrvie_geom* g, const qrvie_compress_opts* o, size_t* res
         rpanels[{b.level, b.c0}] = b.cn;
         if (!b.primary) continue;
         prim += (m + n) * r;
+        const bool small = b.rn <= kDirectMaxParticles && b.cn <= kDirectMaxParticles;
+        if (aca && !small) {
+            const double e = (double)aca_elems(b, (int)std::min<double>(kAcaStart, std::min(m, n)));
+            if (aacc > 0.0 && aacc + e > (double)chunk_elems) aflush();
+            aacc += e;
+            acprim += (m + n) * r;
+            continue;
+        }
         const double e = m * n;
         if (acc > 0.0 && acc + e > (double)chunk_elems) flush();
         acc += e;
@@ -595,6 +922,7 @@ void op_footprint(const qrvie_geom* g, const qrvie_compress_opts* o, size_t* res
         }
     }
     flush();
+    aflush();
     for (const auto& kv : rpanels) rpad += (double)(kAlign - 1) * kv.second * kNp;
     for (int32_t id = 0; id < (int32_t)g->nodes.size(); ++id) qstrips += std::ceil(g->nodes[id].count * kNp / 64.0);
     const double panel_elems = fac + rpad;
@@ -639,7 +967,7 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
     if ((o->far_prec != QRVIE_PREC_C128 && o->far_prec != QRVIE_PREC_C64 && o->far_prec != QRVIE_PREC_C64_ONLY &&
          o->far_prec != QRVIE_PREC_BF16X2) ||
         o->near_prec != QRVIE_PREC_C128 ||
-        (o->share_transpose != 0 && o->share_transpose != 1) ||
+        (o->share_transpose != 0 && o->share_transpose != 1) || (o->compression != 0 && o->compression != 1) ||
         o->max_block_rows < 0 || o->chunk_bytes < 0) {
         set_err(ctx, "op_create: unsupported precision or option");
         return QRVIE_ERR_INVALID_ARG;
@@ -697,8 +1025,12 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
     const double t1 = now_s();
     op->stats.t_precond_setup_s = t1 - t0;
 
-    // block list, with the optional row cap splitting far pairs into child pairs
-    Builder bld{op, ctx, g, split_blocks(g, o->max_block_rows), {}, {}, o->eps};
+    // block list, with the optional row cap splitting far pairs into child pairs (cross
+    // approximation keeps one flag per row in LDS: its blocks have at most kAcaMaxRows rows)
+    const bool aca = o->compression == 1;
+    const int64_t cap = aca ? (o->max_block_rows > 0 ? std::min<int64_t>(o->max_block_rows, kAcaMaxRows) : kAcaMaxRows)
+                            : o->max_block_rows;
+    Builder bld{op, ctx, g, split_blocks(g, cap), {}, {}, o->eps};
     bld.compact32 = o->far_prec == QRVIE_PREC_C64_ONLY || o->far_prec == QRVIE_PREC_BF16X2;
     const size_t NB = bld.blocks.size();
     bld.fac.resize(NB);
@@ -709,16 +1041,68 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
     // and concurrent builds on one device still leave room for each other)
     const int64_t chunk_elems =
         std::max<int64_t>(1, (o->chunk_bytes > 0 ? o->chunk_bytes : (int64_t)auto_chunk_bytes(ctx)) / (int64_t)sizeof(c128));
+    std::vector<int32_t> fallback;          // cross approximation: blocks left to the sketch path
+    if (aca) {
+        std::vector<int32_t> ids, kmx;
+        std::vector<double> ea;
+        int64_t acc = 0;
+        size_t nprim = 0, ndone = 0;
+        for (const BlockRec& b : bld.blocks)
+            nprim += b.primary && !(b.rn <= kDirectMaxParticles && b.cn <= kDirectMaxParticles) ? 1 : 0;
+        for (size_t i = 0; i <= NB; ++i) {
+            if (i < NB) {
+                const BlockRec& b = bld.blocks[i];
+                if (!b.primary || (b.rn <= kDirectMaxParticles && b.cn <= kDirectMaxParticles)) continue;
+                const int kmax = (int)std::min<int64_t>(kAcaStart, (int64_t)std::min(b.rn, b.cn) * kNp);
+                const int64_t e = aca_elems(b, kmax);
+                if (acc == 0 || acc + e <= chunk_elems) {
+                    ids.push_back((int32_t)i);
+                    kmx.push_back(kmax);
+                    ea.push_back(kAcaEps * o->eps);
+                    acc += e;
+                    continue;
+                }
+            }
+            if (!ids.empty()) {
+                st = bld.compress_aca(ids, kmx, ea, fallback);
+                if (st != QRVIE_OK) {
+                    for (auto& sg : bld.segments) dfree(ctx, sg.first, sg.second);
+                    return fail(st);
+                }
+                ndone += ids.size();
+                if (o->verbose) {
+                    std::fprintf(stderr, "[qrvie] cross approximation: %zu / %zu blocks (%.1f s)\n", ndone, nprim,
+                                 now_s() - t1);
+                    std::fflush(stderr);
+                }
+            }
+            ids.clear();
+            kmx.clear();
+            ea.clear();
+            acc = 0;
+            if (i < NB) --i;   // re-visit the block that did not fit
+        }
+        bld.release_pools();                // the direct and sketch passes size their own
+        if (o->verbose && !fallback.empty()) {
+            std::fprintf(stderr, "[qrvie] cross approximation: %zu blocks left to the sketch path\n", fallback.size());
+            std::fflush(stderr);
+        }
+    }
     {
         std::vector<int32_t> ids, kw;
         int64_t acc = 0;
         size_t nprim = 0, ndone = 0;
-        for (const BlockRec& b : bld.blocks) nprim += b.primary ? 1 : 0;
+        std::vector<char> sketch_ok(NB, aca ? 0 : 1);
+        for (int32_t f : fallback) sketch_ok[f] = 1;
+        auto mine = [&](const BlockRec& b, size_t i) {
+            return b.primary && (sketch_ok[i] || (b.rn <= kDirectMaxParticles && b.cn <= kDirectMaxParticles));
+        };
+        for (size_t i = 0; i < NB; ++i) nprim += mine(bld.blocks[i], i) ? 1 : 0;
         for (size_t i = 0; i <= NB; ++i) {
             bool flush = (i == NB);
             if (!flush) {
                 const BlockRec& b = bld.blocks[i];
-                if (!b.primary) continue;
+                if (!mine(b, i)) continue;
                 const int64_t e = (int64_t)b.rn * kNp * b.cn * kNp;
                 if (acc > 0 && acc + e > chunk_elems) flush = true;
                 if (!flush) {
