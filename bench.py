@@ -435,8 +435,8 @@ def main() -> int:
     ap.add_argument("--c64-only", action="store_true", help="block mode with complex64 far factors only")
     ap.add_argument("--block-basis", type=int, default=16384, help="block mode: basis vectors per cycle")
     ap.add_argument("--max-block-rows", type=int, default=0, help="split far blocks taller than this")
-    ap.add_argument("--compression", choices=["sketch", "aca"], default="sketch",
-                    help="far-block compression: assembled blocks and a randomised sketch, or cross approximation")
+    ap.add_argument("--compression", choices=["aca", "sketch"], default="aca",
+                    help="far-block compression: cross approximation, or assembled blocks and a randomised sketch")
     ap.add_argument("--build", action="store_true",
                     help="operator build leg: build time, ranks and memory of one operator (--side / --graded)")
     ap.add_argument("--block-width", type=int, default=0, help="block mode: right-hand sides per block (0 = 64)")

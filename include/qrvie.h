@@ -128,6 +128,7 @@ qrvie_status qrvie_assemble(qrvie_ctx* ctx, const qrvie_geom* g, int32_t nr, con
 /* ----------------------------------------------------------------- operator */
 enum { QRVIE_PREC_C128 = 0, QRVIE_PREC_C64 = 1, QRVIE_PREC_BF16X2 = 2, QRVIE_PREC_C64_ONLY = 3,
        QRVIE_PREC_C64_F32 = 4 };
+enum { QRVIE_COMPRESS_ACA = 0, QRVIE_COMPRESS_SKETCH = 1 };
 
 /*
  *   eps              per-block relative Frobenius tolerance of the low-rank
@@ -160,22 +161,26 @@ enum { QRVIE_PREC_C128 = 0, QRVIE_PREC_C64 = 1, QRVIE_PREC_BF16X2 = 2, QRVIE_PRE
  *                    refuse them (QRVIE_ERR_INVALID_ARG).
  *   seed             seed of the random sketches used by compression
  *   verbose          1: print one progress line per compression chunk to stderr
- *   chunk_bytes      device bytes of materialised blocks compressed together; 0 = a
- *                    quarter of the free device memory (or of the context's remaining
- *                    budget), at most 64 GiB.  Larger chunks keep more blocks in flight.
- *                    With compression = 1: the bytes of the cross approximations' working
- *                    buffers (about 32 (m + n) k per block of k crosses).
- *   compression      0: blocks of more than 2 x 2 particles are assembled and compressed
- *                    through a randomised sketch.  1: cross approximation (the compression of
- *                    §6.5, after Kurz et al. 2002): only the pivot rows and columns of such a
+ *   chunk_bytes      device bytes compressed together; 0 = a quarter of the free device
+ *                    memory (or of the context's remaining budget), at most 64 GiB.  Larger
+ *                    chunks keep more blocks in flight.  Cross approximation counts its working
+ *                    buffers (about 32 (m + n) k bytes per block of k crosses), the sketch path
+ *                    its materialised blocks.
+ *   compression      how blocks of more than 2 x 2 particles are compressed (smaller ones always
+ *                    by the truncated pivoted QR of the assembled block):
+ *                    QRVIE_COMPRESS_ACA (0, the default): cross approximation, the compression
+ *                    of §6.5 (after Kurz et al. 2002).  Only the pivot rows and columns of a
  *                    block are generated (256 crosses at first, continued up to 512 when all are
- *                    used, stopping at 0.1 eps), the crosses are recompressed by a truncated pivoted
- *                    QR at 0.9 eps, and the factors are certified against every entry of the
- *                    block generated again, so eq. 5.3 holds exactly as with the sketch; a block
- *                    that misses eps after two tighter rounds is compressed by the sketch path.
- *                    No far block is materialised, so max_block_rows is only needed above
- *                    147456 rows (1024 particles), where the operator splits blocks by itself.
- *                    Blocks of at most 2 x 2 particles use the direct pivoted QR either way.
+ *                    used, stopping at 0.1 eps); the crosses are recompressed by a truncated
+ *                    pivoted QR at 0.9 eps, and the factors are certified against every entry of
+ *                    the block generated again, so eq. 5.3 holds exactly as with the sketch.  A
+ *                    block that misses eps is redone twice with a tenfold tighter stopping
+ *                    tolerance, then by the sketch path.  No far block is materialised, so
+ *                    max_block_rows is not needed for memory; blocks above 147456 rows (1024
+ *                    particles) are split into their child pairs by the operator itself.
+ *                    QRVIE_COMPRESS_SKETCH (1): every block is assembled and compressed through
+ *                    a randomised range sketch (CGS2 basis, projection, truncated pivoted QR),
+ *                    certified against the assembled block.
  */
 typedef struct {
     double eps;

@@ -226,9 +226,9 @@ def rhs_plane_waves(ctx: Context, geom: Geometry, theta_deg, phi_deg, pol):
 
 
 def _compression(name: str) -> int:
-    """'sketch' (assembled blocks, randomised range sketch) or 'aca' (cross approximation)."""
+    """'aca' (cross approximation, the default) or 'sketch' (assembled blocks, randomised sketch)."""
     try:
-        return {"sketch": 0, "aca": 1}[name]
+        return {"aca": 0, "sketch": 1}[name]
     except KeyError:
         raise ValueError(f"compression must be 'sketch' or 'aca', not {name!r}") from None
 
@@ -238,7 +238,7 @@ class Operator:
 
     def __init__(self, ctx: Context, geom: Geometry, eps: float = 1e-6, max_block_rows: int = 0, seed: int = 0,
                  far_prec: int = L.PREC_C128, verbose: bool = False, chunk_bytes: int = 0,
-                 share_transpose: bool = False, compression: str = "sketch"):
+                 share_transpose: bool = False, compression: str = "aca"):
         self.ctx, self.geom, self.far_prec = ctx, geom, far_prec
         self.shared = bool(share_transpose)
         o = L.CompressOpts(eps=eps, far_prec=far_prec, near_prec=L.PREC_C128, max_block_rows=max_block_rows,
@@ -252,7 +252,7 @@ class Operator:
 
     @staticmethod
     def footprint_estimate(geom: Geometry, eps: float = 1e-6, max_block_rows: int = 0, far_prec: int = L.PREC_C128,
-                           chunk_bytes: int = 0, share_transpose: bool = False, compression: str = "sketch") -> int:
+                           chunk_bytes: int = 0, share_transpose: bool = False, compression: str = "aca") -> int:
         o = L.CompressOpts(eps=eps, far_prec=far_prec, max_block_rows=max_block_rows, chunk_bytes=chunk_bytes,
                            share_transpose=1 if share_transpose else 0, compression=_compression(compression))
         out = C.c_size_t()

@@ -530,7 +530,7 @@ struct Builder {
 // (m + n) kmax, the orthonormalised copy of U (m kmax) and the projected rows (kmax n).
 int64_t aca_elems(const BlockRec& b, int kmax) { return 2 * ((int64_t)b.rn + b.cn) * kNp * kmax; }
 
-// Compression through cross approximation (compression = 1): the block B is never formed.
+// Compression through cross approximation (the default): the block B is never formed.
 //  1. U V ~ B from k pivot rows and columns of B (k_aca, stopping tolerance eps_aca);
 //  2. Y = orth(U) (CGS2), T = Y^H U, W = T V (so Y W = U V);
 //  3. truncated pivoted QR of W at 0.9 eps relative to ||W||_F: W ~ Q_W R, Q = Y Q_W;
@@ -872,7 +872,7 @@ std::vector<BlockRec> split_blocks(const qrvie_geom* g, int64_t cap) {
 }
 
 void op_footprint(const qrvie_geom* g, const qrvie_compress_opts* o, size_t* resident, size_t* transient) {
-    const bool aca = o->compression == 1;
+    const bool aca = o->compression == QRVIE_COMPRESS_ACA;
     const std::vector<BlockRec> blocks = split_blocks(
         g, aca ? (o->max_block_rows > 0 ? std::min<int64_t>(o->max_block_rows, kAcaMaxRows) : kAcaMaxRows)
                : o->max_block_rows);
@@ -967,7 +967,8 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
     if ((o->far_prec != QRVIE_PREC_C128 && o->far_prec != QRVIE_PREC_C64 && o->far_prec != QRVIE_PREC_C64_ONLY &&
          o->far_prec != QRVIE_PREC_BF16X2) ||
         o->near_prec != QRVIE_PREC_C128 ||
-        (o->share_transpose != 0 && o->share_transpose != 1) || (o->compression != 0 && o->compression != 1) ||
+        (o->share_transpose != 0 && o->share_transpose != 1) ||
+        (o->compression != QRVIE_COMPRESS_ACA && o->compression != QRVIE_COMPRESS_SKETCH) ||
         o->max_block_rows < 0 || o->chunk_bytes < 0) {
         set_err(ctx, "op_create: unsupported precision or option");
         return QRVIE_ERR_INVALID_ARG;
@@ -1027,7 +1028,7 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
 
     // block list, with the optional row cap splitting far pairs into child pairs (cross
     // approximation keeps one flag per row in LDS: its blocks have at most kAcaMaxRows rows)
-    const bool aca = o->compression == 1;
+    const bool aca = o->compression == QRVIE_COMPRESS_ACA;
     const int64_t cap = aca ? (o->max_block_rows > 0 ? std::min<int64_t>(o->max_block_rows, kAcaMaxRows) : kAcaMaxRows)
                             : o->max_block_rows;
     Builder bld{op, ctx, g, split_blocks(g, cap), {}, {}, o->eps};

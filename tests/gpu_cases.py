@@ -34,16 +34,19 @@ ARRAYS = {
 
 
 class Case:
-    def __init__(self, name: str, eps: float = 1e-6, max_block_rows: int = 0, far_prec: int = 0):
+    def __init__(self, name: str, eps: float = 1e-6, max_block_rows: int = 0, far_prec: int = 0,
+                 compression: str = "aca"):
         import paper_2603_10586_amd as q
-        print(f"[gpu case] building {name} eps={eps} cap={max_block_rows} far_prec={far_prec}", flush=True)
+        print(f"[gpu case] building {name} eps={eps} cap={max_block_rows} far_prec={far_prec} {compression}",
+              flush=True)
         self.name = name
         self.eps = eps
         self.array = ARRAYS[name]()
         self.disc = discretise.Discretisation(self.array)
         self.ctx = ctx()
         self.geom = q.Geometry(self.ctx, self.array)
-        self.op = q.Operator(self.ctx, self.geom, eps=eps, max_block_rows=max_block_rows, far_prec=far_prec)
+        self.op = q.Operator(self.ctx, self.geom, eps=eps, max_block_rows=max_block_rows, far_prec=far_prec,
+                             compression=compression)
         self.order = self.geom.order()
         self._Z = None
         self._factors = None
@@ -73,10 +76,10 @@ class Case:
         return grouping.build_blocks(self.array.lattice_ij, self.array.nx, self.array.ny)
 
 
-def case(name: str, eps: float = 1e-6, max_block_rows: int = 0, far_prec: int = 0) -> Case:
-    key = (name, eps, max_block_rows, far_prec)
+def case(name: str, eps: float = 1e-6, max_block_rows: int = 0, far_prec: int = 0, compression: str = "aca") -> Case:
+    key = (name, eps, max_block_rows, far_prec, compression)
     if key not in _CACHE:
-        _CACHE[key] = Case(name, eps, max_block_rows, far_prec)
+        _CACHE[key] = Case(name, eps, max_block_rows, far_prec, compression)
     return _CACHE[key]
 
 
@@ -92,21 +95,24 @@ def to_host(t) -> np.ndarray:
 _MID = {}
 
 
-def mid():
+def mid(compression: str = "aca"):
     """The mid-size workload (32 x 32 disks, 147,456 unknowns, eps = 1e-6) on the GPU, with the
-    oracle's discretisation, the internal order and every block's export record."""
+    oracle's discretisation, the internal order and every block's export record; one operator
+    per compression, on one geometry."""
+    import paper_2603_10586_amd as q
     if not _MID:
-        import paper_2603_10586_amd as q
-        print("[gpu case] building mid 32x32 eps=1e-6", flush=True)
+        print("[gpu case] mid 32x32 geometry", flush=True)
         arr = W.mid(0)
-        c = ctx()
-        geom = q.Geometry(c, arr)
-        op = q.Operator(c, geom, eps=1e-6)
-        order = geom.order()
+        geom = q.Geometry(ctx(), arr)
+        _MID[None] = dict(arr=arr, disc=discretise.Discretisation(arr), geom=geom, order=geom.order())
+        _MID[None]["internal"] = np.argsort(_MID[None]["order"])
+    if compression not in _MID:
+        print(f"[gpu case] building mid 32x32 eps=1e-6 {compression}", flush=True)
+        base = _MID[None]
+        op = q.Operator(ctx(), base["geom"], eps=1e-6, compression=compression)
         infos = [op.export_block(b, factors=False)[0] for b in range(op.num_blocks())]
-        _MID.update(arr=arr, disc=discretise.Discretisation(arr), geom=geom, op=op, order=order, infos=infos,
-                    internal=np.argsort(order))
-    return _MID
+        _MID[compression] = dict(base, op=op, infos=infos)
+    return _MID[compression]
 
 
 def block_particles(order, info):

@@ -1,4 +1,4 @@
-"""Cross-approximation compression (compression='aca') against the oracle.
+"""Cross-approximation compression (compression='aca', the default) against the oracle.
 
 The operator's far blocks are compressed from pivot rows and columns generated on the device
 (§6.5: the compression step is a cross approximation after Kurz et al. 2002); no far block
@@ -19,7 +19,7 @@ import pytest
 
 from oracle import compressed, greens
 
-from gpu_cases import ARRAYS, block_particles, case, ctx, mid, to_dev, to_host
+from gpu_cases import ARRAYS, block_particles, case, mid, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -28,16 +28,17 @@ _OPS = {}
 
 
 def _aca(name, max_block_rows=0, far_prec=0, share_transpose=False):
-    """The array's oracle case plus an operator built by cross approximation."""
+    """The array's oracle case and its operator built by cross approximation."""
     import paper_2603_10586_amd as q
-    key = (name, max_block_rows, far_prec, share_transpose)
+    c = case(name, max_block_rows=max_block_rows, far_prec=far_prec)
+    if not share_transpose:
+        return c, c.op
+    key = (name, max_block_rows, far_prec)
     if key not in _OPS:
-        c = case(name)
-        print(f"[gpu case] cross approximation {name} cap={max_block_rows} far_prec={far_prec}", flush=True)
-        op = q.Operator(c.ctx, c.geom, eps=EPS, max_block_rows=max_block_rows, far_prec=far_prec,
-                        share_transpose=share_transpose, compression="aca")
-        _OPS[key] = (c, op)
-    return _OPS[key]
+        print(f"[gpu case] shared cross approximation {name} cap={max_block_rows} far_prec={far_prec}", flush=True)
+        _OPS[key] = q.Operator(c.ctx, c.geom, eps=EPS, max_block_rows=max_block_rows, far_prec=far_prec,
+                               share_transpose=True, compression="aca")
+    return c, _OPS[key]
 
 
 def _certify(disc, order, op, b, eps=EPS, svd_max_rows=2304, slab=None):
@@ -126,10 +127,8 @@ def test_blocks_beyond_the_sketch_row_cap_are_certified_without_one():
 def test_mid_blocks_are_certified_and_rows_meet_the_operator_bound():
     """Mid-size (32 x 32): sampled blocks of 9216, 2304, 576 and 144 rows certified; sampled
     rows of the product against the oracle's matrix-free rows (as for the sketch path)."""
-    import paper_2603_10586_amd as q
-    m = mid()
-    op = q.Operator(ctx(), m["geom"], eps=EPS, compression="aca")
-    infos = [op.export_block(b, factors=False)[0] for b in range(op.num_blocks())]
+    m = mid("aca")
+    op, infos = m["op"], m["infos"]
     seen = set()
     for b in _stratified(infos, 3, seed=41):
         seen.add(_certify(m["disc"], m["order"], op, int(b), slab=16)["m"])
@@ -145,12 +144,11 @@ def test_mid_blocks_are_certified_and_rows_meet_the_operator_bound():
         diff = np.linalg.norm(y[p * 144:(p + 1) * 144] - blk @ x)
         assert diff <= EPS * zoff * np.linalg.norm(x), (p, diff)
     # the recompressed crosses keep ranks close to the sketch path's (both truncated pivoted QR)
-    sk = m["op"].stats()["mean_rank_level"]
+    sk = mid("sketch")["op"].stats()["mean_rank_level"]
     ac = op.stats()["mean_rank_level"]
     for lvl, (a, s) in enumerate(zip(ac, sk)):
         if s > 0:
             assert a <= 1.1 * s + 2.0, (lvl, a, s)
-    op.close()
 
 
 def test_complex64_factors_and_shared_storage_from_crosses():

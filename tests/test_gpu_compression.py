@@ -1,4 +1,5 @@
-"""Compression parity at full size: the sketch path and the row cap against the oracle.
+"""Compression parity at full size: the sketch path (compression='sketch') and the row cap
+against the oracle.
 
 Small arrays only reach the direct pivoted-QR path (blocks of at most 2 x 2 particles) and
 576-row sketches.  Here the randomised-sketch path that builds every block of 2304 rows or
@@ -70,7 +71,7 @@ def _stratified(infos, per_level, seed, pick=None):
 
 def test_mid_sketch_blocks_are_certified_against_the_oracle():
     """Mid-size (32 x 32): blocks of 9216, 2304, 576 and 144 rows, sampled on every level."""
-    m = mid()
+    m = mid("sketch")
     levels = {}
     for b in _stratified(m["infos"], 3, seed=1):
         info = _certify(m["disc"], m["order"], m["op"], int(b))
@@ -81,7 +82,7 @@ def test_mid_sketch_blocks_are_certified_against_the_oracle():
 
 def test_mid_product_rows_meet_the_operator_bound_against_the_oracle():
     """F2 on sampled rows: the library's product against the oracle's independent Z."""
-    m = mid()
+    m = mid("sketch")
     n = m["geom"].ndof
     rng = np.random.default_rng(31)
     x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
@@ -99,7 +100,7 @@ def test_mid_product_rows_meet_the_operator_bound_against_the_oracle():
 def test_serving_array_edge_blocks_are_certified_against_the_oracle():
     """The 33 x 33 serving array with the serving row cap (9216): its 2304 x 144 edge blocks and
     a sample of every level, including split children of capped pairs."""
-    c = case("serving33", max_block_rows=9216)
+    c = case("serving33", max_block_rows=9216, compression="sketch")
     assert c.array.n_particles == 1089
     infos = [c.op.export_block(b, factors=False)[0] for b in range(c.op.num_blocks())]
     assert len(infos) == 42714
@@ -124,7 +125,7 @@ def test_row_cap_keeps_exact_coverage_and_certifies_every_block():
     exported blocks still cover each ordered pair of distinct particles exactly once, every
     block meets eps against the oracle, and the product meets the global bound against the
     dense Z."""
-    c = case("rand8x8", max_block_rows=288)
+    c = case("rand8x8", max_block_rows=288, compression="sketch")
     n = c.array.n_particles
     cover = _coverage_from_exports(c)
     assert np.array_equal(cover, 1 - np.eye(n, dtype=np.int64))
@@ -145,7 +146,7 @@ def test_row_cap_keeps_exact_coverage_and_certifies_every_block():
 def test_row_cap_splits_sketch_blocks_that_stay_certified():
     """rand16x16 with a cap of 576: 2304-row pairs become 576-row children, compressed on the
     sketch path; a sample per level is certified against the oracle."""
-    c = case("rand16x16", max_block_rows=576)
+    c = case("rand16x16", max_block_rows=576, compression="sketch")
     infos = [c.op.export_block(b, factors=False)[0] for b in range(c.op.num_blocks())]
     assert max(i["m"] for i in infos) == 576
     for b in _stratified(infos, 3, seed=4):
@@ -153,7 +154,7 @@ def test_row_cap_splits_sketch_blocks_that_stay_certified():
 
 
 @pytest.mark.parametrize("name,cap,far_prec", [("rand8x8", 288, 0), ("rand6x7", 0, 1), ("rand16x16", 576, 0)])
-def test_footprint_estimate_bounds_the_build(name, cap, far_prec):
+def test_footprint_estimate_bounds_the_sketch_build(name, cap, far_prec):
     """The estimate covers the built operator and the build's peak (transient buffers
     included), following the same capped block list."""
     import paper_2603_10586_amd as q
@@ -161,10 +162,12 @@ def test_footprint_estimate_bounds_the_build(name, cap, far_prec):
     arr = ARRAYS[name]()
     geom = q.Geometry(c.ctx, arr)
     chunk = 64 << 20
-    est = q.Operator.footprint_estimate(geom, eps=EPS, max_block_rows=cap, far_prec=far_prec, chunk_bytes=chunk)
+    est = q.Operator.footprint_estimate(geom, eps=EPS, max_block_rows=cap, far_prec=far_prec, chunk_bytes=chunk,
+                                        compression="sketch")
     base = c.ctx.bytes_in_use()
     c.ctx.peak_bytes(reset=True)
-    op = q.Operator(c.ctx, geom, eps=EPS, max_block_rows=cap, far_prec=far_prec, chunk_bytes=chunk)
+    op = q.Operator(c.ctx, geom, eps=EPS, max_block_rows=cap, far_prec=far_prec, chunk_bytes=chunk,
+                    compression="sketch")
     peak = c.ctx.peak_bytes() - base
     assert op.stats()["device_bytes"] <= est
     assert peak <= est, (peak, est)
