@@ -74,21 +74,36 @@ size_t       qrvie_ctx_peak_bytes(qrvie_ctx* ctx, int32_t reset);
 
 /* ----------------------------------------------------------------- geometry */
 /*
- * An array of disk meta-atoms (the paper's scatterers, §6.1; disks with the
- * voxel discretisation of the configured workloads).  All pointers are HOST
+ * An array of meta-atoms (the paper's scatterers, §6.1), each voxelised into 48
+ * cells with three current components per cell.  All pointers are HOST
  * pointers, read during the call only.
  *   n                  number of particles (>= 1)
  *   centers[n][3]      particle centres; the disks' axes are along z
- *   radius[n]          disk radius (> 0)
- *   height[n]          disk height (> 0)
+ *   radius[n]          disk or sphere radius (> 0)
+ *   height[n]          disk height (> 0; ignored for spheres)
  *   eps_r[n_eps]       relative permittivity; n_eps is 1 (shared) or n
- *   lattice_ij[n][2]   integer lattice site of each particle; sites must be
- *                      distinct.  Grouping follows the lattice (§5.4: a particle
- *                      belongs whole to the grid block containing its centre).
+ *   lattice_ij[n][2]   QRVIE_GRID_LATTICE: integer lattice site of each particle; sites
+ *                      must be distinct.  Grouping follows the lattice (§5.4: a particle
+ *                      belongs whole to the grid block containing its centre).  Ignored
+ *                      (may be NULL) with QRVIE_GRID_PAPER.
  *   pitch              lattice pitch (informational; centres are authoritative)
  *   wavelength         free-space wavelength (> 0)
- *   cells_per_particle must be 48 (24 in-plane squares x 2 layers)
+ *   cells_per_particle must be 48
+ *   shape              QRVIE_SHAPE_DISK (0): 24 in-plane squares of side r sqrt(pi/24) in two
+ *                      layers of height/2.  QRVIE_SHAPE_SPHERE (1): the voxelised sphere of the
+ *                      paper's test arrays (§6.1), 48 cubes of side h = r (pi/36)^(1/3) (the
+ *                      sphere's volume) in four layers, each the 12 squares of a 4 x 4 grid
+ *                      without its corners.
+ *   grid               QRVIE_GRID_LATTICE (0): a quadtree on the lattice sites, padded to 2^L
+ *                      per side.  QRVIE_GRID_PAPER (1): the paper's grid for arrays without a
+ *                      lattice (§5.3, §5.4): the root is the bounding square of the centres
+ *                      (side 1 + 2^-20 times the larger extent, centred on the bounding box),
+ *                      level l has 3 2^(l-1) blocks per side, each particle belongs to the block
+ *                      containing its centre, and the finest level L is the first at which no
+ *                      block holds two particles (at most 20; coincident centres are an error).
  */
+enum { QRVIE_SHAPE_DISK = 0, QRVIE_SHAPE_SPHERE = 1 };
+enum { QRVIE_GRID_LATTICE = 0, QRVIE_GRID_PAPER = 1 };
 typedef struct {
     int32_t n;
     const double* centers;
@@ -100,6 +115,8 @@ typedef struct {
     double pitch;
     double wavelength;
     int32_t cells_per_particle;
+    int32_t shape;
+    int32_t grid;
 } qrvie_array_desc;
 
 /* Discretise the array (paper §3 / the voxel reading) and build the recursive
@@ -111,6 +128,9 @@ int32_t      qrvie_geom_nlevels(const qrvie_geom* g);
 qrvie_status qrvie_geom_order(const qrvie_geom* g, int32_t* internal_to_caller);
 /* Cell centres [N*48][3] and cell volumes [N*48] in caller order (host buffers). */
 qrvie_status qrvie_geom_cells(const qrvie_geom* g, double* centers, double* volumes);
+/* The finest-level block (i, j) of each caller particle [N][2] (host buffer): the lattice
+ * site shifted to start at 0, or the paper-grid block of its centre. */
+qrvie_status qrvie_geom_blocks(const qrvie_geom* g, int32_t* block_ij);
 void         qrvie_geom_destroy(qrvie_geom* g);
 
 /*

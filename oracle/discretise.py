@@ -1,4 +1,4 @@
-"""Voxel discretisation of a disk meta-atom (oracle, FP64).
+"""Voxel discretisation of a disk or sphere meta-atom (oracle, FP64).
 
 The paper discretises the polarisation current with loop/star functions on a
 tetrahedral mesh (§3, eq. 3.1).  The configured workloads instead voxelise each
@@ -15,8 +15,11 @@ is the oracle's reading of that rule:
 * canonical order: layer (lower, upper), then b ascending, then a ascending;
   DoF index = (cell * 3 + component), component x, y, z fastest.
 
+Spheres (``sphere_cells``): 48 equal cubes, four layers of a 4 x 4 grid without corners.
+
 Pins (tests): 24 squares, volume exactness, symmetry of the offset set; the
-equal-volume sphere radius of a cell in closed form, (r^2 t / 64)^(1/3).
+equal-volume sphere radius of a cell in closed form, (r^2 t / 64)^(1/3); for spheres,
+48 distinct non-overlapping cubes whose volume is the sphere's, mirror symmetry in x, y, z.
 Unknowns are ordered particle by particle (§4, eq. 4.1).
 """
 from __future__ import annotations
@@ -56,6 +59,26 @@ def particle_cells(radius: float, height: float) -> tuple[np.ndarray, float]:
     return cells, vol
 
 
+def sphere_cells(radius: float) -> tuple[np.ndarray, float]:
+    """Voxelised sphere (the paper's meta-atom, §6.1; shape-only stand-in for its mesh):
+    48 cubes of side h with 48 h^3 = (4/3) pi r^3, i.e. h = r (pi/36)^(1/3), in four layers
+    z in {-3/2, -1/2, 1/2, 3/2} h; each layer holds the cubes of a 4 x 4 grid of centres
+    (x, y) in {-3/2, -1/2, 1/2, 3/2} h except the four with |x| = |y| = 3h/2.
+    Canonical order: layer, then y ascending, then x ascending."""
+    h = radius * (math.pi / 36.0) ** (1.0 / 3.0)
+    ticks = (-1.5, -0.5, 0.5, 1.5)
+    out = []
+    for z in ticks:
+        for y in ticks:
+            for x in ticks:
+                if abs(x) == 1.5 and abs(y) == 1.5:
+                    continue
+                out.append((x * h, y * h, z * h))
+    cells = np.array(out, dtype=np.float64)
+    assert cells.shape == (N_CELLS, 3)
+    return cells, h ** 3
+
+
 def equivalent_radius(volume: float) -> float:
     """Radius of the sphere with the cell's volume (used by the self term)."""
     return (3.0 * volume / (4.0 * math.pi)) ** (1.0 / 3.0)
@@ -73,8 +96,12 @@ class Discretisation:
         self.vol = np.zeros(n)
         self.a_eq = np.zeros(n)
         self.chi = np.asarray(array.eps_r, dtype=np.complex128) - 1.0
+        sphere = getattr(array, "shape", "disk") == "sphere"
         for p in range(n):
-            off, v = particle_cells(float(array.radius[p]), float(array.height[p]))
+            if sphere:
+                off, v = sphere_cells(float(array.radius[p]))
+            else:
+                off, v = particle_cells(float(array.radius[p]), float(array.height[p]))
             self.offsets[p] = off
             self.pos[p] = array.centers[p][None, :] + off
             self.vol[p] = v

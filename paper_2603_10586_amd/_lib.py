@@ -21,7 +21,7 @@ class ArrayDescC(C.Structure):
     _fields_ = [("n", C.c_int32), ("centers", C.POINTER(C.c_double)), ("radius", C.POINTER(C.c_double)),
                 ("height", C.POINTER(C.c_double)), ("eps_r", C.POINTER(C128)), ("n_eps", C.c_int32),
                 ("lattice_ij", C.POINTER(C.c_int32)), ("pitch", C.c_double), ("wavelength", C.c_double),
-                ("cells_per_particle", C.c_int32)]
+                ("cells_per_particle", C.c_int32), ("shape", C.c_int32), ("grid", C.c_int32)]
 
 
 class CompressOpts(C.Structure):
@@ -102,6 +102,7 @@ SIGNATURES = {
     "qrvie_geom_nlevels": (I32, [P]),
     "qrvie_geom_order": (ST, [P, C.POINTER(I32)]),
     "qrvie_geom_cells": (ST, [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "qrvie_geom_blocks": (ST, [P, C.POINTER(I32)]),
     "qrvie_geom_destroy": (None, [P]),
     "qrvie_assemble": (ST, [P, P, I32, C.POINTER(I32), I32, C.POINTER(I32), P, I64]),
     "qrvie_op_footprint_estimate": (ST, [P, C.POINTER(CompressOpts), C.POINTER(C.c_size_t)]),

@@ -112,7 +112,8 @@ def array_desc(array):
         radius=np.ascontiguousarray(array.radius, dtype=np.float64),
         height=np.ascontiguousarray(array.height, dtype=np.float64),
         eps=np.ascontiguousarray(np.asarray(array.eps_r, dtype=np.complex128).reshape(-1)),
-        ij=np.ascontiguousarray(array.lattice_ij, dtype=np.int32),
+        ij=np.ascontiguousarray(array.lattice_ij if getattr(array, "lattice_ij", None) is not None
+                                else np.zeros((len(array.centers), 2)), dtype=np.int32),
     )
     # the library reads n entries of each (n_eps = 1 or n): refuse mismatched lengths here
     n = int(keep["centers"].shape[0]) if keep["centers"].ndim == 2 else -1
@@ -132,6 +133,12 @@ def array_desc(array):
     d.pitch = float(getattr(array, "pitch", 0.0))
     d.wavelength = float(getattr(array, "wavelength", 1.0))
     d.cells_per_particle = int(getattr(array, "cells_per_particle", 48))
+    shape = getattr(array, "shape", "disk")
+    grid = getattr(array, "grid", "lattice")
+    if shape not in ("disk", "sphere") or grid not in ("lattice", "paper"):
+        raise ValueError(f"array: shape must be 'disk' or 'sphere' and grid 'lattice' or 'paper', got {shape!r}, {grid!r}")
+    d.shape = 0 if shape == "disk" else 1
+    d.grid = 0 if grid == "lattice" else 1
     return d, keep
 
 
@@ -154,6 +161,12 @@ class Geometry:
     def order(self) -> np.ndarray:
         out = np.zeros(self.n_particles, dtype=np.int32)
         self.ctx.check(self.ctx.lib.qrvie_geom_order(self.h, _dptr(out, C.c_int32)), "geom_order")
+        return out
+
+    def blocks(self) -> np.ndarray:
+        """Finest-level grid block (i, j) of each caller particle."""
+        out = np.zeros((self.n_particles, 2), dtype=np.int32)
+        self.ctx.check(self.ctx.lib.qrvie_geom_blocks(self.h, _dptr(out, C.c_int32)), "geom_blocks")
         return out
 
     def cells(self):

@@ -3,11 +3,17 @@
 // Discretisation: each disk becomes 24 in-plane squares of side h = r sqrt(pi/24)
 // (centres ((a+1/2)h, (b+1/2)h) with (a+1/2)^2 + (b+1/2)^2 <= 24/pi) in two layers at
 // z = -t/4 and z = +t/4; cell volume h^2 t / 2 (48 cells fill the disk volume exactly).
+// A sphere (the paper's meta-atom, §6.1) becomes 48 cubes of side h = r (pi/36)^(1/3):
+// four layers at z = (-3/2, -1/2, 1/2, 3/2) h, each the 12 squares of a 4 x 4 grid whose
+// centres satisfy max(|x|, |y|) < 3h/2 or min(|x|, |y|) < h (the grid without its corners).
 // Unknowns are grouped particle by particle (§4, eq. 4.1).
 //
 // Grouping (§5.1, §5.3, §5.4): a quadtree aligned with the particle lattice, padded to
-// 2^L sites per side.  Particles are ordered along a Morton curve so that every tree
-// node is a contiguous range of particles (and of DoFs).  At level l the ordered pairs
+// 2^L sites per side, or the paper's grid (level 1 is 3 x 3 blocks of the bounding square,
+// halving per level) with each particle in the block of its centre.  Both are indexed by
+// the finest-level block (i, j): the level-l block is (i, j) >> (L - l).  Particles are
+// ordered along a Morton curve of (i, j) so that every tree node is a contiguous range of
+// particles (and of DoFs).  At level l the ordered pairs
 // (I, J) of occupied nodes whose parents are near (share a grid node: Chebyshev distance
 // <= 1) and which are far (Chebyshev >= 2) are compressed; at the finest level, where a
 // node holds one particle, the near pairs I != J are compressed too, so the near part
@@ -82,6 +88,51 @@ void particle_offsets(double radius, double height, double* off) {
                 }
             }
     }
+}
+
+void sphere_offsets(double radius, double* off) {
+    const double h = radius * std::cbrt(M_PI / 36.0);
+    int c = 0;
+    for (int layer = 0; layer < 4; ++layer)
+        for (int b = 0; b < 4; ++b)
+            for (int a = 0; a < 4; ++a) {
+                if ((a == 0 || a == 3) && (b == 0 || b == 3)) continue;   // the grid's corners
+                off[3 * c + 0] = (a - 1.5) * h;
+                off[3 * c + 1] = (b - 1.5) * h;
+                off[3 * c + 2] = (layer - 1.5) * h;
+                ++c;
+            }
+}
+
+// The paper's grid over the bounding square of the centres: the finest level L (>= 1) at
+// which the blocks of side D / (3 2^(L-1)) hold at most one particle each, and each
+// particle's block there.  Returns L, or 0 when two centres share a block at level 20.
+int paper_grid(int n, const double* centers, std::vector<int32_t>& ij) {
+    double xmin = centers[0], xmax = centers[0], ymin = centers[1], ymax = centers[1];
+    for (int p = 1; p < n; ++p) {
+        xmin = std::min(xmin, centers[3 * p]); xmax = std::max(xmax, centers[3 * p]);
+        ymin = std::min(ymin, centers[3 * p + 1]); ymax = std::max(ymax, centers[3 * p + 1]);
+    }
+    double side = std::max(xmax - xmin, ymax - ymin);
+    if (!(side > 0.0)) side = 1.0;                   // one particle (or all on one point)
+    side *= 1.0 + std::ldexp(1.0, -20);
+    const double x0 = 0.5 * (xmin + xmax) - 0.5 * side, y0 = 0.5 * (ymin + ymax) - 0.5 * side;
+    ij.assign(2 * (size_t)n, 0);
+    for (int L = 1; L <= 20; ++L) {
+        const int64_t nb = (int64_t)3 << (L - 1);
+        const double h = side / (double)nb;
+        std::vector<int64_t> keys(n);
+        for (int p = 0; p < n; ++p) {
+            const int64_t i = std::min<int64_t>(nb - 1, (int64_t)std::floor((centers[3 * p] - x0) / h));
+            const int64_t j = std::min<int64_t>(nb - 1, (int64_t)std::floor((centers[3 * p + 1] - y0) / h));
+            ij[2 * p] = (int32_t)i;
+            ij[2 * p + 1] = (int32_t)j;
+            keys[p] = i * nb + j;
+        }
+        std::sort(keys.begin(), keys.end());
+        if (std::adjacent_find(keys.begin(), keys.end()) == keys.end() || n == 1) return L;
+    }
+    return 0;
 }
 
 static uint64_t morton(uint32_t i, uint32_t j) {
@@ -198,44 +249,64 @@ size_t qrvie_ctx_peak_bytes(qrvie_ctx* ctx, int32_t reset) {
 qrvie_status qrvie_geom_create(qrvie_ctx* ctx, const qrvie_array_desc* d, qrvie_geom** out) {
     if (!ctx || !d || !out) return QRVIE_ERR_INVALID_ARG;
     *out = nullptr;
-    if (d->n < 1 || !d->centers || !d->radius || !d->height || !d->eps_r || !d->lattice_ij) {
+    if (d->n < 1 || !d->centers || !d->radius || !d->height || !d->eps_r ||
+        (!d->lattice_ij && d->grid != QRVIE_GRID_PAPER)) {
         set_err(ctx, "geom_create: null pointer or n < 1");
         return QRVIE_ERR_INVALID_ARG;
     }
     if (d->n_eps != 1 && d->n_eps != d->n) { set_err(ctx, "geom_create: n_eps must be 1 or n"); return QRVIE_ERR_INVALID_ARG; }
     if (d->cells_per_particle != kCells) { set_err(ctx, "geom_create: cells_per_particle must be 48"); return QRVIE_ERR_INVALID_ARG; }
+    if ((d->shape != QRVIE_SHAPE_DISK && d->shape != QRVIE_SHAPE_SPHERE) ||
+        (d->grid != QRVIE_GRID_LATTICE && d->grid != QRVIE_GRID_PAPER)) {
+        set_err(ctx, "geom_create: unknown shape or grid");
+        return QRVIE_ERR_INVALID_ARG;
+    }
+    const bool paper = d->grid == QRVIE_GRID_PAPER;
     if (!(d->wavelength > 0.0) || !std::isfinite(d->wavelength)) { set_err(ctx, "geom_create: wavelength must be > 0"); return QRVIE_ERR_INVALID_ARG; }
     const int N = d->n;
     for (int p = 0; p < N; ++p) {
         const qrvie_c128 e = d->eps_r[d->n_eps == 1 ? 0 : p];
         if (!std::isfinite(d->centers[3 * p]) || !std::isfinite(d->centers[3 * p + 1]) ||
             !std::isfinite(d->centers[3 * p + 2]) || !(d->radius[p] > 0.0) || !std::isfinite(d->radius[p]) ||
-            !(d->height[p] > 0.0) || !std::isfinite(d->height[p]) || !std::isfinite(e.re) || !std::isfinite(e.im) ||
+            (d->shape == QRVIE_SHAPE_DISK && (!(d->height[p] > 0.0) || !std::isfinite(d->height[p]))) ||
+            !std::isfinite(e.re) || !std::isfinite(e.im) ||
             (e.re == 1.0 && e.im == 0.0)) {
             set_err(ctx, "geom_create: particle " + std::to_string(p) + " has a non-finite or invalid parameter");
             return QRVIE_ERR_INVALID_ARG;
         }
     }
-    int32_t imin = INT32_MAX, jmin = INT32_MAX, imax = INT32_MIN, jmax = INT32_MIN;
-    for (int p = 0; p < N; ++p) {
-        imin = std::min(imin, d->lattice_ij[2 * p]); imax = std::max(imax, d->lattice_ij[2 * p]);
-        jmin = std::min(jmin, d->lattice_ij[2 * p + 1]); jmax = std::max(jmax, d->lattice_ij[2 * p + 1]);
+    // finest-level block of each particle (caller order)
+    std::vector<int32_t> bij;
+    int L = 0;
+    if (paper) {
+        L = paper_grid(N, d->centers, bij);
+        if (L == 0) { set_err(ctx, "geom_create: two particle centres share a block of the finest grid level"); return QRVIE_ERR_GEOMETRY; }
+    } else {
+        int32_t imin = INT32_MAX, jmin = INT32_MAX, imax = INT32_MIN, jmax = INT32_MIN;
+        for (int p = 0; p < N; ++p) {
+            imin = std::min(imin, d->lattice_ij[2 * p]); imax = std::max(imax, d->lattice_ij[2 * p]);
+            jmin = std::min(jmin, d->lattice_ij[2 * p + 1]); jmax = std::max(jmax, d->lattice_ij[2 * p + 1]);
+        }
+        const int64_t nx = (int64_t)imax - imin + 1, ny = (int64_t)jmax - jmin + 1;
+        if (nx > (1 << 24) || ny > (1 << 24)) { set_err(ctx, "geom_create: lattice extent too large"); return QRVIE_ERR_GEOMETRY; }
+        while ((int64_t(1) << L) < std::max(nx, ny)) ++L;
+        bij.resize(2 * (size_t)N);
+        for (int p = 0; p < N; ++p) {
+            bij[2 * p] = d->lattice_ij[2 * p] - imin;
+            bij[2 * p + 1] = d->lattice_ij[2 * p + 1] - jmin;
+        }
     }
-    const int64_t nx = (int64_t)imax - imin + 1, ny = (int64_t)jmax - jmin + 1;
-    if (nx > (1 << 24) || ny > (1 << 24)) { set_err(ctx, "geom_create: lattice extent too large"); return QRVIE_ERR_GEOMETRY; }
 
     auto* g = new qrvie_geom;
     g->ctx = ctx;
     g->N = N;
     g->wavelength = d->wavelength;
     g->k = 2.0 * M_PI / d->wavelength;
-    int L = 0;
-    while ((int64_t(1) << L) < std::max(nx, ny)) ++L;
     g->L = L;
+    g->paper_grid = paper;
 
     std::vector<std::pair<uint64_t, int32_t>> codes(N);
-    for (int p = 0; p < N; ++p)
-        codes[p] = {morton((uint32_t)(d->lattice_ij[2 * p] - imin), (uint32_t)(d->lattice_ij[2 * p + 1] - jmin)), p};
+    for (int p = 0; p < N; ++p) codes[p] = {morton((uint32_t)bij[2 * p], (uint32_t)bij[2 * p + 1]), p};
     std::sort(codes.begin(), codes.end());
     for (int p = 1; p < N; ++p)
         if (codes[p].first == codes[p - 1].first) {
@@ -256,21 +327,28 @@ qrvie_status qrvie_geom_create(qrvie_ctx* ctx, const qrvie_array_desc* d, qrvie_
         const int c = codes[p].second;
         g->i2c[p] = c;
         g->c2i[c] = p;
-        lat.li[p] = d->lattice_ij[2 * c] - imin;
-        lat.lj[p] = d->lattice_ij[2 * c + 1] - jmin;
+        lat.li[p] = bij[2 * c];
+        lat.lj[p] = bij[2 * c + 1];
         for (int a = 0; a < 3; ++a) g->center[3 * p + a] = d->centers[3 * c + a];
         const qrvie_c128 e = d->eps_r[d->n_eps == 1 ? 0 : c];
-        double vals[4] = {d->radius[c], d->height[c], e.re, e.im};
-        std::vector<uint64_t> key(4);
+        const bool sphere = d->shape == QRVIE_SHAPE_SPHERE;
+        double vals[5] = {d->radius[c], sphere ? 0.0 : d->height[c], e.re, e.im, sphere ? 1.0 : 0.0};
+        std::vector<uint64_t> key(5);
         std::memcpy(key.data(), vals, sizeof vals);
         auto it = tmap.find(key);
         if (it == tmap.end()) {
             PType t{};
             t.radius = vals[0]; t.height = vals[1]; t.eps_re = vals[2]; t.eps_im = vals[3];
-            const double h = t.radius * std::sqrt(M_PI / 24.0);
-            t.vol = h * h * t.height / 2.0;
+            if (sphere) {
+                const double h = t.radius * std::cbrt(M_PI / 36.0);
+                t.vol = h * h * h;
+                sphere_offsets(t.radius, t.off);
+            } else {
+                const double h = t.radius * std::sqrt(M_PI / 24.0);
+                t.vol = h * h * t.height / 2.0;
+                particle_offsets(t.radius, t.height, t.off);
+            }
             t.aeq = std::pow(3.0 * t.vol / (4.0 * M_PI), 1.0 / 3.0);
-            particle_offsets(t.radius, t.height, t.off);
             it = tmap.emplace(key, (int32_t)g->types.size()).first;
             g->types.push_back(t);
         }
@@ -284,7 +362,8 @@ qrvie_status qrvie_geom_create(qrvie_ctx* ctx, const qrvie_array_desc* d, qrvie_
         const int sh = L - l;
         int64_t prev = INT64_MIN;
         for (int p = 0; p < N; ++p) {
-            const int64_t X = lat.li[p] >> sh, Y = lat.lj[p] >> sh;
+            // level 0 is the single root (the paper grid's 3 x 3 level 1 has no 2 x 2 parent)
+            const int64_t X = l == 0 ? 0 : lat.li[p] >> sh, Y = l == 0 ? 0 : lat.lj[p] >> sh;
             const int64_t k = key2(X, Y);
             if (k != prev || p == 0) {
                 const int32_t id = (int32_t)g->nodes.size();
@@ -375,6 +454,17 @@ int32_t qrvie_geom_nlevels(const qrvie_geom* g) { return g ? g->L : 0; }
 qrvie_status qrvie_geom_order(const qrvie_geom* g, int32_t* i2c) {
     if (!g || !i2c) return QRVIE_ERR_INVALID_ARG;
     std::memcpy(i2c, g->i2c.data(), sizeof(int32_t) * g->N);
+    return QRVIE_OK;
+}
+
+qrvie_status qrvie_geom_blocks(const qrvie_geom* g, int32_t* block_ij) {
+    if (!g || !block_ij) return QRVIE_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(lattice_mutex());
+    const auto& lat = lattices().at(g);
+    for (int p = 0; p < g->N; ++p) {
+        block_ij[2 * g->i2c[p]] = lat.li[p];
+        block_ij[2 * g->i2c[p] + 1] = lat.lj[p];
+    }
     return QRVIE_OK;
 }
 

@@ -170,6 +170,7 @@ struct qrvie_geom {
     qrvie_ctx* ctx = nullptr;
     int32_t N = 0;
     int32_t L = 0;
+    bool paper_grid = false;                  // grouping on the paper's 3 x 3-rooted grid
     double wavelength = 1.0, k = 0.0;
     std::vector<int32_t> i2c, c2i;            // internal <-> caller particle index
     std::vector<int32_t> ptype;               // internal particle -> type

@@ -35,14 +35,14 @@ double clock_s() {
 
 // Owned copy of an array description.
 struct ArrayCopy {
-    int32_t n = 0, n_eps = 0, cells = 0;
+    int32_t n = 0, n_eps = 0, cells = 0, shape = 0, grid = 0;
     std::vector<double> centers, radius, height;
     std::vector<qrvie_c128> eps_r;
     std::vector<int32_t> lattice;
     double pitch = 0, wavelength = 0;
     qrvie_array_desc desc() const {
         return qrvie_array_desc{n, centers.data(), radius.data(), height.data(), eps_r.data(), n_eps,
-                                lattice.data(), pitch, wavelength, cells};
+                                lattice.empty() ? nullptr : lattice.data(), pitch, wavelength, cells, shape, grid};
     }
 };
 
@@ -328,7 +328,8 @@ qrvie_status qrvie_server_create(int hip_device, const qrvie_server_opts* o, qrv
 qrvie_status qrvie_server_submit(qrvie_server* s, const qrvie_array_desc* a, int32_t nrhs, const double* th,
                                  const double* ph, const int32_t* pol, double tol, uint64_t* ticket) {
     if (!s || !a || !th || !ph || !pol || !ticket || nrhs < 1 || nrhs > kMaxBlockRhs || !(tol > 0.0) || a->n < 1 ||
-        !a->centers || !a->radius || !a->height || !a->eps_r || !a->lattice_ij || (a->n_eps != 1 && a->n_eps != a->n))
+        !a->centers || !a->radius || !a->height || !a->eps_r || (!a->lattice_ij && a->grid != QRVIE_GRID_PAPER) ||
+        (a->n_eps != 1 && a->n_eps != a->n))
         return bad(s, "submit: invalid argument");
     auto r = std::make_unique<Request>();
     ArrayCopy& c = r->arr;
@@ -341,7 +342,9 @@ qrvie_status qrvie_server_submit(qrvie_server* s, const qrvie_array_desc* a, int
     c.radius.assign(a->radius, a->radius + a->n);
     c.height.assign(a->height, a->height + a->n);
     c.eps_r.assign(a->eps_r, a->eps_r + a->n_eps);
-    c.lattice.assign(a->lattice_ij, a->lattice_ij + 2 * (size_t)a->n);
+    c.shape = a->shape;
+    c.grid = a->grid;
+    if (a->grid != QRVIE_GRID_PAPER) c.lattice.assign(a->lattice_ij, a->lattice_ij + 2 * (size_t)a->n);
     r->nrhs = nrhs;
     r->th.assign(th, th + nrhs);
     r->ph.assign(ph, ph + nrhs);
@@ -355,6 +358,8 @@ qrvie_status qrvie_server_submit(qrvie_server* s, const qrvie_array_desc* a, int
     k.add(c.height.data(), sizeof(double) * c.height.size());
     k.add(c.eps_r.data(), sizeof(qrvie_c128) * c.eps_r.size());
     k.add(c.lattice.data(), sizeof(int32_t) * c.lattice.size());
+    k.add(&c.shape, sizeof c.shape);
+    k.add(&c.grid, sizeof c.grid);
     k.add(&c.wavelength, sizeof c.wavelength);
     k.add(&s->o.eps, sizeof s->o.eps);
     k.add(&s->o.seed, sizeof s->o.seed);

@@ -173,3 +173,24 @@ def test_footprint_estimate_bounds_the_sketch_build(name, cap, far_prec):
     assert peak <= est, (peak, est)
     op.close()
     geom.close()
+
+
+@pytest.mark.parametrize("compression", ["sketch", "aca"])
+def test_matrix_core_products_over_edge_blocks_match_the_oracle(compression):
+    """The 33 x 33 serving array (row cap 9216) has 2304 x 144 edge blocks, the shape on which
+    an FP64-MFMA variant of the build GEMM once failed certification.  Its factors were built
+    by CGS2 panels on FP64 matrix cores (certified above); here the block product (16 and 20
+    right-hand sides: FP64-MFMA strip kernels over every Q and R panel, edge strips included)
+    must match the oracle's product of the exported factors."""
+    c = case("serving33", max_block_rows=9216, compression=compression)
+    fac = [(r, cc, Q, R) for r, cc, Q, R, _ in c.factors()]
+    edge = [i for *_, i in c.factors() if (i["m"], i["n"]) in ((2304, 144), (144, 2304))]
+    assert edge
+    sb = greens.self_blocks(c.disc)
+    rng = np.random.default_rng(90)
+    for nrhs in (16, 20):
+        x = rng.standard_normal((nrhs, c.geom.ndof)) + 1j * rng.standard_normal((nrhs, c.geom.ndof))
+        y = to_host(c.op.apply(to_dev(x)))
+        ref = compressed.compressed_apply(sb, fac, x.T).T
+        for r in range(nrhs):
+            assert np.linalg.norm(y[r] - ref[r]) <= 1e-12 * np.linalg.norm(ref[r]), (nrhs, r)

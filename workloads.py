@@ -18,6 +18,8 @@ workloads; the paper's own test geometry, a Vogel spiral of spheres, is given by
 * batching  64x64 lattice, graded metalens radius profile (``graded_metalens_radii``)
 * precision 96x96 lattice, radii U[0.15, 0.25] from ``default_rng(0)``
 * serving   256 requests, side U{8..48}, radii U[0.15, 0.25], 1-16 RHS, Poisson arrivals
+* vogel     the paper's arrays: n = 100 / 500 / 1000 / 2000 gold spheres (radius 1/6) on a
+            Vogel spiral, grouped on the paper's grid
 """
 from __future__ import annotations
 
@@ -47,6 +49,8 @@ class ArrayDesc:
     wavelength: float = 1.0
     cells_per_particle: int = CELLS_PER_PARTICLE
     name: str = ""
+    shape: str = "disk"          # "disk" or "sphere"
+    grid: str = "lattice"        # "lattice" (lattice_ij) or "paper" (blocks from the centres)
 
     @property
     def n_particles(self) -> int:
@@ -189,6 +193,22 @@ def vogel_centers(n: int, sphere_radius: float) -> np.ndarray:
     i = np.arange(1, n + 1, dtype=np.float64)
     r = c * np.sqrt(i)
     return np.stack([r * np.cos(i * alpha), r * np.sin(i * alpha), np.zeros(n)], axis=1)
+
+
+VOGEL_SPHERE_RADIUS = 0.1 / 0.6          # 100 nm spheres at 600 nm wavelength
+VOGEL_EPS_R = -9.428 - 1.513j             # gold at 500 THz, passive sign for the e^{+j omega t} convention
+
+
+def vogel(n: int) -> ArrayDesc:
+    """The paper's test array (§6.1): n gold spheres of radius 100 nm on a Vogel spiral at a
+    600 nm wavelength, grouped on the paper's grid (no lattice).  The tabulated permittivity
+    -9.428 + 1.513i belongs to the e^{-i omega t} convention; with the e^{+j omega t}
+    convention of the kernel the same passive (lossy) gold is -9.428 - 1.513j."""
+    centers = vogel_centers(n, VOGEL_SPHERE_RADIUS)
+    r = np.full(n, VOGEL_SPHERE_RADIUS)
+    return ArrayDesc(nx=0, ny=0, pitch=0.0, centers=centers, lattice_ij=np.zeros((n, 2), dtype=np.int32),
+                     radius=r, height=2.0 * r, eps_r=np.full(n, VOGEL_EPS_R, dtype=np.complex128),
+                     name=f"vogel-{n}", shape="sphere", grid="paper")
 
 
 def to_c_desc_arrays(a: ArrayDesc) -> dict:
