@@ -270,44 +270,67 @@ __global__ void k_add(const c128* __restrict__ d, int64_t n, c128* __restrict__ 
 // Column j of the Hessenberg matrix: hcol[0..j] from Gram-Schmidt, h_{j+1,j} = sqrt(hnorm2).
 // Apply the previous rotations, build rotation j so that [[c, s], [-conj(s), c]] zeroes
 // h_{j+1,j} (c real), and rotate the right-hand side g.  status = {|g_{j+1}|, h_{j+1,j}}.
-// The previous rotations are a sequential sweep; their operands are staged through LDS
-// in segments by the whole workgroup so that the sweep itself only touches LDS.
-constexpr int kSeg = 2048;
+//
+// Rotation t maps the running entry a_t and the next entry b_t = h_{t+1} to the output
+// c_t a_t + s_t b_t and the next running entry a_{t+1} = -conj(s_t) a_t + c_t b_t, an affine
+// recurrence in a.  One wave applies the j rotations as a scan: each lane composes the affine
+// maps of its contiguous chunk, a 6-step shuffle scan gives every lane the running entry at
+// the start of its chunk, and each lane then produces its chunk's outputs.  The critical path
+// is about 2 j / 64 + 6 dependent steps instead of j.
+__device__ __forceinline__ c128 cmul_k(c128 x, c128 y) {
+    return make_double2(x.x * y.x - x.y * y.y, x.x * y.y + x.y * y.x);
+}
 
 __global__ void __launch_bounds__(256) k_givens(int j, c128* hcol, c128* H, int ldh, double* cs, c128* sn, c128* g,
                                                 const double* hnorm2, double* status) {
-    __shared__ c128 hs[kSeg + 1];
-    __shared__ double cl[kSeg];
-    __shared__ c128 sl[kSeg];
     __shared__ c128 carry;
     const int tid = threadIdx.x;
     const double hn = sqrt(hnorm2[0]);
-    if (tid == 0) carry = hcol[0];
-    __syncthreads();
-    for (int i0 = 0; i0 < j; i0 += kSeg) {
-        const int cnt = min(kSeg, j - i0);
-        for (int t = tid; t < cnt; t += 256) {
-            hs[t + 1] = (i0 + t + 1 == j + 1) ? make_double2(hn, 0.0) : hcol[i0 + t + 1];
-            cl[t] = cs[i0 + t];
-            sl[t] = sn[i0 + t];
+    c128* Hj = H + (int64_t)j * ldh;
+    if (tid < 64) {
+        const int lane = tid;
+        const int len = (j + 63) / 64;
+        const int t0 = min(j, lane * len), t1 = min(j, t0 + len);
+        // compose this chunk's maps a -> A a + B
+        c128 A = make_double2(1.0, 0.0), B = make_double2(0.0, 0.0);
+        for (int t = t0; t < t1; ++t) {
+            const c128 st = sn[t];
+            const double ct = cs[t];
+            const c128 al = make_double2(-st.x, st.y);               // -conj(s)
+            const c128 bt = hcol[t + 1];
+            B = cmul_k(al, B);
+            B = make_double2(B.x + ct * bt.x, B.y + ct * bt.y);
+            A = cmul_k(al, A);
         }
-        __syncthreads();
-        if (tid == 0) {
-            c128 a = carry;
-            for (int t = 0; t < cnt; ++t) {
-                const c128 b = hs[t + 1];
-                const double c = cl[t];
-                const c128 s = sl[t];
-                // [c a + s b, -conj(s) a + c b]
-                hs[t] = make_double2(c * a.x + (s.x * b.x - s.y * b.y), c * a.y + (s.x * b.y + s.y * b.x));
-                a = make_double2(-(s.x * a.x + s.y * a.y) + c * b.x, -(s.x * a.y - s.y * a.x) + c * b.y);
+        // inclusive scan of the maps over the lanes (lane l: chunks 0..l composed)
+        for (int o = 1; o < 64; o <<= 1) {
+            const c128 Ao = make_double2(__shfl_up(A.x, o, 64), __shfl_up(A.y, o, 64));
+            const c128 Bo = make_double2(__shfl_up(B.x, o, 64), __shfl_up(B.y, o, 64));
+            if (lane >= o) {                                          // mine after theirs
+                const c128 nb = cmul_k(A, Bo);
+                B = make_double2(nb.x + B.x, nb.y + B.y);
+                A = cmul_k(A, Ao);
             }
-            carry = a;
         }
-        __syncthreads();
-        for (int t = tid; t < cnt; t += 256) hcol[i0 + t] = hs[t];
-        __syncthreads();
+        // the running entry at the start of this chunk: the previous lanes' maps applied to h_0
+        const c128 h0 = hcol[0];
+        c128 Ap = make_double2(__shfl_up(A.x, 1, 64), __shfl_up(A.y, 1, 64));
+        c128 Bp = make_double2(__shfl_up(B.x, 1, 64), __shfl_up(B.y, 1, 64));
+        if (lane == 0) { Ap = make_double2(1.0, 0.0); Bp = make_double2(0.0, 0.0); }
+        const c128 pa = cmul_k(Ap, h0);
+        c128 a = make_double2(pa.x + Bp.x, pa.y + Bp.y);
+        for (int t = t0; t < t1; ++t) {
+            const c128 st = sn[t];
+            const double ct = cs[t];
+            const c128 bt = hcol[t + 1];
+            const c128 sb = cmul_k(st, bt);
+            const c128 out = make_double2(ct * a.x + sb.x, ct * a.y + sb.y);
+            a = make_double2(-(st.x * a.x + st.y * a.y) + ct * bt.x, -(st.x * a.y - st.y * a.x) + ct * bt.y);
+            Hj[t] = out;                // rotated entries go to H; hcol is only read
+        }
+        if (lane == 63) carry = j == 0 ? h0 : a;
     }
+    __syncthreads();
     if (tid == 0) {
         const c128 a = carry, b = make_double2(hn, 0.0);
         const double aa = sqrt(a.x * a.x + a.y * a.y), ab = sqrt(b.x * b.x + b.y * b.y);
@@ -324,16 +347,13 @@ __global__ void __launch_bounds__(256) k_givens(int j, c128* hcol, c128* H, int 
         }
         cs[j] = c;
         sn[j] = s;
-        hcol[j] = make_double2(c * a.x + (s.x * b.x - s.y * b.y), c * a.y + (s.x * b.y + s.y * b.x));
-        hcol[j + 1] = make_double2(0.0, 0.0);
+        Hj[j] = make_double2(c * a.x + (s.x * b.x - s.y * b.y), c * a.y + (s.x * b.y + s.y * b.x));
         const c128 gj = g[j];
         g[j + 1] = make_double2(-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x));
         g[j] = make_double2(c * gj.x, c * gj.y);
         status[0] = sqrt(g[j + 1].x * g[j + 1].x + g[j + 1].y * g[j + 1].y);
         status[1] = hn;
     }
-    __syncthreads();
-    for (int i = tid; i <= j; i += 256) H[i + (int64_t)j * ldh] = hcol[i];
 }
 
 // Solve the k x k upper-triangular system H y = g by column sweeps (one workgroup):
