@@ -183,6 +183,17 @@ constexpr int kDppQuadXor2 = 0x4E;     // quad_perm [2, 3, 0, 1]
 // Sums of 8 values per lane over the 64 lanes of a wave: every lane L returns the total of
 // v[L >> 3].  Each of the first three steps halves the values a lane keeps (lanes with bit
 // 5, 4, 3 set keep the upper half), then the 8 lanes of a group reduce their common column.
+// The same from the second fold on: w2[p] = fold_swap(fold_swap(v[p], v[4 + p], true),
+// fold_swap(v[2 + p], v[6 + p], true), false) already taken.
+__device__ __forceinline__ c128 transpose_sum2(const c128 w2[2], int lane) {
+    const c128 s0 = cadd(w2[0], dpp_c<kDppRor8>(w2[0]));
+    const c128 s1 = cadd(w2[1], dpp_c<kDppRor8>(w2[1]));
+    c128 w = (lane & 8) ? s1 : s0;
+    w = cadd(w, dpp_c<kDppHalfMirror>(w));
+    w = cadd(w, dpp_c<kDppQuadXor1>(w));
+    return cadd(w, dpp_c<kDppQuadXor2>(w));
+}
+
 __device__ __forceinline__ c128 transpose_sum8(const c128 v[8], int lane) {
     c128 w4[4], w2[2];
 #pragma unroll
@@ -283,16 +294,23 @@ __global__ void __launch_bounds__(64 * WAVES) k_rphase_sh(const RStrip* __restri
         const c128* vv = xv + jb;
 #pragma unroll
         for (int h = 0; h < U; h += 8) {
-            c128 q[8];
+            // the eight products are folded as soon as they exist (columns p, p + 4, p + 2, p + 6
+            // into w2[p]), so few of them are live at once
+            c128 w2[2];
 #pragma unroll
-            for (int u = 0; u < 8; u += 2) {
-                const c128 a0 = widen(w[h + u]), a1 = widen(w[h + u + 1]);
-                cfma(acc0, a0, vv[h + u]);
-                cfma(acc1, a1, vv[h + u + 1]);
-                q[u] = cmul(a0, sv);
-                q[u + 1] = cmul(a1, sv);
+            for (int p = 0; p < 2; ++p) {
+                c128 f[2];
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    const int u = p + 2 * r;
+                    const c128 a0 = widen(w[h + u]), a1 = widen(w[h + u + 4]);
+                    cfma(acc0, a0, vv[h + u]);
+                    cfma(acc1, a1, vv[h + u + 4]);
+                    f[r] = fold_swap(cmul(a0, sv), cmul(a1, sv), true);
+                }
+                w2[p] = fold_swap(f[0], f[1], false);
             }
-            const c128 tot = transpose_sum8(q, lane);
+            const c128 tot = transpose_sum2(w2, lane);
             if ((lane & 7) == 0) pr[jb + h + (lane >> 3)] = tot;
         }
     });
