@@ -195,7 +195,9 @@ enum { QRVIE_COMPRESS_ACA = 0, QRVIE_COMPRESS_SKETCH = 1 };
  *                    pivoted QR at 0.9 eps, and the factors are certified against every entry of
  *                    the block generated again, so eq. 5.3 holds exactly as with the sketch.  A
  *                    block that misses eps is redone twice with a tenfold tighter stopping
- *                    tolerance, then by the sketch path.  No far block is materialised, so
+ *                    tolerance, then by the sketch path.  aca_start and aca_stop set the first
+ *                    number of crosses and the stopping tolerance (the op's stats count the
+ *                    continuations, repeats and sketch fallbacks).  No far block is materialised, so
  *                    max_block_rows is not needed for memory; blocks above 147456 rows (1024
  *                    particles) are split into their child pairs by the operator itself.
  *                    QRVIE_COMPRESS_SKETCH (1): every block is assembled and compressed through
@@ -212,6 +214,8 @@ typedef struct {
     int32_t verbose;
     int64_t chunk_bytes;
     int32_t compression;
+    int32_t aca_start;       /* crosses per block at first, 1..512 (0 = 256) */
+    double  aca_stop;        /* stopping tolerance of the crosses relative to eps, > 0 (0 = 0.1) */
 } qrvie_compress_opts;
 
 #define QRVIE_MAX_LEVELS 24
@@ -231,6 +235,10 @@ typedef struct {
     int64_t device_bytes;                     /* device memory held by the operator */
     double  t_assembly_s, t_compression_s, t_precond_setup_s;
     int64_t apply_bytes_c64;                  /* the same product with complex64 far factors (0: none) */
+    int64_t n_aca;                            /* cross approximation: blocks compressed by it */
+    int64_t n_aca_resumed;                    /*   continuations in wider buffers (all crosses used) */
+    int64_t n_aca_retried;                    /*   repeats with a tighter stopping tolerance */
+    int64_t n_aca_sketch;                     /*   blocks left to the sketch path */
 } qrvie_op_stats;
 
 typedef struct {

@@ -27,7 +27,8 @@ class ArrayDescC(C.Structure):
 class CompressOpts(C.Structure):
     _fields_ = [("eps", C.c_double), ("far_prec", C.c_int32), ("near_prec", C.c_int32),
                 ("max_block_rows", C.c_int64), ("share_transpose", C.c_int32), ("seed", C.c_uint64),
-                ("verbose", C.c_int32), ("chunk_bytes", C.c_int64), ("compression", C.c_int32)]
+                ("verbose", C.c_int32), ("chunk_bytes", C.c_int64), ("compression", C.c_int32),
+                ("aca_start", C.c_int32), ("aca_stop", C.c_double)]
 
 
 class OpStats(C.Structure):
@@ -37,7 +38,8 @@ class OpStats(C.Structure):
                 ("n_qr_entries", C.c_int64), ("gain", C.c_double), ("max_block_rel_err", C.c_double),
                 ("apply_bytes", C.c_int64), ("device_bytes", C.c_int64), ("t_assembly_s", C.c_double),
                 ("t_compression_s", C.c_double), ("t_precond_setup_s", C.c_double),
-                ("apply_bytes_c64", C.c_int64)]
+                ("apply_bytes_c64", C.c_int64), ("n_aca", C.c_int64), ("n_aca_resumed", C.c_int64),
+                ("n_aca_retried", C.c_int64), ("n_aca_sketch", C.c_int64)]
 
 
 class BlockInfo(C.Structure):

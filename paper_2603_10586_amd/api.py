@@ -251,12 +251,14 @@ class Operator:
 
     def __init__(self, ctx: Context, geom: Geometry, eps: float = 1e-6, max_block_rows: int = 0, seed: int = 0,
                  far_prec: int = L.PREC_C128, verbose: bool = False, chunk_bytes: int = 0,
-                 share_transpose: bool = False, compression: str = "aca"):
+                 share_transpose: bool = False, compression: str = "aca", aca_start: int = 0,
+                 aca_stop: float = 0.0):
         self.ctx, self.geom, self.far_prec = ctx, geom, far_prec
         self.shared = bool(share_transpose)
         o = L.CompressOpts(eps=eps, far_prec=far_prec, near_prec=L.PREC_C128, max_block_rows=max_block_rows,
                            share_transpose=1 if share_transpose else 0, seed=seed, verbose=1 if verbose else 0,
-                           chunk_bytes=chunk_bytes, compression=_compression(compression))
+                           chunk_bytes=chunk_bytes, compression=_compression(compression), aca_start=aca_start,
+                           aca_stop=aca_stop)
         self.opts = o
         h = C.c_void_p()
         ctx.check(ctx.lib.qrvie_op_create(ctx.h, geom.h, C.byref(o), C.byref(h)), "op_create")
@@ -292,7 +294,9 @@ class Operator:
                     mean_rank_level=list(s.mean_rank_level[:nl]), n_self_types=s.n_self_types,
                     n_qr_entries=s.n_qr_entries, gain=s.gain, max_block_rel_err=s.max_block_rel_err,
                     apply_bytes=s.apply_bytes, apply_bytes_c64=s.apply_bytes_c64, device_bytes=s.device_bytes,
-                    t_compression_s=s.t_compression_s, t_precond_setup_s=s.t_precond_setup_s)
+                    t_compression_s=s.t_compression_s, t_precond_setup_s=s.t_precond_setup_s,
+                    n_aca=s.n_aca, n_aca_resumed=s.n_aca_resumed, n_aca_retried=s.n_aca_retried,
+                    n_aca_sketch=s.n_aca_sketch)
 
     def num_blocks(self) -> int:
         return int(self.ctx.lib.qrvie_op_num_blocks(self.h))

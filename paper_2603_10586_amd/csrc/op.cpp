@@ -130,6 +130,8 @@ struct Builder {
     std::vector<std::pair<void*, size_t>> segments; // compact factor storage
     double eps;
     bool compact32 = false;                         // round each chunk's compact factors to complex64
+    int64_t n_aca = 0, n_resumed = 0, n_retried = 0; // cross approximation counters
+    double aca_eps0 = 0.0;                          // the crosses' first stopping tolerance
     // The materialised blocks of a chunk and the direct blocks' working copies live in two
     // grow-only buffers kept across chunks: allocating and releasing tens of GB per chunk
     // cost about as much host time as the chunk's kernels.
@@ -593,6 +595,7 @@ qrvie_status Builder::compress_aca(const std::vector<int32_t>& ids, const std::v
             const int32_t full = (int32_t)std::min<int64_t>(std::min(m[i], n[i]), kAcaMaxRank);
             if (k[i] >= cap[i] && cap[i] < full) more.push_back(i);
         }
+        n_resumed += (int64_t)more.size();
         for (size_t i : more) {
             const int32_t c2 = (int32_t)std::min<int64_t>(2 * (int64_t)cap[i], std::min<int64_t>(std::min(m[i], n[i]), kAcaMaxRank));
             c128 *u2, *v2;
@@ -806,7 +809,7 @@ qrvie_status Builder::compress_aca(const std::vector<int32_t>& ids, const std::v
         f.rank = rank[i];
         f.rel_err = nrm2[i] > 0.0 ? std::sqrt(err2[i] / nrm2[i]) : 0.0;
         if (f.rel_err <= eps) continue;
-        if (eaca[i] > 5e-4 * eps) {                       // two rounds at a tenth of the tolerance
+        if (eaca[i] > 5e-2 * aca_eps0) {                  // two rounds, each at a tenth of the tolerance
             retry_ids.push_back(ids[i]);
             retry_k.push_back(cap[i]);
             retry_e.push_back(eaca[i] * 0.1);
@@ -816,6 +819,7 @@ qrvie_status Builder::compress_aca(const std::vector<int32_t>& ids, const std::v
     }
     CHECK(round_segment(seg, ctot, act, ids, qo, ro));
     ar.release();
+    n_retried += (int64_t)retry_ids.size();
     if (!retry_ids.empty()) return compress_aca(retry_ids, retry_k, retry_e, fallback);
     return QRVIE_OK;
 }
@@ -905,7 +909,8 @@ void op_footprint(const qrvie_geom* g, const qrvie_compress_opts* o, size_t* res
         prim += (m + n) * r;
         const bool small = b.rn <= kDirectMaxParticles && b.cn <= kDirectMaxParticles;
         if (aca && !small) {
-            const double e = (double)aca_elems(b, (int)std::min<double>(kAcaStart, std::min(m, n)));
+            const double e = (double)aca_elems(b, (int)std::min<double>(o->aca_start > 0 ? o->aca_start : kAcaStart,
+                                                                        std::min(m, n)));
             if (aacc > 0.0 && aacc + e > (double)chunk_elems) aflush();
             aacc += e;
             acprim += (m + n) * r;
@@ -969,6 +974,7 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
         o->near_prec != QRVIE_PREC_C128 ||
         (o->share_transpose != 0 && o->share_transpose != 1) ||
         (o->compression != QRVIE_COMPRESS_ACA && o->compression != QRVIE_COMPRESS_SKETCH) ||
+        o->aca_start < 0 || o->aca_start > kAcaMaxRank || !(o->aca_stop >= 0.0) ||
         o->max_block_rows < 0 || o->chunk_bytes < 0) {
         set_err(ctx, "op_create: unsupported precision or option");
         return QRVIE_ERR_INVALID_ARG;
@@ -1033,6 +1039,7 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
                             : o->max_block_rows;
     Builder bld{op, ctx, g, split_blocks(g, cap), {}, {}, o->eps};
     bld.compact32 = o->far_prec == QRVIE_PREC_C64_ONLY || o->far_prec == QRVIE_PREC_BF16X2;
+    bld.aca_eps0 = (o->aca_stop > 0.0 ? o->aca_stop : kAcaEps) * o->eps;
     const size_t NB = bld.blocks.size();
     bld.fac.resize(NB);
 
@@ -1054,12 +1061,13 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
             if (i < NB) {
                 const BlockRec& b = bld.blocks[i];
                 if (!b.primary || (b.rn <= kDirectMaxParticles && b.cn <= kDirectMaxParticles)) continue;
-                const int kmax = (int)std::min<int64_t>(kAcaStart, (int64_t)std::min(b.rn, b.cn) * kNp);
+                const int kmax = (int)std::min<int64_t>(o->aca_start > 0 ? o->aca_start : kAcaStart,
+                                                        (int64_t)std::min(b.rn, b.cn) * kNp);
                 const int64_t e = aca_elems(b, kmax);
                 if (acc == 0 || acc + e <= chunk_elems) {
                     ids.push_back((int32_t)i);
                     kmx.push_back(kmax);
-                    ea.push_back(kAcaEps * o->eps);
+                    ea.push_back(bld.aca_eps0);
                     acc += e;
                     continue;
                 }
@@ -1083,6 +1091,10 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
             acc = 0;
             if (i < NB) --i;   // re-visit the block that did not fit
         }
+        op->stats.n_aca = (int64_t)ndone - (int64_t)fallback.size();
+        op->stats.n_aca_resumed = bld.n_resumed;
+        op->stats.n_aca_retried = bld.n_retried;
+        op->stats.n_aca_sketch = (int64_t)fallback.size();
         bld.release_pools();                // the direct and sketch passes size their own
         if (o->verbose && !fallback.empty()) {
             std::fprintf(stderr, "[qrvie] cross approximation: %zu blocks left to the sketch path\n", fallback.size());

@@ -188,3 +188,35 @@ def test_footprint_estimate_bounds_the_cross_approximation_build():
     assert peak <= est, (peak, est)
     op.close()
     geom.close()
+
+
+def test_continued_cross_approximations_stay_certified():
+    """Starting with 8 crosses, nearly every block uses them all and continues in wider buffers
+    (8 -> 16 -> ... from its saved pivots and running estimate); the factors still meet eps
+    against the oracle and match the default build's ranks closely."""
+    import paper_2603_10586_amd as q
+    c = case("rand16x16")
+    op = q.Operator(c.ctx, c.geom, eps=EPS, aca_start=8)
+    st = op.stats()
+    assert st["n_aca_resumed"] >= st["n_aca"] > 0 and st["n_aca_sketch"] == 0
+    infos = [op.export_block(b, factors=False)[0] for b in range(op.num_blocks())]
+    for b in _stratified(infos, 3, seed=61):
+        _certify(c.disc, c.order, op, int(b))
+    ref = c.op.stats()["mean_rank_level"]
+    for a, r in zip(st["mean_rank_level"], ref):
+        assert abs(a - r) <= 0.1 * r + 2.0
+    op.close()
+
+
+def test_uncertified_crosses_are_repeated_then_left_to_the_sketch():
+    """A stopping tolerance far above eps (1e4 eps) makes the crosses miss eps: every such block
+    is repeated twice with a tenfold tighter tolerance, and the ones still missing go to the
+    sketch path; every stored block is certified against the oracle either way."""
+    import paper_2603_10586_amd as q
+    c = case("rand8x8")
+    op = q.Operator(c.ctx, c.geom, eps=EPS, aca_stop=1e4)
+    st = op.stats()
+    assert st["n_aca_retried"] > 0 and st["n_aca_sketch"] > 0
+    for b in range(op.num_blocks()):
+        _certify(c.disc, c.order, op, b)
+    op.close()
