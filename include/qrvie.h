@@ -191,7 +191,7 @@ enum { QRVIE_COMPRESS_ACA = 0, QRVIE_COMPRESS_SKETCH = 1 };
  *                    QRVIE_COMPRESS_ACA (0, the default): cross approximation, the compression
  *                    of §6.5 (after Kurz et al. 2002).  Only the pivot rows and columns of a
  *                    block are generated (256 crosses at first, continued up to 512 when all are
- *                    used, stopping at 0.1 eps); the crosses are recompressed by a truncated
+ *                    used, stopping at 0.05 eps); the crosses are recompressed by a truncated
  *                    pivoted QR at 0.9 eps, and the factors are certified against every entry of
  *                    the block generated again, so eq. 5.3 holds exactly as with the sketch.  A
  *                    block that misses eps is redone twice with a tenfold tighter stopping
@@ -215,7 +215,7 @@ typedef struct {
     int64_t chunk_bytes;
     int32_t compression;
     int32_t aca_start;       /* crosses per block at first, 1..512 (0 = 256) */
-    double  aca_stop;        /* stopping tolerance of the crosses relative to eps, > 0 (0 = 0.1) */
+    double  aca_stop;        /* stopping tolerance of the crosses relative to eps, > 0 (0 = 0.05) */
 } qrvie_compress_opts;
 
 #define QRVIE_MAX_LEVELS 24

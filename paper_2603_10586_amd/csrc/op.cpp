@@ -116,7 +116,7 @@ constexpr int kDirectMaxParticles = 2;   // both sides at most this many particl
 constexpr int kSketchStart = 128;
 constexpr int kMaxSketch = 512;          // widest sketch the CGS2 kernel orthonormalises
 constexpr int kAcaStart = 256;           // crosses per block at first (doubled while all are used)
-constexpr double kAcaEps = 0.1;          // stopping tolerance of the crosses, relative to eps
+constexpr double kAcaEps = 0.05;         // stopping tolerance of the crosses, relative to eps
 constexpr int64_t kAcaWide = 2 * 4608;   // rows plus columns above which a block gets 16 waves
 constexpr int kPhaseWaves = 4;           // waves per strip in the product kernels
 constexpr int64_t kAlign = 16;           // R-panel leading dimension multiple: 128 B in complex64, 256 B in complex128
@@ -135,8 +135,11 @@ struct Builder {
     // The materialised blocks of a chunk and the direct blocks' working copies live in two
     // grow-only buffers kept across chunks: allocating and releasing tens of GB per chunk
     // cost about as much host time as the chunk's kernels.
-    c128* pool[2] = {nullptr, nullptr};
-    size_t pool_elems[2] = {0, 0};
+    // slots: 0 blocks / crosses U, 1 work copies / crosses V, 2 bases of the crosses, 3 projected
+    // rows, 4 complex128 staging of compact factors that are kept as complex64
+    static constexpr int kPools = 5;
+    c128* pool[kPools] = {};
+    size_t pool_elems[kPools] = {};
 
     qrvie_status pooled(int which, size_t elems, c128** p, const char* what) {
         *p = nullptr;
@@ -155,9 +158,11 @@ struct Builder {
         return QRVIE_OK;
     }
     void release_pools() {
-        if (!pool[0] && !pool[1]) return;
+        bool any = false;
+        for (int w = 0; w < kPools; ++w) any = any || pool[w];
+        if (!any) return;
         (void)hipStreamSynchronize(ctx->stream);
-        for (int w = 0; w < 2; ++w) {
+        for (int w = 0; w < kPools; ++w) {
             if (pool[w]) dfree(ctx, pool[w], pool_elems[w] * sizeof(c128));
             pool[w] = nullptr;
             pool_elems[w] = 0;
@@ -425,7 +430,8 @@ struct Builder {
             ro[i] = ctot; ctot += (int64_t)rank[i] * n[i];
         }
         c128* seg;
-        CHECK(new_segment(ctot, &seg));
+        if (compact32) CHECK(pooled(4, (size_t)ctot, &seg, "compact factor staging"));
+        else CHECK(new_segment(ctot, &seg));
         // Q
         {
             std::vector<FormQDesc> fdir, fsk;
@@ -621,7 +627,7 @@ qrvie_status Builder::compress_aca(const std::vector<int32_t>& ids, const std::v
     int64_t ytot = 0;
     for (size_t i : act) { yo[i] = ytot; ytot += m[i] * k[i]; }
     c128* dY;
-    CHECK(ar.alloc(&dY, ytot, "cross approximation basis"));
+    CHECK(pooled(2, (size_t)ytot, &dY, "cross approximation basis"));
     std::vector<int32_t> kept(nb, 0);
     if (na) {
         for (size_t i : act)
@@ -653,7 +659,7 @@ qrvie_status Builder::compress_aca(const std::vector<int32_t>& ids, const std::v
     }
     c128 *dT, *dW;
     CHECK(ar.alloc(&dT, ttot, "cross approximation T"));
-    CHECK(ar.alloc(&dW, wtot, "projected rows"));
+    CHECK(pooled(3, (size_t)wtot, &dW, "projected rows"));
     auto gemm = [&](int mode, const std::vector<GemmDesc>& gd) -> qrvie_status {
         if (gd.empty()) return QRVIE_OK;
         std::vector<int32_t> td, tmn;
@@ -736,7 +742,8 @@ qrvie_status Builder::compress_aca(const std::vector<int32_t>& ids, const std::v
         ro[i] = ctot; ctot += (int64_t)rank[i] * n[i];
     }
     c128* seg;
-    CHECK(new_segment(ctot, &seg));
+    if (compact32) CHECK(pooled(4, (size_t)ctot, &seg, "compact factor staging"));
+    else CHECK(new_segment(ctot, &seg));
     {
         int64_t qwtot = 0;
         std::vector<int64_t> qwo(nb, 0);
@@ -1051,45 +1058,57 @@ qrvie_status qrvie_op_create(qrvie_ctx* ctx, const qrvie_geom* g, const qrvie_co
         std::max<int64_t>(1, (o->chunk_bytes > 0 ? o->chunk_bytes : (int64_t)auto_chunk_bytes(ctx)) / (int64_t)sizeof(c128));
     std::vector<int32_t> fallback;          // cross approximation: blocks left to the sketch path
     if (aca) {
-        std::vector<int32_t> ids, kmx;
-        std::vector<double> ea;
+        // chunks of blocks bounded by the crosses' working buffers
+        struct Chunk { std::vector<int32_t> ids, kmx; };
+        std::vector<Chunk> chunks(1);
         int64_t acc = 0;
         size_t nprim = 0, ndone = 0;
-        for (const BlockRec& b : bld.blocks)
-            nprim += b.primary && !(b.rn <= kDirectMaxParticles && b.cn <= kDirectMaxParticles) ? 1 : 0;
-        for (size_t i = 0; i <= NB; ++i) {
-            if (i < NB) {
-                const BlockRec& b = bld.blocks[i];
-                if (!b.primary || (b.rn <= kDirectMaxParticles && b.cn <= kDirectMaxParticles)) continue;
-                const int kmax = (int)std::min<int64_t>(o->aca_start > 0 ? o->aca_start : kAcaStart,
-                                                        (int64_t)std::min(b.rn, b.cn) * kNp);
-                const int64_t e = aca_elems(b, kmax);
-                if (acc == 0 || acc + e <= chunk_elems) {
-                    ids.push_back((int32_t)i);
-                    kmx.push_back(kmax);
-                    ea.push_back(bld.aca_eps0);
-                    acc += e;
-                    continue;
-                }
+        for (size_t i = 0; i < NB; ++i) {
+            const BlockRec& b = bld.blocks[i];
+            if (!b.primary || (b.rn <= kDirectMaxParticles && b.cn <= kDirectMaxParticles)) continue;
+            const int kmax = (int)std::min<int64_t>(o->aca_start > 0 ? o->aca_start : kAcaStart,
+                                                    (int64_t)std::min(b.rn, b.cn) * kNp);
+            const int64_t e = aca_elems(b, kmax);
+            if (acc > 0 && acc + e > chunk_elems) {
+                chunks.emplace_back();
+                acc = 0;
             }
-            if (!ids.empty()) {
-                st = bld.compress_aca(ids, kmx, ea, fallback);
-                if (st != QRVIE_OK) {
-                    for (auto& sg : bld.segments) dfree(ctx, sg.first, sg.second);
-                    return fail(st);
-                }
-                ndone += ids.size();
-                if (o->verbose) {
-                    std::fprintf(stderr, "[qrvie] cross approximation: %zu / %zu blocks (%.1f s)\n", ndone, nprim,
-                                 now_s() - t1);
-                    std::fflush(stderr);
-                }
+            chunks.back().ids.push_back((int32_t)i);
+            chunks.back().kmx.push_back(kmax);
+            acc += e;
+            ++nprim;
+        }
+        // size the reused buffers once for the largest chunk: growing them chunk by chunk
+        // (release, then allocate tens of GB again) cost seconds of host time in large builds
+        size_t mx[2] = {0, 0};
+        for (const Chunk& ch : chunks) {
+            size_t u = 0, v = 0;
+            for (size_t a = 0; a < ch.ids.size(); ++a) {
+                const BlockRec& b = bld.blocks[ch.ids[a]];
+                u += (size_t)b.rn * kNp * ch.kmx[a];
+                v += (size_t)b.cn * kNp * ch.kmx[a];
             }
-            ids.clear();
-            kmx.clear();
-            ea.clear();
-            acc = 0;
-            if (i < NB) --i;   // re-visit the block that did not fit
+            mx[0] = std::max(mx[0], u);
+            mx[1] = std::max(mx[1], v);
+        }
+        for (int w = 0; w < 4 && st == QRVIE_OK; ++w) {     // crosses U, V; basis of U (<= U); rows (<= V)
+            c128* p = nullptr;
+            st = bld.pooled(w, mx[w & 1], &p, "cross approximation buffers");
+        }
+        if (st != QRVIE_OK) return fail(st);
+        for (const Chunk& ch : chunks) {
+            if (ch.ids.empty()) continue;
+            st = bld.compress_aca(ch.ids, ch.kmx, std::vector<double>(ch.ids.size(), bld.aca_eps0), fallback);
+            if (st != QRVIE_OK) {
+                for (auto& sg : bld.segments) dfree(ctx, sg.first, sg.second);
+                return fail(st);
+            }
+            ndone += ch.ids.size();
+            if (o->verbose) {
+                std::fprintf(stderr, "[qrvie] cross approximation: %zu / %zu blocks (%.1f s)\n", ndone, nprim,
+                             now_s() - t1);
+                std::fflush(stderr);
+            }
         }
         op->stats.n_aca = (int64_t)ndone - (int64_t)fallback.size();
         op->stats.n_aca_resumed = bld.n_resumed;
