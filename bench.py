@@ -388,7 +388,8 @@ def precision_pattern(args) -> int:
     """The precision workload: far factors in BF16 split-complex (with the complex64 factors they
     were rounded from, stored once per pair), corrections by block GMRES with the BF16 factors on
     FP32 matrix cores and complex64 self blocks, FP64-accumulated residuals of the complex64
-    operator, 8 plane waves (4 angles in [-30, 30] deg x TE/TM).  With --ir-reference the same
+    operator, 8 plane waves (4 angles in [-30, 30] deg x TE/TM; --nrhs N > 1: the batching sweep of N
+    waves, solved in blocks of --block-width).  With --ir-reference the same
     right-hand sides are then solved by FP64 block GMRES on the complex128 factors of the same
     array (another operator, built after this one is freed) and each wave's relative difference
     is reported."""
@@ -415,24 +416,30 @@ def precision_pattern(args) -> int:
     st = op.stats()
     print(f"[bench] precision: operator {st['device_bytes'] / 1e9:.1f} GB built in {setup:.1f} s", file=sys.stderr,
           flush=True)
-    th = np.linspace(-30.0, 30.0, 4)
-    thetas, pols = np.concatenate([th, th]), np.array([0] * 4 + [1] * 4, dtype=np.int32)
-    v = q.rhs_plane_waves(ctx, geom, thetas, np.zeros(8), pols)
+    if args.nrhs > 1:                          # the batching sweep: nrhs waves, nrhs / 2 angles x TE/TM
+        sw = W.sweep((args.nrhs + 1) // 2)
+        thetas, phis, pols = sw.theta_deg[:args.nrhs], sw.phi_deg[:args.nrhs], sw.pol[:args.nrhs]
+    else:
+        th = np.linspace(-30.0, 30.0, 4)
+        thetas, pols = np.concatenate([th, th]), np.array([0] * 4 + [1] * 4, dtype=np.int32)
+        phis = np.zeros(8)
+    nrhs = len(thetas)
+    v = q.rhs_plane_waves(ctx, geom, thetas, phis, pols)
     torch.cuda.synchronize()
     t = time.perf_counter()
     x, info, status = op.solve(v, restart=args.block_basis, tol=args.tol, max_iter=args.max_iter,
-                               mode=q.SOLVE_BLOCK_IR, verbose=True)
+                               mode=q.SOLVE_BLOCK_IR, verbose=True, block_width=args.block_width)
     torch.cuda.synchronize()
     t_ir = time.perf_counter() - t
     print(f"[bench] precision: BF16 refinement {t_ir:.1f} s, {info[0]['iterations']} block steps, "
           f"{info[0]['n_refine']} corrections, true residuals {max(i['rel_res_true'] for i in info):.2e}",
           file=sys.stderr, flush=True)
-    out = {"metric": METRIC, "value": round(8 / t_ir, 4) if all(i["converged"] for i in info) else None,
+    out = {"metric": METRIC, "value": round(nrhs / t_ir, 4) if all(i["converged"] for i in info) else None,
            "unit": "RHS solves/s", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": round(t_ir * 1e3, 1),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "bf16 far factors on f32 MFMA (inner), f64-accumulated c64 residuals", "data": "synthetic",
            "config": {"workload": f"{arr.name}: {arr.n_particles} disks, {geom.ndof} unknowns, eps {args.eps:g}, "
-                                  f"8 plane waves, BF16 split-complex far factors, mixed-precision block refinement "
+                                  f"{nrhs} plane waves, BF16 split-complex far factors, mixed-precision block refinement "
                                   f"to {args.tol:g}, transpose-shared factors, block rows <= {cap}",
                       "particles": arr.n_particles, "unknowns": geom.ndof, "basis_vectors": args.block_basis,
                       "max_block_steps": args.max_iter},
@@ -450,7 +457,7 @@ def precision_pattern(args) -> int:
                           compression=args.compression)
         t = time.perf_counter()
         x64, i64, _ = op64.solve(v, restart=args.block_basis, tol=args.tol, max_iter=args.max_iter,
-                                 mode=q.SOLVE_BLOCK, verbose=True)
+                                 mode=q.SOLVE_BLOCK, verbose=True, block_width=args.block_width)
         torch.cuda.synchronize()
         t64 = time.perf_counter() - t
         x64h = x64.cpu()
@@ -458,7 +465,7 @@ def precision_pattern(args) -> int:
             "s": round(t64, 2), "build_s": round(t - t0, 1), "block_steps": i64[0]["iterations"],
             "converged": [bool(i["converged"]) for i in i64], "rel_res_true": [i["rel_res_true"] for i in i64],
             "rel_diff_per_rhs": [float(torch.linalg.norm(xh[r] - x64h[r]) / torch.linalg.norm(x64h[r]))
-                                 for r in range(8)]}
+                                 for r in range(nrhs)]}
         print(f"[bench] precision: FP64 reference {t64:.1f} s, per-RHS differences "
               f"{max(out['fp64_reference']['rel_diff_per_rhs']):.2e}", file=sys.stderr, flush=True)
     print(json.dumps(out))
@@ -536,6 +543,8 @@ def main() -> int:
                     help="store every ordered far block's factors (no transpose sharing) for the single-vector line")
     ap.add_argument("--gmres50-steps", type=int, default=2000,
                     help="default line: Arnoldi steps of the GMRES(50) leg (0 skips it)")
+    ap.add_argument("--no-batching64", dest="batching64_leg", action="store_false",
+                    help="default line: skip the 64 x 64 batching form (about 80 s)")
     ap.add_argument("--serving-leg", type=int, default=24,
                     help="default line: requests of the bounded serving leg (0 skips it)")
     ap.add_argument("--serving-leg-rate", type=float, default=0.9, help="serving leg arrival rate (1/s)")
@@ -703,6 +712,11 @@ def main() -> int:
     }
     if not args.mixed_ir and not args.no_forms and args.nrhs == 1:
         out["forms"] = other_forms(q, W, ctx, geom, op, v, args, out["solves_per_s"], share)
+        if args.batching64_leg:
+            try:
+                out["forms"]["batching64"] = batching64_leg(args)
+            except Exception as e:                 # the line is still reported without this form
+                out["forms"]["batching64"] = {"error": str(e)[:300]}
         if args.serving_leg > 0:
             leg = serving_leg(args)
             out["forms"]["serving"] = leg
@@ -801,6 +815,43 @@ def other_forms(q, W, ctx, geom, op, v, args, plain_solves_per_s: float, share: 
                           "note": "the configured restart length, for a bounded step budget; the timed solves run "
                                   "unrestarted GMRES because GMRES(50) stalls on this array"}
     return out
+
+
+def batching64_leg(args) -> dict:
+    """The batching workload as one timed form of the default line: the 64 x 64 graded metalens
+    array (589,824 unknowns), complex64 far factors by cross approximation, 64 plane waves solved
+    by block GMRES as two 32-wide blocks (12,288 basis vectors each, no restart) to the tolerance."""
+    import torch
+    import paper_2603_10586_amd as q
+    import workloads as W
+    ctx = q.Context(0)
+    arr = W.batching()
+    geom = q.Geometry(ctx, arr)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    op = q.Operator(ctx, geom, eps=args.eps, far_prec=q.PREC_C64_ONLY)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    try:
+        tune_tiles(op)
+        sw = W.sweep(32)
+        v = q.rhs_plane_waves(ctx, geom, sw.theta_deg, sw.phi_deg, sw.pol)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, info, st = op.solve(v, restart=12288, tol=args.tol, max_iter=1200, mode=q.SOLVE_BLOCK, block_width=32)
+        ts = time.perf_counter() - t
+        print(f"[bench] batching 64x64: {ts:.1f} s for 64 waves, {info[0]['iterations']} block steps", file=sys.stderr,
+              flush=True)
+        return {"workload": f"{arr.name}: {arr.n_particles} disks, {geom.ndof} unknowns, 64 plane waves as two 32-wide "
+                            f"blocks, complex64 far factors, tol {args.tol:g}",
+                "solves_per_s": round(64 / ts, 3), "s_per_64": round(ts, 2), "build_s": round(build_s, 2),
+                "block_steps": info[0]["iterations"], "converged": all(i["converged"] for i in info),
+                "worst_true_residual": max(i["rel_res_true"] for i in info),
+                "operator_device_bytes": op.stats()["device_bytes"]}
+    finally:
+        op.close()
+        geom.close()
+        ctx.close()
 
 
 def serving_leg(args) -> dict:
