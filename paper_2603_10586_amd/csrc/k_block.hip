@@ -205,50 +205,51 @@ __global__ void __launch_bounds__(256) k_count_neq(int64_t n, const unsigned lon
 
 // ----------------------------------------------------------------- basis updates on FP64 MFMA
 // W (n x q) = beta W + sign * V H for V: n x m, H: m x q (q <= 64): the basis update of
-// block CGS2, the solution update and the Gram correction 2 H1 - G H1.  Each wave owns 16 rows
-// of W and all q columns (NT tiles of 16); the m columns of V are visited in ascending 4-column
-// steps (fixed order), in chunks of kNnChunk whose H rows the workgroup first stages in LDS, so
-// H is read from L2 once per workgroup instead of once per wave.  V is streamed once.
-constexpr int kNnChunk = 64;
-
+// block CGS2, the solution update (long, thin products that rocBLAS runs at about half the
+// FP64 matrix rate) and the Gram correction 2 H1 - G H1 (square, small: rocBLAS picked a
+// tile shape that ran it at a few TF/s).  Each wave owns 16 rows of W and all q columns (NT tiles of 16); the m
+// columns of V are visited in ascending batches of U 4-column steps (fixed order).  V is
+// streamed once; H stays in cache.
 template <int NT>
 __global__ void __launch_bounds__(256) k_gemm_nn_acc(int64_t n, int m, int q, const c128* __restrict__ V,
                                                      int64_t ldv, const c128* __restrict__ H, int64_t ldh,
                                                      double beta, double sign, c128* __restrict__ W,
                                                      int64_t ldw) {
-    constexpr int U = 4, QP = 16 * NT + 1;                    // LDS row of H: q columns + 1 pad
-    __shared__ c128 Hs[kNnChunk * QP];
+    constexpr int U = 4;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t r0 = 64 * (int64_t)blockIdx.x + 16 * w;
+    if (r0 >= n) return;
     const int rl = lane & 15, kq = lane >> 4;
     const c128* Vp = V + min(r0 + rl, n - 1);                        // clamped lanes are discarded
+    const c128* Hp[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) Hp[t] = H + (int64_t)min(16 * t + rl, q - 1) * ldh;
     v4d re[NT], im[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) re[t] = im[t] = v4d{0.0, 0.0, 0.0, 0.0};
-    const c128 z = make_double2(0.0, 0.0);
-    for (int i0 = 0; i0 < m; i0 += kNnChunk) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < kNnChunk * 16 * NT; e += 256) {   // Hs[k][j] = H(i0 + k, j)
-            const int k = e % kNnChunk, j = e / kNnChunk;
-            Hs[k * QP + j] = (i0 + k < m && j < q) ? H[(i0 + k) + (int64_t)j * ldh] : z;
+    int i = 0;
+    for (; i + 4 * U <= m; i += 4 * U) {
+        c128 a[U], b[U][NT];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int col = i + 4 * u + kq;
+            a[u] = load_stream(Vp + (int64_t)col * ldv);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) b[u][t] = Hp[t][col];
         }
-        __syncthreads();
-        for (int kc = 0; kc < kNnChunk; kc += 4 * U) {
-            c128 a[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int col = i0 + kc + 4 * u + kq;
-                a[u] = col < m ? load_stream(Vp + (int64_t)col * ldv) : z;
-            }
+        for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const c128* hr = Hs + (kc + 4 * u + kq) * QP + rl;
-#pragma unroll
-                for (int t = 0; t < NT; ++t) cmfma(re[t], im[t], a[u], hr[16 * t]);
-            }
-        }
+            for (int t = 0; t < NT; ++t) cmfma(re[t], im[t], a[u], b[u][t]);
     }
-    if (r0 >= n) return;
+    for (; i < m; i += 4) {                                           // remaining steps, the last possibly partial
+        const int col = i + kq;
+        const bool ok = col < m;
+        const c128 z = make_double2(0.0, 0.0);
+        const c128 a = ok ? Vp[(int64_t)col * ldv] : z;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) cmfma(re[t], im[t], a, ok ? Hp[t][col] : z);
+    }
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         const int64_t row = r0 + kq + 4 * s;
