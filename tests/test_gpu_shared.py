@@ -147,9 +147,13 @@ def test_shared_full_size_product_matches_the_unshared_product():
     v = rng.standard_normal(n) + 1j * rng.standard_normal(n)
     y = to_host(op.apply(to_dev(x)))
     y0 = to_host(m["op"].apply(to_dev(x)))
-    assert np.linalg.norm(y - y0) <= 1e-12 * np.linalg.norm(y0)
+    # the same factors summed in another order: every entry is a sum of at most n products, so
+    # two FP64 orders differ by at most 2 gamma_n (n u each) times the sum of the products'
+    # magnitudes; bounded here by 8 n u ||y0|| (measured: 3.3e-11 relative, about 2 n u)
+    u = 2.0 ** -53
+    assert np.linalg.norm(y - y0) <= 8 * n * u * np.linalg.norm(y0)
     Zv = to_host(op.apply(to_dev(v)))
-    assert abs(x @ Zv - v @ y) <= 1e-12 * np.linalg.norm(x) * np.linalg.norm(Zv)
+    assert abs(x @ Zv - v @ y) <= 8 * n * u * np.linalg.norm(x) * np.linalg.norm(Zv)
     s0, s1 = m["op"].stats(), op.stats()
     print(f"[shared mid] device GB {s1['device_bytes'] / 1e9:.2f} vs {s0['device_bytes'] / 1e9:.2f}, "
           f"product GB {s1['apply_bytes'] / 1e9:.2f} vs {s0['apply_bytes'] / 1e9:.2f}", flush=True)
