@@ -267,9 +267,11 @@ class Operator:
 
     @staticmethod
     def footprint_estimate(geom: Geometry, eps: float = 1e-6, max_block_rows: int = 0, far_prec: int = L.PREC_C128,
-                           chunk_bytes: int = 0, share_transpose: bool = False, compression: str = "aca") -> int:
+                           chunk_bytes: int = 0, share_transpose: bool = False, compression: str = "aca",
+                           aca_start: int = 0) -> int:
         o = L.CompressOpts(eps=eps, far_prec=far_prec, max_block_rows=max_block_rows, chunk_bytes=chunk_bytes,
-                           share_transpose=1 if share_transpose else 0, compression=_compression(compression))
+                           share_transpose=1 if share_transpose else 0, compression=_compression(compression),
+                           aca_start=aca_start)
         out = C.c_size_t()
         st = geom.ctx.lib.qrvie_op_footprint_estimate(geom.h, C.byref(o), C.byref(out))
         geom.ctx.check(st, "footprint")
