@@ -328,6 +328,8 @@ __global__ void __launch_bounds__(NT) k_aca(GeomView g, const AcaDesc* descs) {
         best = wg_argmax<NW>(best, bj, rv, ri);
         if (!(best > 0.0)) break;                          // the residual row vanishes
         const c128 piv = d.V[bj + (int64_t)k * n];
+        __syncthreads();                                   // every wave holds the pivot before the
+                                                           // wave owning it normalises it in place
         const c128 inv = make_double2(piv.x / best, -piv.y / best);
         double vn2 = 0.0;
         for (int c = t; c < n / 3; c += NT) {

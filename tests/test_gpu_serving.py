@@ -75,6 +75,27 @@ def test_served_solution_matches_the_oracle_on_the_same_operator():
     assert np.array_equal(to_host(xd), res.x)
 
 
+def test_a_vogel_array_of_spheres_on_the_paper_grid_is_served():
+    """A request for the paper's own geometry (voxelised spheres, grouped on the grid of
+    §5.3) carries its cell shape and grouping through the server: the served solution is the
+    directly built operator's bitwise."""
+    import paper_2603_10586_amd as q
+    from paper_2603_10586_amd.server import Server, ServerOpts
+    rng = np.random.default_rng(12)
+    arr = W.vogel(100)
+    r = W.Request(rid=0, arrival_s=0.0, array=arr, incidence=W.random_incidence(2, rng), tol=1e-4)
+    srv = Server(ServerOpts(slots=1, hbm_budget=8 << 30, restart=400, max_iter=2000, op_cache=1))
+    res = srv.result(srv.submit(r), timeout=120)
+    srv.close()
+    assert res.status == 0 and all(i["converged"] for i in res.info)
+    geom = q.Geometry(ctx(), arr)
+    assert geom.n_levels > 1
+    op = q.Operator(ctx(), geom, eps=1e-6)
+    vd = q.rhs_plane_waves(ctx(), geom, r.incidence.theta_deg, r.incidence.phi_deg, r.incidence.pol)
+    xd, _, _ = op.solve(vd, restart=400, tol=1e-4, max_iter=2000, mode=q.SOLVE_BLOCK)
+    assert np.array_equal(to_host(xd), res.x)
+
+
 def test_operator_cache_serves_repeated_geometries():
     from paper_2603_10586_amd.server import Server, ServerOpts
     reqs = _requests()
