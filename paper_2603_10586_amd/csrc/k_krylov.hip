@@ -113,16 +113,18 @@ __global__ void k_cgs2_coeffs(const c128* __restrict__ partial, int nchunks, int
     h[i] = make_double2(2.0 * h[i].x - re, 2.0 * h[i].y - im);
 }
 
-// w += SIGN * V h; npart[block] = ||w_block||^2 after (when given).  One row per lane; the
-// coefficients are wave-uniform scalar loads and the basis columns stream in
-// double-buffered batches of 8 (rows past n re-read row n-1 and are not stored).
+// w += SIGN * V h; npart[block] = ||w_block||^2 after (when given).  One row per lane and one
+// wave per workgroup: every wave streams all the basis columns for its 64 rows, so n / 64
+// equal workgroups spread evenly over the compute units (n / 256 four-wave groups left some
+// units a third more work than others).  The coefficients are wave-uniform scalar loads and the
+// basis columns stream in double-buffered batches of 8 (rows past n re-read row n-1 and are
+// not stored).
 template <int SIGN>
-__global__ void __launch_bounds__(256) k_gemv_acc(const c128* __restrict__ V, int64_t ldv, int ncols,
-                                                  const c128* __restrict__ h, c128* __restrict__ w, int64_t n,
-                                                  double* __restrict__ npart) {
+__global__ void __launch_bounds__(64) k_gemv_acc(const c128* __restrict__ V, int64_t ldv, int ncols,
+                                                 const c128* __restrict__ h, c128* __restrict__ w, int64_t n,
+                                                 double* __restrict__ npart) {
     constexpr int U = 8;
-    __shared__ double red[4];
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t e = (int64_t)blockIdx.x * 64 + threadIdx.x;
     const bool live = e < n;
     const int64_t row = live ? e : n - 1;
     c128 acc0 = live ? w[e] : make_double2(0.0, 0.0), acc1 = make_double2(0.0, 0.0);
@@ -142,7 +144,7 @@ __global__ void __launch_bounds__(256) k_gemv_acc(const c128* __restrict__ V, in
     const double re = acc0.x + acc1.x, im = acc0.y + acc1.y;
     if (live) w[e] = make_double2(re, im);
     if (npart) {
-        const double s = block_sum(live ? re * re + im * im : 0.0, red);
+        const double s = wave_sum(live ? re * re + im * im : 0.0);
         if (threadIdx.x == 0) npart[blockIdx.x] = s;
     }
 }
@@ -383,7 +385,7 @@ __global__ void __launch_bounds__(256) k_trisolve(int k, const c128* H, int ldh,
 }  // namespace
 
 int krylov_nchunks(int64_t n) { return (int)((n + kChunk - 1) / kChunk); }
-int krylov_nblocks(int64_t n) { return (int)((n + 255) / 256); }
+int krylov_nblocks(int64_t n) { return (int)((n + 63) / 64); }
 
 void launch_multidot(hipStream_t s, const c128* V, int64_t ldv, int ncols, const c128* w, const c128* u, int64_t n,
                      c128* partial, c128* upartial) {
@@ -401,10 +403,10 @@ void launch_cgs2_coeffs(hipStream_t s, const c128* partial, int nchunks, int nco
 }
 void launch_gemv_sub(hipStream_t s, const c128* V, int64_t ldv, int ncols, const c128* h, c128* w, int64_t n,
                      double* npart) {
-    hipLaunchKernelGGL(k_gemv_acc<-1>, dim3(krylov_nblocks(n)), dim3(256), 0, s, V, ldv, ncols, h, w, n, npart);
+    hipLaunchKernelGGL(k_gemv_acc<-1>, dim3(krylov_nblocks(n)), dim3(64), 0, s, V, ldv, ncols, h, w, n, npart);
 }
 void launch_gemv_add(hipStream_t s, const c128* V, int64_t ldv, int ncols, const c128* y, c128* x, int64_t n) {
-    hipLaunchKernelGGL(k_gemv_acc<1>, dim3(krylov_nblocks(n)), dim3(256), 0, s, V, ldv, ncols, y, x, n, nullptr);
+    hipLaunchKernelGGL(k_gemv_acc<1>, dim3(krylov_nblocks(n)), dim3(64), 0, s, V, ldv, ncols, y, x, n, nullptr);
 }
 void launch_norm2(hipStream_t s, const c128* w, int64_t n, double* partial) {
     hipLaunchKernelGGL(k_norm2, dim3(krylov_nchunks(n)), dim3(256), 0, s, w, n, partial);
